@@ -1,0 +1,273 @@
+"""CPU ORACLE — test infrastructure only.
+
+Plain, slow CPU implementation of the TPC track-finding hot path (neighbour
+links with FP32 decisions, mutual-link cleaning, cellular-automaton chains and
+assignment, FP64 maximum-a-posteriori helix fit, FP64 Kalman diagnostic).
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+import it; the GPU library never does, and it shares no code with the GPU path.
+
+The arithmetic lives in ``tpcoracle.c`` (built with gcc, ``-ffp-contract=off``,
+no fast-math). This module only marshals arguments. The rules it follows are
+the readings of the paper adopted for this build (the paper, Sec. 1, names
+the step -- CA seeding on pad-row links with time as the seeding coordinate
+and a Kalman fit, derived from the Run 2 HLT tracker -- but gives no formulas):
+see the header of ``tpcoracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tpcoracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("n_rows", ctypes.c_int32),
+        ("row_x", ctypes.c_void_p),
+        ("win_y", ctypes.c_float),
+        ("win_t", ctypes.c_float),
+        ("pair_c2", ctypes.c_float),
+        ("max_gap", ctypes.c_int32),
+        ("min_track_hits", ctypes.c_int32),
+        ("bz", ctypes.c_double),
+        ("sigma_y", ctypes.c_double),
+        ("sigma_t", ctypes.c_double),
+        ("ivar_s", ctypes.c_double),
+        ("ivar_tau", ctypes.c_double),
+        ("ivar_k", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("s_max", ctypes.c_double),
+    ]
+
+
+class _Fit(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("n_iter", ctypes.c_int32),
+        ("ndf", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("x_ref", ctypes.c_double),
+        ("y", ctypes.c_double),
+        ("t", ctypes.c_double),
+        ("sinphi", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("qpt", ctypes.c_double),
+        ("chi2", ctypes.c_double),
+        ("cov", ctypes.c_double * 15),
+        ("init", ctypes.c_double * 5),
+    ]
+
+
+FIT_DTYPE = np.dtype([
+    ("status", np.int32), ("n_iter", np.int32), ("ndf", np.int32), ("pad", np.int32),
+    ("x_ref", np.float64), ("y", np.float64), ("t", np.float64), ("sinphi", np.float64),
+    ("tau", np.float64), ("qpt", np.float64), ("chi2", np.float64),
+    ("cov", np.float64, (15,)), ("init", np.float64, (5,)),
+])
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle (plain C, gcc, no FP contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+                               "-mfpmath=sse", "-msse2", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.ora_links.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P]
+        lib.ora_links_subset.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P, P, P]
+        lib.ora_clean.argtypes = [ctypes.c_int64, P, P, P, P]
+        lib.ora_tracks.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P]
+        lib.ora_tracks.restype = ctypes.c_int64
+        lib.ora_chain_len.argtypes = [ctypes.c_int64, P, P, P]
+        lib.ora_fit_map.argtypes = [P, ctypes.c_int32, P, P, P, P]
+        lib.ora_fit_kf.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.c_int32, P]
+        lib.ora_fit_tracks.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32, P]
+        lib.ora_map_cost.argtypes = [P, ctypes.c_int32, P, P, P, P, P]
+        lib.ora_map_cost.restype = ctypes.c_double
+        lib.ora_propagate_c.argtypes = [P, P, ctypes.c_double, P, P]
+        lib.ora_propagate_c.restype = ctypes.c_int32
+        lib.ora_sizeof_fit.restype = ctypes.c_int32
+        lib.ora_sizeof_cfg.restype = ctypes.c_int32
+        assert lib.ora_sizeof_fit() == ctypes.sizeof(_Fit) == FIT_DTYPE.itemsize
+        assert lib.ora_sizeof_cfg() == ctypes.sizeof(_Cfg)
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Config:
+    """Tracker constants (the readings of the paper adopted for this build)."""
+    row_x: np.ndarray                 # float32[n_rows] pad-row x (cm)
+    win_y: float = 1.5                # box half width in y per unit row gap (cm)
+    win_t: float = 2.0                # box half width in time per unit row gap (cm)
+    pair_c2: float = 0.2              # pair score acceptance (cm^2)
+    max_gap: int = 2
+    min_track_hits: int = 10
+    bz: float = 0.5                   # tesla
+    sigma_y: float = 0.1              # cm
+    sigma_t: float = 0.1              # cm
+    var_s: float | None = 1.0         # prior variances (None = prior off)
+    var_tau: float | None = 1.0
+    var_k: float | None = 100.0       # (1/GeV)^2
+    max_iter: int = 50
+    s_max: float = 0.999
+
+    def _c(self):
+        self._rx = np.ascontiguousarray(self.row_x, np.float32)
+        c = _Cfg()
+        c.n_rows = len(self._rx)
+        c.row_x = self._rx.ctypes.data
+        c.win_y, c.win_t, c.pair_c2 = self.win_y, self.win_t, self.pair_c2
+        c.max_gap, c.min_track_hits = self.max_gap, self.min_track_hits
+        c.bz, c.sigma_y, c.sigma_t = self.bz, self.sigma_y, self.sigma_t
+        c.ivar_s = 0.0 if self.var_s is None else 1.0 / self.var_s
+        c.ivar_tau = 0.0 if self.var_tau is None else 1.0 / self.var_tau
+        c.ivar_k = 0.0 if self.var_k is None else 1.0 / self.var_k
+        c.max_iter, c.s_max = self.max_iter, self.s_max
+        return c
+
+
+def _p(a):
+    return a.ctypes.data
+
+
+def _in(row, y, t):
+    return (np.ascontiguousarray(row, np.uint8), np.ascontiguousarray(y, np.float32),
+            np.ascontiguousarray(t, np.float32))
+
+
+def links(cfg: Config, row, y, t):
+    """Uncleaned links (up, dn, gap) of every hit, in input-index space."""
+    lib = _load()
+    row, y, t = _in(row, y, t)
+    n = len(row)
+    up = np.empty(n, np.int32); dn = np.empty(n, np.int32); gap = np.empty(n, np.int32)
+    c = cfg._c()
+    lib.ora_links(ctypes.byref(c), n, _p(row), _p(y), _p(t), _p(up), _p(dn), _p(gap))
+    return up, dn, gap
+
+
+def links_subset(cfg: Config, row, y, t, query):
+    """Uncleaned links of the listed hits only (indexed like `query`)."""
+    lib = _load()
+    row, y, t = _in(row, y, t)
+    q = np.ascontiguousarray(query, np.int32)
+    up = np.empty(len(q), np.int32); dn = np.empty(len(q), np.int32); gap = np.empty(len(q), np.int32)
+    c = cfg._c()
+    lib.ora_links_subset(ctypes.byref(c), len(row), _p(row), _p(y), _p(t), len(q), _p(q), _p(up), _p(dn), _p(gap))
+    return up, dn, gap
+
+
+def clean(up, dn):
+    lib = _load()
+    up = np.ascontiguousarray(up, np.int32); dn = np.ascontiguousarray(dn, np.int32)
+    upc = np.empty_like(up); dnc = np.empty_like(dn)
+    lib.ora_clean(len(up), _p(up), _p(dn), _p(upc), _p(dnc))
+    return upc, dnc
+
+
+def tracks(cfg: Config, upc, dnc):
+    """Tracks from cleaned links: (first int64[T], len int32[T], clusters int32[], assign int32[n])."""
+    lib = _load()
+    upc = np.ascontiguousarray(upc, np.int32); dnc = np.ascontiguousarray(dnc, np.int32)
+    n = len(upc)
+    first = np.empty(max(n, 1), np.int64); ln = np.empty(max(n, 1), np.int32)
+    cl = np.empty(max(n, 1), np.int32); assign = np.empty(n, np.int32)
+    c = cfg._c()
+    nt = lib.ora_tracks(ctypes.byref(c), n, _p(upc), _p(dnc), _p(first), _p(ln), _p(cl), _p(assign))
+    nc = int(ln[:nt].sum()) if nt else 0
+    return first[:nt].copy(), ln[:nt].copy(), cl[:nc].copy(), assign
+
+
+def chain_len(upc, dnc):
+    lib = _load()
+    upc = np.ascontiguousarray(upc, np.int32); dnc = np.ascontiguousarray(dnc, np.int32)
+    out = np.empty(len(upc), np.int32)
+    lib.ora_chain_len(len(upc), _p(upc), _p(dnc), _p(out))
+    return out
+
+
+def fit_map(cfg: Config, x, y, t):
+    """FP64 MAP helix fit of one track (clusters ordered by row)."""
+    lib = _load()
+    x = np.ascontiguousarray(x, np.float64); y = np.ascontiguousarray(y, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    out = np.zeros(1, FIT_DTYPE)
+    c = cfg._c()
+    lib.ora_fit_map(ctypes.byref(c), len(x), _p(x), _p(y), _p(t), _p(out))
+    return out[0]
+
+
+def fit_kf(cfg: Config, x, y, t, passes: int = 3):
+    """FP64 Kalman diagnostic (pass 1 extended, then linearised passes)."""
+    lib = _load()
+    x = np.ascontiguousarray(x, np.float64); y = np.ascontiguousarray(y, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    out = np.zeros(1, FIT_DTYPE)
+    c = cfg._c()
+    lib.ora_fit_kf(ctypes.byref(c), len(x), _p(x), _p(y), _p(t), passes, _p(out))
+    return out[0]
+
+
+def map_cost(cfg: Config, x, y, t, q, q0):
+    lib = _load()
+    x = np.ascontiguousarray(x, np.float64); y = np.ascontiguousarray(y, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    q = np.ascontiguousarray(q, np.float64); q0 = np.ascontiguousarray(q0, np.float64)
+    c = cfg._c()
+    return lib.ora_map_cost(ctypes.byref(c), len(x), _p(x), _p(y), _p(t), _p(q), _p(q0))
+
+
+def propagate(cfg: Config, q, dx):
+    """Closed-form helix transport of state q=(y,t,sinphi,tau,q/pT) by dx; (q', F) or None."""
+    lib = _load()
+    q = np.ascontiguousarray(q, np.float64)
+    qo = np.zeros(5); F = np.zeros(25)
+    c = cfg._c()
+    ok = lib.ora_propagate_c(ctypes.byref(c), _p(q), float(dx), _p(qo), _p(F))
+    return (qo, F.reshape(5, 5)) if ok else None
+
+
+def fit_tracks(cfg: Config, first, ln, clusters, row, y, t, kf_passes: int = 0):
+    """Fit every track of a sector: MAP (kf_passes=0) or the Kalman diagnostic."""
+    lib = _load()
+    row, y, t = _in(row, y, t)
+    first = np.ascontiguousarray(first, np.int64); ln = np.ascontiguousarray(ln, np.int32)
+    clusters = np.ascontiguousarray(clusters, np.int32)
+    out = np.zeros(len(first), FIT_DTYPE)
+    c = cfg._c()
+    if len(first):
+        lib.ora_fit_tracks(ctypes.byref(c), len(first), _p(first), _p(ln), _p(clusters), _p(row), _p(y), _p(t),
+                           kf_passes, _p(out))
+    return out
+
+
+def run_sector(cfg: Config, row, y, t, fit: bool = True):
+    """The whole path on one sector: links, cleaning, chains, assignment, fit."""
+    up, dn, gap = links(cfg, row, y, t)
+    upc, dnc = clean(up, dn)
+    first, ln, cl, assign = tracks(cfg, upc, dnc)
+    res = dict(up=up, dn=dn, gap=gap, upc=upc, dnc=dnc, first=first, len=ln, clusters=cl, assign=assign)
+    if fit:
+        res["fit"] = fit_tracks(cfg, first, ln, cl, row, y, t)
+    return res
