@@ -1,0 +1,204 @@
+/*
+ * tpcca.h - C ABI of the MI355X TPC track finder.
+ *
+ * The library runs the track-finding step that the paper (Sec. 1) names as
+ * the most compute-intensive part of ALICE's synchronous Run 3 processing:
+ * full TPC tracking of whole continuous-readout time frames (~10 ms), with
+ * the clusters kept in native coordinates (pad row, pad-direction y, drift
+ * time) and track seeding that uses time, not z, as its coordinate, because
+ * the collisions of a frame are not known before tracking (Sec. 1). A whole
+ * frame is resident in GPU memory and device buffers are reused across the
+ * sequential steps (Sec. 1). The paper prints no algorithm; the steps below
+ * are the ones this library defines:
+ *
+ *   1. per sector, a per-row search grid ordered by drift time;
+ *   2. neighbour links: for every cluster, the best (down, up) pair of
+ *      clusters on rows r-g / r+g (g = 1, then 2) by the distance of the
+ *      cluster from the straight line through the pair in (y, t), scored in
+ *      FP32 with a fixed operation order (bit-reproducible);
+ *   3. cleaning to mutual links, and cellular-automaton chains of mutual
+ *      links; a chain of >= min_track_hits clusters is a track;
+ *   4. an FP32 Kalman helix fit of every track, iterated (re-linearised)
+ *      so that it converges to the maximum-a-posteriori helix.
+ *
+ * Conventions
+ *   - Every function returns a tpcca_status; no exception crosses the ABI.
+ *     tpcca_last_error() gives a message for the last failing call.
+ *   - One context is used by one host thread at a time.
+ *   - A cluster's identity is its index in the arrays passed to
+ *     tpcca_load_sector (the sector-local input index). All tie-breaks and
+ *     every output ordering use it, so results do not depend on the order
+ *     in which the GPU processes anything.
+ *   - The library never allocates device memory: all working buffers live
+ *     in one caller-owned arena (tpcca_attach_arena); tpcca_required_arena
+ *     says how large it must be for the frames currently loaded.
+ *   - All device work is enqueued on the caller's stream (tpcca_set_stream)
+ *     and tpcca_run() does not wait for it; tpcca_synchronize() does.
+ */
+#ifndef TPCCA_H
+#define TPCCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tpcca_ctx tpcca_ctx;
+
+typedef enum {
+    TPCCA_OK = 0,
+    TPCCA_ERR_INVALID_ARG = -1, /* bad pointer, size, index or input value */
+    TPCCA_ERR_NOMEM = -2,       /* arena missing or too small */
+    TPCCA_ERR_CAPACITY = -3,    /* caller's output buffer too small; *n_out holds the size needed */
+    TPCCA_ERR_STATE = -4,       /* call not valid in the context's current state */
+    TPCCA_ERR_DEVICE = -5,      /* a HIP runtime call failed */
+    TPCCA_ERR_ABORTED = -6      /* run stopped by tpcca_request_abort */
+} tpcca_status;
+
+/* Tracker constants. tpcca_config_default() fills the defaults listed. */
+typedef struct {
+    float bz_tesla;            /* solenoid field, 0.5 */
+    int32_t n_sectors;         /* sectors per frame, 36 */
+    int32_t n_rows;            /* pad rows per sector, 152 (at most 255) */
+    const float *row_x;        /* host pointer, [n_rows] local x of each pad row (cm), strictly
+                                  increasing; copied by tpcca_create. The default points to a
+                                  built-in table x_r = 85 + r*160/151 cm, rounded to float */
+    float sigma_y, sigma_t;    /* cluster resolution (cm), 0.1, 0.1 */
+    float win_y, win_t;        /* neighbour box half widths per unit row gap (cm), 1.5, 2.0 */
+    float pair_c2;             /* largest accepted pair score (cm^2), 0.2 */
+    int32_t max_gap;           /* symmetric row gaps tried, 1..max_gap, 2 */
+    int32_t min_track_hits;    /* shortest chain reported as a track, 10 */
+    float prior_var_sinphi;    /* prior variances of the fit, centred on the three-point */
+    float prior_var_tau;       /*   estimate: 1, 1, 100 (GeV^-2) */
+    float prior_var_qpt;
+    int32_t kf_passes;         /* most Kalman passes: 1 extended, then re-linearised passes until
+                                  one moves no parameter by more than 1e-5 relative, 12 */
+    float s_max;               /* |sin phi| at which a propagation fails, 0.999 */
+    int32_t use_mlp;           /* 1: prune candidate triplets with the loaded MLP, 0 */
+    float mlp_logit_threshold; /* triplets with logit below this are pruned, 0 */
+} tpcca_config;
+
+/* One fitted track. Tracks of a sector are numbered 0..T-1 in ascending
+   input index of their first (innermost) cluster. */
+typedef struct {
+    int32_t frame, sector;
+    int32_t n_clusters;        /* clusters in the chain */
+    int32_t status;            /* 0 ok; 2: propagation or initialisation failed;
+                                  4: not converged within kf_passes passes */
+    int64_t first;             /* offset of its clusters in the sector's cluster list */
+    int32_t seed;              /* input index of its innermost cluster */
+    int32_t ndf;               /* 2*n_clusters - 5 */
+    float x_ref;               /* x of the outermost cluster: parameters are given there */
+    float y;                   /* local y (cm) */
+    float t_base;              /* input time of the outermost cluster (cm of drift) */
+    float dt;                  /* fitted time minus t_base (cm) */
+    float sinphi;              /* sin of the transverse direction w.r.t. local x */
+    float tau;                 /* d(time)/d(transverse arc length) */
+    float qpt;                 /* q/pT (1/GeV) */
+    float chi2;                /* data chi2 of the fitted helix over all clusters */
+    float cov[15];             /* covariance of (y, t, sinphi, tau, qpt), lower triangle row-major */
+} tpcca_track;
+
+/* Per-run figures filled by tpcca_get_stats. Stage times need the timing
+   flag (tpcca_set_timing) and a completed run. */
+typedef struct {
+    int64_t n_clusters;        /* clusters in the run (all loaded frames) */
+    int64_t n_links;           /* clusters with an (uncleaned) neighbour pair */
+    int64_t n_seeds;           /* chain starts */
+    int64_t n_tracks;          /* chains with >= min_track_hits clusters */
+    int64_t n_track_clusters;  /* clusters assigned to tracks */
+    int64_t n_invalid;         /* input clusters rejected on the device (row or value) */
+    int32_t n_stages;          /* entries used in stage_ms / stage_name */
+    float stage_ms[16];        /* device time per stage, last run */
+    char stage_name[16][24];
+} tpcca_stats;
+
+/* Fill *out with the defaults above. */
+tpcca_status tpcca_config_default(tpcca_config *out);
+
+/* Create a context for one device (the current HIP device). Copies cfg and
+   its row table. Errors: INVALID_ARG for out-of-range constants. */
+tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out);
+
+/* Release the context (not the arena or the stream, which the caller owns). */
+void tpcca_destroy(tpcca_ctx *ctx);
+
+/* Message for the last failing call on this context (never NULL). */
+const char *tpcca_last_error(const tpcca_ctx *ctx);
+
+/* Use `stream` (a hipStream_t; NULL = null stream) for all device work. */
+tpcca_status tpcca_set_stream(tpcca_ctx *ctx, void *stream);
+
+/* Open a new, empty time frame; *frame_id receives its index (0, 1, ...). */
+tpcca_status tpcca_add_frame(tpcca_ctx *ctx, int32_t *frame_id);
+
+/* Drop all frames and their results. */
+tpcca_status tpcca_clear_frames(tpcca_ctx *ctx);
+
+/* Give the clusters of one sector of one frame: n entries of pad row
+   (uint8, < n_rows), local y (cm) and drift time (cm). Arrays are SoA.
+   is_device_ptr = 0: host arrays, copied before return (the caller may free
+   them); they are staged into the arena by the next run. is_device_ptr = 1:
+   device arrays, borrowed (not copied) until the next tpcca_synchronize
+   after the last run that uses them. Host arrays are validated here
+   (INVALID_ARG for a row >= n_rows or a non-finite value); device arrays
+   are checked on the device and offending clusters are left out of the run
+   and counted in tpcca_stats.n_invalid. A sector given twice for one frame:
+   STATE. n = 0 is allowed. */
+tpcca_status tpcca_load_sector(tpcca_ctx *ctx, int32_t frame, int32_t sector, int64_t n,
+                               const uint8_t *row, const float *y, const float *t, int32_t is_device_ptr);
+
+/* Arena bytes a run over the currently loaded frames needs. */
+tpcca_status tpcca_required_arena(tpcca_ctx *ctx, size_t *bytes);
+
+/* Use [device_ptr, device_ptr + bytes) as the arena (caller-owned device
+   memory, e.g. a torch uint8 tensor; 256-byte aligned). Results of earlier
+   runs live in the arena and stay valid until the next run or attach. */
+tpcca_status tpcca_attach_arena(tpcca_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* Enqueue the whole hot path over every loaded frame on the stream and
+   return without waiting. NOMEM if the arena is smaller than
+   tpcca_required_arena; STATE if no frame is loaded. */
+tpcca_status tpcca_run(tpcca_ctx *ctx);
+
+/* Wait for the last run; DEVICE on a HIP error, ABORTED if it was aborted. */
+tpcca_status tpcca_synchronize(tpcca_ctx *ctx);
+
+/* Ask a run in flight to stop early (checked between work items). The run's
+   results are then undefined and tpcca_synchronize returns ABORTED. */
+tpcca_status tpcca_request_abort(tpcca_ctx *ctx);
+
+/* Enable (1) or disable (0) per-stage device timing with HIP events. */
+tpcca_status tpcca_set_timing(tpcca_ctx *ctx, int32_t on);
+
+/* Figures of the last run (synchronises first). */
+tpcca_status tpcca_get_stats(tpcca_ctx *ctx, tpcca_stats *out);
+
+/* Results of the last run for one (frame, sector), copied to host memory
+   (each call synchronises first). CAPACITY if cap is too small; *n_out
+   always receives the number of entries available. */
+tpcca_status tpcca_get_tracks(tpcca_ctx *ctx, int32_t frame, int32_t sector, tpcca_track *out, int64_t cap,
+                              int64_t *n_out);
+
+/* Input indices of the clusters of every track of the sector, track after
+   track, innermost cluster first (rows ascending). */
+tpcca_status tpcca_get_track_clusters(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *out, int64_t cap,
+                                      int64_t *n_out);
+
+/* Track number of every input cluster of the sector (-1: none); out[n]
+   with n equal to the sector's cluster count. */
+tpcca_status tpcca_get_assignment(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *out, int64_t n);
+
+/* Neighbour links of every input cluster of the sector, in input indices
+   (-1: none): cleaned = 0 gives the best pair of step 2, cleaned = 1 keeps
+   only mutual links. For checking and debugging. */
+tpcca_status tpcca_get_links(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t cleaned, int32_t *up,
+                             int32_t *dn, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPCCA_H */

@@ -1,0 +1,695 @@
+// Host side of the C ABI declared in include/tpcca.h: context, validation,
+// the arena plan (every device buffer of a run is a sub-range of the
+// caller's arena; buffers that are dead after a stage are reused by later
+// stages), stage orchestration on the caller's stream and result fetches.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tpcca_internal.h"
+
+using namespace tpcca;
+
+namespace {
+
+struct SectorIn {
+    int64_t n = 0;
+    bool loaded = false;
+    bool host = false;
+    const uint8_t *drow = nullptr;
+    const float *dy = nullptr;
+    const float *dt = nullptr;
+    std::vector<uint8_t> hrow;
+    std::vector<float> hy, ht;
+    size_t stage_off = 0;  // arena offset of staged host inputs
+};
+
+// Arena layout of one run.
+struct Layout {
+    size_t total = 0;
+    size_t inputs, si, st, cnt, chunk, row_x, w_tab;
+    size_t rcnt, rstart, rcur, coff;
+    size_t tmp, rec, link;
+    size_t seeds, tseed, tlen, tslot;
+    size_t bits, wpre;
+    size_t trk_len, trk_seed, cl_off, trk;
+    size_t clusters, assign, scan_tmp;
+    size_t chain_yt, chain_row;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Bump {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        off = align_up(off, 256);
+        const size_t r = off;
+        off += align_up(bytes ? bytes : 1, 256);
+        return r;
+    }
+};
+
+const char *kStageNames[] = {"reset",   "hist",  "setup",   "scatter", "rowsort", "links", "seeds",
+                             "chainlen", "slots", "clscan",  "emit",    "fit"};
+constexpr int kNumStages = 12;
+
+}  // namespace
+
+struct tpcca_ctx {
+    tpcca_config cfg{};
+    std::vector<float> row_x;
+    int device = 0;
+    int n_cu = 256;
+    hipStream_t stream = nullptr;
+    std::vector<std::vector<SectorIn>> frames;
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    bool plan_dirty = true;
+    bool upload_dirty = true;
+    bool have_results = false;
+    bool ran = false;
+    Layout lay;
+    KArgs args{};
+    std::string err;
+    int32_t *abort_host = nullptr;
+    int32_t *abort_dev = nullptr;
+    bool timing = false;
+    bool events_ok = false;
+    hipEvent_t ev[kNumStages + 1];
+    float stage_ms[kNumStages] = {};
+    std::vector<SiDesc> si_host;
+    std::vector<int32_t> chunks;
+    std::vector<float> wtab;
+    int64_t n_in = 0;
+    int32_t n_words = 0;
+    Launch lc[kNumStages];
+};
+
+static tpcca_status fail(tpcca_ctx *c, tpcca_status s, const std::string &m) {
+    if (c) c->err = m;
+    return s;
+}
+
+static tpcca_status hip_fail(tpcca_ctx *c, hipError_t e, const char *what) {
+    return fail(c, TPCCA_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, call)                                             \
+    do {                                                            \
+        hipError_t e_ = (call);                                     \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #call);      \
+    } while (0)
+
+static const float *default_row_x() {
+    static float tab[152];
+    static bool init = false;
+    if (!init) {
+        for (int r = 0; r < 152; r++) tab[r] = (float)(85.0 + r * 160.0 / 151.0);
+        init = true;
+    }
+    return tab;
+}
+
+extern "C" {
+
+tpcca_status tpcca_config_default(tpcca_config *out) {
+    if (!out) return TPCCA_ERR_INVALID_ARG;
+    tpcca_config c{};
+    c.bz_tesla = 0.5f;
+    c.n_sectors = 36;
+    c.n_rows = 152;
+    c.row_x = default_row_x();
+    c.sigma_y = 0.1f;
+    c.sigma_t = 0.1f;
+    c.win_y = 1.5f;
+    c.win_t = 2.0f;
+    c.pair_c2 = 0.2f;
+    c.max_gap = 2;
+    c.min_track_hits = 10;
+    c.prior_var_sinphi = 1.0f;
+    c.prior_var_tau = 1.0f;
+    c.prior_var_qpt = 100.0f;
+    c.kf_passes = 12;
+    c.s_max = 0.999f;
+    c.use_mlp = 0;
+    c.mlp_logit_threshold = 0.0f;
+    *out = c;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
+    if (!cfg || !out) return TPCCA_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (cfg->n_rows < 5 || cfg->n_rows > kMaxRows || cfg->n_sectors < 1 || cfg->n_sectors > 4096 || !cfg->row_x)
+        return TPCCA_ERR_INVALID_ARG;
+    if (cfg->max_gap < 1 || cfg->max_gap > kMaxGap || cfg->min_track_hits < 3 || cfg->kf_passes < 1 ||
+        cfg->kf_passes > 64)
+        return TPCCA_ERR_INVALID_ARG;
+    if (!(cfg->win_y > 0) || !(cfg->win_t > 0) || !(cfg->pair_c2 >= 0) || !(cfg->sigma_y > 0) ||
+        !(cfg->sigma_t > 0) || !(cfg->prior_var_sinphi > 0) || !(cfg->prior_var_tau > 0) ||
+        !(cfg->prior_var_qpt > 0) || !(cfg->s_max > 0 && cfg->s_max < 1) || !std::isfinite(cfg->bz_tesla))
+        return TPCCA_ERR_INVALID_ARG;
+    for (int r = 0; r < cfg->n_rows; r++) {
+        if (!std::isfinite(cfg->row_x[r])) return TPCCA_ERR_INVALID_ARG;
+        if (r && !(cfg->row_x[r] > cfg->row_x[r - 1])) return TPCCA_ERR_INVALID_ARG;
+    }
+    tpcca_ctx *c = new tpcca_ctx();
+    c->cfg = *cfg;
+    c->row_x.assign(cfg->row_x, cfg->row_x + cfg->n_rows);
+    c->cfg.row_x = c->row_x.data();
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->abort_host, sizeof(int32_t), hipHostMallocMapped);
+    if (e == hipSuccess) {
+        *c->abort_host = 0;
+        e = hipHostGetDevicePointer((void **)&c->abort_dev, c->abort_host, 0);
+    }
+    if (e != hipSuccess) {
+        if (c->abort_host) (void)hipHostFree(c->abort_host);
+        delete c;
+        return TPCCA_ERR_DEVICE;
+    }
+    c->events_ok = true;
+    for (int i = 0; i <= kNumStages; i++)
+        if (hipEventCreate(&c->ev[i]) != hipSuccess) c->events_ok = false;
+    const int cu = std::max(1, c->n_cu);
+    for (int i = 0; i < kNumStages; i++) c->lc[i] = Launch{cu * 8, 256};
+    c->lc[4] = Launch{cu * 2, 512};  // rowsort: 34 KB LDS, 512 threads
+    c->lc[5] = Launch{cu * 4, 256};  // links: 48 KB LDS
+    // decision-path constants, computed once on the host in FP32
+    c->wtab.assign((size_t)cfg->n_rows * kMaxGap, 0.f);
+    for (int r = 0; r < cfg->n_rows; r++)
+        for (int g = 1; g <= kMaxGap; g++) {
+            if (r - g < 0 || r + g >= cfg->n_rows) continue;
+            volatile float num = c->row_x[r] - c->row_x[r - g];
+            volatile float den = c->row_x[r + g] - c->row_x[r - g];
+            volatile float w = num / den;
+            c->wtab[(size_t)r * kMaxGap + g - 1] = w;
+        }
+    *out = c;
+    return TPCCA_OK;
+}
+
+void tpcca_destroy(tpcca_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->events_ok)
+        for (int i = 0; i <= kNumStages; i++) (void)hipEventDestroy(c->ev[i]);
+    if (c->abort_host) (void)hipHostFree(c->abort_host);
+    delete c;
+}
+
+const char *tpcca_last_error(const tpcca_ctx *c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+tpcca_status tpcca_set_stream(tpcca_ctx *c, void *stream) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    c->stream = (hipStream_t)stream;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_set_timing(tpcca_ctx *c, int32_t on) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    if (on && !c->events_ok) return fail(c, TPCCA_ERR_DEVICE, "HIP events unavailable");
+    c->timing = on != 0;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_add_frame(tpcca_ctx *c, int32_t *frame_id) {
+    if (!c || !frame_id) return TPCCA_ERR_INVALID_ARG;
+    c->frames.emplace_back((size_t)c->cfg.n_sectors);
+    *frame_id = (int32_t)c->frames.size() - 1;
+    c->plan_dirty = true;
+    c->have_results = false;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_clear_frames(tpcca_ctx *c) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    c->frames.clear();
+    c->plan_dirty = true;
+    c->have_results = false;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_load_sector(tpcca_ctx *c, int32_t frame, int32_t sector, int64_t n, const uint8_t *row,
+                               const float *y, const float *t, int32_t is_device_ptr) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    if (frame < 0 || frame >= (int32_t)c->frames.size())
+        return fail(c, TPCCA_ERR_INVALID_ARG, "frame index out of range");
+    if (sector < 0 || sector >= c->cfg.n_sectors) return fail(c, TPCCA_ERR_INVALID_ARG, "sector out of range");
+    if (n < 0 || n > (int64_t)0x3fffffff) return fail(c, TPCCA_ERR_INVALID_ARG, "cluster count out of range");
+    if (n > 0 && (!row || !y || !t)) return fail(c, TPCCA_ERR_INVALID_ARG, "null input array");
+    SectorIn &s = c->frames[frame][sector];
+    if (s.loaded) return fail(c, TPCCA_ERR_STATE, "sector already loaded for this frame");
+    s = SectorIn();
+    s.n = n;
+    s.loaded = true;
+    if (is_device_ptr) {
+        s.host = false;
+        s.drow = row;
+        s.dy = y;
+        s.dt = t;
+    } else {
+        for (int64_t i = 0; i < n; i++) {
+            if (row[i] >= c->cfg.n_rows || !std::isfinite(y[i]) || !std::isfinite(t[i])) {
+                s = SectorIn();
+                return fail(c, TPCCA_ERR_INVALID_ARG,
+                            "cluster " + std::to_string(i) + ": row out of range or non-finite value");
+            }
+        }
+        s.host = true;
+        s.hrow.assign(row, row + n);
+        s.hy.assign(y, y + n);
+        s.ht.assign(t, t + n);
+    }
+    c->plan_dirty = true;
+    c->have_results = false;
+    return TPCCA_OK;
+}
+
+}  // extern "C"
+
+// Compute the arena layout and the host tables of the current frames.
+static tpcca_status plan(tpcca_ctx *c) {
+    const int R = c->cfg.n_rows;
+    const int NS = c->cfg.n_sectors;
+    const int S = (int)c->frames.size() * NS;
+    int64_t N = 0, W = 0, host_bytes = 0;
+    c->si_host.assign((size_t)S, SiDesc{});
+    c->chunks.clear();
+    Bump b;
+    Layout &L = c->lay;
+    // staged host inputs first
+    L.inputs = b.take(0);
+    for (int f = 0; f < (int)c->frames.size(); f++)
+        for (int s = 0; s < NS; s++) {
+            SectorIn &x = c->frames[f][s];
+            if (x.loaded && x.host && x.n > 0) {
+                x.stage_off = b.take((size_t)x.n);
+                b.take((size_t)x.n * 4);
+                b.take((size_t)x.n * 4);
+                host_bytes += x.n * 9;
+            }
+        }
+    for (int f = 0; f < (int)c->frames.size(); f++)
+        for (int s = 0; s < NS; s++) {
+            const int si = f * NS + s;
+            const SectorIn &x = c->frames[f][s];
+            SiDesc &d = c->si_host[si];
+            d.n = x.loaded ? (int32_t)x.n : 0;
+            d.in_base = (int32_t)N;
+            d.frame = f;
+            d.sector = s;
+            d.word_base = (int32_t)W;
+            d.nwords = (d.n + 31) / 32;
+            N += d.n;
+            W += d.nwords;
+            for (int64_t st = 0; st < d.n; st += kChunk) {
+                c->chunks.push_back(si);
+                c->chunks.push_back((int32_t)st);
+            }
+        }
+    if (N > (int64_t)0x7fff0000 || W > (int64_t)0x7fff0000)
+        return fail(c, TPCCA_ERR_INVALID_ARG, "too many clusters in one run");
+    const int64_t seed_cap = N / 2 + 64;
+    const int64_t tseed_cap = N / std::max(2, c->cfg.min_track_hits) + 64;
+    const int64_t trk_cap = tseed_cap;
+    const int64_t SR = (int64_t)S * R;
+    L.si = b.take(sizeof(SiDesc) * S);
+    L.st = b.take(sizeof(SiState) * S);
+    L.cnt = b.take(sizeof(Counters));
+    L.chunk = b.take(sizeof(int32_t) * c->chunks.size());
+    L.row_x = b.take(sizeof(float) * R);
+    L.w_tab = b.take(sizeof(float) * R * kMaxGap);
+    L.rcnt = b.take(sizeof(int32_t) * SR);
+    L.rstart = b.take(sizeof(int32_t) * SR);
+    L.rcur = b.take(sizeof(int32_t) * SR);
+    L.coff = b.take(sizeof(int32_t) * SR * (kNcbMax + 1));
+    // the row-grouped staging buffer is dead after the row sort: the chain
+    // copies for the fit reuse it
+    L.tmp = b.take(std::max(sizeof(Rec) * N, align_up(sizeof(float2) * N, 256) + (size_t)N));
+    L.chain_yt = L.tmp;
+    L.chain_row = L.tmp + align_up(sizeof(float2) * N, 256);
+    L.rec = b.take(sizeof(Rec) * N);
+    L.link = b.take(sizeof(int2) * N);
+    L.seeds = b.take(sizeof(int32_t) * seed_cap);
+    L.tseed = b.take(sizeof(int32_t) * tseed_cap);
+    L.tlen = b.take(sizeof(int32_t) * tseed_cap);
+    L.tslot = b.take(sizeof(int32_t) * tseed_cap);
+    L.bits = b.take(sizeof(uint32_t) * (W + 1));
+    L.wpre = b.take(sizeof(int32_t) * (W + 1));
+    L.trk_len = b.take(sizeof(int32_t) * (trk_cap + 1));
+    L.trk_seed = b.take(sizeof(int32_t) * trk_cap);
+    L.cl_off = b.take(sizeof(int32_t) * (trk_cap + 1));
+    L.trk = b.take(sizeof(tpcca_track) * trk_cap);
+    L.clusters = b.take(sizeof(int32_t) * N);
+    L.assign = b.take(sizeof(int32_t) * N);
+    const int64_t nblk = (std::max<int64_t>(W, trk_cap) + kScanItems - 1) / kScanItems + 2;
+    L.scan_tmp = b.take(sizeof(int32_t) * nblk);
+    L.total = align_up(b.off, 256);
+    c->n_in = N;
+    c->n_words = (int32_t)W;
+
+    KArgs &a = c->args;
+    a = KArgs{};
+    a.n_si = S;
+    a.n_rows = R;
+    a.n_in = (int32_t)N;
+    a.n_chunks = (int32_t)(c->chunks.size() / 2);
+    a.n_words = (int32_t)W;
+    a.seed_cap = (int32_t)seed_cap;
+    a.tseed_cap = (int32_t)tseed_cap;
+    a.trk_cap = (int32_t)trk_cap;
+    a.max_gap = c->cfg.max_gap;
+    a.min_track_hits = c->cfg.min_track_hits;
+    a.kf_passes = c->cfg.kf_passes;
+    for (int g = 1; g <= kMaxGap; g++) {
+        volatile float gy = (float)g * c->cfg.win_y;
+        volatile float gt = (float)g * c->cfg.win_t;
+        a.win_y[g - 1] = gy;
+        a.win_t[g - 1] = gt;
+    }
+    a.pair_c2 = c->cfg.pair_c2;
+    // a coarse bin must be at least twice the widest time window, so that
+    // every candidate of a cluster lies in its own or an adjacent bin
+    a.cbw_min = std::max(16.0f, 4.0f * (float)c->cfg.max_gap * c->cfg.win_t);
+    a.bz_kb = (float)(2.99792458e-3 * (double)c->cfg.bz_tesla);
+    a.sigma_y2 = c->cfg.sigma_y * c->cfg.sigma_y;
+    a.sigma_t2 = c->cfg.sigma_t * c->cfg.sigma_t;
+    a.var_s = c->cfg.prior_var_sinphi;
+    a.var_tau = c->cfg.prior_var_tau;
+    a.var_k = c->cfg.prior_var_qpt;
+    a.s_max = c->cfg.s_max;
+    (void)host_bytes;
+    c->plan_dirty = false;
+    c->upload_dirty = true;
+    return TPCCA_OK;
+}
+
+static void bind_pointers(tpcca_ctx *c) {
+    KArgs &a = c->args;
+    const Layout &L = c->lay;
+    char *A = c->arena;
+    a.row_x = (const float *)(A + L.row_x);
+    a.w_tab = (const float *)(A + L.w_tab);
+    a.si = (const SiDesc *)(A + L.si);
+    a.st = (SiState *)(A + L.st);
+    a.cnt = (Counters *)(A + L.cnt);
+    a.chunk = (const int32_t *)(A + L.chunk);
+    a.rcnt = (int32_t *)(A + L.rcnt);
+    a.rstart = (int32_t *)(A + L.rstart);
+    a.rcur = (int32_t *)(A + L.rcur);
+    a.coff = (int32_t *)(A + L.coff);
+    a.tmp = (Rec *)(A + L.tmp);
+    a.rec = (Rec *)(A + L.rec);
+    a.link = (int2 *)(A + L.link);
+    a.seeds = (int32_t *)(A + L.seeds);
+    a.tseed = (int32_t *)(A + L.tseed);
+    a.tlen = (int32_t *)(A + L.tlen);
+    a.tslot = (int32_t *)(A + L.tslot);
+    a.bits = (uint32_t *)(A + L.bits);
+    a.wpre = (int32_t *)(A + L.wpre);
+    a.trk_len = (int32_t *)(A + L.trk_len);
+    a.trk_seed = (int32_t *)(A + L.trk_seed);
+    a.cl_off = (int32_t *)(A + L.cl_off);
+    a.trk = (tpcca_track *)(A + L.trk);
+    a.clusters = (int32_t *)(A + L.clusters);
+    a.chain_yt = (float2 *)(A + L.chain_yt);
+    a.chain_row = (uint8_t *)(A + L.chain_row);
+    a.assign = (int32_t *)(A + L.assign);
+    a.scan_tmp = (int32_t *)(A + L.scan_tmp);
+    a.abort_flag = c->abort_dev;
+}
+
+extern "C" {
+
+tpcca_status tpcca_required_arena(tpcca_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return TPCCA_ERR_INVALID_ARG;
+    if (c->plan_dirty) {
+        tpcca_status s = plan(c);
+        if (s != TPCCA_OK) return s;
+    }
+    *bytes = c->lay.total;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_attach_arena(tpcca_ctx *c, void *ptr, size_t bytes) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    if (ptr && ((uintptr_t)ptr & 255)) return fail(c, TPCCA_ERR_INVALID_ARG, "arena must be 256-byte aligned");
+    (void)hipStreamSynchronize(c->stream);
+    c->arena = (char *)ptr;
+    c->arena_bytes = ptr ? bytes : 0;
+    c->upload_dirty = true;
+    c->have_results = false;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_request_abort(tpcca_ctx *c) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    __atomic_store_n(c->abort_host, 1, __ATOMIC_SEQ_CST);
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_run(tpcca_ctx *c) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    if (c->frames.empty()) return fail(c, TPCCA_ERR_STATE, "no frame loaded");
+    if (c->plan_dirty) {
+        tpcca_status s = plan(c);
+        if (s != TPCCA_OK) return s;
+    }
+    if (!c->arena || c->arena_bytes < c->lay.total)
+        return fail(c, TPCCA_ERR_NOMEM, "arena of " + std::to_string(c->arena_bytes) + " bytes, run needs " +
+                                            std::to_string(c->lay.total));
+    hipStream_t s = c->stream;
+    bind_pointers(c);
+    const KArgs &a = c->args;
+    const Layout &L = c->lay;
+    char *A = c->arena;
+    if (c->upload_dirty) {
+        const int NS = c->cfg.n_sectors;
+        for (int f = 0; f < (int)c->frames.size(); f++)
+            for (int k = 0; k < NS; k++) {
+                SectorIn &x = c->frames[f][k];
+                SiDesc &d = c->si_host[(size_t)f * NS + k];
+                if (!x.loaded || x.n == 0) {
+                    d.row = nullptr;
+                    d.y = d.t = nullptr;
+                    continue;
+                }
+                if (x.host) {
+                    char *p = A + x.stage_off;
+                    const size_t o1 = align_up((size_t)x.n, 256), o2 = o1 + align_up((size_t)x.n * 4, 256);
+                    HIPCHK(c, hipMemcpyAsync(p, x.hrow.data(), (size_t)x.n, hipMemcpyHostToDevice, s));
+                    HIPCHK(c, hipMemcpyAsync(p + o1, x.hy.data(), (size_t)x.n * 4, hipMemcpyHostToDevice, s));
+                    HIPCHK(c, hipMemcpyAsync(p + o2, x.ht.data(), (size_t)x.n * 4, hipMemcpyHostToDevice, s));
+                    d.row = (const uint8_t *)p;
+                    d.y = (const float *)(p + o1);
+                    d.t = (const float *)(p + o2);
+                } else {
+                    d.row = x.drow;
+                    d.y = x.dy;
+                    d.t = x.dt;
+                }
+            }
+        HIPCHK(c, hipMemcpyAsync(A + L.si, c->si_host.data(), sizeof(SiDesc) * c->si_host.size(),
+                                 hipMemcpyHostToDevice, s));
+        if (!c->chunks.empty())
+            HIPCHK(c, hipMemcpyAsync(A + L.chunk, c->chunks.data(), sizeof(int32_t) * c->chunks.size(),
+                                     hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(A + L.row_x, c->row_x.data(), sizeof(float) * c->row_x.size(),
+                                 hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(A + L.w_tab, c->wtab.data(), sizeof(float) * c->wtab.size(),
+                                 hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        c->upload_dirty = false;
+    }
+    const bool tm = c->timing && c->events_ok;
+    int st = 0;
+    auto mark = [&](int i) {
+        if (tm) (void)hipEventRecord(c->ev[i], s);
+    };
+    mark(st++);
+    // reset: counters, per-sector state, row counts, bitmap, assignment
+    launch_fill_i32(a.rcnt, (int64_t)a.n_si * a.n_rows, 0, s);
+    launch_fill_i32((int32_t *)a.bits, (int64_t)a.n_words + 1, 0, s);
+    launch_fill_i32(a.assign, (int64_t)a.n_in, -1, s);
+    mark(st++);
+    launch_grid_hist(a, c->lc[1], s);  // also resets per-sector state and counters
+    mark(st++);
+    launch_grid_setup(a, s);
+    mark(st++);
+    launch_grid_scatter(a, c->lc[3], s);
+    mark(st++);
+    launch_grid_rowsort(a, c->lc[4], s);
+    mark(st++);
+    launch_links(a, c->lc[5], s);
+    mark(st++);
+    launch_seeds(a, c->lc[6], s);
+    mark(st++);
+    launch_chainlen(a, c->lc[7], s);
+    mark(st++);
+    launch_scan_popc(a.bits, a.n_words, a.wpre, &((Counters *)(A + L.cnt))->n_tracks, a.scan_tmp, s);
+    launch_track_slots(a, c->lc[8], s);
+    launch_si_tracks(a, s);
+    mark(st++);
+    launch_scan_i32_dev(a.trk_len, &((Counters *)(A + L.cnt))->n_tracks, a.trk_cap, a.cl_off,
+                        &((Counters *)(A + L.cnt))->n_cl, a.scan_tmp, s);
+    launch_si_clusters(a, s);
+    mark(st++);
+    launch_emit(a, c->lc[10], s);
+    mark(st++);
+    launch_fit(a, c->lc[11], s);
+    mark(st++);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+    c->ran = true;
+    c->have_results = true;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_synchronize(tpcca_ctx *c) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (__atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST)) {
+        __atomic_store_n(c->abort_host, 0, __ATOMIC_SEQ_CST);
+        c->have_results = false;
+        return fail(c, TPCCA_ERR_ABORTED, "run aborted");
+    }
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_stats(tpcca_ctx *c, tpcca_stats *out) {
+    if (!c || !out) return TPCCA_ERR_INVALID_ARG;
+    tpcca_stats z{};
+    *out = z;
+    if (!c->ran) return fail(c, TPCCA_ERR_STATE, "no run yet");
+    tpcca_status ss = tpcca_synchronize(c);
+    if (ss != TPCCA_OK) return ss;
+    Counters k;
+    HIPCHK(c, hipMemcpy(&k, c->arena + c->lay.cnt, sizeof(k), hipMemcpyDeviceToHost));
+    out->n_clusters = c->n_in;
+    out->n_links = k.n_links;
+    out->n_seeds = k.n_seeds;
+    out->n_tracks = k.n_tracks;
+    out->n_track_clusters = k.n_cl;
+    out->n_invalid = k.n_invalid;
+    out->n_stages = 0;
+    if (c->timing && c->events_ok) {
+        for (int i = 0; i < kNumStages; i++) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) != hipSuccess) ms = -1.f;
+            out->stage_ms[i] = ms;
+            std::snprintf(out->stage_name[i], sizeof(out->stage_name[i]), "%s", kStageNames[i]);
+        }
+        out->n_stages = kNumStages;
+    }
+    return TPCCA_OK;
+}
+
+}  // extern "C"
+
+static tpcca_status locate(tpcca_ctx *c, int32_t frame, int32_t sector, int &si, SiState &st) {
+    if (frame < 0 || frame >= (int32_t)c->frames.size() || sector < 0 || sector >= c->cfg.n_sectors)
+        return fail(c, TPCCA_ERR_INVALID_ARG, "frame or sector out of range");
+    if (!c->have_results) return fail(c, TPCCA_ERR_STATE, "no results (run first)");
+    tpcca_status s = tpcca_synchronize(c);
+    if (s != TPCCA_OK) return s;
+    si = frame * c->cfg.n_sectors + sector;
+    HIPCHK(c, hipMemcpy(&st, c->arena + c->lay.st + sizeof(SiState) * si, sizeof(SiState), hipMemcpyDeviceToHost));
+    return TPCCA_OK;
+}
+
+extern "C" {
+
+tpcca_status tpcca_get_tracks(tpcca_ctx *c, int32_t frame, int32_t sector, tpcca_track *out, int64_t cap,
+                              int64_t *n_out) {
+    if (!c || !n_out) return TPCCA_ERR_INVALID_ARG;
+    int si;
+    SiState st;
+    tpcca_status s = locate(c, frame, sector, si, st);
+    if (s != TPCCA_OK) return s;
+    *n_out = st.n_tracks;
+    if (cap < st.n_tracks) return fail(c, TPCCA_ERR_CAPACITY, "track buffer too small");
+    if (st.n_tracks > 0) {
+        if (!out) return TPCCA_ERR_INVALID_ARG;
+        HIPCHK(c, hipMemcpy(out, c->arena + c->lay.trk + sizeof(tpcca_track) * (size_t)st.trk_base,
+                            sizeof(tpcca_track) * (size_t)st.n_tracks, hipMemcpyDeviceToHost));
+    }
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_track_clusters(tpcca_ctx *c, int32_t frame, int32_t sector, int32_t *out, int64_t cap,
+                                      int64_t *n_out) {
+    if (!c || !n_out) return TPCCA_ERR_INVALID_ARG;
+    int si;
+    SiState st;
+    tpcca_status s = locate(c, frame, sector, si, st);
+    if (s != TPCCA_OK) return s;
+    *n_out = st.n_cl;
+    if (cap < st.n_cl) return fail(c, TPCCA_ERR_CAPACITY, "cluster buffer too small");
+    if (st.n_cl > 0) {
+        if (!out) return TPCCA_ERR_INVALID_ARG;
+        HIPCHK(c, hipMemcpy(out, c->arena + c->lay.clusters + sizeof(int32_t) * (size_t)st.cl_base,
+                            sizeof(int32_t) * (size_t)st.n_cl, hipMemcpyDeviceToHost));
+    }
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_assignment(tpcca_ctx *c, int32_t frame, int32_t sector, int32_t *out, int64_t n) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    int si;
+    SiState st;
+    tpcca_status s = locate(c, frame, sector, si, st);
+    if (s != TPCCA_OK) return s;
+    const SiDesc &d = c->si_host[si];
+    if (n != d.n) return fail(c, TPCCA_ERR_INVALID_ARG, "n must equal the sector's cluster count");
+    if (n > 0) {
+        if (!out) return TPCCA_ERR_INVALID_ARG;
+        HIPCHK(c, hipMemcpy(out, c->arena + c->lay.assign + sizeof(int32_t) * (size_t)d.in_base,
+                            sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost));
+    }
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_links(tpcca_ctx *c, int32_t frame, int32_t sector, int32_t cleaned, int32_t *up,
+                             int32_t *dn, int64_t n) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    int si;
+    SiState st;
+    tpcca_status s = locate(c, frame, sector, si, st);
+    if (s != TPCCA_OK) return s;
+    const SiDesc &d = c->si_host[si];
+    if (n != d.n) return fail(c, TPCCA_ERR_INVALID_ARG, "n must equal the sector's cluster count");
+    if (n == 0) return TPCCA_OK;
+    if (!up || !dn) return TPCCA_ERR_INVALID_ARG;
+    const int nv = st.n_valid;
+    std::vector<Rec> rec((size_t)nv);
+    std::vector<int2> lk((size_t)nv);
+    if (nv > 0) {
+        HIPCHK(c, hipMemcpy(rec.data(), c->arena + c->lay.rec + sizeof(Rec) * (size_t)st.sbase,
+                            sizeof(Rec) * (size_t)nv, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(lk.data(), c->arena + c->lay.link + sizeof(int2) * (size_t)st.sbase,
+                            sizeof(int2) * (size_t)nv, hipMemcpyDeviceToHost));
+    }
+    for (int64_t i = 0; i < n; i++) up[i] = dn[i] = -1;
+    const int base = st.sbase;
+    for (int p = 0; p < nv; p++) {
+        const int u = lk[p].x, dd = lk[p].y;
+        const int id = rec[p].id;
+        int uo = -1, doo = -1;
+        if (u >= 0 && (!cleaned || lk[u - base].y == p + base)) uo = rec[u - base].id;
+        if (dd >= 0 && (!cleaned || lk[dd - base].x == p + base)) doo = rec[dd - base].id;
+        up[id] = uo;
+        dn[id] = doo;
+    }
+    return TPCCA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+// Track fit: one lane per track, FP32 Kalman filter with the state
+// (y, t, sin phi, dt/darc, q/pT) and its 5x5 covariance in registers.
+//
+// The helix is transported between pad rows in closed form (exact for a
+// helix, no material): with kappa = -kB*q/pT,
+//   s' = s + kappa*dx,  dy = dx*(s+s')/(c+c'),  chord L = sqrt(dx^2+dy^2),
+//   darc = L*asin(kappa*L/2)/(kappa*L/2),  dt = tau*darc.
+// The filter starts at the innermost cluster from a three-point estimate
+// (circle through the first, middle and last cluster) which also centres
+// Gaussian priors on (sin phi, tau, q/pT). Pass 1 is an extended Kalman
+// filter; every further pass is a Kalman filter linearised about the helix of
+// the previous pass's result carried back to the first cluster, i.e. one
+// Gauss-Newton step of the maximum-a-posteriori problem, so the passes
+// converge to the MAP helix. Passes stop when one changes no parameter by
+// more than 1e-5 relative, or after kf_passes passes (status 4). Positions are kept relative to the first
+// cluster so that FP32 resolves the sagitta of short tracks.
+#include "tpcca_internal.h"
+
+namespace tpcca {
+
+// asin(u)/u and its derivative (Maclaurin series near 0)
+__device__ inline float asin_ratio(float u) {
+    if (fabsf(u) < 0.05f) {
+        const float u2 = u * u;
+        return 1.f + u2 * (1.f / 6.f + u2 * (3.f / 40.f + u2 * (5.f / 112.f)));
+    }
+    return asinf(u) / u;
+}
+__device__ inline float asin_ratio_d(float u) {
+    if (fabsf(u) < 0.05f) {
+        const float u2 = u * u;
+        return u * (1.f / 3.f + u2 * (3.f / 10.f + u2 * (15.f / 56.f)));
+    }
+    return (1.f / sqrtf(1.f - u * u) - asinf(u) / u) / u;
+}
+
+struct Jac {
+    float ys, yk, ts, tt, tk, sk;
+};
+
+// transport q by dx; Jacobian if J != nullptr; false on |sin phi| >= smax
+__device__ inline bool transport(float kB, float smax, const float q[5], float dx, float qo[5], Jac *J) {
+    const float s = q[2], tau = q[3], k = q[4];
+    const float kap = -kB * k;
+    const float s1 = s + kap * dx;
+    if (!(fabsf(s) < smax) || !(fabsf(s1) < smax)) return false;
+    const float c = sqrtf(1.f - s * s), c1 = sqrtf(1.f - s1 * s1);
+    const float S = s + s1, C = c + c1;
+    const float dy = dx * S / C;
+    const float L = sqrtf(dx * dx + dy * dy);
+    const float u = 0.5f * kap * L;
+    if (!(fabsf(u) < 1.f)) return false;
+    const float sgn = dx < 0.f ? -1.f : 1.f;
+    const float dl = sgn * L * asin_ratio(u);
+    qo[0] = q[0] + dy;
+    qo[1] = q[1] + tau * dl;
+    qo[2] = s1;
+    qo[3] = tau;
+    qo[4] = k;
+    if (J) {
+        const float iC = 1.f / C;
+        J->ys = dx * (2.f * iC + S * (s / c + s1 / c1) * iC * iC);
+        J->yk = -kB * dx * dx * (iC + S * s1 / c1 * iC * iC);
+        float dls = 0.f, dlk = 0.f;
+        if (L > 0.f) {
+            const float dldL = sgn / sqrtf(1.f - u * u);
+            dls = dldL * (dy / L) * J->ys;
+            dlk = dldL * (dy / L) * J->yk - sgn * 0.5f * L * L * asin_ratio_d(u) * kB;
+        }
+        J->ts = tau * dls;
+        J->tt = dl;
+        J->tk = tau * dlk;
+        J->sk = -kB * dx;
+    }
+    return true;
+}
+
+// d' = F d, C' = F C F^T for the sparse transport Jacobian
+__device__ inline void apply_jac(const Jac &J, float d[5], float C[5][5]) {
+    d[0] += J.ys * d[2] + J.yk * d[4];
+    d[1] += J.ts * d[2] + J.tt * d[3] + J.tk * d[4];
+    d[2] += J.sk * d[4];
+    float T[5][5];
+#pragma unroll
+    for (int b = 0; b < 5; b++) {
+        T[0][b] = C[0][b] + J.ys * C[2][b] + J.yk * C[4][b];
+        T[1][b] = C[1][b] + J.ts * C[2][b] + J.tt * C[3][b] + J.tk * C[4][b];
+        T[2][b] = C[2][b] + J.sk * C[4][b];
+        T[3][b] = C[3][b];
+        T[4][b] = C[4][b];
+    }
+#pragma unroll
+    for (int a = 0; a < 5; a++) {
+        C[a][0] = T[a][0] + J.ys * T[a][2] + J.yk * T[a][4];
+        C[a][1] = T[a][1] + J.ts * T[a][2] + J.tt * T[a][3] + J.tk * T[a][4];
+        C[a][2] = T[a][2] + J.sk * T[a][4];
+        C[a][3] = T[a][3];
+        C[a][4] = T[a][4];
+    }
+}
+
+// measurement update with (ry, rt) = measurement - prediction
+__device__ inline void kf_update(float d[5], float C[5][5], float ry, float rt, float vy, float vt) {
+    const float S00 = C[0][0] + vy, S01 = C[0][1], S11 = C[1][1] + vt;
+    const float idet = 1.f / (S00 * S11 - S01 * S01);
+    const float i00 = S11 * idet, i01 = -S01 * idet, i11 = S00 * idet;
+    float K0[5], K1[5];
+#pragma unroll
+    for (int a = 0; a < 5; a++) {
+        K0[a] = C[a][0] * i00 + C[a][1] * i01;
+        K1[a] = C[a][0] * i01 + C[a][1] * i11;
+    }
+#pragma unroll
+    for (int a = 0; a < 5; a++) d[a] += K0[a] * ry + K1[a] * rt;
+    float R0[5], R1[5];
+#pragma unroll
+    for (int b = 0; b < 5; b++) {
+        R0[b] = C[0][b];
+        R1[b] = C[1][b];
+    }
+#pragma unroll
+    for (int a = 0; a < 5; a++)
+#pragma unroll
+        for (int b = 0; b <= a; b++) {
+            const float v = C[a][b] - (K0[a] * R0[b] + K1[a] * R1[b]);
+            C[a][b] = v;
+            C[b][a] = v;
+        }
+}
+
+constexpr float kConvTol = 1e-5f;
+
+__global__ __launch_bounds__(256) void k_fit(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    const int nt = min(a.cnt->n_tracks, a.trk_cap);
+    const float kB = a.bz_kb, smax = a.s_max;
+    const float vy = a.sigma_y2, vt = a.sigma_t2;
+    const int P = a.kf_passes;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nt; g += gridDim.x * blockDim.x) {
+        const int L = a.trk_len[g];
+        const int off = a.cl_off[g];
+        const Rec e0 = a.rec[a.trk_seed[g]];
+        const int si = e0.sr >> 8;
+        const float2 *yt = a.chain_yt + off;
+        const uint8_t *rw = a.chain_row + off;
+        const float x1 = a.row_x[rw[0]];
+        const float y1 = yt[0].x, t1 = yt[0].y;
+        const int m = (L + 1) / 2 - 1;
+        const float Xm = a.row_x[rw[m]] - x1, Ym = yt[m].x - y1;
+        const float XL = a.row_x[rw[L - 1]] - x1;
+        const float YL = yt[L - 1].x - y1, TL = yt[L - 1].y - t1;
+
+        // three-point estimate at the first cluster
+        bool ok = true;
+        float q0[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        {
+            const float bcx = XL - Xm, bcy = YL - Ym;
+            const float cr = Xm * YL - Ym * XL;
+            const float dab = sqrtf(Xm * Xm + Ym * Ym), dac = sqrtf(XL * XL + YL * YL),
+                        dbc = sqrtf(bcx * bcx + bcy * bcy);
+            if (!(dab > 0.f && dac > 0.f && dbc > 0.f)) ok = false;
+            const float kap = 2.f * cr / (dab * dac * dbc);
+            const float u = 0.5f * kap * dac;
+            if (!(fabsf(u) < 1.f)) ok = false;
+            if (ok) {
+                const float phi = atan2f(YL, XL) - asinf(u);
+                if (!(cosf(phi) > 0.f)) ok = false;
+                q0[2] = sinf(phi);
+                q0[3] = TL / (dac * asin_ratio(u));
+                q0[4] = (kB != 0.f) ? -kap / kB : 0.f;
+            }
+        }
+        float ref1[5] = {q0[0], q0[1], q0[2], q0[3], q0[4]};
+        float est[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float prev[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float C[5][5];
+        float chi2 = 0.f;
+        bool conv = false;
+        for (int pass = 0; pass < P && ok; pass++) {
+            const bool ext = (pass == 0);
+            float ref[5], dev[5];
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                ref[i] = ref1[i];
+                dev[i] = q0[i] - ref1[i];
+            }
+#pragma unroll
+            for (int i = 0; i < 5; i++)
+#pragma unroll
+                for (int j = 0; j < 5; j++) C[i][j] = 0.f;
+            C[0][0] = vy;
+            C[1][1] = vt;
+            C[2][2] = a.var_s;
+            C[3][3] = a.var_tau;
+            C[4][4] = a.var_k;
+            float chi = (ref[0] * ref[0]) / vy + (ref[1] * ref[1]) / vt;
+            float Xp = 0.f;
+            for (int j = 1; j < L; j++) {
+                const float Xj = a.row_x[rw[j]] - x1;
+                const float2 m2 = yt[j];
+                float rn[5];
+                Jac J;
+                if (!transport(kB, smax, ref, Xj - Xp, rn, &J)) {
+                    ok = false;
+                    break;
+                }
+                Xp = Xj;
+                apply_jac(J, dev, C);
+#pragma unroll
+                for (int i = 0; i < 5; i++) ref[i] = rn[i];
+                const float Yj = m2.x - y1, Tj = m2.y - t1;
+                const float ey = Yj - ref[0], et = Tj - ref[1];
+                chi += (ey * ey) / vy + (et * et) / vt;
+                kf_update(dev, C, ey - dev[0], et - dev[1], vy, vt);
+                if (ext) {
+#pragma unroll
+                    for (int i = 0; i < 5; i++) {
+                        ref[i] += dev[i];
+                        dev[i] = 0.f;
+                    }
+                }
+            }
+            if (!ok) break;
+#pragma unroll
+            for (int i = 0; i < 5; i++) est[i] = ref[i] + dev[i];
+            chi2 = chi;
+            // converged once a re-linearised pass moves no parameter by more
+            // than kConvTol relative (floor 1 in every unit)
+            if (pass > 0) {
+                conv = true;
+#pragma unroll
+                for (int i = 0; i < 5; i++)
+                    conv = conv && fabsf(est[i] - prev[i]) <= kConvTol * fmaxf(fabsf(est[i]), 1.f);
+            }
+#pragma unroll
+            for (int i = 0; i < 5; i++) prev[i] = est[i];
+            if (conv) break;
+            if (pass + 1 < P) {
+                if (!transport(kB, smax, est, -Xp, ref1, nullptr)) ok = false;
+            }
+        }
+        tpcca_track o;
+        o.frame = a.si[si].frame;
+        o.sector = a.si[si].sector;
+        o.n_clusters = L;
+        o.status = ok ? (conv ? 0 : 4) : 2;
+        o.first = (int64_t)(off - a.st[si].cl_base);
+        o.seed = e0.id;
+        o.ndf = 2 * L - 5;
+        o.x_ref = a.row_x[rw[L - 1]];
+        o.t_base = yt[L - 1].y;
+        if (ok) {
+            o.y = y1 + est[0];
+            o.dt = est[1] - TL;
+            o.sinphi = est[2];
+            o.tau = est[3];
+            o.qpt = est[4];
+            o.chi2 = chi2;
+            int k = 0;
+#pragma unroll
+            for (int i = 0; i < 5; i++)
+#pragma unroll
+                for (int j = 0; j <= i; j++) o.cov[k++] = C[i][j];
+        } else {
+            o.y = o.dt = o.sinphi = o.tau = o.qpt = o.chi2 = 0.f;
+#pragma unroll
+            for (int i = 0; i < 15; i++) o.cov[i] = 0.f;
+        }
+        a.trk[g] = o;
+    }
+}
+
+void launch_fit(const KArgs &a, Launch l, hipStream_t s) {
+    hipLaunchKernelGGL(k_fit, dim3(l.grid), dim3(256), 0, s, a);
+}
+
+}  // namespace tpcca

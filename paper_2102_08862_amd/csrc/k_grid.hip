@@ -1,0 +1,404 @@
+// Search-grid construction: per sector, clusters are grouped by pad row and
+// each row is ordered by drift time (ties by input index), with coarse time
+// bins giving O(1) range lookups. The grid is an acceleration structure
+// only: neighbour candidate sets are decided by exact predicates later, so
+// the layout cannot change any result.
+//
+// Kernels (persistent, grid-stride over device-side work counts):
+//   k_si_init   reset per-sector state
+//   k_hist      per-chunk LDS row histogram + time range, validation
+//   k_si_rows   per sector: row prefix, bin geometry, tiles per row
+//   k_si_prefix sorted-space base and tile base of every sector
+//   k_scatter   stable-free scatter of clusters into row segments (LDS ranks)
+//   k_rowsort   per (sector,row): fine-bin counting sort in LDS, then an
+//               in-place sort of each fine bin by (t, id); writes the coarse
+//               bin offsets used by the neighbour tiles
+#include "tpcca_internal.h"
+
+namespace tpcca {
+
+__device__ inline bool valid_cluster(int r, float y, float t, int n_rows) {
+    return r < n_rows && __builtin_isfinite(y) && __builtin_isfinite(t);
+}
+
+__device__ inline float bin_coord(float t, float t0, float inv) {
+    return __fmul_rn(__fsub_rn(t, t0), inv);
+}
+
+__global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t n4 = n >> 2;
+    int4 v4 = make_int4(v, v, v, v);
+    int4 *p4 = reinterpret_cast<int4 *>(p);
+    for (int64_t k = i; k < n4; k += stride) p4[k] = v4;
+    for (int64_t k = (n4 << 2) + i; k < n; k += stride) p[k] = v;
+}
+
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t blocks = ((n >> 2) + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+}
+
+__global__ void k_si_init(KArgs a) {
+    for (int si = blockIdx.x * blockDim.x + threadIdx.x; si < a.n_si; si += gridDim.x * blockDim.x) {
+        SiState z = {};
+        z.tmin_key = 0xffffffffu;
+        z.tmax_key = 0u;
+        a.st[si] = z;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Counters c = {};
+        *a.cnt = c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_hist(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    __shared__ int32_t h[kMaxRows];
+    __shared__ uint32_t smin, smax;
+    __shared__ int32_t sinv;
+    const int R = a.n_rows;
+    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
+        const int si = a.chunk[2 * c], start = a.chunk[2 * c + 1];
+        const SiDesc d = a.si[si];
+        const int end = min(start + kChunk, d.n);
+        for (int r = threadIdx.x; r < R; r += blockDim.x) h[r] = 0;
+        if (threadIdx.x == 0) {
+            smin = 0xffffffffu;
+            smax = 0u;
+            sinv = 0;
+        }
+        __syncthreads();
+        uint32_t lmin = 0xffffffffu, lmax = 0u;
+        int linv = 0;
+        for (int i = start + threadIdx.x; i < end; i += blockDim.x) {
+            const int r = d.row[i];
+            const float y = d.y[i], t = d.t[i];
+            if (valid_cluster(r, y, t, R)) {
+                atomicAdd(&h[r], 1);
+                const uint32_t k = fkey(t);
+                lmin = min(lmin, k);
+                lmax = max(lmax, k);
+            } else {
+                linv++;
+            }
+        }
+        // wave reductions, then one LDS atomic per wave
+        for (int off = 32; off > 0; off >>= 1) {
+            lmin = min(lmin, (uint32_t)__shfl_xor((int)lmin, off));
+            lmax = max(lmax, (uint32_t)__shfl_xor((int)lmax, off));
+            linv += __shfl_xor(linv, off);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(&smin, lmin);
+            atomicMax(&smax, lmax);
+            if (linv) atomicAdd(&sinv, linv);
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < R; r += blockDim.x)
+            if (h[r]) atomicAdd(&a.rcnt[si * R + r], h[r]);
+        if (threadIdx.x == 0) {
+            if (smax >= smin) {
+                atomicMin(&a.st[si].tmin_key, smin);
+                atomicMax(&a.st[si].tmax_key, smax);
+            }
+            if (sinv) atomicAdd(&a.cnt->n_invalid, sinv);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
+    __shared__ int32_t sc[256];
+    const int R = a.n_rows;
+    const int r = threadIdx.x;
+    for (int si = blockIdx.x; si < a.n_si; si += gridDim.x) {
+        const int v = (r < R) ? a.rcnt[si * R + r] : 0;
+        sc[r] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int x = (r >= off) ? sc[r - off] : 0;
+            __syncthreads();
+            sc[r] += x;
+            __syncthreads();
+        }
+        if (r < R) {
+            a.rstart[si * R + r] = sc[r] - v;
+            a.rcur[si * R + r] = sc[r] - v;
+        }
+        if (r == 0) {
+            SiState s = a.st[si];
+            const int nv = sc[255];
+            float tmin = 0.f, tmax = 0.f;
+            if (nv > 0) {
+                tmin = fkey_inv(s.tmin_key);
+                tmax = fkey_inv(s.tmax_key);
+            }
+            const float range = __fsub_rn(tmax, tmin);
+            float inv;
+            int ncb;
+            if (__builtin_isfinite(range)) {
+                const float cbw = fmaxf(a.cbw_min, range / (float)(kNcbMax - 4));
+                inv = 1.0f / cbw;
+                ncb = (int)__fmul_rn(range, inv) + 1;
+                ncb = min(max(ncb, 1), kNcbMax);
+            } else {
+                inv = 0.f;
+                ncb = 1;
+            }
+            s.t0 = tmin;
+            s.inv_cbw = inv;
+            s.ncb = ncb;
+            s.nslab = nv > 0 ? (ncb + kTileCb - 1) / kTileCb : 0;
+            s.n_valid = nv;
+            a.st[si] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// exclusive block scan of two ints over blockDim (<= 1024) threads
+__device__ inline void block_scan2(int &v0, int &v1, int &tot0, int &tot1, int *sh0, int *sh1) {
+    const int tid = threadIdx.x, n = blockDim.x;
+    sh0[tid] = v0;
+    sh1[tid] = v1;
+    __syncthreads();
+    for (int off = 1; off < n; off <<= 1) {
+        const int x0 = (tid >= off) ? sh0[tid - off] : 0;
+        const int x1 = (tid >= off) ? sh1[tid - off] : 0;
+        __syncthreads();
+        sh0[tid] += x0;
+        sh1[tid] += x1;
+        __syncthreads();
+    }
+    tot0 = sh0[n - 1];
+    tot1 = sh1[n - 1];
+    v0 = sh0[tid] - v0;
+    v1 = sh1[tid] - v1;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_si_prefix(KArgs a) {
+    __shared__ int sh0[1024], sh1[1024];
+    int carry_s = 0, carry_t = 0;
+    for (int base = 0; base < a.n_si; base += blockDim.x) {
+        const int si = base + threadIdx.x;
+        int nv = 0, nt = 0;
+        if (si < a.n_si) {
+            nv = a.st[si].n_valid;
+            nt = a.st[si].nslab * a.n_rows;
+        }
+        int tv, tt;
+        block_scan2(nv, nt, tv, tt, sh0, sh1);
+        if (si < a.n_si) {
+            a.st[si].sbase = carry_s + nv;
+            a.st[si].tile_base = carry_t + nt;
+        }
+        carry_s += tv;
+        carry_t += tt;
+    }
+    if (threadIdx.x == 0) {
+        a.cnt->n_valid_total = carry_s;
+        a.cnt->n_tiles = carry_t;
+    }
+}
+
+void launch_grid_hist(const KArgs &a, Launch l, hipStream_t s) {
+    int g = a.n_si < 1 ? 1 : a.n_si;
+    hipLaunchKernelGGL(k_si_init, dim3((g + 255) / 256), dim3(256), 0, s, a);
+    if (a.n_chunks > 0)
+        hipLaunchKernelGGL(k_hist, dim3(min(l.grid, a.n_chunks)), dim3(256), 0, s, a);
+}
+
+void launch_grid_setup(const KArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_si_rows, dim3(min(a.n_si, 4096)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_si_prefix, dim3(1), dim3(1024), 0, s, a);
+}
+
+__global__ __launch_bounds__(256) void k_scatter(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    __shared__ int32_t h[kMaxRows], gb[kMaxRows];
+    const int R = a.n_rows;
+    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
+        const int si = a.chunk[2 * c], start = a.chunk[2 * c + 1];
+        const SiDesc d = a.si[si];
+        const int end = min(start + kChunk, d.n);
+        const int sbase = a.st[si].sbase;
+        for (int r = threadIdx.x; r < R; r += blockDim.x) h[r] = 0;
+        __syncthreads();
+        for (int i = start + threadIdx.x; i < end; i += blockDim.x) {
+            const int r = d.row[i];
+            if (valid_cluster(r, d.y[i], d.t[i], R)) atomicAdd(&h[r], 1);
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < R; r += blockDim.x) {
+            const int k = h[r];
+            gb[r] = k ? sbase + atomicAdd(&a.rcur[si * R + r], k) : 0;
+            h[r] = 0;
+        }
+        __syncthreads();
+        for (int i = start + threadIdx.x; i < end; i += blockDim.x) {
+            const int r = d.row[i];
+            const float y = d.y[i], t = d.t[i];
+            if (valid_cluster(r, y, t, R)) {
+                const int slot = gb[r] + atomicAdd(&h[r], 1);
+                Rec e;
+                e.y = y;
+                e.t = t;
+                e.id = i;
+                e.sr = (si << 8) | r;
+                a.tmp[slot] = e;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s) {
+    if (a.n_chunks > 0)
+        hipLaunchKernelGGL(k_scatter, dim3(min(l.grid, a.n_chunks)), dim3(256), 0, s, a);
+}
+
+__device__ inline bool rec_less(float ta, int ia, float tb, int ib) {
+    return ta < tb || (ta == tb && ia < ib);
+}
+
+// sort k (> 1) records in place by (t, id)
+__device__ void sort_bin(Rec *__restrict__ p, int k) {
+    if (k <= 8) {
+        float ky[8], kt[8];
+        int kid[8], ksr[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if (j < k) {
+                const Rec e = p[j];
+                ky[j] = e.y;
+                kt[j] = e.t;
+                kid[j] = e.id;
+                ksr[j] = e.sr;
+            } else {
+                ky[j] = 0.f;
+                kt[j] = __builtin_inff();
+                kid[j] = 0x7fffffff;
+                ksr[j] = 0;
+            }
+        }
+#pragma unroll
+        for (int round = 0; round < 8; round++) {
+#pragma unroll
+            for (int j = (round & 1); j + 1 < 8; j += 2) {
+                if (rec_less(kt[j + 1], kid[j + 1], kt[j], kid[j])) {
+                    float fy = ky[j]; ky[j] = ky[j + 1]; ky[j + 1] = fy;
+                    float ft = kt[j]; kt[j] = kt[j + 1]; kt[j + 1] = ft;
+                    int fi = kid[j]; kid[j] = kid[j + 1]; kid[j + 1] = fi;
+                    int fs = ksr[j]; ksr[j] = ksr[j + 1]; ksr[j + 1] = fs;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if (j < k) {
+                Rec e;
+                e.y = ky[j];
+                e.t = kt[j];
+                e.id = kid[j];
+                e.sr = ksr[j];
+                p[j] = e;
+            }
+        }
+    } else {
+        for (int i = 1; i < k; i++) {
+            const Rec e = p[i];
+            int j = i - 1;
+            while (j >= 0 && rec_less(e.t, e.id, p[j].t, p[j].id)) {
+                p[j + 1] = p[j];
+                j--;
+            }
+            p[j + 1] = e;
+        }
+    }
+}
+
+constexpr int kFineMax = kNcbMax * kFinePerCb;
+constexpr int kSortBlock = 512;
+
+__global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    __shared__ int32_t fh[kFineMax];
+    __shared__ int32_t part[kSortBlock];
+    const int R = a.n_rows;
+    const int nseg = a.n_si * R;
+    const int tid = threadIdx.x, bd = blockDim.x;
+    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        const int si = seg / R;
+        const SiState s = a.st[si];
+        const int n = a.rcnt[seg];
+        const int start = s.sbase + a.rstart[seg];
+        const int ncb = s.ncb, nf = ncb * kFinePerCb;
+        const float t0 = s.t0, inv = s.inv_cbw;
+        int32_t *co = a.coff + (int64_t)seg * (kNcbMax + 1);
+        if (n == 0) {
+            for (int cb = tid; cb <= ncb; cb += bd) co[cb] = start;
+            continue;
+        }
+        for (int b = tid; b < nf; b += bd) fh[b] = 0;
+        __syncthreads();
+        for (int k = tid; k < n; k += bd) {
+            const float v = bin_coord(a.tmp[start + k].t, t0, inv);
+            const int fb = min((int)__fmul_rn(v, (float)kFinePerCb), nf - 1);
+            atomicAdd(&fh[fb], 1);
+        }
+        __syncthreads();
+        // exclusive scan of fh[0, nf)
+        const int per = (nf + bd - 1) / bd;
+        const int lo = min(tid * per, nf), hi = min(lo + per, nf);
+        int sum = 0;
+        for (int b = lo; b < hi; b++) sum += fh[b];
+        part[tid] = sum;
+        __syncthreads();
+        for (int off = 1; off < bd; off <<= 1) {
+            const int x = (tid >= off) ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += x;
+            __syncthreads();
+        }
+        int run = part[tid] - sum;
+        for (int b = lo; b < hi; b++) {
+            const int v = fh[b];
+            fh[b] = run;
+            run += v;
+        }
+        __syncthreads();
+        for (int cb = tid; cb <= ncb; cb += bd) co[cb] = start + (cb < ncb ? fh[cb * kFinePerCb] : n);
+        __syncthreads();
+        for (int k = tid; k < n; k += bd) {
+            const Rec e = a.tmp[start + k];
+            const float v = bin_coord(e.t, t0, inv);
+            const int fb = min((int)__fmul_rn(v, (float)kFinePerCb), nf - 1);
+            const int slot = atomicAdd(&fh[fb], 1);
+            a.rec[start + slot] = e;
+        }
+        __threadfence_block();
+        __syncthreads();
+        // fh[b] now holds the end of fine bin b
+        for (int b = tid; b < nf; b += bd) {
+            const int blo = b ? fh[b - 1] : 0;
+            const int bhi = fh[b];
+            if (bhi - blo > 1) sort_bin(a.rec + start + blo, bhi - blo);
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+void launch_grid_rowsort(const KArgs &a, Launch l, hipStream_t s) {
+    const int nseg = a.n_si * a.n_rows;
+    if (nseg > 0)
+        hipLaunchKernelGGL(k_rowsort, dim3(min(l.grid, nseg)), dim3(kSortBlock), 0, s, a);
+}
+
+}  // namespace tpcca

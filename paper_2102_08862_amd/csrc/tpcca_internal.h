@@ -1,0 +1,176 @@
+// Internal definitions shared by the HIP kernels and the host side of the
+// tracker library. Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tpcca.h"
+
+namespace tpcca {
+
+constexpr int kMaxRows = 255;      // rows are uint8
+constexpr int kMaxGap = 2;         // symmetric row gaps handled by the link kernel
+constexpr int kNcbMax = 2048;      // coarse time bins per sector row (upper bound)
+constexpr int kFinePerCb = 4;      // fine bins per coarse bin (row sort)
+constexpr int kTileCb = 16;        // coarse bins per neighbour-finding tile
+constexpr int kChunk = 8192;       // clusters per histogram / scatter work item
+constexpr int kStageCap = 1024;    // clusters of one neighbour row staged in LDS per tile
+constexpr int kScanItems = 2048;   // elements per block of the device-wide scans
+constexpr int kMaxStages = 16;
+
+// One sector of one frame ("sector instance"), uploaded by the host.
+struct SiDesc {
+    const uint8_t *row;
+    const float *y;
+    const float *t;
+    int32_t n;          // input clusters
+    int32_t in_base;    // offset of the sector's input indices in the job (assignment space)
+    int32_t frame, sector;
+    int32_t word_base;  // first word of the sector's track-seed bitmap
+    int32_t nwords;
+};
+
+// Per sector instance, computed on the device during a run.
+struct SiState {
+    uint32_t tmin_key, tmax_key;   // order-preserving keys of the time range
+    float t0;                      // time origin of the bins
+    float inv_cbw;                 // 1 / coarse bin width
+    int32_t ncb;                   // coarse bins per row
+    int32_t nslab;                 // neighbour tiles per row
+    int32_t n_valid;               // clusters that passed validation
+    int32_t sbase;                 // first position of the sector in the sorted space
+    int32_t tile_base;             // first neighbour tile of the sector
+    int32_t trk_base, n_tracks;    // first global track slot, number of tracks
+    int32_t cl_base, n_cl;         // first entry in the cluster lists, entries
+    int32_t pad[3];
+};
+
+// Device counters of one run (zeroed at the start of the run).
+struct Counters {
+    int32_t n_valid_total;
+    int32_t n_tiles;
+    int32_t n_links;
+    int32_t n_seeds;
+    int32_t n_tseeds;
+    int32_t n_tracks;
+    int32_t n_cl;
+    int32_t n_invalid;
+    int32_t overflow;
+    int32_t pad[7];
+};
+
+// A cluster in the sorted space: 16 bytes, one load per chain step.
+struct Rec {
+    float y, t;
+    int32_t id;   // sector-local input index
+    int32_t sr;   // (sector instance << 8) | row
+};
+
+// Everything a kernel needs, passed by value.
+struct KArgs {
+    // job shape
+    int32_t n_si;
+    int32_t n_rows;
+    int32_t n_in;            // input clusters of the job (sum of n)
+    int32_t n_chunks;
+    int32_t n_words;
+    int32_t seed_cap, tseed_cap, trk_cap;
+    // constants of the method
+    int32_t max_gap, min_track_hits, kf_passes;
+    float win_y[kMaxGap], win_t[kMaxGap];   // (float)g * win, computed on the host
+    float pair_c2;
+    float cbw_min;
+    float bz_kb;             // 2.99792458e-3 * Bz
+    float sigma_y2, sigma_t2;
+    float var_s, var_tau, var_k;
+    float s_max;
+    // tables
+    const float *row_x;      // [n_rows]
+    const float *w_tab;      // [n_rows * kMaxGap], (x_r - x_{r-g}) / (x_{r+g} - x_{r-g})
+    // buffers
+    const SiDesc *si;
+    SiState *st;
+    Counters *cnt;
+    const int32_t *chunk;    // [2 * n_chunks] (si, start)
+    int32_t *rcnt;           // [n_si * n_rows]
+    int32_t *rstart;         // [n_si * n_rows] local exclusive prefix
+    int32_t *rcur;           // [n_si * n_rows]
+    int32_t *coff;           // [n_si * n_rows * (kNcbMax + 1)] global sorted positions
+    Rec *tmp;                // [n_in]
+    Rec *rec;                // [n_in]
+    int2 *link;              // [n_in] (up, dn) as sorted positions
+    int32_t *seeds;          // [seed_cap]
+    int32_t *tseed;          // [tseed_cap]
+    int32_t *tlen;           // [tseed_cap]
+    int32_t *tslot;          // [tseed_cap]
+    uint32_t *bits;          // [n_words]
+    int32_t *wpre;           // [n_words + 1]
+    int32_t *trk_len;        // [trk_cap + 1]
+    int32_t *trk_seed;       // [trk_cap]
+    int32_t *cl_off;         // [trk_cap + 1]
+    tpcca_track *trk;        // [trk_cap]
+    int32_t *clusters;       // [n_in]
+    float2 *chain_yt;        // [n_in]
+    uint8_t *chain_row;      // [n_in]
+    int32_t *assign;         // [n_in]
+    int32_t *scan_tmp;       // block sums of the scans
+    const volatile int32_t *abort_flag;  // host-mapped
+};
+
+// Order-preserving map of a float to an unsigned key.
+__host__ __device__ inline uint32_t fkey(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float fkey_inv(uint32_t k) {
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// The host's abort request (host-mapped memory, read with a system-scope
+// load). It only goes from 0 to 1 during a run, so once a kernel sees it set
+// every later kernel of the run sees it too: a kernel that checks it at block
+// start therefore never consumes the output of a kernel that stopped early.
+__device__ inline bool abort_requested(const KArgs &a) {
+    return __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+}
+
+// Block-uniform abort check at kernel start (uses one LDS word).
+#define TPCCA_ABORT_GUARD(a)                                   \
+    do {                                                       \
+        __shared__ int s_abort_guard;                          \
+        if (threadIdx.x == 0) s_abort_guard = abort_requested(a); \
+        __syncthreads();                                       \
+        if (s_abort_guard) return;                             \
+    } while (0)
+
+// Kernel launchers (one per stage); each enqueues on `s`.
+struct Launch {
+    int grid;    // persistent grid size (blocks)
+    int block;   // threads per block
+};
+
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+void launch_grid_hist(const KArgs &a, Launch l, hipStream_t s);
+void launch_grid_setup(const KArgs &a, hipStream_t s);
+void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s);
+void launch_grid_rowsort(const KArgs &a, Launch l, hipStream_t s);
+void launch_links(const KArgs &a, Launch l, hipStream_t s);
+void launch_seeds(const KArgs &a, Launch l, hipStream_t s);
+void launch_chainlen(const KArgs &a, Launch l, hipStream_t s);
+void launch_track_slots(const KArgs &a, Launch l, hipStream_t s);
+void launch_emit(const KArgs &a, Launch l, hipStream_t s);
+void launch_fit(const KArgs &a, Launch l, hipStream_t s);
+// exclusive scans: out[i] = sum_{j<i} f(in[j]), out[n] = total, *total_dst = total
+void launch_scan_popc(const uint32_t *in, int32_t n, int32_t *out, int32_t *total_dst, int32_t *tmp,
+                      hipStream_t s);
+void launch_scan_i32_dev(const int32_t *in, const int32_t *n_dev, int32_t n_cap, int32_t *out,
+                         int32_t *total_dst, int32_t *tmp, hipStream_t s);
+void launch_si_tracks(const KArgs &a, hipStream_t s);
+void launch_si_clusters(const KArgs &a, hipStream_t s);
+
+}  // namespace tpcca

@@ -1,0 +1,324 @@
+"""Python binding of libtpcca.so (the MI355X TPC track finder).
+
+Argument marshalling only: every step of the tracking runs in the library's
+HIP kernels. PyTorch provides the device memory (the arena and, optionally,
+device-resident inputs) and the stream. There is no CPU fallback: if the
+library is not built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpcca.so")
+HEADER = os.path.join(_HERE, "..", "include", "tpcca.h")
+
+OK, ERR_INVALID_ARG, ERR_NOMEM, ERR_CAPACITY, ERR_STATE, ERR_DEVICE, ERR_ABORTED = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "NOMEM", -3: "CAPACITY", -4: "STATE", -5: "DEVICE", -6: "ABORTED"}
+
+
+class TpccaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("tpcca %s: %s" % (_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("bz_tesla", ctypes.c_float),
+        ("n_sectors", ctypes.c_int32),
+        ("n_rows", ctypes.c_int32),
+        ("row_x", ctypes.POINTER(ctypes.c_float)),
+        ("sigma_y", ctypes.c_float), ("sigma_t", ctypes.c_float),
+        ("win_y", ctypes.c_float), ("win_t", ctypes.c_float),
+        ("pair_c2", ctypes.c_float),
+        ("max_gap", ctypes.c_int32),
+        ("min_track_hits", ctypes.c_int32),
+        ("prior_var_sinphi", ctypes.c_float),
+        ("prior_var_tau", ctypes.c_float),
+        ("prior_var_qpt", ctypes.c_float),
+        ("kf_passes", ctypes.c_int32),
+        ("s_max", ctypes.c_float),
+        ("use_mlp", ctypes.c_int32),
+        ("mlp_logit_threshold", ctypes.c_float),
+    ]
+
+
+TRACK_DTYPE = np.dtype([
+    ("frame", np.int32), ("sector", np.int32), ("n_clusters", np.int32), ("status", np.int32),
+    ("first", np.int64), ("seed", np.int32), ("ndf", np.int32),
+    ("x_ref", np.float32), ("y", np.float32), ("t_base", np.float32), ("dt", np.float32),
+    ("sinphi", np.float32), ("tau", np.float32), ("qpt", np.float32), ("chi2", np.float32),
+    ("cov", np.float32, (15,)),
+], align=True)
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_clusters", ctypes.c_int64), ("n_links", ctypes.c_int64), ("n_seeds", ctypes.c_int64),
+        ("n_tracks", ctypes.c_int64), ("n_track_clusters", ctypes.c_int64), ("n_invalid", ctypes.c_int64),
+        ("n_stages", ctypes.c_int32),
+        ("stage_ms", ctypes.c_float * 16),
+        ("stage_name", (ctypes.c_char * 24) * 16),
+    ]
+
+
+# every entry point declared in include/tpcca.h
+EXPORTS = [
+    "tpcca_config_default", "tpcca_create", "tpcca_destroy", "tpcca_last_error", "tpcca_set_stream",
+    "tpcca_add_frame", "tpcca_clear_frames", "tpcca_load_sector", "tpcca_required_arena",
+    "tpcca_attach_arena", "tpcca_run", "tpcca_synchronize", "tpcca_request_abort", "tpcca_set_timing",
+    "tpcca_get_stats", "tpcca_get_tracks", "tpcca_get_track_clusters", "tpcca_get_assignment",
+    "tpcca_get_links",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtpcca.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libtpcca.so is not built (run __graft_entry__.build() or "
+                           "python paper_2102_08862_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "tpcca_config_default": [ctypes.POINTER(Config)],
+        "tpcca_create": [ctypes.POINTER(Config), ctypes.POINTER(P)],
+        "tpcca_set_stream": [P, P],
+        "tpcca_add_frame": [P, ctypes.POINTER(I32)],
+        "tpcca_clear_frames": [P],
+        "tpcca_load_sector": [P, I32, I32, I64, P, P, P, I32],
+        "tpcca_required_arena": [P, ctypes.POINTER(SZ)],
+        "tpcca_attach_arena": [P, P, SZ],
+        "tpcca_run": [P],
+        "tpcca_synchronize": [P],
+        "tpcca_request_abort": [P],
+        "tpcca_set_timing": [P, I32],
+        "tpcca_get_stats": [P, ctypes.POINTER(Stats)],
+        "tpcca_get_tracks": [P, I32, I32, P, I64, ctypes.POINTER(I64)],
+        "tpcca_get_track_clusters": [P, I32, I32, P, I64, ctypes.POINTER(I64)],
+        "tpcca_get_assignment": [P, I32, I32, P, I64],
+        "tpcca_get_links": [P, I32, I32, I32, P, P, I64],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.tpcca_destroy.argtypes = [P]
+    lib.tpcca_destroy.restype = None
+    lib.tpcca_last_error.argtypes = [P]
+    lib.tpcca_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def default_config() -> Config:
+    lib = load_library()
+    c = Config()
+    lib.tpcca_config_default(ctypes.byref(c))
+    return c
+
+
+class Tracker:
+    """One tracking context on the current GPU (torch's current device)."""
+
+    def __init__(self, config: Config | None = None, **overrides):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the TPC tracker needs a GPU (no CPU fallback)")
+        self._torch = torch
+        self.lib = load_library()
+        cfg = config if config is not None else default_config()
+        self._row_x_keep = None
+        for k, v in overrides.items():
+            if k == "row_x":
+                arr = np.ascontiguousarray(v, np.float32)
+                self._row_x_keep = arr
+                cfg.row_x = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+                cfg.n_rows = len(arr)
+            else:
+                setattr(cfg, k, v)
+        self.config = cfg
+        h = ctypes.c_void_p()
+        self._check(self.lib.tpcca_create(ctypes.byref(cfg), ctypes.byref(h)), None)
+        self.h = h
+        self.arena = None
+        self._keep = []          # device inputs borrowed by the library
+        self.n_frames = 0
+        self.sector_n = {}
+        self.set_stream(torch.cuda.current_stream())
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, st, h=-1):
+        if st != OK:
+            hh = self.h if h == -1 else h
+            msg = self.lib.tpcca_last_error(hh).decode() if hh else ""
+            raise TpccaError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tpcca_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        self._check(self.lib.tpcca_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)))
+
+    # ------------------------------------------------------------- inputs
+    def add_frame(self) -> int:
+        f = ctypes.c_int32()
+        self._check(self.lib.tpcca_add_frame(self.h, ctypes.byref(f)))
+        self.n_frames = f.value + 1
+        return f.value
+
+    def clear_frames(self):
+        self._check(self.lib.tpcca_clear_frames(self.h))
+        self._keep = []
+        self.sector_n = {}
+        self.n_frames = 0
+
+    def load_sector(self, frame, sector, row, y, t, device: bool = True):
+        """Give one sector's clusters. numpy arrays (host, copied) or torch
+        device tensors (borrowed); with device=True numpy inputs are first
+        moved to device tensors that this object keeps alive."""
+        torch = self._torch
+        n = len(row)
+        if isinstance(row, torch.Tensor):
+            tr, ty, tt = row, y, t
+            assert tr.is_cuda and tr.dtype == torch.uint8 and ty.dtype == torch.float32 and tt.dtype == torch.float32
+            assert tr.is_contiguous() and ty.is_contiguous() and tt.is_contiguous()
+            self._keep += [tr, ty, tt]
+            ptrs = (tr.data_ptr(), ty.data_ptr(), tt.data_ptr())
+            is_dev = 1
+        elif device:
+            tr = torch.from_numpy(np.ascontiguousarray(row, np.uint8)).cuda()
+            ty = torch.from_numpy(np.ascontiguousarray(y, np.float32)).cuda()
+            tt = torch.from_numpy(np.ascontiguousarray(t, np.float32)).cuda()
+            torch.cuda.synchronize()
+            self._keep += [tr, ty, tt]
+            ptrs = (tr.data_ptr(), ty.data_ptr(), tt.data_ptr())
+            is_dev = 1
+        else:
+            r = np.ascontiguousarray(row, np.uint8)
+            yy = np.ascontiguousarray(y, np.float32)
+            ttt = np.ascontiguousarray(t, np.float32)
+            ptrs = (r.ctypes.data, yy.ctypes.data, ttt.ctypes.data)
+            is_dev = 0
+        if n == 0:
+            ptrs = (None, None, None)
+        self._check(self.lib.tpcca_load_sector(self.h, frame, sector, n, ptrs[0], ptrs[1], ptrs[2], is_dev))
+        self.sector_n[(frame, sector)] = n
+
+    def load_frame(self, fr, frame=None, device: bool = True, sectors=None):
+        """Load every sector of a generated frame (paper_2102_08862_amd.synth.Frame)."""
+        if frame is None:
+            frame = self.add_frame()
+        ss = range(len(fr.rows)) if sectors is None else sectors
+        for s in ss:
+            self.load_sector(frame, s, fr.rows[s], fr.ys[s], fr.ts[s], device=device)
+        return frame
+
+    def load_frame_packed(self, fr, frame=None):
+        """Copy a whole frame into three device tensors (one H2D each) and
+        load every sector as a borrowed slice of them."""
+        torch = self._torch
+        if frame is None:
+            frame = self.add_frame()
+        ns = [len(r) for r in fr.rows]
+        off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+        row = torch.from_numpy(np.concatenate(fr.rows) if off[-1] else np.zeros(0, np.uint8)).cuda()
+        y = torch.from_numpy(np.concatenate(fr.ys) if off[-1] else np.zeros(0, np.float32)).cuda()
+        t = torch.from_numpy(np.concatenate(fr.ts) if off[-1] else np.zeros(0, np.float32)).cuda()
+        torch.cuda.synchronize()
+        for s, n in enumerate(ns):
+            a, b = int(off[s]), int(off[s + 1])
+            self.load_sector(frame, s, row[a:b], y[a:b], t[a:b])
+        return frame
+
+    # ---------------------------------------------------------------- run
+    def required_arena(self) -> int:
+        b = ctypes.c_size_t()
+        self._check(self.lib.tpcca_required_arena(self.h, ctypes.byref(b)))
+        return b.value
+
+    def ensure_arena(self):
+        need = self.required_arena()
+        if self.arena is None or self.arena.numel() < need:
+            self.arena = None
+            self.arena = self._torch.empty(need + 4096, dtype=self._torch.uint8, device="cuda")
+            base = self.arena.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            self._check(self.lib.tpcca_attach_arena(self.h, ctypes.c_void_p(aligned), need))
+        return need
+
+    def run(self, sync: bool = False):
+        self.ensure_arena()
+        self._check(self.lib.tpcca_run(self.h))
+        if sync:
+            self.synchronize()
+
+    def synchronize(self):
+        self._check(self.lib.tpcca_synchronize(self.h))
+
+    def request_abort(self):
+        self._check(self.lib.tpcca_request_abort(self.h))
+
+    def set_timing(self, on: bool):
+        self._check(self.lib.tpcca_set_timing(self.h, 1 if on else 0))
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.tpcca_get_stats(self.h, ctypes.byref(s)))
+        d = {k: getattr(s, k) for k in ("n_clusters", "n_links", "n_seeds", "n_tracks", "n_track_clusters",
+                                        "n_invalid")}
+        d["stage_ms"] = {s.stage_name[i].value.decode(): s.stage_ms[i] for i in range(s.n_stages)}
+        return d
+
+    # ------------------------------------------------------------ outputs
+    def tracks(self, frame, sector) -> np.ndarray:
+        n = ctypes.c_int64()
+        st = self.lib.tpcca_get_tracks(self.h, frame, sector, None, 0, ctypes.byref(n))
+        if st not in (OK, ERR_CAPACITY):
+            self._check(st)
+        out = np.zeros(n.value, TRACK_DTYPE)
+        if n.value:
+            self._check(self.lib.tpcca_get_tracks(self.h, frame, sector, out.ctypes.data, n.value, ctypes.byref(n)))
+        return out
+
+    def track_clusters(self, frame, sector) -> np.ndarray:
+        n = ctypes.c_int64()
+        st = self.lib.tpcca_get_track_clusters(self.h, frame, sector, None, 0, ctypes.byref(n))
+        if st not in (OK, ERR_CAPACITY):
+            self._check(st)
+        out = np.zeros(n.value, np.int32)
+        if n.value:
+            self._check(self.lib.tpcca_get_track_clusters(self.h, frame, sector, out.ctypes.data, n.value,
+                                                          ctypes.byref(n)))
+        return out
+
+    def assignment(self, frame, sector) -> np.ndarray:
+        n = self.sector_n.get((frame, sector), 0)
+        out = np.zeros(n, np.int32)
+        self._check(self.lib.tpcca_get_assignment(self.h, frame, sector, out.ctypes.data if n else None, n))
+        return out
+
+    def links(self, frame, sector, cleaned: bool = False):
+        n = self.sector_n.get((frame, sector), 0)
+        up = np.zeros(n, np.int32)
+        dn = np.zeros(n, np.int32)
+        self._check(self.lib.tpcca_get_links(self.h, frame, sector, 1 if cleaned else 0,
+                                             up.ctypes.data if n else None, dn.ctypes.data if n else None, n))
+        return up, dn
