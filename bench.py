@@ -1,0 +1,191 @@
+"""Throughput of the MI355X TPC track finder: clusters tracked per second.
+
+One step = one pass of the whole hot path (search grid, neighbour links,
+cleaning and CA chains, canonical output, iterated Kalman fit) over one whole
+synthetic 10 ms Pb-Pb time frame (36 sectors, 500 collisions at 50 kHz,
+~1.45e8 clusters), with the frame already resident in HBM. Prints one JSON
+line (rank 0) with the throughput, the roofline position of the dominant
+kernel (per-stage device times from HIP events recorded on the run's stream
+over the timed region) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector
+
+# Algorithmic traffic of each stage (what the method must move), bytes per
+# unit; the unit is given by the function of the run's counts.
+#   hist:    row + y + t read (validation)                          9 B/cluster
+#   scatter: row + y + t read, 16-byte record written               25 B/cluster
+#   rowsort: record read, record written                            32 B/cluster
+#   links:   own record read, (up, dn) link written                 24 B/cluster
+#   seeds:   link read                                              8 B/cluster
+#   emit:    record + link read; list, assignment, chain copy (y,t,row)
+#            written                                                41 B/track cluster
+#   fit:     chain copy (y, t, row) read, 128-byte record written  9 B/track cluster + 128 B/track
+STAGE_BYTES = {
+    "hist": lambda s: 9 * s["n_clusters"],
+    "scatter": lambda s: 25 * s["n_clusters"],
+    "rowsort": lambda s: 32 * s["n_clusters"],
+    "links": lambda s: 24 * s["n_clusters"],
+    "seeds": lambda s: 8 * s["n_clusters"],
+    "emit": lambda s: 41 * s["n_track_clusters"],
+    "fit": lambda s: 9 * s["n_track_clusters"] + 128 * s["n_tracks"],
+}
+
+WORKLOADS = {
+    "frame_10ms": "whole 10 ms TPC time frame: 36 sectors x 152 rows, 500 Pb-Pb collisions at 50 kHz "
+                  "(multiplicity Exp(2000) truncated at 15000, |eta|<0.9, pT=0.1+Exp(0.6) GeV), 0.5 T, "
+                  "sigma 0.1 cm, 5% noise, drift time as coordinate",
+    "slice_1ms": "1 ms continuous TPC slice: 36 sectors, 50 collisions, same generator",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(fr, n_sectors: int):
+    """The CPU oracle (whole path: links, cleaning, chains, MAP fit) on the
+    first n_sectors sectors of the same frame, one thread per sector."""
+    import oracle
+    from paper_2102_08862_amd import synth
+    x, _ = synth.geometry()
+    cfg = oracle.Config(row_x=x)
+    oracle.build()
+    secs = list(range(min(n_sectors, len(fr.rows))))
+    n = sum(len(fr.rows[s]) for s in secs)
+
+    def one(s):
+        row, y, t = fr.sector(s)
+        oracle.run_sector(cfg, row, y, t)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=len(secs)) as ex:
+        list(ex.map(one, secs))
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "clusters/s", "cores": len(secs), "kind": "oracle",
+            "sample": "sectors 0-%d of the same frame (%d clusters), links + cleaning + chains + MAP fit, "
+                      "one thread per sector, %.1f s" % (secs[-1], n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="frame_10ms", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=3000)
+    ap.add_argument("--cpu-sectors", type=int, default=4, help="oracle sample size (0: skip)")
+    ap.add_argument("--threads", type=int, default=0, help="generator threads (0: auto)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(frames and sectors are independent; see the sharding notes). Use --gpus 1.")
+        sys.exit(2)
+
+    import torch
+    from paper_2102_08862_amd import synth, tpcca
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    nth = args.threads or min(16, os.cpu_count() or 1)
+    fr = synth.generate(args.workload, seed=args.seed, n_threads=nth)
+    log("generated %s seed %d: %d clusters, %d particles in %.1f s"
+        % (args.workload, args.seed, fr.n_clusters, len(fr.tracks), time.perf_counter() - t0))
+
+    trk = tpcca.Tracker()
+    th = time.perf_counter()
+    f = trk.load_frame_packed(fr)
+    h2d_s = time.perf_counter() - th
+    need = trk.ensure_arena()
+    log("inputs resident in HBM (%.2f GB H2D in %.2f s); arena %.2f GB"
+        % (fr.n_clusters * 9 / 1e9, h2d_s, need / 1e9))
+
+    for _ in range(args.warmup):
+        trk.run()
+    trk.synchronize()
+    log("warmup done (%d steps)" % args.warmup)
+    trk.set_timing(True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        trk.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1) / args.steps
+    st = trk.stats()
+    log("timed %d steps: %.3f ms/step (wall %.3f ms/step)" % (args.steps, ms, 1e3 * wall / args.steps))
+
+    n = fr.n_clusters
+    runs = max(1, st["n_timed_runs"])
+    stage = {k: v / runs for k, v in st["stage_ms_total"].items()}
+    table = {}
+    for k, v in stage.items():
+        row = {"ms": round(v, 4)}
+        if k in STAGE_BYTES and v > 0:
+            b = STAGE_BYTES[k](st)
+            row["alg_GB"] = round(b / 1e9, 4)
+            row["GB_s"] = round(b / 1e9 / (v / 1e3), 1)
+        table[k] = row
+    for k, v in table.items():
+        log("  %-9s %s" % (k, v))
+    dom = max((k for k in stage if k in STAGE_BYTES), key=lambda k: stage[k])
+    b = STAGE_BYTES[dom](st)
+    achieved = b / 1e9 / (stage[dom] / 1e3)
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": int(b), "avg_ms": round(stage[dom], 4)}
+
+    cpu = None
+    if args.cpu_sectors > 0:
+        log("cpu baseline: oracle on %d sectors ..." % args.cpu_sectors)
+        cpu = cpu_baseline(fr, args.cpu_sectors)
+        log("cpu baseline: %.3g clusters/s" % cpu["value"])
+
+    out = {
+        "metric": "TPC clusters tracked per second (plain CA tracker, whole 10 ms frame resident in HBM)",
+        "value": round(n / (ms / 1e3), 1),
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "seed": args.seed,
+                   "clusters": n, "tracks": int(st["n_tracks"]), "track_clusters": int(st["n_track_clusters"]),
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "h2d_s": round(h2d_s, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

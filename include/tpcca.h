@@ -101,8 +101,11 @@ typedef struct {
     float cov[15];             /* covariance of (y, t, sinphi, tau, qpt), lower triangle row-major */
 } tpcca_track;
 
-/* Per-run figures filled by tpcca_get_stats. Stage times need the timing
-   flag (tpcca_set_timing) and a completed run. */
+/* Figures filled by tpcca_get_stats. Counts are those of the last run.
+   Stage times need the timing flag (tpcca_set_timing): each run records HIP
+   events on the stream between its stages; stage_ms is the last timed run,
+   stage_ms_total the sum over the n_timed_runs runs since timing was
+   switched on (back-to-back runs need no synchronisation in between). */
 typedef struct {
     int64_t n_clusters;        /* clusters in the run (all loaded frames) */
     int64_t n_links;           /* clusters with an (uncleaned) neighbour pair */
@@ -110,8 +113,11 @@ typedef struct {
     int64_t n_tracks;          /* chains with >= min_track_hits clusters */
     int64_t n_track_clusters;  /* clusters assigned to tracks */
     int64_t n_invalid;         /* input clusters rejected on the device (row or value) */
+    int64_t n_overflow_rows;   /* neighbour-finding strip rows too dense for LDS (read from L2) */
+    int64_t n_timed_runs;      /* runs summed in stage_ms_total */
     int32_t n_stages;          /* entries used in stage_ms / stage_name */
-    float stage_ms[16];        /* device time per stage, last run */
+    float stage_ms[16];        /* device time per stage, last timed run */
+    double stage_ms_total[16]; /* device time per stage summed over the timed runs */
     char stage_name[16][24];
 } tpcca_stats;
 
@@ -170,7 +176,8 @@ tpcca_status tpcca_synchronize(tpcca_ctx *ctx);
    results are then undefined and tpcca_synchronize returns ABORTED. */
 tpcca_status tpcca_request_abort(tpcca_ctx *ctx);
 
-/* Enable (1) or disable (0) per-stage device timing with HIP events. */
+/* Enable (1) or disable (0) per-stage device timing with HIP events; either
+   call also resets the accumulated stage times. */
 tpcca_status tpcca_set_timing(tpcca_ctx *ctx, int32_t on);
 
 /* Figures of the last run (synchronises first). */

@@ -23,7 +23,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "tpcoracle.c")
+_SRCS = [os.path.join(_HERE, "tpcoracle.c"), os.path.join(_HERE, "tpcmlp.c")]
+_HDR = os.path.join(_HERE, "tpcoracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
@@ -75,10 +76,11 @@ FIT_DTYPE = np.dtype([
 
 def build(force: bool = False) -> str:
     """Compile the oracle (plain C, gcc, no FP contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(f) for f in _SRCS + [_HDR])
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-                               "-mfpmath=sse", "-msse2", "-o", tmp, _SRC, "-lm"])
+                               "-mfpmath=sse", "-msse2", "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -108,6 +110,19 @@ def _load():
         lib.ora_propagate_c.restype = ctypes.c_int32
         lib.ora_sizeof_fit.restype = ctypes.c_int32
         lib.ora_sizeof_cfg.restype = ctypes.c_int32
+        lib.ora_links_pruned.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                         P, P, P, P]
+        lib.ora_triplets.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P]
+        lib.ora_triplets.restype = ctypes.c_int64
+        lib.ora_bf16.argtypes = [ctypes.c_float]
+        lib.ora_bf16.restype = ctypes.c_float
+        lib.ora_mlp_features.argtypes = [ctypes.c_float] * 9 + [ctypes.c_int32] + [ctypes.c_float] * 4 + \
+            [ctypes.c_int32, P]
+        lib.ora_mlp_forward_batch.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P]
+        lib.ora_mlp_grad.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_double, ctypes.c_int32, P, P, P, P, P, P]
+        lib.ora_mlp_grad.restype = ctypes.c_double
+        lib.ora_mlp_sizeof.restype = ctypes.c_int32
+        assert lib.ora_mlp_sizeof() == 4 * MLP_NPARAM
         assert lib.ora_sizeof_fit() == ctypes.sizeof(_Fit) == FIT_DTYPE.itemsize
         assert lib.ora_sizeof_cfg() == ctypes.sizeof(_Cfg)
         _lib = lib
@@ -271,3 +286,116 @@ def run_sector(cfg: Config, row, y, t, fit: bool = True):
     if fit:
         res["fit"] = fit_tracks(cfg, first, ln, cl, row, y, t)
     return res
+
+
+# ----------------------------------------------------------------- MLP
+MLP_IN, MLP_INP, MLP_H = 12, 16, 64
+MLP_NPARAM = MLP_H * MLP_INP + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
+
+
+def bf16(a):
+    """Round float32 values to BF16 (nearest even), returned as float32."""
+    a = np.ascontiguousarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    special = (u & 0x7F800000) == 0x7F800000
+    r = np.where(special, (u & 0xFFFF0000).astype(np.uint32) | np.where((u & 0x7FFFFF) != 0, 0x400000, 0), r)
+    return r.astype(np.uint32).view(np.float32).reshape(a.shape)
+
+
+@dataclass
+class MLP:
+    """Network weights (FP32 values on the BF16 grid for w*, FP32 biases)."""
+    w1: np.ndarray   # [64, 16] (columns 12..15 unused, zero)
+    b1: np.ndarray   # [64]
+    w2: np.ndarray   # [64, 64]
+    b2: np.ndarray   # [64]
+    w3: np.ndarray   # [64]
+    b3: float
+
+    def flat(self):
+        return np.concatenate([np.asarray(self.w1, np.float32).ravel(), np.asarray(self.b1, np.float32),
+                               np.asarray(self.w2, np.float32).ravel(), np.asarray(self.b2, np.float32),
+                               np.asarray(self.w3, np.float32), np.array([self.b3], np.float32)])
+
+    @staticmethod
+    def from_flat(v):
+        v = np.asarray(v, np.float32)
+        o = 0
+        def take(n):
+            nonlocal o
+            r = v[o:o + n]
+            o += n
+            return r
+        w1 = take(MLP_H * MLP_INP).reshape(MLP_H, MLP_INP); b1 = take(MLP_H)
+        w2 = take(MLP_H * MLP_H).reshape(MLP_H, MLP_H); b2 = take(MLP_H)
+        w3 = take(MLP_H); b3 = float(take(1)[0])
+        return MLP(w1.copy(), b1.copy(), w2.copy(), b2.copy(), w3.copy(), b3)
+
+    @staticmethod
+    def random(seed=0, scale=1.0):
+        rng = np.random.default_rng(seed)
+        w1 = np.zeros((MLP_H, MLP_INP), np.float32)
+        w1[:, :MLP_IN] = rng.normal(0, scale * np.sqrt(2.0 / MLP_IN), (MLP_H, MLP_IN))
+        w2 = rng.normal(0, scale * np.sqrt(2.0 / MLP_H), (MLP_H, MLP_H))
+        w3 = rng.normal(0, scale * np.sqrt(1.0 / MLP_H), MLP_H)
+        return MLP(bf16(w1), rng.normal(0, 0.1, MLP_H).astype(np.float32), bf16(w2),
+                   rng.normal(0, 0.1, MLP_H).astype(np.float32), bf16(w3), 0.0)
+
+
+def mlp_forward(m: MLP, x, round_act=True):
+    lib = _load()
+    x = np.ascontiguousarray(x, np.float32).reshape(-1, MLP_INP)
+    z = np.zeros(len(x), np.float64)
+    w = m.flat()
+    lib.ora_mlp_forward_batch(_p(w), len(x), _p(x), 1 if round_act else 0, _p(z))
+    return z
+
+
+def mlp_grad(m: MLP, x, label, w_pos=1.0, round_act=True):
+    """Mean weighted BCE-with-logits loss and its FP64 gradient (an MLP of
+    gradients, as float64 arrays)."""
+    lib = _load()
+    x = np.ascontiguousarray(x, np.float32).reshape(-1, MLP_INP)
+    lab = np.ascontiguousarray(label, np.float32)
+    g1 = np.zeros((MLP_H, MLP_INP)); gb1 = np.zeros(MLP_H); g2 = np.zeros((MLP_H, MLP_H)); gb2 = np.zeros(MLP_H)
+    g3 = np.zeros(MLP_H); gb3 = np.zeros(1)
+    w = m.flat()
+    loss = lib.ora_mlp_grad(_p(w), len(x), _p(x), _p(lab), float(w_pos), 1 if round_act else 0,
+                            _p(g1), _p(gb1), _p(g2), _p(gb2), _p(g3), _p(gb3))
+    return loss, dict(w1=g1, b1=gb1, w2=g2, b2=gb2, w3=g3, b3=gb3[0])
+
+
+def mlp_features(yd, td, xd, yi, ti, xi, yu, tu, xu, g, wy, wt, w, c2s, n_cand):
+    lib = _load()
+    f = np.zeros(MLP_INP, np.float32)
+    lib.ora_mlp_features(yd, td, xd, yi, ti, xi, yu, tu, xu, g, wy, wt, w, c2s, n_cand, _p(f))
+    return f
+
+
+def triplets(cfg: Config, row, y, t, cap=None):
+    """Every accepted triplet (d, i, u, g) of a sector and its features."""
+    lib = _load()
+    row, y, t = _in(row, y, t)
+    c = cfg._c()
+    n = lib.ora_triplets(ctypes.byref(c), len(row), _p(row), _p(y), _p(t), 0, None, None)
+    cap = n if cap is None else min(cap, n)
+    tri = np.zeros((max(cap, 1), 4), np.int32)
+    feat = np.zeros((max(cap, 1), MLP_INP), np.float32)
+    lib.ora_triplets(ctypes.byref(c), len(row), _p(row), _p(y), _p(t), cap, _p(tri), _p(feat))
+    return tri[:cap], feat[:cap]
+
+
+def links_pruned(cfg: Config, row, y, t, m: MLP, theta: float, tol: float = 1e-3):
+    """Links with the triplet network gate (logit >= theta); near[i] counts
+    hit i's triplets within tol of theta."""
+    lib = _load()
+    row, y, t = _in(row, y, t)
+    n = len(row)
+    up = np.empty(n, np.int32); dn = np.empty(n, np.int32); gap = np.empty(n, np.int32)
+    near = np.zeros(n, np.int32)
+    w = m.flat()
+    c = cfg._c()
+    lib.ora_links_pruned(ctypes.byref(c), n, _p(row), _p(y), _p(t), _p(w), float(theta), float(tol),
+                         _p(up), _p(dn), _p(gap), _p(near))
+    return up, dn, gap, near

@@ -41,19 +41,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-typedef struct {
-    int32_t n_rows;
-    const float *row_x;      /* [n_rows] pad-row x (cm) */
-    float win_y, win_t;      /* box half widths per unit row gap (cm) */
-    float pair_c2;           /* acceptance of the pair score (cm^2) */
-    int32_t max_gap;         /* largest symmetric row gap tried */
-    int32_t min_track_hits;  /* shortest chain that is a track */
-    double bz;               /* field (T) */
-    double sigma_y, sigma_t; /* cluster resolution (cm) */
-    double ivar_s, ivar_tau, ivar_k; /* prior inverse variances (0 = prior off) */
-    int32_t max_iter;        /* Gauss-Newton iterations */
-    double s_max;            /* |sin phi| above which a propagation fails */
-} ora_cfg;
+#include "tpcoracle.h"
 
 /* ---------------------------------------------------------------- links */
 
@@ -102,10 +90,43 @@ static int32_t ora_lower(const ora_rows *R, const float *t, int r, double tmin) 
     return lo;
 }
 
+/* Candidates of hit i on row rr (= r - g or r + g) inside the box of gap g,
+   in time order; returns the count (list grows as needed). */
+static int32_t ora_box(const ora_rows *R, const float *y, const float *t, int rr, float yi, float ti, float wy,
+                       float wt, int is_down, int32_t **list, int32_t *cap) {
+    /* conservative search range in time (a superset); the exact FP32
+       predicates decide membership */
+    double margin = (double)wt + 1.0;
+    int32_t n = 0;
+    for (int32_t p = ora_lower(R, t, rr, (double)ti - margin); p < R->start[rr + 1]; p++) {
+        int32_t k = R->idx[p];
+        if ((double)t[k] > (double)ti + margin) break;
+        int in = is_down ? (fabsf(yi - y[k]) <= wy && fabsf(ti - t[k]) <= wt)
+                         : (fabsf(y[k] - yi) <= wy && fabsf(t[k] - ti) <= wt);
+        if (!in) continue;
+        if (n == *cap) {
+            *cap = *cap ? 2 * *cap : 64;
+            *list = (int32_t *)realloc(*list, sizeof(int32_t) * (size_t)*cap);
+        }
+        (*list)[n++] = k;
+    }
+    return n;
+}
+
+/* Triplet network gate of the neighbour finder (NULL: none). */
+typedef struct {
+    const ora_mlp *m;
+    double theta, tol;
+    int32_t *near;      /* per hit: triplets with |logit - theta| < tol */
+} ora_gate;
+
 static void ora_links_one(const ora_cfg *cfg, const ora_rows *R, const uint8_t *row, const float *y,
-                          const float *t, int32_t i, int32_t *up_i, int32_t *dn_i, int32_t *gap_i) {
+                          const float *t, int32_t i, int32_t *up_i, int32_t *dn_i, int32_t *gap_i,
+                          const ora_gate *gate) {
     int r = row[i];
     *up_i = -1; *dn_i = -1; *gap_i = 0;
+    int32_t *D = NULL, *U = NULL, capd = 0, capu = 0;
+    float c2s = sqrtf(cfg->pair_c2);
     for (int g = 1; g <= cfg->max_gap; g++) {
         if (r - g < 0 || r + g > cfg->n_rows - 1) continue;
         float xd = cfg->row_x[r - g], xi = cfg->row_x[r], xu = cfg->row_x[r + g];
@@ -115,24 +136,17 @@ static void ora_links_one(const ora_cfg *cfg, const ora_rows *R, const uint8_t *
         float wy = (float)g * cfg->win_y;
         float wt = (float)g * cfg->win_t;
         float yi = y[i], ti = t[i];
-        /* conservative search range in time (a superset); the exact FP32
-           predicates below decide membership */
-        double margin = (double)wt + 1.0;
-        int32_t d0 = ora_lower(R, t, r - g, (double)ti - margin);
-        int32_t u0 = ora_lower(R, t, r + g, (double)ti - margin);
+        int32_t nd = ora_box(R, y, t, r - g, yi, ti, wy, wt, 1, &D, &capd);
+        int32_t nu = ora_box(R, y, t, r + g, yi, ti, wy, wt, 0, &U, &capu);
         int found = 0;
         float bc = 0.f;
         int32_t bu = -1, bd = -1;
-        for (int32_t pd = d0; pd < R->start[r - g + 1]; pd++) {
-            int32_t d = R->idx[pd];
-            if ((double)t[d] > (double)ti + margin) break;
+        for (int32_t a = 0; a < nd; a++) {
+            int32_t d = D[a];
             float yd = y[d], td = t[d];
-            if (!(fabsf(yi - yd) <= wy && fabsf(ti - td) <= wt)) continue;
-            for (int32_t pu = u0; pu < R->start[r + g + 1]; pu++) {
-                int32_t u = R->idx[pu];
-                if ((double)t[u] > (double)ti + margin) break;
+            for (int32_t b = 0; b < nu; b++) {
+                int32_t u = U[b];
                 float yu = y[u], tu = t[u];
-                if (!(fabsf(yu - yi) <= wy && fabsf(tu - ti) <= wt)) continue;
                 float ady = yi - yd;
                 float adt = ti - td;
                 float by = yu - yd;
@@ -145,6 +159,13 @@ static void ora_links_one(const ora_cfg *cfg, const ora_rows *R, const uint8_t *
                 float rt2 = rt * rt;
                 float c = ry2 + rt2;
                 if (!(c <= cfg->pair_c2)) continue;
+                if (gate && gate->m) {
+                    float f[MLP_INP];
+                    ora_mlp_features(yd, td, xd, yi, ti, xi, yu, tu, xu, g, wy, wt, w, c2s, nd + nu, f);
+                    double z = ora_mlp_forward(gate->m, f, 1, NULL, NULL);
+                    if (gate->near && fabs(z - gate->theta) < gate->tol) gate->near[i]++;
+                    if (!(z >= gate->theta)) continue;
+                }
                 if (!found || c < bc || (c == bc && (u < bu || (u == bu && d < bd)))) {
                     found = 1; bc = c; bu = u; bd = d;
                 }
@@ -152,9 +173,11 @@ static void ora_links_one(const ora_cfg *cfg, const ora_rows *R, const uint8_t *
         }
         if (found) {
             *up_i = bu; *dn_i = bd; *gap_i = g;
-            return;
+            break;
         }
     }
+    free(D);
+    free(U);
 }
 
 /* Links of every hit of one sector (input-index space). */
@@ -162,7 +185,7 @@ void ora_links(const ora_cfg *cfg, int64_t n, const uint8_t *row, const float *y
                int32_t *up, int32_t *dn, int32_t *gap) {
     ora_rows R;
     ora_rows_build(cfg, n, row, t, &R);
-    for (int64_t i = 0; i < n; i++) ora_links_one(cfg, &R, row, y, t, (int32_t)i, &up[i], &dn[i], &gap[i]);
+    for (int64_t i = 0; i < n; i++) ora_links_one(cfg, &R, row, y, t, (int32_t)i, &up[i], &dn[i], &gap[i], NULL);
     ora_rows_free(&R);
 }
 
@@ -173,8 +196,76 @@ void ora_links_subset(const ora_cfg *cfg, int64_t n, const uint8_t *row, const f
     ora_rows R;
     ora_rows_build(cfg, n, row, t, &R);
     for (int64_t k = 0; k < nq; k++)
-        ora_links_one(cfg, &R, row, y, t, query[k], &up[k], &dn[k], &gap[k]);
+        ora_links_one(cfg, &R, row, y, t, query[k], &up[k], &dn[k], &gap[k], NULL);
     ora_rows_free(&R);
+}
+
+/* Links with the triplet network gate: a pair is accepted only if also its
+   logit is >= theta; near[i] counts hit i's triplets within tol of theta
+   (decisions there may legitimately differ from an FP32-accumulating
+   implementation). */
+void ora_links_pruned(const ora_cfg *cfg, int64_t n, const uint8_t *row, const float *y, const float *t,
+                      const ora_mlp *m, double theta, double tol, int32_t *up, int32_t *dn, int32_t *gap,
+                      int32_t *near) {
+    ora_rows R;
+    ora_rows_build(cfg, n, row, t, &R);
+    ora_gate gt = {m, theta, tol, near};
+    for (int64_t i = 0; i < n; i++) near[i] = 0;
+    for (int64_t i = 0; i < n; i++) ora_links_one(cfg, &R, row, y, t, (int32_t)i, &up[i], &dn[i], &gap[i], &gt);
+    ora_rows_free(&R);
+}
+
+/* Every accepted triplet (c <= pair_c2) of every hit for every gap
+   g = 1..max_gap, with its features: tri[4k..4k+3] = (d, i, u, g),
+   feat[16k..16k+15]. Returns the number found (entries beyond cap are
+   counted, not stored). */
+int64_t ora_triplets(const ora_cfg *cfg, int64_t n, const uint8_t *row, const float *y, const float *t,
+                     int64_t cap, int32_t *tri, float *feat) {
+    ora_rows R;
+    ora_rows_build(cfg, n, row, t, &R);
+    int32_t *D = NULL, *U = NULL, capd = 0, capu = 0;
+    float c2s = sqrtf(cfg->pair_c2);
+    int64_t cnt = 0;
+    for (int64_t ii = 0; ii < n; ii++) {
+        int32_t i = (int32_t)ii;
+        int r = row[i];
+        for (int g = 1; g <= cfg->max_gap; g++) {
+            if (r - g < 0 || r + g > cfg->n_rows - 1) continue;
+            float xd = cfg->row_x[r - g], xi = cfg->row_x[r], xu = cfg->row_x[r + g];
+            float num = xi - xd;
+            float den = xu - xd;
+            float w = num / den;
+            float wy = (float)g * cfg->win_y;
+            float wt = (float)g * cfg->win_t;
+            float yi = y[i], ti = t[i];
+            int32_t nd = ora_box(&R, y, t, r - g, yi, ti, wy, wt, 1, &D, &capd);
+            int32_t nu = ora_box(&R, y, t, r + g, yi, ti, wy, wt, 0, &U, &capu);
+            for (int32_t a = 0; a < nd; a++) {
+                int32_t d = D[a];
+                float yd = y[d], td = t[d];
+                for (int32_t b = 0; b < nu; b++) {
+                    int32_t u = U[b];
+                    float yu = y[u], tu = t[u];
+                    float ady = yi - yd, adt = ti - td, by = yu - yd, bt = tu - td;
+                    float wby = w * by, wbt = w * bt;
+                    float ry = ady - wby, rt = adt - wbt;
+                    float ry2 = ry * ry, rt2 = rt * rt;
+                    float c = ry2 + rt2;
+                    if (!(c <= cfg->pair_c2)) continue;
+                    if (cnt < cap) {
+                        tri[4 * cnt] = d; tri[4 * cnt + 1] = i; tri[4 * cnt + 2] = u; tri[4 * cnt + 3] = g;
+                        ora_mlp_features(yd, td, xd, yi, ti, xi, yu, tu, xu, g, wy, wt, w, c2s, nd + nu,
+                                         feat + 16 * cnt);
+                    }
+                    cnt++;
+                }
+            }
+        }
+    }
+    free(D);
+    free(U);
+    ora_rows_free(&R);
+    return cnt;
 }
 
 /* ------------------------------------------------------------- cleaning */

@@ -37,7 +37,7 @@ struct Layout {
     size_t bits, wpre;
     size_t trk_len, trk_seed, cl_off, trk;
     size_t clusters, assign, scan_tmp;
-    size_t chain_yt, chain_row;
+    size_t off8, perm, lhist, chain;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -55,6 +55,7 @@ struct Bump {
 const char *kStageNames[] = {"reset",   "hist",  "setup",   "scatter", "rowsort", "links", "seeds",
                              "chainlen", "slots", "clscan",  "emit",    "fit"};
 constexpr int kNumStages = 12;
+constexpr int kEvRing = 64;
 
 }  // namespace
 
@@ -78,8 +79,14 @@ struct tpcca_ctx {
     int32_t *abort_dev = nullptr;
     bool timing = false;
     bool events_ok = false;
-    hipEvent_t ev[kNumStages + 1];
-    float stage_ms[kNumStages] = {};
+    // ring of per-run event sets, so that back-to-back timed runs need no
+    // host synchronisation; completed sets are folded into the totals
+    hipEvent_t ev[kEvRing][kNumStages + 1];
+    bool ev_pending[kEvRing] = {};
+    int ev_next = 0;
+    int64_t timed_runs = 0;
+    double stage_ms_total[kNumStages] = {};
+    float stage_ms_last[kNumStages] = {};
     std::vector<SiDesc> si_host;
     std::vector<int32_t> chunks;
     std::vector<float> wtab;
@@ -173,12 +180,13 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
         return TPCCA_ERR_DEVICE;
     }
     c->events_ok = true;
-    for (int i = 0; i <= kNumStages; i++)
-        if (hipEventCreate(&c->ev[i]) != hipSuccess) c->events_ok = false;
+    for (int r = 0; r < kEvRing; r++)
+        for (int i = 0; i <= kNumStages; i++)
+            if (hipEventCreate(&c->ev[r][i]) != hipSuccess) c->events_ok = false;
     const int cu = std::max(1, c->n_cu);
     for (int i = 0; i < kNumStages; i++) c->lc[i] = Launch{cu * 8, 256};
     c->lc[4] = Launch{cu * 2, 512};  // rowsort: 34 KB LDS, 512 threads
-    c->lc[5] = Launch{cu * 4, 256};  // links: 48 KB LDS
+    c->lc[5] = Launch{cu * 3, 256};  // links: 48 KB LDS -> 3 resident blocks per CU
     // decision-path constants, computed once on the host in FP32
     c->wtab.assign((size_t)cfg->n_rows * kMaxGap, 0.f);
     for (int r = 0; r < cfg->n_rows; r++)
@@ -197,7 +205,8 @@ void tpcca_destroy(tpcca_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     if (c->events_ok)
-        for (int i = 0; i <= kNumStages; i++) (void)hipEventDestroy(c->ev[i]);
+        for (int r = 0; r < kEvRing; r++)
+            for (int i = 0; i <= kNumStages; i++) (void)hipEventDestroy(c->ev[r][i]);
     if (c->abort_host) (void)hipHostFree(c->abort_host);
     delete c;
 }
@@ -216,7 +225,14 @@ tpcca_status tpcca_set_stream(tpcca_ctx *c, void *stream) {
 tpcca_status tpcca_set_timing(tpcca_ctx *c, int32_t on) {
     if (!c) return TPCCA_ERR_INVALID_ARG;
     if (on && !c->events_ok) return fail(c, TPCCA_ERR_DEVICE, "HIP events unavailable");
+    (void)hipStreamSynchronize(c->stream);
     c->timing = on != 0;
+    for (int r = 0; r < kEvRing; r++) c->ev_pending[r] = false;
+    c->timed_runs = 0;
+    for (int i = 0; i < kNumStages; i++) {
+        c->stage_ms_total[i] = 0.0;
+        c->stage_ms_last[i] = 0.f;
+    }
     return TPCCA_OK;
 }
 
@@ -334,9 +350,7 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.coff = b.take(sizeof(int32_t) * SR * (kNcbMax + 1));
     // the row-grouped staging buffer is dead after the row sort: the chain
     // copies for the fit reuse it
-    L.tmp = b.take(std::max(sizeof(Rec) * N, align_up(sizeof(float2) * N, 256) + (size_t)N));
-    L.chain_yt = L.tmp;
-    L.chain_row = L.tmp + align_up(sizeof(float2) * N, 256);
+    L.tmp = b.take(sizeof(Rec) * N);
     L.rec = b.take(sizeof(Rec) * N);
     L.link = b.take(sizeof(int2) * N);
     L.seeds = b.take(sizeof(int32_t) * seed_cap);
@@ -349,6 +363,12 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.trk_seed = b.take(sizeof(int32_t) * trk_cap);
     L.cl_off = b.take(sizeof(int32_t) * (trk_cap + 1));
     L.trk = b.take(sizeof(tpcca_track) * trk_cap);
+    L.off8 = b.take(sizeof(int32_t) * (trk_cap + 1));
+    L.perm = b.take(sizeof(int32_t) * trk_cap);
+    L.lhist = b.take(sizeof(int32_t) * (kLenBins + 1));
+    // chain copies for the fit: every track's chain padded to 8 entries; the
+    // row-grouped staging buffer is dead by then and covers the first N
+    L.chain = b.take(sizeof(Rec) * (N + 7 * trk_cap));
     L.clusters = b.take(sizeof(int32_t) * N);
     L.assign = b.take(sizeof(int32_t) * N);
     const int64_t nblk = (std::max<int64_t>(W, trk_cap) + kScanItems - 1) / kScanItems + 2;
@@ -421,11 +441,27 @@ static void bind_pointers(tpcca_ctx *c) {
     a.cl_off = (int32_t *)(A + L.cl_off);
     a.trk = (tpcca_track *)(A + L.trk);
     a.clusters = (int32_t *)(A + L.clusters);
-    a.chain_yt = (float2 *)(A + L.chain_yt);
-    a.chain_row = (uint8_t *)(A + L.chain_row);
+    a.off8 = (int32_t *)(A + L.off8);
+    a.perm = (int32_t *)(A + L.perm);
+    a.lhist = (int32_t *)(A + L.lhist);
+    a.chain = (Rec *)(A + L.chain);
     a.assign = (int32_t *)(A + L.assign);
     a.scan_tmp = (int32_t *)(A + L.scan_tmp);
     a.abort_flag = c->abort_dev;
+}
+
+// Fold one completed ring slot into the totals (waits for its last event).
+static void fold_slot(tpcca_ctx *c, int r) {
+    if (!c->ev_pending[r]) return;
+    (void)hipEventSynchronize(c->ev[r][kNumStages]);
+    for (int i = 0; i < kNumStages; i++) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[r][i], c->ev[r][i + 1]) != hipSuccess) ms = 0.f;
+        c->stage_ms_total[i] += ms;
+        c->stage_ms_last[i] = ms;
+    }
+    c->timed_runs++;
+    c->ev_pending[r] = false;
 }
 
 extern "C" {
@@ -511,9 +547,14 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
         c->upload_dirty = false;
     }
     const bool tm = c->timing && c->events_ok;
+    const int slot = c->ev_next;
+    if (tm) {
+        fold_slot(c, slot);  // the slot is reused: fold its previous run first
+        c->ev_next = (slot + 1) % kEvRing;
+    }
     int st = 0;
     auto mark = [&](int i) {
-        if (tm) (void)hipEventRecord(c->ev[i], s);
+        if (tm) (void)hipEventRecord(c->ev[slot][i], s);
     };
     mark(st++);
     // reset: counters, per-sector state, row counts, bitmap, assignment
@@ -541,14 +582,18 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
     mark(st++);
     launch_scan_i32_dev(a.trk_len, &((Counters *)(A + L.cnt))->n_tracks, a.trk_cap, a.cl_off,
                         &((Counters *)(A + L.cnt))->n_cl, a.scan_tmp, s);
+    launch_scan_round8_dev(a.trk_len, &((Counters *)(A + L.cnt))->n_tracks, a.trk_cap, a.off8, a.scan_tmp, s);
     launch_si_clusters(a, s);
     mark(st++);
     launch_emit(a, c->lc[10], s);
+    launch_lists(a, c->lc[10], s);
     mark(st++);
+    launch_len_sort(a, c->lc[11], s);
     launch_fit(a, c->lc[11], s);
     mark(st++);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+    if (tm) c->ev_pending[slot] = true;
     c->ran = true;
     c->have_results = true;
     return TPCCA_OK;
@@ -580,15 +625,17 @@ tpcca_status tpcca_get_stats(tpcca_ctx *c, tpcca_stats *out) {
     out->n_tracks = k.n_tracks;
     out->n_track_clusters = k.n_cl;
     out->n_invalid = k.n_invalid;
+    out->n_overflow_rows = k.n_glb_rows;
     out->n_stages = 0;
     if (c->timing && c->events_ok) {
+        for (int r = 0; r < kEvRing; r++) fold_slot(c, (c->ev_next + r) % kEvRing);
         for (int i = 0; i < kNumStages; i++) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) != hipSuccess) ms = -1.f;
-            out->stage_ms[i] = ms;
+            out->stage_ms[i] = c->stage_ms_last[i];
+            out->stage_ms_total[i] = c->stage_ms_total[i];
             std::snprintf(out->stage_name[i], sizeof(out->stage_name[i]), "%s", kStageNames[i]);
         }
         out->n_stages = kNumStages;
+        out->n_timed_runs = c->timed_runs;
     }
     return TPCCA_OK;
 }

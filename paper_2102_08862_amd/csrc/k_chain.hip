@@ -18,45 +18,77 @@
 
 namespace tpcca {
 
-// wave-level stream compaction: returns the output slot of lanes with pred
-__device__ inline int wave_compact(bool pred, int32_t *counter) {
-    const unsigned long long m = __ballot(pred);
-    const int lane = __lane_id();
-    const int before = __popcll(m & ((1ull << lane) - 1ull));
-    int base = 0;
-    if (lane == 0 && m) base = atomicAdd(counter, __popcll(m));
-    base = __shfl(base, 0);
-    return base + before;
+// block-wide exclusive scan of one int per thread (blockDim <= 1024)
+__device__ inline int block_excl_scan(int v, int *sh, int &total) {
+    const int tid = threadIdx.x, n = blockDim.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < n; off <<= 1) {
+        const int x = (tid >= off) ? sh[tid - off] : 0;
+        __syncthreads();
+        sh[tid] += x;
+        __syncthreads();
+    }
+    total = sh[n - 1];
+    const int r = sh[tid] - v;
+    __syncthreads();
+    return r;
 }
+
+
+// Compaction of a block's flags: one global atomic per chunk of kCompactChunk
+// positions, so that the single output counter is not contended.
+constexpr int kCompactPer = 32;
+constexpr int kCompactChunk = 256 * kCompactPer;
 
 __global__ __launch_bounds__(256) void k_seeds(KArgs a) {
     TPCCA_ABORT_GUARD(a);
+    __shared__ int s_scan[256];
+    __shared__ int s_base;
     const int n = min(a.cnt->n_valid_total, a.n_in);
-    const int stride = gridDim.x * blockDim.x;
-    for (int base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const int p = base + threadIdx.x;
-        bool seed = false;
-        if (p < n) {
-            const int2 l = a.link[p];
-            const bool mu = l.x >= 0 && l.x < n && a.link[l.x].y == p;
-            const bool md = l.y >= 0 && l.y < n && a.link[l.y].x == p;
-            seed = mu && !md;
+    const int nch = (n + kCompactChunk - 1) / kCompactChunk;
+    const int tid = threadIdx.x;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int base = c * kCompactChunk;
+        uint32_t mask = 0;
+#pragma unroll 4
+        for (int k = 0; k < kCompactPer; k++) {
+            const int p = base + k * 256 + tid;
+            if (p < n) {
+                const int2 l = a.link[p];
+                const bool mu = l.x >= 0 && l.x < n && a.link[l.x].y == p;
+                const bool md = l.y >= 0 && l.y < n && a.link[l.y].x == p;
+                if (mu && !md) mask |= 1u << k;
+            }
         }
-        const int slot = wave_compact(seed, &a.cnt->n_seeds);
-        if (seed && slot < a.seed_cap) a.seeds[slot] = p;
+        int tot;
+        const int excl = block_excl_scan(__popc(mask), s_scan, tot);
+        if (tid == 0) s_base = tot ? atomicAdd(&a.cnt->n_seeds, tot) : 0;
+        __syncthreads();
+        int o = s_base + excl;
+        for (int k = 0; k < kCompactPer; k++) {
+            if ((mask >> k) & 1u) {
+                if (o < a.seed_cap) a.seeds[o] = base + k * 256 + tid;
+                o++;
+            }
+        }
+        __syncthreads();
     }
 }
 
 void launch_seeds(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL(k_seeds, dim3(l.grid), dim3(256), 0, s, a);
+    const int nch = (a.n_in + kCompactChunk - 1) / kCompactChunk;
+    hipLaunchKernelGGL(k_seeds, dim3(max(1, min(l.grid, nch))), dim3(256), 0, s, a);
 }
 
 __global__ __launch_bounds__(256) void k_chainlen(KArgs a) {
     TPCCA_ABORT_GUARD(a);
+    __shared__ int s_scan[256];
+    __shared__ int s_base;
     const int ns = min(a.cnt->n_seeds, a.seed_cap);
     const int nv = min(a.cnt->n_valid_total, a.n_in);
-    const int stride = gridDim.x * blockDim.x;
     const int R = a.n_rows;
+    const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x; base < ns; base += stride) {
         const int k = base + threadIdx.x;
         int p = 0, L = 0;
@@ -73,7 +105,11 @@ __global__ __launch_bounds__(256) void k_chainlen(KArgs a) {
             }
         }
         const bool trk = (k < ns) && L >= a.min_track_hits;
-        const int slot = wave_compact(trk, &a.cnt->n_tseeds);
+        int tot;
+        const int excl = block_excl_scan(trk ? 1 : 0, s_scan, tot);
+        if (threadIdx.x == 0) s_base = tot ? atomicAdd(&a.cnt->n_tseeds, tot) : 0;
+        __syncthreads();
+        const int slot = s_base + excl;
         if (trk && slot < a.tseed_cap) {
             a.tseed[slot] = p;
             a.tlen[slot] = L;
@@ -81,6 +117,7 @@ __global__ __launch_bounds__(256) void k_chainlen(KArgs a) {
             const int si = e.sr >> 8;
             atomicOr(&a.bits[a.si[si].word_base + (e.id >> 5)], 1u << (e.id & 31));
         }
+        __syncthreads();
     }
 }
 
@@ -136,6 +173,12 @@ void launch_si_clusters(const KArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_si_clusters, dim3((a.n_si + 255) / 256), dim3(256), 0, s, a);
 }
 
+// One lane per track, in seed order (neighbouring seeds walk neighbouring
+// rows, so the gathers share cache lines). Each lane buffers 8 chain entries
+// in registers and writes them as one 128-byte line of its track's chain
+// copy, so the scattered per-lane output never leaves partial lines.
+constexpr int kEmitBatch = 8;
+
 __global__ __launch_bounds__(256) void k_emit(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     const int nt = min(a.cnt->n_tseeds, a.tseed_cap);
@@ -144,27 +187,120 @@ __global__ __launch_bounds__(256) void k_emit(KArgs a) {
         const int g = a.tslot[k];
         if (g >= a.trk_cap) continue;
         int q = a.tseed[k];
-        const int off = a.cl_off[g];
-        const int L = a.trk_len[g];
+        const int L = min(a.trk_len[g], R);
+        Rec *dst = a.chain + a.off8[g];
         Rec e = a.rec[q];
         const int si = e.sr >> 8;
         const int tn = g - a.st[si].trk_base;
-        const int inb = a.si[si].in_base;
-        for (int j = 0; j < L && j <= R; j++) {
-            a.clusters[off + j] = e.id;
-            a.assign[inb + e.id] = tn;
-            a.chain_yt[off + j] = make_float2(e.y, e.t);
-            a.chain_row[off + j] = (uint8_t)(e.sr & 255);
-            if (j + 1 < L) {
-                q = a.link[q].x;
-                e = a.rec[q];
+        int32_t *asg = a.assign + a.si[si].in_base;
+        for (int j0 = 0; j0 < L; j0 += kEmitBatch) {
+            Rec buf[kEmitBatch];
+#pragma unroll
+            for (int b = 0; b < kEmitBatch; b++) {
+                const int j = j0 + b;
+                if (j < L) {
+                    asg[e.id] = tn;
+                    buf[b].y = e.y;
+                    buf[b].t = e.t;
+                    buf[b].id = e.id;
+                    buf[b].sr = e.sr & 255;
+                    if (j + 1 < L) {
+                        q = a.link[q].x;
+                        e = a.rec[q];
+                    }
+                } else {
+                    buf[b] = Rec{0.f, 0.f, -1, 0};
+                }
             }
+#pragma unroll
+            for (int b = 0; b < kEmitBatch; b++) dst[j0 + b] = buf[b];
         }
     }
 }
 
 void launch_emit(const KArgs &a, Launch l, hipStream_t s) {
     hipLaunchKernelGGL(k_emit, dim3(l.grid), dim3(256), 0, s, a);
+}
+
+// Canonical cluster lists: one wave per track copies the input indices of
+// its chain copy to the track's list (coalesced reads and writes).
+__global__ __launch_bounds__(256) void k_lists(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    const int nt = min(a.cnt->n_tracks, a.trk_cap);
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    for (int g = blockIdx.x * wpb + (threadIdx.x >> 6); g < nt; g += gridDim.x * wpb) {
+        const int L = a.trk_len[g];
+        const Rec *src = a.chain + a.off8[g];
+        int32_t *dst = a.clusters + a.cl_off[g];
+        for (int j = lane; j < L; j += 64) dst[j] = src[j].id;
+    }
+}
+
+void launch_lists(const KArgs &a, Launch l, hipStream_t s) {
+    hipLaunchKernelGGL(k_lists, dim3(l.grid), dim3(256), 0, s, a);
+}
+
+// Track slots ordered by decreasing chain length (counting sort), so that the
+// lanes of a fit wave carry chains of nearly equal length.
+__global__ __launch_bounds__(256) void k_len_hist(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    __shared__ int h[kLenBins];
+    for (int b = threadIdx.x; b < kLenBins; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    const int nt = min(a.cnt->n_tracks, a.trk_cap);
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nt; g += gridDim.x * blockDim.x)
+        atomicAdd(&h[min(a.trk_len[g], kLenBins - 1)], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < kLenBins; b += blockDim.x)
+        if (h[b]) atomicAdd(&a.lhist[b], h[b]);
+}
+
+__global__ __launch_bounds__(kLenBins) void k_len_scan(KArgs a) {
+    __shared__ int sh[kLenBins];
+    // bucket b (length) goes before shorter buckets: scan in decreasing length
+    const int b = kLenBins - 1 - (int)threadIdx.x;
+    const int v = a.lhist[b];
+    int tot;
+    const int e = block_excl_scan(v, sh, tot);
+    a.lhist[b] = e;
+}
+
+constexpr int kLenPer = 8;
+
+__global__ __launch_bounds__(256) void k_len_scatter(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    __shared__ int h[kLenBins], base[kLenBins];
+    const int nt = min(a.cnt->n_tracks, a.trk_cap);
+    const int chunk = 256 * kLenPer;
+    for (int g0 = blockIdx.x * chunk; g0 < nt; g0 += gridDim.x * chunk) {
+        for (int b = threadIdx.x; b < kLenBins; b += blockDim.x) h[b] = 0;
+        __syncthreads();
+        int lb[kLenPer];
+#pragma unroll
+        for (int k = 0; k < kLenPer; k++) {
+            const int g = g0 + k * 256 + threadIdx.x;
+            lb[k] = (g < nt) ? min(a.trk_len[g], kLenBins - 1) : -1;
+            if (lb[k] >= 0) atomicAdd(&h[lb[k]], 1);
+        }
+        __syncthreads();
+        for (int b = threadIdx.x; b < kLenBins; b += blockDim.x) {
+            base[b] = h[b] ? atomicAdd(&a.lhist[b], h[b]) : 0;
+            h[b] = 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kLenPer; k++)
+            if (lb[k] >= 0) a.perm[base[lb[k]] + atomicAdd(&h[lb[k]], 1)] = g0 + k * 256 + threadIdx.x;
+        __syncthreads();
+    }
+}
+
+void launch_len_sort(const KArgs &a, Launch l, hipStream_t s) {
+    launch_fill_i32(a.lhist, kLenBins, 0, s);
+    hipLaunchKernelGGL(k_len_hist, dim3(l.grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_len_scan, dim3(1), dim3(kLenBins), 0, s, a);
+    hipLaunchKernelGGL(k_len_scatter, dim3(l.grid), dim3(256), 0, s, a);
 }
 
 // ------------------------------------------------------------------ scans
@@ -183,22 +319,10 @@ struct I32In {
     const int32_t *p;
     __device__ int operator()(int i) const { return p[i]; }
 };
-
-__device__ inline int block_excl_scan(int v, int *sh, int &total) {
-    const int tid = threadIdx.x, n = blockDim.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < n; off <<= 1) {
-        const int x = (tid >= off) ? sh[tid - off] : 0;
-        __syncthreads();
-        sh[tid] += x;
-        __syncthreads();
-    }
-    total = sh[n - 1];
-    const int r = sh[tid] - v;
-    __syncthreads();
-    return r;
-}
+struct Round8In {
+    const int32_t *p;
+    __device__ int operator()(int i) const { return (p[i] + 7) & ~7; }
+};
 
 template <class F>
 __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(F f, const int32_t *n_dev, int32_t n_host, int32_t n_cap,
@@ -288,4 +412,11 @@ void launch_scan_i32_dev(const int32_t *in, const int32_t *n_dev, int32_t n_cap,
     scan_impl(I32In{in}, n_dev, 0, n_cap, out, total_dst, tmp, s);
 }
 
+}  // namespace tpcca
+
+namespace tpcca {
+void launch_scan_round8_dev(const int32_t *in, const int32_t *n_dev, int32_t n_cap, int32_t *out, int32_t *tmp,
+                            hipStream_t s) {
+    scan_impl(Round8In{in}, n_dev, 0, n_cap, out, nullptr, tmp, s);
+}
 }  // namespace tpcca

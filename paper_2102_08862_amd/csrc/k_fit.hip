@@ -132,23 +132,30 @@ constexpr float kConvTol = 1e-5f;
 
 __global__ __launch_bounds__(256) void k_fit(KArgs a) {
     TPCCA_ABORT_GUARD(a);
+    __shared__ float sx[kMaxRows];
+    for (int r = threadIdx.x; r < a.n_rows; r += blockDim.x) sx[r] = a.row_x[r];
+    __syncthreads();
     const int nt = min(a.cnt->n_tracks, a.trk_cap);
     const float kB = a.bz_kb, smax = a.s_max;
     const float vy = a.sigma_y2, vt = a.sigma_t2;
     const int P = a.kf_passes;
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nt; g += gridDim.x * blockDim.x) {
+    // tracks in order of decreasing length: the lanes of a wave carry chains
+    // of nearly equal length
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
+        const int g = a.perm[i];
         const int L = a.trk_len[g];
         const int off = a.cl_off[g];
         const Rec e0 = a.rec[a.trk_seed[g]];
         const int si = e0.sr >> 8;
-        const float2 *yt = a.chain_yt + off;
-        const uint8_t *rw = a.chain_row + off;
-        const float x1 = a.row_x[rw[0]];
-        const float y1 = yt[0].x, t1 = yt[0].y;
+        const Rec *ch = a.chain + a.off8[g];
+        const Rec c1 = ch[0];
         const int m = (L + 1) / 2 - 1;
-        const float Xm = a.row_x[rw[m]] - x1, Ym = yt[m].x - y1;
-        const float XL = a.row_x[rw[L - 1]] - x1;
-        const float YL = yt[L - 1].x - y1, TL = yt[L - 1].y - t1;
+        const Rec cm = ch[m], cL = ch[L - 1];
+        const float x1 = sx[c1.sr];
+        const float y1 = c1.y, t1 = c1.t;
+        const float Xm = sx[cm.sr] - x1, Ym = cm.y - y1;
+        const float XL = sx[cL.sr] - x1;
+        const float YL = cL.y - y1, TL = cL.t - t1;
 
         // three-point estimate at the first cluster
         bool ok = true;
@@ -196,8 +203,9 @@ __global__ __launch_bounds__(256) void k_fit(KArgs a) {
             float chi = (ref[0] * ref[0]) / vy + (ref[1] * ref[1]) / vt;
             float Xp = 0.f;
             for (int j = 1; j < L; j++) {
-                const float Xj = a.row_x[rw[j]] - x1;
-                const float2 m2 = yt[j];
+                const Rec cj = ch[j];
+                const float Xj = sx[cj.sr] - x1;
+                const float2 m2 = make_float2(cj.y, cj.t);
                 float rn[5];
                 Jac J;
                 if (!transport(kB, smax, ref, Xj - Xp, rn, &J)) {
@@ -247,8 +255,8 @@ __global__ __launch_bounds__(256) void k_fit(KArgs a) {
         o.first = (int64_t)(off - a.st[si].cl_base);
         o.seed = e0.id;
         o.ndf = 2 * L - 5;
-        o.x_ref = a.row_x[rw[L - 1]];
-        o.t_base = yt[L - 1].y;
+        o.x_ref = sx[cL.sr];
+        o.t_base = cL.t;
         if (ok) {
             o.y = y1 + est[0];
             o.dt = est[1] - TL;

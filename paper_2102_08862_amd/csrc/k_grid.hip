@@ -150,10 +150,17 @@ __global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
                 inv = 0.f;
                 ncb = 1;
             }
+            // strip width: about 0.9 x 256 own clusters per row on average
+            int tcb = kMaxStripCb;
+            if (nv > 0) {
+                const float dens = (float)nv / ((float)R * (float)ncb);
+                tcb = min(max((int)(230.f / fmaxf(dens, 1e-3f)), 2), kMaxStripCb);
+            }
             s.t0 = tmin;
             s.inv_cbw = inv;
             s.ncb = ncb;
-            s.nslab = nv > 0 ? (ncb + kTileCb - 1) / kTileCb : 0;
+            s.tcb = tcb;
+            s.nslab = nv > 0 ? (ncb + tcb - 1) / tcb : 0;
             s.n_valid = nv;
             a.st[si] = s;
         }
@@ -190,20 +197,20 @@ __global__ __launch_bounds__(1024) void k_si_prefix(KArgs a) {
         int nv = 0, nt = 0;
         if (si < a.n_si) {
             nv = a.st[si].n_valid;
-            nt = a.st[si].nslab * a.n_rows;
+            nt = a.st[si].nslab;
         }
         int tv, tt;
         block_scan2(nv, nt, tv, tt, sh0, sh1);
         if (si < a.n_si) {
             a.st[si].sbase = carry_s + nv;
-            a.st[si].tile_base = carry_t + nt;
+            a.st[si].strip_base = carry_t + nt;
         }
         carry_s += tv;
         carry_t += tt;
     }
     if (threadIdx.x == 0) {
         a.cnt->n_valid_total = carry_s;
-        a.cnt->n_tiles = carry_t;
+        a.cnt->n_strips = carry_t;
     }
 }
 

@@ -1,84 +1,90 @@
-// Neighbour finding: one lane per cluster, one workgroup per tile (a sector,
-// a pad row r and a slab of kTileCb coarse time bins). The rows r-2..r+2 of
-// the slab plus one coarse bin of halo on each side are staged in LDS; a
-// lane finds, for gap g = 1 then 2, the exact time windows on rows r-g and
-// r+g by binary search in the time-ordered rows, and scores every (down, up)
-// pair that passes the box cut:
+// Neighbour finding: one lane per cluster, one workgroup per strip (a sector
+// and a slab of coarse time bins), sweeping the pad rows of the strip in
+// order. The rows r-2..r+2 (plus one coarse bin of time halo on each side)
+// live in a five-slot LDS ring: each step stages the one new row r+2, builds
+// a small time index over it, and then every lane scores the candidates of
+// one cluster of row r:
 //
 //   ry = (y_i - y_d) - w*(y_u - y_d),  rt = (t_i - t_d) - w*(t_u - t_d),
 //   c  = ry*ry + rt*rt,                accepted if c <= pair_c2,
 //
-// with w = (x_r - x_{r-g}) / (x_{r+g} - x_{r-g}) precomputed in FP32 on the
-// host. Every operation is a separately rounded FP32 op (no contraction),
-// so the decisions are bit-identical to any IEEE implementation of the same
-// sequence. The winner is the lexicographic minimum of (c, up input index,
-// down input index). Time is the seeding coordinate: no z or vertex is used.
+// over down clusters d on row r-g and up clusters u on row r+g inside the
+// box |y - y_i| <= g*win_y, |t - t_i| <= g*win_t, for g = 1, then g = 2 only
+// if g = 1 found nothing. w = (x_r - x_{r-g}) / (x_{r+g} - x_{r-g}) comes
+// precomputed in FP32 from the host. Every operation is one separately
+// rounded FP32 op (no contraction), so the decisions are bit-identical to
+// any IEEE implementation of the same sequence. The winner is the
+// lexicographic minimum of (c, up input index, down input index). Time is the
+// seeding coordinate; no z or vertex is involved.
 //
-// Tiles are visited persistently in an XCD-aware order: the logical tile
-// order is (sector, slab, row), and each XCD takes a contiguous range of it,
-// so the five rows that share staged data are processed on the same XCD at
-// about the same time and the re-reads hit that XCD's L2.
+// Strips come from a device-side work queue, so uneven sectors and frames
+// balance across the persistent workgroups. A row whose staged range does not
+// fit its LDS slot is read from global memory (L2) instead, with the same
+// predicates.
 #include "tpcca_internal.h"
 
 namespace tpcca {
 
-struct LdsRows {
+constexpr int kSweepBlock = 256;
+constexpr int kSlots = 2 * kMaxGap + 1;
+constexpr int kSlotCap = 768;
+constexpr int kIdxPerCb = 8;                                  // index bins per coarse bin
+constexpr int kIdxMax = (kMaxStripCb + 2) * kIdxPerCb + 1;
+
+struct LdsSlot {
     const float *y, *t;
     const int32_t *id;
-    int32_t pos0, n;
+    const int32_t *first;  // index bin -> first position with bin >= it
+    int32_t pos0, n, nb;
+    float T0, sidx;        // index bin = floor((t - T0) * sidx)
     __device__ float Y(int k) const { return y[k]; }
     __device__ float T(int k) const { return t[k]; }
     __device__ int32_t I(int k) const { return id[k]; }
+    // a position at or before the first element with time >= tl
+    __device__ int start(float tl) const {
+        int b = (int)floorf(__fmul_rn(__fsub_rn(tl, T0), sidx)) - 1;
+        b = min(max(b, 0), nb);
+        return first[b];
+    }
 };
 
-struct GlbRows {
+struct GlbSlot {
     const Rec *r;
-    int32_t pos0, n;
+    const int32_t *co;     // coarse offsets of the row
+    int32_t pos0, n, cb_lo;
+    float t0, inv_cbw;
     __device__ float Y(int k) const { return r[pos0 + k].y; }
     __device__ float T(int k) const { return r[pos0 + k].t; }
     __device__ int32_t I(int k) const { return r[pos0 + k].id; }
+    __device__ int start(float tl) const {
+        // every time >= tl - 1 coarse bin lies at or after this coarse bin
+        int cb = (int)floorf(__fmul_rn(__fsub_rn(tl, t0), inv_cbw)) - 1;
+        cb = max(cb, cb_lo);
+        const int p = co[cb] - pos0;
+        return min(max(p, 0), n);
+    }
 };
 
-// first k with !(ti - t_k > wt)
-template <class V>
-__device__ inline int win_lo(const V &v, float ti, float wt) {
-    int lo = 0, hi = v.n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (__fsub_rn(ti, v.T(mid)) > wt) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// first k with t_k - ti > wt
-template <class V>
-__device__ inline int win_hi(const V &v, float ti, float wt) {
-    int lo = 0, hi = v.n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (__fsub_rn(v.T(mid), ti) > wt) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
-}
-
-template <class V>
-__device__ inline bool best_pair(const V &D, const V &U, float yi, float ti, float w, float wy, float wt, float c2,
-                                 int &bu, int &bd) {
-    const int dlo = win_lo(D, ti, wt), dhi = win_hi(D, ti, wt);
-    const int ulo = win_lo(U, ti, wt), uhi = win_hi(U, ti, wt);
+template <class VD, class VU>
+__device__ inline bool best_pair(const VD &D, const VU &U, float yi, float ti, float w, float wy, float wt,
+                                 float c2, int &bu, int &bd) {
+    const float tl = __fsub_rn(ti, wt);
+    const int sd = D.start(tl), su = U.start(tl);
     bool found = false;
     float bc = 0.f;
     int biu = 0, bid = 0;
-    for (int kd = dlo; kd < dhi; kd++) {
-        const float yd = D.Y(kd), td = D.T(kd);
+    for (int kd = sd; kd < D.n; kd++) {
+        const float td = D.T(kd);
+        if (__fsub_rn(td, ti) > wt) break;
+        const float yd = D.Y(kd);
         if (!(fabsf(__fsub_rn(yi, yd)) <= wy && fabsf(__fsub_rn(ti, td)) <= wt)) continue;
-        const int idd = D.I(kd);
         const float ady = __fsub_rn(yi, yd);
         const float adt = __fsub_rn(ti, td);
-        for (int ku = ulo; ku < uhi; ku++) {
-            const float yu = U.Y(ku), tu = U.T(ku);
+        int idd = -1;
+        for (int ku = su; ku < U.n; ku++) {
+            const float tu = U.T(ku);
+            if (__fsub_rn(tu, ti) > wt) break;
+            const float yu = U.Y(ku);
             if (!(fabsf(__fsub_rn(yu, yi)) <= wy && fabsf(__fsub_rn(tu, ti)) <= wt)) continue;
             const float by = __fsub_rn(yu, yd);
             const float bt = __fsub_rn(tu, td);
@@ -86,6 +92,7 @@ __device__ inline bool best_pair(const V &D, const V &U, float yi, float ti, flo
             const float rt = __fsub_rn(adt, __fmul_rn(w, bt));
             const float c = __fadd_rn(__fmul_rn(ry, ry), __fmul_rn(rt, rt));
             if (!(c <= c2)) continue;
+            if (idd < 0) idd = D.I(kd);
             const int idu = U.I(ku);
             if (!found || c < bc || (c == bc && (idu < biu || (idu == biu && idd < bid)))) {
                 found = true;
@@ -100,116 +107,140 @@ __device__ inline bool best_pair(const V &D, const V &U, float yi, float ti, flo
     return found;
 }
 
-constexpr int kLinkBlock = 256;
-
-__global__ __launch_bounds__(kLinkBlock) void k_links(KArgs a) {
-    __shared__ float sy[2 * kMaxGap][kStageCap];
-    __shared__ float st[2 * kMaxGap][kStageCap];
-    __shared__ int32_t sid[2 * kMaxGap][kStageCap];
-    __shared__ int32_t s_lo[2 * kMaxGap], s_n[2 * kMaxGap];
-    __shared__ int32_t s_glb, s_links, s_abort;
+__global__ __launch_bounds__(kSweepBlock) void k_links(KArgs a) {
+    __shared__ float sy[kSlots][kSlotCap];
+    __shared__ float st[kSlots][kSlotCap];
+    __shared__ int32_t sid[kSlots][kSlotCap];
+    __shared__ int32_t sfirst[kSlots][kIdxMax];
+    __shared__ int32_t s_lo[kSlots], s_n[kSlots], s_glb[kSlots];
+    __shared__ int32_t s_strip, s_links, s_glbrows;
     const int R = a.n_rows;
     const int G = a.max_gap;
-    const int ntiles = min(a.cnt->n_tiles, 0x7ffffff0);
-    const int per = (ntiles + 7) / 8;
-    const int nlog = per * 8;
+    const int tid = threadIdx.x;
+    const int n_strips = a.cnt->n_strips;
     int iter = 0;
-    for (int wv = blockIdx.x; wv < nlog; wv += gridDim.x, iter++) {
-        const int L = (wv & 7) * per + (wv >> 3);
-        if ((iter & 15) == 0) {
-            if (threadIdx.x == 0) s_abort = __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __syncthreads();
-            if (s_abort) break;
+    for (;; iter++) {
+        if (tid == 0) {
+            int v = atomicAdd(&a.cnt->strip_next, 1);
+            if ((iter & 7) == 0 && abort_requested(a)) v = n_strips;
+            s_strip = v;
+            s_links = 0;
+            s_glbrows = 0;
         }
-        if (L >= ntiles) continue;
-        // tile -> (sector instance, slab, row)
+        __syncthreads();
+        const int strip = s_strip;
+        if (strip >= n_strips) break;
+        // strip -> sector instance
         int lo = 0, hi = a.n_si - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (a.st[mid].tile_base <= L) lo = mid;
+            if (a.st[mid].strip_base <= strip) lo = mid;
             else hi = mid - 1;
         }
         const int si = lo;
-        const int local = L - a.st[si].tile_base;
-        const int slab = local / R;
-        const int r = local - slab * R;
-        const int ncb = a.st[si].ncb;
-        const int cb0 = slab * kTileCb;
-        const int cb1 = min(cb0 + kTileCb, ncb);
-        const int32_t *co_r = a.coff + (int64_t)(si * R + r) * (kNcbMax + 1);
-        const int own_lo = co_r[cb0], own_hi = co_r[cb1];
-        if (own_lo >= own_hi) continue;
-        if (threadIdx.x == 0) {
-            s_glb = 0;
-            s_links = 0;
-        }
-        if (threadIdx.x < 2 * kMaxGap) {
-            const int j = threadIdx.x;
-            const int g = (j < kMaxGap) ? (kMaxGap - j) : (j - kMaxGap + 1);  // j: r-2, r-1, r+1, r+2
-            const int rr = (j < kMaxGap) ? r - g : r + g;
-            int plo = 0, pn = 0;
-            if (g <= G && rr >= 0 && rr < R) {
-                const int32_t *co = a.coff + (int64_t)(si * R + rr) * (kNcbMax + 1);
-                plo = co[max(cb0 - 1, 0)];
-                pn = co[min(cb1 + 1, ncb)] - plo;
-            }
-            s_lo[j] = plo;
-            s_n[j] = pn;
-        }
-        __syncthreads();
-        for (int j = 0; j < 2 * kMaxGap; j++)
-            if (s_n[j] > kStageCap) s_glb = 1;
-        __syncthreads();
-        const bool glb = s_glb != 0;
-        if (!glb) {
-            for (int j = 0; j < 2 * kMaxGap; j++) {
-                const int n = s_n[j], plo = s_lo[j];
-                for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const SiState S = a.st[si];
+        const int slab = strip - S.strip_base;
+        const int cb0 = slab * S.tcb;
+        const int cb1 = min(cb0 + S.tcb, S.ncb);
+        const int cb_lo = max(cb0 - 1, 0);
+        const int cb_hi = min(cb1 + 1, S.ncb);
+        const float cbw = 1.0f / S.inv_cbw;
+        const float T0 = __fadd_rn(S.t0, __fmul_rn((float)cb_lo, cbw));
+        const float sidx = __fmul_rn(S.inv_cbw, (float)kIdxPerCb);
+        const int nb = (cb_hi - cb_lo) * kIdxPerCb;
+        const int32_t *co_si = a.coff + (int64_t)si * R * (kNcbMax + 1);
+        int nl = 0;
+
+        // stage row rr into its ring slot and build the slot's time index
+        auto stage = [&](int rr) {
+            const int j = rr % kSlots;
+            const int32_t *co = co_si + (int64_t)rr * (kNcbMax + 1);
+            const int plo = co[cb_lo];
+            const int n = co[cb_hi] - plo;
+            const bool glb = n > kSlotCap;
+            if (!glb) {
+                for (int k = tid; k < n; k += kSweepBlock) {
                     const Rec e = a.rec[plo + k];
                     sy[j][k] = e.y;
                     st[j][k] = e.t;
                     sid[j][k] = e.id;
                 }
             }
-        }
-        __syncthreads();
-        int nl = 0;
-        for (int p = own_lo + threadIdx.x; p < own_hi; p += blockDim.x) {
-            const Rec me = a.rec[p];
-            int bu = -1, bd = -1;
-            for (int g = 1; g <= G; g++) {
-                if (r - g < 0 || r + g > R - 1) continue;
-                const int jd = kMaxGap - g, ju = kMaxGap + g - 1;
-                const float w = a.w_tab[r * kMaxGap + g - 1];
-                const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
-                bool f;
-                if (!glb) {
-                    LdsRows D{sy[jd], st[jd], sid[jd], s_lo[jd], s_n[jd]};
-                    LdsRows U{sy[ju], st[ju], sid[ju], s_lo[ju], s_n[ju]};
-                    f = best_pair(D, U, me.y, me.t, w, wy, wt, a.pair_c2, bu, bd);
-                } else {
-                    GlbRows D{a.rec, s_lo[jd], s_n[jd]};
-                    GlbRows U{a.rec, s_lo[ju], s_n[ju]};
-                    f = best_pair(D, U, me.y, me.t, w, wy, wt, a.pair_c2, bu, bd);
-                }
-                if (f) break;
-                bu = -1;
-                bd = -1;
+            if (tid == 0) {
+                s_lo[j] = plo;
+                s_n[j] = n;
+                s_glb[j] = glb ? 1 : 0;
+                if (glb) s_glbrows++;
             }
-            a.link[p] = make_int2(bu, bd);
-            nl += (bu >= 0);
+            __syncthreads();
+            if (!glb) {
+                for (int k = tid; k <= n; k += kSweepBlock) {
+                    int bk = nb + 1, bp = -1;
+                    if (k < n) bk = min(max((int)floorf(__fmul_rn(__fsub_rn(st[j][k], T0), sidx)), 0), nb);
+                    if (k > 0) bp = min(max((int)floorf(__fmul_rn(__fsub_rn(st[j][k - 1], T0), sidx)), 0), nb);
+                    for (int b = bp + 1; b <= min(bk, nb); b++) sfirst[j][b] = k;
+                }
+            }
+        };
+
+        for (int r = 0; r < min(kMaxGap, R); r++) stage(r);
+        for (int r = 0; r < R; r++) {
+            if (r + kMaxGap < R) stage(r + kMaxGap);
+            __syncthreads();
+            // own clusters of row r: coarse bins [cb0, cb1)
+            const int32_t *co_r = co_si + (int64_t)r * (kNcbMax + 1);
+            const int jr = r % kSlots;
+            const int own_lo = co_r[cb0], own_hi = co_r[cb1];
+            for (int p = own_lo + tid; p < own_hi; p += kSweepBlock) {
+                const int k = p - s_lo[jr];
+                float yi, ti;
+                if (!s_glb[jr]) {
+                    yi = sy[jr][k];
+                    ti = st[jr][k];
+                } else {
+                    const Rec e = a.rec[p];
+                    yi = e.y;
+                    ti = e.t;
+                }
+                int bu = -1, bd = -1;
+                for (int g = 1; g <= G; g++) {
+                    if (r - g < 0 || r + g > R - 1) continue;
+                    const int jd = (r - g) % kSlots, ju = (r + g) % kSlots;
+                    const float w = a.w_tab[r * kMaxGap + g - 1];
+                    const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
+                    const bool gd = s_glb[jd] != 0, gu = s_glb[ju] != 0;
+                    LdsSlot LD{sy[jd], st[jd], sid[jd], sfirst[jd], s_lo[jd], s_n[jd], nb, T0, sidx};
+                    LdsSlot LU{sy[ju], st[ju], sid[ju], sfirst[ju], s_lo[ju], s_n[ju], nb, T0, sidx};
+                    GlbSlot GD{a.rec, co_si + (int64_t)(r - g) * (kNcbMax + 1), s_lo[jd], s_n[jd], cb_lo, S.t0,
+                               S.inv_cbw};
+                    GlbSlot GU{a.rec, co_si + (int64_t)(r + g) * (kNcbMax + 1), s_lo[ju], s_n[ju], cb_lo, S.t0,
+                               S.inv_cbw};
+                    bool f;
+                    if (!gd && !gu) f = best_pair(LD, LU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
+                    else if (!gd) f = best_pair(LD, GU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
+                    else if (!gu) f = best_pair(GD, LU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
+                    else f = best_pair(GD, GU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
+                    if (f) break;
+                    bu = -1;
+                    bd = -1;
+                }
+                a.link[p] = make_int2(bu, bd);
+                nl += (bu >= 0);
+            }
+            __syncthreads();
         }
         for (int off = 32; off > 0; off >>= 1) nl += __shfl_xor(nl, off);
-        if ((threadIdx.x & 63) == 0 && nl) atomicAdd(&s_links, nl);
+        if ((tid & 63) == 0 && nl) atomicAdd(&s_links, nl);
         __syncthreads();
-        if (threadIdx.x == 0 && s_links) atomicAdd(&a.cnt->n_links, s_links);
+        if (tid == 0) {
+            if (s_links) atomicAdd(&a.cnt->n_links, s_links);
+            if (s_glbrows) atomicAdd(&a.cnt->n_glb_rows, s_glbrows);
+        }
     }
 }
 
 void launch_links(const KArgs &a, Launch l, hipStream_t s) {
-    int grid = (l.grid / 8) * 8;
-    if (grid < 8) grid = 8;
-    hipLaunchKernelGGL(k_links, dim3(grid), dim3(kLinkBlock), 0, s, a);
+    hipLaunchKernelGGL(k_links, dim3(max(l.grid, 1)), dim3(kSweepBlock), 0, s, a);
 }
 
 }  // namespace tpcca

@@ -13,11 +13,12 @@ constexpr int kMaxRows = 255;      // rows are uint8
 constexpr int kMaxGap = 2;         // symmetric row gaps handled by the link kernel
 constexpr int kNcbMax = 2048;      // coarse time bins per sector row (upper bound)
 constexpr int kFinePerCb = 4;      // fine bins per coarse bin (row sort)
-constexpr int kTileCb = 16;        // coarse bins per neighbour-finding tile
+constexpr int kMaxStripCb = 32;    // most coarse bins in one neighbour-finding strip
 constexpr int kChunk = 8192;       // clusters per histogram / scatter work item
 constexpr int kStageCap = 1024;    // clusters of one neighbour row staged in LDS per tile
 constexpr int kScanItems = 2048;   // elements per block of the device-wide scans
 constexpr int kMaxStages = 16;
+constexpr int kLenBins = 256;      // chain lengths are < 256 (rows are uint8)
 
 // One sector of one frame ("sector instance"), uploaded by the host.
 struct SiDesc {
@@ -37,19 +38,21 @@ struct SiState {
     float t0;                      // time origin of the bins
     float inv_cbw;                 // 1 / coarse bin width
     int32_t ncb;                   // coarse bins per row
-    int32_t nslab;                 // neighbour tiles per row
+    int32_t nslab;                 // neighbour-finding strips (time slabs) of the sector
+    int32_t tcb;                   // coarse bins per strip
     int32_t n_valid;               // clusters that passed validation
     int32_t sbase;                 // first position of the sector in the sorted space
-    int32_t tile_base;             // first neighbour tile of the sector
+    int32_t strip_base;            // first neighbour-finding strip of the sector
     int32_t trk_base, n_tracks;    // first global track slot, number of tracks
     int32_t cl_base, n_cl;         // first entry in the cluster lists, entries
-    int32_t pad[3];
+    int32_t pad[2];
 };
 
 // Device counters of one run (zeroed at the start of the run).
 struct Counters {
     int32_t n_valid_total;
-    int32_t n_tiles;
+    int32_t n_strips;
+    int32_t strip_next;      // work queue of the neighbour-finding strips
     int32_t n_links;
     int32_t n_seeds;
     int32_t n_tseeds;
@@ -57,7 +60,8 @@ struct Counters {
     int32_t n_cl;
     int32_t n_invalid;
     int32_t overflow;
-    int32_t pad[7];
+    int32_t n_glb_rows;      // strip rows that did not fit in LDS (served from L2)
+    int32_t pad[5];
 };
 
 // A cluster in the sorted space: 16 bytes, one load per chain step.
@@ -108,11 +112,13 @@ struct KArgs {
     int32_t *wpre;           // [n_words + 1]
     int32_t *trk_len;        // [trk_cap + 1]
     int32_t *trk_seed;       // [trk_cap]
-    int32_t *cl_off;         // [trk_cap + 1]
+    int32_t *cl_off;         // [trk_cap + 1] offsets of the canonical cluster lists
+    int32_t *off8;           // [trk_cap + 1] offsets of the chain copies (8-entry aligned)
+    int32_t *perm;           // [trk_cap] track slots ordered by decreasing length
+    int32_t *lhist;          // [kLenBins + 1] length histogram / bucket cursors
     tpcca_track *trk;        // [trk_cap]
     int32_t *clusters;       // [n_in]
-    float2 *chain_yt;        // [n_in]
-    uint8_t *chain_row;      // [n_in]
+    Rec *chain;              // [n_in + 7 * trk_cap] chain copies {y, t, id, row}
     int32_t *assign;         // [n_in]
     int32_t *scan_tmp;       // block sums of the scans
     const volatile int32_t *abort_flag;  // host-mapped
@@ -164,6 +170,10 @@ void launch_seeds(const KArgs &a, Launch l, hipStream_t s);
 void launch_chainlen(const KArgs &a, Launch l, hipStream_t s);
 void launch_track_slots(const KArgs &a, Launch l, hipStream_t s);
 void launch_emit(const KArgs &a, Launch l, hipStream_t s);
+void launch_lists(const KArgs &a, Launch l, hipStream_t s);
+void launch_len_sort(const KArgs &a, Launch l, hipStream_t s);
+void launch_scan_round8_dev(const int32_t *in, const int32_t *n_dev, int32_t n_cap, int32_t *out, int32_t *tmp,
+                            hipStream_t s);
 void launch_fit(const KArgs &a, Launch l, hipStream_t s);
 // exclusive scans: out[i] = sum_{j<i} f(in[j]), out[n] = total, *total_dst = total
 void launch_scan_popc(const uint32_t *in, int32_t n, int32_t *out, int32_t *total_dst, int32_t *tmp,

@@ -101,6 +101,23 @@ def test_degenerate_sectors(tp, x):
         compare_sector(trk, f, 0, row, y, t, oc)
 
 
+def test_dense_rows_overflow_lds(tp, x):
+    """A hot spot with far more clusters per strip row than an LDS slot
+    holds: those rows are read from global memory with the same predicates."""
+    rng = np.random.default_rng(11)
+    n = 12000
+    row = rng.integers(20, 26, n).astype(np.uint8)
+    y = (np.round(rng.uniform(-20, 20, n) * 64) / 64).astype(np.float32)
+    t = (np.round(rng.uniform(0, 40, n) * 64) / 64).astype(np.float32)
+    fr = synth.generate("sector_300", seed=3)
+    r0, y0, t0 = fr.sector(0)
+    row = np.concatenate([row, r0]); y = np.concatenate([y, y0]); t = np.concatenate([t, t0])
+    print("case dense", len(row), flush=True)
+    trk, f = _one_sector(tp, row, y, t, min_track_hits=3)
+    assert trk.stats()["n_overflow_rows"] > 0
+    compare_sector(trk, f, 0, row, y, t, oracle_cfg(x, min_track_hits=3), check_params=False)
+
+
 def test_empty_frame_and_ragged_sizes(tp, x):
     """Several frames in one run: empty sectors, a single cluster, and sizes
     around the work-chunk boundary; each sector equals its own oracle."""
