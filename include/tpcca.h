@@ -76,8 +76,9 @@ typedef struct {
     int32_t kf_passes;         /* most Kalman passes: 1 extended, then re-linearised passes until
                                   one moves no parameter by more than 1e-5 relative, 12 */
     float s_max;               /* |sin phi| at which a propagation fails, 0.999 */
-    int32_t use_mlp;           /* 1: prune candidate triplets with the loaded MLP, 0 */
+    int32_t use_mlp;           /* 1: prune candidate triplets with the loaded network, 0 */
     float mlp_logit_threshold; /* triplets with logit below this are pruned, 0 */
+    int32_t pool_per_cluster;  /* triplet-pool slots per input cluster in pruned runs, 3 */
 } tpcca_config;
 
 /* One fitted track. Tracks of a sector are numbered 0..T-1 in ascending
@@ -114,6 +115,10 @@ typedef struct {
     int64_t n_track_clusters;  /* clusters assigned to tracks */
     int64_t n_invalid;         /* input clusters rejected on the device (row or value) */
     int64_t n_overflow_rows;   /* neighbour-finding strip rows too dense for LDS (read from L2) */
+    int64_t n_triplets;        /* pruned runs: accepted candidate triplets scored by the network */
+    int64_t n_pruned;          /* pruned runs: triplets below the threshold (among those examined) */
+    int64_t n_pool_overflow;   /* pruned runs: triplets that did not fit the pool (run is invalid) */
+    int32_t mlp_used;          /* 1 if the last run pruned with the network */
     int64_t n_timed_runs;      /* runs summed in stage_ms_total */
     int32_t n_stages;          /* entries used in stage_ms / stage_name */
     float stage_ms[16];        /* device time per stage, last timed run */
@@ -176,6 +181,20 @@ tpcca_status tpcca_synchronize(tpcca_ctx *ctx);
    results are then undefined and tpcca_synchronize returns ABORTED. */
 tpcca_status tpcca_request_abort(tpcca_ctx *ctx);
 
+/* Replay runs from a captured HIP graph (1) or launch kernel by kernel (0,
+   the default). With graphs on, the first run after a change of frames,
+   arena, configuration or launch settings captures the whole kernel sequence
+   on the stream; later runs launch that graph with one call. Per-stage
+   timing is not recorded in graph mode. */
+tpcca_status tpcca_set_graph(tpcca_ctx *ctx, int32_t on);
+
+/* Launch shape of one stage (the tpcca_stats.stage_name order: 1 hist,
+   3 scatter, 4 rowsort, 5 links, 6 seeds, 7 chainlen, 8 slots, 10 emit,
+   11 fit): blocks_per_cu persistent workgroups per compute unit (0: keep).
+   For stage 5, param sets the target clusters per strip row (64..1024,
+   0: keep). Results do not depend on these settings. */
+tpcca_status tpcca_set_launch(tpcca_ctx *ctx, int32_t stage, int32_t blocks_per_cu, int32_t param);
+
 /* Enable (1) or disable (0) per-stage device timing with HIP events; either
    call also resets the accumulated stage times. */
 tpcca_status tpcca_set_timing(tpcca_ctx *ctx, int32_t on);
@@ -203,6 +222,70 @@ tpcca_status tpcca_get_assignment(tpcca_ctx *ctx, int32_t frame, int32_t sector,
    only mutual links. For checking and debugging. */
 tpcca_status tpcca_get_links(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t cleaned, int32_t *up,
                              int32_t *dn, int64_t n);
+
+/* ---------------------------------------------------------------------
+ * Learned triplet pruning. A small network (12 features -> 64 -> 64 -> 1,
+ * ReLU, BF16 weights and activations, FP32 biases and accumulation) scores
+ * every accepted candidate triplet (down, cluster, up) of the neighbour
+ * finder; with use_mlp = 1 triplets whose logit is below
+ * mlp_logit_threshold are dropped before the best pair is chosen, i.e.
+ * before the cellular automaton. Without loaded weights a run falls back to
+ * the plain finder (tpcca_stats.mlp_used = 0).
+ *
+ * Parameters are exchanged as kMlpNParam = 5313 FP32 values in this order:
+ * w1[64][16] (input columns 12..15 unused), b1[64], w2[64][64], b2[64],
+ * w3[64], b3. The network's state (BF16 weights, FP32 master copy, AdamW
+ * moments, gradient, training workspace) lives in one caller-owned device
+ * buffer of tpcca_mlp_state_bytes() bytes.
+ * --------------------------------------------------------------------- */
+
+/* Bytes of the network state buffer. */
+tpcca_status tpcca_mlp_state_bytes(size_t *bytes);
+
+/* Use [device_ptr, device_ptr + bytes) (256-byte aligned, caller-owned) as
+   the network state. Its contents are (re)initialised by tpcca_mlp_load. */
+tpcca_status tpcca_mlp_attach(tpcca_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* Set the parameters from host FP32 values (weights are rounded to BF16 for
+   use, the FP32 values become the training master copy); resets the AdamW
+   state. STATE without an attached state buffer. Synchronous. */
+tpcca_status tpcca_mlp_load(tpcca_ctx *ctx, const float *params);
+
+/* Copy the FP32 master parameters to host memory (synchronous). */
+tpcca_status tpcca_mlp_fetch(tpcca_ctx *ctx, float *params);
+
+/* Logits of n triplets: x_dev = device [n][16] BF16 features (columns
+   12..15 zero), z_dev = device float[n]. Enqueued on the stream. */
+tpcca_status tpcca_mlp_infer(tpcca_ctx *ctx, const uint16_t *x_dev, int64_t n, float *z_dev);
+
+/* Hyper-parameters of one AdamW step on the weighted BCE-with-logits loss
+   (positive examples weighted by pos_weight). */
+typedef struct {
+    float lr, beta1, beta2, eps, weight_decay, pos_weight;
+} tpcca_mlp_hparams;
+
+/* Gradient of the mean weighted BCE loss over the n (<= 8192) examples
+   (x_dev [n][16] BF16, y_dev float[n] in {0,1}) with respect to the
+   parameters, as FP32 in the parameter order, into grad_dev (device,
+   5313 floats); loss_dev (device, 1 float) receives the loss. Forward and
+   backward products run on the matrix cores with BF16 operands and FP32
+   accumulation. Enqueued on the stream. */
+tpcca_status tpcca_mlp_grad(tpcca_ctx *ctx, const uint16_t *x_dev, const float *y_dev, int64_t n, float pos_weight,
+                            float *grad_dev, float *loss_dev);
+
+/* One AdamW step on a minibatch (same inputs as tpcca_mlp_grad): updates
+   the FP32 master parameters and their BF16 copies on the device. loss_dev
+   may be NULL. Enqueued on the stream. */
+tpcca_status tpcca_mlp_train_step(tpcca_ctx *ctx, const uint16_t *x_dev, const float *y_dev, int64_t n,
+                                  const tpcca_mlp_hparams *hp, float *loss_dev);
+
+/* Triplets of the last pruned run for one (frame, sector), ordered by the
+   input index of the middle cluster, then gap, then candidate order:
+   tri[k] = (down, cluster, up, gap) input indices, feat[k] = 16 BF16
+   features, z[k] = logit (any output pointer may be NULL). CAPACITY if cap
+   is too small; *n_out receives the count. Synchronous. */
+tpcca_status tpcca_get_triplets(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *tri, uint16_t *feat,
+                                float *z, int64_t cap, int64_t *n_out);
 
 #ifdef __cplusplus
 }

@@ -3,6 +3,8 @@
 // caller's arena; buffers that are dead after a stage are reused by later
 // stages), stage orchestration on the caller's stream and result fetches.
 #include <algorithm>
+#include <climits>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -38,6 +40,8 @@ struct Layout {
     size_t trk_len, trk_seed, cl_off, trk;
     size_t clusters, assign, scan_tmp;
     size_t off8, perm, lhist, chain;
+    size_t pfeat, pd, pu, pc, pz, hoff, hn1, hn2;
+    int64_t pool_cap = 0;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -93,7 +97,23 @@ struct tpcca_ctx {
     int64_t n_in = 0;
     int32_t n_words = 0;
     Launch lc[kNumStages];
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_valid = false;
+    int32_t strip_target = 230;  // clusters per strip row (link finding)
+    char *mlp = nullptr;       // caller-owned network state buffer
+    bool mlp_loaded = false;
+    bool pruned_run = false;   // the plan includes the triplet pool
 };
+
+static void drop_graph(tpcca_ctx *c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_valid = false;
+}
 
 static tpcca_status fail(tpcca_ctx *c, tpcca_status s, const std::string &m) {
     if (c) c->err = m;
@@ -143,6 +163,7 @@ tpcca_status tpcca_config_default(tpcca_config *out) {
     c.s_max = 0.999f;
     c.use_mlp = 0;
     c.mlp_logit_threshold = 0.0f;
+    c.pool_per_cluster = 3;
     *out = c;
     return TPCCA_OK;
 }
@@ -154,6 +175,9 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
         return TPCCA_ERR_INVALID_ARG;
     if (cfg->max_gap < 1 || cfg->max_gap > kMaxGap || cfg->min_track_hits < 3 || cfg->kf_passes < 1 ||
         cfg->kf_passes > 64)
+        return TPCCA_ERR_INVALID_ARG;
+    if (cfg->pool_per_cluster < 1 || cfg->pool_per_cluster > 64 || !std::isfinite(cfg->mlp_logit_threshold) ||
+        cfg->use_mlp < 0 || cfg->use_mlp > 1)
         return TPCCA_ERR_INVALID_ARG;
     if (!(cfg->win_y > 0) || !(cfg->win_t > 0) || !(cfg->pair_c2 >= 0) || !(cfg->sigma_y > 0) ||
         !(cfg->sigma_t > 0) || !(cfg->prior_var_sinphi > 0) || !(cfg->prior_var_tau > 0) ||
@@ -207,6 +231,8 @@ void tpcca_destroy(tpcca_ctx *c) {
     if (c->events_ok)
         for (int r = 0; r < kEvRing; r++)
             for (int i = 0; i <= kNumStages; i++) (void)hipEventDestroy(c->ev[r][i]);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->abort_host) (void)hipHostFree(c->abort_host);
     delete c;
 }
@@ -236,11 +262,37 @@ tpcca_status tpcca_set_timing(tpcca_ctx *c, int32_t on) {
     return TPCCA_OK;
 }
 
+tpcca_status tpcca_set_graph(tpcca_ctx *c, int32_t on) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    c->use_graph = on != 0;
+    drop_graph(c);
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_set_launch(tpcca_ctx *c, int32_t stage, int32_t blocks_per_cu, int32_t param) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    static const int tunable[] = {1, 3, 4, 5, 6, 7, 8, 10, 11};
+    bool ok = false;
+    for (int v : tunable) ok = ok || v == stage;
+    if (!ok || blocks_per_cu < 0 || blocks_per_cu > 64) return fail(c, TPCCA_ERR_INVALID_ARG, "bad stage or blocks");
+    if (param != 0 && (stage != 5 || param < 64 || param > 1024)) return fail(c, TPCCA_ERR_INVALID_ARG, "bad param");
+    if (stage == 4 && blocks_per_cu > 4) return fail(c, TPCCA_ERR_INVALID_ARG, "rowsort: at most 4 blocks per CU");
+    if (stage == 5 && blocks_per_cu > 3) return fail(c, TPCCA_ERR_INVALID_ARG, "links: at most 3 blocks per CU");
+    (void)hipStreamSynchronize(c->stream);
+    if (blocks_per_cu) c->lc[stage].grid = std::max(1, c->n_cu) * blocks_per_cu;
+    if (param) c->strip_target = param;
+    c->plan_dirty = true;  // the strip target is a kernel argument
+    c->graph_valid = false;
+    return TPCCA_OK;
+}
+
 tpcca_status tpcca_add_frame(tpcca_ctx *c, int32_t *frame_id) {
     if (!c || !frame_id) return TPCCA_ERR_INVALID_ARG;
     c->frames.emplace_back((size_t)c->cfg.n_sectors);
     *frame_id = (int32_t)c->frames.size() - 1;
     c->plan_dirty = true;
+    c->graph_valid = false;
     c->have_results = false;
     return TPCCA_OK;
 }
@@ -250,6 +302,7 @@ tpcca_status tpcca_clear_frames(tpcca_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     c->frames.clear();
     c->plan_dirty = true;
+    c->graph_valid = false;
     c->have_results = false;
     return TPCCA_OK;
 }
@@ -286,6 +339,7 @@ tpcca_status tpcca_load_sector(tpcca_ctx *c, int32_t frame, int32_t sector, int6
         s.ht.assign(t, t + n);
     }
     c->plan_dirty = true;
+    c->graph_valid = false;
     c->have_results = false;
     return TPCCA_OK;
 }
@@ -371,6 +425,17 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.chain = b.take(sizeof(Rec) * (N + 7 * trk_cap));
     L.clusters = b.take(sizeof(int32_t) * N);
     L.assign = b.take(sizeof(int32_t) * N);
+    c->pruned_run = c->cfg.use_mlp != 0;
+    L.pool_cap = c->pruned_run ? (int64_t)c->cfg.pool_per_cluster * N + kPoolChunk : 0;
+    if (L.pool_cap > (int64_t)0x7fff0000) L.pool_cap = 0x7fff0000;
+    L.pfeat = b.take(sizeof(uint16_t) * kMlpInP * L.pool_cap);
+    L.pd = b.take(sizeof(int32_t) * L.pool_cap);
+    L.pu = b.take(sizeof(int32_t) * L.pool_cap);
+    L.pc = b.take(sizeof(float) * L.pool_cap);
+    L.pz = b.take(sizeof(float) * L.pool_cap);
+    L.hoff = b.take(c->pruned_run ? sizeof(int32_t) * N : 0);
+    L.hn1 = b.take(c->pruned_run ? sizeof(int32_t) * N : 0);
+    L.hn2 = b.take(c->pruned_run ? sizeof(int32_t) * N : 0);
     const int64_t nblk = (std::max<int64_t>(W, trk_cap) + kScanItems - 1) / kScanItems + 2;
     L.scan_tmp = b.take(sizeof(int32_t) * nblk);
     L.total = align_up(b.off, 256);
@@ -388,6 +453,7 @@ static tpcca_status plan(tpcca_ctx *c) {
     a.tseed_cap = (int32_t)tseed_cap;
     a.trk_cap = (int32_t)trk_cap;
     a.max_gap = c->cfg.max_gap;
+    a.strip_target = c->strip_target;
     a.min_track_hits = c->cfg.min_track_hits;
     a.kf_passes = c->cfg.kf_passes;
     for (int g = 1; g <= kMaxGap; g++) {
@@ -407,6 +473,12 @@ static tpcca_status plan(tpcca_ctx *c) {
     a.var_tau = c->cfg.prior_var_tau;
     a.var_k = c->cfg.prior_var_qpt;
     a.s_max = c->cfg.s_max;
+    a.theta = c->cfg.mlp_logit_threshold;
+    {
+        volatile float c2 = c->cfg.pair_c2;
+        a.c2s = sqrtf(c2);
+    }
+    a.pool_cap = (int32_t)L.pool_cap;
     (void)host_bytes;
     c->plan_dirty = false;
     c->upload_dirty = true;
@@ -448,6 +520,75 @@ static void bind_pointers(tpcca_ctx *c) {
     a.assign = (int32_t *)(A + L.assign);
     a.scan_tmp = (int32_t *)(A + L.scan_tmp);
     a.abort_flag = c->abort_dev;
+    a.pfeat = (uint16_t *)(A + L.pfeat);
+    a.pd = (int32_t *)(A + L.pd);
+    a.pu = (int32_t *)(A + L.pu);
+    a.pc = (float *)(A + L.pc);
+    a.pz = (float *)(A + L.pz);
+    a.hoff = (int32_t *)(A + L.hoff);
+    a.hn1 = (int32_t *)(A + L.hn1);
+    a.hn2 = (int32_t *)(A + L.hn2);
+    a.use_mlp = (c->pruned_run && c->mlp_loaded) ? 1 : 0;
+    if (c->mlp) {
+        a.mlp.w1 = (const uint16_t *)(c->mlp + MlpState::w1);
+        a.mlp.w2 = (const uint16_t *)(c->mlp + MlpState::w2);
+        a.mlp.w3 = (const uint16_t *)(c->mlp + MlpState::w3);
+        a.mlp.b1 = (const float *)(c->mlp + MlpState::b1);
+        a.mlp.b2 = (const float *)(c->mlp + MlpState::b2);
+        a.mlp.b3 = (const float *)(c->mlp + MlpState::b3);
+    }
+}
+
+// Enqueue the kernels of one run on s (events into ring slot `slot` if tm).
+static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
+    const KArgs &a = c->args;
+    const Layout &L = c->lay;
+    char *A = c->arena;
+    Counters *cnt = (Counters *)(A + L.cnt);
+    int st = 0;
+    auto mark = [&](int i) {
+        if (tm) (void)hipEventRecord(c->ev[slot][i], s);
+    };
+    mark(st++);
+    // reset: row counts, bitmap, assignment (fill kernels: graph-safe)
+    launch_fill_i32(a.rcnt, (int64_t)a.n_si * a.n_rows, 0, s);
+    launch_fill_i32((int32_t *)a.bits, (int64_t)a.n_words + 1, 0, s);
+    launch_fill_i32(a.assign, (int64_t)a.n_in, -1, s);
+    mark(st++);
+    launch_grid_hist(a, c->lc[1], s);  // also resets per-sector state and counters
+    mark(st++);
+    launch_grid_setup(a, s);
+    mark(st++);
+    launch_grid_scatter(a, c->lc[3], s);
+    mark(st++);
+    launch_grid_rowsort(a, c->lc[4], s);
+    mark(st++);
+    if (a.use_mlp) {
+        launch_links_enum(a, c->lc[5], s);
+        launch_mlp_infer(a.mlp, a.pfeat, &cnt->pool_next, a.pool_cap, a.pz, c->n_cu * 8, s);
+        launch_select(a, c->lc[6], s);
+    } else {
+        launch_links(a, c->lc[5], s);
+    }
+    mark(st++);
+    launch_seeds(a, c->lc[6], s);
+    mark(st++);
+    launch_chainlen(a, c->lc[7], s);
+    mark(st++);
+    launch_scan_popc(a.bits, a.n_words, a.wpre, &cnt->n_tracks, a.scan_tmp, s);
+    launch_track_slots(a, c->lc[8], s);
+    launch_si_tracks(a, s);
+    mark(st++);
+    launch_scan_i32_dev(a.trk_len, &cnt->n_tracks, a.trk_cap, a.cl_off, &cnt->n_cl, a.scan_tmp, s);
+    launch_scan_round8_dev(a.trk_len, &cnt->n_tracks, a.trk_cap, a.off8, a.scan_tmp, s);
+    launch_si_clusters(a, s);
+    mark(st++);
+    launch_emit(a, c->lc[10], s);
+    launch_lists(a, c->lc[10], s);
+    mark(st++);
+    launch_len_sort(a, c->lc[11], s);
+    launch_fit(a, c->lc[11], s);
+    mark(st++);
 }
 
 // Fold one completed ring slot into the totals (waits for its last event).
@@ -483,6 +624,7 @@ tpcca_status tpcca_attach_arena(tpcca_ctx *c, void *ptr, size_t bytes) {
     c->arena = (char *)ptr;
     c->arena_bytes = ptr ? bytes : 0;
     c->upload_dirty = true;
+    c->graph_valid = false;
     c->have_results = false;
     return TPCCA_OK;
 }
@@ -505,7 +647,6 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
                                             std::to_string(c->lay.total));
     hipStream_t s = c->stream;
     bind_pointers(c);
-    const KArgs &a = c->args;
     const Layout &L = c->lay;
     char *A = c->arena;
     if (c->upload_dirty) {
@@ -546,51 +687,28 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
         HIPCHK(c, hipStreamSynchronize(s));
         c->upload_dirty = false;
     }
-    const bool tm = c->timing && c->events_ok;
+    const bool tm = c->timing && c->events_ok && !c->use_graph;
     const int slot = c->ev_next;
     if (tm) {
         fold_slot(c, slot);  // the slot is reused: fold its previous run first
         c->ev_next = (slot + 1) % kEvRing;
     }
-    int st = 0;
-    auto mark = [&](int i) {
-        if (tm) (void)hipEventRecord(c->ev[slot][i], s);
-    };
-    mark(st++);
-    // reset: counters, per-sector state, row counts, bitmap, assignment
-    launch_fill_i32(a.rcnt, (int64_t)a.n_si * a.n_rows, 0, s);
-    launch_fill_i32((int32_t *)a.bits, (int64_t)a.n_words + 1, 0, s);
-    launch_fill_i32(a.assign, (int64_t)a.n_in, -1, s);
-    mark(st++);
-    launch_grid_hist(a, c->lc[1], s);  // also resets per-sector state and counters
-    mark(st++);
-    launch_grid_setup(a, s);
-    mark(st++);
-    launch_grid_scatter(a, c->lc[3], s);
-    mark(st++);
-    launch_grid_rowsort(a, c->lc[4], s);
-    mark(st++);
-    launch_links(a, c->lc[5], s);
-    mark(st++);
-    launch_seeds(a, c->lc[6], s);
-    mark(st++);
-    launch_chainlen(a, c->lc[7], s);
-    mark(st++);
-    launch_scan_popc(a.bits, a.n_words, a.wpre, &((Counters *)(A + L.cnt))->n_tracks, a.scan_tmp, s);
-    launch_track_slots(a, c->lc[8], s);
-    launch_si_tracks(a, s);
-    mark(st++);
-    launch_scan_i32_dev(a.trk_len, &((Counters *)(A + L.cnt))->n_tracks, a.trk_cap, a.cl_off,
-                        &((Counters *)(A + L.cnt))->n_cl, a.scan_tmp, s);
-    launch_scan_round8_dev(a.trk_len, &((Counters *)(A + L.cnt))->n_tracks, a.trk_cap, a.off8, a.scan_tmp, s);
-    launch_si_clusters(a, s);
-    mark(st++);
-    launch_emit(a, c->lc[10], s);
-    launch_lists(a, c->lc[10], s);
-    mark(st++);
-    launch_len_sort(a, c->lc[11], s);
-    launch_fit(a, c->lc[11], s);
-    mark(st++);
+    if (c->use_graph) {
+        if (!c->graph_valid) {
+            drop_graph(c);
+            HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+            enqueue_run(c, s, false, slot);
+            hipGraph_t g = nullptr;
+            hipError_t ec = hipStreamEndCapture(s, &g);
+            if (ec != hipSuccess) return hip_fail(c, ec, "hipStreamEndCapture (graph mode needs a non-default stream)");
+            c->graph = g;
+            HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+            c->graph_valid = true;
+        }
+        HIPCHK(c, hipGraphLaunch(c->graph_exec, s));
+    } else {
+        enqueue_run(c, s, tm, slot);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
     if (tm) c->ev_pending[slot] = true;
@@ -602,6 +720,15 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
 tpcca_status tpcca_synchronize(tpcca_ctx *c) {
     if (!c) return TPCCA_ERR_INVALID_ARG;
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->have_results && c->args.use_mlp && c->arena) {
+        int32_t ovf = 0;
+        HIPCHK(c, hipMemcpy(&ovf, c->arena + c->lay.cnt + offsetof(Counters, pool_overflow), sizeof(ovf),
+                            hipMemcpyDeviceToHost));
+        if (ovf > 0) {
+            c->have_results = false;
+            return fail(c, TPCCA_ERR_CAPACITY, "triplet pool overflow: raise pool_per_cluster");
+        }
+    }
     if (__atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST)) {
         __atomic_store_n(c->abort_host, 0, __ATOMIC_SEQ_CST);
         c->have_results = false;
@@ -626,6 +753,10 @@ tpcca_status tpcca_get_stats(tpcca_ctx *c, tpcca_stats *out) {
     out->n_track_clusters = k.n_cl;
     out->n_invalid = k.n_invalid;
     out->n_overflow_rows = k.n_glb_rows;
+    out->n_triplets = c->args.use_mlp ? k.pool_used : 0;
+    out->n_pruned = k.n_pruned;
+    out->n_pool_overflow = k.pool_overflow;
+    out->mlp_used = c->args.use_mlp;
     out->n_stages = 0;
     if (c->timing && c->events_ok) {
         for (int r = 0; r < kEvRing; r++) fold_slot(c, (c->ev_next + r) % kEvRing);
@@ -735,6 +866,208 @@ tpcca_status tpcca_get_links(tpcca_ctx *c, int32_t frame, int32_t sector, int32_
         if (dd >= 0 && (!cleaned || lk[dd - base].x == p + base)) doo = rec[dd - base].id;
         up[id] = uo;
         dn[id] = doo;
+    }
+    return TPCCA_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------- MLP
+static uint16_t host_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+extern "C" {
+
+tpcca_status tpcca_mlp_state_bytes(size_t *bytes) {
+    if (!bytes) return TPCCA_ERR_INVALID_ARG;
+    *bytes = MlpState::bytes;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_mlp_attach(tpcca_ctx *c, void *ptr, size_t bytes) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    if (ptr && ((uintptr_t)ptr & 255)) return fail(c, TPCCA_ERR_INVALID_ARG, "state buffer must be 256-byte aligned");
+    if (ptr && bytes < MlpState::bytes) return fail(c, TPCCA_ERR_NOMEM, "network state buffer too small");
+    (void)hipStreamSynchronize(c->stream);
+    c->mlp = (char *)ptr;
+    c->mlp_loaded = false;
+    c->graph_valid = false;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_mlp_load(tpcca_ctx *c, const float *params) {
+    if (!c || !params) return TPCCA_ERR_INVALID_ARG;
+    if (!c->mlp) return fail(c, TPCCA_ERR_STATE, "no network state buffer attached");
+    for (int i = 0; i < kMlpNParam; i++)
+        if (!std::isfinite(params[i])) return fail(c, TPCCA_ERR_INVALID_ARG, "non-finite network parameter");
+    std::vector<uint16_t> w1(kMlpH * kMlpInP), w2(kMlpH * kMlpH), w3(kMlpH);
+    std::vector<float> master(params, params + kMlpNParam);
+    for (int j = 0; j < kMlpH; j++)
+        for (int k = kMlpIn; k < kMlpInP; k++) master[j * kMlpInP + k] = 0.f;  // unused input columns
+    for (int i = 0; i < kMlpH * kMlpInP; i++) w1[i] = host_bf16(master[i]);
+    for (int i = 0; i < kMlpH * kMlpH; i++) w2[i] = host_bf16(master[1088 + i]);
+    for (int i = 0; i < kMlpH; i++) w3[i] = host_bf16(master[5248 + i]);
+    std::vector<char> zeros(MlpState::bytes - MlpState::adam_m, 0);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->mlp + MlpState::w1, w1.data(), w1.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->mlp + MlpState::w2, w2.data(), w2.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->mlp + MlpState::w3, w3.data(), w3.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->mlp + MlpState::b1, master.data() + 1024, kMlpH * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->mlp + MlpState::b2, master.data() + 5184, kMlpH * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->mlp + MlpState::b3, master.data() + 5312, 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->mlp + MlpState::master, master.data(), kMlpNParam * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->mlp + MlpState::adam_m, zeros.data(), zeros.size(), hipMemcpyHostToDevice));
+    if (!c->mlp_loaded) c->graph_valid = false;  // the run's flow changes (plain -> pruned)
+    c->mlp_loaded = true;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_mlp_fetch(tpcca_ctx *c, float *params) {
+    if (!c || !params) return TPCCA_ERR_INVALID_ARG;
+    if (!c->mlp || !c->mlp_loaded) return fail(c, TPCCA_ERR_STATE, "no network loaded");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(params, c->mlp + MlpState::master, kMlpNParam * 4, hipMemcpyDeviceToHost));
+    return TPCCA_OK;
+}
+
+static MlpDev mlp_dev(tpcca_ctx *c) {
+    MlpDev W;
+    W.w1 = (const uint16_t *)(c->mlp + MlpState::w1);
+    W.w2 = (const uint16_t *)(c->mlp + MlpState::w2);
+    W.w3 = (const uint16_t *)(c->mlp + MlpState::w3);
+    W.b1 = (const float *)(c->mlp + MlpState::b1);
+    W.b2 = (const float *)(c->mlp + MlpState::b2);
+    W.b3 = (const float *)(c->mlp + MlpState::b3);
+    return W;
+}
+
+tpcca_status tpcca_mlp_infer(tpcca_ctx *c, const uint16_t *x, int64_t n, float *z) {
+    if (!c || n < 0 || n > 0x7fff0000 || (n > 0 && (!x || !z))) return TPCCA_ERR_INVALID_ARG;
+    if (!c->mlp || !c->mlp_loaded) return fail(c, TPCCA_ERR_STATE, "no network loaded");
+    if (n == 0) return TPCCA_OK;
+    const int grid = (int)std::min<int64_t>((n + 63) / 64, (int64_t)c->n_cu * 8);
+    launch_mlp_infer(mlp_dev(c), x, nullptr, (int32_t)n, z, grid, c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "mlp infer launch");
+    return TPCCA_OK;
+}
+
+static tpcca_status mlp_step(tpcca_ctx *c, const uint16_t *x, const float *y, int64_t n, float pos_weight,
+                             const tpcca_mlp_hparams *hp, float *grad, float *loss) {
+    if (!c || n < 1 || n > kMlpMaxBatch || !x || !y) return fail(c, TPCCA_ERR_INVALID_ARG, "batch of 1..8192 examples");
+    if (!c->mlp || !c->mlp_loaded) return fail(c, TPCCA_ERR_STATE, "no network loaded");
+    MlpTrainArgs t{};
+    char *M = c->mlp;
+    t.w1 = (uint16_t *)(M + MlpState::w1);
+    t.w2 = (uint16_t *)(M + MlpState::w2);
+    t.w3 = (uint16_t *)(M + MlpState::w3);
+    t.b1 = (float *)(M + MlpState::b1);
+    t.b2 = (float *)(M + MlpState::b2);
+    t.b3 = (float *)(M + MlpState::b3);
+    t.master = (float *)(M + MlpState::master);
+    t.adam_m = (float *)(M + MlpState::adam_m);
+    t.adam_v = (float *)(M + MlpState::adam_v);
+    t.step = (int32_t *)(M + MlpState::step);
+    t.X = x;
+    t.Y = y;
+    t.n = (int32_t)n;
+    t.pos_weight = hp ? hp->pos_weight : pos_weight;
+    if (hp) {
+        if (!(hp->lr > 0) || !(hp->beta1 >= 0 && hp->beta1 < 1) || !(hp->beta2 >= 0 && hp->beta2 < 1) ||
+            !(hp->eps > 0) || !(hp->weight_decay >= 0) || !(hp->pos_weight > 0))
+            return fail(c, TPCCA_ERR_INVALID_ARG, "bad optimiser hyper-parameters");
+        t.lr = hp->lr;
+        t.beta1 = hp->beta1;
+        t.beta2 = hp->beta2;
+        t.eps = hp->eps;
+        t.weight_decay = hp->weight_decay;
+        t.update = 1;
+    } else {
+        if (!grad) return TPCCA_ERR_INVALID_ARG;
+        t.update = 0;
+        t.grad_out = grad;
+    }
+    t.loss_out = loss;
+    launch_mlp_train(t, c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "mlp step launch");
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_mlp_grad(tpcca_ctx *c, const uint16_t *x, const float *y, int64_t n, float pos_weight, float *grad,
+                            float *loss) {
+    if (!(pos_weight > 0)) return fail(c, TPCCA_ERR_INVALID_ARG, "pos_weight must be > 0");
+    return mlp_step(c, x, y, n, pos_weight, nullptr, grad, loss);
+}
+
+tpcca_status tpcca_mlp_train_step(tpcca_ctx *c, const uint16_t *x, const float *y, int64_t n,
+                                  const tpcca_mlp_hparams *hp, float *loss) {
+    if (!hp) return TPCCA_ERR_INVALID_ARG;
+    return mlp_step(c, x, y, n, 0.f, hp, nullptr, loss);
+}
+
+tpcca_status tpcca_get_triplets(tpcca_ctx *c, int32_t frame, int32_t sector, int32_t *tri, uint16_t *feat, float *z,
+                                int64_t cap, int64_t *n_out) {
+    if (!c || !n_out) return TPCCA_ERR_INVALID_ARG;
+    int si;
+    SiState st;
+    tpcca_status s = locate(c, frame, sector, si, st);
+    if (s != TPCCA_OK) return s;
+    if (!c->args.use_mlp) return fail(c, TPCCA_ERR_STATE, "the last run was not a pruned run");
+    const int nv = st.n_valid;
+    std::vector<int32_t> hoff(nv), hn1(nv), hn2(nv);
+    std::vector<Rec> rec(nv);
+    if (nv > 0) {
+        const size_t o = (size_t)st.sbase;
+        HIPCHK(c, hipMemcpy(hoff.data(), c->arena + c->lay.hoff + 4 * o, 4 * (size_t)nv, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(hn1.data(), c->arena + c->lay.hn1 + 4 * o, 4 * (size_t)nv, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(hn2.data(), c->arena + c->lay.hn2 + 4 * o, 4 * (size_t)nv, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(rec.data(), c->arena + c->lay.rec + sizeof(Rec) * o, sizeof(Rec) * (size_t)nv,
+                            hipMemcpyDeviceToHost));
+    }
+    int64_t total = 0, lo = INT64_MAX, hi = 0;
+    std::vector<int> order(nv);
+    for (int p = 0; p < nv; p++) {
+        order[p] = p;
+        const int64_t k = (int64_t)hn1[p] + hn2[p];
+        total += k;
+        if (k > 0 && hoff[p] >= 0) {
+            lo = std::min<int64_t>(lo, hoff[p]);
+            hi = std::max<int64_t>(hi, hoff[p] + k);
+        }
+    }
+    *n_out = total;
+    if (cap < total) return fail(c, TPCCA_ERR_CAPACITY, "triplet buffer too small");
+    if (total == 0) return TPCCA_OK;
+    const size_t span = (size_t)(hi - lo);
+    std::vector<uint16_t> pf(span * kMlpInP);
+    std::vector<int32_t> pd(span), pu(span);
+    std::vector<float> pz(span);
+    HIPCHK(c, hipMemcpy(pf.data(), c->arena + c->lay.pfeat + 2 * kMlpInP * (size_t)lo, 2 * kMlpInP * span,
+                        hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(pd.data(), c->arena + c->lay.pd + 4 * (size_t)lo, 4 * span, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(pu.data(), c->arena + c->lay.pu + 4 * (size_t)lo, 4 * span, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(pz.data(), c->arena + c->lay.pz + 4 * (size_t)lo, 4 * span, hipMemcpyDeviceToHost));
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return rec[a].id < rec[b].id; });
+    int64_t k = 0;
+    const int base = st.sbase;
+    for (int p : order) {
+        const int n = hn1[p] + hn2[p];
+        for (int j = 0; j < n; j++, k++) {
+            const int64_t src = (int64_t)hoff[p] + j - lo;
+            if (tri) {
+                tri[4 * k] = rec[pd[src] - base].id;
+                tri[4 * k + 1] = rec[p].id;
+                tri[4 * k + 2] = rec[pu[src] - base].id;
+                tri[4 * k + 3] = j < hn1[p] ? 1 : 2;
+            }
+            if (feat) std::memcpy(feat + kMlpInP * k, pf.data() + kMlpInP * src, 2 * kMlpInP);
+            if (z) z[k] = pz[src];
+        }
     }
     return TPCCA_OK;
 }

@@ -150,11 +150,11 @@ __global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
                 inv = 0.f;
                 ncb = 1;
             }
-            // strip width: about 0.9 x 256 own clusters per row on average
+            // strip width: about strip_target own clusters per row on average
             int tcb = kMaxStripCb;
             if (nv > 0) {
                 const float dens = (float)nv / ((float)R * (float)ncb);
-                tcb = min(max((int)(230.f / fmaxf(dens, 1e-3f)), 2), kMaxStripCb);
+                tcb = min(max((int)((float)a.strip_target / fmaxf(dens, 1e-3f)), 2), kMaxStripCb);
             }
             s.t0 = tmin;
             s.inv_cbw = inv;

@@ -107,6 +107,109 @@ __device__ inline bool best_pair(const VD &D, const VU &U, float yi, float ti, f
     return found;
 }
 
+// Number of clusters inside the box on each of the two rows.
+template <class VD, class VU>
+__device__ inline int box_count(const VD &D, const VU &U, float yi, float ti, float wy, float wt) {
+    const float tl = __fsub_rn(ti, wt);
+    int n = 0;
+    for (int k = D.start(tl); k < D.n; k++) {
+        const float td = D.T(k);
+        if (__fsub_rn(td, ti) > wt) break;
+        n += (fabsf(__fsub_rn(yi, D.Y(k))) <= wy && fabsf(__fsub_rn(ti, td)) <= wt);
+    }
+    for (int k = U.start(tl); k < U.n; k++) {
+        const float tu = U.T(k);
+        if (__fsub_rn(tu, ti) > wt) break;
+        n += (fabsf(__fsub_rn(U.Y(k), yi)) <= wy && fabsf(__fsub_rn(tu, ti)) <= wt);
+    }
+    return n;
+}
+
+__device__ inline uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// The 12 triplet features, every FP32 operation separately rounded in a
+// fixed order (division and square root correctly rounded), then BF16.
+__device__ inline void triplet_features(float yd, float td, float xd, float yi, float ti, float xi, float yu, float tu,
+                                        float xu, int g, float wy, float wt, float w, float c2s, int ncand,
+                                        uint16_t *f) {
+    const float dyu = __fsub_rn(yu, yi), dtu = __fsub_rn(tu, ti);
+    const float dyd = __fsub_rn(yi, yd), dtd = __fsub_rn(ti, td);
+    const float by = __fsub_rn(yu, yd), bt = __fsub_rn(tu, td);
+    const float ry = __fsub_rn(dyd, __fmul_rn(w, by));
+    const float rt = __fsub_rn(dtd, __fmul_rn(w, bt));
+    const float ax = __fsub_rn(xi, xd), cx = __fsub_rn(xu, xd), ux = __fsub_rn(xu, xi);
+    const float cr = __fsub_rn(__fmul_rn(ax, by), __fmul_rn(dyd, cx));
+    const float dab = __fsqrt_rn(__fadd_rn(__fmul_rn(ax, ax), __fmul_rn(dyd, dyd)));
+    const float dac = __fsqrt_rn(__fadd_rn(__fmul_rn(cx, cx), __fmul_rn(by, by)));
+    const float dbc = __fsqrt_rn(__fadd_rn(__fmul_rn(ux, ux), __fmul_rn(dyu, dyu)));
+    const float den = __fmul_rn(__fmul_rn(dab, dac), dbc);
+    const float kap = __fdiv_rn(__fmul_rn(2.0f, cr), den);
+    f[0] = bf16_rne(__fdiv_rn(dyu, wy));
+    f[1] = bf16_rne(__fdiv_rn(dtu, wt));
+    f[2] = bf16_rne(__fdiv_rn(dyd, wy));
+    f[3] = bf16_rne(__fdiv_rn(dtd, wt));
+    f[4] = bf16_rne((float)g);
+    f[5] = bf16_rne(__fdiv_rn(xi, 245.0f));
+    f[6] = bf16_rne(__fdiv_rn(ry, c2s));
+    f[7] = bf16_rne(__fdiv_rn(rt, c2s));
+    f[8] = bf16_rne(__fdiv_rn(kap, 0.015f));
+    f[9] = bf16_rne(__fdiv_rn(by, cx));
+    f[10] = bf16_rne(__fdiv_rn(bt, cx));
+    f[11] = bf16_rne(__fdiv_rn((float)ncand, 8.0f));
+    f[12] = f[13] = f[14] = f[15] = 0;
+}
+
+// Visit every accepted pair (c <= c2) of the cluster in the fixed order
+// (down clusters in time order, then up clusters in time order); with
+// write = false it only counts them.
+template <bool write, class VD, class VU>
+__device__ inline int visit_pairs(const VD &D, const VU &U, float yi, float ti, float xd, float xi, float xu, int g,
+                                  float w, float wy, float wt, float c2, float c2s, int ncand, const KArgs &a,
+                                  int slot) {
+    const float tl = __fsub_rn(ti, wt);
+    const int sd = D.start(tl), su = U.start(tl);
+    int n = 0;
+    for (int kd = sd; kd < D.n; kd++) {
+        const float td = D.T(kd);
+        if (__fsub_rn(td, ti) > wt) break;
+        const float yd = D.Y(kd);
+        if (!(fabsf(__fsub_rn(yi, yd)) <= wy && fabsf(__fsub_rn(ti, td)) <= wt)) continue;
+        const float ady = __fsub_rn(yi, yd);
+        const float adt = __fsub_rn(ti, td);
+        for (int ku = su; ku < U.n; ku++) {
+            const float tu = U.T(ku);
+            if (__fsub_rn(tu, ti) > wt) break;
+            const float yu = U.Y(ku);
+            if (!(fabsf(__fsub_rn(yu, yi)) <= wy && fabsf(__fsub_rn(tu, ti)) <= wt)) continue;
+            const float by = __fsub_rn(yu, yd);
+            const float bt = __fsub_rn(tu, td);
+            const float ry = __fsub_rn(ady, __fmul_rn(w, by));
+            const float rt = __fsub_rn(adt, __fmul_rn(w, bt));
+            const float c = __fadd_rn(__fmul_rn(ry, ry), __fmul_rn(rt, rt));
+            if (!(c <= c2)) continue;
+            if (write) {
+                const int k = slot + n;
+                uint16_t f[kMlpInP];
+                triplet_features(yd, td, xd, yi, ti, xi, yu, tu, xu, g, wy, wt, w, c2s, ncand, f);
+                uint4 *dst = reinterpret_cast<uint4 *>(a.pfeat + (int64_t)k * kMlpInP);
+                dst[0] = make_uint4(f[0] | ((uint32_t)f[1] << 16), f[2] | ((uint32_t)f[3] << 16),
+                                    f[4] | ((uint32_t)f[5] << 16), f[6] | ((uint32_t)f[7] << 16));
+                dst[1] = make_uint4(f[8] | ((uint32_t)f[9] << 16), f[10] | ((uint32_t)f[11] << 16), 0u, 0u);
+                a.pd[k] = D.pos0 + kd;
+                a.pu[k] = U.pos0 + ku;
+                a.pc[k] = c;
+            }
+            n++;
+        }
+    }
+    return n;
+}
+
+template <bool Enum>
 __global__ __launch_bounds__(kSweepBlock) void k_links(KArgs a) {
     __shared__ float sy[kSlots][kSlotCap];
     __shared__ float st[kSlots][kSlotCap];
@@ -114,6 +217,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_links(KArgs a) {
     __shared__ int32_t sfirst[kSlots][kIdxMax];
     __shared__ int32_t s_lo[kSlots], s_n[kSlots], s_glb[kSlots];
     __shared__ int32_t s_strip, s_links, s_glbrows;
+    __shared__ int32_t s_scan[kSweepBlock];
+    __shared__ int32_t s_cpos, s_cend, s_base;
     const int R = a.n_rows;
     const int G = a.max_gap;
     const int tid = threadIdx.x;
@@ -126,6 +231,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_links(KArgs a) {
             s_strip = v;
             s_links = 0;
             s_glbrows = 0;
+            if (iter == 0) {
+                s_cpos = 0;
+                s_cend = 0;
+            }
         }
         __syncthreads();
         const int strip = s_strip;
@@ -191,19 +300,25 @@ __global__ __launch_bounds__(kSweepBlock) void k_links(KArgs a) {
             const int32_t *co_r = co_si + (int64_t)r * (kNcbMax + 1);
             const int jr = r % kSlots;
             const int own_lo = co_r[cb0], own_hi = co_r[cb1];
-            for (int p = own_lo + tid; p < own_hi; p += kSweepBlock) {
-                const int k = p - s_lo[jr];
-                float yi, ti;
-                if (!s_glb[jr]) {
-                    yi = sy[jr][k];
-                    ti = st[jr][k];
-                } else {
-                    const Rec e = a.rec[p];
-                    yi = e.y;
-                    ti = e.t;
+            for (int base = own_lo; base < own_hi; base += kSweepBlock) {
+                const int p = base + tid;
+                const bool act = p < own_hi;
+                float yi = 0.f, ti = 0.f;
+                if (act) {
+                    const int k = p - s_lo[jr];
+                    if (!s_glb[jr]) {
+                        yi = sy[jr][k];
+                        ti = st[jr][k];
+                    } else {
+                        const Rec e = a.rec[p];
+                        yi = e.y;
+                        ti = e.t;
+                    }
                 }
                 int bu = -1, bd = -1;
-                for (int g = 1; g <= G; g++) {
+                int ng[kMaxGap] = {};
+                int nc[kMaxGap] = {};
+                for (int g = 1; g <= G && act; g++) {
                     if (r - g < 0 || r + g > R - 1) continue;
                     const int jd = (r - g) % kSlots, ju = (r + g) % kSlots;
                     const float w = a.w_tab[r * kMaxGap + g - 1];
@@ -215,17 +330,100 @@ __global__ __launch_bounds__(kSweepBlock) void k_links(KArgs a) {
                                S.inv_cbw};
                     GlbSlot GU{a.rec, co_si + (int64_t)(r + g) * (kNcbMax + 1), s_lo[ju], s_n[ju], cb_lo, S.t0,
                                S.inv_cbw};
-                    bool f;
-                    if (!gd && !gu) f = best_pair(LD, LU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
-                    else if (!gd) f = best_pair(LD, GU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
-                    else if (!gu) f = best_pair(GD, LU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
-                    else f = best_pair(GD, GU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
-                    if (f) break;
-                    bu = -1;
-                    bd = -1;
+                    if (!Enum) {
+                        bool f;
+                        if (!gd && !gu) f = best_pair(LD, LU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
+                        else if (!gd) f = best_pair(LD, GU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
+                        else if (!gu) f = best_pair(GD, LU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
+                        else f = best_pair(GD, GU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
+                        if (f) break;
+                        bu = -1;
+                        bd = -1;
+                    } else {
+                        const float xd = a.row_x[r - g], xi = a.row_x[r], xu = a.row_x[r + g];
+                        int ncd, npr;
+                        if (!gd && !gu) {
+                            ncd = box_count(LD, LU, yi, ti, wy, wt);
+                            npr = visit_pairs<false>(LD, LU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, 0);
+                        } else if (!gd) {
+                            ncd = box_count(LD, GU, yi, ti, wy, wt);
+                            npr = visit_pairs<false>(LD, GU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, 0);
+                        } else if (!gu) {
+                            ncd = box_count(GD, LU, yi, ti, wy, wt);
+                            npr = visit_pairs<false>(GD, LU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, 0);
+                        } else {
+                            ncd = box_count(GD, GU, yi, ti, wy, wt);
+                            npr = visit_pairs<false>(GD, GU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, 0);
+                        }
+                        ng[g - 1] = npr;
+                        nc[g - 1] = ncd;
+                    }
                 }
-                a.link[p] = make_int2(bu, bd);
-                nl += (bu >= 0);
+                if (!Enum) {
+                    if (act) {
+                        a.link[p] = make_int2(bu, bd);
+                        nl += (bu >= 0);
+                    }
+                } else {
+                    // reserve this lane's pool slots: block scan, chunked grabs
+                    int tot = 0;
+#pragma unroll
+                    for (int g = 0; g < kMaxGap; g++) tot += ng[g];
+                    s_scan[tid] = tot;
+                    __syncthreads();
+                    for (int off = 1; off < kSweepBlock; off <<= 1) {
+                        const int xv = (tid >= off) ? s_scan[tid - off] : 0;
+                        __syncthreads();
+                        s_scan[tid] += xv;
+                        __syncthreads();
+                    }
+                    const int excl = s_scan[tid] - tot;
+                    if (tid == kSweepBlock - 1) {
+                        const int total = s_scan[tid];
+                        if (s_cpos + total > s_cend) {
+                            const int grab = max(total, kPoolChunk);
+                            s_cpos = atomicAdd(&a.cnt->pool_next, grab);
+                            s_cend = s_cpos + grab;
+                        }
+                        s_base = s_cpos;
+                        s_cpos += total;
+                        if (total) atomicAdd(&a.cnt->pool_used, total);
+                    }
+                    __syncthreads();
+                    const int slot0 = s_base + excl;
+                    if (act) {
+                        const bool fits = slot0 + tot <= a.pool_cap;
+                        if (fits) {
+                            int sl = slot0;
+                            for (int g = 1; g <= G; g++) {
+                                if (ng[g - 1] == 0) continue;
+                                const int jd = (r - g) % kSlots, ju = (r + g) % kSlots;
+                                const float w = a.w_tab[r * kMaxGap + g - 1];
+                                const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
+                                const float xd = a.row_x[r - g], xi = a.row_x[r], xu = a.row_x[r + g];
+                                const bool gd = s_glb[jd] != 0, gu = s_glb[ju] != 0;
+                                LdsSlot LD{sy[jd], st[jd], sid[jd], sfirst[jd], s_lo[jd], s_n[jd], nb, T0, sidx};
+                                LdsSlot LU{sy[ju], st[ju], sid[ju], sfirst[ju], s_lo[ju], s_n[ju], nb, T0, sidx};
+                                GlbSlot GD{a.rec, co_si + (int64_t)(r - g) * (kNcbMax + 1), s_lo[jd], s_n[jd], cb_lo,
+                                           S.t0, S.inv_cbw};
+                                GlbSlot GU{a.rec, co_si + (int64_t)(r + g) * (kNcbMax + 1), s_lo[ju], s_n[ju], cb_lo,
+                                           S.t0, S.inv_cbw};
+                                const int ncd = nc[g - 1];
+                                if (!gd && !gu) visit_pairs<true>(LD, LU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, sl);
+                                else if (!gd) visit_pairs<true>(LD, GU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, sl);
+                                else if (!gu) visit_pairs<true>(GD, LU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, sl);
+                                else visit_pairs<true>(GD, GU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, sl);
+                                sl += ng[g - 1];
+                            }
+                            a.hoff[p] = slot0;
+                        } else {
+                            a.hoff[p] = -1;
+                            atomicAdd(&a.cnt->pool_overflow, tot);
+                        }
+                        a.hn1[p] = ng[0];
+                        a.hn2[p] = kMaxGap > 1 ? ng[1] : 0;
+                    }
+                }
             }
             __syncthreads();
         }
@@ -240,7 +438,65 @@ __global__ __launch_bounds__(kSweepBlock) void k_links(KArgs a) {
 }
 
 void launch_links(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL(k_links, dim3(max(l.grid, 1)), dim3(kSweepBlock), 0, s, a);
+    hipLaunchKernelGGL(k_links<false>, dim3(max(l.grid, 1)), dim3(kSweepBlock), 0, s, a);
+}
+
+void launch_links_enum(const KArgs &a, Launch l, hipStream_t s) {
+    hipLaunchKernelGGL(k_links<true>, dim3(max(l.grid, 1)), dim3(kSweepBlock), 0, s, a);
+}
+
+// Pruned links: per cluster, the best pair among its triplets whose logit
+// is >= theta, gap 1 first, gap 2 only if no gap-1 triplet survives; the
+// same (c, up id, down id) order as the plain finder.
+__global__ __launch_bounds__(256) void k_select(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    const int n = min(a.cnt->n_valid_total, a.n_in);
+    const float th = a.theta;
+    int pruned = 0, nl = 0;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        const int off = a.hoff[p];
+        int bu = -1, bd = -1;
+        if (off >= 0) {
+            const int n1 = a.hn1[p], n2 = a.hn2[p];
+            for (int g = 0; g < 2 && bu < 0; g++) {
+                const int k0 = off + (g ? n1 : 0), k1 = k0 + (g ? n2 : n1);
+                bool found = false;
+                float bc = 0.f;
+                int biu = 0, bid = 0;
+                for (int k = k0; k < k1; k++) {
+                    if (!(a.pz[k] >= th)) {
+                        pruned++;
+                        continue;
+                    }
+                    const float c = a.pc[k];
+                    const int pu = a.pu[k], pd = a.pd[k];
+                    const int idu = a.rec[pu].id, idd = a.rec[pd].id;
+                    if (!found || c < bc || (c == bc && (idu < biu || (idu == biu && idd < bid)))) {
+                        found = true;
+                        bc = c;
+                        biu = idu;
+                        bid = idd;
+                        bu = pu;
+                        bd = pd;
+                    }
+                }
+            }
+        }
+        a.link[p] = make_int2(bu, bd);
+        nl += (bu >= 0);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        pruned += __shfl_xor(pruned, off);
+        nl += __shfl_xor(nl, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (pruned) atomicAdd(&a.cnt->n_pruned, pruned);
+        if (nl) atomicAdd(&a.cnt->n_links, nl);
+    }
+}
+
+void launch_select(const KArgs &a, Launch l, hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(max(l.grid, 1)), dim3(256), 0, s, a);
 }
 
 }  // namespace tpcca

@@ -19,6 +19,52 @@ constexpr int kStageCap = 1024;    // clusters of one neighbour row staged in LD
 constexpr int kScanItems = 2048;   // elements per block of the device-wide scans
 constexpr int kMaxStages = 16;
 constexpr int kLenBins = 256;      // chain lengths are < 256 (rows are uint8)
+constexpr int kMlpIn = 12;         // triplet features
+constexpr int kMlpInP = 16;        // padded to the MFMA K of 16
+constexpr int kMlpH = 64;          // hidden units per layer
+constexpr int kMlpNParam = kMlpH * kMlpInP + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH + 1;
+constexpr int kMlpMaxBatch = 8192; // largest training minibatch
+constexpr int kPoolChunk = 4096;   // triplet-pool slots reserved per grab
+
+// Device view of the triplet network (BF16 weights, FP32 biases).
+struct MlpDev {
+    const uint16_t *w1;  // [64][16]
+    const uint16_t *w2;  // [64][64]
+    const uint16_t *w3;  // [64]
+    const float *b1;     // [64]
+    const float *b2;     // [64]
+    const float *b3;     // [1]
+};
+
+// Layout of the caller-owned network state buffer (byte offsets).
+struct MlpState {
+    static constexpr size_t w1 = 0;                        // BF16 [64][16]
+    static constexpr size_t w2 = 2048;                     // BF16 [64][64]
+    static constexpr size_t w3 = w2 + 8192;                // BF16 [64]
+    static constexpr size_t b1 = w3 + 256;                 // FP32 [64]
+    static constexpr size_t b2 = b1 + 256;                 // FP32 [64]
+    static constexpr size_t b3 = b2 + 256;                 // FP32 [1]
+    static constexpr size_t master = b3 + 256;             // FP32 [kMlpNParam]
+    static constexpr size_t adam_m = master + 21504;       // FP32 [kMlpNParam]
+    static constexpr size_t adam_v = adam_m + 21504;       // FP32 [kMlpNParam]
+    static constexpr size_t step = adam_v + 21504;         // int32 step counter
+    static constexpr size_t bytes = step + 256;
+};
+
+// Arguments of one training (or gradient-only) step.
+struct MlpTrainArgs {
+    uint16_t *w1, *w2, *w3;    // BF16 copies, rewritten after an update
+    float *b1, *b2, *b3;
+    float *master, *adam_m, *adam_v;
+    int32_t *step;
+    const uint16_t *X;         // [n][16] BF16
+    const float *Y;            // [n]
+    int32_t n;
+    float pos_weight, lr, beta1, beta2, eps, weight_decay;
+    int32_t update;            // 1: AdamW step, 0: gradient only
+    float *grad_out;           // [kMlpNParam] (gradient-only mode)
+    float *loss_out;           // [1] or null
+};
 
 // One sector of one frame ("sector instance"), uploaded by the host.
 struct SiDesc {
@@ -61,7 +107,11 @@ struct Counters {
     int32_t n_invalid;
     int32_t overflow;
     int32_t n_glb_rows;      // strip rows that did not fit in LDS (served from L2)
-    int32_t pad[5];
+    int32_t pool_next;       // triplet pool: slots handed out
+    int32_t pool_used;       // triplet pool: slots holding triplets
+    int32_t pool_overflow;   // triplets that did not fit the pool
+    int32_t n_pruned;        // triplets below the logit threshold
+    int32_t pad[1];
 };
 
 // A cluster in the sorted space: 16 bytes, one load per chain step.
@@ -82,6 +132,7 @@ struct KArgs {
     int32_t seed_cap, tseed_cap, trk_cap;
     // constants of the method
     int32_t max_gap, min_track_hits, kf_passes;
+    int32_t strip_target;    // clusters per row that a link-finding strip aims at
     float win_y[kMaxGap], win_t[kMaxGap];   // (float)g * win, computed on the host
     float pair_c2;
     float cbw_min;
@@ -122,6 +173,18 @@ struct KArgs {
     int32_t *assign;         // [n_in]
     int32_t *scan_tmp;       // block sums of the scans
     const volatile int32_t *abort_flag;  // host-mapped
+    // learned pruning (pruned runs only)
+    int32_t use_mlp;
+    float theta;             // prune triplets with logit < theta
+    float c2s;               // sqrt(pair_c2), FP32
+    int32_t pool_cap;
+    uint16_t *pfeat;         // [pool_cap][16] BF16 features
+    int32_t *pd, *pu;        // [pool_cap] down / up sorted positions
+    float *pc;               // [pool_cap] pair score
+    float *pz;               // [pool_cap] logit
+    int32_t *hoff;           // [n_in] first pool slot of each cluster
+    int32_t *hn1, *hn2;      // [n_in] triplets of gap 1 / gap 2
+    MlpDev mlp;
 };
 
 // Order-preserving map of a float to an unsigned key.
@@ -166,6 +229,11 @@ void launch_grid_setup(const KArgs &a, hipStream_t s);
 void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s);
 void launch_grid_rowsort(const KArgs &a, Launch l, hipStream_t s);
 void launch_links(const KArgs &a, Launch l, hipStream_t s);
+void launch_links_enum(const KArgs &a, Launch l, hipStream_t s);
+void launch_select(const KArgs &a, Launch l, hipStream_t s);
+void launch_mlp_infer(const MlpDev &W, const uint16_t *X, const int32_t *n_dev, int32_t n_cap, float *z, int grid,
+                      hipStream_t s);
+void launch_mlp_train(const MlpTrainArgs &t, hipStream_t s);
 void launch_seeds(const KArgs &a, Launch l, hipStream_t s);
 void launch_chainlen(const KArgs &a, Launch l, hipStream_t s);
 void launch_track_slots(const KArgs &a, Launch l, hipStream_t s);

@@ -44,6 +44,7 @@ class Config(ctypes.Structure):
         ("s_max", ctypes.c_float),
         ("use_mlp", ctypes.c_int32),
         ("mlp_logit_threshold", ctypes.c_float),
+        ("pool_per_cluster", ctypes.c_int32),
     ]
 
 
@@ -60,7 +61,9 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("n_clusters", ctypes.c_int64), ("n_links", ctypes.c_int64), ("n_seeds", ctypes.c_int64),
         ("n_tracks", ctypes.c_int64), ("n_track_clusters", ctypes.c_int64), ("n_invalid", ctypes.c_int64),
-        ("n_overflow_rows", ctypes.c_int64), ("n_timed_runs", ctypes.c_int64),
+        ("n_overflow_rows", ctypes.c_int64), ("n_triplets", ctypes.c_int64), ("n_pruned", ctypes.c_int64),
+        ("n_pool_overflow", ctypes.c_int64), ("mlp_used", ctypes.c_int32),
+        ("n_timed_runs", ctypes.c_int64),
         ("n_stages", ctypes.c_int32),
         ("stage_ms", ctypes.c_float * 16),
         ("stage_ms_total", ctypes.c_double * 16),
@@ -74,8 +77,17 @@ EXPORTS = [
     "tpcca_add_frame", "tpcca_clear_frames", "tpcca_load_sector", "tpcca_required_arena",
     "tpcca_attach_arena", "tpcca_run", "tpcca_synchronize", "tpcca_request_abort", "tpcca_set_timing",
     "tpcca_get_stats", "tpcca_get_tracks", "tpcca_get_track_clusters", "tpcca_get_assignment",
-    "tpcca_get_links",
+    "tpcca_get_links", "tpcca_mlp_state_bytes", "tpcca_mlp_attach", "tpcca_mlp_load", "tpcca_mlp_fetch",
+    "tpcca_mlp_infer", "tpcca_mlp_grad", "tpcca_mlp_train_step", "tpcca_get_triplets", "tpcca_set_graph",
+    "tpcca_set_launch",
 ]
+
+MLP_NPARAM = 5313
+
+
+class MlpHparams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("weight_decay", ctypes.c_float), ("pos_weight", ctypes.c_float)]
 
 _lib = None
 
@@ -108,6 +120,16 @@ def load_library(path: str = LIB_PATH):
         "tpcca_get_track_clusters": [P, I32, I32, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_assignment": [P, I32, I32, P, I64],
         "tpcca_get_links": [P, I32, I32, I32, P, P, I64],
+        "tpcca_mlp_state_bytes": [ctypes.POINTER(SZ)],
+        "tpcca_mlp_attach": [P, P, SZ],
+        "tpcca_mlp_load": [P, P],
+        "tpcca_mlp_fetch": [P, P],
+        "tpcca_mlp_infer": [P, P, I64, P],
+        "tpcca_mlp_grad": [P, P, P, I64, ctypes.c_float, P, P],
+        "tpcca_mlp_train_step": [P, P, P, I64, ctypes.POINTER(MlpHparams), P],
+        "tpcca_get_triplets": [P, I32, I32, P, P, P, I64, ctypes.POINTER(I64)],
+        "tpcca_set_graph": [P, I32],
+        "tpcca_set_launch": [P, I32, I32, I32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -278,6 +300,15 @@ class Tracker:
     def request_abort(self):
         self._check(self.lib.tpcca_request_abort(self.h))
 
+    def set_graph(self, on: bool):
+        """Replay runs from a captured HIP graph (needs a non-default stream)."""
+        if on and self.stream.cuda_stream == 0:
+            self.set_stream(self._torch.cuda.Stream())
+        self._check(self.lib.tpcca_set_graph(self.h, 1 if on else 0))
+
+    def set_launch(self, stage: int, blocks_per_cu: int = 0, param: int = 0):
+        self._check(self.lib.tpcca_set_launch(self.h, stage, blocks_per_cu, param))
+
     def set_timing(self, on: bool):
         self._check(self.lib.tpcca_set_timing(self.h, 1 if on else 0))
 
@@ -285,7 +316,8 @@ class Tracker:
         s = Stats()
         self._check(self.lib.tpcca_get_stats(self.h, ctypes.byref(s)))
         d = {k: getattr(s, k) for k in ("n_clusters", "n_links", "n_seeds", "n_tracks", "n_track_clusters",
-                                        "n_invalid", "n_overflow_rows")}
+                                        "n_invalid", "n_overflow_rows", "n_triplets", "n_pruned",
+                                        "n_pool_overflow", "mlp_used")}
         d["stage_ms"] = {s.stage_name[i].value.decode(): s.stage_ms[i] for i in range(s.n_stages)}
         d["n_timed_runs"] = s.n_timed_runs
         d["stage_ms_total"] = {s.stage_name[i].value.decode(): s.stage_ms_total[i] for i in range(s.n_stages)}
@@ -326,3 +358,64 @@ class Tracker:
         self._check(self.lib.tpcca_get_links(self.h, frame, sector, 1 if cleaned else 0,
                                              up.ctypes.data if n else None, dn.ctypes.data if n else None, n))
         return up, dn
+
+    # ------------------------------------------------------ triplet network
+    def mlp_attach(self):
+        torch = self._torch
+        b = ctypes.c_size_t()
+        self._check(self.lib.tpcca_mlp_state_bytes(ctypes.byref(b)))
+        self.mlp_state = torch.zeros(b.value + 256, dtype=torch.uint8, device="cuda")
+        base = (self.mlp_state.data_ptr() + 255) // 256 * 256
+        self._check(self.lib.tpcca_mlp_attach(self.h, ctypes.c_void_p(base), b.value))
+
+    def mlp_load(self, params):
+        """params: 5313 FP32 values (w1[64][16], b1, w2[64][64], b2, w3, b3)."""
+        if getattr(self, "mlp_state", None) is None:
+            self.mlp_attach()
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.size == MLP_NPARAM
+        self._check(self.lib.tpcca_mlp_load(self.h, p.ctypes.data))
+
+    def mlp_fetch(self):
+        p = np.zeros(MLP_NPARAM, np.float32)
+        self._check(self.lib.tpcca_mlp_fetch(self.h, p.ctypes.data))
+        return p
+
+    def mlp_infer(self, x_dev, z_dev=None):
+        """x_dev: torch int16/uint16-bit tensor [n, 16] of BF16 features on the GPU."""
+        n = x_dev.shape[0]
+        if z_dev is None:
+            z_dev = self._torch.empty(n, dtype=self._torch.float32, device="cuda")
+        self._check(self.lib.tpcca_mlp_infer(self.h, ctypes.c_void_p(x_dev.data_ptr()), n,
+                                             ctypes.c_void_p(z_dev.data_ptr())))
+        return z_dev
+
+    def mlp_grad(self, x_dev, y_dev, pos_weight=1.0):
+        torch = self._torch
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        self._check(self.lib.tpcca_mlp_grad(self.h, ctypes.c_void_p(x_dev.data_ptr()),
+                                            ctypes.c_void_p(y_dev.data_ptr()), x_dev.shape[0], float(pos_weight),
+                                            ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(loss.data_ptr())))
+        return g, loss
+
+    def mlp_train_step(self, x_dev, y_dev, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4,
+                       pos_weight=1.0, loss_dev=None):
+        hp = MlpHparams(lr, beta1, beta2, eps, weight_decay, pos_weight)
+        self._check(self.lib.tpcca_mlp_train_step(self.h, ctypes.c_void_p(x_dev.data_ptr()),
+                                                  ctypes.c_void_p(y_dev.data_ptr()), x_dev.shape[0], ctypes.byref(hp),
+                                                  ctypes.c_void_p(loss_dev.data_ptr()) if loss_dev is not None else None))
+
+    def triplets(self, frame, sector):
+        """(tri int32[n,4] = (down, cluster, up, gap) input ids, feat uint16[n,16], z float32[n])."""
+        n = ctypes.c_int64()
+        st = self.lib.tpcca_get_triplets(self.h, frame, sector, None, None, None, 0, ctypes.byref(n))
+        if st not in (OK, ERR_CAPACITY):
+            self._check(st)
+        tri = np.zeros((n.value, 4), np.int32)
+        feat = np.zeros((n.value, 16), np.uint16)
+        z = np.zeros(n.value, np.float32)
+        if n.value:
+            self._check(self.lib.tpcca_get_triplets(self.h, frame, sector, tri.ctypes.data, feat.ctypes.data,
+                                                    z.ctypes.data, n.value, ctypes.byref(n)))
+        return tri, feat, z

@@ -1,0 +1,158 @@
+"""GPU tests of the learned triplet pruning: the MFMA inference and training
+kernels against the CPU oracle (FP64 with the same BF16 roundings), and the
+pruned neighbour finder against the oracle's pruned links."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_08862_amd import synth
+
+from _parity import compare_sector, oracle_cfg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tp():
+    import torch
+    from paper_2102_08862_amd import tpcca
+    assert torch.cuda.is_available()
+    tpcca.load_library()
+    return tpcca
+
+
+@pytest.fixture(scope="module")
+def x():
+    return synth.geometry()[0]
+
+
+def _feat(n, seed):
+    rng = np.random.default_rng(seed)
+    f = np.zeros((n, 16), np.float32)
+    f[:, :12] = rng.normal(0, 1.5, (n, 12))
+    return oracle.bf16(f)
+
+
+def _to_dev_bf16(f):
+    import torch
+    bits = (f.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    return torch.from_numpy(bits.view(np.int16).copy()).cuda()
+
+
+def test_infer_matches_oracle(tp):
+    import torch
+    m = oracle.MLP.random(11)
+    f = _feat(20000, 1)
+    trk = tp.Tracker()
+    trk.mlp_load(m.flat())
+    z = trk.mlp_infer(_to_dev_bf16(f)).cpu().numpy()
+    zo = oracle.mlp_forward(m, f)
+    bad = np.abs(z - zo) > 1e-3 * (1 + np.abs(zo))
+    print("infer: max |dz| %.3g, beyond tolerance %d of %d" % (np.abs(z - zo).max(), bad.sum(), len(z)))
+    assert bad.mean() <= 1e-3
+    assert np.abs(z - zo).max() < 0.1
+
+
+def test_grad_matches_oracle(tp):
+    import torch
+    m = oracle.MLP.random(12)
+    n = 4096
+    f = _feat(n, 2)
+    y = (np.random.default_rng(3).random(n) < 0.2).astype(np.float32)
+    trk = tp.Tracker()
+    trk.mlp_load(m.flat())
+    g, loss = trk.mlp_grad(_to_dev_bf16(f), torch.from_numpy(y).cuda(), pos_weight=3.0)
+    g = g.cpu().numpy()
+    lo, go = oracle.mlp_grad(m, f, y, w_pos=3.0)
+    assert abs(loss.item() - lo) < 1e-3 * max(1.0, abs(lo))
+    gflat = np.concatenate([go["w1"].ravel(), go["b1"], go["w2"].ravel(), go["b2"], go["w3"], [go["b3"]]])
+    segs = {"w1": (0, 1024), "b1": (1024, 1088), "w2": (1088, 5184), "b2": (5184, 5248), "w3": (5248, 5312),
+            "b3": (5312, 5313)}
+    for k, (a, b) in segs.items():
+        u, v = g[a:b].astype(np.float64), gflat[a:b]
+        rel = np.linalg.norm(u - v) / max(np.linalg.norm(v), 1e-30)
+        cos = float(u @ v / (np.linalg.norm(u) * np.linalg.norm(v) + 1e-300))
+        print("grad %s: rel L2 %.2e cos %.6f" % (k, rel, cos))
+        assert rel <= 1e-2 and (cos >= 0.9999 or b - a == 1), k
+
+
+def test_train_step_is_adamw(tp):
+    import torch
+    m = oracle.MLP.random(13)
+    n = 2048
+    f = _feat(n, 4)
+    y = (np.random.default_rng(5).random(n) < 0.3).astype(np.float32)
+    trk = tp.Tracker()
+    trk.mlp_load(m.flat())
+    xd, yd = _to_dev_bf16(f), torch.from_numpy(y).cuda()
+    g, _ = trk.mlp_grad(xd, yd, pos_weight=2.0)
+    g = g.cpu().numpy().astype(np.float64)
+    lr, b1, b2, eps, wd = 1e-3, 0.9, 0.999, 1e-8, 1e-4
+    trk.mlp_train_step(xd, yd, lr=lr, beta1=b1, beta2=b2, eps=eps, weight_decay=wd, pos_weight=2.0)
+    p1 = trk.mlp_fetch().astype(np.float64)
+    p0 = m.flat().astype(np.float64)
+    mm = (1 - b1) * g
+    vv = (1 - b2) * g * g
+    isw = np.zeros(len(p0), bool)
+    isw[:1024] = True; isw[1088:5184] = True; isw[5248:5312] = True
+    exp = p0 - lr * wd * p0 * isw - lr * (mm / (1 - b1)) / (np.sqrt(vv / (1 - b2)) + eps)
+    exp[:1024].reshape(64, 16)[:, 12:] = 0
+    assert np.allclose(p1, exp, rtol=1e-5, atol=1e-6)
+
+
+def test_training_reduces_loss(tp):
+    """A separable toy task: label = (feature 0 + feature 6 > 0)."""
+    import torch
+    n = 8192
+    f = _feat(n, 6)
+    y = ((f[:, 0] + f[:, 6]) > 0).astype(np.float32)
+    trk = tp.Tracker()
+    trk.mlp_load(oracle.MLP.random(14).flat())
+    xd, yd = _to_dev_bf16(f), torch.from_numpy(y).cuda()
+    loss = torch.zeros(1, device="cuda")
+    losses = []
+    for step in range(300):
+        trk.mlp_train_step(xd, yd, lr=3e-3, loss_dev=loss)
+        if step % 50 == 0:
+            losses.append(loss.item())
+    print("losses", losses)
+    assert losses[-1] < 0.5 * losses[0]
+    z = trk.mlp_infer(xd).cpu().numpy()
+    acc = ((z > 0) == (y > 0.5)).mean()
+    assert acc > 0.95
+
+
+def test_pruned_run_triplets_and_links(tp, x):
+    fr = synth.generate("sector_300", seed=21)
+    row, y, t = fr.sector(0)
+    oc = oracle_cfg(x)
+    m = oracle.MLP.random(15)
+    # theta = -inf: no pruning, links identical to the plain finder
+    trk = tp.Tracker(use_mlp=1, mlp_logit_threshold=-1e30)
+    trk.mlp_load(m.flat())
+    f = trk.add_frame()
+    trk.load_sector(f, 0, row, y, t)
+    trk.run(sync=True)
+    st = trk.stats()
+    assert st["mlp_used"] == 1 and st["n_pool_overflow"] == 0
+    compare_sector(trk, f, 0, row, y, t, oc)
+    tri, feat, z = trk.triplets(f, 0)
+    otri, ofeat = oracle.triplets(oc, row, y, t)
+    assert np.array_equal(tri, otri), "triplet identities differ"
+    gf = (feat.astype(np.uint32) << 16).view(np.float32)
+    assert np.array_equal(gf, ofeat), "triplet features differ"
+    zo = oracle.mlp_forward(m, ofeat)
+    assert (np.abs(z - zo) > 1e-3 * (1 + np.abs(zo))).mean() <= 1e-3
+    # a real threshold: links equal the oracle's except where a triplet sits at the threshold
+    th = float(np.median(zo))
+    trk2 = tp.Tracker(use_mlp=1, mlp_logit_threshold=th)
+    trk2.mlp_load(m.flat())
+    g = trk2.add_frame()
+    trk2.load_sector(g, 0, row, y, t)
+    trk2.run(sync=True)
+    up, dn = trk2.links(g, 0)
+    oup, odn, ogap, near = oracle.links_pruned(oc, row, y, t, m, th, tol=1e-3 * (1 + abs(th)))
+    ok = near == 0
+    print("pruned: %d of %d clusters compared, %d pruned triplets" % (ok.sum(), len(ok), trk2.stats()["n_pruned"]))
+    assert ok.mean() > 0.99
+    assert np.array_equal(up[ok], oup[ok]) and np.array_equal(dn[ok], odn[ok])
