@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--seed", type=int, default=3000)
     ap.add_argument("--cpu-sectors", type=int, default=4, help="oracle sample size (0: skip)")
     ap.add_argument("--threads", type=int, default=0, help="generator threads (0: auto)")
+    ap.add_argument("--tune", action="store_true", help="autotune launch shapes on this frame first (and cache)")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore the cached launch shapes")
+    ap.add_argument("--graph", action="store_true", help="replay each step from a captured HIP graph")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -109,6 +112,7 @@ def main():
     log("generated %s seed %d: %d clusters, %d particles in %.1f s"
         % (args.workload, args.seed, fr.n_clusters, len(fr.tracks), time.perf_counter() - t0))
 
+    from paper_2102_08862_amd import autotune
     trk = tpcca.Tracker()
     th = time.perf_counter()
     f = trk.load_frame_packed(fr)
@@ -116,13 +120,26 @@ def main():
     need = trk.ensure_arena()
     log("inputs resident in HBM (%.2f GB H2D in %.2f s); arena %.2f GB"
         % (fr.n_clusters * 9 / 1e9, h2d_s, need / 1e9))
+    tuning = {}
+    if args.tune:
+        log("autotuning launch shapes ...")
+        tuning, _ = autotune.tune(trk, [f], log=log)
+        autotune.save(tuning, fr.n_clusters)
+        log("tuned: %s" % tuning)
+    elif not args.no_tuning:
+        tuning = autotune.apply(trk, fr.n_clusters)
+        if tuning:
+            log("cached launch shapes: %s" % tuning)
+    trk.ensure_arena()
+    if args.graph:
+        trk.set_graph(True)
 
     for _ in range(args.warmup):
         trk.run()
     trk.synchronize()
     log("warmup done (%d steps)" % args.warmup)
     trk.set_timing(True)
-    stream = torch.cuda.current_stream()
+    stream = trk.stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -140,6 +157,15 @@ def main():
     n = fr.n_clusters
     runs = max(1, st["n_timed_runs"])
     stage = {k: v / runs for k, v in st["stage_ms_total"].items()}
+    if args.graph:
+        # graph replays record no per-stage events: time the stages in eager runs
+        trk.set_graph(False)
+        trk.set_timing(True)
+        for _ in range(min(args.steps, 5)):
+            trk.run()
+        trk.synchronize()
+        st2 = trk.stats()
+        stage = {k: v / max(1, st2["n_timed_runs"]) for k, v in st2["stage_ms_total"].items()}
     table = {}
     for k, v in stage.items():
         row = {"ms": round(v, 4)}
@@ -183,6 +209,7 @@ def main():
         "cpu_baseline": cpu,
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
         "h2d_s": round(h2d_s, 3),
+        "launch": {"graph": bool(args.graph), "tuning": tuning},
     }
     print(json.dumps(out), flush=True)
 
