@@ -254,6 +254,12 @@ tpcca_status tpcca_mlp_load(tpcca_ctx *ctx, const float *params);
 /* Copy the FP32 master parameters to host memory (synchronous). */
 tpcca_status tpcca_mlp_fetch(tpcca_ctx *ctx, float *params);
 
+/* Switch pruning on (use_mlp = 1) or off (0) and set the logit threshold for
+   the following runs, without reloading frames (the pool is sized at the
+   next run, so the arena may need to grow: check tpcca_required_arena).
+   INVALID_ARG for use_mlp outside {0, 1} or a NaN threshold. */
+tpcca_status tpcca_set_pruning(tpcca_ctx *ctx, int32_t use_mlp, float logit_threshold);
+
 /* Logits of n triplets: x_dev = device [n][16] BF16 features (columns
    12..15 zero), z_dev = device float[n]. Enqueued on the stream. */
 tpcca_status tpcca_mlp_infer(tpcca_ctx *ctx, const uint16_t *x_dev, int64_t n, float *z_dev);

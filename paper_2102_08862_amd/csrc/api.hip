@@ -287,6 +287,19 @@ tpcca_status tpcca_set_launch(tpcca_ctx *c, int32_t stage, int32_t blocks_per_cu
     return TPCCA_OK;
 }
 
+tpcca_status tpcca_set_pruning(tpcca_ctx *c, int32_t use_mlp, float theta) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    if ((use_mlp != 0 && use_mlp != 1) || std::isnan(theta))
+        return fail(c, TPCCA_ERR_INVALID_ARG, "use_mlp must be 0 or 1 and the threshold a number");
+    (void)hipStreamSynchronize(c->stream);
+    c->cfg.use_mlp = use_mlp;
+    c->cfg.mlp_logit_threshold = theta;
+    c->plan_dirty = true;  // pool size and threshold are part of the plan
+    c->graph_valid = false;
+    c->have_results = false;
+    return TPCCA_OK;
+}
+
 tpcca_status tpcca_add_frame(tpcca_ctx *c, int32_t *frame_id) {
     if (!c || !frame_id) return TPCCA_ERR_INVALID_ARG;
     c->frames.emplace_back((size_t)c->cfg.n_sectors);

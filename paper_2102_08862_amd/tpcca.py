@@ -79,7 +79,7 @@ EXPORTS = [
     "tpcca_get_stats", "tpcca_get_tracks", "tpcca_get_track_clusters", "tpcca_get_assignment",
     "tpcca_get_links", "tpcca_mlp_state_bytes", "tpcca_mlp_attach", "tpcca_mlp_load", "tpcca_mlp_fetch",
     "tpcca_mlp_infer", "tpcca_mlp_grad", "tpcca_mlp_train_step", "tpcca_get_triplets", "tpcca_set_graph",
-    "tpcca_set_launch",
+    "tpcca_set_launch", "tpcca_set_pruning",
 ]
 
 MLP_NPARAM = 5313
@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH):
         "tpcca_get_triplets": [P, I32, I32, P, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_set_graph": [P, I32],
         "tpcca_set_launch": [P, I32, I32, I32],
+        "tpcca_set_pruning": [P, I32, ctypes.c_float],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -308,6 +309,12 @@ class Tracker:
 
     def set_launch(self, stage: int, blocks_per_cu: int = 0, param: int = 0):
         self._check(self.lib.tpcca_set_launch(self.h, stage, blocks_per_cu, param))
+
+    def set_pruning(self, use_mlp: bool, threshold: float = 0.0):
+        """Switch triplet pruning on or off and set the logit threshold."""
+        self._check(self.lib.tpcca_set_pruning(self.h, 1 if use_mlp else 0, float(threshold)))
+        self.config.use_mlp = 1 if use_mlp else 0
+        self.config.mlp_logit_threshold = float(threshold)
 
     def set_timing(self, on: bool):
         self._check(self.lib.tpcca_set_timing(self.h, 1 if on else 0))
