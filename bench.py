@@ -81,6 +81,61 @@ def cpu_baseline(fr, n_sectors: int):
                       "one thread per sector, %.1f s" % (secs[-1], n, dt)}
 
 
+def frame_quality(trk, fr, f):
+    from paper_2102_08862_amd import metrics
+    return metrics.frame_quality(fr, lambda s: trk.track_clusters(f, s), lambda s: trk.tracks(f, s)["n_clusters"])
+
+
+def pruned_leg(trk, fr, f, args, log):
+    """The MLP-pruned tracker on the same frame, at the trained network's
+    threshold, timed like the plain one; with the efficiency of both against
+    the generator's truth."""
+    import torch
+    from paper_2102_08862_amd import prune_train
+    params, meta = prune_train.load_weights()
+    if params is None or "theta" not in meta:
+        log("pruned leg skipped: no trained weights")
+        return {"skipped": "no trained weights"}
+    q_plain = None if args.no_quality else frame_quality(trk, fr, f)
+    theta = float(meta["theta"])
+    trk.set_graph(False)
+    trk.mlp_load(params)
+    trk.set_pruning(True, theta)
+    trk.ensure_arena()
+    for _ in range(max(1, args.warmup)):
+        trk.run()
+    trk.synchronize()
+    trk.set_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(trk.stream)
+    for _ in range(args.steps):
+        trk.run()
+    e1.record(trk.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = trk.stats()
+    runs = max(1, st["n_timed_runs"])
+    out = {"value": round(fr.n_clusters / (ms / 1e3), 1), "unit": "clusters/s", "ms_per_step": round(ms, 4),
+           "theta": theta, "triplets": int(st["n_triplets"]), "pruned": int(st["n_pruned"]),
+           "pruned_fraction": round(st["n_pruned"] / max(1, st["n_triplets"]), 4),
+           "pool_overflow": int(st["n_pool_overflow"]),
+           "stage_ms": {k: round(v / runs, 4) for k, v in st["stage_ms_total"].items()}}
+    log("pruned: %.3f ms/step, %d triplets, %.1f%% pruned" % (ms, out["triplets"], 100 * out["pruned_fraction"]))
+    if q_plain is not None:
+        q = frame_quality(trk, fr, f)
+        out["efficiency_plain"] = round(q_plain["efficiency"], 6)
+        out["efficiency_pruned"] = round(q["efficiency"], 6)
+        out["efficiency_loss"] = round(q_plain["efficiency"] - q["efficiency"], 6)
+        out["fake_rate_plain"] = round(q_plain["fake_rate"], 6)
+        out["fake_rate_pruned"] = round(q["fake_rate"], 6)
+        log("efficiency plain %.5f pruned %.5f (loss %.5f); fake %.5f -> %.5f"
+            % (q_plain["efficiency"], q["efficiency"], out["efficiency_loss"], q_plain["fake_rate"], q["fake_rate"]))
+    trk.set_pruning(False)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +148,8 @@ def main():
     ap.add_argument("--tune", action="store_true", help="autotune launch shapes on this frame first (and cache)")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the cached launch shapes")
     ap.add_argument("--graph", action="store_true", help="replay each step from a captured HIP graph")
+    ap.add_argument("--no-pruned", action="store_true", help="skip the MLP-pruned tracker leg")
+    ap.add_argument("--no-quality", action="store_true", help="skip the truth-based efficiency of both trackers")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -183,6 +240,10 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_launch": int(b), "avg_ms": round(stage[dom], 4)}
 
+    pruned = None
+    if not args.no_pruned:
+        pruned = pruned_leg(trk, fr, f, args, log)
+
     cpu = None
     if args.cpu_sectors > 0:
         log("cpu baseline: oracle on %d sectors ..." % args.cpu_sectors)
@@ -206,7 +267,10 @@ def main():
                    "clusters": n, "tracks": int(st["n_tracks"]), "track_clusters": int(st["n_track_clusters"]),
                    "parallelism": "single GPU"},
         "roofline": roof,
+        "pruned": pruned,
         "cpu_baseline": cpu,
+        "counts": {k: int(st[k]) for k in ("n_links", "n_seeds", "n_tracks", "n_track_clusters", "n_invalid",
+                                            "n_overflow_tiles", "n_tiles")},
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
         "h2d_s": round(h2d_s, 3),
         "launch": {"graph": bool(args.graph), "tuning": tuning},

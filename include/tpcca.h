@@ -114,7 +114,7 @@ typedef struct {
     int64_t n_tracks;          /* chains with >= min_track_hits clusters */
     int64_t n_track_clusters;  /* clusters assigned to tracks */
     int64_t n_invalid;         /* input clusters rejected on the device (row or value) */
-    int64_t n_overflow_rows;   /* neighbour-finding strip rows too dense for LDS (read from L2) */
+    int64_t n_overflow_tiles;  /* neighbour-finding tiles too dense for LDS (searched in global memory) */
     int64_t n_triplets;        /* pruned runs: accepted candidate triplets scored by the network */
     int64_t n_pruned;          /* pruned runs: triplets below the threshold (among those examined) */
     int64_t n_pool_overflow;   /* pruned runs: triplets that did not fit the pool (run is invalid) */
@@ -124,6 +124,7 @@ typedef struct {
     float stage_ms[16];        /* device time per stage, last timed run */
     double stage_ms_total[16]; /* device time per stage summed over the timed runs */
     char stage_name[16][24];
+    int64_t n_tiles;           /* neighbour-finding work items (sector, row block, time slab) */
 } tpcca_stats;
 
 /* Fill *out with the defaults above. */
@@ -191,8 +192,9 @@ tpcca_status tpcca_set_graph(tpcca_ctx *ctx, int32_t on);
 /* Launch shape of one stage (the tpcca_stats.stage_name order: 1 hist,
    3 scatter, 4 rowsort, 5 links, 6 seeds, 7 chainlen, 8 slots, 10 emit,
    11 fit): blocks_per_cu persistent workgroups per compute unit (0: keep).
-   For stage 5, param sets the target clusters per strip row (64..1024,
-   0: keep). Results do not depend on these settings. */
+   For stage 5, param sets how many clusters a neighbour-finding tile may
+   stage in LDS (256..3072, 0: keep; smaller tiles give more work items).
+   Results do not depend on these settings. */
 tpcca_status tpcca_set_launch(tpcca_ctx *ctx, int32_t stage, int32_t blocks_per_cu, int32_t param);
 
 /* Enable (1) or disable (0) per-stage device timing with HIP events; either
@@ -286,7 +288,7 @@ tpcca_status tpcca_mlp_train_step(tpcca_ctx *ctx, const uint16_t *x_dev, const f
                                   const tpcca_mlp_hparams *hp, float *loss_dev);
 
 /* Triplets of the last pruned run for one (frame, sector), ordered by the
-   input index of the middle cluster, then gap, then candidate order:
+   input index of the middle cluster, then gap, then down and up input index:
    tri[k] = (down, cluster, up, gap) input indices, feat[k] = 16 BF16
    features, z[k] = logit (any output pointer may be NULL). CAPACITY if cap
    is too small; *n_out receives the count. Synchronous. */

@@ -1,8 +1,8 @@
 """Launch-shape autotuner for the track finder.
 
 Sweeps, stage by stage, the persistent grid size (workgroups per compute
-unit) and, for neighbour finding, the strip width (target clusters per strip
-row), timing each stage with the library's HIP events on a real frame. A
+unit) and, for neighbour finding, the tile budget (clusters a tile may stage
+in LDS), timing each stage with the library's HIP events on a real frame. A
 candidate is kept only if the run's outputs are bit-identical to the
 reference run (the settings must not change any result). The winners are
 cached in a JSON file keyed by GPU architecture and workload size bucket.
@@ -15,11 +15,11 @@ import os
 
 import numpy as np
 
-STAGES = {            # stage index -> (name, blocks-per-CU candidates, strip-target candidates)
+STAGES = {            # stage index -> (name, blocks-per-CU candidates, tile-budget candidates)
     1: ("hist", (2, 4, 8, 16), (0,)),
     3: ("scatter", (2, 4, 8, 16), (0,)),
     4: ("rowsort", (1, 2, 3, 4), (0,)),
-    5: ("links", (1, 2, 3), (128, 192, 230, 320, 448)),
+    5: ("links", (2, 3, 4), (768, 1536, 2304, 3072)),
     6: ("seeds", (2, 4, 8, 16), (0,)),
     7: ("chainlen", (2, 4, 8, 16), (0,)),
     10: ("emit", (2, 4, 8, 16), (0,)),
@@ -96,7 +96,7 @@ def tune(trk, frame_ids, sectors=(0, 17, 35), reps=3, log=print):
 
 def _default(stage):
     # the library's built-in shapes
-    return {1: (8, 0), 3: (8, 0), 4: (2, 0), 5: (3, 230), 6: (8, 0), 7: (8, 0), 10: (8, 0), 11: (8, 0)}[stage]
+    return {1: (8, 0), 3: (8, 0), 4: (2, 0), 5: (4, 3072), 6: (8, 0), 7: (8, 0), 10: (8, 0), 11: (8, 0)}[stage]
 
 
 def save(settings, n_clusters, path=DEFAULT_CACHE):

@@ -32,8 +32,10 @@ struct SectorIn {
 // Arena layout of one run.
 struct Layout {
     size_t total = 0;
-    size_t inputs, si, st, cnt, chunk, row_x, w_tab;
+    size_t inputs, si, st, cnt, chunk, row_x, w_tab, ycell;
     size_t rcnt, rstart, rcur, coff;
+    size_t tstart, ntile, tile_base, tiles;
+    int64_t tile_cap = 0;
     size_t tmp, rec, link;
     size_t seeds, tseed, tlen, tslot;
     size_t bits, wpre;
@@ -94,6 +96,7 @@ struct tpcca_ctx {
     std::vector<SiDesc> si_host;
     std::vector<int32_t> chunks;
     std::vector<float> wtab;
+    std::vector<YCell> ycell;
     int64_t n_in = 0;
     int32_t n_words = 0;
     Launch lc[kNumStages];
@@ -101,7 +104,7 @@ struct tpcca_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool graph_valid = false;
-    int32_t strip_target = 230;  // clusters per strip row (link finding)
+    int32_t tile_budget = kTileCap;  // clusters a neighbour tile may stage
     char *mlp = nullptr;       // caller-owned network state buffer
     bool mlp_loaded = false;
     bool pruned_run = false;   // the plan includes the triplet pool
@@ -210,7 +213,7 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
     const int cu = std::max(1, c->n_cu);
     for (int i = 0; i < kNumStages; i++) c->lc[i] = Launch{cu * 8, 256};
     c->lc[4] = Launch{cu * 2, 512};  // rowsort: 34 KB LDS, 512 threads
-    c->lc[5] = Launch{cu * 3, 256};  // links: 48 KB LDS -> 3 resident blocks per CU
+    c->lc[5] = Launch{cu * 4, 256};  // links: 34 KB LDS -> 4 resident blocks per CU
     // decision-path constants, computed once on the host in FP32
     c->wtab.assign((size_t)cfg->n_rows * kMaxGap, 0.f);
     for (int r = 0; r < cfg->n_rows; r++)
@@ -221,6 +224,19 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
             volatile float w = num / den;
             c->wtab[(size_t)r * kMaxGap + g - 1] = w;
         }
+    // y cells of the row order: about 2*win_y wide across the sector's width
+    // at the row (clusters outside are clamped to the edge cells)
+    c->ycell.assign((size_t)cfg->n_rows, YCell{0.f, 0.f, 1, 0});
+    for (int r = 0; r < cfg->n_rows; r++) {
+        const double half_angle = cfg->n_sectors >= 6 ? 2.0 * M_PI / cfg->n_sectors : 0.0;
+        const double hw = std::fabs((double)c->row_x[r]) * std::tan(half_angle) + 2.0 * cfg->win_y;
+        int ny = (int)std::floor(2.0 * hw / (2.0 * cfg->win_y));
+        ny = std::min(std::max(ny, 1), kMaxYCells);
+        YCell &yc = c->ycell[r];
+        yc.ylo = (float)(-hw);
+        yc.inv = (float)(ny / (2.0 * hw));
+        yc.ny = ny;
+    }
     *out = c;
     return TPCCA_OK;
 }
@@ -276,13 +292,14 @@ tpcca_status tpcca_set_launch(tpcca_ctx *c, int32_t stage, int32_t blocks_per_cu
     bool ok = false;
     for (int v : tunable) ok = ok || v == stage;
     if (!ok || blocks_per_cu < 0 || blocks_per_cu > 64) return fail(c, TPCCA_ERR_INVALID_ARG, "bad stage or blocks");
-    if (param != 0 && (stage != 5 || param < 64 || param > 1024)) return fail(c, TPCCA_ERR_INVALID_ARG, "bad param");
+    if (param != 0 && (stage != 5 || param < 256 || param > kTileCap))
+        return fail(c, TPCCA_ERR_INVALID_ARG, "bad param");
     if (stage == 4 && blocks_per_cu > 4) return fail(c, TPCCA_ERR_INVALID_ARG, "rowsort: at most 4 blocks per CU");
-    if (stage == 5 && blocks_per_cu > 3) return fail(c, TPCCA_ERR_INVALID_ARG, "links: at most 3 blocks per CU");
+    if (stage == 5 && blocks_per_cu > 4) return fail(c, TPCCA_ERR_INVALID_ARG, "links: at most 4 blocks per CU");
     (void)hipStreamSynchronize(c->stream);
     if (blocks_per_cu) c->lc[stage].grid = std::max(1, c->n_cu) * blocks_per_cu;
-    if (param) c->strip_target = param;
-    c->plan_dirty = true;  // the strip target is a kernel argument
+    if (param) c->tile_budget = param;
+    c->plan_dirty = true;  // the tile budget is a kernel argument
     c->graph_valid = false;
     return TPCCA_OK;
 }
@@ -411,10 +428,20 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.chunk = b.take(sizeof(int32_t) * c->chunks.size());
     L.row_x = b.take(sizeof(float) * R);
     L.w_tab = b.take(sizeof(float) * R * kMaxGap);
+    L.ycell = b.take(sizeof(YCell) * R);
     L.rcnt = b.take(sizeof(int32_t) * SR);
     L.rstart = b.take(sizeof(int32_t) * SR);
     L.rcur = b.take(sizeof(int32_t) * SR);
     L.coff = b.take(sizeof(int32_t) * SR * (kNcbMax + 1));
+    const int nrb = (R + kTileRows - 1) / kTileRows;
+    const int64_t NW = (int64_t)S * nrb;
+    L.tstart = b.take(sizeof(int16_t) * NW * kNcbMax);
+    L.ntile = b.take(sizeof(int32_t) * (NW + 1));
+    L.tile_base = b.take(sizeof(int32_t) * (NW + 1));
+    // a (sector instance, row block) has at most one tile per coarse bin
+    L.tile_cap = NW * kNcbMax;
+    if (L.tile_cap > (int64_t)0x7fff0000) return fail(c, TPCCA_ERR_INVALID_ARG, "too many sectors in one run");
+    L.tiles = b.take(sizeof(int2) * L.tile_cap);
     // the row-grouped staging buffer is dead after the row sort: the chain
     // copies for the fit reuse it
     L.tmp = b.take(sizeof(Rec) * N);
@@ -449,7 +476,7 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.hoff = b.take(c->pruned_run ? sizeof(int32_t) * N : 0);
     L.hn1 = b.take(c->pruned_run ? sizeof(int32_t) * N : 0);
     L.hn2 = b.take(c->pruned_run ? sizeof(int32_t) * N : 0);
-    const int64_t nblk = (std::max<int64_t>(W, trk_cap) + kScanItems - 1) / kScanItems + 2;
+    const int64_t nblk = (std::max<int64_t>(std::max<int64_t>(W, trk_cap), NW) + kScanItems - 1) / kScanItems + 2;
     L.scan_tmp = b.take(sizeof(int32_t) * nblk);
     L.total = align_up(b.off, 256);
     c->n_in = N;
@@ -466,7 +493,9 @@ static tpcca_status plan(tpcca_ctx *c) {
     a.tseed_cap = (int32_t)tseed_cap;
     a.trk_cap = (int32_t)trk_cap;
     a.max_gap = c->cfg.max_gap;
-    a.strip_target = c->strip_target;
+    a.n_rb = nrb;
+    a.tile_budget = std::min(c->tile_budget, kTileCap);
+    a.tile_cap = (int32_t)L.tile_cap;
     a.min_track_hits = c->cfg.min_track_hits;
     a.kf_passes = c->cfg.kf_passes;
     for (int g = 1; g <= kMaxGap; g++) {
@@ -504,6 +533,11 @@ static void bind_pointers(tpcca_ctx *c) {
     char *A = c->arena;
     a.row_x = (const float *)(A + L.row_x);
     a.w_tab = (const float *)(A + L.w_tab);
+    a.ycell = (const YCell *)(A + L.ycell);
+    a.tstart = (int16_t *)(A + L.tstart);
+    a.ntile = (int32_t *)(A + L.ntile);
+    a.tile_base = (int32_t *)(A + L.tile_base);
+    a.tiles = (int2 *)(A + L.tiles);
     a.si = (const SiDesc *)(A + L.si);
     a.st = (SiState *)(A + L.st);
     a.cnt = (Counters *)(A + L.cnt);
@@ -576,6 +610,7 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     mark(st++);
     launch_grid_rowsort(a, c->lc[4], s);
     mark(st++);
+    launch_tiles(a, s);
     if (a.use_mlp) {
         launch_links_enum(a, c->lc[5], s);
         launch_mlp_infer(a.mlp, a.pfeat, &cnt->pool_next, a.pool_cap, a.pz, c->n_cu * 8, s);
@@ -697,6 +732,8 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
                                  hipMemcpyHostToDevice, s));
         HIPCHK(c, hipMemcpyAsync(A + L.w_tab, c->wtab.data(), sizeof(float) * c->wtab.size(),
                                  hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(A + L.ycell, c->ycell.data(), sizeof(YCell) * c->ycell.size(),
+                                 hipMemcpyHostToDevice, s));
         HIPCHK(c, hipStreamSynchronize(s));
         c->upload_dirty = false;
     }
@@ -765,7 +802,8 @@ tpcca_status tpcca_get_stats(tpcca_ctx *c, tpcca_stats *out) {
     out->n_tracks = k.n_tracks;
     out->n_track_clusters = k.n_cl;
     out->n_invalid = k.n_invalid;
-    out->n_overflow_rows = k.n_glb_rows;
+    out->n_overflow_tiles = k.n_glb_tiles;
+    out->n_tiles = k.n_tiles;
     out->n_triplets = c->args.use_mlp ? k.pool_used : 0;
     out->n_pruned = k.n_pruned;
     out->n_pool_overflow = k.pool_overflow;
@@ -1068,18 +1106,28 @@ tpcca_status tpcca_get_triplets(tpcca_ctx *c, int32_t frame, int32_t sector, int
     std::sort(order.begin(), order.end(), [&](int a, int b) { return rec[a].id < rec[b].id; });
     int64_t k = 0;
     const int base = st.sbase;
+    std::vector<int64_t> srcs;
     for (int p : order) {
-        const int n = hn1[p] + hn2[p];
-        for (int j = 0; j < n; j++, k++) {
-            const int64_t src = (int64_t)hoff[p] + j - lo;
-            if (tri) {
-                tri[4 * k] = rec[pd[src] - base].id;
-                tri[4 * k + 1] = rec[p].id;
-                tri[4 * k + 2] = rec[pu[src] - base].id;
-                tri[4 * k + 3] = j < hn1[p] ? 1 : 2;
+        for (int g = 0; g < 2; g++) {
+            // one gap's triplets, by (down id, up id)
+            const int j0 = g ? hn1[p] : 0, j1 = g ? hn1[p] + hn2[p] : hn1[p];
+            srcs.clear();
+            for (int j = j0; j < j1; j++) srcs.push_back((int64_t)hoff[p] + j - lo);
+            std::sort(srcs.begin(), srcs.end(), [&](int64_t u, int64_t v) {
+                const int du = rec[pd[u] - base].id, dv = rec[pd[v] - base].id;
+                return du < dv || (du == dv && rec[pu[u] - base].id < rec[pu[v] - base].id);
+            });
+            for (int64_t src : srcs) {
+                if (tri) {
+                    tri[4 * k] = rec[pd[src] - base].id;
+                    tri[4 * k + 1] = rec[p].id;
+                    tri[4 * k + 2] = rec[pu[src] - base].id;
+                    tri[4 * k + 3] = g + 1;
+                }
+                if (feat) std::memcpy(feat + kMlpInP * k, pf.data() + kMlpInP * src, 2 * kMlpInP);
+                if (z) z[k] = pz[src];
+                k++;
             }
-            if (feat) std::memcpy(feat + kMlpInP * k, pf.data() + kMlpInP * src, 2 * kMlpInP);
-            if (z) z[k] = pz[src];
         }
     }
     return TPCCA_OK;

@@ -407,6 +407,10 @@ void launch_scan_popc(const uint32_t *in, int32_t n, int32_t *out, int32_t *tota
     scan_impl(PopcIn{in}, nullptr, n, n, out, total_dst, tmp, s);
 }
 
+void launch_scan_i32(const int32_t *in, int32_t n, int32_t *out, int32_t *total_dst, int32_t *tmp, hipStream_t s) {
+    scan_impl(I32In{in}, nullptr, n, n, out, total_dst, tmp, s);
+}
+
 void launch_scan_i32_dev(const int32_t *in, const int32_t *n_dev, int32_t n_cap, int32_t *out, int32_t *total_dst,
                          int32_t *tmp, hipStream_t s) {
     scan_impl(I32In{in}, n_dev, 0, n_cap, out, total_dst, tmp, s);

@@ -1,28 +1,24 @@
 // Search-grid construction: per sector, clusters are grouped by pad row and
-// each row is ordered by drift time (ties by input index), with coarse time
-// bins giving O(1) range lookups. The grid is an acceleration structure
+// each row is ordered by fine drift-time bin, then y cell, then time (ties by
+// input index), with coarse time bins giving O(1) range lookups. The grid is an acceleration structure
 // only: neighbour candidate sets are decided by exact predicates later, so
 // the layout cannot change any result.
 //
 // Kernels (persistent, grid-stride over device-side work counts):
 //   k_si_init   reset per-sector state
 //   k_hist      per-chunk LDS row histogram + time range, validation
-//   k_si_rows   per sector: row prefix, bin geometry, tiles per row
-//   k_si_prefix sorted-space base and tile base of every sector
+//   k_si_rows   per sector: row prefix, bin geometry
+//   k_si_prefix sorted-space base of every sector
 //   k_scatter   stable-free scatter of clusters into row segments (LDS ranks)
 //   k_rowsort   per (sector,row): fine-bin counting sort in LDS, then an
-//               in-place sort of each fine bin by (t, id); writes the coarse
-//               bin offsets used by the neighbour tiles
+//               in-place sort of each fine bin by (y cell, t, id); writes
+//               the coarse bin offsets used by the neighbour tiles
 #include "tpcca_internal.h"
 
 namespace tpcca {
 
 __device__ inline bool valid_cluster(int r, float y, float t, int n_rows) {
     return r < n_rows && __builtin_isfinite(y) && __builtin_isfinite(t);
-}
-
-__device__ inline float bin_coord(float t, float t0, float inv) {
-    return __fmul_rn(__fsub_rn(t, t0), inv);
 }
 
 __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
@@ -150,17 +146,9 @@ __global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
                 inv = 0.f;
                 ncb = 1;
             }
-            // strip width: about strip_target own clusters per row on average
-            int tcb = kMaxStripCb;
-            if (nv > 0) {
-                const float dens = (float)nv / ((float)R * (float)ncb);
-                tcb = min(max((int)((float)a.strip_target / fmaxf(dens, 1e-3f)), 2), kMaxStripCb);
-            }
             s.t0 = tmin;
             s.inv_cbw = inv;
             s.ncb = ncb;
-            s.tcb = tcb;
-            s.nslab = nv > 0 ? (ncb + tcb - 1) / tcb : 0;
             s.n_valid = nv;
             a.st[si] = s;
         }
@@ -191,27 +179,17 @@ __device__ inline void block_scan2(int &v0, int &v1, int &tot0, int &tot1, int *
 
 __global__ __launch_bounds__(1024) void k_si_prefix(KArgs a) {
     __shared__ int sh0[1024], sh1[1024];
-    int carry_s = 0, carry_t = 0;
+    int carry_s = 0;
     for (int base = 0; base < a.n_si; base += blockDim.x) {
         const int si = base + threadIdx.x;
-        int nv = 0, nt = 0;
-        if (si < a.n_si) {
-            nv = a.st[si].n_valid;
-            nt = a.st[si].nslab;
-        }
-        int tv, tt;
-        block_scan2(nv, nt, tv, tt, sh0, sh1);
-        if (si < a.n_si) {
-            a.st[si].sbase = carry_s + nv;
-            a.st[si].strip_base = carry_t + nt;
-        }
+        int nv = 0, nz = 0;
+        if (si < a.n_si) nv = a.st[si].n_valid;
+        int tv, tz;
+        block_scan2(nv, nz, tv, tz, sh0, sh1);
+        if (si < a.n_si) a.st[si].sbase = carry_s + nv;
         carry_s += tv;
-        carry_t += tt;
     }
-    if (threadIdx.x == 0) {
-        a.cnt->n_valid_total = carry_s;
-        a.cnt->n_strips = carry_t;
-    }
+    if (threadIdx.x == 0) a.cnt->n_valid_total = carry_s;
 }
 
 void launch_grid_hist(const KArgs &a, Launch l, hipStream_t s) {
@@ -270,15 +248,16 @@ void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s) {
         hipLaunchKernelGGL(k_scatter, dim3(min(l.grid, a.n_chunks)), dim3(256), 0, s, a);
 }
 
-__device__ inline bool rec_less(float ta, int ia, float tb, int ib) {
-    return ta < tb || (ta == tb && ia < ib);
+// order inside a fine time bin: (y cell, t, id)
+__device__ inline bool rec_less(int ca, float ta, int ia, int cb, float tb, int ib) {
+    return ca < cb || (ca == cb && (ta < tb || (ta == tb && ia < ib)));
 }
 
-// sort k (> 1) records in place by (t, id)
-__device__ void sort_bin(Rec *__restrict__ p, int k) {
+// sort k (> 1) records in place by (y cell, t, id)
+__device__ void sort_bin(Rec *__restrict__ p, int k, const YCell &yc) {
     if (k <= 8) {
         float ky[8], kt[8];
-        int kid[8], ksr[8];
+        int kid[8], ksr[8], kc[8];
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             if (j < k) {
@@ -287,22 +266,25 @@ __device__ void sort_bin(Rec *__restrict__ p, int k) {
                 kt[j] = e.t;
                 kid[j] = e.id;
                 ksr[j] = e.sr;
+                kc[j] = ycell_of(yc, e.y);
             } else {
                 ky[j] = 0.f;
                 kt[j] = __builtin_inff();
                 kid[j] = 0x7fffffff;
                 ksr[j] = 0;
+                kc[j] = 0x7fffffff;
             }
         }
 #pragma unroll
         for (int round = 0; round < 8; round++) {
 #pragma unroll
             for (int j = (round & 1); j + 1 < 8; j += 2) {
-                if (rec_less(kt[j + 1], kid[j + 1], kt[j], kid[j])) {
+                if (rec_less(kc[j + 1], kt[j + 1], kid[j + 1], kc[j], kt[j], kid[j])) {
                     float fy = ky[j]; ky[j] = ky[j + 1]; ky[j + 1] = fy;
                     float ft = kt[j]; kt[j] = kt[j + 1]; kt[j + 1] = ft;
                     int fi = kid[j]; kid[j] = kid[j + 1]; kid[j + 1] = fi;
                     int fs = ksr[j]; ksr[j] = ksr[j + 1]; ksr[j + 1] = fs;
+                    int fc = kc[j]; kc[j] = kc[j + 1]; kc[j + 1] = fc;
                 }
             }
         }
@@ -320,9 +302,12 @@ __device__ void sort_bin(Rec *__restrict__ p, int k) {
     } else {
         for (int i = 1; i < k; i++) {
             const Rec e = p[i];
+            const int ce = ycell_of(yc, e.y);
             int j = i - 1;
-            while (j >= 0 && rec_less(e.t, e.id, p[j].t, p[j].id)) {
-                p[j + 1] = p[j];
+            while (j >= 0) {
+                const Rec f = p[j];
+                if (!rec_less(ce, e.t, e.id, ycell_of(yc, f.y), f.t, f.id)) break;
+                p[j + 1] = f;
                 j--;
             }
             p[j + 1] = e;
@@ -354,11 +339,7 @@ __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
         }
         for (int b = tid; b < nf; b += bd) fh[b] = 0;
         __syncthreads();
-        for (int k = tid; k < n; k += bd) {
-            const float v = bin_coord(a.tmp[start + k].t, t0, inv);
-            const int fb = min((int)__fmul_rn(v, (float)kFinePerCb), nf - 1);
-            atomicAdd(&fh[fb], 1);
-        }
+        for (int k = tid; k < n; k += bd) atomicAdd(&fh[fine_bin(a.tmp[start + k].t, t0, inv, nf)], 1);
         __syncthreads();
         // exclusive scan of fh[0, nf)
         const int per = (nf + bd - 1) / bd;
@@ -384,18 +365,17 @@ __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
         __syncthreads();
         for (int k = tid; k < n; k += bd) {
             const Rec e = a.tmp[start + k];
-            const float v = bin_coord(e.t, t0, inv);
-            const int fb = min((int)__fmul_rn(v, (float)kFinePerCb), nf - 1);
-            const int slot = atomicAdd(&fh[fb], 1);
+            const int slot = atomicAdd(&fh[fine_bin(e.t, t0, inv, nf)], 1);
             a.rec[start + slot] = e;
         }
         __threadfence_block();
         __syncthreads();
         // fh[b] now holds the end of fine bin b
+        const YCell yc = a.ycell[seg - si * R];
         for (int b = tid; b < nf; b += bd) {
             const int blo = b ? fh[b - 1] : 0;
             const int bhi = fh[b];
-            if (bhi - blo > 1) sort_bin(a.rec + start + blo, bhi - blo);
+            if (bhi - blo > 1) sort_bin(a.rec + start + blo, bhi - blo, yc);
         }
         __threadfence_block();
         __syncthreads();

@@ -1,127 +1,243 @@
-// Neighbour finding: one lane per cluster, one workgroup per strip (a sector
-// and a slab of coarse time bins), sweeping the pad rows of the strip in
-// order. The rows r-2..r+2 (plus one coarse bin of time halo on each side)
-// live in a five-slot LDS ring: each step stages the one new row r+2, builds
-// a small time index over it, and then every lane scores the candidates of
-// one cluster of row r:
+// Neighbour finding (the pair search of the cellular-automaton seeding, with
+// drift time as the seeding coordinate). For every cluster i on pad row r and
+// gap g = 1, then g = 2 only if g = 1 found nothing, the candidates are the
+// clusters d on row r-g and u on row r+g inside the box |y - y_i| <= g*win_y,
+// |t - t_i| <= g*win_t, and a pair is scored
 //
 //   ry = (y_i - y_d) - w*(y_u - y_d),  rt = (t_i - t_d) - w*(t_u - t_d),
 //   c  = ry*ry + rt*rt,                accepted if c <= pair_c2,
 //
-// over down clusters d on row r-g and up clusters u on row r+g inside the
-// box |y - y_i| <= g*win_y, |t - t_i| <= g*win_t, for g = 1, then g = 2 only
-// if g = 1 found nothing. w = (x_r - x_{r-g}) / (x_{r+g} - x_{r-g}) comes
-// precomputed in FP32 from the host. Every operation is one separately
-// rounded FP32 op (no contraction), so the decisions are bit-identical to
-// any IEEE implementation of the same sequence. The winner is the
-// lexicographic minimum of (c, up input index, down input index). Time is the
-// seeding coordinate; no z or vertex is involved.
+// with w = (x_r - x_{r-g}) / (x_{r+g} - x_{r-g}) precomputed in FP32 on the
+// host. Every operation is one separately rounded FP32 op (no contraction),
+// so decisions are bit-identical to any IEEE implementation of the same
+// sequence. The link is the lexicographic minimum of (c, up input index,
+// down input index) over the accepted pairs, so the order in which pairs are
+// visited cannot change it.
 //
-// Strips come from a device-side work queue, so uneven sectors and frames
-// balance across the persistent workgroups. A row whose staged range does not
-// fit its LDS slot is read from global memory (L2) instead, with the same
-// predicates.
+// Work decomposition: a tile is (sector instance, block of kTileRows pad
+// rows, slab of coarse time bins). k_tiles cuts every (sector instance, row
+// block) into slabs whose staged clusters (own rows plus kMaxGap rows on each
+// side, plus one coarse bin of time on each side) fit the LDS budget; tiles
+// come from a device work queue, so uneven sectors and frames balance over
+// the persistent workgroups. Within a staged row the clusters are ordered by
+// (fine time bin, y cell, t, id) (the row sort leaves them so): a box lookup
+// visits the 1-3 fine bins the box overlaps and, in each, binary-searches its
+// first y cell. A tile too dense for LDS (a single coarse bin over budget)
+// runs the same search on global memory. Clusters without a g = 1 link go to
+// an LDS queue and are searched at g = 2 by the whole workgroup.
 #include "tpcca_internal.h"
 
 namespace tpcca {
 
-constexpr int kSweepBlock = 256;
-constexpr int kSlots = 2 * kMaxGap + 1;
-constexpr int kSlotCap = 768;
-constexpr int kIdxPerCb = 8;                                  // index bins per coarse bin
-constexpr int kIdxMax = (kMaxStripCb + 2) * kIdxPerCb + 1;
+constexpr int kLinkBlock = 256;
+constexpr int kSlots = kTileRows + 2 * kMaxGap;          // staged rows of a tile
+constexpr int kTileFb = (kMaxTileCb + 2) * kFinePerCb;   // fine bins of a staged row
+constexpr int kBatch = 8;                                // down candidates held in registers
 
-struct LdsSlot {
-    const float *y, *t;
-    const int32_t *id;
-    const int32_t *first;  // index bin -> first position with bin >= it
-    int32_t pos0, n, nb;
-    float T0, sidx;        // index bin = floor((t - T0) * sidx)
-    __device__ float Y(int k) const { return y[k]; }
-    __device__ float T(int k) const { return t[k]; }
-    __device__ int32_t I(int k) const { return id[k]; }
-    // a position at or before the first element with time >= tl
-    __device__ int start(float tl) const {
-        int b = (int)floorf(__fmul_rn(__fsub_rn(tl, T0), sidx)) - 1;
-        b = min(max(b, 0), nb);
-        return first[b];
-    }
-};
-
-struct GlbSlot {
-    const Rec *r;
-    const int32_t *co;     // coarse offsets of the row
-    int32_t pos0, n, cb_lo;
-    float t0, inv_cbw;
-    __device__ float Y(int k) const { return r[pos0 + k].y; }
-    __device__ float T(int k) const { return r[pos0 + k].t; }
-    __device__ int32_t I(int k) const { return r[pos0 + k].id; }
-    __device__ int start(float tl) const {
-        // every time >= tl - 1 coarse bin lies at or after this coarse bin
-        int cb = (int)floorf(__fmul_rn(__fsub_rn(tl, t0), inv_cbw)) - 1;
-        cb = max(cb, cb_lo);
-        const int p = co[cb] - pos0;
-        return min(max(p, 0), n);
-    }
-};
-
-template <class VD, class VU>
-__device__ inline bool best_pair(const VD &D, const VU &U, float yi, float ti, float w, float wy, float wt,
-                                 float c2, int &bu, int &bd) {
-    const float tl = __fsub_rn(ti, wt);
-    const int sd = D.start(tl), su = U.start(tl);
-    bool found = false;
-    float bc = 0.f;
-    int biu = 0, bid = 0;
-    for (int kd = sd; kd < D.n; kd++) {
-        const float td = D.T(kd);
-        if (__fsub_rn(td, ti) > wt) break;
-        const float yd = D.Y(kd);
-        if (!(fabsf(__fsub_rn(yi, yd)) <= wy && fabsf(__fsub_rn(ti, td)) <= wt)) continue;
-        const float ady = __fsub_rn(yi, yd);
-        const float adt = __fsub_rn(ti, td);
-        int idd = -1;
-        for (int ku = su; ku < U.n; ku++) {
-            const float tu = U.T(ku);
-            if (__fsub_rn(tu, ti) > wt) break;
-            const float yu = U.Y(ku);
-            if (!(fabsf(__fsub_rn(yu, yi)) <= wy && fabsf(__fsub_rn(tu, ti)) <= wt)) continue;
-            const float by = __fsub_rn(yu, yd);
-            const float bt = __fsub_rn(tu, td);
-            const float ry = __fsub_rn(ady, __fmul_rn(w, by));
-            const float rt = __fsub_rn(adt, __fmul_rn(w, bt));
-            const float c = __fadd_rn(__fmul_rn(ry, ry), __fmul_rn(rt, rt));
-            if (!(c <= c2)) continue;
-            if (idd < 0) idd = D.I(kd);
-            const int idu = U.I(ku);
-            if (!found || c < bc || (c == bc && (idu < biu || (idu == biu && idd < bid)))) {
-                found = true;
-                bc = c;
-                biu = idu;
-                bid = idd;
-                bu = U.pos0 + ku;
-                bd = D.pos0 + kd;
-            }
+// ---------------------------------------------------------------- tiles
+// One workgroup per (sector instance, row block): cumulative staged counts
+// per coarse bin in LDS, then wave 0 cuts greedy slabs, 64 candidate ends at
+// a time (the staged count is non-decreasing in the slab end).
+__global__ __launch_bounds__(256) void k_tiles(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    __shared__ int32_t cum[kNcbMax + 1];
+    const int R = a.n_rows, nrb = a.n_rb;
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int w = blockIdx.x; w < a.n_si * nrb; w += gridDim.x) {
+        const int si = w / nrb, rb = w - si * nrb;
+        const SiState S = a.st[si];
+        const int ncb = S.ncb;
+        if (S.n_valid == 0) {
+            if (tid == 0) a.ntile[w] = 0;
+            continue;
         }
+        const int r0 = rb * kTileRows, r1 = min(r0 + kTileRows, R);
+        const int s0 = max(r0 - kMaxGap, 0), s1 = min(r1 + kMaxGap, R);
+        const int32_t *co0 = a.coff + ((int64_t)si * R + s0) * (kNcbMax + 1);
+        for (int cb = tid; cb <= ncb; cb += blockDim.x) {
+            int sum = 0;
+            for (int r = 0; r < s1 - s0; r++) {
+                const int32_t *co = co0 + (int64_t)r * (kNcbMax + 1);
+                sum += co[cb] - co[0];
+            }
+            cum[cb] = sum;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            int16_t *ts = a.tstart + (int64_t)w * kNcbMax;
+            const int budget = a.tile_budget;
+            int c0 = 0, n = 0;
+            while (c0 < ncb) {
+                const int c1 = c0 + 1 + lane;     // candidate slab end (exclusive)
+                bool ok = false;
+                if (lane < kMaxTileCb && c1 <= ncb)
+                    ok = cum[min(c1 + 1, ncb)] - cum[max(c0 - 1, 0)] <= budget;
+                const int take = max(1, (int)__popcll(__ballot(ok)));
+                if (lane == 0) ts[n] = (int16_t)c0;
+                n++;
+                c0 += take;
+            }
+            if (lane == 0) a.ntile[w] = n;
+        }
+        __syncthreads();
     }
-    return found;
 }
 
-// Number of clusters inside the box on each of the two rows.
-template <class VD, class VU>
-__device__ inline int box_count(const VD &D, const VU &U, float yi, float ti, float wy, float wt) {
-    const float tl = __fsub_rn(ti, wt);
+// Tile list: tiles[tile_base[w] + k] = (w, cb0 | cb1 << 16).
+__global__ __launch_bounds__(256) void k_tile_list(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    const int nrb = a.n_rb;
+    for (int w = blockIdx.x; w < a.n_si * nrb; w += gridDim.x) {
+        const int n = a.ntile[w], base = a.tile_base[w];
+        const int ncb = a.st[w / nrb].ncb;
+        const int16_t *ts = a.tstart + (int64_t)w * kNcbMax;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            if (base + k >= a.tile_cap) break;
+            const int c0 = ts[k], c1 = (k + 1 < n) ? ts[k + 1] : ncb;
+            a.tiles[base + k] = make_int2(w, c0 | (c1 << 16));
+        }
+    }
+}
+
+void launch_tiles(const KArgs &a, hipStream_t s) {
+    const int nw = a.n_si * a.n_rb;
+    if (nw <= 0) return;
+    hipLaunchKernelGGL(k_tiles, dim3(min(nw, 8192)), dim3(256), 0, s, a);
+    launch_scan_i32(a.ntile, nw, a.tile_base, &a.cnt->n_tiles, a.scan_tmp, s);
+    hipLaunchKernelGGL(k_tile_list, dim3(min(nw, 8192)), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------- staged rows
+// Staged row j of a tile: clusters [plo, plo + n) of the sorted space, its
+// fine bins relative to the tile's first staged coarse bin.
+struct TileGeo {
+    float t0, inv_cbw;
+    int nf;        // fine bins of the sector row
+    int fb0;       // first staged fine bin
+    int nfb;       // staged fine bins
+};
+
+// Rows held in LDS.
+struct LdsRows {
+    const float2 *yt;              // staged (y, t)
+    const int32_t *base;           // [kSlots] LDS index of row j's first cluster
+    const int16_t (*fs)[kTileFb + 1];
+    __device__ float2 at(int j, int q) const { return yt[base[j] + q]; }
+    __device__ int fstart(int j, int f) const { return fs[j][f]; }
+};
+
+// Rows read from global memory (tiles over the LDS budget); the fine-bin
+// starts come from a binary search inside the coarse bin.
+struct GlbRows {
+    const Rec *rec;
+    const int32_t *plo;            // [kSlots] (LDS) first staged position of row j
+    const int32_t *n;              // [kSlots] (LDS) staged clusters of row j
+    const int32_t *co_s0;          // coarse offsets of the first staged row
+    TileGeo g;
+    __device__ float2 at(int j, int q) const {
+        const Rec e = rec[plo[j] + q];
+        return make_float2(e.y, e.t);
+    }
+    __device__ int fstart(int j, int f) const {
+        if (f >= g.nfb) return n[j];
+        const int fa = g.fb0 + f;
+        const int32_t *co = co_s0 + (int64_t)j * (kNcbMax + 1);
+        const int cb = fa / kFinePerCb;
+        int lo = co[cb], hi = co[cb + 1];
+        while (lo < hi) {
+            const int m = (lo + hi) >> 1;
+            if (fine_bin(rec[m].t, g.t0, g.inv_cbw, g.nf) < fa) lo = m + 1;
+            else hi = m;
+        }
+        return lo - plo[j];
+    }
+};
+
+// A bound that every time (or y) passing the box test lies beyond: the exact
+// FP32 predicate |fl(a - b)| <= w admits |a - b| slightly above w.
+__device__ inline float slack(float v, float w) { return __fadd_rn(__fmul_rn(fabsf(v), 1.0e-6f), __fmul_rn(w, 1.0e-3f)); }
+
+// Visit the clusters of staged row j inside the box around (yi, ti), in row
+// order, calling fn(q, y, t) with q the row-local index. The box test is the
+// exact predicate: for the down row |yi - y| <= wy && |ti - t| <= wt, for
+// the up row |y - yi| <= wy && |t - ti| <= wt.
+template <bool Down, class Rows, class Fn>
+__device__ inline void box_visit(const Rows &A, const TileGeo &G, const YCell &yc, int j, float yi, float ti, float wy,
+                                 float wt, Fn &&fn) {
+    const float sy = slack(yi, wy), st = slack(ti, wt);
+    const int f0 = fine_bin(__fsub_rn(__fsub_rn(ti, wt), st), G.t0, G.inv_cbw, G.nf) - G.fb0;
+    const int f1 = fine_bin(__fadd_rn(__fadd_rn(ti, wt), st), G.t0, G.inv_cbw, G.nf) - G.fb0;
+    const int c0 = ycell_of(yc, __fsub_rn(__fsub_rn(yi, wy), sy));
+    const int c1 = ycell_of(yc, __fadd_rn(__fadd_rn(yi, wy), sy));
+    for (int f = max(f0, 0); f <= min(f1, G.nfb - 1); f++) {
+        int lo = A.fstart(j, f);
+        const int hi = A.fstart(j, f + 1);
+        int h = hi;
+        while (lo < h) {
+            const int m = (lo + h) >> 1;
+            if (ycell_of(yc, A.at(j, m).x) < c0) lo = m + 1;
+            else h = m;
+        }
+        for (int q = lo; q < hi; q++) {
+            const float2 e = A.at(j, q);
+            if (ycell_of(yc, e.x) > c1) break;
+            const bool in = Down ? (fabsf(__fsub_rn(yi, e.x)) <= wy && fabsf(__fsub_rn(ti, e.y)) <= wt)
+                                 : (fabsf(__fsub_rn(e.x, yi)) <= wy && fabsf(__fsub_rn(e.y, ti)) <= wt);
+            if (in) fn(q, e.x, e.y);
+        }
+    }
+}
+
+// Every accepted pair (c <= c2) of cluster (yi, ti) between staged rows jd
+// (down) and ju (up): on_pair(qd, yd, td, qu, yu, tu, c). Down candidates are
+// taken kBatch at a time into registers, then the up row is visited once per
+// batch.
+template <class Rows, class Fn>
+__device__ inline void visit_pairs(const Rows &A, const TileGeo &G, const YCell &ycd, const YCell &ycu, int jd,
+                                   int ju, float yi, float ti, float w, float wy, float wt, float c2, Fn &&on_pair) {
+    for (int skip = 0;; skip += kBatch) {
+        float dy[kBatch], dt[kBatch];
+        int dq[kBatch];
+        int nd = 0, seen = 0;
+        box_visit<true>(A, G, ycd, jd, yi, ti, wy, wt, [&](int q, float y, float t) {
+            if (seen >= skip && nd < kBatch) {
+#pragma unroll
+                for (int k = 0; k < kBatch; k++)
+                    if (k == nd) {
+                        dy[k] = y;
+                        dt[k] = t;
+                        dq[k] = q;
+                    }
+                nd++;
+            }
+            seen++;
+        });
+        if (nd == 0) return;
+        box_visit<false>(A, G, ycu, ju, yi, ti, wy, wt, [&](int qu, float yu, float tu) {
+#pragma unroll
+            for (int k = 0; k < kBatch; k++) {
+                if (k >= nd) break;
+                const float ady = __fsub_rn(yi, dy[k]);
+                const float adt = __fsub_rn(ti, dt[k]);
+                const float by = __fsub_rn(yu, dy[k]);
+                const float bt = __fsub_rn(tu, dt[k]);
+                const float ry = __fsub_rn(ady, __fmul_rn(w, by));
+                const float rt = __fsub_rn(adt, __fmul_rn(w, bt));
+                const float c = __fadd_rn(__fmul_rn(ry, ry), __fmul_rn(rt, rt));
+                if (c <= c2) on_pair(dq[k], dy[k], dt[k], qu, yu, tu, c);
+            }
+        });
+        if (seen <= skip + kBatch) return;
+    }
+}
+
+// Number of clusters in the box on the down and the up row.
+template <class Rows>
+__device__ inline int box_count(const Rows &A, const TileGeo &G, const YCell &ycd, const YCell &ycu, int jd, int ju,
+                                float yi, float ti, float wy, float wt) {
     int n = 0;
-    for (int k = D.start(tl); k < D.n; k++) {
-        const float td = D.T(k);
-        if (__fsub_rn(td, ti) > wt) break;
-        n += (fabsf(__fsub_rn(yi, D.Y(k))) <= wy && fabsf(__fsub_rn(ti, td)) <= wt);
-    }
-    for (int k = U.start(tl); k < U.n; k++) {
-        const float tu = U.T(k);
-        if (__fsub_rn(tu, ti) > wt) break;
-        n += (fabsf(__fsub_rn(U.Y(k), yi)) <= wy && fabsf(__fsub_rn(tu, ti)) <= wt);
-    }
+    box_visit<true>(A, G, ycd, jd, yi, ti, wy, wt, [&](int, float, float) { n++; });
+    box_visit<false>(A, G, ycu, ju, yi, ti, wy, wt, [&](int, float, float) { n++; });
     return n;
 }
 
@@ -163,286 +279,313 @@ __device__ inline void triplet_features(float yd, float td, float xd, float yi, 
     f[12] = f[13] = f[14] = f[15] = 0;
 }
 
-// Visit every accepted pair (c <= c2) of the cluster in the fixed order
-// (down clusters in time order, then up clusters in time order); with
-// write = false it only counts them.
-template <bool write, class VD, class VU>
-__device__ inline int visit_pairs(const VD &D, const VU &U, float yi, float ti, float xd, float xi, float xu, int g,
-                                  float w, float wy, float wt, float c2, float c2s, int ncand, const KArgs &a,
-                                  int slot) {
-    const float tl = __fsub_rn(ti, wt);
-    const int sd = D.start(tl), su = U.start(tl);
-    int n = 0;
-    for (int kd = sd; kd < D.n; kd++) {
-        const float td = D.T(kd);
-        if (__fsub_rn(td, ti) > wt) break;
-        const float yd = D.Y(kd);
-        if (!(fabsf(__fsub_rn(yi, yd)) <= wy && fabsf(__fsub_rn(ti, td)) <= wt)) continue;
-        const float ady = __fsub_rn(yi, yd);
-        const float adt = __fsub_rn(ti, td);
-        for (int ku = su; ku < U.n; ku++) {
-            const float tu = U.T(ku);
-            if (__fsub_rn(tu, ti) > wt) break;
-            const float yu = U.Y(ku);
-            if (!(fabsf(__fsub_rn(yu, yi)) <= wy && fabsf(__fsub_rn(tu, ti)) <= wt)) continue;
-            const float by = __fsub_rn(yu, yd);
-            const float bt = __fsub_rn(tu, td);
-            const float ry = __fsub_rn(ady, __fmul_rn(w, by));
-            const float rt = __fsub_rn(adt, __fmul_rn(w, bt));
-            const float c = __fadd_rn(__fmul_rn(ry, ry), __fmul_rn(rt, rt));
-            if (!(c <= c2)) continue;
-            if (write) {
-                const int k = slot + n;
-                uint16_t f[kMlpInP];
-                triplet_features(yd, td, xd, yi, ti, xi, yu, tu, xu, g, wy, wt, w, c2s, ncand, f);
-                uint4 *dst = reinterpret_cast<uint4 *>(a.pfeat + (int64_t)k * kMlpInP);
-                dst[0] = make_uint4(f[0] | ((uint32_t)f[1] << 16), f[2] | ((uint32_t)f[3] << 16),
-                                    f[4] | ((uint32_t)f[5] << 16), f[6] | ((uint32_t)f[7] << 16));
-                dst[1] = make_uint4(f[8] | ((uint32_t)f[9] << 16), f[10] | ((uint32_t)f[11] << 16), 0u, 0u);
-                a.pd[k] = D.pos0 + kd;
-                a.pu[k] = U.pos0 + ku;
-                a.pc[k] = c;
+// Shared state of one tile.
+struct TileShared {
+    float2 yt[kTileCap];
+    int16_t fs[kSlots][kTileFb + 1];
+    int16_t queue[kTileCap];
+    YCell yc[kSlots];
+    int32_t base[kSlots + 1];      // LDS index of each staged row (prefix of n)
+    int32_t plo[kSlots];           // first staged sorted position of each row
+    int32_t n[kSlots];             // staged clusters of each row
+    int32_t olo[kSlots];           // own range of each own row, row-local
+    int32_t opre[kTileRows + 1];   // prefix of own counts over the own rows
+    int32_t scan[kLinkBlock];
+    int32_t item, nq, links, cpos, cend, pbase;
+};
+
+// Best pair of one cluster at gap g (false: none). bu/bd are sorted positions.
+template <class Rows>
+__device__ inline bool best_pair(const Rows &A, const TileGeo &G, const TileShared &T, const KArgs &a, int j, int r,
+                                 int g, float yi, float ti, int &bu, int &bd) {
+    const int jd = j - g, ju = j + g;
+    const float w = a.w_tab[r * kMaxGap + g - 1];
+    const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
+    bool found = false;
+    float bc = 0.f;
+    int bqu = 0, bqd = 0;
+    visit_pairs(A, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2,
+                [&](int qd, float, float, int qu, float, float, float c) {
+                    bool better = !found || c < bc;
+                    if (found && c == bc) {
+                        // exact tie of the score: compare input indices
+                        const int idu = a.rec[T.plo[ju] + qu].id, idd = a.rec[T.plo[jd] + qd].id;
+                        const int biu = a.rec[T.plo[ju] + bqu].id, bid = a.rec[T.plo[jd] + bqd].id;
+                        better = idu < biu || (idu == biu && idd < bid);
+                    }
+                    if (better) {
+                        found = true;
+                        bc = c;
+                        bqu = qu;
+                        bqd = qd;
+                    }
+                });
+    if (found) {
+        bu = T.plo[ju] + bqu;
+        bd = T.plo[jd] + bqd;
+    }
+    return found;
+}
+
+// Own cluster o of the tile -> staged row j and row-local index q.
+__device__ inline void own_locate(const TileShared &T, int jr0, int nown, int o, int &j, int &q) {
+    int k = 0;
+    while (k + 1 < nown && T.opre[k + 1] <= o) k++;
+    j = jr0 + k;
+    q = T.olo[j] + (o - T.opre[k]);
+}
+
+template <bool Enum, bool InLds>
+__device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int si, int r0, int s0, int nown,
+                           int own_total) {
+    const int R = a.n_rows;
+    const int tid = threadIdx.x;
+    const int jr0 = r0 - s0;
+    const int G2 = a.max_gap;
+    LdsRows L{T.yt, T.base, T.fs};
+    GlbRows Gl{a.rec, T.plo, T.n, a.coff + ((int64_t)si * R + s0) * (kNcbMax + 1), G};
+    int nl = 0;
+    if (!Enum) {
+        for (int o = tid; o < own_total; o += kLinkBlock) {
+            int j, q;
+            own_locate(T, jr0, nown, o, j, q);
+            const int r = s0 + j;
+            const float2 e = InLds ? L.at(j, q) : Gl.at(j, q);
+            int bu = -1, bd = -1;
+            bool done = true;
+            if (r >= 1 && r + 1 <= R - 1) {
+                const bool f = InLds ? best_pair(L, G, T, a, j, r, 1, e.x, e.y, bu, bd)
+                                     : best_pair(Gl, G, T, a, j, r, 1, e.x, e.y, bu, bd);
+                if (!f && G2 >= 2 && r >= 2 && r + 2 <= R - 1) {
+                    if (InLds) {
+                        // searched by the whole workgroup after this pass
+                        T.queue[atomicAdd(&T.nq, 1)] = (int16_t)o;
+                        done = false;
+                    } else {
+                        best_pair(Gl, G, T, a, j, r, 2, e.x, e.y, bu, bd);
+                    }
+                }
             }
-            n++;
+            if (done) {
+                a.link[T.plo[j] + q] = make_int2(bu, bd);
+                nl += (bu >= 0);
+            }
+        }
+        __syncthreads();
+        const int nq = InLds ? T.nq : 0;
+        for (int k = tid; k < nq; k += kLinkBlock) {
+            const int o = T.queue[k];
+            int j, q;
+            own_locate(T, jr0, nown, o, j, q);
+            const int r = s0 + j;
+            const float2 e = InLds ? L.at(j, q) : Gl.at(j, q);
+            int bu = -1, bd = -1;
+            best_pair(L, G, T, a, j, r, 2, e.x, e.y, bu, bd);
+            a.link[T.plo[j] + q] = make_int2(bu, bd);
+            nl += (bu >= 0);
+        }
+    } else {
+        // every triplet of every gap goes to the pool; slots are reserved
+        // per pass with a block scan and chunked grabs of the pool counter
+        for (int base = 0; base < own_total; base += kLinkBlock) {
+            const int o = base + tid;
+            const bool act = o < own_total;
+            int j = 0, q = 0, r = 0;
+            float yi = 0.f, ti = 0.f;
+            int ng[kMaxGap] = {}, nc[kMaxGap] = {};
+            if (act) {
+                own_locate(T, jr0, nown, o, j, q);
+                r = s0 + j;
+                const float2 e = InLds ? L.at(j, q) : Gl.at(j, q);
+                yi = e.x;
+                ti = e.y;
+                for (int g = 1; g <= G2; g++) {
+                    if (r - g < 0 || r + g > R - 1) continue;
+                    const int jd = j - g, ju = j + g;
+                    const float w = a.w_tab[r * kMaxGap + g - 1];
+                    const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
+                    int np = 0;
+                    auto cnt = [&](int, float, float, int, float, float, float) { np++; };
+                    if (InLds) {
+                        nc[g - 1] = box_count(L, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, wy, wt);
+                        visit_pairs(L, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2, cnt);
+                    } else {
+                        nc[g - 1] = box_count(Gl, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, wy, wt);
+                        visit_pairs(Gl, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2, cnt);
+                    }
+                    ng[g - 1] = np;
+                }
+            }
+            int tot = 0;
+#pragma unroll
+            for (int g = 0; g < kMaxGap; g++) tot += ng[g];
+            T.scan[tid] = tot;
+            __syncthreads();
+            for (int off = 1; off < kLinkBlock; off <<= 1) {
+                const int xv = (tid >= off) ? T.scan[tid - off] : 0;
+                __syncthreads();
+                T.scan[tid] += xv;
+                __syncthreads();
+            }
+            const int excl = T.scan[tid] - tot;
+            if (tid == kLinkBlock - 1) {
+                const int total = T.scan[tid];
+                if (T.cpos + total > T.cend) {
+                    const int grab = max(total, kPoolChunk);
+                    T.cpos = atomicAdd(&a.cnt->pool_next, grab);
+                    T.cend = T.cpos + grab;
+                }
+                T.pbase = T.cpos;
+                T.cpos += total;
+                if (total) atomicAdd(&a.cnt->pool_used, total);
+            }
+            __syncthreads();
+            const int slot0 = T.pbase + excl;
+            if (act) {
+                const int p = T.plo[j] + q;
+                const bool fits = (int64_t)slot0 + tot <= (int64_t)a.pool_cap;
+                if (fits) {
+                    int sl = slot0;
+                    for (int g = 1; g <= G2; g++) {
+                        if (ng[g - 1] == 0) continue;
+                        const int jd = j - g, ju = j + g;
+                        const float w = a.w_tab[r * kMaxGap + g - 1];
+                        const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
+                        const float xd = a.row_x[r - g], xi = a.row_x[r], xu = a.row_x[r + g];
+                        const int ncd = nc[g - 1];
+                        const int pd0 = T.plo[jd], pu0 = T.plo[ju];
+                        auto put = [&](int qd, float yd, float td, int qu, float yu, float tu, float c) {
+                            uint16_t f[kMlpInP];
+                            triplet_features(yd, td, xd, yi, ti, xi, yu, tu, xu, g, wy, wt, w, a.c2s, ncd, f);
+                            uint4 *dst = reinterpret_cast<uint4 *>(a.pfeat + (int64_t)sl * kMlpInP);
+                            dst[0] = make_uint4(f[0] | ((uint32_t)f[1] << 16), f[2] | ((uint32_t)f[3] << 16),
+                                                f[4] | ((uint32_t)f[5] << 16), f[6] | ((uint32_t)f[7] << 16));
+                            dst[1] = make_uint4(f[8] | ((uint32_t)f[9] << 16), f[10] | ((uint32_t)f[11] << 16), 0u, 0u);
+                            a.pd[sl] = pd0 + qd;
+                            a.pu[sl] = pu0 + qu;
+                            a.pc[sl] = c;
+                            sl++;
+                        };
+                        if (InLds) visit_pairs(L, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2, put);
+                        else visit_pairs(Gl, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2, put);
+                    }
+                    a.hoff[p] = slot0;
+                } else {
+                    a.hoff[p] = -1;
+                    atomicAdd(&a.cnt->pool_overflow, tot);
+                }
+                a.hn1[p] = ng[0];
+                a.hn2[p] = kMaxGap > 1 ? ng[1] : 0;
+            }
         }
     }
-    return n;
+    for (int off = 32; off > 0; off >>= 1) nl += __shfl_xor(nl, off);
+    if ((tid & 63) == 0 && nl) atomicAdd(&T.links, nl);
 }
 
 template <bool Enum>
-__global__ __launch_bounds__(kSweepBlock) void k_links(KArgs a) {
-    __shared__ float sy[kSlots][kSlotCap];
-    __shared__ float st[kSlots][kSlotCap];
-    __shared__ int32_t sid[kSlots][kSlotCap];
-    __shared__ int32_t sfirst[kSlots][kIdxMax];
-    __shared__ int32_t s_lo[kSlots], s_n[kSlots], s_glb[kSlots];
-    __shared__ int32_t s_strip, s_links, s_glbrows;
-    __shared__ int32_t s_scan[kSweepBlock];
-    __shared__ int32_t s_cpos, s_cend, s_base;
+__global__ __launch_bounds__(kLinkBlock) void k_links(KArgs a) {
+    __shared__ TileShared T;
     const int R = a.n_rows;
-    const int G = a.max_gap;
     const int tid = threadIdx.x;
-    const int n_strips = a.cnt->n_strips;
-    int iter = 0;
-    for (;; iter++) {
+    const int n_tiles = min(a.cnt->n_tiles, a.tile_cap);
+    if (tid == 0) {
+        T.cpos = 0;
+        T.cend = 0;
+    }
+    for (int iter = 0;; iter++) {
         if (tid == 0) {
-            int v = atomicAdd(&a.cnt->strip_next, 1);
-            if ((iter & 7) == 0 && abort_requested(a)) v = n_strips;
-            s_strip = v;
-            s_links = 0;
-            s_glbrows = 0;
-            if (iter == 0) {
-                s_cpos = 0;
-                s_cend = 0;
-            }
+            int v = atomicAdd(&a.cnt->tile_next, 1);
+            if ((iter & 15) == 0 && abort_requested(a)) v = n_tiles;
+            T.item = v;
+            T.nq = 0;
+            T.links = 0;
         }
         __syncthreads();
-        const int strip = s_strip;
-        if (strip >= n_strips) break;
-        // strip -> sector instance
-        int lo = 0, hi = a.n_si - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.st[mid].strip_base <= strip) lo = mid;
-            else hi = mid - 1;
-        }
-        const int si = lo;
+        const int item = T.item;
+        if (item >= n_tiles) break;
+        const int2 tl = a.tiles[item];
+        const int w = tl.x;
+        const int si = w / a.n_rb, rb = w - si * a.n_rb;
+        const int cb0 = tl.y & 0xffff, cb1 = tl.y >> 16;
         const SiState S = a.st[si];
-        const int slab = strip - S.strip_base;
-        const int cb0 = slab * S.tcb;
-        const int cb1 = min(cb0 + S.tcb, S.ncb);
-        const int cb_lo = max(cb0 - 1, 0);
-        const int cb_hi = min(cb1 + 1, S.ncb);
-        const float cbw = 1.0f / S.inv_cbw;
-        const float T0 = __fadd_rn(S.t0, __fmul_rn((float)cb_lo, cbw));
-        const float sidx = __fmul_rn(S.inv_cbw, (float)kIdxPerCb);
-        const int nb = (cb_hi - cb_lo) * kIdxPerCb;
-        const int32_t *co_si = a.coff + (int64_t)si * R * (kNcbMax + 1);
-        int nl = 0;
-
-        // stage row rr into its ring slot and build the slot's time index
-        auto stage = [&](int rr) {
-            const int j = rr % kSlots;
-            const int32_t *co = co_si + (int64_t)rr * (kNcbMax + 1);
+        const int r0 = rb * kTileRows, r1 = min(r0 + kTileRows, R);
+        const int s0 = max(r0 - kMaxGap, 0), s1 = min(r1 + kMaxGap, R);
+        const int nsr = s1 - s0, nown = r1 - r0;
+        const int cb_lo = max(cb0 - 1, 0), cb_hi = min(cb1 + 1, S.ncb);
+        TileGeo G;
+        G.t0 = S.t0;
+        G.inv_cbw = S.inv_cbw;
+        G.nf = S.ncb * kFinePerCb;
+        G.fb0 = cb_lo * kFinePerCb;
+        G.nfb = (cb_hi - cb_lo) * kFinePerCb;
+        const int32_t *co_s0 = a.coff + ((int64_t)si * R + s0) * (kNcbMax + 1);
+        if (tid < nsr) {
+            const int32_t *co = co_s0 + (int64_t)tid * (kNcbMax + 1);
             const int plo = co[cb_lo];
-            const int n = co[cb_hi] - plo;
-            const bool glb = n > kSlotCap;
-            if (!glb) {
-                for (int k = tid; k < n; k += kSweepBlock) {
-                    const Rec e = a.rec[plo + k];
-                    sy[j][k] = e.y;
-                    st[j][k] = e.t;
-                    sid[j][k] = e.id;
-                }
-            }
-            if (tid == 0) {
-                s_lo[j] = plo;
-                s_n[j] = n;
-                s_glb[j] = glb ? 1 : 0;
-                if (glb) s_glbrows++;
-            }
-            __syncthreads();
-            if (!glb) {
-                for (int k = tid; k <= n; k += kSweepBlock) {
-                    int bk = nb + 1, bp = -1;
-                    if (k < n) bk = min(max((int)floorf(__fmul_rn(__fsub_rn(st[j][k], T0), sidx)), 0), nb);
-                    if (k > 0) bp = min(max((int)floorf(__fmul_rn(__fsub_rn(st[j][k - 1], T0), sidx)), 0), nb);
-                    for (int b = bp + 1; b <= min(bk, nb); b++) sfirst[j][b] = k;
-                }
-            }
-        };
-
-        for (int r = 0; r < min(kMaxGap, R); r++) stage(r);
-        for (int r = 0; r < R; r++) {
-            if (r + kMaxGap < R) stage(r + kMaxGap);
-            __syncthreads();
-            // own clusters of row r: coarse bins [cb0, cb1)
-            const int32_t *co_r = co_si + (int64_t)r * (kNcbMax + 1);
-            const int jr = r % kSlots;
-            const int own_lo = co_r[cb0], own_hi = co_r[cb1];
-            for (int base = own_lo; base < own_hi; base += kSweepBlock) {
-                const int p = base + tid;
-                const bool act = p < own_hi;
-                float yi = 0.f, ti = 0.f;
-                if (act) {
-                    const int k = p - s_lo[jr];
-                    if (!s_glb[jr]) {
-                        yi = sy[jr][k];
-                        ti = st[jr][k];
-                    } else {
-                        const Rec e = a.rec[p];
-                        yi = e.y;
-                        ti = e.t;
-                    }
-                }
-                int bu = -1, bd = -1;
-                int ng[kMaxGap] = {};
-                int nc[kMaxGap] = {};
-                for (int g = 1; g <= G && act; g++) {
-                    if (r - g < 0 || r + g > R - 1) continue;
-                    const int jd = (r - g) % kSlots, ju = (r + g) % kSlots;
-                    const float w = a.w_tab[r * kMaxGap + g - 1];
-                    const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
-                    const bool gd = s_glb[jd] != 0, gu = s_glb[ju] != 0;
-                    LdsSlot LD{sy[jd], st[jd], sid[jd], sfirst[jd], s_lo[jd], s_n[jd], nb, T0, sidx};
-                    LdsSlot LU{sy[ju], st[ju], sid[ju], sfirst[ju], s_lo[ju], s_n[ju], nb, T0, sidx};
-                    GlbSlot GD{a.rec, co_si + (int64_t)(r - g) * (kNcbMax + 1), s_lo[jd], s_n[jd], cb_lo, S.t0,
-                               S.inv_cbw};
-                    GlbSlot GU{a.rec, co_si + (int64_t)(r + g) * (kNcbMax + 1), s_lo[ju], s_n[ju], cb_lo, S.t0,
-                               S.inv_cbw};
-                    if (!Enum) {
-                        bool f;
-                        if (!gd && !gu) f = best_pair(LD, LU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
-                        else if (!gd) f = best_pair(LD, GU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
-                        else if (!gu) f = best_pair(GD, LU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
-                        else f = best_pair(GD, GU, yi, ti, w, wy, wt, a.pair_c2, bu, bd);
-                        if (f) break;
-                        bu = -1;
-                        bd = -1;
-                    } else {
-                        const float xd = a.row_x[r - g], xi = a.row_x[r], xu = a.row_x[r + g];
-                        int ncd, npr;
-                        if (!gd && !gu) {
-                            ncd = box_count(LD, LU, yi, ti, wy, wt);
-                            npr = visit_pairs<false>(LD, LU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, 0);
-                        } else if (!gd) {
-                            ncd = box_count(LD, GU, yi, ti, wy, wt);
-                            npr = visit_pairs<false>(LD, GU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, 0);
-                        } else if (!gu) {
-                            ncd = box_count(GD, LU, yi, ti, wy, wt);
-                            npr = visit_pairs<false>(GD, LU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, 0);
-                        } else {
-                            ncd = box_count(GD, GU, yi, ti, wy, wt);
-                            npr = visit_pairs<false>(GD, GU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, 0);
-                        }
-                        ng[g - 1] = npr;
-                        nc[g - 1] = ncd;
-                    }
-                }
-                if (!Enum) {
-                    if (act) {
-                        a.link[p] = make_int2(bu, bd);
-                        nl += (bu >= 0);
-                    }
-                } else {
-                    // reserve this lane's pool slots: block scan, chunked grabs
-                    int tot = 0;
-#pragma unroll
-                    for (int g = 0; g < kMaxGap; g++) tot += ng[g];
-                    s_scan[tid] = tot;
-                    __syncthreads();
-                    for (int off = 1; off < kSweepBlock; off <<= 1) {
-                        const int xv = (tid >= off) ? s_scan[tid - off] : 0;
-                        __syncthreads();
-                        s_scan[tid] += xv;
-                        __syncthreads();
-                    }
-                    const int excl = s_scan[tid] - tot;
-                    if (tid == kSweepBlock - 1) {
-                        const int total = s_scan[tid];
-                        if (s_cpos + total > s_cend) {
-                            const int grab = max(total, kPoolChunk);
-                            s_cpos = atomicAdd(&a.cnt->pool_next, grab);
-                            s_cend = s_cpos + grab;
-                        }
-                        s_base = s_cpos;
-                        s_cpos += total;
-                        if (total) atomicAdd(&a.cnt->pool_used, total);
-                    }
-                    __syncthreads();
-                    const int slot0 = s_base + excl;
-                    if (act) {
-                        const bool fits = slot0 + tot <= a.pool_cap;
-                        if (fits) {
-                            int sl = slot0;
-                            for (int g = 1; g <= G; g++) {
-                                if (ng[g - 1] == 0) continue;
-                                const int jd = (r - g) % kSlots, ju = (r + g) % kSlots;
-                                const float w = a.w_tab[r * kMaxGap + g - 1];
-                                const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
-                                const float xd = a.row_x[r - g], xi = a.row_x[r], xu = a.row_x[r + g];
-                                const bool gd = s_glb[jd] != 0, gu = s_glb[ju] != 0;
-                                LdsSlot LD{sy[jd], st[jd], sid[jd], sfirst[jd], s_lo[jd], s_n[jd], nb, T0, sidx};
-                                LdsSlot LU{sy[ju], st[ju], sid[ju], sfirst[ju], s_lo[ju], s_n[ju], nb, T0, sidx};
-                                GlbSlot GD{a.rec, co_si + (int64_t)(r - g) * (kNcbMax + 1), s_lo[jd], s_n[jd], cb_lo,
-                                           S.t0, S.inv_cbw};
-                                GlbSlot GU{a.rec, co_si + (int64_t)(r + g) * (kNcbMax + 1), s_lo[ju], s_n[ju], cb_lo,
-                                           S.t0, S.inv_cbw};
-                                const int ncd = nc[g - 1];
-                                if (!gd && !gu) visit_pairs<true>(LD, LU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, sl);
-                                else if (!gd) visit_pairs<true>(LD, GU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, sl);
-                                else if (!gu) visit_pairs<true>(GD, LU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, sl);
-                                else visit_pairs<true>(GD, GU, yi, ti, xd, xi, xu, g, w, wy, wt, a.pair_c2, a.c2s, ncd, a, sl);
-                                sl += ng[g - 1];
-                            }
-                            a.hoff[p] = slot0;
-                        } else {
-                            a.hoff[p] = -1;
-                            atomicAdd(&a.cnt->pool_overflow, tot);
-                        }
-                        a.hn1[p] = ng[0];
-                        a.hn2[p] = kMaxGap > 1 ? ng[1] : 0;
-                    }
-                }
-            }
-            __syncthreads();
+            T.plo[tid] = plo;
+            T.n[tid] = co[cb_hi] - plo;
+            T.olo[tid] = co[cb0] - plo;
+            T.yc[tid] = a.ycell[s0 + tid];
+            if (tid >= r0 - s0 && tid < r1 - s0) T.scan[tid] = co[cb1] - co[cb0];
         }
-        for (int off = 32; off > 0; off >>= 1) nl += __shfl_xor(nl, off);
-        if ((tid & 63) == 0 && nl) atomicAdd(&s_links, nl);
         __syncthreads();
         if (tid == 0) {
-            if (s_links) atomicAdd(&a.cnt->n_links, s_links);
-            if (s_glbrows) atomicAdd(&a.cnt->n_glb_rows, s_glbrows);
+            int b = 0;
+            for (int j = 0; j < nsr; j++) {
+                T.base[j] = b;
+                b += T.n[j];
+            }
+            T.base[nsr] = b;
+            int o = 0;
+            for (int k = 0; k < nown; k++) {
+                T.opre[k] = o;
+                o += T.scan[r0 - s0 + k];
+            }
+            T.opre[nown] = o;
+        }
+        __syncthreads();
+        const int total = T.base[nsr];
+        const int own_total = T.opre[nown];
+        const bool in_lds = total <= kTileCap;
+        if (in_lds) {
+            // fine-bin starts: every bin at or below a row's last bin is set
+            // by exactly one cluster below; the rest mark the row's end
+            for (int k = tid; k < nsr * (kTileFb + 1); k += kLinkBlock) {
+                const int j = k / (kTileFb + 1), f = k - j * (kTileFb + 1);
+                T.fs[j][f] = (int16_t)T.n[j];
+            }
+            __syncthreads();
+            for (int k = tid; k < total; k += kLinkBlock) {
+                int j = 0;
+                while (j + 1 < nsr && T.base[j + 1] <= k) j++;
+                const int q = k - T.base[j];
+                const float2 e = *reinterpret_cast<const float2 *>(a.rec + T.plo[j] + q);
+                T.yt[k] = e;
+                const int f = fine_bin(e.y, G.t0, G.inv_cbw, G.nf) - G.fb0;
+                int fp = -1;
+                if (q > 0) fp = fine_bin(a.rec[T.plo[j] + q - 1].t, G.t0, G.inv_cbw, G.nf) - G.fb0;
+                for (int b = max(fp + 1, 0); b <= min(f, G.nfb); b++) T.fs[j][b] = (int16_t)q;
+            }
+            __syncthreads();
+            tile_links<Enum, true>(a, T, G, si, r0, s0, nown, own_total);
+        } else {
+            tile_links<Enum, false>(a, T, G, si, r0, s0, nown, own_total);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (T.links) atomicAdd(&a.cnt->n_links, T.links);
+            if (!in_lds) atomicAdd(&a.cnt->n_glb_tiles, 1);
         }
     }
 }
 
 void launch_links(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL(k_links<false>, dim3(max(l.grid, 1)), dim3(kSweepBlock), 0, s, a);
+    hipLaunchKernelGGL(k_links<false>, dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
 }
 
 void launch_links_enum(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL(k_links<true>, dim3(max(l.grid, 1)), dim3(kSweepBlock), 0, s, a);
+    hipLaunchKernelGGL(k_links<true>, dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
 }
 
 // Pruned links: per cluster, the best pair among its triplets whose logit

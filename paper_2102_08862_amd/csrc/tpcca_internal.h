@@ -13,9 +13,11 @@ constexpr int kMaxRows = 255;      // rows are uint8
 constexpr int kMaxGap = 2;         // symmetric row gaps handled by the link kernel
 constexpr int kNcbMax = 2048;      // coarse time bins per sector row (upper bound)
 constexpr int kFinePerCb = 4;      // fine bins per coarse bin (row sort)
-constexpr int kMaxStripCb = 32;    // most coarse bins in one neighbour-finding strip
+constexpr int kTileRows = 8;       // own pad rows of a neighbour-finding tile
+constexpr int kMaxTileCb = 16;     // most own coarse bins of a tile
+constexpr int kTileCap = 3072;     // clusters a tile stages in LDS (own rows, +-kMaxGap rows, time halo)
+constexpr int kMaxYCells = 32;     // y cells per pad row in the row order
 constexpr int kChunk = 8192;       // clusters per histogram / scatter work item
-constexpr int kStageCap = 1024;    // clusters of one neighbour row staged in LDS per tile
 constexpr int kScanItems = 2048;   // elements per block of the device-wide scans
 constexpr int kMaxStages = 16;
 constexpr int kLenBins = 256;      // chain lengths are < 256 (rows are uint8)
@@ -84,21 +86,18 @@ struct SiState {
     float t0;                      // time origin of the bins
     float inv_cbw;                 // 1 / coarse bin width
     int32_t ncb;                   // coarse bins per row
-    int32_t nslab;                 // neighbour-finding strips (time slabs) of the sector
-    int32_t tcb;                   // coarse bins per strip
     int32_t n_valid;               // clusters that passed validation
     int32_t sbase;                 // first position of the sector in the sorted space
-    int32_t strip_base;            // first neighbour-finding strip of the sector
     int32_t trk_base, n_tracks;    // first global track slot, number of tracks
     int32_t cl_base, n_cl;         // first entry in the cluster lists, entries
-    int32_t pad[2];
+    int32_t pad[1];
 };
 
 // Device counters of one run (zeroed at the start of the run).
 struct Counters {
     int32_t n_valid_total;
-    int32_t n_strips;
-    int32_t strip_next;      // work queue of the neighbour-finding strips
+    int32_t n_tiles;
+    int32_t tile_next;       // work queue of the neighbour-finding tiles
     int32_t n_links;
     int32_t n_seeds;
     int32_t n_tseeds;
@@ -106,13 +105,36 @@ struct Counters {
     int32_t n_cl;
     int32_t n_invalid;
     int32_t overflow;
-    int32_t n_glb_rows;      // strip rows that did not fit in LDS (served from L2)
+    int32_t n_glb_tiles;     // tiles that did not fit in LDS (served from L2)
     int32_t pool_next;       // triplet pool: slots handed out
     int32_t pool_used;       // triplet pool: slots holding triplets
     int32_t pool_overflow;   // triplets that did not fit the pool
     int32_t n_pruned;        // triplets below the logit threshold
     int32_t pad[1];
 };
+
+// y cells of one pad row: cell = clamp(floor((y - ylo) * inv), 0, ny - 1).
+// Within each fine time bin a row is ordered by (cell, t, id), so a box
+// lookup binary-searches its first cell. Only the speed of the search
+// depends on these values; any choice gives the same links.
+struct YCell {
+    float ylo, inv;
+    int32_t ny, pad;
+};
+
+__device__ inline int ycell_of(const YCell &c, float y) {
+    float v = __fmul_rn(__fsub_rn(y, c.ylo), c.inv);
+    v = fminf(fmaxf(v, -1.0f), (float)c.ny);
+    return min(max((int)floorf(v), 0), c.ny - 1);
+}
+
+// Fine time bin of a time (non-decreasing in t; the row sort and the
+// neighbour tiles use this one definition).
+__device__ inline int fine_bin(float t, float t0, float inv_cbw, int nf) {
+    const float v = __fmul_rn(__fmul_rn(__fsub_rn(t, t0), inv_cbw), (float)kFinePerCb);
+    const float c = fminf(fmaxf(v, -1.0f), (float)nf);
+    return min(max((int)c, 0), nf - 1);
+}
 
 // A cluster in the sorted space: 16 bytes, one load per chain step.
 struct Rec {
@@ -132,7 +154,8 @@ struct KArgs {
     int32_t seed_cap, tseed_cap, trk_cap;
     // constants of the method
     int32_t max_gap, min_track_hits, kf_passes;
-    int32_t strip_target;    // clusters per row that a link-finding strip aims at
+    int32_t n_rb;            // row blocks per sector instance (ceil(n_rows / kTileRows))
+    int32_t tile_budget;     // staged clusters a tile may hold (<= kTileCap)
     float win_y[kMaxGap], win_t[kMaxGap];   // (float)g * win, computed on the host
     float pair_c2;
     float cbw_min;
@@ -143,6 +166,7 @@ struct KArgs {
     // tables
     const float *row_x;      // [n_rows]
     const float *w_tab;      // [n_rows * kMaxGap], (x_r - x_{r-g}) / (x_{r+g} - x_{r-g})
+    const struct YCell *ycell; // [n_rows] y cells of the row order
     // buffers
     const SiDesc *si;
     SiState *st;
@@ -152,6 +176,11 @@ struct KArgs {
     int32_t *rstart;         // [n_si * n_rows] local exclusive prefix
     int32_t *rcur;           // [n_si * n_rows]
     int32_t *coff;           // [n_si * n_rows * (kNcbMax + 1)] global sorted positions
+    int16_t *tstart;         // [n_si * n_rb * kNcbMax] first coarse bin of each tile
+    int32_t *ntile;          // [n_si * n_rb + 1] tiles per (sector instance, row block)
+    int32_t *tile_base;      // [n_si * n_rb + 1] exclusive prefix of ntile
+    int2 *tiles;             // [tile_cap] (si * n_rb + rb, cb0 | cb1 << 16)
+    int32_t tile_cap;
     Rec *tmp;                // [n_in]
     Rec *rec;                // [n_in]
     int2 *link;              // [n_in] (up, dn) as sorted positions
@@ -228,6 +257,7 @@ void launch_grid_hist(const KArgs &a, Launch l, hipStream_t s);
 void launch_grid_setup(const KArgs &a, hipStream_t s);
 void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s);
 void launch_grid_rowsort(const KArgs &a, Launch l, hipStream_t s);
+void launch_tiles(const KArgs &a, hipStream_t s);
 void launch_links(const KArgs &a, Launch l, hipStream_t s);
 void launch_links_enum(const KArgs &a, Launch l, hipStream_t s);
 void launch_select(const KArgs &a, Launch l, hipStream_t s);
@@ -246,6 +276,7 @@ void launch_fit(const KArgs &a, Launch l, hipStream_t s);
 // exclusive scans: out[i] = sum_{j<i} f(in[j]), out[n] = total, *total_dst = total
 void launch_scan_popc(const uint32_t *in, int32_t n, int32_t *out, int32_t *total_dst, int32_t *tmp,
                       hipStream_t s);
+void launch_scan_i32(const int32_t *in, int32_t n, int32_t *out, int32_t *total_dst, int32_t *tmp, hipStream_t s);
 void launch_scan_i32_dev(const int32_t *in, const int32_t *n_dev, int32_t n_cap, int32_t *out,
                          int32_t *total_dst, int32_t *tmp, hipStream_t s);
 void launch_si_tracks(const KArgs &a, hipStream_t s);

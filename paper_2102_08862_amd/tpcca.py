@@ -61,13 +61,14 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("n_clusters", ctypes.c_int64), ("n_links", ctypes.c_int64), ("n_seeds", ctypes.c_int64),
         ("n_tracks", ctypes.c_int64), ("n_track_clusters", ctypes.c_int64), ("n_invalid", ctypes.c_int64),
-        ("n_overflow_rows", ctypes.c_int64), ("n_triplets", ctypes.c_int64), ("n_pruned", ctypes.c_int64),
+        ("n_overflow_tiles", ctypes.c_int64), ("n_triplets", ctypes.c_int64), ("n_pruned", ctypes.c_int64),
         ("n_pool_overflow", ctypes.c_int64), ("mlp_used", ctypes.c_int32),
         ("n_timed_runs", ctypes.c_int64),
         ("n_stages", ctypes.c_int32),
         ("stage_ms", ctypes.c_float * 16),
         ("stage_ms_total", ctypes.c_double * 16),
         ("stage_name", (ctypes.c_char * 24) * 16),
+        ("n_tiles", ctypes.c_int64),
     ]
 
 
@@ -323,8 +324,8 @@ class Tracker:
         s = Stats()
         self._check(self.lib.tpcca_get_stats(self.h, ctypes.byref(s)))
         d = {k: getattr(s, k) for k in ("n_clusters", "n_links", "n_seeds", "n_tracks", "n_track_clusters",
-                                        "n_invalid", "n_overflow_rows", "n_triplets", "n_pruned",
-                                        "n_pool_overflow", "mlp_used")}
+                                        "n_invalid", "n_overflow_tiles", "n_triplets", "n_pruned",
+                                        "n_pool_overflow", "mlp_used", "n_tiles")}
         d["stage_ms"] = {s.stage_name[i].value.decode(): s.stage_ms[i] for i in range(s.n_stages)}
         d["n_timed_runs"] = s.n_timed_runs
         d["stage_ms_total"] = {s.stage_name[i].value.decode(): s.stage_ms_total[i] for i in range(s.n_stages)}

@@ -1,6 +1,6 @@
 """Graph replay and launch shapes: a run captured once in a HIP graph and
 replayed several times (with eager work and synchronisations between the
-replays) gives the eager results every time; launch shapes and strip widths
+replays) gives the eager results every time; launch shapes and tile budgets
 chosen by the autotuner never change a result."""
 import numpy as np
 import pytest
@@ -63,7 +63,7 @@ def test_launch_shapes_do_not_change_results(tp):
     f = base.load_frame_packed(fr)
     base.run(sync=True)
     ref = _outputs(base, f, sectors)
-    for stage, bpc, param in ((5, 1, 96), (5, 2, 512), (4, 1, 0), (1, 2, 0), (6, 1, 0), (7, 2, 0), (10, 1, 0),
+    for stage, bpc, param in ((5, 1, 256), (5, 2, 1024), (5, 4, 3072), (4, 1, 0), (1, 2, 0), (6, 1, 0), (7, 2, 0), (10, 1, 0),
                               (11, 4, 0), (3, 1, 0), (8, 1, 0)):
         t = tp.Tracker()
         t.set_launch(stage, bpc, param)

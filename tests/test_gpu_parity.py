@@ -102,8 +102,9 @@ def test_degenerate_sectors(tp, x):
 
 
 def test_dense_rows_overflow_lds(tp, x):
-    """A hot spot with far more clusters per strip row than an LDS slot
-    holds: those rows are read from global memory with the same predicates."""
+    """A hot spot with far more clusters per coarse bin than a neighbour tile
+    can stage in LDS: those tiles are searched in global memory with the
+    same predicates."""
     rng = np.random.default_rng(11)
     n = 12000
     row = rng.integers(20, 26, n).astype(np.uint8)
@@ -114,7 +115,7 @@ def test_dense_rows_overflow_lds(tp, x):
     row = np.concatenate([row, r0]); y = np.concatenate([y, y0]); t = np.concatenate([t, t0])
     print("case dense", len(row), flush=True)
     trk, f = _one_sector(tp, row, y, t, min_track_hits=3)
-    assert trk.stats()["n_overflow_rows"] > 0
+    assert trk.stats()["n_overflow_tiles"] > 0
     compare_sector(trk, f, 0, row, y, t, oracle_cfg(x, min_track_hits=3), check_params=False)
 
 
