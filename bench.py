@@ -45,6 +45,10 @@ STAGE_BYTES = {
     "fit": lambda s: 9 * s["n_track_clusters"] + 128 * s["n_tracks"],
 }
 
+# the kernel that dominates each stage (the stage's other launches are small)
+STAGE_KERNEL = {"hist": "k_hist", "scatter": "k_scatter", "rowsort": "k_rowsort", "links": "k_links",
+                "seeds": "k_seeds", "chainlen": "k_chainlen", "emit": "k_emit", "fit": "k_fit"}
+
 WORKLOADS = {
     "frame_10ms": "whole 10 ms TPC time frame: 36 sectors x 152 rows, 500 Pb-Pb collisions at 50 kHz "
                   "(multiplicity Exp(2000) truncated at 15000, |eta|<0.9, pT=0.1+Exp(0.6) GeV), 0.5 T, "
@@ -236,8 +240,11 @@ def main():
     dom = max((k for k in stage if k in STAGE_BYTES), key=lambda k: stage[k])
     b = STAGE_BYTES[dom](st)
     achieved = b / 1e9 / (stage[dom] / 1e3)
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+    from paper_2102_08862_amd import traffic as trf
+    kname = STAGE_KERNEL.get(dom)
+    tb = trf.lookup(os.path.join(ROOT, "profiles", "traffic_%s.txt" % args.workload), kname) if kname else None
+    roof = {"kernel": kname or dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": round(tb) if tb else None,
             "bytes_per_launch": int(b), "avg_ms": round(stage[dom], 4)}
 
     pruned = None

@@ -197,6 +197,12 @@ tpcca_status tpcca_set_graph(tpcca_ctx *ctx, int32_t on);
    Results do not depend on these settings. */
 tpcca_status tpcca_set_launch(tpcca_ctx *ctx, int32_t stage, int32_t blocks_per_cu, int32_t param);
 
+/* Measurement helper (not part of the method): copy `bytes` (a multiple of
+   16) from device src to device dst with a plain streaming kernel on the
+   context's stream. Its hardware-counter readings for a known size calibrate
+   the HBM traffic counters of the tracker's kernels. */
+tpcca_status tpcca_copy(tpcca_ctx *ctx, const void *src, void *dst, size_t bytes);
+
 /* Enable (1) or disable (0) per-stage device timing with HIP events; either
    call also resets the accumulated stage times. */
 tpcca_status tpcca_set_timing(tpcca_ctx *ctx, int32_t on);

@@ -609,8 +609,8 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     launch_grid_scatter(a, c->lc[3], s);
     mark(st++);
     launch_grid_rowsort(a, c->lc[4], s);
+    launch_tiles(a, s);  // tile partition of the neighbour search (part of the search grid)
     mark(st++);
-    launch_tiles(a, s);
     if (a.use_mlp) {
         launch_links_enum(a, c->lc[5], s);
         launch_mlp_infer(a.mlp, a.pfeat, &cnt->pool_next, a.pool_cap, a.pz, c->n_cu * 8, s);
@@ -994,6 +994,15 @@ static MlpDev mlp_dev(tpcca_ctx *c) {
     W.b2 = (const float *)(c->mlp + MlpState::b2);
     W.b3 = (const float *)(c->mlp + MlpState::b3);
     return W;
+}
+
+tpcca_status tpcca_copy(tpcca_ctx *c, const void *src, void *dst, size_t bytes) {
+    if (!c || (bytes && (!src || !dst)) || (bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15))
+        return fail(c, TPCCA_ERR_INVALID_ARG, "copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+    launch_copy(src, dst, (int64_t)(bytes / 16), std::max(1, c->n_cu) * 8, c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "copy launch");
+    return TPCCA_OK;
 }
 
 tpcca_status tpcca_mlp_infer(tpcca_ctx *c, const uint16_t *x, int64_t n, float *z) {

@@ -31,6 +31,17 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
     for (int64_t k = (n4 << 2) + i; k < n; k += stride) p[k] = v;
 }
 
+// Plain streaming copy (16-byte vectors), the reference for traffic counters.
+__global__ __launch_bounds__(256) void k_copy(const int4 *__restrict__ src, int4 *__restrict__ dst, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+void launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStream_t s) {
+    if (n16 <= 0) return;
+    hipLaunchKernelGGL(k_copy, dim3(max(grid, 1)), dim3(256), 0, s, (const int4 *)src, (int4 *)dst, n16);
+}
+
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n <= 0) return;
     int64_t blocks = ((n >> 2) + 255) / 256;

@@ -253,6 +253,7 @@ struct Launch {
 };
 
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+void launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStream_t s);
 void launch_grid_hist(const KArgs &a, Launch l, hipStream_t s);
 void launch_grid_setup(const KArgs &a, hipStream_t s);
 void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s);
