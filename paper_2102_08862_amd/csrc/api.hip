@@ -466,7 +466,9 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.clusters = b.take(sizeof(int32_t) * N);
     L.assign = b.take(sizeof(int32_t) * N);
     c->pruned_run = c->cfg.use_mlp != 0;
-    L.pool_cap = c->pruned_run ? (int64_t)c->cfg.pool_per_cluster * N + kPoolChunk : 0;
+    // every workgroup of the neighbour search may leave up to one partly used
+    // chunk of the pool behind
+    L.pool_cap = c->pruned_run ? (int64_t)c->cfg.pool_per_cluster * N + (int64_t)(c->lc[5].grid + 1) * kPoolChunk : 0;
     if (L.pool_cap > (int64_t)0x7fff0000) L.pool_cap = 0x7fff0000;
     L.pfeat = b.take(sizeof(uint16_t) * kMlpInP * L.pool_cap);
     L.pd = b.take(sizeof(int32_t) * L.pool_cap);

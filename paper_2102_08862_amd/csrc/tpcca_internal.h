@@ -26,7 +26,7 @@ constexpr int kMlpInP = 16;        // padded to the MFMA K of 16
 constexpr int kMlpH = 64;          // hidden units per layer
 constexpr int kMlpNParam = kMlpH * kMlpInP + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH + 1;
 constexpr int kMlpMaxBatch = 8192; // largest training minibatch
-constexpr int kPoolChunk = 4096;   // triplet-pool slots reserved per grab
+constexpr int kPoolChunk = 1024;   // triplet-pool slots reserved per grab
 
 // Device view of the triplet network (BF16 weights, FP32 biases).
 struct MlpDev {
