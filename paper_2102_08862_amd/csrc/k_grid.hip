@@ -215,48 +215,62 @@ void launch_grid_setup(const KArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_si_prefix, dim3(1), dim3(1024), 0, s, a);
 }
 
+// Scatter into row segments: a workgroup takes a run of up to kScatterRun
+// consecutive chunks of one sector (the run is cut where the sector
+// changes), ranks its clusters per row in LDS and grabs one range per row
+// of the segment cursor, so each row receives one contiguous run of records.
+constexpr int kScatterRun = 8;
+
 __global__ __launch_bounds__(256) void k_scatter(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ int32_t h[kMaxRows], gb[kMaxRows];
     const int R = a.n_rows;
-    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
-        const int si = a.chunk[2 * c], start = a.chunk[2 * c + 1];
-        const SiDesc d = a.si[si];
-        const int end = min(start + kChunk, d.n);
-        const int sbase = a.st[si].sbase;
-        for (int r = threadIdx.x; r < R; r += blockDim.x) h[r] = 0;
-        __syncthreads();
-        for (int i = start + threadIdx.x; i < end; i += blockDim.x) {
-            const int r = d.row[i];
-            if (valid_cluster(r, d.y[i], d.t[i], R)) atomicAdd(&h[r], 1);
-        }
-        __syncthreads();
-        for (int r = threadIdx.x; r < R; r += blockDim.x) {
-            const int k = h[r];
-            gb[r] = k ? sbase + atomicAdd(&a.rcur[si * R + r], k) : 0;
-            h[r] = 0;
-        }
-        __syncthreads();
-        for (int i = start + threadIdx.x; i < end; i += blockDim.x) {
-            const int r = d.row[i];
-            const float y = d.y[i], t = d.t[i];
-            if (valid_cluster(r, y, t, R)) {
-                const int slot = gb[r] + atomicAdd(&h[r], 1);
-                Rec e;
-                e.y = y;
-                e.t = t;
-                e.id = i;
-                e.sr = (si << 8) | r;
-                a.tmp[slot] = e;
+    for (int run = blockIdx.x; run * kScatterRun < a.n_chunks; run += gridDim.x) {
+        const int c_end = min((run + 1) * kScatterRun, a.n_chunks);
+        int c = run * kScatterRun;
+        while (c < c_end) {
+            const int si = a.chunk[2 * c];
+            int c2 = c + 1;
+            while (c2 < c_end && a.chunk[2 * c2] == si) c2++;
+            const SiDesc d = a.si[si];
+            const int sbase = a.st[si].sbase;
+            const int i0 = a.chunk[2 * c + 1];
+            const int i1 = min(a.chunk[2 * (c2 - 1) + 1] + kChunk, d.n);
+            for (int r = threadIdx.x; r < R; r += blockDim.x) h[r] = 0;
+            __syncthreads();
+            for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+                const int r = d.row[i];
+                if (valid_cluster(r, d.y[i], d.t[i], R)) atomicAdd(&h[r], 1);
             }
+            __syncthreads();
+            for (int r = threadIdx.x; r < R; r += blockDim.x) {
+                const int k = h[r];
+                gb[r] = k ? sbase + atomicAdd(&a.rcur[si * R + r], k) : 0;
+                h[r] = 0;
+            }
+            __syncthreads();
+            for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+                const int r = d.row[i];
+                const float y = d.y[i], t = d.t[i];
+                if (valid_cluster(r, y, t, R)) {
+                    const int slot = gb[r] + atomicAdd(&h[r], 1);
+                    Rec e;
+                    e.y = y;
+                    e.t = t;
+                    e.id = i;
+                    e.sr = (si << 8) | r;
+                    a.tmp[slot] = e;
+                }
+            }
+            __syncthreads();
+            c = c2;
         }
-        __syncthreads();
     }
 }
 
 void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s) {
-    if (a.n_chunks > 0)
-        hipLaunchKernelGGL(k_scatter, dim3(min(l.grid, a.n_chunks)), dim3(256), 0, s, a);
+    const int runs = (a.n_chunks + kScatterRun - 1) / kScatterRun;
+    if (runs > 0) hipLaunchKernelGGL(k_scatter, dim3(min(l.grid, runs)), dim3(256), 0, s, a);
 }
 
 // order inside a fine time bin: (y cell, t, id)
@@ -328,11 +342,13 @@ __device__ void sort_bin(Rec *__restrict__ p, int k, const YCell &yc) {
 
 constexpr int kFineMax = kNcbMax * kFinePerCb;
 constexpr int kSortBlock = 512;
+constexpr int kSortWin = 2048;   // records of whole fine bins ordered in LDS at a time
 
 __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ int32_t fh[kFineMax];
     __shared__ int32_t part[kSortBlock];
+    __shared__ Rec win[kSortWin];
     const int R = a.n_rows;
     const int nseg = a.n_si * R;
     const int tid = threadIdx.x, bd = blockDim.x;
@@ -381,12 +397,53 @@ __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
         }
         __threadfence_block();
         __syncthreads();
-        // fh[b] now holds the end of fine bin b
+        // fh[b] now holds the end of fine bin b. Order each bin by (y cell,
+        // t, id): windows of whole bins holding at most kSortWin records are
+        // loaded into LDS, each bin is sorted there by one thread, and the
+        // window is written back (coalesced); a single bin over kSortWin is
+        // sorted in place in global memory.
         const YCell yc = a.ycell[seg - si * R];
-        for (int b = tid; b < nf; b += bd) {
-            const int blo = b ? fh[b - 1] : 0;
-            const int bhi = fh[b];
-            if (bhi - blo > 1) sort_bin(a.rec + start + blo, bhi - blo, yc);
+        int b0 = 0;
+        while (b0 < nf) {
+            const int r0 = b0 ? fh[b0 - 1] : 0;
+            // last bin end within the window: fh is non-decreasing
+            int lo_b = b0, hi_b = nf - 1;
+            while (lo_b < hi_b) {
+                const int m = (lo_b + hi_b + 1) >> 1;
+                if (fh[m] - r0 <= kSortWin) lo_b = m;
+                else hi_b = m - 1;
+            }
+            int b1 = lo_b + 1;
+            if (fh[b0] - r0 > kSortWin) {
+                b1 = b0 + 1;
+                if (tid == 0) sort_bin(a.rec + start + r0, fh[b0] - r0, yc);
+                __threadfence_block();
+                __syncthreads();
+                b0 = b1;
+                continue;
+            }
+            const int r1 = fh[b1 - 1];
+            for (int k = tid; k < r1 - r0; k += bd) win[k] = a.rec[start + r0 + k];
+            __syncthreads();
+            for (int b = b0 + tid; b < b1; b += bd) {
+                const int lo = (b ? fh[b - 1] : 0) - r0, hi = fh[b] - r0;
+                for (int i = lo + 1; i < hi; i++) {
+                    const Rec e = win[i];
+                    const int ce = ycell_of(yc, e.y);
+                    int j = i - 1;
+                    while (j >= lo) {
+                        const Rec f = win[j];
+                        if (!rec_less(ce, e.t, e.id, ycell_of(yc, f.y), f.t, f.id)) break;
+                        win[j + 1] = f;
+                        j--;
+                    }
+                    win[j + 1] = e;
+                }
+            }
+            __syncthreads();
+            for (int k = tid; k < r1 - r0; k += bd) a.rec[start + r0 + k] = win[k];
+            __syncthreads();
+            b0 = b1;
         }
         __threadfence_block();
         __syncthreads();
