@@ -78,7 +78,7 @@ typedef struct {
     float s_max;               /* |sin phi| at which a propagation fails, 0.999 */
     int32_t use_mlp;           /* 1: prune candidate triplets with the loaded network, 0 */
     float mlp_logit_threshold; /* triplets with logit below this are pruned, 0 */
-    int32_t pool_per_cluster;  /* triplet-pool slots per input cluster in pruned runs, 3 */
+    int32_t pool_per_cluster;  /* triplet-pool slots per input cluster in pruned runs, 8 */
 } tpcca_config;
 
 /* One fitted track. Tracks of a sector are numbered 0..T-1 in ascending
@@ -292,6 +292,17 @@ tpcca_status tpcca_mlp_grad(tpcca_ctx *ctx, const uint16_t *x_dev, const float *
    may be NULL. Enqueued on the stream. */
 tpcca_status tpcca_mlp_train_step(tpcca_ctx *ctx, const uint16_t *x_dev, const float *y_dev, int64_t n,
                                   const tpcca_mlp_hparams *hp, float *loss_dev);
+
+/* Training examples from the last pruned run (all loaded frames), built on
+   the device: each triplet is kept with probability `keep` (decided by a
+   hash of seed, sector, input index and the triplet's rank in its cluster,
+   so the subset is reproducible) and labelled 1 if the run's cleaned links
+   put its down and up clusters directly below and above its middle cluster
+   and that cluster is on a track, else 0. feat_dev receives [n][16] BF16
+   features (16-byte aligned), label_dev n floats, in arbitrary order;
+   *n_out = kept triplets (CAPACITY if above cap). Synchronous. */
+tpcca_status tpcca_triplet_samples(tpcca_ctx *ctx, float keep, uint64_t seed, uint16_t *feat_dev, float *label_dev,
+                                   int64_t cap, int64_t *n_out);
 
 /* Triplets of the last pruned run for one (frame, sector), ordered by the
    input index of the middle cluster, then gap, then down and up input index:

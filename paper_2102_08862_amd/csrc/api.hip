@@ -166,7 +166,7 @@ tpcca_status tpcca_config_default(tpcca_config *out) {
     c.s_max = 0.999f;
     c.use_mlp = 0;
     c.mlp_logit_threshold = 0.0f;
-    c.pool_per_cluster = 3;
+    c.pool_per_cluster = 8;
     *out = c;
     return TPCCA_OK;
 }
@@ -1070,6 +1070,24 @@ tpcca_status tpcca_mlp_train_step(tpcca_ctx *c, const uint16_t *x, const float *
                                   const tpcca_mlp_hparams *hp, float *loss) {
     if (!hp) return TPCCA_ERR_INVALID_ARG;
     return mlp_step(c, x, y, n, 0.f, hp, nullptr, loss);
+}
+
+tpcca_status tpcca_triplet_samples(tpcca_ctx *c, float keep, uint64_t seed, uint16_t *feat_dev, float *label_dev,
+                                   int64_t cap, int64_t *n_out) {
+    if (!c || !n_out || !(keep >= 0.f && keep <= 1.f) || cap < 0 || (cap > 0 && (!feat_dev || !label_dev)))
+        return fail(c, TPCCA_ERR_INVALID_ARG, "keep in [0, 1], cap >= 0, output buffers for cap > 0");
+    if (((uintptr_t)feat_dev & 15)) return fail(c, TPCCA_ERR_INVALID_ARG, "feature buffer must be 16-byte aligned");
+    if (!c->have_results || !c->args.use_mlp || !c->arena) return fail(c, TPCCA_ERR_STATE, "no pruned run to sample");
+    unsigned long long *cnt_dev = nullptr;
+    HIPCHK(c, hipMallocAsync((void **)&cnt_dev, sizeof(unsigned long long), c->stream));
+    HIPCHK(c, hipMemsetAsync(cnt_dev, 0, sizeof(unsigned long long), c->stream));
+    launch_samples(c->args, keep, seed, feat_dev, label_dev, cap, cnt_dev, std::max(1, c->n_cu) * 8, c->stream);
+    unsigned long long h = 0;
+    HIPCHK(c, hipMemcpyAsync(&h, cnt_dev, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipFreeAsync(cnt_dev, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *n_out = (int64_t)h;
+    return (int64_t)h > cap ? fail(c, TPCCA_ERR_CAPACITY, "sample buffer too small") : TPCCA_OK;
 }
 
 tpcca_status tpcca_get_triplets(tpcca_ctx *c, int32_t frame, int32_t sector, int32_t *tri, uint16_t *feat, float *z,

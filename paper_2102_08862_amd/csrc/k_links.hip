@@ -601,16 +601,14 @@ __global__ __launch_bounds__(256) void k_select(KArgs a) {
         int bu = -1, bd = -1;
         if (off >= 0) {
             const int n1 = a.hn1[p], n2 = a.hn2[p];
+            for (int k = off; k < off + n1 + n2; k++) pruned += !(a.pz[k] >= th);
             for (int g = 0; g < 2 && bu < 0; g++) {
                 const int k0 = off + (g ? n1 : 0), k1 = k0 + (g ? n2 : n1);
                 bool found = false;
                 float bc = 0.f;
                 int biu = 0, bid = 0;
                 for (int k = k0; k < k1; k++) {
-                    if (!(a.pz[k] >= th)) {
-                        pruned++;
-                        continue;
-                    }
+                    if (!(a.pz[k] >= th)) continue;
                     const float c = a.pc[k];
                     const int pu = a.pu[k], pd = a.pd[k];
                     const int idu = a.rec[pu].id, idd = a.rec[pd].id;
@@ -640,6 +638,80 @@ __global__ __launch_bounds__(256) void k_select(KArgs a) {
 
 void launch_select(const KArgs &a, Launch l, hipStream_t s) {
     hipLaunchKernelGGL(k_select, dim3(max(l.grid, 1)), dim3(256), 0, s, a);
+}
+
+// Training examples from the last pruned run: every triplet is kept with
+// probability `keep` (a hash of (seed, sector instance, input index, rank of
+// the triplet within its cluster), so the subset does not depend on
+// scheduling) and labelled 1 if the run's cleaned links put its down and up
+// clusters directly below and above its middle cluster and that cluster is
+// on a track, else 0. Output order is arbitrary.
+__device__ inline uint64_t mix64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_samples(KArgs a, float keep, uint64_t seed, uint16_t *feat, float *label,
+                                                 int64_t cap, unsigned long long *n_out) {
+    const int n = min(a.cnt->n_valid_total, a.n_in);
+    const uint64_t thr = keep >= 1.f ? ~0ull : (uint64_t)((double)keep * 18446744073709551616.0);
+    const int lane = threadIdx.x & 63;
+    for (int p0 = blockIdx.x * blockDim.x; p0 < n; p0 += gridDim.x * blockDim.x) {
+        const int p = p0 + threadIdx.x;
+        int off = -1, nt = 0;
+        Rec e{};
+        int2 l = make_int2(-1, -1);
+        bool in_trk = false;
+        if (p < n) {
+            off = a.hoff[p];
+            nt = off >= 0 ? a.hn1[p] + a.hn2[p] : 0;
+            if (nt) {
+                e = a.rec[p];
+                l = a.link[p];
+                in_trk = a.assign[a.si[e.sr >> 8].in_base + e.id] >= 0;
+            }
+        }
+        // lanes walk their triplets in lock step; one atomic per wave and step
+        int mx = nt;
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+        for (int j = 0; j < mx; j++) {
+            bool take = false;
+            float lab = 0.f;
+            int k = 0;
+            if (j < nt) {
+                k = off + j;
+                const uint64_t h = mix64(seed ^ mix64(((uint64_t)(e.sr >> 8) << 40) ^ ((uint64_t)e.id << 8) ^ (uint64_t)j));
+                take = h < thr;
+                if (take) {
+                    const int d = a.pd[k], u = a.pu[k];
+                    lab = (in_trk && l.y == d && l.x == u && a.link[d].x == p && a.link[u].y == p) ? 1.f : 0.f;
+                }
+            }
+            const uint64_t m = __ballot(take);
+            if (!m) continue;
+            const int first = __ffsll((unsigned long long)m) - 1;
+            unsigned long long base = 0;
+            if (lane == first) base = atomicAdd(n_out, (unsigned long long)__popcll(m));
+            base = __shfl(base, first);
+            if (take) {
+                const int64_t o = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
+                if (o < cap) {
+                    const uint4 *src = reinterpret_cast<const uint4 *>(a.pfeat + (int64_t)k * kMlpInP);
+                    uint4 *dst = reinterpret_cast<uint4 *>(feat + o * kMlpInP);
+                    dst[0] = src[0];
+                    dst[1] = src[1];
+                    label[o] = lab;
+                }
+            }
+        }
+    }
+}
+
+void launch_samples(const KArgs &a, float keep, uint64_t seed, uint16_t *feat, float *label, int64_t cap,
+                    unsigned long long *n_out, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_samples, dim3(max(grid, 1)), dim3(256), 0, s, a, keep, seed, feat, label, cap, n_out);
 }
 
 }  // namespace tpcca

@@ -262,6 +262,8 @@ void launch_tiles(const KArgs &a, hipStream_t s);
 void launch_links(const KArgs &a, Launch l, hipStream_t s);
 void launch_links_enum(const KArgs &a, Launch l, hipStream_t s);
 void launch_select(const KArgs &a, Launch l, hipStream_t s);
+void launch_samples(const KArgs &a, float keep, uint64_t seed, uint16_t *feat, float *label, int64_t cap,
+                    unsigned long long *n_out, int grid, hipStream_t s);
 void launch_mlp_infer(const MlpDev &W, const uint16_t *X, const int32_t *n_dev, int32_t n_cap, float *z, int grid,
                       hipStream_t s);
 void launch_mlp_train(const MlpTrainArgs &t, hipStream_t s);

@@ -11,7 +11,7 @@ choices here are this project's:
   - label: 1 if the plain tracker's cleaned links put `down` directly below
     and `up` directly above `cluster` and `cluster` sits on a track, else 0;
   - sampling: a uniform random share of every training frame's triplets
-    (stratified by frame and sector);
+    (stratified by frame), kept and labelled on the device;
   - loss: binary cross-entropy on the logit, positives weighted by
     N_neg / N_pos; optimiser AdamW (lr 1e-3, betas 0.9/0.999, weight decay
     1e-4), batch 4096, FP32 master weights with BF16 copies, all on the GPU
@@ -123,27 +123,30 @@ def prefetch(workload, seeds, n_threads):
 
 
 def collect(trk, seeds, per_frame, seed, n_threads):
-    """Training set from the given 1 ms slice seeds: returns host arrays
-    (feat uint16[m, 16], label float32[m]) and counts."""
-    rng = np.random.default_rng(seed)
-    X, Y, tot, pos = [], [], 0, 0
+    """Training set from the given 1 ms slice seeds, sampled and labelled on
+    the device: returns device tensors (feat int16 [m, 16], label float [m])
+    and counts (triplets seen, positives among the kept)."""
+    import torch
+    X, Y, tot = [], [], 0
     trk.set_pruning(True, -1e30)
     for sd, fr in prefetch("slice_1ms", seeds, n_threads):
         trk.clear_frames()
-        f = trk.load_frame_packed(fr)
+        trk.load_frame_packed(fr)
         trk.run(sync=True)
         st = trk.stats()
         if st["n_pool_overflow"]:
             raise RuntimeError("triplet pool overflow on seed %d" % sd)
-        n_est = max(1, st["n_triplets"])
-        x, y, n_all, n_pos = frame_triplets(trk, f, len(fr.rows), min(1.0, per_frame / n_est), rng)
-        X.append(x)
-        Y.append(y)
+        n_all = max(1, st["n_triplets"])
+        keep = min(1.0, per_frame / n_all)
+        x, y = trk.triplet_samples(keep, seed * 1000003 + sd, int(per_frame * 1.2) + 4096)
+        X.append(x.clone())
+        Y.append(y.clone())
         tot += n_all
-        pos += n_pos
-        log("  seed %d: %d clusters, %d triplets (%.1f%% positive), kept %d"
-            % (sd, fr.n_clusters, n_all, 100.0 * n_pos / max(1, n_all), len(y)))
-    return np.concatenate(X), np.concatenate(Y), tot, pos
+        log("  seed %d: %d clusters, %d triplets (%.2f per cluster), kept %d (%.1f%% positive)"
+            % (sd, fr.n_clusters, n_all, n_all / max(1, fr.n_clusters), len(y), 100.0 * float(y.mean().item())))
+    X = torch.cat(X)
+    Y = torch.cat(Y)
+    return X, Y, tot, int(Y.sum().item())
 
 
 # ------------------------------------------------------------------ training
@@ -279,6 +282,7 @@ def select_theta(trk, vset, z_sample, max_loss=0.004, log=log):
 
 
 def matched_pair_cut(make_tracker, vset, target_fraction, base_c2=0.2, log=log):
+    import torch
     """Tighter pair cut C2' whose accepted triplets are (1 - target_fraction)
     of those at base_c2, by bisection; counts come from pruned runs with the
     threshold at -inf (enumeration only)."""
@@ -288,6 +292,7 @@ def matched_pair_cut(make_tracker, vset, target_fraction, base_c2=0.2, log=log):
         t.set_pruning(True, -1e30)
         n = vset.evaluate(t, quality=False)["triplets"]
         del t
+        torch.cuda.empty_cache()
         return n
     n0 = count(base_c2)
     lo, hi = 0.0, base_c2
@@ -322,6 +327,7 @@ def main(argv=None):
     x_row, _ = synth.geometry()
 
     def make_tracker(**kw):
+        kw.setdefault("pool_per_cluster", 12)
         return tpcca.Tracker(row_x=x_row, **kw)
 
     trk = make_tracker()
@@ -339,12 +345,13 @@ def main(argv=None):
         t0 = time.perf_counter()
         X, Y, tot, pos = collect(trk, tr_seeds, args.samples / len(tr_seeds), args.seed, nth)
         log("  %d of %d triplets sampled (%.1f%% positive) in %.0f s"
-            % (len(Y), tot, 100.0 * pos / max(1, tot), time.perf_counter() - t0))
+            % (len(Y), tot, 100.0 * pos / max(1, len(Y)), time.perf_counter() - t0))
         # 2% held out for a loss check
-        rng = np.random.default_rng(args.seed + 1)
-        ho = rng.random(len(Y)) < 0.02
-        xt, yt = to_device(X[~ho], Y[~ho])
-        xh, yh = to_device(X[ho], Y[ho])
+        g = torch.Generator(device="cuda")
+        g.manual_seed(args.seed + 1)
+        ho = torch.rand(len(Y), device="cuda", generator=g) < 0.02
+        xt, yt = X[~ho].contiguous(), Y[~ho].contiguous()
+        xh, yh = X[ho].contiguous(), Y[ho].contiguous()
         del X, Y
         trk.mlp_load(init_params(args.seed))
         z0 = logits(trk, xh)
@@ -354,7 +361,7 @@ def main(argv=None):
         zh = logits(trk, xh)
         acc = float(((zh > 0).float() == yh).float().mean().item())
         meta = {"train_seeds": [tr_seeds[0], tr_seeds[-1]], "triplets_seen": int(tot), "samples": int(xt.shape[0]),
-                "positive_fraction": pos / max(1, tot), "pos_weight": pw, "epochs": args.epochs, "batch": 4096,
+                "positive_fraction": float(yt.mean().item()), "pos_weight": pw, "epochs": args.epochs, "batch": 4096,
                 "lr": 1e-3, "weight_decay": 1e-4, "seed": args.seed, "train_s": round(train_s, 1),
                 "heldout_bce_init": bce(z0, yh, pw), "heldout_bce": bce(zh, yh, pw), "heldout_accuracy": acc,
                 "loss_history": hist[:: max(1, len(hist) // 50)]}
@@ -394,6 +401,7 @@ def main(argv=None):
     hand_trk = make_tracker(pair_c2=c2)
     hand = ev.evaluate(hand_trk, timing=True)
     del hand_trk
+    torch.cuda.empty_cache()
     rnd = make_tracker()
     rnd.mlp_load(init_params(args.seed + 100))
     rnd.set_pruning(True, -1e30)

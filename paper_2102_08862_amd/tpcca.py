@@ -80,7 +80,7 @@ EXPORTS = [
     "tpcca_get_stats", "tpcca_get_tracks", "tpcca_get_track_clusters", "tpcca_get_assignment",
     "tpcca_get_links", "tpcca_mlp_state_bytes", "tpcca_mlp_attach", "tpcca_mlp_load", "tpcca_mlp_fetch",
     "tpcca_mlp_infer", "tpcca_mlp_grad", "tpcca_mlp_train_step", "tpcca_get_triplets", "tpcca_set_graph",
-    "tpcca_set_launch", "tpcca_set_pruning", "tpcca_copy",
+    "tpcca_set_launch", "tpcca_set_pruning", "tpcca_copy", "tpcca_triplet_samples",
 ]
 
 MLP_NPARAM = 5313
@@ -133,6 +133,7 @@ def load_library(path: str = LIB_PATH):
         "tpcca_set_launch": [P, I32, I32, I32],
         "tpcca_set_pruning": [P, I32, ctypes.c_float],
         "tpcca_copy": [P, P, P, SZ],
+        "tpcca_triplet_samples": [P, ctypes.c_float, ctypes.c_uint64, P, P, I64, ctypes.POINTER(I64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -420,6 +421,18 @@ class Tracker:
         self._check(self.lib.tpcca_mlp_train_step(self.h, ctypes.c_void_p(x_dev.data_ptr()),
                                                   ctypes.c_void_p(y_dev.data_ptr()), x_dev.shape[0], ctypes.byref(hp),
                                                   ctypes.c_void_p(loss_dev.data_ptr()) if loss_dev is not None else None))
+
+    def triplet_samples(self, keep: float, seed: int, cap: int):
+        """Labelled training triplets of the last pruned run, on the device:
+        (feat int16 [n, 16] BF16 bits, label float32 [n])."""
+        torch = self._torch
+        feat = torch.empty((max(cap, 1), 16), dtype=torch.int16, device="cuda")
+        lab = torch.empty(max(cap, 1), dtype=torch.float32, device="cuda")
+        n = ctypes.c_int64()
+        self._check(self.lib.tpcca_triplet_samples(self.h, float(keep), int(seed) & 0xffffffffffffffff,
+                                                   ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(lab.data_ptr()),
+                                                   cap, ctypes.byref(n)))
+        return feat[:n.value], lab[:n.value]
 
     def triplets(self, frame, sector):
         """(tri int32[n,4] = (down, cluster, up, gap) input ids, feat uint16[n,16], z float32[n])."""

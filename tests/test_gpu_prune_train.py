@@ -36,3 +36,29 @@ def test_labels_match_chains_and_training_separates():
     auc = (np.searchsorted(np.sort(zn), zp).sum()) / (len(zp) * len(zn))
     print("bce %.4f -> %.4f, auc %.4f" % (l0, l1, auc))
     assert l1 < 0.7 * l0 and auc > 0.9
+
+
+def test_device_samples_match_host_labels():
+    """The device sampler with keep = 1 returns every triplet with the same
+    label as the host-side labelling; keep < 1 returns a reproducible subset
+    of about that share."""
+    from paper_2102_08862_amd import tpcca
+    fr = synth.generate("sector_300", seed=32)
+    x, _ = synth.geometry()
+    trk = tpcca.Tracker(row_x=x)
+    trk.mlp_load(prune_train.init_params(2))
+    trk.set_pruning(True, -1e30)
+    f = trk.load_frame(fr, sectors=[0])
+    trk.run(sync=True)
+    xs, ys, n_all, n_pos = prune_train.frame_triplets(trk, f, 1, 1.0, np.random.default_rng(0))
+    fd, ld = trk.triplet_samples(1.0, 7, n_all + 10)
+    assert len(ld) == n_all and int(ld.sum().item()) == n_pos
+
+    def rows(feat, lab):
+        a = np.concatenate([feat.view(np.uint16).astype(np.int64), lab[:, None].astype(np.int64)], axis=1)
+        return a[np.lexsort(a.T[::-1])]
+    assert np.array_equal(rows(fd.cpu().numpy(), ld.cpu().numpy()), rows(xs, ys))
+    f1, l1 = trk.triplet_samples(0.25, 9, n_all)
+    f2, l2 = trk.triplet_samples(0.25, 9, n_all)
+    assert np.array_equal(rows(f1.cpu().numpy(), l1.cpu().numpy()), rows(f2.cpu().numpy(), l2.cpu().numpy()))
+    assert abs(len(l1) / n_all - 0.25) < 0.02
