@@ -34,7 +34,7 @@ struct Layout {
     size_t total = 0;
     size_t inputs, si, st, cnt, chunk, row_x, w_tab, ycell;
     size_t rcnt, rstart, rcur, coff;
-    size_t tstart, ntile, tile_base, tiles;
+    size_t tstart, ntile, tile_base, tiles, glb_tiles;
     int64_t tile_cap = 0;
     size_t tmp, rec, link;
     size_t seeds, tseed, tlen, tslot;
@@ -442,6 +442,7 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.tile_cap = NW * kNcbMax;
     if (L.tile_cap > (int64_t)0x7fff0000) return fail(c, TPCCA_ERR_INVALID_ARG, "too many sectors in one run");
     L.tiles = b.take(sizeof(int2) * L.tile_cap);
+    L.glb_tiles = b.take(sizeof(int32_t) * L.tile_cap);
     // the row-grouped staging buffer is dead after the row sort: the chain
     // copies for the fit reuse it
     L.tmp = b.take(sizeof(Rec) * N);
@@ -540,6 +541,7 @@ static void bind_pointers(tpcca_ctx *c) {
     a.ntile = (int32_t *)(A + L.ntile);
     a.tile_base = (int32_t *)(A + L.tile_base);
     a.tiles = (int2 *)(A + L.tiles);
+    a.glb_tiles = (int32_t *)(A + L.glb_tiles);
     a.si = (const SiDesc *)(A + L.si);
     a.st = (SiState *)(A + L.st);
     a.cnt = (Counters *)(A + L.cnt);

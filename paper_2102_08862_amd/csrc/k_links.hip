@@ -120,9 +120,11 @@ struct TileGeo {
 // Rows held in LDS.
 struct LdsRows {
     const float2 *yt;              // staged (y, t)
+    const uint8_t *cell;           // staged y cells
     const int32_t *base;           // [kSlots] LDS index of row j's first cluster
     const int16_t (*fs)[kTileFb + 1];
     __device__ float2 at(int j, int q) const { return yt[base[j] + q]; }
+    __device__ int ycell(int j, int q, const YCell &) const { return cell[base[j] + q]; }
     __device__ int fstart(int j, int f) const { return fs[j][f]; }
 };
 
@@ -138,6 +140,7 @@ struct GlbRows {
         const Rec e = rec[plo[j] + q];
         return make_float2(e.y, e.t);
     }
+    __device__ int ycell(int j, int q, const YCell &yc) const { return ycell_of(yc, rec[plo[j] + q].y); }
     __device__ int fstart(int j, int f) const {
         if (f >= g.nfb) return n[j];
         const int fa = g.fb0 + f;
@@ -175,12 +178,12 @@ __device__ inline void box_visit(const Rows &A, const TileGeo &G, const YCell &y
         int h = hi;
         while (lo < h) {
             const int m = (lo + h) >> 1;
-            if (ycell_of(yc, A.at(j, m).x) < c0) lo = m + 1;
+            if (A.ycell(j, m, yc) < c0) lo = m + 1;
             else h = m;
         }
         for (int q = lo; q < hi; q++) {
+            if (A.ycell(j, q, yc) > c1) break;
             const float2 e = A.at(j, q);
-            if (ycell_of(yc, e.x) > c1) break;
             const bool in = Down ? (fabsf(__fsub_rn(yi, e.x)) <= wy && fabsf(__fsub_rn(ti, e.y)) <= wt)
                                  : (fabsf(__fsub_rn(e.x, yi)) <= wy && fabsf(__fsub_rn(e.y, ti)) <= wt);
             if (in) fn(q, e.x, e.y);
@@ -194,7 +197,9 @@ __device__ inline void box_visit(const Rows &A, const TileGeo &G, const YCell &y
 // batch.
 template <class Rows, class Fn>
 __device__ inline void visit_pairs(const Rows &A, const TileGeo &G, const YCell &ycd, const YCell &ycu, int jd,
-                                   int ju, float yi, float ti, float w, float wy, float wt, float c2, Fn &&on_pair) {
+                                   int ju, float yi, float ti, float w, float wy, float wt, float c2, Fn &&on_pair,
+                                   int *n_box = nullptr) {
+    // n_box (optional): clusters in the box on the down and the up row
     for (int skip = 0;; skip += kBatch) {
         float dy[kBatch], dt[kBatch];
         int dq[kBatch];
@@ -212,8 +217,17 @@ __device__ inline void visit_pairs(const Rows &A, const TileGeo &G, const YCell 
             }
             seen++;
         });
-        if (nd == 0) return;
+        if (nd == 0) {
+            if (n_box) {
+                int nu = 0;
+                box_visit<false>(A, G, ycu, ju, yi, ti, wy, wt, [&](int, float, float) { nu++; });
+                *n_box = seen + nu;
+            }
+            return;
+        }
+        int nu = 0;
         box_visit<false>(A, G, ycu, ju, yi, ti, wy, wt, [&](int qu, float yu, float tu) {
+            nu++;
 #pragma unroll
             for (int k = 0; k < kBatch; k++) {
                 if (k >= nd) break;
@@ -227,18 +241,9 @@ __device__ inline void visit_pairs(const Rows &A, const TileGeo &G, const YCell 
                 if (c <= c2) on_pair(dq[k], dy[k], dt[k], qu, yu, tu, c);
             }
         });
+        if (n_box && skip == 0) *n_box = seen + nu;
         if (seen <= skip + kBatch) return;
     }
-}
-
-// Number of clusters in the box on the down and the up row.
-template <class Rows>
-__device__ inline int box_count(const Rows &A, const TileGeo &G, const YCell &ycd, const YCell &ycu, int jd, int ju,
-                                float yi, float ti, float wy, float wt) {
-    int n = 0;
-    box_visit<true>(A, G, ycd, jd, yi, ti, wy, wt, [&](int, float, float) { n++; });
-    box_visit<false>(A, G, ycu, ju, yi, ti, wy, wt, [&](int, float, float) { n++; });
-    return n;
 }
 
 __device__ inline uint16_t bf16_rne(float f) {
@@ -282,6 +287,7 @@ __device__ inline void triplet_features(float yd, float td, float xd, float yi, 
 // Shared state of one tile.
 struct TileShared {
     float2 yt[kTileCap];
+    uint8_t cell[kTileCap];
     int16_t fs[kSlots][kTileFb + 1];
     int16_t queue[kTileCap];
     YCell yc[kSlots];
@@ -342,7 +348,7 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
     const int tid = threadIdx.x;
     const int jr0 = r0 - s0;
     const int G2 = a.max_gap;
-    LdsRows L{T.yt, T.base, T.fs};
+    LdsRows L{T.yt, T.cell, T.base, T.fs};
     GlbRows Gl{a.rec, T.plo, T.n, a.coff + ((int64_t)si * R + s0) * (kNcbMax + 1), G};
     int nl = 0;
     if (!Enum) {
@@ -406,13 +412,8 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
                     const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
                     int np = 0;
                     auto cnt = [&](int, float, float, int, float, float, float) { np++; };
-                    if (InLds) {
-                        nc[g - 1] = box_count(L, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, wy, wt);
-                        visit_pairs(L, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2, cnt);
-                    } else {
-                        nc[g - 1] = box_count(Gl, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, wy, wt);
-                        visit_pairs(Gl, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2, cnt);
-                    }
+                    if (InLds) visit_pairs(L, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2, cnt, &nc[g - 1]);
+                    else visit_pairs(Gl, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2, cnt, &nc[g - 1]);
                     ng[g - 1] = np;
                 }
             }
@@ -483,19 +484,23 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
     if ((tid & 63) == 0 && nl) atomicAdd(&T.links, nl);
 }
 
-template <bool Enum>
-__global__ __launch_bounds__(kLinkBlock) void k_links(KArgs a) {
+// InLds: tiles from the work queue, searched in LDS; a tile over the LDS
+// budget is appended to the overflow list. !InLds: the overflow tiles, one
+// workgroup each, searched in global memory (a separate kernel, so that the
+// common kernel keeps its register budget).
+template <bool Enum, bool InLds>
+__global__ __launch_bounds__(kLinkBlock, Enum ? 3 : 4) void k_links(KArgs a) {
     __shared__ TileShared T;
     const int R = a.n_rows;
     const int tid = threadIdx.x;
-    const int n_tiles = min(a.cnt->n_tiles, a.tile_cap);
+    const int n_tiles = InLds ? min(a.cnt->n_tiles, a.tile_cap) : min(a.cnt->n_glb_tiles, a.tile_cap);
     if (tid == 0) {
         T.cpos = 0;
         T.cend = 0;
     }
     for (int iter = 0;; iter++) {
         if (tid == 0) {
-            int v = atomicAdd(&a.cnt->tile_next, 1);
+            int v = InLds ? atomicAdd(&a.cnt->tile_next, 1) : (int)blockIdx.x + iter * (int)gridDim.x;
             if ((iter & 15) == 0 && abort_requested(a)) v = n_tiles;
             T.item = v;
             T.nq = 0;
@@ -504,7 +509,7 @@ __global__ __launch_bounds__(kLinkBlock) void k_links(KArgs a) {
         __syncthreads();
         const int item = T.item;
         if (item >= n_tiles) break;
-        const int2 tl = a.tiles[item];
+        const int2 tl = a.tiles[InLds ? item : a.glb_tiles[item]];
         const int w = tl.x;
         const int si = w / a.n_rb, rb = w - si * a.n_rb;
         const int cb0 = tl.y & 0xffff, cb1 = tl.y >> 16;
@@ -547,8 +552,11 @@ __global__ __launch_bounds__(kLinkBlock) void k_links(KArgs a) {
         __syncthreads();
         const int total = T.base[nsr];
         const int own_total = T.opre[nown];
-        const bool in_lds = total <= kTileCap;
-        if (in_lds) {
+        if (InLds && total > kTileCap) {
+            if (tid == 0) a.glb_tiles[atomicAdd(&a.cnt->n_glb_tiles, 1)] = item;
+            continue;   // uniform: every thread skips the tile
+        }
+        if (InLds) {
             // fine-bin starts: every bin at or below a row's last bin is set
             // by exactly one cluster below; the rest mark the row's end
             for (int k = tid; k < nsr * (kTileFb + 1); k += kLinkBlock) {
@@ -562,6 +570,7 @@ __global__ __launch_bounds__(kLinkBlock) void k_links(KArgs a) {
                 const int q = k - T.base[j];
                 const float2 e = *reinterpret_cast<const float2 *>(a.rec + T.plo[j] + q);
                 T.yt[k] = e;
+                T.cell[k] = (uint8_t)ycell_of(T.yc[j], e.x);
                 const int f = fine_bin(e.y, G.t0, G.inv_cbw, G.nf) - G.fb0;
                 int fp = -1;
                 if (q > 0) fp = fine_bin(a.rec[T.plo[j] + q - 1].t, G.t0, G.inv_cbw, G.nf) - G.fb0;
@@ -573,19 +582,18 @@ __global__ __launch_bounds__(kLinkBlock) void k_links(KArgs a) {
             tile_links<Enum, false>(a, T, G, si, r0, s0, nown, own_total);
         }
         __syncthreads();
-        if (tid == 0) {
-            if (T.links) atomicAdd(&a.cnt->n_links, T.links);
-            if (!in_lds) atomicAdd(&a.cnt->n_glb_tiles, 1);
-        }
+        if (tid == 0 && T.links) atomicAdd(&a.cnt->n_links, T.links);
     }
 }
 
 void launch_links(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL(k_links<false>, dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
+    hipLaunchKernelGGL((k_links<false, true>), dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
+    hipLaunchKernelGGL((k_links<false, false>), dim3(max(l.grid / 4, 1)), dim3(kLinkBlock), 0, s, a);
 }
 
 void launch_links_enum(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL(k_links<true>, dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
+    hipLaunchKernelGGL((k_links<true, true>), dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
+    hipLaunchKernelGGL((k_links<true, false>), dim3(max(l.grid / 4, 1)), dim3(kLinkBlock), 0, s, a);
 }
 
 // Pruned links: per cluster, the best pair among its triplets whose logit

@@ -180,6 +180,7 @@ struct KArgs {
     int32_t *ntile;          // [n_si * n_rb + 1] tiles per (sector instance, row block)
     int32_t *tile_base;      // [n_si * n_rb + 1] exclusive prefix of ntile
     int2 *tiles;             // [tile_cap] (si * n_rb + rb, cb0 | cb1 << 16)
+    int32_t *glb_tiles;      // [tile_cap] tiles over the LDS budget (searched in global memory)
     int32_t tile_cap;
     Rec *tmp;                // [n_in]
     Rec *rec;                // [n_in]
