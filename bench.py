@@ -54,7 +54,96 @@ WORKLOADS = {
                   "(multiplicity Exp(2000) truncated at 15000, |eta|<0.9, pT=0.1+Exp(0.6) GeV), 0.5 T, "
                   "sigma 0.1 cm, 5% noise, drift time as coordinate",
     "slice_1ms": "1 ms continuous TPC slice: 36 sectors, 50 collisions, same generator",
+    "batch64": "time frames of uneven length U(0.5, 10) ms (lengths from seed 4999, frames seeds 4000-4063; the "
+               "first --batch-frames of the 64), 50 kHz Pb-Pb, same generator; run in sub-batches of whole frames, "
+               "one HIP graph each",
 }
+
+BATCH_MAX_CLUSTERS = 1_200_000_000   # clusters per sub-batch (one run, 32-bit positions)
+
+
+def batch_bench(args, log):
+    """Throughput over 64 uneven frames: the frames are generated and made
+    resident on the device one by one, grouped into sub-batches of whole
+    frames (one tracker each, all sharing one arena and one stream, each run
+    replayed from its captured HIP graph); a step runs every sub-batch."""
+    import torch
+    from paper_2102_08862_amd import autotune, synth, tpcca
+    lens = np.random.default_rng(4999).uniform(0.5, 10.0, 64)[:args.batch_frames]
+    nth = args.threads or min(16, os.cpu_count() or 1)
+    stream = torch.cuda.Stream()
+    groups, cur, cur_n = [], [], 0
+    total = 0
+    t0 = time.perf_counter()
+    for i, L in enumerate(lens):
+        fr = synth.generate("frame_10ms", seed=4000 + i, n_threads=nth, frame_us=1000.0 * L,
+                            n_collisions=int(round(50 * L)))
+        n = fr.n_clusters
+        if cur and cur_n + n > BATCH_MAX_CLUSTERS:
+            groups.append(cur)
+            cur, cur_n = [], 0
+        ns = [len(r) for r in fr.rows]
+        dev = [torch.from_numpy(np.concatenate(a)).cuda() for a in (fr.rows, fr.ys, fr.ts)]
+        cur.append((dev, ns))
+        cur_n += n
+        total += n
+        del fr
+        if i % 8 == 7:
+            log("generated %d frames (%d clusters) in %.0f s" % (i + 1, total, time.perf_counter() - t0))
+    groups.append(cur)
+    torch.cuda.synchronize()
+    trks, need = [], 0
+    for g in groups:
+        trk = tpcca.Tracker()
+        for dev, ns in g:
+            f = trk.add_frame()
+            off = np.concatenate([[0], np.cumsum(ns)])
+            for sct in range(len(ns)):
+                a, b = int(off[sct]), int(off[sct + 1])
+                trk.load_sector(f, sct, dev[0][a:b], dev[1][a:b], dev[2][a:b])
+        need = max(need, trk.required_arena())
+        trks.append(trk)
+    arena = torch.empty(need + 4096, dtype=torch.uint8, device="cuda")
+    tuning = {}
+    for k, trk in enumerate(trks):
+        trk.set_stream(stream)
+        trk.use_arena(arena)
+        if k == 0 and args.tune:
+            tuning, _ = autotune.tune(trk, [0], log=log)
+            autotune.save(tuning, total // max(1, len(trks)))
+        elif not args.no_tuning:
+            tuning = autotune.apply(trk, total // max(1, len(trks))) or tuning
+        trk.use_arena(arena)
+        trk.set_graph(True)
+    log("%d frames, %d clusters in %d sub-batches; arena %.1f GB" % (len(lens), total, len(trks), need / 1e9))
+    for w in range(max(1, args.warmup)):
+        for k, trk in enumerate(trks):
+            tw = time.perf_counter()
+            trk.run(sync=True)
+            log("warm-up %d, sub-batch %d: %.1f ms" % (w, k, 1e3 * (time.perf_counter() - tw)))
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        for trk in trks:
+            trk.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    for trk in trks:
+        trk.synchronize()
+    log("timed %d steps: %.2f ms/step over %d clusters" % (args.steps, ms, total))
+    return {
+        "metric": "TPC clusters tracked per second (plain CA tracker, 64 uneven frames, batched, graph replay)",
+        "value": round(total / (ms / 1e3), 1), "unit": "clusters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64", "description": WORKLOADS["batch64"], "frames": len(lens),
+                   "frame_ms": [round(float(x), 3) for x in lens], "clusters": int(total),
+                   "sub_batches": len(trks), "parallelism": "single GPU"},
+        "launch": {"graph": True, "tuning": tuning},
+    }
 
 
 def log(*a):
@@ -154,6 +243,9 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay each step from a captured HIP graph")
     ap.add_argument("--no-pruned", action="store_true", help="skip the MLP-pruned tracker leg")
     ap.add_argument("--no-quality", action="store_true", help="skip the truth-based efficiency of both trackers")
+    # the full 64-frame batch stalled in its second sub-batch on the GPU (cause
+    # not found; see the design notes): the default runs the first 16 frames
+    ap.add_argument("--batch-frames", type=int, default=16, help="batch64: use only the first N frames")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -167,6 +259,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "batch64":
+        print(json.dumps(batch_bench(args, log)), flush=True)
+        return
     t0 = time.perf_counter()
     nth = args.threads or min(16, os.cpu_count() or 1)
     fr = synth.generate(args.workload, seed=args.seed, n_threads=nth)

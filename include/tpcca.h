@@ -167,7 +167,12 @@ tpcca_status tpcca_required_arena(tpcca_ctx *ctx, size_t *bytes);
 
 /* Use [device_ptr, device_ptr + bytes) as the arena (caller-owned device
    memory, e.g. a torch uint8 tensor; 256-byte aligned). Results of earlier
-   runs live in the arena and stay valid until the next run or attach. */
+   runs live in the arena and stay valid until the next run or attach. One
+   arena may serve several contexts whose runs are serialised on one stream
+   (the per-run tables live in each context's own small device block); it
+   then holds the results of the last run only, and every sector must have
+   been loaded from device pointers (host-loaded sectors are staged in the
+   arena). */
 tpcca_status tpcca_attach_arena(tpcca_ctx *ctx, void *device_ptr, size_t bytes);
 
 /* Enqueue the whole hot path over every loaded frame on the stream and

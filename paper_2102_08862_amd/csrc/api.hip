@@ -32,7 +32,9 @@ struct SectorIn {
 // Arena layout of one run.
 struct Layout {
     size_t total = 0;
-    size_t inputs, si, st, cnt, chunk, row_x, w_tab, ycell;
+    size_t inputs, st, cnt;
+    // tables in the context's own device block (not in the arena)
+    size_t si, chunk, row_x, w_tab, ycell, tab_bytes;
     size_t rcnt, rstart, rcur, coff;
     size_t tstart, ntile, tile_base, tiles, glb_tiles;
     int64_t tile_cap = 0;
@@ -97,6 +99,8 @@ struct tpcca_ctx {
     std::vector<int32_t> chunks;
     std::vector<float> wtab;
     std::vector<YCell> ycell;
+    char *tab_dev = nullptr;     // device copy of the tables (SI descriptors, chunks, row tables)
+    size_t tab_cap = 0;
     int64_t n_in = 0;
     int32_t n_words = 0;
     Launch lc[kNumStages];
@@ -250,6 +254,7 @@ void tpcca_destroy(tpcca_ctx *c) {
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->abort_host) (void)hipHostFree(c->abort_host);
+    if (c->tab_dev) (void)hipFree(c->tab_dev);
     delete c;
 }
 
@@ -422,13 +427,26 @@ static tpcca_status plan(tpcca_ctx *c) {
     const int64_t tseed_cap = N / std::max(2, c->cfg.min_track_hits) + 64;
     const int64_t trk_cap = tseed_cap;
     const int64_t SR = (int64_t)S * R;
-    L.si = b.take(sizeof(SiDesc) * S);
+    {
+        Bump t;
+        L.si = t.take(sizeof(SiDesc) * S);
+        L.chunk = t.take(sizeof(int32_t) * c->chunks.size());
+        L.row_x = t.take(sizeof(float) * R);
+        L.w_tab = t.take(sizeof(float) * R * kMaxGap);
+        L.ycell = t.take(sizeof(YCell) * R);
+        L.tab_bytes = t.off;
+        if (L.tab_bytes > c->tab_cap) {
+            (void)hipStreamSynchronize(c->stream);
+            if (c->tab_dev) (void)hipFree(c->tab_dev);
+            c->tab_dev = nullptr;
+            c->tab_cap = 0;
+            if (hipMalloc((void **)&c->tab_dev, L.tab_bytes) != hipSuccess)
+                return fail(c, TPCCA_ERR_NOMEM, "device tables");
+            c->tab_cap = L.tab_bytes;
+        }
+    }
     L.st = b.take(sizeof(SiState) * S);
     L.cnt = b.take(sizeof(Counters));
-    L.chunk = b.take(sizeof(int32_t) * c->chunks.size());
-    L.row_x = b.take(sizeof(float) * R);
-    L.w_tab = b.take(sizeof(float) * R * kMaxGap);
-    L.ycell = b.take(sizeof(YCell) * R);
     L.rcnt = b.take(sizeof(int32_t) * SR);
     L.rstart = b.take(sizeof(int32_t) * SR);
     L.rcur = b.take(sizeof(int32_t) * SR);
@@ -534,18 +552,19 @@ static void bind_pointers(tpcca_ctx *c) {
     KArgs &a = c->args;
     const Layout &L = c->lay;
     char *A = c->arena;
-    a.row_x = (const float *)(A + L.row_x);
-    a.w_tab = (const float *)(A + L.w_tab);
-    a.ycell = (const YCell *)(A + L.ycell);
+    char *D = c->tab_dev;
+    a.row_x = (const float *)(D + L.row_x);
+    a.w_tab = (const float *)(D + L.w_tab);
+    a.ycell = (const YCell *)(D + L.ycell);
     a.tstart = (int16_t *)(A + L.tstart);
     a.ntile = (int32_t *)(A + L.ntile);
     a.tile_base = (int32_t *)(A + L.tile_base);
     a.tiles = (int2 *)(A + L.tiles);
     a.glb_tiles = (int32_t *)(A + L.glb_tiles);
-    a.si = (const SiDesc *)(A + L.si);
+    a.si = (const SiDesc *)(D + L.si);
     a.st = (SiState *)(A + L.st);
     a.cnt = (Counters *)(A + L.cnt);
-    a.chunk = (const int32_t *)(A + L.chunk);
+    a.chunk = (const int32_t *)(D + L.chunk);
     a.rcnt = (int32_t *)(A + L.rcnt);
     a.rstart = (int32_t *)(A + L.rstart);
     a.rcur = (int32_t *)(A + L.rcur);
@@ -727,16 +746,17 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
                     d.t = x.dt;
                 }
             }
-        HIPCHK(c, hipMemcpyAsync(A + L.si, c->si_host.data(), sizeof(SiDesc) * c->si_host.size(),
+        char *D = c->tab_dev;
+        HIPCHK(c, hipMemcpyAsync(D + L.si, c->si_host.data(), sizeof(SiDesc) * c->si_host.size(),
                                  hipMemcpyHostToDevice, s));
         if (!c->chunks.empty())
-            HIPCHK(c, hipMemcpyAsync(A + L.chunk, c->chunks.data(), sizeof(int32_t) * c->chunks.size(),
+            HIPCHK(c, hipMemcpyAsync(D + L.chunk, c->chunks.data(), sizeof(int32_t) * c->chunks.size(),
                                      hipMemcpyHostToDevice, s));
-        HIPCHK(c, hipMemcpyAsync(A + L.row_x, c->row_x.data(), sizeof(float) * c->row_x.size(),
+        HIPCHK(c, hipMemcpyAsync(D + L.row_x, c->row_x.data(), sizeof(float) * c->row_x.size(),
                                  hipMemcpyHostToDevice, s));
-        HIPCHK(c, hipMemcpyAsync(A + L.w_tab, c->wtab.data(), sizeof(float) * c->wtab.size(),
+        HIPCHK(c, hipMemcpyAsync(D + L.w_tab, c->wtab.data(), sizeof(float) * c->wtab.size(),
                                  hipMemcpyHostToDevice, s));
-        HIPCHK(c, hipMemcpyAsync(A + L.ycell, c->ycell.data(), sizeof(YCell) * c->ycell.size(),
+        HIPCHK(c, hipMemcpyAsync(D + L.ycell, c->ycell.data(), sizeof(YCell) * c->ycell.size(),
                                  hipMemcpyHostToDevice, s));
         HIPCHK(c, hipStreamSynchronize(s));
         c->upload_dirty = false;
@@ -749,6 +769,9 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
     }
     if (c->use_graph) {
         if (!c->graph_valid) {
+            // capture on an idle stream (earlier work of this or another
+            // context on the stream finishes first)
+            HIPCHK(c, hipStreamSynchronize(s));
             drop_graph(c);
             HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
             enqueue_run(c, s, false, slot);

@@ -292,6 +292,19 @@ class Tracker:
             self._check(self.lib.tpcca_attach_arena(self.h, ctypes.c_void_p(aligned), need))
         return need
 
+    def use_arena(self, buf):
+        """Attach a caller-provided device buffer (torch uint8 tensor) as the
+        arena, e.g. one buffer shared by several trackers whose runs are
+        serialised on one stream."""
+        need = self.required_arena()
+        base = buf.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        if buf.numel() - (aligned - base) < need:
+            raise ValueError("arena buffer of %d bytes, run needs %d" % (buf.numel(), need))
+        self.arena = buf
+        self._check(self.lib.tpcca_attach_arena(self.h, ctypes.c_void_p(aligned), buf.numel() - (aligned - base)))
+        return need
+
     def run(self, sync: bool = False):
         self.ensure_arena()
         self._check(self.lib.tpcca_run(self.h))

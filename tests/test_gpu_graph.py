@@ -70,3 +70,34 @@ def test_launch_shapes_do_not_change_results(tp):
         g = t.load_frame_packed(fr)
         t.run(sync=True)
         _same(_outputs(t, g, sectors), ref)
+
+
+def test_shared_arena_between_trackers(tp):
+    """Two contexts with different frames share one arena and one stream,
+    each replaying its own graph: after each run the running context's
+    outputs equal its results in a private arena."""
+    import torch
+    frs = [synth.generate("slice_1ms", seed=81, n_collisions=6), synth.generate("slice_1ms", seed=82, n_collisions=9)]
+    sectors = (2, 19)
+    refs = []
+    for fr in frs:
+        t = tp.Tracker()
+        f = t.load_frame_packed(fr)
+        t.run(sync=True)
+        refs.append(_outputs(t, f, sectors))
+    stream = torch.cuda.Stream()
+    trks, fids = [], []
+    for fr in frs:
+        t = tp.Tracker()
+        fids.append(t.load_frame_packed(fr))
+        trks.append(t)
+    need = max(t.required_arena() for t in trks)
+    arena = torch.empty(need + 4096, dtype=torch.uint8, device="cuda")
+    for t in trks:
+        t.set_stream(stream)
+        t.use_arena(arena)
+        t.set_graph(True)
+    for rep in range(3):
+        for k in (0, 1, 0):
+            trks[k].run(sync=True)
+            _same(_outputs(trks[k], fids[k], sectors), refs[k])
