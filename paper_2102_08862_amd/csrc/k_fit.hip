@@ -18,6 +18,14 @@
 
 namespace tpcca {
 
+// Hardware reciprocal and reciprocal square root (about 1 ulp), used only
+// for the transport Jacobian and the Kalman gain: errors there change how
+// fast the passes converge, not the helix they converge to. The reference
+// trajectory itself (positions, arc lengths) keeps correctly rounded
+// division and square root.
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // asin(u)/u and its derivative (Maclaurin series near 0)
 __device__ inline float asin_ratio(float u) {
     if (fabsf(u) < 0.05f) {
@@ -31,7 +39,7 @@ __device__ inline float asin_ratio_d(float u) {
         const float u2 = u * u;
         return u * (1.f / 3.f + u2 * (3.f / 10.f + u2 * (15.f / 56.f)));
     }
-    return (1.f / sqrtf(1.f - u * u) - asinf(u) / u) / u;
+    return (rsq(1.f - u * u) - asinf(u) * rcp(u)) * rcp(u);
 }
 
 struct Jac {
@@ -58,14 +66,15 @@ __device__ inline bool transport(float kB, float smax, const float q[5], float d
     qo[3] = tau;
     qo[4] = k;
     if (J) {
-        const float iC = 1.f / C;
-        J->ys = dx * (2.f * iC + S * (s / c + s1 / c1) * iC * iC);
-        J->yk = -kB * dx * dx * (iC + S * s1 / c1 * iC * iC);
+        const float iC = rcp(C), ic = rcp(c), ic1 = rcp(c1);
+        J->ys = dx * (2.f * iC + S * (s * ic + s1 * ic1) * iC * iC);
+        J->yk = -kB * dx * dx * (iC + S * s1 * ic1 * iC * iC);
         float dls = 0.f, dlk = 0.f;
         if (L > 0.f) {
-            const float dldL = sgn / sqrtf(1.f - u * u);
-            dls = dldL * (dy / L) * J->ys;
-            dlk = dldL * (dy / L) * J->yk - sgn * 0.5f * L * L * asin_ratio_d(u) * kB;
+            const float dldL = sgn * rsq(1.f - u * u);
+            const float dyL = dy * rcp(L);
+            dls = dldL * dyL * J->ys;
+            dlk = dldL * dyL * J->yk - sgn * 0.5f * L * L * asin_ratio_d(u) * kB;
         }
         J->ts = tau * dls;
         J->tt = dl;
@@ -102,7 +111,7 @@ __device__ inline void apply_jac(const Jac &J, float d[5], float C[5][5]) {
 // measurement update with (ry, rt) = measurement - prediction
 __device__ inline void kf_update(float d[5], float C[5][5], float ry, float rt, float vy, float vt) {
     const float S00 = C[0][0] + vy, S01 = C[0][1], S11 = C[1][1] + vt;
-    const float idet = 1.f / (S00 * S11 - S01 * S01);
+    const float idet = rcp(S00 * S11 - S01 * S01);
     const float i00 = S11 * idet, i01 = -S01 * idet, i11 = S00 * idet;
     float K0[5], K1[5];
 #pragma unroll
@@ -138,6 +147,7 @@ __global__ __launch_bounds__(256) void k_fit(KArgs a) {
     const int nt = min(a.cnt->n_tracks, a.trk_cap);
     const float kB = a.bz_kb, smax = a.s_max;
     const float vy = a.sigma_y2, vt = a.sigma_t2;
+    const float ivy = 1.f / vy, ivt = 1.f / vt;
     const int P = a.kf_passes;
     // tracks in order of decreasing length: the lanes of a wave carry chains
     // of nearly equal length
@@ -200,7 +210,7 @@ __global__ __launch_bounds__(256) void k_fit(KArgs a) {
             C[2][2] = a.var_s;
             C[3][3] = a.var_tau;
             C[4][4] = a.var_k;
-            float chi = (ref[0] * ref[0]) / vy + (ref[1] * ref[1]) / vt;
+            float chi = ref[0] * ref[0] * ivy + ref[1] * ref[1] * ivt;
             float Xp = 0.f;
             for (int j = 1; j < L; j++) {
                 const Rec cj = ch[j];
@@ -218,7 +228,7 @@ __global__ __launch_bounds__(256) void k_fit(KArgs a) {
                 for (int i = 0; i < 5; i++) ref[i] = rn[i];
                 const float Yj = m2.x - y1, Tj = m2.y - t1;
                 const float ey = Yj - ref[0], et = Tj - ref[1];
-                chi += (ey * ey) / vy + (et * et) / vt;
+                chi += ey * ey * ivy + et * et * ivt;
                 kf_update(dev, C, ey - dev[0], et - dev[1], vy, vt);
                 if (ext) {
 #pragma unroll

@@ -564,17 +564,31 @@ __global__ __launch_bounds__(kLinkBlock, Enum ? 3 : 4) void k_links(KArgs a) {
                 T.fs[j][f] = (int16_t)T.n[j];
             }
             __syncthreads();
-            for (int k = tid; k < total; k += kLinkBlock) {
-                int j = 0;
-                while (j + 1 < nsr && T.base[j + 1] <= k) j++;
-                const int q = k - T.base[j];
-                const float2 e = *reinterpret_cast<const float2 *>(a.rec + T.plo[j] + q);
-                T.yt[k] = e;
-                T.cell[k] = (uint8_t)ycell_of(T.yc[j], e.x);
-                const int f = fine_bin(e.y, G.t0, G.inv_cbw, G.nf) - G.fb0;
-                int fp = -1;
-                if (q > 0) fp = fine_bin(a.rec[T.plo[j] + q - 1].t, G.t0, G.inv_cbw, G.nf) - G.fb0;
-                for (int b = max(fp + 1, 0); b <= min(f, G.nfb); b++) T.fs[j][b] = (int16_t)q;
+            // one wave per staged row; the previous cluster's fine bin comes
+            // from the neighbouring lane (or the last lane of the previous
+            // step), so every cluster is read once
+            {
+                const int wv = tid >> 6, lane = tid & 63;
+                for (int j = wv; j < nsr; j += kLinkBlock / 64) {
+                    const int n = T.n[j], bj = T.base[j], plo = T.plo[j];
+                    const YCell yc = T.yc[j];
+                    int carry = -1;
+                    for (int q0 = 0; q0 < n; q0 += 64) {
+                        const int q = q0 + lane;
+                        int f = 0x7fffffff;
+                        if (q < n) {
+                            const float2 e = *reinterpret_cast<const float2 *>(a.rec + plo + q);
+                            T.yt[bj + q] = e;
+                            T.cell[bj + q] = (uint8_t)ycell_of(yc, e.x);
+                            f = fine_bin(e.y, G.t0, G.inv_cbw, G.nf) - G.fb0;
+                        }
+                        int fp = __shfl_up(f, 1);
+                        if (lane == 0) fp = carry;
+                        if (q < n)
+                            for (int b = max(fp + 1, 0); b <= min(f, G.nfb); b++) T.fs[j][b] = (int16_t)q;
+                        carry = __shfl(f, 63);
+                    }
+                }
             }
             __syncthreads();
             tile_links<Enum, true>(a, T, G, si, r0, s0, nown, own_total);
