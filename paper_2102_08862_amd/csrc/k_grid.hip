@@ -343,12 +343,16 @@ __device__ void sort_bin(Rec *__restrict__ p, int k, const YCell &yc) {
 constexpr int kFineMax = kNcbMax * kFinePerCb;
 constexpr int kSortBlock = 512;
 constexpr int kSortWin = 2048;   // records of whole fine bins ordered in LDS at a time
+constexpr int kMaxWin = 448;     // windows per row segment handled by the partition path
 
 __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ int32_t fh[kFineMax];
     __shared__ int32_t part[kSortBlock];
     __shared__ Rec win[kSortWin];
+    __shared__ uint16_t idx[kSortWin];
+    __shared__ int32_t wb[kMaxWin + 1], wc[kMaxWin];
+    __shared__ int32_t s_nw;
     const int R = a.n_rows;
     const int nseg = a.n_si * R;
     const int tid = threadIdx.x, bd = blockDim.x;
@@ -390,60 +394,94 @@ __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
         __syncthreads();
         for (int cb = tid; cb <= ncb; cb += bd) co[cb] = start + (cb < ncb ? fh[cb * kFinePerCb] : n);
         __syncthreads();
-        for (int k = tid; k < n; k += bd) {
-            const Rec e = a.tmp[start + k];
-            const int slot = atomicAdd(&fh[fine_bin(e.t, t0, inv, nf)], 1);
-            a.rec[start + slot] = e;
-        }
-        __threadfence_block();
-        __syncthreads();
-        // fh[b] now holds the end of fine bin b. Order each bin by (y cell,
-        // t, id): windows of whole bins holding at most kSortWin records are
-        // loaded into LDS, each bin is sorted there by one thread, and the
-        // window is written back (coalesced); a single bin over kSortWin is
-        // sorted in place in global memory.
+        // windows of whole fine bins holding at most kSortWin clusters
+        // (a single larger bin is a window of its own); fh holds bin starts
         const YCell yc = a.ycell[seg - si * R];
-        int b0 = 0;
-        while (b0 < nf) {
-            const int r0 = b0 ? fh[b0 - 1] : 0;
-            // last bin end within the window: fh is non-decreasing
-            int lo_b = b0, hi_b = nf - 1;
-            while (lo_b < hi_b) {
-                const int m = (lo_b + hi_b + 1) >> 1;
-                if (fh[m] - r0 <= kSortWin) lo_b = m;
-                else hi_b = m - 1;
-            }
-            int b1 = lo_b + 1;
-            if (fh[b0] - r0 > kSortWin) {
-                b1 = b0 + 1;
-                if (tid == 0) sort_bin(a.rec + start + r0, fh[b0] - r0, yc);
-                __threadfence_block();
-                __syncthreads();
-                b0 = b1;
-                continue;
-            }
-            const int r1 = fh[b1 - 1];
-            for (int k = tid; k < r1 - r0; k += bd) win[k] = a.rec[start + r0 + k];
-            __syncthreads();
-            for (int b = b0 + tid; b < b1; b += bd) {
-                const int lo = (b ? fh[b - 1] : 0) - r0, hi = fh[b] - r0;
-                for (int i = lo + 1; i < hi; i++) {
-                    const Rec e = win[i];
-                    const int ce = ycell_of(yc, e.y);
-                    int j = i - 1;
-                    while (j >= lo) {
-                        const Rec f = win[j];
-                        if (!rec_less(ce, e.t, e.id, ycell_of(yc, f.y), f.t, f.id)) break;
-                        win[j + 1] = f;
-                        j--;
-                    }
-                    win[j + 1] = e;
+        if (tid == 0) {
+            int nw = 0, b0 = 0;
+            while (b0 < nf && nw < kMaxWin) {
+                const int r0 = fh[b0];
+                int lo_b = b0 + 1, hi_b = nf;   // largest b1 with S(b1) - S(b0) <= kSortWin
+                while (lo_b < hi_b) {
+                    const int m = (lo_b + hi_b + 1) >> 1;
+                    if ((m < nf ? fh[m] : n) - r0 <= kSortWin) lo_b = m;
+                    else hi_b = m - 1;
                 }
+                wb[nw++] = b0;
+                b0 = lo_b;
             }
+            wb[nw] = nf;
+            s_nw = b0 < nf ? -1 : nw;   // -1: too many windows
+        }
+        __syncthreads();
+        const int nw = s_nw;
+        if (nw > 0) {
+            // partition into the windows (runs of each window's range)
+            for (int w = tid; w < nw; w += bd) wc[w] = fh[wb[w]];
             __syncthreads();
-            for (int k = tid; k < r1 - r0; k += bd) a.rec[start + r0 + k] = win[k];
+            for (int k = tid; k < n; k += bd) {
+                const Rec e = a.tmp[start + k];
+                const int f = fine_bin(e.t, t0, inv, nf);
+                int lo_w = 0, hi_w = nw - 1;   // last window starting at or before f
+                while (lo_w < hi_w) {
+                    const int m = (lo_w + hi_w + 1) >> 1;
+                    if (wb[m] <= f) lo_w = m;
+                    else hi_w = m - 1;
+                }
+                a.rec[start + atomicAdd(&wc[lo_w], 1)] = e;
+            }
+            __threadfence_block();
             __syncthreads();
-            b0 = b1;
+            // each window: counting sort by fine bin in LDS, every bin ordered
+            // by (y cell, t, id), written back in place (coalesced)
+            for (int w = 0; w < nw; w++) {
+                const int wb0 = wb[w], wb1 = wb[w + 1];
+                const int r0 = fh[wb0], r1 = wb1 < nf ? fh[wb1] : n;
+                const int m = r1 - r0;
+                if (m > kSortWin) {
+                    if (tid == 0) sort_bin(a.rec + start + r0, m, yc);
+                    __threadfence_block();
+                    __syncthreads();
+                    continue;
+                }
+                for (int j = tid; j < m; j += bd) win[j] = a.rec[start + r0 + j];
+                __syncthreads();
+                for (int j = tid; j < m; j += bd)
+                    idx[atomicAdd(&fh[fine_bin(win[j].t, t0, inv, nf)], 1) - r0] = (uint16_t)j;
+                __syncthreads();
+                // fh[b] is now the end of bin b
+                for (int b = wb0 + tid; b < wb1; b += bd) {
+                    const int lo = (b > wb0 ? fh[b - 1] : r0) - r0, hi = fh[b] - r0;
+                    for (int i = lo + 1; i < hi; i++) {
+                        const int ei = idx[i];
+                        const Rec e = win[ei];
+                        const int ce = ycell_of(yc, e.y);
+                        int j = i - 1;
+                        while (j >= lo) {
+                            const Rec f = win[idx[j]];
+                            if (!rec_less(ce, e.t, e.id, ycell_of(yc, f.y), f.t, f.id)) break;
+                            idx[j + 1] = idx[j];
+                            j--;
+                        }
+                        idx[j + 1] = (uint16_t)ei;
+                    }
+                }
+                __syncthreads();
+                for (int j = tid; j < m; j += bd) a.rec[start + r0 + j] = win[idx[j]];
+                __syncthreads();
+            }
+        } else {
+            // too many windows: scatter by fine bin, then sort every bin
+            for (int k = tid; k < n; k += bd) {
+                const Rec e = a.tmp[start + k];
+                a.rec[start + atomicAdd(&fh[fine_bin(e.t, t0, inv, nf)], 1)] = e;
+            }
+            __threadfence_block();
+            __syncthreads();
+            for (int b = tid; b < nf; b += bd) {
+                const int lo = b ? fh[b - 1] : 0, hi = fh[b];
+                if (hi - lo > 1) sort_bin(a.rec + start + lo, hi - lo, yc);
+            }
         }
         __threadfence_block();
         __syncthreads();
