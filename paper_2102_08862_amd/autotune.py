@@ -96,7 +96,7 @@ def tune(trk, frame_ids, sectors=(0, 17, 35), reps=3, log=print):
 
 def _default(stage):
     # the library's built-in shapes
-    return {1: (8, 0), 3: (8, 0), 4: (2, 0), 5: (4, 3072), 6: (8, 0), 7: (8, 0), 10: (8, 0), 11: (8, 0)}[stage]
+    return {1: (8, 0), 3: (8, 0), 4: (4, 0), 5: (4, 3072), 6: (8, 0), 7: (8, 0), 10: (8, 0), 11: (8, 0)}[stage]
 
 
 def save(settings, n_clusters, path=DEFAULT_CACHE):

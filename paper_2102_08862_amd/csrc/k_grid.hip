@@ -1,6 +1,6 @@
 // Search-grid construction: per sector, clusters are grouped by pad row and
-// each row is ordered by fine drift-time bin, then y cell, then time (ties by
-// input index), with coarse time bins giving O(1) range lookups. The grid is an acceleration structure
+// each row is ordered by fine drift-time bin (4 per coarse bin), with coarse
+// time bins giving O(1) range lookups. The grid is an acceleration structure
 // only: neighbour candidate sets are decided by exact predicates later, so
 // the layout cannot change any result.
 //
@@ -10,9 +10,9 @@
 //   k_si_rows   per sector: row prefix, bin geometry
 //   k_si_prefix sorted-space base of every sector
 //   k_scatter   stable-free scatter of clusters into row segments (LDS ranks)
-//   k_rowsort   per (sector,row): fine-bin counting sort in LDS, then an
-//               in-place sort of each fine bin by (y cell, t, id); writes
-//               the coarse bin offsets used by the neighbour tiles
+//   k_rowsort   per (sector,row): counting sort by fine time bin (LDS
+//               histogram, scatter); writes the coarse bin offsets used by
+//               the neighbour tiles
 #include "tpcca_internal.h"
 
 namespace tpcca {
@@ -273,86 +273,13 @@ void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s) {
     if (runs > 0) hipLaunchKernelGGL(k_scatter, dim3(min(l.grid, runs)), dim3(256), 0, s, a);
 }
 
-// order inside a fine time bin: (y cell, t, id)
-__device__ inline bool rec_less(int ca, float ta, int ia, int cb, float tb, int ib) {
-    return ca < cb || (ca == cb && (ta < tb || (ta == tb && ia < ib)));
-}
-
-// sort k (> 1) records in place by (y cell, t, id)
-__device__ void sort_bin(Rec *__restrict__ p, int k, const YCell &yc) {
-    if (k <= 8) {
-        float ky[8], kt[8];
-        int kid[8], ksr[8], kc[8];
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-            if (j < k) {
-                const Rec e = p[j];
-                ky[j] = e.y;
-                kt[j] = e.t;
-                kid[j] = e.id;
-                ksr[j] = e.sr;
-                kc[j] = ycell_of(yc, e.y);
-            } else {
-                ky[j] = 0.f;
-                kt[j] = __builtin_inff();
-                kid[j] = 0x7fffffff;
-                ksr[j] = 0;
-                kc[j] = 0x7fffffff;
-            }
-        }
-#pragma unroll
-        for (int round = 0; round < 8; round++) {
-#pragma unroll
-            for (int j = (round & 1); j + 1 < 8; j += 2) {
-                if (rec_less(kc[j + 1], kt[j + 1], kid[j + 1], kc[j], kt[j], kid[j])) {
-                    float fy = ky[j]; ky[j] = ky[j + 1]; ky[j + 1] = fy;
-                    float ft = kt[j]; kt[j] = kt[j + 1]; kt[j + 1] = ft;
-                    int fi = kid[j]; kid[j] = kid[j + 1]; kid[j + 1] = fi;
-                    int fs = ksr[j]; ksr[j] = ksr[j + 1]; ksr[j + 1] = fs;
-                    int fc = kc[j]; kc[j] = kc[j + 1]; kc[j + 1] = fc;
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-            if (j < k) {
-                Rec e;
-                e.y = ky[j];
-                e.t = kt[j];
-                e.id = kid[j];
-                e.sr = ksr[j];
-                p[j] = e;
-            }
-        }
-    } else {
-        for (int i = 1; i < k; i++) {
-            const Rec e = p[i];
-            const int ce = ycell_of(yc, e.y);
-            int j = i - 1;
-            while (j >= 0) {
-                const Rec f = p[j];
-                if (!rec_less(ce, e.t, e.id, ycell_of(yc, f.y), f.t, f.id)) break;
-                p[j + 1] = f;
-                j--;
-            }
-            p[j + 1] = e;
-        }
-    }
-}
-
 constexpr int kFineMax = kNcbMax * kFinePerCb;
 constexpr int kSortBlock = 512;
-constexpr int kSortWin = 2048;   // records of whole fine bins ordered in LDS at a time
-constexpr int kMaxWin = 448;     // windows per row segment handled by the partition path
 
 __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ int32_t fh[kFineMax];
     __shared__ int32_t part[kSortBlock];
-    __shared__ Rec win[kSortWin];
-    __shared__ uint16_t idx[kSortWin];
-    __shared__ int32_t wb[kMaxWin + 1], wc[kMaxWin];
-    __shared__ int32_t s_nw;
     const int R = a.n_rows;
     const int nseg = a.n_si * R;
     const int tid = threadIdx.x, bd = blockDim.x;
@@ -394,96 +321,12 @@ __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
         __syncthreads();
         for (int cb = tid; cb <= ncb; cb += bd) co[cb] = start + (cb < ncb ? fh[cb * kFinePerCb] : n);
         __syncthreads();
-        // windows of whole fine bins holding at most kSortWin clusters
-        // (a single larger bin is a window of its own); fh holds bin starts
-        const YCell yc = a.ycell[seg - si * R];
-        if (tid == 0) {
-            int nw = 0, b0 = 0;
-            while (b0 < nf && nw < kMaxWin) {
-                const int r0 = fh[b0];
-                int lo_b = b0 + 1, hi_b = nf;   // largest b1 with S(b1) - S(b0) <= kSortWin
-                while (lo_b < hi_b) {
-                    const int m = (lo_b + hi_b + 1) >> 1;
-                    if ((m < nf ? fh[m] : n) - r0 <= kSortWin) lo_b = m;
-                    else hi_b = m - 1;
-                }
-                wb[nw++] = b0;
-                b0 = lo_b;
-            }
-            wb[nw] = nf;
-            s_nw = b0 < nf ? -1 : nw;   // -1: too many windows
+        // counting-sort scatter by fine bin (order inside a bin is arbitrary:
+        // the neighbour tiles order each bin by y cell in LDS)
+        for (int k = tid; k < n; k += bd) {
+            const Rec e = a.tmp[start + k];
+            a.rec[start + atomicAdd(&fh[fine_bin(e.t, t0, inv, nf)], 1)] = e;
         }
-        __syncthreads();
-        const int nw = s_nw;
-        if (nw > 0) {
-            // partition into the windows (runs of each window's range)
-            for (int w = tid; w < nw; w += bd) wc[w] = fh[wb[w]];
-            __syncthreads();
-            for (int k = tid; k < n; k += bd) {
-                const Rec e = a.tmp[start + k];
-                const int f = fine_bin(e.t, t0, inv, nf);
-                int lo_w = 0, hi_w = nw - 1;   // last window starting at or before f
-                while (lo_w < hi_w) {
-                    const int m = (lo_w + hi_w + 1) >> 1;
-                    if (wb[m] <= f) lo_w = m;
-                    else hi_w = m - 1;
-                }
-                a.rec[start + atomicAdd(&wc[lo_w], 1)] = e;
-            }
-            __threadfence_block();
-            __syncthreads();
-            // each window: counting sort by fine bin in LDS, every bin ordered
-            // by (y cell, t, id), written back in place (coalesced)
-            for (int w = 0; w < nw; w++) {
-                const int wb0 = wb[w], wb1 = wb[w + 1];
-                const int r0 = fh[wb0], r1 = wb1 < nf ? fh[wb1] : n;
-                const int m = r1 - r0;
-                if (m > kSortWin) {
-                    if (tid == 0) sort_bin(a.rec + start + r0, m, yc);
-                    __threadfence_block();
-                    __syncthreads();
-                    continue;
-                }
-                for (int j = tid; j < m; j += bd) win[j] = a.rec[start + r0 + j];
-                __syncthreads();
-                for (int j = tid; j < m; j += bd)
-                    idx[atomicAdd(&fh[fine_bin(win[j].t, t0, inv, nf)], 1) - r0] = (uint16_t)j;
-                __syncthreads();
-                // fh[b] is now the end of bin b
-                for (int b = wb0 + tid; b < wb1; b += bd) {
-                    const int lo = (b > wb0 ? fh[b - 1] : r0) - r0, hi = fh[b] - r0;
-                    for (int i = lo + 1; i < hi; i++) {
-                        const int ei = idx[i];
-                        const Rec e = win[ei];
-                        const int ce = ycell_of(yc, e.y);
-                        int j = i - 1;
-                        while (j >= lo) {
-                            const Rec f = win[idx[j]];
-                            if (!rec_less(ce, e.t, e.id, ycell_of(yc, f.y), f.t, f.id)) break;
-                            idx[j + 1] = idx[j];
-                            j--;
-                        }
-                        idx[j + 1] = (uint16_t)ei;
-                    }
-                }
-                __syncthreads();
-                for (int j = tid; j < m; j += bd) a.rec[start + r0 + j] = win[idx[j]];
-                __syncthreads();
-            }
-        } else {
-            // too many windows: scatter by fine bin, then sort every bin
-            for (int k = tid; k < n; k += bd) {
-                const Rec e = a.tmp[start + k];
-                a.rec[start + atomicAdd(&fh[fine_bin(e.t, t0, inv, nf)], 1)] = e;
-            }
-            __threadfence_block();
-            __syncthreads();
-            for (int b = tid; b < nf; b += bd) {
-                const int lo = b ? fh[b - 1] : 0, hi = fh[b];
-                if (hi - lo > 1) sort_bin(a.rec + start + lo, hi - lo, yc);
-            }
-        }
-        __threadfence_block();
         __syncthreads();
     }
 }

@@ -20,9 +20,9 @@
 // side, plus one coarse bin of time on each side) fit the LDS budget; tiles
 // come from a device work queue, so uneven sectors and frames balance over
 // the persistent workgroups. Within a staged row the clusters are ordered by
-// (fine time bin, y cell, t, id) (the row sort leaves them so): a box lookup
-// visits the 1-3 fine bins the box overlaps and, in each, binary-searches its
-// first y cell. A tile too dense for LDS (a single coarse bin over budget)
+// fine time bin (the row sort leaves them so) and, once staged in LDS, each
+// fine bin by y cell: a box lookup visits the 1-3 fine bins the box overlaps
+// and, in each, binary-searches its first y cell. A tile too dense for LDS (a single coarse bin over budget)
 // runs the same search on global memory. Clusters without a g = 1 link go to
 // an LDS queue and are searched at g = 2 by the whole workgroup.
 #include "tpcca_internal.h"
@@ -33,6 +33,7 @@ constexpr int kLinkBlock = 256;
 constexpr int kSlots = kTileRows + 2 * kMaxGap;          // staged rows of a tile
 constexpr int kTileFb = (kMaxTileCb + 2) * kFinePerCb;   // fine bins of a staged row
 constexpr int kBatch = 8;                                // down candidates held in registers
+constexpr int kQueueCap = 1024;                          // gap-2 queue of a tile (overflow: searched at once)
 
 // ---------------------------------------------------------------- tiles
 // One workgroup per (sector instance, row block): cumulative staged counts
@@ -118,19 +119,25 @@ struct TileGeo {
 };
 
 // Rows held in LDS.
+// Inside each fine bin the staged clusters are ordered by y cell.
 struct LdsRows {
+    static constexpr bool kYSorted = true;
     const float2 *yt;              // staged (y, t)
     const uint8_t *cell;           // staged y cells
+    const int16_t *oq;             // staged cluster -> index in its row segment
     const int32_t *base;           // [kSlots] LDS index of row j's first cluster
+    const int32_t *plo;            // [kSlots] first staged sorted position of row j
     const int16_t (*fs)[kTileFb + 1];
     __device__ float2 at(int j, int q) const { return yt[base[j] + q]; }
     __device__ int ycell(int j, int q, const YCell &) const { return cell[base[j] + q]; }
     __device__ int fstart(int j, int f) const { return fs[j][f]; }
+    __device__ int pos(int j, int q) const { return plo[j] + oq[base[j] + q]; }
 };
 
 // Rows read from global memory (tiles over the LDS budget); the fine-bin
 // starts come from a binary search inside the coarse bin.
 struct GlbRows {
+    static constexpr bool kYSorted = false;   // row order: fine bin only
     const Rec *rec;
     const int32_t *plo;            // [kSlots] (LDS) first staged position of row j
     const int32_t *n;              // [kSlots] (LDS) staged clusters of row j
@@ -141,6 +148,7 @@ struct GlbRows {
         return make_float2(e.y, e.t);
     }
     __device__ int ycell(int j, int q, const YCell &yc) const { return ycell_of(yc, rec[plo[j] + q].y); }
+    __device__ int pos(int j, int q) const { return plo[j] + q; }
     __device__ int fstart(int j, int f) const {
         if (f >= g.nfb) return n[j];
         const int fa = g.fb0 + f;
@@ -175,14 +183,16 @@ __device__ inline void box_visit(const Rows &A, const TileGeo &G, const YCell &y
     for (int f = max(f0, 0); f <= min(f1, G.nfb - 1); f++) {
         int lo = A.fstart(j, f);
         const int hi = A.fstart(j, f + 1);
-        int h = hi;
-        while (lo < h) {
-            const int m = (lo + h) >> 1;
-            if (A.ycell(j, m, yc) < c0) lo = m + 1;
-            else h = m;
+        if (Rows::kYSorted) {
+            int h = hi;
+            while (lo < h) {
+                const int m = (lo + h) >> 1;
+                if (A.ycell(j, m, yc) < c0) lo = m + 1;
+                else h = m;
+            }
         }
         for (int q = lo; q < hi; q++) {
-            if (A.ycell(j, q, yc) > c1) break;
+            if (Rows::kYSorted && A.ycell(j, q, yc) > c1) break;
             const float2 e = A.at(j, q);
             const bool in = Down ? (fabsf(__fsub_rn(yi, e.x)) <= wy && fabsf(__fsub_rn(ti, e.y)) <= wt)
                                  : (fabsf(__fsub_rn(e.x, yi)) <= wy && fabsf(__fsub_rn(e.y, ti)) <= wt);
@@ -288,8 +298,9 @@ __device__ inline void triplet_features(float yd, float td, float xd, float yi, 
 struct TileShared {
     float2 yt[kTileCap];
     uint8_t cell[kTileCap];
+    int16_t oq[kTileCap];
     int16_t fs[kSlots][kTileFb + 1];
-    int16_t queue[kTileCap];
+    int16_t queue[kQueueCap];
     YCell yc[kSlots];
     int32_t base[kSlots + 1];      // LDS index of each staged row (prefix of n)
     int32_t plo[kSlots];           // first staged sorted position of each row
@@ -315,8 +326,8 @@ __device__ inline bool best_pair(const Rows &A, const TileGeo &G, const TileShar
                     bool better = !found || c < bc;
                     if (found && c == bc) {
                         // exact tie of the score: compare input indices
-                        const int idu = a.rec[T.plo[ju] + qu].id, idd = a.rec[T.plo[jd] + qd].id;
-                        const int biu = a.rec[T.plo[ju] + bqu].id, bid = a.rec[T.plo[jd] + bqd].id;
+                        const int idu = a.rec[A.pos(ju, qu)].id, idd = a.rec[A.pos(jd, qd)].id;
+                        const int biu = a.rec[A.pos(ju, bqu)].id, bid = a.rec[A.pos(jd, bqd)].id;
                         better = idu < biu || (idu == biu && idd < bid);
                     }
                     if (better) {
@@ -327,8 +338,8 @@ __device__ inline bool best_pair(const Rows &A, const TileGeo &G, const TileShar
                     }
                 });
     if (found) {
-        bu = T.plo[ju] + bqu;
-        bd = T.plo[jd] + bqd;
+        bu = A.pos(ju, bqu);
+        bd = A.pos(jd, bqd);
     }
     return found;
 }
@@ -348,7 +359,7 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
     const int tid = threadIdx.x;
     const int jr0 = r0 - s0;
     const int G2 = a.max_gap;
-    LdsRows L{T.yt, T.cell, T.base, T.fs};
+    LdsRows L{T.yt, T.cell, T.oq, T.base, T.plo, T.fs};
     GlbRows Gl{a.rec, T.plo, T.n, a.coff + ((int64_t)si * R + s0) * (kNcbMax + 1), G};
     int nl = 0;
     if (!Enum) {
@@ -363,22 +374,25 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
                 const bool f = InLds ? best_pair(L, G, T, a, j, r, 1, e.x, e.y, bu, bd)
                                      : best_pair(Gl, G, T, a, j, r, 1, e.x, e.y, bu, bd);
                 if (!f && G2 >= 2 && r >= 2 && r + 2 <= R - 1) {
-                    if (InLds) {
+                    const int slot = InLds ? atomicAdd(&T.nq, 1) : kQueueCap;
+                    if (slot < kQueueCap) {
                         // searched by the whole workgroup after this pass
-                        T.queue[atomicAdd(&T.nq, 1)] = (int16_t)o;
+                        T.queue[slot] = (int16_t)o;
                         done = false;
+                    } else if (InLds) {
+                        best_pair(L, G, T, a, j, r, 2, e.x, e.y, bu, bd);
                     } else {
                         best_pair(Gl, G, T, a, j, r, 2, e.x, e.y, bu, bd);
                     }
                 }
             }
             if (done) {
-                a.link[T.plo[j] + q] = make_int2(bu, bd);
+                a.link[InLds ? L.pos(j, q) : Gl.pos(j, q)] = make_int2(bu, bd);
                 nl += (bu >= 0);
             }
         }
         __syncthreads();
-        const int nq = InLds ? T.nq : 0;
+        const int nq = InLds ? min(T.nq, kQueueCap) : 0;
         for (int k = tid; k < nq; k += kLinkBlock) {
             const int o = T.queue[k];
             int j, q;
@@ -387,7 +401,7 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
             const float2 e = InLds ? L.at(j, q) : Gl.at(j, q);
             int bu = -1, bd = -1;
             best_pair(L, G, T, a, j, r, 2, e.x, e.y, bu, bd);
-            a.link[T.plo[j] + q] = make_int2(bu, bd);
+            a.link[L.pos(j, q)] = make_int2(bu, bd);
             nl += (bu >= 0);
         }
     } else {
@@ -443,7 +457,7 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
             __syncthreads();
             const int slot0 = T.pbase + excl;
             if (act) {
-                const int p = T.plo[j] + q;
+                const int p = InLds ? L.pos(j, q) : Gl.pos(j, q);
                 const bool fits = (int64_t)slot0 + tot <= (int64_t)a.pool_cap;
                 if (fits) {
                     int sl = slot0;
@@ -454,7 +468,6 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
                         const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
                         const float xd = a.row_x[r - g], xi = a.row_x[r], xu = a.row_x[r + g];
                         const int ncd = nc[g - 1];
-                        const int pd0 = T.plo[jd], pu0 = T.plo[ju];
                         auto put = [&](int qd, float yd, float td, int qu, float yu, float tu, float c) {
                             uint16_t f[kMlpInP];
                             triplet_features(yd, td, xd, yi, ti, xi, yu, tu, xu, g, wy, wt, w, a.c2s, ncd, f);
@@ -462,8 +475,8 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
                             dst[0] = make_uint4(f[0] | ((uint32_t)f[1] << 16), f[2] | ((uint32_t)f[3] << 16),
                                                 f[4] | ((uint32_t)f[5] << 16), f[6] | ((uint32_t)f[7] << 16));
                             dst[1] = make_uint4(f[8] | ((uint32_t)f[9] << 16), f[10] | ((uint32_t)f[11] << 16), 0u, 0u);
-                            a.pd[sl] = pd0 + qd;
-                            a.pu[sl] = pu0 + qu;
+                            a.pd[sl] = InLds ? L.pos(jd, qd) : Gl.pos(jd, qd);
+                            a.pu[sl] = InLds ? L.pos(ju, qu) : Gl.pos(ju, qu);
                             a.pc[sl] = c;
                             sl++;
                         };
@@ -580,6 +593,7 @@ __global__ __launch_bounds__(kLinkBlock, Enum ? 3 : 4) void k_links(KArgs a) {
                             const float2 e = *reinterpret_cast<const float2 *>(a.rec + plo + q);
                             T.yt[bj + q] = e;
                             T.cell[bj + q] = (uint8_t)ycell_of(yc, e.x);
+                            T.oq[bj + q] = (int16_t)q;
                             f = fine_bin(e.y, G.t0, G.inv_cbw, G.nf) - G.fb0;
                         }
                         int fp = __shfl_up(f, 1);
@@ -588,6 +602,27 @@ __global__ __launch_bounds__(kLinkBlock, Enum ? 3 : 4) void k_links(KArgs a) {
                             for (int b = max(fp + 1, 0); b <= min(f, G.nfb); b++) T.fs[j][b] = (int16_t)q;
                         carry = __shfl(f, 63);
                     }
+                }
+            }
+            __syncthreads();
+            // order every (row, fine bin) by y cell (a few clusters each)
+            for (int k = tid; k < nsr * G.nfb; k += kLinkBlock) {
+                const int j = k / G.nfb, f = k - j * G.nfb;
+                const int lo = T.base[j] + T.fs[j][f], hi = T.base[j] + T.fs[j][f + 1];
+                for (int i = lo + 1; i < hi; i++) {
+                    const float2 e = T.yt[i];
+                    const uint8_t c = T.cell[i];
+                    const int16_t o = T.oq[i];
+                    int m = i - 1;
+                    while (m >= lo && T.cell[m] > c) {
+                        T.yt[m + 1] = T.yt[m];
+                        T.cell[m + 1] = T.cell[m];
+                        T.oq[m + 1] = T.oq[m];
+                        m--;
+                    }
+                    T.yt[m + 1] = e;
+                    T.cell[m + 1] = c;
+                    T.oq[m + 1] = o;
                 }
             }
             __syncthreads();
