@@ -39,7 +39,7 @@ struct Layout {
     size_t tstart, ntile, tile_base, tiles, glb_tiles;
     int64_t tile_cap = 0;
     size_t tmp, rec, link;
-    size_t seeds, tseed, tlen, tslot;
+    size_t seeds, tseed, tlen, tslot, tprov, prov;
     size_t bits, wpre;
     size_t trk_len, trk_seed, cl_off, trk;
     size_t clusters, assign, scan_tmp;
@@ -470,6 +470,12 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.tseed = b.take(sizeof(int32_t) * tseed_cap);
     L.tlen = b.take(sizeof(int32_t) * tseed_cap);
     L.tslot = b.take(sizeof(int32_t) * tseed_cap);
+    L.tprov = b.take(sizeof(int32_t) * tseed_cap);
+    // the chain walk records the positions it visits for the first
+    // prov_seeds seeds (chains are a few percent of the clusters); the output
+    // stage then gathers them instead of walking again
+    const int64_t prov_seeds = N / 32 + 64;
+    L.prov = b.take(sizeof(int32_t) * prov_seeds * R);
     L.bits = b.take(sizeof(uint32_t) * (W + 1));
     L.wpre = b.take(sizeof(int32_t) * (W + 1));
     L.trk_len = b.take(sizeof(int32_t) * (trk_cap + 1));
@@ -512,6 +518,7 @@ static tpcca_status plan(tpcca_ctx *c) {
     a.n_words = (int32_t)W;
     a.seed_cap = (int32_t)seed_cap;
     a.tseed_cap = (int32_t)tseed_cap;
+    a.prov_seeds = (int32_t)prov_seeds;
     a.trk_cap = (int32_t)trk_cap;
     a.max_gap = c->cfg.max_gap;
     a.n_rb = nrb;
@@ -576,6 +583,8 @@ static void bind_pointers(tpcca_ctx *c) {
     a.tseed = (int32_t *)(A + L.tseed);
     a.tlen = (int32_t *)(A + L.tlen);
     a.tslot = (int32_t *)(A + L.tslot);
+    a.tprov = (int32_t *)(A + L.tprov);
+    a.prov = (int32_t *)(A + L.prov);
     a.bits = (uint32_t *)(A + L.bits);
     a.wpre = (int32_t *)(A + L.wpre);
     a.trk_len = (int32_t *)(A + L.trk_len);

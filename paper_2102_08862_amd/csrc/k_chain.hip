@@ -94,14 +94,32 @@ __global__ __launch_bounds__(256) void k_chainlen(KArgs a) {
         int p = 0, L = 0;
         if (k < ns) {
             p = a.seeds[k];
+            // positions are kept 8 at a time in registers and stored as
+            // two 16-byte vectors (rows of prov are 16-byte aligned)
+            int32_t *pv = (k < a.prov_seeds && (R & 3) == 0) ? a.prov + (int64_t)k * R : nullptr;
             int q = p;
             L = 1;
+            int qb[8];
+            qb[0] = q;
             for (int step = 0; step < R; step++) {
                 const int u = a.link[q].x;
                 if (u < 0 || u >= nv) break;
                 if (a.link[u].y != q) break;
                 q = u;
+                if ((L & 7) == 0 && pv && L <= R - 8) {
+                    reinterpret_cast<int4 *>(pv + L - 8)[0] = make_int4(qb[0], qb[1], qb[2], qb[3]);
+                    reinterpret_cast<int4 *>(pv + L - 8)[1] = make_int4(qb[4], qb[5], qb[6], qb[7]);
+                }
+#pragma unroll
+                for (int b = 0; b < 8; b++)
+                    if (b == (L & 7)) qb[b] = q;
                 L++;
+            }
+            if (pv) {
+                const int j0 = (L - 1) & ~7;
+#pragma unroll
+                for (int b = 0; b < 8; b++)
+                    if (j0 + b < L && j0 + b < R) pv[j0 + b] = qb[b];
             }
         }
         const bool trk = (k < ns) && L >= a.min_track_hits;
@@ -113,6 +131,7 @@ __global__ __launch_bounds__(256) void k_chainlen(KArgs a) {
         if (trk && slot < a.tseed_cap) {
             a.tseed[slot] = p;
             a.tlen[slot] = L;
+            a.tprov[slot] = (k < a.prov_seeds && L <= R && (R & 3) == 0) ? k : -1;
             const Rec e = a.rec[p];
             const int si = e.sr >> 8;
             atomicOr(&a.bits[a.si[si].word_base + (e.id >> 5)], 1u << (e.id & 31));
@@ -193,6 +212,35 @@ __global__ __launch_bounds__(256) void k_emit(KArgs a) {
         const int si = e.sr >> 8;
         const int tn = g - a.st[si].trk_base;
         int32_t *asg = a.assign + a.si[si].in_base;
+        const int pk = a.tprov[k];
+        if (pk >= 0) {
+            // positions recorded by the chain walk: independent gathers
+            const int32_t *pv = a.prov + (int64_t)pk * R;
+            for (int j0 = 0; j0 < L; j0 += kEmitBatch) {
+                int qs[kEmitBatch];
+#pragma unroll
+                for (int b = 0; b < kEmitBatch; b++) qs[b] = (j0 + b < L) ? pv[j0 + b] : -1;
+                Rec buf[kEmitBatch];
+#pragma unroll
+                for (int b = 0; b < kEmitBatch; b++) {
+                    if (qs[b] >= 0) {
+                        const Rec f = a.rec[qs[b]];
+                        buf[b].y = f.y;
+                        buf[b].t = f.t;
+                        buf[b].id = f.id;
+                        buf[b].sr = f.sr & 255;
+                    } else {
+                        buf[b] = Rec{0.f, 0.f, -1, 0};
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < kEmitBatch; b++) {
+                    if (qs[b] >= 0) asg[buf[b].id] = tn;
+                    dst[j0 + b] = buf[b];
+                }
+            }
+            continue;
+        }
         for (int j0 = 0; j0 < L; j0 += kEmitBatch) {
             Rec buf[kEmitBatch];
 #pragma unroll

@@ -189,6 +189,9 @@ struct KArgs {
     int32_t *tseed;          // [tseed_cap]
     int32_t *tlen;           // [tseed_cap]
     int32_t *tslot;          // [tseed_cap]
+    int32_t *tprov;          // [tseed_cap] row of the track's walk in prov, or -1
+    int32_t *prov;           // [prov_seeds * n_rows] positions visited by each seed's walk
+    int32_t prov_seeds;
     uint32_t *bits;          // [n_words]
     int32_t *wpre;           // [n_words + 1]
     int32_t *trk_len;        // [trk_cap + 1]
