@@ -42,7 +42,7 @@ struct Layout {
     size_t seeds, tseed, tlen, tslot, tprov, prov;
     size_t bits, wpre;
     size_t trk_len, trk_seed, cl_off, trk;
-    size_t clusters, assign, scan_tmp;
+    size_t clusters, assign, scan_tmp, asg_cnt;
     size_t off8, perm, lhist, chain;
     size_t pfeat, pd, pu, pc, pz, hoff, hn1, hn2;
     int64_t pool_cap = 0;
@@ -463,7 +463,8 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.glb_tiles = b.take(sizeof(int32_t) * L.tile_cap);
     // the row-grouped staging buffer is dead after the row sort: the chain
     // copies for the fit reuse it
-    L.tmp = b.take(sizeof(Rec) * N);
+    // also holds the assignment's bucketed pairs after the row sort
+    L.tmp = b.take(std::max(sizeof(Rec) * N, sizeof(int2) * (size_t)(N + 16384)));
     L.rec = b.take(sizeof(Rec) * N);
     L.link = b.take(sizeof(int2) * N);
     L.seeds = b.take(sizeof(int32_t) * seed_cap);
@@ -490,6 +491,7 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.chain = b.take(sizeof(Rec) * (N + 7 * trk_cap));
     L.clusters = b.take(sizeof(int32_t) * N);
     L.assign = b.take(sizeof(int32_t) * N);
+    L.asg_cnt = b.take(sizeof(int32_t) * (N / 16384 + 2));
     c->pruned_run = c->cfg.use_mlp != 0;
     // every workgroup of the neighbour search may leave up to one partly used
     // chunk of the pool behind
@@ -597,6 +599,8 @@ static void bind_pointers(tpcca_ctx *c) {
     a.lhist = (int32_t *)(A + L.lhist);
     a.chain = (Rec *)(A + L.chain);
     a.assign = (int32_t *)(A + L.assign);
+    a.asg_pairs = (int2 *)(A + L.tmp);
+    a.asg_cnt = (int32_t *)(A + L.asg_cnt);
     a.scan_tmp = (int32_t *)(A + L.scan_tmp);
     a.abort_flag = c->abort_dev;
     a.pfeat = (uint16_t *)(A + L.pfeat);
@@ -632,7 +636,7 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     // reset: row counts, bitmap, assignment (fill kernels: graph-safe)
     launch_fill_i32(a.rcnt, (int64_t)a.n_si * a.n_rows, 0, s);
     launch_fill_i32((int32_t *)a.bits, (int64_t)a.n_words + 1, 0, s);
-    launch_fill_i32(a.assign, (int64_t)a.n_in, -1, s);
+    launch_fill_i32(a.asg_cnt, (int64_t)a.n_in / 16384 + 2, 0, s);
     mark(st++);
     launch_grid_hist(a, c->lc[1], s);  // also resets per-sector state and counters
     mark(st++);

@@ -10,10 +10,12 @@
 //                tracks are numbered in ascending seed input index
 //   k_track_slot track slot, length and seed of every track
 //   (scan)       prefix of lengths -> offsets of the cluster lists
-//   k_emit       one lane per track: walk the chain again, write the
-//                cluster list (input indices, rows ascending), the
-//                assignment of every member, and the chain's (y, t, row)
-//                contiguously for the fit
+//   k_emit       one lane per track: gather the chain's clusters (positions
+//                recorded by the walk, or a second walk) and write the
+//                track's chain copy {y, t, id, row} contiguously
+//   k_lists      cluster lists (input indices, rows ascending) and the
+//                assignment, through per-bucket runs
+//   k_asg_fill   the assignment, one bucket of input indices at a time
 #include "tpcca_internal.h"
 
 namespace tpcca {
@@ -209,9 +211,6 @@ __global__ __launch_bounds__(256) void k_emit(KArgs a) {
         const int L = min(a.trk_len[g], R);
         Rec *dst = a.chain + a.off8[g];
         Rec e = a.rec[q];
-        const int si = e.sr >> 8;
-        const int tn = g - a.st[si].trk_base;
-        int32_t *asg = a.assign + a.si[si].in_base;
         const int pk = a.tprov[k];
         if (pk >= 0) {
             // positions recorded by the chain walk: independent gathers
@@ -234,10 +233,7 @@ __global__ __launch_bounds__(256) void k_emit(KArgs a) {
                     }
                 }
 #pragma unroll
-                for (int b = 0; b < kEmitBatch; b++) {
-                    if (qs[b] >= 0) asg[buf[b].id] = tn;
-                    dst[j0 + b] = buf[b];
-                }
+                for (int b = 0; b < kEmitBatch; b++) dst[j0 + b] = buf[b];
             }
             continue;
         }
@@ -247,7 +243,6 @@ __global__ __launch_bounds__(256) void k_emit(KArgs a) {
             for (int b = 0; b < kEmitBatch; b++) {
                 const int j = j0 + b;
                 if (j < L) {
-                    asg[e.id] = tn;
                     buf[b].y = e.y;
                     buf[b].t = e.t;
                     buf[b].id = e.id;
@@ -270,23 +265,111 @@ void launch_emit(const KArgs &a, Launch l, hipStream_t s) {
     hipLaunchKernelGGL(k_emit, dim3(l.grid), dim3(256), 0, s, a);
 }
 
-// Canonical cluster lists: one wave per track copies the input indices of
-// its chain copy to the track's list (coalesced reads and writes).
+// Canonical cluster lists and the assignment. The lists: one wave per track
+// copies the input indices of its chain copy (coalesced). The assignment is
+// a permutation from track order to input order; instead of one scattered
+// 4-byte store per cluster it goes through buckets of kAsgBucket input
+// indices: each workgroup takes a range of tracks, counts its clusters per
+// bucket in LDS, reserves one run per bucket and writes (input index, track
+// number) pairs there; k_asg_fill then builds each bucket's slice of the
+// assignment in LDS (-1 where no pair) and writes it out whole.
+constexpr int kAsgBucket = 16384;          // input indices per bucket (64 KB of assignment)
+constexpr int kAsgTracks = 1024;           // tracks per workgroup range
+constexpr int kAsgHist = 4096;             // buckets a range may span (else direct stores)
+
 __global__ __launch_bounds__(256) void k_lists(KArgs a) {
     TPCCA_ABORT_GUARD(a);
+    __shared__ int32_t h[kAsgHist];
+    __shared__ int32_t s_lo, s_span;
     const int nt = min(a.cnt->n_tracks, a.trk_cap);
     const int lane = threadIdx.x & 63;
-    const int wpb = blockDim.x >> 6;
-    for (int g = blockIdx.x * wpb + (threadIdx.x >> 6); g < nt; g += gridDim.x * wpb) {
-        const int L = a.trk_len[g];
-        const Rec *src = a.chain + a.off8[g];
-        int32_t *dst = a.clusters + a.cl_off[g];
-        for (int j = lane; j < L; j += 64) dst[j] = src[j].id;
+    const int wv = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    for (int g0 = blockIdx.x * kAsgTracks; g0 < nt; g0 += gridDim.x * kAsgTracks) {
+        const int g1 = min(g0 + kAsgTracks, nt);
+        if (threadIdx.x == 0) {
+            const int sa = a.rec[a.trk_seed[g0]].sr >> 8, sb = a.rec[a.trk_seed[g1 - 1]].sr >> 8;
+            const int lo = a.si[sa].in_base / kAsgBucket;
+            const int hi = (a.si[sb].in_base + a.si[sb].n) / kAsgBucket;
+            s_lo = lo;
+            s_span = hi - lo + 1;
+        }
+        __syncthreads();
+        const int blo = s_lo, span = s_span;
+        const bool bucketed = span <= kAsgHist;
+        if (bucketed) {
+            for (int b = threadIdx.x; b < span; b += blockDim.x) h[b] = 0;
+            __syncthreads();
+        }
+        // lists, and the bucket counts
+        for (int g = g0 + wv; g < g1; g += wpb) {
+            const int L = a.trk_len[g];
+            const Rec *src = a.chain + a.off8[g];
+            int32_t *dst = a.clusters + a.cl_off[g];
+            const int si = a.rec[a.trk_seed[g]].sr >> 8;
+            const int ib = a.si[si].in_base;
+            const int tn = g - a.st[si].trk_base;
+            for (int j = lane; j < L; j += 64) {
+                const int id = src[j].id;
+                dst[j] = id;
+                const int gi = ib + id;
+                if (bucketed) {
+                    atomicAdd(&h[gi / kAsgBucket - blo], 1);
+                } else {
+                    const int bk = gi / kAsgBucket;   // a range spanning many sectors: one grab per pair
+                    a.asg_pairs[(int64_t)bk * kAsgBucket + atomicAdd(&a.asg_cnt[bk], 1)] = make_int2(gi, tn);
+                }
+            }
+        }
+        if (!bucketed) continue;   // uniform
+        __syncthreads();
+        for (int b = threadIdx.x; b < span; b += blockDim.x) {
+            const int v = h[b];
+            // runs are reserved inside the bucket's fixed region (a bucket
+            // holds at most kAsgBucket pairs: one per input index)
+            h[b] = v ? (blo + b) * kAsgBucket + atomicAdd(&a.asg_cnt[blo + b], v) : 0;   // < n_in + kAsgBucket
+        }
+        __syncthreads();
+        for (int g = g0 + wv; g < g1; g += wpb) {
+            const int L = a.trk_len[g];
+            const int32_t *ids = a.clusters + a.cl_off[g];
+            const int si = a.rec[a.trk_seed[g]].sr >> 8;
+            const int ib = a.si[si].in_base;
+            const int tn = g - a.st[si].trk_base;
+            for (int j = lane; j < L; j += 64) {
+                const int gi = ib + ids[j];
+                a.asg_pairs[(int64_t)atomicAdd(&h[gi / kAsgBucket - blo], 1)] = make_int2(gi, tn);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup per bucket: the bucket's slice of the assignment.
+__global__ __launch_bounds__(256) void k_asg_fill(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    __shared__ int32_t img[kAsgBucket];
+    const int nb = (a.n_in + kAsgBucket - 1) / kAsgBucket;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int i0 = b * kAsgBucket, m = min(kAsgBucket, a.n_in - i0);
+        for (int k = threadIdx.x; k < m; k += blockDim.x) img[k] = -1;
+        __syncthreads();
+        const int np = min(a.asg_cnt[b], kAsgBucket);
+        const int2 *pr = a.asg_pairs + (int64_t)i0;
+        for (int k = threadIdx.x; k < np; k += blockDim.x) {
+            const int2 v = pr[k];
+            const int o = v.x - i0;
+            if ((unsigned)o < (unsigned)m) img[o] = v.y;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < m; k += blockDim.x) a.assign[i0 + k] = img[k];
+        __syncthreads();
     }
 }
 
 void launch_lists(const KArgs &a, Launch l, hipStream_t s) {
     hipLaunchKernelGGL(k_lists, dim3(l.grid), dim3(256), 0, s, a);
+    const int nb = (a.n_in + kAsgBucket - 1) / kAsgBucket;
+    if (nb > 0) hipLaunchKernelGGL(k_asg_fill, dim3(min(nb, 4096)), dim3(256), 0, s, a);
 }
 
 // Track slots ordered by decreasing chain length (counting sort), so that the

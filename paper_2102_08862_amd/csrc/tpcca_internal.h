@@ -204,6 +204,8 @@ struct KArgs {
     int32_t *clusters;       // [n_in]
     Rec *chain;              // [n_in + 7 * trk_cap] chain copies {y, t, id, row}
     int32_t *assign;         // [n_in]
+    int2 *asg_pairs;         // [buckets * 16384] (input index, track number), in the dead staging buffer
+    int32_t *asg_cnt;        // [buckets] pairs per bucket of 16384 input indices
     int32_t *scan_tmp;       // block sums of the scans
     const volatile int32_t *abort_flag;  // host-mapped
     // learned pruning (pruned runs only)
