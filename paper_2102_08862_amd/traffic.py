@@ -8,7 +8,8 @@ HBM bytes. The summary records a fingerprint of the kernel sources: a figure
 is only valid for the kernels it was taken on.
 
   W="python -m paper_2102_08862_amd.traffic run"
-  rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'k_links|k_rowsort|k_scatter|k_emit|k_fit|k_copy' \\
+  rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \\
+      'k_links|k_rowsort|k_scatter|k_hist|k_emit|k_lists|k_asg_fill|k_fit|k_seeds|k_chainlen|k_copy' \\
       -d OUT/fetch -o f --output-format csv -- $W
   rocprofv3 --pmc WRITE_SIZE (same options) -d OUT/write -o w --output-format csv -- $W
   python -m paper_2102_08862_amd.traffic summarize OUT/fetch OUT/write --out profiles/traffic_frame_10ms.txt
@@ -32,6 +33,7 @@ SOURCES = {
     "k_hist": "k_grid.hip", "k_scatter": "k_grid.hip", "k_rowsort": "k_grid.hip", "k_copy": "k_grid.hip",
     "k_tiles": "k_links.hip", "k_links": "k_links.hip", "k_select": "k_links.hip",
     "k_seeds": "k_chain.hip", "k_chainlen": "k_chain.hip", "k_emit": "k_chain.hip", "k_lists": "k_chain.hip",
+    "k_asg_fill": "k_chain.hip", "k_tile_list": "k_links.hip",
     "k_fit": "k_fit.hip", "k_mlp_infer": "k_mlp.hip",
 }
 
@@ -45,8 +47,14 @@ def fingerprint(kernel: str) -> str:
 
 
 def short_name(full: str) -> str:
-    m = re.search(r"(k_[a-z0-9_]+)", full)
-    return m.group(1) if m else full
+    """Kernel name without namespace and arguments; template arguments are
+    kept (spaces removed) so that instantiations stay apart."""
+    m = re.search(r"(k_[a-z0-9_]+(<[^()]*>)?)", full)
+    return m.group(1).replace(" ", "") if m else full
+
+
+def base_name(kernel: str) -> str:
+    return kernel.split("<")[0]
 
 
 def run(argv):
@@ -116,23 +124,29 @@ def summarize(argv):
         fb = sum(f) / len(f) * 1024 * ff
         wb = sum(w) / len(w) * 1024 * fw
         lines.append("%s %d %.4f %.4f %.4f %s" % (k, len(f), fb / 1e9, wb / 1e9, (fb + wb) / 1e9,
-                                                  fingerprint(k) if k in SOURCES else "-"))
+                                                  fingerprint(base_name(k)) if base_name(k) in SOURCES else "-"))
     with open(a.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
 def lookup(path: str, kernel: str):
-    """Traffic bytes per dispatch of `kernel` from a summary, or None if the
-    summary is absent or was taken on other kernel sources."""
+    """Traffic bytes of one launch of `kernel` (the sum over its template
+    instantiations, which one launch of the stage runs once each) from a
+    summary, or None if the summary is absent, lacks the kernel or was taken
+    on other kernel sources."""
     if not os.path.exists(path) or kernel not in SOURCES:
         return None
+    total, found = 0.0, False
     with open(path) as fh:
         for line in fh:
             p = line.split()
-            if len(p) == 6 and p[0] == kernel:
-                return float(p[4]) * 1e9 if p[5] == fingerprint(kernel) else None
-    return None
+            if len(p) == 6 and base_name(p[0]) == kernel:
+                if p[5] != fingerprint(kernel):
+                    return None
+                total += float(p[4]) * 1e9
+                found = True
+    return total if found else None
 
 
 if __name__ == "__main__":
