@@ -211,11 +211,12 @@ def pruned_leg(trk, fr, f, args, log):
     st = trk.stats()
     runs = max(1, st["n_timed_runs"])
     out = {"value": round(fr.n_clusters / (ms / 1e3), 1), "unit": "clusters/s", "ms_per_step": round(ms, 4),
-           "theta": theta, "triplets": int(st["n_triplets"]), "pruned": int(st["n_pruned"]),
-           "pruned_fraction": round(st["n_pruned"] / max(1, st["n_triplets"]), 4),
+           "theta": theta, "triplets_scored": int(st["n_triplets"]), "pruned": int(st["n_pruned"]),
+           "pruned_fraction_of_scored": round(st["n_pruned"] / max(1, st["n_triplets"]), 4),
            "pool_overflow": int(st["n_pool_overflow"]),
            "stage_ms": {k: round(v / runs, 4) for k, v in st["stage_ms_total"].items()}}
-    log("pruned: %.3f ms/step, %d triplets, %.1f%% pruned" % (ms, out["triplets"], 100 * out["pruned_fraction"]))
+    log("pruned: %.3f ms/step, %d triplets scored, %.1f%% pruned"
+        % (ms, out["triplets_scored"], 100 * out["pruned_fraction_of_scored"]))
     if q_plain is not None:
         q = frame_quality(trk, fr, f)
         out["efficiency_plain"] = round(q_plain["efficiency"], 6)

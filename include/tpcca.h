@@ -78,7 +78,7 @@ typedef struct {
     float s_max;               /* |sin phi| at which a propagation fails, 0.999 */
     int32_t use_mlp;           /* 1: prune candidate triplets with the loaded network, 0 */
     float mlp_logit_threshold; /* triplets with logit below this are pruned, 0 */
-    int32_t pool_per_cluster;  /* triplet-pool slots per input cluster in pruned runs, 8 */
+    int32_t pool_per_cluster;  /* triplet-pool slots per input cluster (runs that keep the pool), 8 */
 } tpcca_config;
 
 /* One fitted track. Tracks of a sector are numbered 0..T-1 in ascending
@@ -117,7 +117,8 @@ typedef struct {
     int64_t n_overflow_tiles;  /* neighbour-finding tiles too dense for LDS (searched in global memory) */
     int64_t n_triplets;        /* pruned runs: accepted candidate triplets scored by the network */
     int64_t n_pruned;          /* pruned runs: triplets below the threshold (among those examined) */
-    int64_t n_pool_overflow;   /* pruned runs: triplets that did not fit the pool (run is invalid) */
+    int64_t n_pool_overflow;   /* pruned runs: triplets that did not fit the pool (run is invalid); without the
+                                  pool, dense-tile pad rows of 2^24 or more clusters */
     int32_t mlp_used;          /* 1 if the last run pruned with the network */
     int64_t n_timed_runs;      /* runs summed in stage_ms_total */
     int32_t n_stages;          /* entries used in stage_ms / stage_name */
@@ -270,8 +271,24 @@ tpcca_status tpcca_mlp_fetch(tpcca_ctx *ctx, float *params);
 /* Switch pruning on (use_mlp = 1) or off (0) and set the logit threshold for
    the following runs, without reloading frames (the pool is sized at the
    next run, so the arena may need to grow: check tpcca_required_arena).
-   INVALID_ARG for use_mlp outside {0, 1} or a NaN threshold. */
+   A pruned run keeps, per cluster, the best (c, up id, down id) pair among
+   its gap-1 triplets whose logit is >= the threshold, and among its gap-2
+   triplets only if none survives (the pruning of the cellular automaton's
+   candidates by a learned network). By default the network scores the
+   triplets inside the neighbour search, gap 2 only where needed, and the
+   stats count the triplets scored; see tpcca_set_triplet_pool for the
+   variant that lists every triplet. INVALID_ARG for use_mlp outside {0, 1}
+   or a NaN threshold. */
 tpcca_status tpcca_set_pruning(tpcca_ctx *ctx, int32_t use_mlp, float logit_threshold);
+
+/* keep = 1: pruned runs write every candidate triplet of every gap, with
+   its features, positions, score and logit, to a pool in the arena
+   (pool_per_cluster slots per cluster; CAPACITY at tpcca_synchronize if it
+   overflows), then score and select in separate kernels; the links are the
+   same as without the pool. tpcca_get_triplets and tpcca_triplet_samples
+   need such a run (training data, inspection). keep = 0 (default): no pool.
+   Takes effect at the next run; INVALID_ARG for keep outside {0, 1}. */
+tpcca_status tpcca_set_triplet_pool(tpcca_ctx *ctx, int32_t keep);
 
 /* Logits of n triplets: x_dev = device [n][16] BF16 features (columns
    12..15 zero), z_dev = device float[n]. Enqueued on the stream. */
@@ -298,7 +315,8 @@ tpcca_status tpcca_mlp_grad(tpcca_ctx *ctx, const uint16_t *x_dev, const float *
 tpcca_status tpcca_mlp_train_step(tpcca_ctx *ctx, const uint16_t *x_dev, const float *y_dev, int64_t n,
                                   const tpcca_mlp_hparams *hp, float *loss_dev);
 
-/* Training examples from the last pruned run (all loaded frames), built on
+/* Training examples from the last pruned run that kept its triplet pool
+   (all loaded frames; STATE otherwise), built on
    the device: each triplet is kept with probability `keep` (decided by a
    hash of seed, sector, input index and the triplet's rank in its cluster,
    so the subset is reproducible) and labelled 1 if the run's cleaned links
@@ -309,7 +327,8 @@ tpcca_status tpcca_mlp_train_step(tpcca_ctx *ctx, const uint16_t *x_dev, const f
 tpcca_status tpcca_triplet_samples(tpcca_ctx *ctx, float keep, uint64_t seed, uint16_t *feat_dev, float *label_dev,
                                    int64_t cap, int64_t *n_out);
 
-/* Triplets of the last pruned run for one (frame, sector), ordered by the
+/* Triplets of the last pruned run that kept its triplet pool (STATE
+   otherwise) for one (frame, sector), ordered by the
    input index of the middle cluster, then gap, then down and up input index:
    tri[k] = (down, cluster, up, gap) input indices, feat[k] = 16 BF16
    features, z[k] = logit (any output pointer may be NULL). CAPACITY if cap

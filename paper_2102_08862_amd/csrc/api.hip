@@ -111,7 +111,8 @@ struct tpcca_ctx {
     int32_t tile_budget = kTileCap;  // clusters a neighbour tile may stage
     char *mlp = nullptr;       // caller-owned network state buffer
     bool mlp_loaded = false;
-    bool pruned_run = false;   // the plan includes the triplet pool
+    bool keep_pool = false;    // pruned runs list every triplet in the pool
+    bool pool_run = false;     // the plan includes the triplet pool
 };
 
 static void drop_graph(tpcca_ctx *c) {
@@ -322,6 +323,17 @@ tpcca_status tpcca_set_pruning(tpcca_ctx *c, int32_t use_mlp, float theta) {
     return TPCCA_OK;
 }
 
+tpcca_status tpcca_set_triplet_pool(tpcca_ctx *c, int32_t keep) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    if (keep != 0 && keep != 1) return fail(c, TPCCA_ERR_INVALID_ARG, "keep must be 0 or 1");
+    (void)hipStreamSynchronize(c->stream);
+    c->keep_pool = keep != 0;
+    c->plan_dirty = true;  // the pool is part of the plan
+    c->graph_valid = false;
+    c->have_results = false;
+    return TPCCA_OK;
+}
+
 tpcca_status tpcca_add_frame(tpcca_ctx *c, int32_t *frame_id) {
     if (!c || !frame_id) return TPCCA_ERR_INVALID_ARG;
     c->frames.emplace_back((size_t)c->cfg.n_sectors);
@@ -492,19 +504,19 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.clusters = b.take(sizeof(int32_t) * N);
     L.assign = b.take(sizeof(int32_t) * N);
     L.asg_cnt = b.take(sizeof(int32_t) * (N / 16384 + 2));
-    c->pruned_run = c->cfg.use_mlp != 0;
+    c->pool_run = c->cfg.use_mlp != 0 && c->keep_pool;
     // every workgroup of the neighbour search may leave up to one partly used
     // chunk of the pool behind
-    L.pool_cap = c->pruned_run ? (int64_t)c->cfg.pool_per_cluster * N + (int64_t)(c->lc[5].grid + 1) * kPoolChunk : 0;
+    L.pool_cap = c->pool_run ? (int64_t)c->cfg.pool_per_cluster * N + (int64_t)(c->lc[5].grid + 1) * kPoolChunk : 0;
     if (L.pool_cap > (int64_t)0x7fff0000) L.pool_cap = 0x7fff0000;
     L.pfeat = b.take(sizeof(uint16_t) * kMlpInP * L.pool_cap);
     L.pd = b.take(sizeof(int32_t) * L.pool_cap);
     L.pu = b.take(sizeof(int32_t) * L.pool_cap);
     L.pc = b.take(sizeof(float) * L.pool_cap);
     L.pz = b.take(sizeof(float) * L.pool_cap);
-    L.hoff = b.take(c->pruned_run ? sizeof(int32_t) * N : 0);
-    L.hn1 = b.take(c->pruned_run ? sizeof(int32_t) * N : 0);
-    L.hn2 = b.take(c->pruned_run ? sizeof(int32_t) * N : 0);
+    L.hoff = b.take(c->pool_run ? sizeof(int32_t) * N : 0);
+    L.hn1 = b.take(c->pool_run ? sizeof(int32_t) * N : 0);
+    L.hn2 = b.take(c->pool_run ? sizeof(int32_t) * N : 0);
     const int64_t nblk = (std::max<int64_t>(std::max<int64_t>(W, trk_cap), NW) + kScanItems - 1) / kScanItems + 2;
     L.scan_tmp = b.take(sizeof(int32_t) * nblk);
     L.total = align_up(b.off, 256);
@@ -524,7 +536,8 @@ static tpcca_status plan(tpcca_ctx *c) {
     a.trk_cap = (int32_t)trk_cap;
     a.max_gap = c->cfg.max_gap;
     a.n_rb = nrb;
-    a.tile_budget = std::min(c->tile_budget, kTileCap);
+    // the pruned search without the pool stages smaller tiles
+    a.tile_budget = std::min(c->tile_budget, (c->cfg.use_mlp && !c->keep_pool) ? kPrCap : kTileCap);
     a.tile_cap = (int32_t)L.tile_cap;
     a.min_track_hits = c->cfg.min_track_hits;
     a.kf_passes = c->cfg.kf_passes;
@@ -611,7 +624,8 @@ static void bind_pointers(tpcca_ctx *c) {
     a.hoff = (int32_t *)(A + L.hoff);
     a.hn1 = (int32_t *)(A + L.hn1);
     a.hn2 = (int32_t *)(A + L.hn2);
-    a.use_mlp = (c->pruned_run && c->mlp_loaded) ? 1 : 0;
+    a.use_mlp = (c->cfg.use_mlp && c->mlp_loaded) ? 1 : 0;
+    a.keep_pool = (a.use_mlp && c->pool_run) ? 1 : 0;
     if (c->mlp) {
         a.mlp.w1 = (const uint16_t *)(c->mlp + MlpState::w1);
         a.mlp.w2 = (const uint16_t *)(c->mlp + MlpState::w2);
@@ -647,10 +661,12 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     launch_grid_rowsort(a, c->lc[4], s);
     launch_tiles(a, s);  // tile partition of the neighbour search (part of the search grid)
     mark(st++);
-    if (a.use_mlp) {
+    if (a.use_mlp && a.keep_pool) {
         launch_links_enum(a, c->lc[5], s);
         launch_mlp_infer(a.mlp, a.pfeat, &cnt->pool_next, a.pool_cap, a.pz, c->n_cu * 8, s);
         launch_select(a, c->lc[6], s);
+    } else if (a.use_mlp) {
+        launch_links_prune(a, c->lc[5], s);
     } else {
         launch_links(a, c->lc[5], s);
     }
@@ -816,7 +832,9 @@ tpcca_status tpcca_synchronize(tpcca_ctx *c) {
                             hipMemcpyDeviceToHost));
         if (ovf > 0) {
             c->have_results = false;
-            return fail(c, TPCCA_ERR_CAPACITY, "triplet pool overflow: raise pool_per_cluster");
+            return fail(c, TPCCA_ERR_CAPACITY, c->args.keep_pool
+                                                   ? "triplet pool overflow: raise pool_per_cluster"
+                                                   : "a pad row of a dense tile holds 2^24 or more clusters");
         }
     }
     if (__atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST)) {
@@ -1115,7 +1133,8 @@ tpcca_status tpcca_triplet_samples(tpcca_ctx *c, float keep, uint64_t seed, uint
     if (!c || !n_out || !(keep >= 0.f && keep <= 1.f) || cap < 0 || (cap > 0 && (!feat_dev || !label_dev)))
         return fail(c, TPCCA_ERR_INVALID_ARG, "keep in [0, 1], cap >= 0, output buffers for cap > 0");
     if (((uintptr_t)feat_dev & 15)) return fail(c, TPCCA_ERR_INVALID_ARG, "feature buffer must be 16-byte aligned");
-    if (!c->have_results || !c->args.use_mlp || !c->arena) return fail(c, TPCCA_ERR_STATE, "no pruned run to sample");
+    if (!c->have_results || !c->args.keep_pool || !c->arena)
+        return fail(c, TPCCA_ERR_STATE, "no pruned run that kept its triplet pool");
     unsigned long long *cnt_dev = nullptr;
     HIPCHK(c, hipMallocAsync((void **)&cnt_dev, sizeof(unsigned long long), c->stream));
     HIPCHK(c, hipMemsetAsync(cnt_dev, 0, sizeof(unsigned long long), c->stream));
@@ -1135,7 +1154,7 @@ tpcca_status tpcca_get_triplets(tpcca_ctx *c, int32_t frame, int32_t sector, int
     SiState st;
     tpcca_status s = locate(c, frame, sector, si, st);
     if (s != TPCCA_OK) return s;
-    if (!c->args.use_mlp) return fail(c, TPCCA_ERR_STATE, "the last run was not a pruned run");
+    if (!c->args.keep_pool) return fail(c, TPCCA_ERR_STATE, "the last run was not a pruned run that kept its triplet pool");
     const int nv = st.n_valid;
     std::vector<int32_t> hoff(nv), hn1(nv), hn2(nv);
     std::vector<Rec> rec(nv);

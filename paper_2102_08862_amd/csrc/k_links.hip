@@ -25,7 +25,9 @@
 // and, in each, binary-searches its first y cell. A tile too dense for LDS (a single coarse bin over budget)
 // runs the same search on global memory. Clusters without a g = 1 link go to
 // an LDS queue and are searched at g = 2 by the whole workgroup.
-#include "tpcca_internal.h"
+#include <type_traits>
+
+#include "mlp_tile.h"
 
 namespace tpcca {
 
@@ -34,6 +36,12 @@ constexpr int kSlots = kTileRows + 2 * kMaxGap;          // staged rows of a til
 constexpr int kTileFb = (kMaxTileCb + 2) * kFinePerCb;   // fine bins of a staged row
 constexpr int kBatch = 8;                                // down candidates held in registers
 constexpr int kQueueCap = 1024;                          // gap-2 queue of a tile (overflow: searched at once)
+constexpr int kPrK = 4;                                  // pruned search: pairs per cluster and round
+
+// The three searches: best pair (plain), every triplet to the pool (the
+// pool is kept for inspection and training), triplets scored by the
+// network inside the search (pruned).
+enum LinkMode { kPlain = 0, kEnum = 1, kPrune = 2 };
 
 // ---------------------------------------------------------------- tiles
 // One workgroup per (sector instance, row block): cumulative staged counts
@@ -201,6 +209,17 @@ __device__ inline void box_visit(const Rows &A, const TileGeo &G, const YCell &y
     }
 }
 
+// The pair score c of the middle cluster (yi, ti) between (yd, td) and (yu, tu).
+__device__ inline float pair_score(float yi, float ti, float yd, float td, float yu, float tu, float w) {
+    const float ady = __fsub_rn(yi, yd);
+    const float adt = __fsub_rn(ti, td);
+    const float by = __fsub_rn(yu, yd);
+    const float bt = __fsub_rn(tu, td);
+    const float ry = __fsub_rn(ady, __fmul_rn(w, by));
+    const float rt = __fsub_rn(adt, __fmul_rn(w, bt));
+    return __fadd_rn(__fmul_rn(ry, ry), __fmul_rn(rt, rt));
+}
+
 // Every accepted pair (c <= c2) of cluster (yi, ti) between staged rows jd
 // (down) and ju (up): on_pair(qd, yd, td, qu, yu, tu, c). Down candidates are
 // taken kBatch at a time into registers, then the up row is visited once per
@@ -241,25 +260,13 @@ __device__ inline void visit_pairs(const Rows &A, const TileGeo &G, const YCell 
 #pragma unroll
             for (int k = 0; k < kBatch; k++) {
                 if (k >= nd) break;
-                const float ady = __fsub_rn(yi, dy[k]);
-                const float adt = __fsub_rn(ti, dt[k]);
-                const float by = __fsub_rn(yu, dy[k]);
-                const float bt = __fsub_rn(tu, dt[k]);
-                const float ry = __fsub_rn(ady, __fmul_rn(w, by));
-                const float rt = __fsub_rn(adt, __fmul_rn(w, bt));
-                const float c = __fadd_rn(__fmul_rn(ry, ry), __fmul_rn(rt, rt));
+                const float c = pair_score(yi, ti, dy[k], dt[k], yu, tu, w);
                 if (c <= c2) on_pair(dq[k], dy[k], dt[k], qu, yu, tu, c);
             }
         });
         if (n_box && skip == 0) *n_box = seen + nu;
         if (seen <= skip + kBatch) return;
     }
-}
-
-__device__ inline uint16_t bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
 }
 
 // The 12 triplet features, every FP32 operation separately rounded in a
@@ -279,26 +286,28 @@ __device__ inline void triplet_features(float yd, float td, float xd, float yi, 
     const float dbc = __fsqrt_rn(__fadd_rn(__fmul_rn(ux, ux), __fmul_rn(dyu, dyu)));
     const float den = __fmul_rn(__fmul_rn(dab, dac), dbc);
     const float kap = __fdiv_rn(__fmul_rn(2.0f, cr), den);
-    f[0] = bf16_rne(__fdiv_rn(dyu, wy));
-    f[1] = bf16_rne(__fdiv_rn(dtu, wt));
-    f[2] = bf16_rne(__fdiv_rn(dyd, wy));
-    f[3] = bf16_rne(__fdiv_rn(dtd, wt));
-    f[4] = bf16_rne((float)g);
-    f[5] = bf16_rne(__fdiv_rn(xi, 245.0f));
-    f[6] = bf16_rne(__fdiv_rn(ry, c2s));
-    f[7] = bf16_rne(__fdiv_rn(rt, c2s));
-    f[8] = bf16_rne(__fdiv_rn(kap, 0.015f));
-    f[9] = bf16_rne(__fdiv_rn(by, cx));
-    f[10] = bf16_rne(__fdiv_rn(bt, cx));
-    f[11] = bf16_rne(__fdiv_rn((float)ncand, 8.0f));
+    f[0] = f2bf(__fdiv_rn(dyu, wy));
+    f[1] = f2bf(__fdiv_rn(dtu, wt));
+    f[2] = f2bf(__fdiv_rn(dyd, wy));
+    f[3] = f2bf(__fdiv_rn(dtd, wt));
+    f[4] = f2bf((float)g);
+    f[5] = f2bf(__fdiv_rn(xi, 245.0f));
+    f[6] = f2bf(__fdiv_rn(ry, c2s));
+    f[7] = f2bf(__fdiv_rn(rt, c2s));
+    f[8] = f2bf(__fdiv_rn(kap, 0.015f));
+    f[9] = f2bf(__fdiv_rn(by, cx));
+    f[10] = f2bf(__fdiv_rn(bt, cx));
+    f[11] = f2bf(__fdiv_rn((float)ncand, 8.0f));
     f[12] = f[13] = f[14] = f[15] = 0;
 }
 
-// Shared state of one tile.
-struct TileShared {
-    float2 yt[kTileCap];
-    uint8_t cell[kTileCap];
-    int16_t oq[kTileCap];
+// Shared state of one tile (Cap: clusters it can stage).
+template <int Cap>
+struct TileSharedT {
+    static constexpr int kCap = Cap;
+    float2 yt[Cap];
+    uint8_t cell[Cap];
+    int16_t oq[Cap];
     int16_t fs[kSlots][kTileFb + 1];
     int16_t queue[kQueueCap];
     YCell yc[kSlots];
@@ -310,10 +319,11 @@ struct TileShared {
     int32_t scan[kLinkBlock];
     int32_t item, nq, links, cpos, cend, pbase;
 };
+using TileShared = TileSharedT<kTileCap>;
 
 // Best pair of one cluster at gap g (false: none). bu/bd are sorted positions.
-template <class Rows>
-__device__ inline bool best_pair(const Rows &A, const TileGeo &G, const TileShared &T, const KArgs &a, int j, int r,
+template <class Rows, class TS>
+__device__ inline bool best_pair(const Rows &A, const TileGeo &G, const TS &T, const KArgs &a, int j, int r,
                                  int g, float yi, float ti, int &bu, int &bd) {
     const int jd = j - g, ju = j + g;
     const float w = a.w_tab[r * kMaxGap + g - 1];
@@ -345,14 +355,15 @@ __device__ inline bool best_pair(const Rows &A, const TileGeo &G, const TileShar
 }
 
 // Own cluster o of the tile -> staged row j and row-local index q.
-__device__ inline void own_locate(const TileShared &T, int jr0, int nown, int o, int &j, int &q) {
+template <class TS>
+__device__ inline void own_locate(const TS &T, int jr0, int nown, int o, int &j, int &q) {
     int k = 0;
     while (k + 1 < nown && T.opre[k + 1] <= o) k++;
     j = jr0 + k;
     q = T.olo[j] + (o - T.opre[k]);
 }
 
-template <bool Enum, bool InLds>
+template <int Mode, bool InLds>
 __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int si, int r0, int s0, int nown,
                            int own_total) {
     const int R = a.n_rows;
@@ -362,7 +373,7 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
     LdsRows L{T.yt, T.cell, T.oq, T.base, T.plo, T.fs};
     GlbRows Gl{a.rec, T.plo, T.n, a.coff + ((int64_t)si * R + s0) * (kNcbMax + 1), G};
     int nl = 0;
-    if (!Enum) {
+    if (Mode == kPlain) {
         for (int o = tid; o < own_total; o += kLinkBlock) {
             int j, q;
             own_locate(T, jr0, nown, o, j, q);
@@ -497,13 +508,271 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
     if ((tid & 63) == 0 && nl) atomicAdd(&T.links, nl);
 }
 
+// ---------------------------------------------------------------- pruned search
+// The network scores the candidate triplets inside the search, one wave at
+// a time (no workgroup barrier between the searches of a tile): per round,
+// every lane enumerates the accepted pairs of one cluster at one gap (up to
+// kPrK of them per round; a cluster with more takes further rounds of its
+// wave), the wave packs them into its LDS list in lane order, computes their
+// features one lane per pair, scores them in tiles of 16 on the matrix cores
+// (the arithmetic of the stand-alone inference), and
+// each lane keeps the best surviving pair of its cluster in the (c, up input
+// index, down input index) order. Gap 2 is searched only for clusters with
+// no surviving gap-1 pair, as in the plain finder: such clusters wait in
+// their wave's queue until 64 of them (or the tile's end) fill a round.
+constexpr int kWaves = kLinkBlock / 64;
+constexpr int kPrEntW = 64 * kPrK;             // pairs of one wave's round
+constexpr int kWq = kQueueCap / kWaves;        // gap-2 queue of a wave
+
+struct alignas(16) PruneShared {
+    uint32_t ed[kWaves][kPrEntW];   // down candidate (row-local) | owner lane << 24
+    uint32_t eu[kWaves][kPrEntW];   // up candidate (row-local) | pruned << 31
+    uint32_t feat[kWaves][64][6];   // BF16 features (pairs) of the pairs being scored
+    int32_t jq[kLinkBlock];         // owner thread -> staged row << 16 | row-local index
+    int32_t nbox[kLinkBlock];       // owner thread -> clusters in its two boxes at this gap
+    int32_t wnq[kWaves];            // queued clusters of each wave
+};
+using TilePr = TileSharedT<kPrCap>;
+
+// LDS written by lanes of one wave and read by others of the same wave:
+// the wave's LDS operations complete in order; this keeps the compiler from
+// moving them across.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline int wave_excl_scan(int v, int &total) {
+    const int lane = threadIdx.x & 63;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    total = __shfl(x, 63);
+    return x - v;
+}
+
+// One round of a wave: lane searches cluster (j, q) of row r at gap g if
+// act; bu/bd receive the best surviving pair (sorted positions) or stay -1.
+// Every lane of the wave must call it.
+template <class Rows>
+__device__ void prune_round(const KArgs &a, const Rows &A, const TileGeo &G, const TilePr &T, PruneShared &P,
+                            int s0, bool act, int j, int q, int r, int g, int &bu, int &bd, int &scored,
+                            int &pruned) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int jd = j - g, ju = j + g;
+    const float wy = a.win_y[g - 1], wt = a.win_t[g - 1];
+    uint32_t *ED = P.ed[wv], *EU = P.eu[wv];
+    float yi = 0.f, ti = 0.f, w = 0.f;
+    if (act) {
+        const float2 e = A.at(j, q);
+        yi = e.x;
+        ti = e.y;
+        w = a.w_tab[r * kMaxGap + g - 1];
+        P.jq[tid] = (j << 16) | q;
+    }
+    bool found = false;
+    float bc = 0.f;
+    int bqu = 0, bqd = 0;
+    int nbox = 0;
+    for (int skip = 0;; skip += kPrK) {
+        uint32_t kd[kPrK], ku[kPrK];
+        int ntot = 0;
+        if (act) {
+            auto take = [&](int qd, float, float, int qu, float, float, float) {
+                const int k = ntot - skip;
+#pragma unroll
+                for (int m = 0; m < kPrK; m++)
+                    if (m == k) {
+                        kd[m] = (uint32_t)qd;
+                        ku[m] = (uint32_t)qu;
+                    }
+                ntot++;
+            };
+            visit_pairs(A, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2, take,
+                        skip == 0 ? &nbox : nullptr);
+            if (skip == 0) P.nbox[tid] = nbox;
+        }
+        const int nk = act ? min(max(ntot - skip, 0), kPrK) : 0;
+        int total;
+        const int off = wave_excl_scan(nk, total);
+        total = __builtin_amdgcn_readfirstlane(total);
+#pragma unroll
+        for (int m = 0; m < kPrK; m++)
+            if (m < nk) {
+                ED[off + m] = kd[m] | ((uint32_t)lane << 24);
+                EU[off + m] = ku[m];
+            }
+        wave_lds_sync();
+        for (int sub = 0; sub < total; sub += 64) {
+            const int e = sub + lane;
+            if (e < total) {
+                const uint32_t ed = ED[e];
+                const int own = (wv << 6) | (int)(ed >> 24), qd = ed & 0xffffff, qu = EU[e];
+                const int jq = P.jq[own];
+                const int oj = jq >> 16, oq = jq & 0xffff, orr = s0 + oj;
+                const float2 ei = A.at(oj, oq), edn = A.at(oj - g, qd), eup = A.at(oj + g, qu);
+                uint16_t f[kMlpInP];
+                triplet_features(edn.x, edn.y, a.row_x[orr - g], ei.x, ei.y, a.row_x[orr], eup.x, eup.y,
+                                 a.row_x[orr + g], g, wy, wt, a.w_tab[orr * kMaxGap + g - 1], a.c2s, P.nbox[own], f);
+#pragma unroll
+                for (int k = 0; k < 6; k++) P.feat[wv][lane][k] = f[2 * k] | ((uint32_t)f[2 * k + 1] << 16);
+            }
+            wave_lds_sync();
+            const int nsub = min(total - sub, 64);
+            const int c = lane & 15, qq = lane >> 4;
+            // the weights are read once per step for its (up to 4) tiles;
+            // the empty asm keeps the loads from being hoisted into the search
+            MlpDev W = a.mlp;
+            asm volatile("" : "+s"(W.w1), "+s"(W.w2), "+s"(W.w3), "+s"(W.b1), "+s"(W.b2), "+s"(W.b3));
+            const int nt = (nsub + 15) >> 4;
+            v4s bx[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int el = t * 16 + c;
+                bx[t] = pack4(0, 0, 0, 0);
+                if (el < nsub && qq < 3) bx[t] = pack4(make_uint2(P.feat[wv][el][2 * qq], P.feat[wv][el][2 * qq + 1]));
+            }
+            float z[4];
+            mlp_logit4(MlpStream(W, lane), bx, nt, z);
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int el = t * 16 + c;
+                if (qq == 0 && el < nsub) {
+                    scored++;
+                    if (!(z[t] >= a.theta)) {
+                        EU[sub + el] |= 0x80000000u;
+                        pruned++;
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+#pragma unroll
+        for (int m = 0; m < kPrK; m++) {
+            if (m >= nk) break;
+            const uint32_t u = EU[off + m];
+            if (u & 0x80000000u) continue;
+            const int qd = (int)kd[m], qu = (int)(u & 0x7fffffffu);
+            const float2 ed = A.at(jd, qd), eu = A.at(ju, qu);
+            const float cc = pair_score(yi, ti, ed.x, ed.y, eu.x, eu.y, w);
+            bool better = !found || cc < bc;
+            if (found && cc == bc) {
+                const int idu = a.rec[A.pos(ju, qu)].id, idd = a.rec[A.pos(jd, qd)].id;
+                const int biu = a.rec[A.pos(ju, bqu)].id, bid = a.rec[A.pos(jd, bqd)].id;
+                better = idu < biu || (idu == biu && idd < bid);
+            }
+            if (better) {
+                found = true;
+                bc = cc;
+                bqu = qu;
+                bqd = qd;
+            }
+        }
+        // the list is rewritten by the next round
+        wave_lds_sync();
+        if (!__any(act && ntot > skip + kPrK)) break;
+    }
+    if (found) {
+        bu = A.pos(ju, bqu);
+        bd = A.pos(jd, bqd);
+    }
+}
+
+template <bool InLds>
+__device__ void tile_prune(const KArgs &a, TilePr &T, PruneShared &P, const TileGeo &G, int si, int r0, int s0,
+                           int nsr, int nown, int own_total) {
+    const int R = a.n_rows;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int jr0 = r0 - s0;
+    const int G2 = a.max_gap;
+    LdsRows L{T.yt, T.cell, T.oq, T.base, T.plo, T.fs};
+    GlbRows Gl{a.rec, T.plo, T.n, a.coff + ((int64_t)si * R + s0) * (kNcbMax + 1), G};
+    if (!InLds) {
+        // row-local indices travel in 24 bits (an error of the run otherwise)
+        bool big = false;
+        for (int j = 0; j < nsr; j++) big |= T.n[j] >= (1 << 24);
+        if (big) {
+            if (tid == 0) atomicAdd(&a.cnt->pool_overflow, 1);
+            return;
+        }
+    }
+    int16_t *WQ = T.queue + wv * kWq;
+    if (lane == 0) P.wnq[wv] = 0;
+    wave_lds_sync();
+    int nl = 0, scored = 0, pruned = 0;
+    auto round = [&](bool act, int o, int g, bool queue_g2) {
+        int j = 0, q = 0, r = 0;
+        if (act) {
+            own_locate(T, jr0, nown, o, j, q);
+            r = s0 + j;
+            act = r - g >= 0 && r + g <= R - 1;
+        }
+        int bu = -1, bd = -1;
+        if (InLds) prune_round(a, L, G, T, P, s0, act, j, q, r, g, bu, bd, scored, pruned);
+        else prune_round(a, Gl, G, T, P, s0, act, j, q, r, g, bu, bd, scored, pruned);
+        const bool g2 = o >= 0 && queue_g2 && bu < 0 && G2 >= 2 && r >= 2 && r + 2 <= R - 1;
+        const uint64_t m = __ballot(g2);
+        if (g2) WQ[P.wnq[wv] + __popcll(m & ((1ull << lane) - 1ull))] = (int16_t)o;
+        else if (o >= 0) {
+            a.link[InLds ? L.pos(j, q) : Gl.pos(j, q)] = make_int2(bu, bd);
+            nl += (bu >= 0);
+        }
+        wave_lds_sync();
+        if (lane == 0) P.wnq[wv] += __popcll(m);
+        wave_lds_sync();
+    };
+    // the waves take the tile's own clusters 64 at a time, round robin; a
+    // full queue (64) is searched at gap 2 before the next 64 clusters, the
+    // rest at the end (one call site: the round is inlined once)
+    int base = wv * 64;
+    for (;;) {
+        const int nq = __builtin_amdgcn_readfirstlane(P.wnq[wv]);
+        const bool drain = nq >= 64 || (base >= own_total && nq > 0);
+        if (!drain && base >= own_total) break;
+        int o;
+        bool act;
+        if (drain) {
+            const int take = min(nq, 64);
+            act = lane < take;
+            o = act ? (int)WQ[nq - take + lane] : -1;
+            wave_lds_sync();
+            if (lane == 0) P.wnq[wv] = nq - take;
+            wave_lds_sync();
+        } else {
+            o = base + lane;
+            act = o < own_total;
+            if (!act) o = -1;
+            base += kLinkBlock;
+        }
+        round(act, o, drain ? 2 : 1, !drain);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        nl += __shfl_xor(nl, off);
+        scored += __shfl_xor(scored, off);
+        pruned += __shfl_xor(pruned, off);
+    }
+    if (lane == 0) {
+        if (nl) atomicAdd(&T.links, nl);
+        if (scored) atomicAdd(&a.cnt->pool_used, scored);
+        if (pruned) atomicAdd(&a.cnt->n_pruned, pruned);
+    }
+}
+
 // InLds: tiles from the work queue, searched in LDS; a tile over the LDS
 // budget is appended to the overflow list. !InLds: the overflow tiles, one
 // workgroup each, searched in global memory (a separate kernel, so that the
 // common kernel keeps its register budget).
-template <bool Enum, bool InLds>
-__global__ __launch_bounds__(kLinkBlock, Enum ? 3 : 4) void k_links(KArgs a) {
-    __shared__ TileShared T;
+template <int Mode> struct ModeShared {};
+template <> struct ModeShared<kPrune> { PruneShared P; };
+
+template <int Mode, bool InLds>
+__global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KArgs a) {
+    using TS = std::conditional_t<Mode == kPrune, TilePr, TileShared>;
+    __shared__ TS T;
+    __shared__ ModeShared<Mode> X;
     const int R = a.n_rows;
     const int tid = threadIdx.x;
     const int n_tiles = InLds ? min(a.cnt->n_tiles, a.tile_cap) : min(a.cnt->n_glb_tiles, a.tile_cap);
@@ -565,7 +834,7 @@ __global__ __launch_bounds__(kLinkBlock, Enum ? 3 : 4) void k_links(KArgs a) {
         __syncthreads();
         const int total = T.base[nsr];
         const int own_total = T.opre[nown];
-        if (InLds && total > kTileCap) {
+        if (InLds && total > TS::kCap) {
             if (tid == 0) a.glb_tiles[atomicAdd(&a.cnt->n_glb_tiles, 1)] = item;
             continue;   // uniform: every thread skips the tile
         }
@@ -626,9 +895,11 @@ __global__ __launch_bounds__(kLinkBlock, Enum ? 3 : 4) void k_links(KArgs a) {
                 }
             }
             __syncthreads();
-            tile_links<Enum, true>(a, T, G, si, r0, s0, nown, own_total);
+            if constexpr (Mode == kPrune) tile_prune<true>(a, T, X.P, G, si, r0, s0, nsr, nown, own_total);
+            else tile_links<Mode, true>(a, T, G, si, r0, s0, nown, own_total);
         } else {
-            tile_links<Enum, false>(a, T, G, si, r0, s0, nown, own_total);
+            if constexpr (Mode == kPrune) tile_prune<false>(a, T, X.P, G, si, r0, s0, nsr, nown, own_total);
+            else tile_links<Mode, false>(a, T, G, si, r0, s0, nown, own_total);
         }
         __syncthreads();
         if (tid == 0 && T.links) atomicAdd(&a.cnt->n_links, T.links);
@@ -636,13 +907,21 @@ __global__ __launch_bounds__(kLinkBlock, Enum ? 3 : 4) void k_links(KArgs a) {
 }
 
 void launch_links(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL((k_links<false, true>), dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
-    hipLaunchKernelGGL((k_links<false, false>), dim3(max(l.grid / 4, 1)), dim3(kLinkBlock), 0, s, a);
+    hipLaunchKernelGGL((k_links<kPlain, true>), dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
+    hipLaunchKernelGGL((k_links<kPlain, false>), dim3(max(l.grid / 4, 1)), dim3(kLinkBlock), 0, s, a);
 }
 
 void launch_links_enum(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL((k_links<true, true>), dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
-    hipLaunchKernelGGL((k_links<true, false>), dim3(max(l.grid / 4, 1)), dim3(kLinkBlock), 0, s, a);
+    hipLaunchKernelGGL((k_links<kEnum, true>), dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
+    hipLaunchKernelGGL((k_links<kEnum, false>), dim3(max(l.grid / 4, 1)), dim3(kLinkBlock), 0, s, a);
+}
+
+void launch_links_prune(const KArgs &a, Launch l, hipStream_t s) {
+    // three workgroups per CU fit the LDS of a pruned search; dense tiles
+    // are more frequent at its smaller tile size, so both launches are full
+    const int grid = max(l.grid / 4 * 3, 1);
+    hipLaunchKernelGGL((k_links<kPrune, true>), dim3(grid), dim3(kLinkBlock), 0, s, a);
+    hipLaunchKernelGGL((k_links<kPrune, false>), dim3(grid), dim3(kLinkBlock), 0, s, a);
 }
 
 // Pruned links: per cluster, the best pair among its triplets whose logit

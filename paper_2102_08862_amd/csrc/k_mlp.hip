@@ -1,63 +1,17 @@
-// Triplet network inference on the matrix cores: z = w3 . relu(W2 relu(W1 x
-// + b1) + b2) + b3 for every candidate triplet of the pruned neighbour
-// finder (12 features padded to 16, 64 and 64 hidden units, BF16 weights and
-// activations, FP32 accumulation).
-//
-// Each layer is computed transposed, H^T = W X^T, with
-// v_mfma_f32_16x16x16_bf16 (A = a 16x16 weight tile held in registers, B =
-// 16 triplets): lane l = 16 q + c holds column c (one triplet) and rows
-// 4q..4q+3 of every tile, which is exactly the B-operand layout of the next
-// layer, so activations never leave registers. The last layer (64 -> 1) is
-// a dot product finished with two cross-lane shuffles.
-#include "tpcca_internal.h"
+// Triplet network inference on the matrix cores over a list of triplets
+// (the per-tile arithmetic and its register layout are in mlp_tile.h), and
+// the training step of the same network.
+#include "mlp_tile.h"
 
 namespace tpcca {
-
-typedef short v4s __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-__device__ inline uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite values)
-    return (uint16_t)(u >> 16);
-}
-__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-__device__ inline v4s pack4(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
-    v4s r;
-    r.x = (short)a;
-    r.y = (short)b;
-    r.z = (short)c;
-    r.w = (short)d;
-    return r;
-}
 
 // Logits of triplets [0, n): X is [n][16] BF16 (row-major), z out FP32.
 __global__ __launch_bounds__(256) void k_mlp_infer(MlpDev W, const uint16_t *__restrict__ X,
                                                    const int32_t *n_dev, int32_t n_cap, float *__restrict__ z) {
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, c = lane & 15;
-    // weights as A operands: tile mt covers hidden units 16 mt .. 16 mt + 15
-    v4s A1[4], A2[4][4];
-    v4f C1[4], C2[4];
-    float w3v[4][4];
-#pragma unroll
-    for (int mt = 0; mt < 4; mt++) {
-        const uint16_t *r1 = W.w1 + (16 * mt + c) * kMlpInP + 4 * q;
-        A1[mt] = pack4(r1[0], r1[1], r1[2], r1[3]);
-#pragma unroll
-        for (int ks = 0; ks < 4; ks++) {
-            const uint16_t *r2 = W.w2 + (16 * mt + c) * kMlpH + 16 * ks + 4 * q;
-            A2[mt][ks] = pack4(r2[0], r2[1], r2[2], r2[3]);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            C1[mt][r] = W.b1[16 * mt + 4 * q + r];
-            C2[mt][r] = W.b2[16 * mt + 4 * q + r];
-            w3v[mt][r] = bf2f(W.w3[16 * mt + 4 * q + r]);
-        }
-    }
-    const float b3 = *W.b3;
+    MlpTile M;
+    M.load(W, lane);
     const int n = n_dev ? min(*n_dev, n_cap) : n_cap;
     const int ntiles = (n + 15) >> 4;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -65,30 +19,9 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpDev W, const uint16_t *__r
     for (int tile = wave; tile < ntiles; tile += nwaves) {
         const int t = tile * 16 + c;
         v4s bx = pack4(0, 0, 0, 0);
-        if (t < n) {
-            const uint2 v = *reinterpret_cast<const uint2 *>(X + (int64_t)t * kMlpInP + 4 * q);
-            bx = pack4((uint16_t)(v.x & 0xffff), (uint16_t)(v.x >> 16), (uint16_t)(v.y & 0xffff),
-                       (uint16_t)(v.y >> 16));
-        }
-        v4s h1[4];
-#pragma unroll
-        for (int mt = 0; mt < 4; mt++) {
-            const v4f d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A1[mt], bx, C1[mt], 0, 0, 0);
-            h1[mt] = pack4(f2bf(fmaxf(d[0], 0.f)), f2bf(fmaxf(d[1], 0.f)), f2bf(fmaxf(d[2], 0.f)),
-                           f2bf(fmaxf(d[3], 0.f)));
-        }
-        float part = 0.f;
-#pragma unroll
-        for (int mt = 0; mt < 4; mt++) {
-            v4f d = C2[mt];
-#pragma unroll
-            for (int ks = 0; ks < 4; ks++) d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A2[mt][ks], h1[ks], d, 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 4; r++) part += w3v[mt][r] * bf2f(f2bf(fmaxf(d[r], 0.f)));
-        }
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        if (q == 0 && t < n) z[t] = part + b3;
+        if (t < n) bx = pack4(*reinterpret_cast<const uint2 *>(X + (int64_t)t * kMlpInP + 4 * q));
+        const float zz = M.logit(bx);
+        if (q == 0 && t < n) z[t] = zz;
     }
 }
 
@@ -205,12 +138,12 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train(MlpTrainArgs T) 
             for (int r = 0; r < 4; r++) {
                 m2[mt][r] = d[r] > 0.f;
                 h2[mt][r] = bf2f(f2bf(fmaxf(d[r], 0.f)));
-                part += sw3[16 * mt + 4 * q + r] * h2[mt][r];
+                part = __fmaf_rn(sw3[16 * mt + 4 * q + r], h2[mt][r], part);
             }
         }
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        const float z = part + b3;
+        part = __fadd_rn(part, __shfl_xor(part, 16));
+        part = __fadd_rn(part, __shfl_xor(part, 32));
+        const float z = __fadd_rn(part, b3);
         float dz = 0.f;
         if (valid) {
             const float yv = T.Y[t];

@@ -16,6 +16,7 @@ constexpr int kFinePerCb = 4;      // fine bins per coarse bin (row sort)
 constexpr int kTileRows = 8;       // own pad rows of a neighbour-finding tile
 constexpr int kMaxTileCb = 16;     // most own coarse bins of a tile
 constexpr int kTileCap = 3072;     // clusters a tile stages in LDS (own rows, +-kMaxGap rows, time halo)
+constexpr int kPrCap = 2816;       // the same for the pruned search (its LDS also holds pairs and the network)
 constexpr int kMaxYCells = 32;     // y cells per pad row in the row order
 constexpr int kChunk = 8192;       // clusters per histogram / scatter work item
 constexpr int kScanItems = 2048;   // elements per block of the device-wide scans
@@ -210,6 +211,7 @@ struct KArgs {
     const volatile int32_t *abort_flag;  // host-mapped
     // learned pruning (pruned runs only)
     int32_t use_mlp;
+    int32_t keep_pool;       // pruned run through the triplet pool (else scored in the search)
     float theta;             // prune triplets with logit < theta
     float c2s;               // sqrt(pair_c2), FP32
     int32_t pool_cap;
@@ -267,6 +269,7 @@ void launch_grid_rowsort(const KArgs &a, Launch l, hipStream_t s);
 void launch_tiles(const KArgs &a, hipStream_t s);
 void launch_links(const KArgs &a, Launch l, hipStream_t s);
 void launch_links_enum(const KArgs &a, Launch l, hipStream_t s);
+void launch_links_prune(const KArgs &a, Launch l, hipStream_t s);
 void launch_select(const KArgs &a, Launch l, hipStream_t s);
 void launch_samples(const KArgs &a, float keep, uint64_t seed, uint16_t *feat, float *label, int64_t cap,
                     unsigned long long *n_out, int grid, hipStream_t s);

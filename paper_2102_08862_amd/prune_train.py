@@ -327,8 +327,12 @@ def main(argv=None):
     x_row, _ = synth.geometry()
 
     def make_tracker(**kw):
+        # training, threshold and gain test count every candidate triplet:
+        # pruned runs keep the triplet pool
         kw.setdefault("pool_per_cluster", 12)
-        return tpcca.Tracker(row_x=x_row, **kw)
+        t = tpcca.Tracker(row_x=x_row, **kw)
+        t.set_triplet_pool(True)
+        return t
 
     trk = make_tracker()
     report = {"seeds": {}}

@@ -80,7 +80,7 @@ EXPORTS = [
     "tpcca_get_stats", "tpcca_get_tracks", "tpcca_get_track_clusters", "tpcca_get_assignment",
     "tpcca_get_links", "tpcca_mlp_state_bytes", "tpcca_mlp_attach", "tpcca_mlp_load", "tpcca_mlp_fetch",
     "tpcca_mlp_infer", "tpcca_mlp_grad", "tpcca_mlp_train_step", "tpcca_get_triplets", "tpcca_set_graph",
-    "tpcca_set_launch", "tpcca_set_pruning", "tpcca_copy", "tpcca_triplet_samples",
+    "tpcca_set_launch", "tpcca_set_pruning", "tpcca_set_triplet_pool", "tpcca_copy", "tpcca_triplet_samples",
 ]
 
 MLP_NPARAM = 5313
@@ -132,6 +132,7 @@ def load_library(path: str = LIB_PATH):
         "tpcca_set_graph": [P, I32],
         "tpcca_set_launch": [P, I32, I32, I32],
         "tpcca_set_pruning": [P, I32, ctypes.c_float],
+        "tpcca_set_triplet_pool": [P, I32],
         "tpcca_copy": [P, P, P, SZ],
         "tpcca_triplet_samples": [P, ctypes.c_float, ctypes.c_uint64, P, P, I64, ctypes.POINTER(I64)],
     }
@@ -331,6 +332,11 @@ class Tracker:
         self._check(self.lib.tpcca_set_pruning(self.h, 1 if use_mlp else 0, float(threshold)))
         self.config.use_mlp = 1 if use_mlp else 0
         self.config.mlp_logit_threshold = float(threshold)
+
+    def set_triplet_pool(self, keep: bool):
+        """Pruned runs list every triplet in a pool (for triplets() and
+        triplet_samples()) instead of scoring them inside the search."""
+        self._check(self.lib.tpcca_set_triplet_pool(self.h, 1 if keep else 0))
 
     def copy(self, src, dst):
         """Plain device copy kernel (counter calibration): src -> dst, torch tensors."""

@@ -129,6 +129,7 @@ def test_pruned_run_triplets_and_links(tp, x):
     m = oracle.MLP.random(15)
     # theta = -inf: no pruning, links identical to the plain finder
     trk = tp.Tracker(use_mlp=1, mlp_logit_threshold=-1e30)
+    trk.set_triplet_pool(True)
     trk.mlp_load(m.flat())
     f = trk.add_frame()
     trk.load_sector(f, 0, row, y, t)
@@ -159,3 +160,77 @@ def test_pruned_run_triplets_and_links(tp, x):
     print("pruned: %d of %d clusters compared, %d pruned triplets" % (ok.sum(), len(ok), trk2.stats()["n_pruned"]))
     assert ok.mean() > 0.99
     assert np.array_equal(up[ok], oup[ok]) and np.array_equal(dn[ok], odn[ok])
+    # the same run through the triplet pool gives the same links everywhere
+    trk2.set_triplet_pool(True)
+    trk2.run(sync=True)
+    up2, dn2 = trk2.links(g, 0)
+    assert np.array_equal(up, up2) and np.array_equal(dn, dn2)
+
+
+def _pruned_links(tp, fr, sectors, params, th, pool, **cfg):
+    trk = tp.Tracker(use_mlp=1, mlp_logit_threshold=th, **cfg)
+    trk.set_triplet_pool(pool)
+    trk.mlp_load(params)
+    f = trk.load_frame(fr, sectors=sectors)
+    trk.run(sync=True)
+    st = trk.stats()
+    assert st["mlp_used"] == 1 and st["n_pool_overflow"] == 0
+    return [trk.links(f, s) for s in sectors], [trk.assignment(f, s) for s in sectors], st
+
+
+@pytest.mark.parametrize("which", ["random", "trained"])
+def test_pruned_search_equals_pool_path(tp, x, which):
+    """Scoring inside the search (gap 2 only where no gap-1 triplet
+    survives) gives bit-identical links and assignment to scoring every
+    triplet from the pool, over a 1 ms slice and at a threshold that prunes
+    a large share."""
+    from paper_2102_08862_amd import prune_train
+    fr = synth.generate("slice_1ms", seed=22)
+    secs = [0, 7, 20, 35]
+    if which == "trained":
+        params, meta = prune_train.load_weights()
+        assert params is not None, "trained weights missing"
+        th = float(meta["theta"])
+    else:
+        m = oracle.MLP.random(16)
+        params = m.flat()
+        th = 0.0
+    la, aa, sa = _pruned_links(tp, fr, secs, params, th, False, row_x=x)
+    lb, ab, sb = _pruned_links(tp, fr, secs, params, th, True, row_x=x)
+    print("%s: scored %d of %d triplets, pruned %d / %d" % (which, sa["n_triplets"], sb["n_triplets"],
+                                                           sa["n_pruned"], sb["n_pruned"]))
+    assert 0 < sa["n_triplets"] <= sb["n_triplets"] and sa["n_pruned"] > 0
+    assert sa["n_links"] == sb["n_links"]
+    for (u1, d1), (u2, d2), a1, a2 in zip(la, lb, aa, ab):
+        assert np.array_equal(u1, u2) and np.array_equal(d1, d2)
+        assert np.array_equal(a1, a2)
+
+
+def test_pruned_search_dense_tiles(tp, x):
+    """Tiles too dense for LDS take the global-memory pruned search: still
+    identical to the pool path."""
+    rng = np.random.default_rng(12)
+    n = 12000
+    row = rng.integers(20, 26, n).astype(np.uint8)
+    y = (np.round(rng.uniform(-20, 20, n) * 64) / 64).astype(np.float32)
+    t = (np.round(rng.uniform(0, 40, n) * 64) / 64).astype(np.float32)
+    fr = synth.generate("sector_300", seed=4)
+    r0, y0, t0 = fr.sector(0)
+    row = np.concatenate([row, r0]); y = np.concatenate([y, y0]); t = np.concatenate([t, t0])
+    m = oracle.MLP.random(17)
+    res = []
+    for pool in (False, True):
+        print("case dense pruned, pool %d" % pool, flush=True)
+        trk = tp.Tracker(use_mlp=1, mlp_logit_threshold=0.0, row_x=x, pool_per_cluster=64, min_track_hits=3)
+        trk.set_triplet_pool(pool)
+        trk.mlp_load(m.flat())
+        f = trk.add_frame()
+        trk.load_sector(f, 0, row, y, t)
+        trk.run(sync=True)
+        st = trk.stats()
+        assert st["n_overflow_tiles"] > 0 and st["n_pool_overflow"] == 0
+        res.append((trk.links(f, 0), trk.assignment(f, 0), st))
+    ((u1, d1), a1, s1), ((u2, d2), a2, s2) = res
+    print("dense: %d overflow tiles, links %d, scored %d of %d" % (s1["n_overflow_tiles"], s1["n_links"],
+                                                                  s1["n_triplets"], s2["n_triplets"]))
+    assert np.array_equal(u1, u2) and np.array_equal(d1, d2) and np.array_equal(a1, a2)

@@ -17,6 +17,7 @@ def test_labels_match_chains_and_training_separates():
     trk = tpcca.Tracker(row_x=x)
     trk.mlp_load(prune_train.init_params(1))
     trk.set_pruning(True, -1e30)
+    trk.set_triplet_pool(True)
     f = trk.load_frame(fr, sectors=[0])
     trk.run(sync=True)
     xs, ys, n_all, n_pos = prune_train.frame_triplets(trk, f, 1, 1.0, np.random.default_rng(0))
@@ -48,6 +49,7 @@ def test_device_samples_match_host_labels():
     trk = tpcca.Tracker(row_x=x)
     trk.mlp_load(prune_train.init_params(2))
     trk.set_pruning(True, -1e30)
+    trk.set_triplet_pool(True)
     f = trk.load_frame(fr, sectors=[0])
     trk.run(sync=True)
     xs, ys, n_all, n_pos = prune_train.frame_triplets(trk, f, 1, 1.0, np.random.default_rng(0))
