@@ -302,14 +302,14 @@ __device__ inline void triplet_features(float yd, float td, float xd, float yi, 
 }
 
 // Shared state of one tile (Cap: clusters it can stage).
-template <int Cap>
+template <int Cap, int QCap = kQueueCap>
 struct TileSharedT {
     static constexpr int kCap = Cap;
     float2 yt[Cap];
     uint8_t cell[Cap];
     int16_t oq[Cap];
     int16_t fs[kSlots][kTileFb + 1];
-    int16_t queue[kQueueCap];
+    int16_t queue[QCap];
     YCell yc[kSlots];
     int32_t base[kSlots + 1];      // LDS index of each staged row (prefix of n)
     int32_t plo[kSlots];           // first staged sorted position of each row
@@ -522,17 +522,23 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
 // their wave's queue until 64 of them (or the tile's end) fill a round.
 constexpr int kWaves = kLinkBlock / 64;
 constexpr int kPrEntW = 64 * kPrK;             // pairs of one wave's round
-constexpr int kWq = kQueueCap / kWaves;        // gap-2 queue of a wave
+constexpr int kWq = 128;                       // gap-2 queue of a wave
 
-struct alignas(16) PruneShared {
+// Lds: the tile is staged in LDS, so a row-local index and a box count are
+// below kTileCap and travel in 16 bits (global-memory tiles: 32 bits).
+template <bool Lds>
+struct alignas(16) PruneSharedT {
+    using Idx = std::conditional_t<Lds, uint16_t, int32_t>;
+    static constexpr int kJqShift = Lds ? 12 : 24;   // staged row << shift | row-local index
     uint32_t ed[kWaves][kPrEntW];   // down candidate (row-local) | owner lane << 24
     uint32_t eu[kWaves][kPrEntW];   // up candidate (row-local) | pruned << 31
     uint32_t feat[kWaves][64][6];   // BF16 features (pairs) of the pairs being scored
-    int32_t jq[kLinkBlock];         // owner thread -> staged row << 16 | row-local index
-    int32_t nbox[kLinkBlock];       // owner thread -> clusters in its two boxes at this gap
+    Idx jq[kLinkBlock];             // owner thread -> staged row and row-local index
+    Idx nbox[kLinkBlock];           // owner thread -> clusters in its two boxes at this gap
     int32_t wnq[kWaves];            // queued clusters of each wave
 };
-using TilePr = TileSharedT<kPrCap>;
+static_assert(kTileCap <= (1 << 12) && kPrCap <= kTileCap, "16-bit LDS indices");
+using TilePr = TileSharedT<kPrCap, kWaves * kWq>;
 
 // LDS written by lanes of one wave and read by others of the same wave:
 // the wave's LDS operations complete in order; this keeps the compiler from
@@ -557,8 +563,8 @@ __device__ inline int wave_excl_scan(int v, int &total) {
 // One round of a wave: lane searches cluster (j, q) of row r at gap g if
 // act; bu/bd receive the best surviving pair (sorted positions) or stay -1.
 // Every lane of the wave must call it.
-template <class Rows>
-__device__ void prune_round(const KArgs &a, const Rows &A, const TileGeo &G, const TilePr &T, PruneShared &P,
+template <class Rows, class PS>
+__device__ void prune_round(const KArgs &a, const Rows &A, const TileGeo &G, const TilePr &T, PS &P,
                             int s0, bool act, int j, int q, int r, int g, int &bu, int &bd, int &scored,
                             int &pruned) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -571,7 +577,7 @@ __device__ void prune_round(const KArgs &a, const Rows &A, const TileGeo &G, con
         yi = e.x;
         ti = e.y;
         w = a.w_tab[r * kMaxGap + g - 1];
-        P.jq[tid] = (j << 16) | q;
+        P.jq[tid] = (typename PS::Idx)((j << PS::kJqShift) | q);
     }
     bool found = false;
     float bc = 0.f;
@@ -593,7 +599,7 @@ __device__ void prune_round(const KArgs &a, const Rows &A, const TileGeo &G, con
             };
             visit_pairs(A, G, T.yc[jd], T.yc[ju], jd, ju, yi, ti, w, wy, wt, a.pair_c2, take,
                         skip == 0 ? &nbox : nullptr);
-            if (skip == 0) P.nbox[tid] = nbox;
+            if (skip == 0) P.nbox[tid] = (typename PS::Idx)nbox;
         }
         const int nk = act ? min(max(ntot - skip, 0), kPrK) : 0;
         int total;
@@ -612,7 +618,7 @@ __device__ void prune_round(const KArgs &a, const Rows &A, const TileGeo &G, con
                 const uint32_t ed = ED[e];
                 const int own = (wv << 6) | (int)(ed >> 24), qd = ed & 0xffffff, qu = EU[e];
                 const int jq = P.jq[own];
-                const int oj = jq >> 16, oq = jq & 0xffff, orr = s0 + oj;
+                const int oj = jq >> PS::kJqShift, oq = jq & ((1 << PS::kJqShift) - 1), orr = s0 + oj;
                 const float2 ei = A.at(oj, oq), edn = A.at(oj - g, qd), eup = A.at(oj + g, qu);
                 uint16_t f[kMlpInP];
                 triplet_features(edn.x, edn.y, a.row_x[orr - g], ei.x, ei.y, a.row_x[orr], eup.x, eup.y,
@@ -682,7 +688,7 @@ __device__ void prune_round(const KArgs &a, const Rows &A, const TileGeo &G, con
 }
 
 template <bool InLds>
-__device__ void tile_prune(const KArgs &a, TilePr &T, PruneShared &P, const TileGeo &G, int si, int r0, int s0,
+__device__ void tile_prune(const KArgs &a, TilePr &T, PruneSharedT<InLds> &P, const TileGeo &G, int si, int r0, int s0,
                            int nsr, int nown, int own_total) {
     const int R = a.n_rows;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -765,14 +771,14 @@ __device__ void tile_prune(const KArgs &a, TilePr &T, PruneShared &P, const Tile
 // budget is appended to the overflow list. !InLds: the overflow tiles, one
 // workgroup each, searched in global memory (a separate kernel, so that the
 // common kernel keeps its register budget).
-template <int Mode> struct ModeShared {};
-template <> struct ModeShared<kPrune> { PruneShared P; };
+template <int Mode, bool InLds> struct ModeShared {};
+template <bool InLds> struct ModeShared<kPrune, InLds> { PruneSharedT<InLds> P; };
 
 template <int Mode, bool InLds>
 __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KArgs a) {
     using TS = std::conditional_t<Mode == kPrune, TilePr, TileShared>;
     __shared__ TS T;
-    __shared__ ModeShared<Mode> X;
+    __shared__ ModeShared<Mode, InLds> X;
     const int R = a.n_rows;
     const int tid = threadIdx.x;
     const int n_tiles = InLds ? min(a.cnt->n_tiles, a.tile_cap) : min(a.cnt->n_glb_tiles, a.tile_cap);
@@ -895,10 +901,10 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
                 }
             }
             __syncthreads();
-            if constexpr (Mode == kPrune) tile_prune<true>(a, T, X.P, G, si, r0, s0, nsr, nown, own_total);
+            if constexpr (Mode == kPrune) tile_prune<InLds>(a, T, X.P, G, si, r0, s0, nsr, nown, own_total);
             else tile_links<Mode, true>(a, T, G, si, r0, s0, nown, own_total);
         } else {
-            if constexpr (Mode == kPrune) tile_prune<false>(a, T, X.P, G, si, r0, s0, nsr, nown, own_total);
+            if constexpr (Mode == kPrune) tile_prune<InLds>(a, T, X.P, G, si, r0, s0, nsr, nown, own_total);
             else tile_links<Mode, false>(a, T, G, si, r0, s0, nown, own_total);
         }
         __syncthreads();

@@ -16,7 +16,7 @@ constexpr int kFinePerCb = 4;      // fine bins per coarse bin (row sort)
 constexpr int kTileRows = 8;       // own pad rows of a neighbour-finding tile
 constexpr int kMaxTileCb = 16;     // most own coarse bins of a tile
 constexpr int kTileCap = 3072;     // clusters a tile stages in LDS (own rows, +-kMaxGap rows, time halo)
-constexpr int kPrCap = 2816;       // the same for the pruned search (its LDS also holds pairs and the network)
+constexpr int kPrCap = 3072;       // the same for the pruned search (its LDS also holds the pair lists)
 constexpr int kMaxYCells = 32;     // y cells per pad row in the row order
 constexpr int kChunk = 8192;       // clusters per histogram / scatter work item
 constexpr int kScanItems = 2048;   // elements per block of the device-wide scans
