@@ -40,7 +40,7 @@ STAGE_BYTES = {
     "scatter": lambda s: 25 * s["n_clusters"],
     "rowsort": lambda s: 32 * s["n_clusters"],
     "links": lambda s: 24 * s["n_clusters"],
-    "seeds": lambda s: 8 * s["n_clusters"],
+    "seeds": lambda s: 12 * s["n_clusters"],
     "emit": lambda s: 41 * s["n_track_clusters"],
     "fit": lambda s: 9 * s["n_track_clusters"] + 128 * s["n_tracks"],
 }

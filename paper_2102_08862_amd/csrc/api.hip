@@ -38,7 +38,7 @@ struct Layout {
     size_t rcnt, rstart, rcur, coff;
     size_t tstart, ntile, tile_base, tiles, glb_tiles;
     int64_t tile_cap = 0;
-    size_t tmp, rec, link;
+    size_t tmp, rec, link, upc;
     size_t seeds, tseed, tlen, tslot, tprov, prov;
     size_t bits, wpre;
     size_t trk_len, trk_seed, cl_off, trk;
@@ -479,6 +479,7 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.tmp = b.take(std::max(sizeof(Rec) * N, sizeof(int2) * (size_t)(N + 16384)));
     L.rec = b.take(sizeof(Rec) * N);
     L.link = b.take(sizeof(int2) * N);
+    L.upc = b.take(sizeof(int32_t) * N);
     L.seeds = b.take(sizeof(int32_t) * seed_cap);
     L.tseed = b.take(sizeof(int32_t) * tseed_cap);
     L.tlen = b.take(sizeof(int32_t) * tseed_cap);
@@ -594,6 +595,7 @@ static void bind_pointers(tpcca_ctx *c) {
     a.tmp = (Rec *)(A + L.tmp);
     a.rec = (Rec *)(A + L.rec);
     a.link = (int2 *)(A + L.link);
+    a.upc = (int32_t *)(A + L.upc);
     a.seeds = (int32_t *)(A + L.seeds);
     a.tseed = (int32_t *)(A + L.tseed);
     a.tlen = (int32_t *)(A + L.tlen);

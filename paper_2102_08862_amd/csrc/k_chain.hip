@@ -1,8 +1,9 @@
 // Cellular-automaton stage and track output.
 //
 //   k_seeds      one lane per cluster: mutual-link test of its up and down
-//                links (cleaning), seed = mutual up link and no mutual down
-//                link; seeds compacted with wave ballots
+//                links (cleaning), kept up links written out (one 4-byte
+//                gather per chain step afterwards); seed = mutual up link
+//                and no mutual down link; seeds compacted with wave ballots
 //   k_chainlen   one lane per seed: walk the chain of mutual links to its
 //                end; chains with >= min_track_hits clusters are tracks; set
 //                the seed's bit in the sector's input-index bitmap
@@ -60,6 +61,7 @@ __global__ __launch_bounds__(256) void k_seeds(KArgs a) {
                 const int2 l = a.link[p];
                 const bool mu = l.x >= 0 && l.x < n && a.link[l.x].y == p;
                 const bool md = l.y >= 0 && l.y < n && a.link[l.y].x == p;
+                a.upc[p] = mu ? l.x : -1;
                 if (mu && !md) mask |= 1u << k;
             }
         }
@@ -88,7 +90,6 @@ __global__ __launch_bounds__(256) void k_chainlen(KArgs a) {
     __shared__ int s_scan[256];
     __shared__ int s_base;
     const int ns = min(a.cnt->n_seeds, a.seed_cap);
-    const int nv = min(a.cnt->n_valid_total, a.n_in);
     const int R = a.n_rows;
     const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x; base < ns; base += stride) {
@@ -104,9 +105,8 @@ __global__ __launch_bounds__(256) void k_chainlen(KArgs a) {
             int qb[8];
             qb[0] = q;
             for (int step = 0; step < R; step++) {
-                const int u = a.link[q].x;
-                if (u < 0 || u >= nv) break;
-                if (a.link[u].y != q) break;
+                const int u = a.upc[q];   // mutual up link (cleaned)
+                if (u < 0) break;
                 q = u;
                 if ((L & 7) == 0 && pv && L <= R - 8) {
                     reinterpret_cast<int4 *>(pv + L - 8)[0] = make_int4(qb[0], qb[1], qb[2], qb[3]);
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_emit(KArgs a) {
                     buf[b].id = e.id;
                     buf[b].sr = e.sr & 255;
                     if (j + 1 < L) {
-                        q = a.link[q].x;
+                        q = a.upc[q];
                         e = a.rec[q];
                     }
                 } else {

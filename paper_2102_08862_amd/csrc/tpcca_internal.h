@@ -186,6 +186,7 @@ struct KArgs {
     Rec *tmp;                // [n_in]
     Rec *rec;                // [n_in]
     int2 *link;              // [n_in] (up, dn) as sorted positions
+    int32_t *upc;            // [n_in] cleaned up link (mutual), else -1
     int32_t *seeds;          // [seed_cap]
     int32_t *tseed;          // [tseed_cap]
     int32_t *tlen;           // [tseed_cap]
