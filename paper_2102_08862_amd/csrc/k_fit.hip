@@ -139,152 +139,206 @@ __device__ inline void kf_update(float d[5], float C[5][5], float ry, float rt, 
 
 constexpr float kConvTol = 1e-5f;
 
+// State of one lane's track between passes.
+struct FitLane {
+    int g;                 // track slot; -1: none, -2: the queue is empty
+    int pass, L;
+    const Rec *ch;
+    float x1, y1, t1, TL;
+    float q0[5], ref1[5], est[5], prev[5];
+    bool ok, conv;
+};
+
+// Three-point estimate at the first cluster of track g (circle through the
+// first, middle and last cluster).
+__device__ inline void fit_init(const KArgs &a, const float *sx, int g, FitLane &F) {
+    const float kB = a.bz_kb;
+    F.g = g;
+    F.pass = 0;
+    F.L = a.trk_len[g];
+    F.ch = a.chain + a.off8[g];
+    const Rec c1 = F.ch[0];
+    const int m = (F.L + 1) / 2 - 1;
+    const Rec cm = F.ch[m], cL = F.ch[F.L - 1];
+    F.x1 = sx[c1.sr];
+    F.y1 = c1.y;
+    F.t1 = c1.t;
+    const float Xm = sx[cm.sr] - F.x1, Ym = cm.y - F.y1;
+    const float XL = sx[cL.sr] - F.x1;
+    const float YL = cL.y - F.y1;
+    F.TL = cL.t - F.t1;
+    F.ok = true;
+    F.conv = false;
+#pragma unroll
+    for (int i = 0; i < 5; i++) F.q0[i] = F.est[i] = F.prev[i] = 0.f;
+    const float bcx = XL - Xm, bcy = YL - Ym;
+    const float cr = Xm * YL - Ym * XL;
+    const float dab = sqrtf(Xm * Xm + Ym * Ym), dac = sqrtf(XL * XL + YL * YL),
+                dbc = sqrtf(bcx * bcx + bcy * bcy);
+    if (!(dab > 0.f && dac > 0.f && dbc > 0.f)) F.ok = false;
+    const float kap = 2.f * cr / (dab * dac * dbc);
+    const float u = 0.5f * kap * dac;
+    if (!(fabsf(u) < 1.f)) F.ok = false;
+    if (F.ok) {
+        const float phi = atan2f(YL, XL) - asinf(u);
+        if (!(cosf(phi) > 0.f)) F.ok = false;
+        F.q0[2] = sinf(phi);
+        F.q0[3] = F.TL / (dac * asin_ratio(u));
+        F.q0[4] = (kB != 0.f) ? -kap / kB : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; i++) F.ref1[i] = F.q0[i];
+}
+
+__device__ inline void fit_output(const KArgs &a, const float *sx, const FitLane &F, const float (&C)[5][5],
+                                  float chi2) {
+    const int g = F.g;
+    const Rec e0 = a.rec[a.trk_seed[g]];
+    const int si = e0.sr >> 8;
+    const Rec cL = F.ch[F.L - 1];
+    tpcca_track o;
+    o.frame = a.si[si].frame;
+    o.sector = a.si[si].sector;
+    o.n_clusters = F.L;
+    o.status = F.ok ? (F.conv ? 0 : 4) : 2;
+    o.first = (int64_t)(a.cl_off[g] - a.st[si].cl_base);
+    o.seed = e0.id;
+    o.ndf = 2 * F.L - 5;
+    o.x_ref = sx[cL.sr];
+    o.t_base = cL.t;
+    if (F.ok) {
+        o.y = F.y1 + F.est[0];
+        o.dt = F.est[1] - F.TL;
+        o.sinphi = F.est[2];
+        o.tau = F.est[3];
+        o.qpt = F.est[4];
+        o.chi2 = chi2;
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 5; i++)
+#pragma unroll
+            for (int j = 0; j <= i; j++) o.cov[k++] = C[i][j];
+    } else {
+        o.y = o.dt = o.sinphi = o.tau = o.qpt = o.chi2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < 15; i++) o.cov[i] = 0.f;
+    }
+    a.trk[g] = o;
+}
+
+// One pass over the chain; when the track is finished (converged, failed,
+// or out of passes) its record is written and true returned.
+__device__ inline bool fit_pass(const KArgs &a, const float *sx, FitLane &F) {
+    const float kB = a.bz_kb, smax = a.s_max;
+    const float vy = a.sigma_y2, vt = a.sigma_t2;
+    const float ivy = 1.f / vy, ivt = 1.f / vt;
+    const bool ext = (F.pass == 0);
+    float ref[5], dev[5], C[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        ref[i] = F.ref1[i];
+        dev[i] = F.q0[i] - F.ref1[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+#pragma unroll
+        for (int j = 0; j < 5; j++) C[i][j] = 0.f;
+    C[0][0] = vy;
+    C[1][1] = vt;
+    C[2][2] = a.var_s;
+    C[3][3] = a.var_tau;
+    C[4][4] = a.var_k;
+    float chi = ref[0] * ref[0] * ivy + ref[1] * ref[1] * ivt;
+    float Xp = 0.f;
+    for (int j = 1; j < F.L; j++) {
+        const Rec cj = F.ch[j];
+        const float Xj = sx[cj.sr] - F.x1;
+        float rn[5];
+        Jac J;
+        if (!transport(kB, smax, ref, Xj - Xp, rn, &J)) {
+            F.ok = false;
+            fit_output(a, sx, F, C, 0.f);
+            return true;
+        }
+        Xp = Xj;
+        apply_jac(J, dev, C);
+#pragma unroll
+        for (int i = 0; i < 5; i++) ref[i] = rn[i];
+        const float Yj = cj.y - F.y1, Tj = cj.t - F.t1;
+        const float ey = Yj - ref[0], et = Tj - ref[1];
+        chi += ey * ey * ivy + et * et * ivt;
+        kf_update(dev, C, ey - dev[0], et - dev[1], vy, vt);
+        if (ext) {
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                ref[i] += dev[i];
+                dev[i] = 0.f;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 5; i++) F.est[i] = ref[i] + dev[i];
+    // converged once a re-linearised pass moves no parameter by more than
+    // kConvTol relative (floor 1 in every unit)
+    if (F.pass > 0) {
+        bool conv = true;
+#pragma unroll
+        for (int i = 0; i < 5; i++) conv = conv && fabsf(F.est[i] - F.prev[i]) <= kConvTol * fmaxf(fabsf(F.est[i]), 1.f);
+        F.conv = conv;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; i++) F.prev[i] = F.est[i];
+    bool done = F.conv || F.pass + 1 >= a.kf_passes;
+    if (!done && !transport(kB, smax, F.est, -Xp, F.ref1, nullptr)) {
+        F.ok = false;
+        done = true;
+    }
+    if (done) {
+        fit_output(a, sx, F, C, chi);
+        return true;
+    }
+    F.pass++;
+    return false;
+}
+
+// Tracks come from a queue in order of decreasing length (so the lanes of a
+// wave carry chains of nearly equal length), and a lane takes its next track
+// as soon as its current one is finished: a wave runs one pass per step for
+// every lane, so a track that needs more passes does not hold the other
+// lanes of its wave idle.
 __global__ __launch_bounds__(256) void k_fit(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ float sx[kMaxRows];
     for (int r = threadIdx.x; r < a.n_rows; r += blockDim.x) sx[r] = a.row_x[r];
     __syncthreads();
     const int nt = min(a.cnt->n_tracks, a.trk_cap);
-    const float kB = a.bz_kb, smax = a.s_max;
-    const float vy = a.sigma_y2, vt = a.sigma_t2;
-    const float ivy = 1.f / vy, ivt = 1.f / vt;
-    const int P = a.kf_passes;
-    // tracks in order of decreasing length: the lanes of a wave carry chains
-    // of nearly equal length
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
-        const int g = a.perm[i];
-        const int L = a.trk_len[g];
-        const int off = a.cl_off[g];
-        const Rec e0 = a.rec[a.trk_seed[g]];
-        const int si = e0.sr >> 8;
-        const Rec *ch = a.chain + a.off8[g];
-        const Rec c1 = ch[0];
-        const int m = (L + 1) / 2 - 1;
-        const Rec cm = ch[m], cL = ch[L - 1];
-        const float x1 = sx[c1.sr];
-        const float y1 = c1.y, t1 = c1.t;
-        const float Xm = sx[cm.sr] - x1, Ym = cm.y - y1;
-        const float XL = sx[cL.sr] - x1;
-        const float YL = cL.y - y1, TL = cL.t - t1;
-
-        // three-point estimate at the first cluster
-        bool ok = true;
-        float q0[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        {
-            const float bcx = XL - Xm, bcy = YL - Ym;
-            const float cr = Xm * YL - Ym * XL;
-            const float dab = sqrtf(Xm * Xm + Ym * Ym), dac = sqrtf(XL * XL + YL * YL),
-                        dbc = sqrtf(bcx * bcx + bcy * bcy);
-            if (!(dab > 0.f && dac > 0.f && dbc > 0.f)) ok = false;
-            const float kap = 2.f * cr / (dab * dac * dbc);
-            const float u = 0.5f * kap * dac;
-            if (!(fabsf(u) < 1.f)) ok = false;
-            if (ok) {
-                const float phi = atan2f(YL, XL) - asinf(u);
-                if (!(cosf(phi) > 0.f)) ok = false;
-                q0[2] = sinf(phi);
-                q0[3] = TL / (dac * asin_ratio(u));
-                q0[4] = (kB != 0.f) ? -kap / kB : 0.f;
-            }
-        }
-        float ref1[5] = {q0[0], q0[1], q0[2], q0[3], q0[4]};
-        float est[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        float prev[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        float C[5][5];
-        float chi2 = 0.f;
-        bool conv = false;
-        for (int pass = 0; pass < P && ok; pass++) {
-            const bool ext = (pass == 0);
-            float ref[5], dev[5];
-#pragma unroll
-            for (int i = 0; i < 5; i++) {
-                ref[i] = ref1[i];
-                dev[i] = q0[i] - ref1[i];
-            }
-#pragma unroll
-            for (int i = 0; i < 5; i++)
-#pragma unroll
-                for (int j = 0; j < 5; j++) C[i][j] = 0.f;
-            C[0][0] = vy;
-            C[1][1] = vt;
-            C[2][2] = a.var_s;
-            C[3][3] = a.var_tau;
-            C[4][4] = a.var_k;
-            float chi = ref[0] * ref[0] * ivy + ref[1] * ref[1] * ivt;
-            float Xp = 0.f;
-            for (int j = 1; j < L; j++) {
-                const Rec cj = ch[j];
-                const float Xj = sx[cj.sr] - x1;
-                const float2 m2 = make_float2(cj.y, cj.t);
-                float rn[5];
-                Jac J;
-                if (!transport(kB, smax, ref, Xj - Xp, rn, &J)) {
-                    ok = false;
-                    break;
-                }
-                Xp = Xj;
-                apply_jac(J, dev, C);
-#pragma unroll
-                for (int i = 0; i < 5; i++) ref[i] = rn[i];
-                const float Yj = m2.x - y1, Tj = m2.y - t1;
-                const float ey = Yj - ref[0], et = Tj - ref[1];
-                chi += ey * ey * ivy + et * et * ivt;
-                kf_update(dev, C, ey - dev[0], et - dev[1], vy, vt);
-                if (ext) {
-#pragma unroll
-                    for (int i = 0; i < 5; i++) {
-                        ref[i] += dev[i];
-                        dev[i] = 0.f;
+    const int lane = threadIdx.x & 63;
+    FitLane F;
+    F.g = -1;
+    for (;;) {
+        const bool need = F.g == -1;
+        const uint64_t m = __ballot(need);
+        if (m) {
+            const int first = __ffsll((unsigned long long)m) - 1;
+            int base = 0;
+            if (lane == first) base = atomicAdd(&a.cnt->fit_next, __popcll(m));
+            base = __shfl(base, first);
+            if (need) {
+                const int i = base + __popcll(m & ((1ull << lane) - 1ull));
+                if (i < nt) {
+                    fit_init(a, sx, a.perm[i], F);
+                    if (!F.ok) {
+                        const float Z[5][5] = {};
+                        fit_output(a, sx, F, Z, 0.f);
+                        F.g = -1;
                     }
+                } else {
+                    F.g = -2;
                 }
             }
-            if (!ok) break;
-#pragma unroll
-            for (int i = 0; i < 5; i++) est[i] = ref[i] + dev[i];
-            chi2 = chi;
-            // converged once a re-linearised pass moves no parameter by more
-            // than kConvTol relative (floor 1 in every unit)
-            if (pass > 0) {
-                conv = true;
-#pragma unroll
-                for (int i = 0; i < 5; i++)
-                    conv = conv && fabsf(est[i] - prev[i]) <= kConvTol * fmaxf(fabsf(est[i]), 1.f);
-            }
-#pragma unroll
-            for (int i = 0; i < 5; i++) prev[i] = est[i];
-            if (conv) break;
-            if (pass + 1 < P) {
-                if (!transport(kB, smax, est, -Xp, ref1, nullptr)) ok = false;
-            }
         }
-        tpcca_track o;
-        o.frame = a.si[si].frame;
-        o.sector = a.si[si].sector;
-        o.n_clusters = L;
-        o.status = ok ? (conv ? 0 : 4) : 2;
-        o.first = (int64_t)(off - a.st[si].cl_base);
-        o.seed = e0.id;
-        o.ndf = 2 * L - 5;
-        o.x_ref = sx[cL.sr];
-        o.t_base = cL.t;
-        if (ok) {
-            o.y = y1 + est[0];
-            o.dt = est[1] - TL;
-            o.sinphi = est[2];
-            o.tau = est[3];
-            o.qpt = est[4];
-            o.chi2 = chi2;
-            int k = 0;
-#pragma unroll
-            for (int i = 0; i < 5; i++)
-#pragma unroll
-                for (int j = 0; j <= i; j++) o.cov[k++] = C[i][j];
-        } else {
-            o.y = o.dt = o.sinphi = o.tau = o.qpt = o.chi2 = 0.f;
-#pragma unroll
-            for (int i = 0; i < 15; i++) o.cov[i] = 0.f;
-        }
-        a.trk[g] = o;
+        if (__all(F.g == -2)) break;
+        if (F.g >= 0 && fit_pass(a, sx, F)) F.g = -1;
     }
 }
 
