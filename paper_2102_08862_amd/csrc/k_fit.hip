@@ -46,13 +46,17 @@ struct Jac {
     float ys, yk, ts, tt, tk, sk;
 };
 
-// transport q by dx; Jacobian if J != nullptr; false on |sin phi| >= smax
-__device__ inline bool transport(float kB, float smax, const float q[5], float dx, float qo[5], Jac *J) {
+// transport q by dx; Jacobian if J != nullptr; false on |sin phi| >= smax.
+// cs: cos phi of q if known (>= 0; a chain of transports hands each
+// step's final cosine to the next), else -1; receives cos phi of qo.
+__device__ inline bool transport(float kB, float smax, const float q[5], float dx, float qo[5], Jac *J,
+                                 float &cs) {
     const float s = q[2], tau = q[3], k = q[4];
     const float kap = -kB * k;
     const float s1 = s + kap * dx;
     if (!(fabsf(s) < smax) || !(fabsf(s1) < smax)) return false;
-    const float c = sqrtf(1.f - s * s), c1 = sqrtf(1.f - s1 * s1);
+    const float c = cs >= 0.f ? cs : sqrtf(1.f - s * s), c1 = sqrtf(1.f - s1 * s1);
+    cs = c1;
     const float S = s + s1, C = c + c1;
     const float dy = dx * S / C;
     const float L = sqrtf(dx * dx + dy * dy);
@@ -250,12 +254,14 @@ __device__ inline bool fit_pass(const KArgs &a, const float *sx, FitLane &F) {
     C[4][4] = a.var_k;
     float chi = ref[0] * ref[0] * ivy + ref[1] * ref[1] * ivt;
     float Xp = 0.f;
+    float cs = -1.f;   // cos phi of ref (the extended filter moves ref: recomputed)
     for (int j = 1; j < F.L; j++) {
         const Rec cj = F.ch[j];
         const float Xj = sx[cj.sr] - F.x1;
         float rn[5];
         Jac J;
-        if (!transport(kB, smax, ref, Xj - Xp, rn, &J)) {
+        if (ext) cs = -1.f;
+        if (!transport(kB, smax, ref, Xj - Xp, rn, &J, cs)) {
             F.ok = false;
             fit_output(a, sx, F, C, 0.f);
             return true;
@@ -289,7 +295,8 @@ __device__ inline bool fit_pass(const KArgs &a, const float *sx, FitLane &F) {
 #pragma unroll
     for (int i = 0; i < 5; i++) F.prev[i] = F.est[i];
     bool done = F.conv || F.pass + 1 >= a.kf_passes;
-    if (!done && !transport(kB, smax, F.est, -Xp, F.ref1, nullptr)) {
+    float cs0 = -1.f;
+    if (!done && !transport(kB, smax, F.est, -Xp, F.ref1, nullptr, cs0)) {
         F.ok = false;
         done = true;
     }
