@@ -274,40 +274,46 @@ void launch_emit(const KArgs &a, Launch l, hipStream_t s) {
 // number) pairs there; k_asg_fill then builds each bucket's slice of the
 // assignment in LDS (-1 where no pair) and writes it out whole.
 constexpr int kAsgBucket = 16384;          // input indices per bucket (64 KB of assignment)
-constexpr int kAsgTracks = 1024;           // tracks per workgroup range
+constexpr int kAsgTracks = 512;            // tracks per workgroup range
 constexpr int kAsgHist = 4096;             // buckets a range may span (else direct stores)
 
 __global__ __launch_bounds__(256) void k_lists(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ int32_t h[kAsgHist];
+    // per-track values of the range, loaded in parallel once (a track's
+    // sector and offsets are a chain of dependent loads)
+    __shared__ int32_t m_len[kAsgTracks], m_cl[kAsgTracks], m_off8[kAsgTracks], m_ib[kAsgTracks],
+        m_tn[kAsgTracks];
     __shared__ int32_t s_lo, s_span;
     const int nt = min(a.cnt->n_tracks, a.trk_cap);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6, wpb = blockDim.x >> 6;
     for (int g0 = blockIdx.x * kAsgTracks; g0 < nt; g0 += gridDim.x * kAsgTracks) {
         const int g1 = min(g0 + kAsgTracks, nt);
-        if (threadIdx.x == 0) {
-            const int sa = a.rec[a.trk_seed[g0]].sr >> 8, sb = a.rec[a.trk_seed[g1 - 1]].sr >> 8;
-            const int lo = a.si[sa].in_base / kAsgBucket;
-            const int hi = (a.si[sb].in_base + a.si[sb].n) / kAsgBucket;
-            s_lo = lo;
-            s_span = hi - lo + 1;
+        for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+            const int si = a.rec[a.trk_seed[g]].sr >> 8;
+            const int k = g - g0;
+            m_len[k] = a.trk_len[g];
+            m_cl[k] = a.cl_off[g];
+            m_off8[k] = a.off8[g];
+            m_ib[k] = a.si[si].in_base;
+            m_tn[k] = g - a.st[si].trk_base;
+            if (g == g0) s_lo = a.si[si].in_base / kAsgBucket;
+            if (g == g1 - 1) s_span = (a.si[si].in_base + a.si[si].n) / kAsgBucket;   // last bucket of the range
         }
         __syncthreads();
-        const int blo = s_lo, span = s_span;
+        const int blo = s_lo, span = s_span - s_lo + 1;
         const bool bucketed = span <= kAsgHist;
         if (bucketed) {
             for (int b = threadIdx.x; b < span; b += blockDim.x) h[b] = 0;
             __syncthreads();
         }
         // lists, and the bucket counts
-        for (int g = g0 + wv; g < g1; g += wpb) {
-            const int L = a.trk_len[g];
-            const Rec *src = a.chain + a.off8[g];
-            int32_t *dst = a.clusters + a.cl_off[g];
-            const int si = a.rec[a.trk_seed[g]].sr >> 8;
-            const int ib = a.si[si].in_base;
-            const int tn = g - a.st[si].trk_base;
+        for (int k = wv; k < g1 - g0; k += wpb) {
+            const int L = m_len[k];
+            const Rec *src = a.chain + m_off8[k];
+            int32_t *dst = a.clusters + m_cl[k];
+            const int ib = m_ib[k], tn = m_tn[k];
             for (int j = lane; j < L; j += 64) {
                 const int id = src[j].id;
                 dst[j] = id;
@@ -320,24 +326,23 @@ __global__ __launch_bounds__(256) void k_lists(KArgs a) {
                 }
             }
         }
-        if (!bucketed) continue;   // uniform
-        __syncthreads();
-        for (int b = threadIdx.x; b < span; b += blockDim.x) {
-            const int v = h[b];
-            // runs are reserved inside the bucket's fixed region (a bucket
-            // holds at most kAsgBucket pairs: one per input index)
-            h[b] = v ? (blo + b) * kAsgBucket + atomicAdd(&a.asg_cnt[blo + b], v) : 0;   // < n_in + kAsgBucket
-        }
-        __syncthreads();
-        for (int g = g0 + wv; g < g1; g += wpb) {
-            const int L = a.trk_len[g];
-            const int32_t *ids = a.clusters + a.cl_off[g];
-            const int si = a.rec[a.trk_seed[g]].sr >> 8;
-            const int ib = a.si[si].in_base;
-            const int tn = g - a.st[si].trk_base;
-            for (int j = lane; j < L; j += 64) {
-                const int gi = ib + ids[j];
-                a.asg_pairs[(int64_t)atomicAdd(&h[gi / kAsgBucket - blo], 1)] = make_int2(gi, tn);
+        if (bucketed) {   // uniform
+            __syncthreads();
+            for (int b = threadIdx.x; b < span; b += blockDim.x) {
+                const int v = h[b];
+                // runs are reserved inside the bucket's fixed region (a bucket
+                // holds at most kAsgBucket pairs: one per input index)
+                h[b] = v ? (blo + b) * kAsgBucket + atomicAdd(&a.asg_cnt[blo + b], v) : 0;   // < n_in + kAsgBucket
+            }
+            __syncthreads();
+            for (int k = wv; k < g1 - g0; k += wpb) {
+                const int L = m_len[k];
+                const int32_t *ids = a.clusters + m_cl[k];
+                const int ib = m_ib[k], tn = m_tn[k];
+                for (int j = lane; j < L; j += 64) {
+                    const int gi = ib + ids[j];
+                    a.asg_pairs[(int64_t)atomicAdd(&h[gi / kAsgBucket - blo], 1)] = make_int2(gi, tn);
+                }
             }
         }
         __syncthreads();
