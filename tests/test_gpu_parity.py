@@ -250,3 +250,32 @@ def test_arena_too_small_and_state_errors(tp, x):
     with pytest.raises(tp.TpccaError) as e:
         trk._check(trk.lib.tpcca_run(trk.h))
     assert e.value.status == tp.ERR_NOMEM
+
+
+def test_more_chains_than_walk_rows(tp, x):
+    """Many short tracks: more seeds than the chain walk keeps records for
+    (n_clusters / 32 + 64 rows), so some tracks take the walk-again path of
+    the output stage; every output still equals the oracle's."""
+    rng = np.random.default_rng(41)
+    rows, ys, ts = [], [], []
+    for k in range(700):
+        r0 = int(rng.integers(0, 140))
+        rr = np.arange(r0, r0 + 12)
+        y0, m = rng.uniform(-12, 12), rng.uniform(-0.1, 0.1)
+        t0, n = 30.0 * k, rng.uniform(-0.5, 0.5)
+        xx = x[rr].astype(np.float64)
+        rows.append(rr)
+        ys.append(y0 + m * (xx - xx[0]) + rng.normal(0, 0.02, len(rr)))
+        ts.append(t0 + n * (xx - xx[0]) + rng.normal(0, 0.02, len(rr)))
+    row = np.concatenate(rows).astype(np.uint8)
+    y = np.concatenate(ys).astype(np.float32)
+    t = np.concatenate(ts).astype(np.float32)
+    perm = rng.permutation(len(row))
+    row, y, t = row[perm], y[perm], t[perm]
+    print("case short tracks", len(row), flush=True)
+    trk, f = _one_sector(tp, row, y, t)
+    st = trk.stats()
+    assert st["n_seeds"] > len(row) // 32 + 64, st["n_seeds"]
+    res = compare_sector(trk, f, 0, row, y, t, oracle_cfg(x))
+    print(res, "seeds", st["n_seeds"])
+    assert res["tracks"] > 500
