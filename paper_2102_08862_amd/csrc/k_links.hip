@@ -852,11 +852,18 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
                 T.fs[j][f] = (int16_t)T.n[j];
             }
             __syncthreads();
-            // one wave per staged row; the previous cluster's fine bin comes
-            // from the neighbouring lane (or the last lane of the previous
-            // step), so every cluster is read once
+            // one wave per staged row, in four steps separated by the wave's
+            // own LDS ordering (no workgroup barrier):
+            //  A: fine bin starts of the row (the previous cluster's bin comes
+            //     from the neighbouring lane), y cell and fine bin of every
+            //     cluster in row order (the bin in the yt slot, as a temp);
+            //  B: every cluster's rank inside its fine bin by (y cell, row
+            //     order): a count over the bin, one lane per cluster;
+            //  C: the row-local index of each rank (oq);
+            //  D: (y, t) and y cell in rank order, read again from the row.
             {
                 const int wv = tid >> 6, lane = tid & 63;
+                int2 *yti = reinterpret_cast<int2 *>(T.yt);
                 for (int j = wv; j < nsr; j += kLinkBlock / 64) {
                     const int n = T.n[j], bj = T.base[j], plo = T.plo[j];
                     const YCell yc = T.yc[j];
@@ -866,10 +873,9 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
                         int f = 0x7fffffff;
                         if (q < n) {
                             const float2 e = *reinterpret_cast<const float2 *>(a.rec + plo + q);
-                            T.yt[bj + q] = e;
                             T.cell[bj + q] = (uint8_t)ycell_of(yc, e.x);
-                            T.oq[bj + q] = (int16_t)q;
                             f = fine_bin(e.y, G.t0, G.inv_cbw, G.nf) - G.fb0;
+                            yti[bj + q].x = f;
                         }
                         int fp = __shfl_up(f, 1);
                         if (lane == 0) fp = carry;
@@ -877,27 +883,27 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
                             for (int b = max(fp + 1, 0); b <= min(f, G.nfb); b++) T.fs[j][b] = (int16_t)q;
                         carry = __shfl(f, 63);
                     }
-                }
-            }
-            __syncthreads();
-            // order every (row, fine bin) by y cell (a few clusters each)
-            for (int k = tid; k < nsr * G.nfb; k += kLinkBlock) {
-                const int j = k / G.nfb, f = k - j * G.nfb;
-                const int lo = T.base[j] + T.fs[j][f], hi = T.base[j] + T.fs[j][f + 1];
-                for (int i = lo + 1; i < hi; i++) {
-                    const float2 e = T.yt[i];
-                    const uint8_t c = T.cell[i];
-                    const int16_t o = T.oq[i];
-                    int m = i - 1;
-                    while (m >= lo && T.cell[m] > c) {
-                        T.yt[m + 1] = T.yt[m];
-                        T.cell[m + 1] = T.cell[m];
-                        T.oq[m + 1] = T.oq[m];
-                        m--;
+                    wave_lds_sync();
+                    for (int q = lane; q < n; q += 64) {
+                        const int f = yti[bj + q].x;
+                        const int lo = T.fs[j][f], hi = T.fs[j][f + 1];
+                        const int c = T.cell[bj + q];
+                        int rank = lo;
+                        for (int m = lo; m < hi; m++) {
+                            const int cm = T.cell[bj + m];
+                            rank += (cm < c) || (cm == c && m < q);
+                        }
+                        yti[bj + q].y = rank;
                     }
-                    T.yt[m + 1] = e;
-                    T.cell[m + 1] = c;
-                    T.oq[m + 1] = o;
+                    wave_lds_sync();
+                    for (int q = lane; q < n; q += 64) T.oq[bj + yti[bj + q].y] = (int16_t)q;
+                    wave_lds_sync();
+                    for (int s = lane; s < n; s += 64) {
+                        const int q = T.oq[bj + s];
+                        const float2 e = *reinterpret_cast<const float2 *>(a.rec + plo + q);
+                        T.yt[bj + s] = e;
+                        T.cell[bj + s] = (uint8_t)ycell_of(yc, e.x);
+                    }
                 }
             }
             __syncthreads();
