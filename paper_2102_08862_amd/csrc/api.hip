@@ -862,7 +862,7 @@ tpcca_status tpcca_get_stats(tpcca_ctx *c, tpcca_stats *out) {
     out->n_tracks = k.n_tracks;
     out->n_track_clusters = k.n_cl;
     out->n_invalid = k.n_invalid;
-    out->n_overflow_tiles = k.n_glb_tiles;
+    out->n_overflow_tiles = k.n_glb_tiles + k.n_glb_inline;
     out->n_tiles = k.n_tiles;
     out->n_triplets = c->args.use_mlp ? k.pool_used : 0;
     out->n_pruned = k.n_pruned;

@@ -841,8 +841,17 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
         const int total = T.base[nsr];
         const int own_total = T.opre[nown];
         if (InLds && total > TS::kCap) {
-            if (tid == 0) a.glb_tiles[atomicAdd(&a.cnt->n_glb_tiles, 1)] = item;
-            continue;   // uniform: every thread skips the tile
+            if constexpr (Mode == kPlain) {
+                // searched at once from global memory by this workgroup, in
+                // its place in the queue (the other workgroups go on)
+                if (tid == 0) atomicAdd(&a.cnt->n_glb_inline, 1);
+                tile_links<Mode, false>(a, T, G, si, r0, s0, nown, own_total);
+                __syncthreads();
+                if (tid == 0 && T.links) atomicAdd(&a.cnt->n_links, T.links);
+            } else {
+                if (tid == 0) a.glb_tiles[atomicAdd(&a.cnt->n_glb_tiles, 1)] = item;
+            }
+            continue;   // uniform: every thread leaves the tile
         }
         if (InLds) {
             // fine-bin starts: every bin at or below a row's last bin is set
@@ -919,8 +928,8 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
 }
 
 void launch_links(const KArgs &a, Launch l, hipStream_t s) {
+    // tiles too dense for LDS are searched inside the same launch
     hipLaunchKernelGGL((k_links<kPlain, true>), dim3(max(l.grid, 1)), dim3(kLinkBlock), 0, s, a);
-    hipLaunchKernelGGL((k_links<kPlain, false>), dim3(max(l.grid / 4, 1)), dim3(kLinkBlock), 0, s, a);
 }
 
 void launch_links_enum(const KArgs &a, Launch l, hipStream_t s) {

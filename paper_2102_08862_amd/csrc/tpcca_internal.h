@@ -100,6 +100,7 @@ struct Counters {
     int32_t n_tiles;
     int32_t tile_next;       // work queue of the neighbour-finding tiles
     int32_t fit_next;        // work queue of the track fit (tracks in length order)
+    int32_t n_glb_inline;    // dense tiles searched from global memory inside the plain launch
     int32_t n_links;
     int32_t n_seeds;
     int32_t n_tseeds;
