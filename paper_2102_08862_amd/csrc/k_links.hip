@@ -813,29 +813,34 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
         G.fb0 = cb_lo * kFinePerCb;
         G.nfb = (cb_hi - cb_lo) * kFinePerCb;
         const int32_t *co_s0 = a.coff + ((int64_t)si * R + s0) * (kNcbMax + 1);
-        if (tid < nsr) {
-            const int32_t *co = co_s0 + (int64_t)tid * (kNcbMax + 1);
-            const int plo = co[cb_lo];
-            T.plo[tid] = plo;
-            T.n[tid] = co[cb_hi] - plo;
-            T.olo[tid] = co[cb0] - plo;
-            T.yc[tid] = a.ycell[s0 + tid];
-            if (tid >= r0 - s0 && tid < r1 - s0) T.scan[tid] = co[cb1] - co[cb0];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int b = 0;
-            for (int j = 0; j < nsr; j++) {
-                T.base[j] = b;
-                b += T.n[j];
+        // wave 0: row ranges and their prefix sums (lane j: staged row j)
+        if (tid < 64) {
+            const int j = tid;
+            int n = 0, own = 0;
+            if (j < nsr) {
+                const int32_t *co = co_s0 + (int64_t)j * (kNcbMax + 1);
+                const int plo = co[cb_lo];
+                n = co[cb_hi] - plo;
+                T.plo[j] = plo;
+                T.n[j] = n;
+                T.olo[j] = co[cb0] - plo;
+                T.yc[j] = a.ycell[s0 + j];
+                if (j >= r0 - s0 && j < r1 - s0) own = co[cb1] - co[cb0];
             }
-            T.base[nsr] = b;
-            int o = 0;
-            for (int k = 0; k < nown; k++) {
-                T.opre[k] = o;
-                o += T.scan[r0 - s0 + k];
+            int bs = n, os = own;
+#pragma unroll
+            for (int o = 1; o < 32; o <<= 1) {
+                const int x = __shfl_up(bs, o), y = __shfl_up(os, o);
+                if (j >= o) {
+                    bs += x;
+                    os += y;
+                }
             }
-            T.opre[nown] = o;
+            if (j < nsr) T.base[j] = bs - n;
+            if (j == nsr - 1) T.base[nsr] = bs;
+            const int k = j - (r0 - s0);
+            if (k >= 0 && k < nown) T.opre[k] = os - own;
+            if (k == nown - 1) T.opre[nown] = os;
         }
         __syncthreads();
         const int total = T.base[nsr];
@@ -854,13 +859,6 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
             continue;   // uniform: every thread leaves the tile
         }
         if (InLds) {
-            // fine-bin starts: every bin at or below a row's last bin is set
-            // by exactly one cluster below; the rest mark the row's end
-            for (int k = tid; k < nsr * (kTileFb + 1); k += kLinkBlock) {
-                const int j = k / (kTileFb + 1), f = k - j * (kTileFb + 1);
-                T.fs[j][f] = (int16_t)T.n[j];
-            }
-            __syncthreads();
             // one wave per staged row, in four steps separated by the wave's
             // own LDS ordering (no workgroup barrier):
             //  A: fine bin starts of the row (the previous cluster's bin comes
@@ -876,6 +874,11 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
                 for (int j = wv; j < nsr; j += kLinkBlock / 64) {
                     const int n = T.n[j], bj = T.base[j], plo = T.plo[j];
                     const YCell yc = T.yc[j];
+                    // fine-bin starts: every bin at or below the row's last
+                    // bin is set by exactly one cluster below; the rest mark
+                    // the row's end
+                    for (int b = lane; b <= G.nfb; b += 64) T.fs[j][b] = (int16_t)n;
+                    wave_lds_sync();
                     int carry = -1;
                     for (int q0 = 0; q0 < n; q0 += 64) {
                         const int q = q0 + lane;
