@@ -549,9 +549,10 @@ static tpcca_status plan(tpcca_ctx *c) {
         a.win_t[g - 1] = gt;
     }
     a.pair_c2 = c->cfg.pair_c2;
-    // a coarse bin must be at least twice the widest time window, so that
-    // every candidate of a cluster lies in its own or an adjacent bin
-    a.cbw_min = std::max(16.0f, 4.0f * (float)c->cfg.max_gap * c->cfg.win_t);
+    // a coarse bin must be at least the widest time window (half width
+    // max_gap * win_t) twice over, so that every candidate of a cluster lies
+    // in its own or an adjacent bin with room for the predicates' slack
+    a.cbw_min = std::max(8.0f, 2.0f * (float)c->cfg.max_gap * c->cfg.win_t);
     a.bz_kb = (float)(2.99792458e-3 * (double)c->cfg.bz_tesla);
     a.sigma_y2 = c->cfg.sigma_y * c->cfg.sigma_y;
     a.sigma_t2 = c->cfg.sigma_t * c->cfg.sigma_t;
