@@ -41,7 +41,9 @@ STAGE_BYTES = {
     "rowsort": lambda s: 32 * s["n_clusters"],
     "links": lambda s: 24 * s["n_clusters"],
     "seeds": lambda s: 12 * s["n_clusters"],
-    "emit": lambda s: 41 * s["n_track_clusters"],
+    # chain copy: walk positions read, records gathered, copies written
+    "emit": lambda s: 36 * s["n_track_clusters"],
+    # the fit (the cluster lists and the assignment run beside it)
     "fit": lambda s: 9 * s["n_track_clusters"] + 128 * s["n_tracks"],
 }
 

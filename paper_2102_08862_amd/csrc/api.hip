@@ -73,6 +73,10 @@ struct tpcca_ctx {
     int device = 0;
     int n_cu = 256;
     hipStream_t stream = nullptr;
+    // the cluster lists and the assignment run on a side stream beside the
+    // fit (they share no buffer with it); forked and joined with events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<std::vector<SectorIn>> frames;
     char *arena = nullptr;
     size_t arena_bytes = 0;
@@ -215,6 +219,12 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
     for (int r = 0; r < kEvRing; r++)
         for (int i = 0; i <= kNumStages; i++)
             if (hipEventCreate(&c->ev[r][i]) != hipSuccess) c->events_ok = false;
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        tpcca_destroy(c);
+        return TPCCA_ERR_DEVICE;
+    }
     const int cu = std::max(1, c->n_cu);
     for (int i = 0; i < kNumStages; i++) c->lc[i] = Launch{cu * 8, 256};
     c->lc[4] = Launch{cu * 4, 512};  // rowsort: 34 KB LDS, 512 threads
@@ -254,6 +264,12 @@ void tpcca_destroy(tpcca_ctx *c) {
             for (int i = 0; i <= kNumStages; i++) (void)hipEventDestroy(c->ev[r][i]);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->abort_host) (void)hipHostFree(c->abort_host);
     if (c->tab_dev) (void)hipFree(c->tab_dev);
     delete c;
@@ -499,8 +515,7 @@ static tpcca_status plan(tpcca_ctx *c) {
     L.off8 = b.take(sizeof(int32_t) * (trk_cap + 1));
     L.perm = b.take(sizeof(int32_t) * trk_cap);
     L.lhist = b.take(sizeof(int32_t) * (kLenBins + 1));
-    // chain copies for the fit: every track's chain padded to 8 entries; the
-    // row-grouped staging buffer is dead by then and covers the first N
+    // chain copies for the fit: every track's chain padded to 8 entries
     L.chain = b.take(sizeof(Rec) * (N + 7 * trk_cap));
     L.clusters = b.take(sizeof(int32_t) * N);
     L.assign = b.take(sizeof(int32_t) * N);
@@ -687,10 +702,15 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     launch_si_clusters(a, s);
     mark(st++);
     launch_emit(a, c->lc[10], s);
-    launch_lists(a, c->lc[10], s);
+    // fork: lists and assignment on the side stream, beside the fit
+    (void)hipEventRecord(c->ev_fork, s);
+    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    launch_lists(a, c->lc[10], c->side);
+    (void)hipEventRecord(c->ev_join, c->side);
     mark(st++);
     launch_len_sort(a, c->lc[11], s);
     launch_fit(a, c->lc[11], s);
+    (void)hipStreamWaitEvent(s, c->ev_join, 0);   // join
     mark(st++);
 }
 
