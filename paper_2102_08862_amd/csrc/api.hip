@@ -76,7 +76,7 @@ struct tpcca_ctx {
     // the cluster lists and the assignment run on a side stream beside the
     // fit (they share no buffer with it); forked and joined with events
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork0 = nullptr, ev_fork = nullptr, ev_sorted = nullptr, ev_join = nullptr;
     std::vector<std::vector<SectorIn>> frames;
     char *arena = nullptr;
     size_t arena_bytes = 0;
@@ -220,7 +220,9 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
         for (int i = 0; i <= kNumStages; i++)
             if (hipEventCreate(&c->ev[r][i]) != hipSuccess) c->events_ok = false;
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork0, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_sorted, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         tpcca_destroy(c);
         return TPCCA_ERR_DEVICE;
@@ -268,8 +270,8 @@ void tpcca_destroy(tpcca_ctx *c) {
         (void)hipStreamSynchronize(c->side);
         (void)hipStreamDestroy(c->side);
     }
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    for (hipEvent_t e : {c->ev_fork0, c->ev_fork, c->ev_sorted, c->ev_join})
+        if (e) (void)hipEventDestroy(e);
     if (c->abort_host) (void)hipHostFree(c->abort_host);
     if (c->tab_dev) (void)hipFree(c->tab_dev);
     delete c;
@@ -701,14 +703,19 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     launch_scan_round8_dev(a.trk_len, &cnt->n_tracks, a.trk_cap, a.off8, a.scan_tmp, s);
     launch_si_clusters(a, s);
     mark(st++);
+    // side stream: the length order of the fit beside the chain copy, then
+    // the cluster lists and the assignment beside the fit
+    (void)hipEventRecord(c->ev_fork0, s);
+    (void)hipStreamWaitEvent(c->side, c->ev_fork0, 0);
+    launch_len_sort(a, c->lc[11], c->side);
+    (void)hipEventRecord(c->ev_sorted, c->side);
     launch_emit(a, c->lc[10], s);
-    // fork: lists and assignment on the side stream, beside the fit
     (void)hipEventRecord(c->ev_fork, s);
     (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
     launch_lists(a, c->lc[10], c->side);
     (void)hipEventRecord(c->ev_join, c->side);
     mark(st++);
-    launch_len_sort(a, c->lc[11], s);
+    (void)hipStreamWaitEvent(s, c->ev_sorted, 0);
     launch_fit(a, c->lc[11], s);
     (void)hipStreamWaitEvent(s, c->ev_join, 0);   // join
     mark(st++);
