@@ -349,14 +349,19 @@ __global__ __launch_bounds__(256) void k_lists(KArgs a) {
     }
 }
 
-// One workgroup per bucket: the bucket's slice of the assignment.
-__global__ __launch_bounds__(256) void k_asg_fill(KArgs a) {
+// One workgroup per bucket: the bucket's slice of the assignment (16-byte
+// vectors for the fill and the write-out; 1024 threads, as two 64 KB images
+// fit a CU).
+constexpr int kAsgFillBlock = 1024;
+
+__global__ __launch_bounds__(kAsgFillBlock) void k_asg_fill(KArgs a) {
     TPCCA_ABORT_GUARD(a);
-    __shared__ int32_t img[kAsgBucket];
+    __shared__ int4 img4[kAsgBucket / 4];
+    int32_t *img = reinterpret_cast<int32_t *>(img4);
     const int nb = (a.n_in + kAsgBucket - 1) / kAsgBucket;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         const int i0 = b * kAsgBucket, m = min(kAsgBucket, a.n_in - i0);
-        for (int k = threadIdx.x; k < m; k += blockDim.x) img[k] = -1;
+        for (int k = threadIdx.x; k < kAsgBucket / 4; k += blockDim.x) img4[k] = make_int4(-1, -1, -1, -1);
         __syncthreads();
         const int np = min(a.asg_cnt[b], kAsgBucket);
         const int2 *pr = a.asg_pairs + (int64_t)i0;
@@ -366,7 +371,10 @@ __global__ __launch_bounds__(256) void k_asg_fill(KArgs a) {
             if ((unsigned)o < (unsigned)m) img[o] = v.y;
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < m; k += blockDim.x) a.assign[i0 + k] = img[k];
+        // i0 is a multiple of kAsgBucket: the slice starts 16-byte aligned
+        int4 *dst4 = reinterpret_cast<int4 *>(a.assign + i0);
+        for (int k = threadIdx.x; k < m / 4; k += blockDim.x) dst4[k] = img4[k];
+        for (int k = (m & ~3) + threadIdx.x; k < m; k += blockDim.x) a.assign[i0 + k] = img[k];
         __syncthreads();
     }
 }
@@ -374,7 +382,7 @@ __global__ __launch_bounds__(256) void k_asg_fill(KArgs a) {
 void launch_lists(const KArgs &a, Launch l, hipStream_t s) {
     hipLaunchKernelGGL(k_lists, dim3(l.grid), dim3(256), 0, s, a);
     const int nb = (a.n_in + kAsgBucket - 1) / kAsgBucket;
-    if (nb > 0) hipLaunchKernelGGL(k_asg_fill, dim3(min(nb, 4096)), dim3(256), 0, s, a);
+    if (nb > 0) hipLaunchKernelGGL(k_asg_fill, dim3(min(nb, 4096)), dim3(kAsgFillBlock), 0, s, a);
 }
 
 // Track slots ordered by decreasing chain length (counting sort), so that the
