@@ -229,7 +229,7 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
     }
     const int cu = std::max(1, c->n_cu);
     for (int i = 0; i < kNumStages; i++) c->lc[i] = Launch{cu * 8, 256};
-    c->lc[4] = Launch{cu * 4, 512};  // rowsort: 34 KB LDS, 512 threads
+    c->lc[4] = Launch{cu * 4, 1024};  // rowsort: 36 KB LDS, 1024 threads
     c->lc[5] = Launch{cu * 4, 256};  // links: 34 KB LDS -> 4 resident blocks per CU
     // decision-path constants, computed once on the host in FP32
     c->wtab.assign((size_t)cfg->n_rows * kMaxGap, 0.f);

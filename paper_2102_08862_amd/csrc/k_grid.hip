@@ -274,7 +274,7 @@ void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s) {
 }
 
 constexpr int kFineMax = kNcbMax * kFinePerCb;
-constexpr int kSortBlock = 512;
+constexpr int kSortBlock = 1024;
 
 __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
     TPCCA_ABORT_GUARD(a);
