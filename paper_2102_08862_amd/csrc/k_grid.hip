@@ -1,5 +1,5 @@
 // Search-grid construction: per sector, clusters are grouped by pad row and
-// each row is ordered by fine drift-time bin (4 per coarse bin), with coarse
+// each row is ordered by fine drift-time bin (2 per coarse bin), with coarse
 // time bins giving O(1) range lookups. The grid is an acceleration structure
 // only: neighbour candidate sets are decided by exact predicates later, so
 // the layout cannot change any result.
