@@ -17,7 +17,7 @@ import numpy as np
 
 STAGES = {            # stage index -> (name, blocks-per-CU candidates, tile-budget candidates)
     1: ("hist", (2, 4, 8, 16), (0,)),
-    3: ("scatter", (2, 4, 8, 16), (0,)),
+    3: ("scatter", (1, 2, 4), (0,)),
     4: ("rowsort", (1, 2, 3, 4), (0,)),
     5: ("links", (2, 3, 4), (768, 1536, 2304, 3072)),
     6: ("seeds", (2, 4, 8, 16), (0,)),
@@ -96,7 +96,7 @@ def tune(trk, frame_ids, sectors=(0, 17, 35), reps=3, log=print):
 
 def _default(stage):
     # the library's built-in shapes
-    return {1: (8, 0), 3: (8, 0), 4: (4, 0), 5: (4, 3072), 6: (8, 0), 7: (8, 0), 10: (8, 0), 11: (8, 0)}[stage]
+    return {1: (8, 0), 3: (1, 0), 4: (4, 0), 5: (4, 3072), 6: (8, 0), 7: (8, 0), 10: (8, 0), 11: (8, 0)}[stage]
 
 
 def save(settings, n_clusters, path=DEFAULT_CACHE):

@@ -229,6 +229,7 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
     }
     const int cu = std::max(1, c->n_cu);
     for (int i = 0; i < kNumStages; i++) c->lc[i] = Launch{cu * 8, 256};
+    c->lc[3] = Launch{cu, 1024};      // scatter: 134 KB LDS, 1024 threads
     c->lc[4] = Launch{cu * 4, 1024};  // rowsort: 36 KB LDS, 1024 threads
     c->lc[5] = Launch{cu * 4, 256};  // links: 34 KB LDS -> 4 resident blocks per CU
     // decision-path constants, computed once on the host in FP32
@@ -319,6 +320,7 @@ tpcca_status tpcca_set_launch(tpcca_ctx *c, int32_t stage, int32_t blocks_per_cu
     if (param != 0 && (stage != 5 || param < 256 || param > kTileCap))
         return fail(c, TPCCA_ERR_INVALID_ARG, "bad param");
     if (stage == 4 && blocks_per_cu > 4) return fail(c, TPCCA_ERR_INVALID_ARG, "rowsort: at most 4 blocks per CU");
+    if (stage == 3 && blocks_per_cu > 4) return fail(c, TPCCA_ERR_INVALID_ARG, "scatter: at most 4 blocks per CU");
     if (stage == 5 && blocks_per_cu > 4) return fail(c, TPCCA_ERR_INVALID_ARG, "links: at most 4 blocks per CU");
     (void)hipStreamSynchronize(c->stream);
     if (blocks_per_cu) c->lc[stage].grid = std::max(1, c->n_cu) * blocks_per_cu;

@@ -9,7 +9,7 @@
 //   k_hist      per-chunk LDS row histogram + time range, validation
 //   k_si_rows   per sector: row prefix, bin geometry
 //   k_si_prefix sorted-space base of every sector
-//   k_scatter   stable-free scatter of clusters into row segments (LDS ranks)
+//   k_scatter   scatter of clusters into row segments (staged by row in LDS)
 //   k_rowsort   per (sector,row): counting sort by fine time bin (LDS
 //               histogram, scatter); writes the coarse bin offsets used by
 //               the neighbour tiles
@@ -215,62 +215,91 @@ void launch_grid_setup(const KArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_si_prefix, dim3(1), dim3(1024), 0, s, a);
 }
 
-// Scatter into row segments: a workgroup takes a run of up to kScatterRun
-// consecutive chunks of one sector (the run is cut where the sector
-// changes), ranks its clusters per row in LDS and grabs one range per row
-// of the segment cursor, so each row receives one contiguous run of records.
-constexpr int kScatterRun = 8;
+// Scatter into row segments, one chunk of kChunk clusters at a time: the
+// chunk's clusters are ranked per row in LDS, the workgroup takes one range
+// of every row's segment cursor, stages the records grouped by row in LDS and
+// writes them out in that order, so consecutive lanes write consecutive
+// addresses of one row's range. Each input is read once.
+constexpr int kScatterBlock = 1024;
+constexpr int kScatterPer = kChunk / kScatterBlock;
+static_assert(kScatterPer * kScatterBlock == kChunk, "a chunk must split evenly over the workgroup");
 
-__global__ __launch_bounds__(256) void k_scatter(KArgs a) {
+__global__ __launch_bounds__(kScatterBlock) void k_scatter(KArgs a) {
     TPCCA_ABORT_GUARD(a);
-    __shared__ int32_t h[kMaxRows], gb[kMaxRows];
-    const int R = a.n_rows;
-    for (int run = blockIdx.x; run * kScatterRun < a.n_chunks; run += gridDim.x) {
-        const int c_end = min((run + 1) * kScatterRun, a.n_chunks);
-        int c = run * kScatterRun;
-        while (c < c_end) {
-            const int si = a.chunk[2 * c];
-            int c2 = c + 1;
-            while (c2 < c_end && a.chunk[2 * c2] == si) c2++;
-            const SiDesc d = a.si[si];
-            const int sbase = a.st[si].sbase;
-            const int i0 = a.chunk[2 * c + 1];
-            const int i1 = min(a.chunk[2 * (c2 - 1) + 1] + kChunk, d.n);
-            for (int r = threadIdx.x; r < R; r += blockDim.x) h[r] = 0;
-            __syncthreads();
-            for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    __shared__ Rec stage[kChunk];
+    __shared__ int32_t h[kMaxRows + 1], ls[kMaxRows + 1], gb[kMaxRows + 1];
+    __shared__ int32_t s_nv;
+    const int R = a.n_rows, tid = threadIdx.x;
+    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
+        const int si = a.chunk[2 * c], i0 = a.chunk[2 * c + 1];
+        const SiDesc d = a.si[si];
+        const int sbase = a.st[si].sbase;
+        const int i1 = min(i0 + kChunk, d.n);
+        for (int r = tid; r < R; r += kScatterBlock) h[r] = 0;
+        __syncthreads();
+        int rr[kScatterPer], rk[kScatterPer];
+        float yy[kScatterPer], tt[kScatterPer];
+#pragma unroll
+        for (int k = 0; k < kScatterPer; k++) {
+            const int i = i0 + k * kScatterBlock + tid;
+            rr[k] = -1;
+            yy[k] = 0.f;
+            tt[k] = 0.f;
+            if (i < i1) {
                 const int r = d.row[i];
-                if (valid_cluster(r, d.y[i], d.t[i], R)) atomicAdd(&h[r], 1);
+                yy[k] = d.y[i];
+                tt[k] = d.t[i];
+                if (valid_cluster(r, yy[k], tt[k], R)) rr[k] = r;
             }
-            __syncthreads();
-            for (int r = threadIdx.x; r < R; r += blockDim.x) {
-                const int k = h[r];
-                gb[r] = k ? sbase + atomicAdd(&a.rcur[si * R + r], k) : 0;
-                h[r] = 0;
-            }
-            __syncthreads();
-            for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-                const int r = d.row[i];
-                const float y = d.y[i], t = d.t[i];
-                if (valid_cluster(r, y, t, R)) {
-                    const int slot = gb[r] + atomicAdd(&h[r], 1);
-                    Rec e;
-                    e.y = y;
-                    e.t = t;
-                    e.id = i;
-                    e.sr = (si << 8) | r;
-                    a.tmp[slot] = e;
-                }
-            }
-            __syncthreads();
-            c = c2;
         }
+#pragma unroll
+        for (int k = 0; k < kScatterPer; k++) rk[k] = rr[k] >= 0 ? atomicAdd(&h[rr[k]], 1) : 0;
+        __syncthreads();
+        // row starts inside the stage (one wave scans the rows) and one
+        // global range of every row's segment
+        if (tid < 64) {
+            int carry = 0;
+            for (int r0 = 0; r0 < R; r0 += 64) {
+                const int r = r0 + tid;
+                const int v = r < R ? h[r] : 0;
+                int x = v;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int u = __shfl_up(x, off);
+                    if (tid >= off) x += u;
+                }
+                if (r < R) {
+                    ls[r] = carry + x - v;
+                    gb[r] = v ? sbase + atomicAdd(&a.rcur[si * R + r], v) : 0;
+                }
+                carry += __shfl(x, 63);
+            }
+            if (tid == 0) s_nv = carry;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kScatterPer; k++) {
+            if (rr[k] >= 0) {
+                Rec e;
+                e.y = yy[k];
+                e.t = tt[k];
+                e.id = i0 + k * kScatterBlock + tid;
+                e.sr = (si << 8) | rr[k];
+                stage[ls[rr[k]] + rk[k]] = e;
+            }
+        }
+        __syncthreads();
+        const int nv = s_nv;
+        for (int j = tid; j < nv; j += kScatterBlock) {
+            const Rec e = stage[j];
+            const int r = e.sr & 255;
+            a.tmp[gb[r] + (j - ls[r])] = e;
+        }
+        __syncthreads();
     }
 }
 
 void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s) {
-    const int runs = (a.n_chunks + kScatterRun - 1) / kScatterRun;
-    if (runs > 0) hipLaunchKernelGGL(k_scatter, dim3(min(l.grid, runs)), dim3(256), 0, s, a);
+    if (a.n_chunks > 0) hipLaunchKernelGGL(k_scatter, dim3(min(l.grid, a.n_chunks)), dim3(kScatterBlock), 0, s, a);
 }
 
 constexpr int kFineMax = kNcbMax * kFinePerCb;
