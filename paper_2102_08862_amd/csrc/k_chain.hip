@@ -265,17 +265,31 @@ void launch_emit(const KArgs &a, Launch l, hipStream_t s) {
     hipLaunchKernelGGL(k_emit, dim3(l.grid), dim3(256), 0, s, a);
 }
 
-// Canonical cluster lists and the assignment. The lists: one wave per track
-// copies the input indices of its chain copy (coalesced). The assignment is
-// a permutation from track order to input order; instead of one scattered
-// 4-byte store per cluster it goes through buckets of kAsgBucket input
-// indices: each workgroup takes a range of tracks, counts its clusters per
+// Canonical cluster lists and the assignment. The lists: the input indices
+// of the chain copies, written in list order (the lists of a range of tracks
+// are contiguous). The assignment is a permutation from track order to input
+// order; instead of one scattered 4-byte store per cluster it goes through
+// buckets of kAsgBucket input indices: each workgroup takes a range of tracks, counts its clusters per
 // bucket in LDS, reserves one run per bucket and writes (input index, track
 // number) pairs there; k_asg_fill then builds each bucket's slice of the
 // assignment in LDS (-1 where no pair) and writes it out whole.
 constexpr int kAsgBucket = 16384;          // input indices per bucket (64 KB of assignment)
 constexpr int kAsgTracks = 512;            // tracks per workgroup range
 constexpr int kAsgHist = 4096;             // buckets a range may span (else direct stores)
+
+constexpr int kListUnroll = 4;
+
+// Track of list position p within a range: the last k with m_cl[k] <= p
+// (m_cl ascending; every track has at least one cluster).
+__device__ inline int range_track(const int32_t *m_cl, int nk, int p) {
+    int lo = 0, hi = nk - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (m_cl[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 __global__ __launch_bounds__(256) void k_lists(KArgs a) {
     TPCCA_ABORT_GUARD(a);
@@ -286,8 +300,6 @@ __global__ __launch_bounds__(256) void k_lists(KArgs a) {
         m_tn[kAsgTracks];
     __shared__ int32_t s_lo, s_span;
     const int nt = min(a.cnt->n_tracks, a.trk_cap);
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6, wpb = blockDim.x >> 6;
     for (int g0 = blockIdx.x * kAsgTracks; g0 < nt; g0 += gridDim.x * kAsgTracks) {
         const int g1 = min(g0 + kAsgTracks, nt);
         for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
@@ -308,21 +320,35 @@ __global__ __launch_bounds__(256) void k_lists(KArgs a) {
             for (int b = threadIdx.x; b < span; b += blockDim.x) h[b] = 0;
             __syncthreads();
         }
-        // lists, and the bucket counts
-        for (int k = wv; k < g1 - g0; k += wpb) {
-            const int L = m_len[k];
-            const Rec *src = a.chain + m_off8[k];
-            int32_t *dst = a.clusters + m_cl[k];
-            const int ib = m_ib[k], tn = m_tn[k];
-            for (int j = lane; j < L; j += 64) {
-                const int id = src[j].id;
-                dst[j] = id;
-                const int gi = ib + id;
+        // lists, and the bucket counts: one flat loop over the range's
+        // contiguous list positions, kListUnroll loads in flight per lane
+        const int nk = g1 - g0;
+        const int P0 = m_cl[0], P1 = m_cl[nk - 1] + m_len[nk - 1];
+        const int bd = blockDim.x;
+        for (int p0 = P0 + threadIdx.x; p0 < P1; p0 += kListUnroll * bd) {
+            int id[kListUnroll], tk[kListUnroll];
+#pragma unroll
+            for (int u = 0; u < kListUnroll; u++) {
+                const int p = p0 + u * bd;
+                tk[u] = -1;
+                id[u] = 0;
+                if (p < P1) {
+                    const int k = range_track(m_cl, nk, p);
+                    tk[u] = k;
+                    id[u] = a.chain[m_off8[k] + (p - m_cl[k])].id;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kListUnroll; u++) {
+                const int k = tk[u];
+                if (k < 0) continue;
+                a.clusters[p0 + u * bd] = id[u];
+                const int gi = m_ib[k] + id[u];
                 if (bucketed) {
                     atomicAdd(&h[gi / kAsgBucket - blo], 1);
                 } else {
                     const int bk = gi / kAsgBucket;   // a range spanning many sectors: one grab per pair
-                    a.asg_pairs[(int64_t)bk * kAsgBucket + atomicAdd(&a.asg_cnt[bk], 1)] = make_int2(gi, tn);
+                    a.asg_pairs[(int64_t)bk * kAsgBucket + atomicAdd(&a.asg_cnt[bk], 1)] = make_int2(gi, m_tn[k]);
                 }
             }
         }
@@ -335,13 +361,24 @@ __global__ __launch_bounds__(256) void k_lists(KArgs a) {
                 h[b] = v ? (blo + b) * kAsgBucket + atomicAdd(&a.asg_cnt[blo + b], v) : 0;   // < n_in + kAsgBucket
             }
             __syncthreads();
-            for (int k = wv; k < g1 - g0; k += wpb) {
-                const int L = m_len[k];
-                const int32_t *ids = a.clusters + m_cl[k];
-                const int ib = m_ib[k], tn = m_tn[k];
-                for (int j = lane; j < L; j += 64) {
-                    const int gi = ib + ids[j];
-                    a.asg_pairs[(int64_t)atomicAdd(&h[gi / kAsgBucket - blo], 1)] = make_int2(gi, tn);
+            for (int p0 = P0 + threadIdx.x; p0 < P1; p0 += kListUnroll * bd) {
+                int id[kListUnroll], tk[kListUnroll];
+#pragma unroll
+                for (int u = 0; u < kListUnroll; u++) {
+                    const int p = p0 + u * bd;
+                    tk[u] = -1;
+                    id[u] = 0;
+                    if (p < P1) {
+                        tk[u] = range_track(m_cl, nk, p);
+                        id[u] = a.clusters[p];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kListUnroll; u++) {
+                    const int k = tk[u];
+                    if (k < 0) continue;
+                    const int gi = m_ib[k] + id[u];
+                    a.asg_pairs[(int64_t)atomicAdd(&h[gi / kAsgBucket - blo], 1)] = make_int2(gi, m_tn[k]);
                 }
             }
         }
