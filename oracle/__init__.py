@@ -122,6 +122,7 @@ def _load():
         lib.ora_mlp_grad.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_double, ctypes.c_int32, P, P, P, P, P, P]
         lib.ora_mlp_grad.restype = ctypes.c_double
         lib.ora_mlp_sizeof.restype = ctypes.c_int32
+        lib.ora_adamw_step.argtypes = [ctypes.c_int64, P, P, P, P, P] + [ctypes.c_double] * 5 + [ctypes.c_int32]
         assert lib.ora_mlp_sizeof() == 4 * MLP_NPARAM
         assert lib.ora_sizeof_fit() == ctypes.sizeof(_Fit) == FIT_DTYPE.itemsize
         assert lib.ora_sizeof_cfg() == ctypes.sizeof(_Cfg)
@@ -364,6 +365,32 @@ def mlp_grad(m: MLP, x, label, w_pos=1.0, round_act=True):
     loss = lib.ora_mlp_grad(_p(w), len(x), _p(x), _p(lab), float(w_pos), 1 if round_act else 0,
                             _p(g1), _p(gb1), _p(g2), _p(gb2), _p(g3), _p(gb3))
     return loss, dict(w1=g1, b1=gb1, w2=g2, b2=gb2, w3=g3, b3=gb3[0])
+
+
+def decay_mask():
+    """1 for the weights (w1, w2, w3), 0 for the biases, in the flat
+    parameter order: AdamW decays the weights only."""
+    m = np.zeros(MLP_NPARAM, np.uint8)
+    m[:MLP_H * MLP_INP] = 1
+    o = MLP_H * MLP_INP + MLP_H
+    m[o:o + MLP_H * MLP_H] = 1
+    o += MLP_H * MLP_H + MLP_H
+    m[o:o + MLP_H] = 1
+    return m
+
+
+def adamw_step(p, m, v, g, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4, decay=None):
+    """One FP64 AdamW step on flat float64 arrays p, m, v (updated in
+    place) with gradient g; step counts from 1."""
+    lib = _load()
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(g, np.float64)
+    dm = np.ascontiguousarray(decay_mask() if decay is None else decay, np.uint8)
+    assert len(p) == len(m) == len(v) == len(g) == len(dm)
+    lib.ora_adamw_step(len(p), _p(p), _p(m), _p(v), _p(g), _p(dm), float(lr), float(beta1), float(beta2),
+                       float(eps), float(weight_decay), int(step))
+    return p
 
 
 def mlp_features(yd, td, xd, yi, ti, xi, yu, tu, xu, g, wy, wt, w, c2s, n_cand):

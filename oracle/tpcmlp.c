@@ -164,3 +164,24 @@ double ora_mlp_grad(const ora_mlp *m, int64_t n, const float *x, const float *la
 }
 
 int32_t ora_mlp_sizeof(void) { return (int32_t)sizeof(ora_mlp); }
+
+/* One AdamW step on a flat parameter vector, FP64 (Adam with bias-corrected
+   first and second moments, Kingma & Ba; weight decay decoupled from the
+   gradient, Loshchilov & Hutter, applied to the entries flagged in `decay`,
+   i.e. the weights, never the biases). With k = step (1 for the first):
+     p <- p - lr*wd*p                              (decay[i] != 0)
+     m <- b1*m + (1 - b1)*g,   v <- b2*v + (1 - b2)*g*g
+     p <- p - lr * (m / (1 - b1^k)) / (sqrt(v / (1 - b2^k)) + eps)
+   The decay uses the parameter before this step's moment update. */
+void ora_adamw_step(int64_t n, double *p, double *m, double *v, const double *g, const uint8_t *decay, double lr,
+                    double b1, double b2, double eps, double wd, int32_t step) {
+    double bc1 = 1.0 - pow(b1, (double)step), bc2 = 1.0 - pow(b2, (double)step);
+    for (int64_t i = 0; i < n; i++) {
+        double pi = p[i];
+        if (decay[i]) pi -= lr * wd * pi;
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        pi -= lr * (m[i] / bc1) / (sqrt(v[i] / bc2) + eps);
+        p[i] = pi;
+    }
+}

@@ -40,7 +40,7 @@ void launch_mlp_infer(const MlpDev &W, const uint16_t *X, const int32_t *n_dev, 
 // with dz = w (sigmoid(z) - y) / n, dh2 = dz w3 [h2 > 0], dh1 = (W2^T dh2)
 // [h1 > 0]. Matrix operands are BF16, accumulation FP32. The two batch
 // reductions read their operands through a per-wave LDS transpose; the
-// waves' partial gradients meet in LDS (float atomics), then the same
+// waves' partial gradients are summed in LDS in a fixed wave order, then the same
 // workgroup applies AdamW to the FP32 master parameters and rewrites the
 // BF16 copies (or, gradient-only, writes the gradient out).
 constexpr int kTrainWaves = 8;
@@ -206,39 +206,58 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train(MlpTrainArgs T) 
                                                                0, 0, 0);
         __syncthreads();
     }
-    // combine the waves' partial gradients in LDS
-#pragma unroll
-    for (int nt = 0; nt < 4; nt++)
-#pragma unroll
-        for (int kt = 0; kt < 4; kt++)
-#pragma unroll
-            for (int r = 0; r < 4; r++)
-                atomicAdd(&sg[kOffW2 + (16 * nt + 4 * q + r) * kMlpH + 16 * kt + c], aW2[nt][kt][r]);
-#pragma unroll
-    for (int mt = 0; mt < 4; mt++)
-#pragma unroll
+    // combine the waves' partial gradients in LDS in a fixed order (wave 0
+    // writes, then waves 1..7 add theirs one after another), so that a step
+    // is bit-reproducible and the gradient-only mode gives exactly the
+    // gradient the update uses
+    for (int i = 0; i < 4; i++)
         for (int r = 0; r < 4; r++) {
-            atomicAdd(&sg[kOffW1 + (16 * mt + 4 * q + r) * kMlpInP + c], aW1[mt][r]);
-            float a3 = g3[mt][r], ab2 = gb2[mt][r], ab1 = gb1[mt][r];
+            float a3 = g3[i][r], ab2 = gb2[i][r], ab1 = gb1[i][r];
             for (int off = 1; off < 16; off <<= 1) {
-                a3 += __shfl_xor(a3, off);
-                ab2 += __shfl_xor(ab2, off);
-                ab1 += __shfl_xor(ab1, off);
+                a3 = __fadd_rn(a3, __shfl_xor(a3, off));
+                ab2 = __fadd_rn(ab2, __shfl_xor(ab2, off));
+                ab1 = __fadd_rn(ab1, __shfl_xor(ab1, off));
             }
-            if (c == 0) {
-                const int u = 16 * mt + 4 * q + r;
-                atomicAdd(&sg[kOffW3 + u], a3);
-                atomicAdd(&sg[kOffB2 + u], ab2);
-                atomicAdd(&sg[kOffB1 + u], ab1);
-            }
+            g3[i][r] = a3;
+            gb2[i][r] = ab2;
+            gb1[i][r] = ab1;
         }
     for (int off = 1; off < 64; off <<= 1) {
-        gb3 += __shfl_xor(gb3, off);
-        loss += __shfl_xor(loss, off);
+        gb3 = __fadd_rn(gb3, __shfl_xor(gb3, off));
+        loss = __fadd_rn(loss, __shfl_xor(loss, off));
     }
-    if (lane == 0) {
-        atomicAdd(&sg[kOffB3], gb3);
-        atomicAdd(&s_loss, loss);
+    for (int ww = 0; ww < kTrainWaves; ww++) {
+        if (w == ww) {
+            const bool first = ww == 0;
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+                for (int kt = 0; kt < 4; kt++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        float &d = sg[kOffW2 + (16 * nt + 4 * q + r) * kMlpH + 16 * kt + c];
+                        d = first ? aW2[nt][kt][r] : __fadd_rn(d, aW2[nt][kt][r]);
+                    }
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    float &d = sg[kOffW1 + (16 * mt + 4 * q + r) * kMlpInP + c];
+                    d = first ? aW1[mt][r] : __fadd_rn(d, aW1[mt][r]);
+                    if (c == 0) {
+                        const int u = 16 * mt + 4 * q + r;
+                        float &d3 = sg[kOffW3 + u], &d2 = sg[kOffB2 + u], &d1 = sg[kOffB1 + u];
+                        d3 = first ? g3[mt][r] : __fadd_rn(d3, g3[mt][r]);
+                        d2 = first ? gb2[mt][r] : __fadd_rn(d2, gb2[mt][r]);
+                        d1 = first ? gb1[mt][r] : __fadd_rn(d1, gb1[mt][r]);
+                    }
+                }
+            if (lane == 0) {
+                sg[kOffB3] = first ? gb3 : __fadd_rn(sg[kOffB3], gb3);
+                s_loss = first ? loss : __fadd_rn(s_loss, loss);
+            }
+        }
+        __syncthreads();
     }
     __syncthreads();
     if (T.loss_out && tid == 0) *T.loss_out = s_loss * inv_n;

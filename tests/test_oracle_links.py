@@ -197,3 +197,53 @@ def test_noise_free_separated_particles_give_one_chain(ocfg, geom):
         assert (res["assign"][inner] == k).all()
         assert (res["assign"][idx[(rr == 0) | (rr == 151)]] == -1).all()
         assert res["len"][k] == len(inner)
+
+
+def brute_triplets(cfg, row, y, t):
+    """Every accepted (down, cluster, up, gap) of every gap, with the number
+    of clusters in the two boxes of that gap, enumerated directly from the
+    definition (pure Python over all cluster pairs)."""
+    n = len(row)
+    x = cfg.row_x
+    out = []
+    for i in range(n):
+        r = int(row[i])
+        for g in range(1, cfg.max_gap + 1):
+            if r - g < 0 or r + g > len(x) - 1:
+                continue
+            w = F(F(x[r] - x[r - g]) / F(x[r + g] - x[r - g]))
+            wy = F(F(g) * F(cfg.win_y)); wt = F(F(g) * F(cfg.win_t))
+            D = [d for d in range(n) if row[d] == r - g and abs(F(y[i] - y[d])) <= wy and abs(F(t[i] - t[d])) <= wt]
+            U = [u for u in range(n) if row[u] == r + g and abs(F(y[u] - y[i])) <= wy and abs(F(t[u] - t[i])) <= wt]
+            for d in D:
+                for u in U:
+                    ry = F(F(y[i] - y[d]) - F(w * F(y[u] - y[d])))
+                    rt = F(F(t[i] - t[d]) - F(w * F(t[u] - t[d])))
+                    if F(F(ry * ry) + F(rt * rt)) <= F(cfg.pair_c2):
+                        out.append((d, i, u, g, len(D) + len(U)))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_triplets_match_brute_force(ocfg, seed):
+    """The triplet enumeration of the pruned finder: exactly the accepted
+    pairs of every gap (none missing, none extra, gap 2 listed also where
+    gap 1 has pairs), and the density feature = (|D| + |U|) / 8 of the
+    boxes of that gap, on tie- and duplicate-heavy tiny inputs."""
+    row, y, t = _tiny(100 + seed, 140 + 40 * seed, dup=0.3)
+    tri, feat = oracle.triplets(ocfg, row, y, t)
+    ref = brute_triplets(ocfg, row, y, t)
+    assert len(ref) > 30 and any(g == 2 for _, _, _, g, _ in ref)
+    got = sorted(zip(map(tuple, tri.tolist()), feat[:, 11].tolist()))
+    exp = sorted(((d, i, u, g), float(oracle.bf16(np.array([F(nb) / F(8.0)], np.float32))[0])) for d, i, u, g, nb in ref)
+    assert [k for k, _ in got] == [k for k, _ in exp]
+    assert [v for _, v in got] == [v for _, v in exp]
+    # features 4 (gap) and 5 (radius) of every triplet, from the definition
+    x = ocfg.row_x
+    assert np.array_equal(feat[:, 4], tri[:, 3].astype(np.float32))
+    assert np.array_equal(feat[:, 5], oracle.bf16(np.asarray(x, np.float32)[row[tri[:, 1]]] / np.float32(245.0)))
+    # every uncleaned link is one of the listed gap-g triplets
+    up, dn, gap = oracle.links(ocfg, row, y, t)
+    s = set(map(tuple, tri.tolist()))
+    for i in np.nonzero(up >= 0)[0]:
+        assert (dn[i], i, up[i], gap[i]) in s

@@ -167,3 +167,51 @@ def test_threshold_limits(ocfg):
     ok = set(map(tuple, tri[keep][:, [0, 1, 2]].tolist()))
     for i in np.nonzero(up >= 0)[0][:2000]:
         assert (dn[i], i, up[i]) in ok
+
+
+def _torch_adamw(p0, grads, lr, betas, eps, wd):
+    """torch.optim.AdamW in float64 with the weights decayed and the biases
+    not (two parameter groups), over the given gradient sequence."""
+    dm = oracle.decay_mask().astype(bool)
+    pw = torch.tensor(p0[dm], dtype=torch.float64, requires_grad=True)
+    pb = torch.tensor(p0[~dm], dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.AdamW([{"params": [pw], "weight_decay": wd}, {"params": [pb], "weight_decay": 0.0}],
+                            lr=lr, betas=betas, eps=eps)
+    out = []
+    for g in grads:
+        pw.grad = torch.tensor(g[dm], dtype=torch.float64)
+        pb.grad = torch.tensor(g[~dm], dtype=torch.float64)
+        opt.step()
+        p = np.empty(len(p0))
+        p[dm] = pw.detach().numpy()
+        p[~dm] = pb.detach().numpy()
+        out.append(p)
+    return out
+
+
+def test_adamw_matches_torch():
+    """The oracle's AdamW step against torch.optim.AdamW (float64, CPU) over
+    six steps with non-default betas, so that the bias corrections, the
+    moment recursions and the step counter all matter; decay on the weights
+    only."""
+    rng = np.random.default_rng(21)
+    p0 = rng.normal(0, 0.5, oracle.MLP_NPARAM)
+    grads = [rng.normal(0, 1, oracle.MLP_NPARAM) * rng.choice([1e-3, 1.0, 30.0], oracle.MLP_NPARAM)
+             for _ in range(6)]
+    hp = dict(lr=1e-2, beta1=0.8, beta2=0.95, eps=1e-6, weight_decay=0.05)
+    ref = _torch_adamw(p0, grads, hp["lr"], (hp["beta1"], hp["beta2"]), hp["eps"], hp["weight_decay"])
+    p, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    for k, g in enumerate(grads):
+        oracle.adamw_step(p, m, v, g, k + 1, **hp)
+        assert np.allclose(p, ref[k], rtol=1e-12, atol=1e-14), k
+    # planted mistakes are caught: a step counter stuck at 1, swapped betas,
+    # decay applied to the biases too
+    for bad in ("step", "betas", "decay"):
+        p, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+        kw = dict(hp)
+        if bad == "betas":
+            kw["beta1"], kw["beta2"] = hp["beta2"], hp["beta1"]
+        for k, g in enumerate(grads):
+            oracle.adamw_step(p, m, v, g, 1 if bad == "step" else k + 1,
+                              decay=np.ones(oracle.MLP_NPARAM, np.uint8) if bad == "decay" else None, **kw)
+        assert not np.allclose(p, ref[-1], rtol=1e-6, atol=1e-9), bad
