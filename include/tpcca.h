@@ -29,9 +29,14 @@
  *     tpcca_load_sector (the sector-local input index). All tie-breaks and
  *     every output ordering use it, so results do not depend on the order
  *     in which the GPU processes anything.
- *   - The library never allocates device memory: all working buffers live
- *     in one caller-owned arena (tpcca_attach_arena); tpcca_required_arena
- *     says how large it must be for the frames currently loaded.
+ *   - Device memory: all working buffers of a run live in one caller-owned
+ *     arena (tpcca_attach_arena); tpcca_required_arena says how large it
+ *     must be for the frames currently loaded. The library itself allocates
+ *     device memory only for a small per-context table block (sector
+ *     descriptors, chunk list, row tables): 1 MiB in tpcca_create, grown only
+ *     by tpcca_required_arena when the loaded frames need more. tpcca_run,
+ *     tpcca_synchronize, the fetches and the network calls never allocate;
+ *     a run whose tables would not fit fails with STATE instead.
  *   - All device work is enqueued on the caller's stream (tpcca_set_stream)
  *     and tpcca_run() does not wait for it; tpcca_synchronize() does.
  */
@@ -128,11 +133,16 @@ typedef struct {
     int64_t n_tiles;           /* neighbour-finding work items (sector, row block, time slab) */
 } tpcca_stats;
 
-/* Fill *out with the defaults above. */
+/* Fill *out with the defaults above. The defaults are readings of the
+   paper, which prints no tracker constants (geometry and field: the TPC of
+   Sec. 1; windows, score cut and prior: this library's definition). */
 tpcca_status tpcca_config_default(tpcca_config *out);
 
 /* Create a context for one device (the current HIP device). Copies cfg and
-   its row table. Errors: INVALID_ARG for out-of-range constants. */
+   its row table; allocates the context's 1 MiB table block, a side stream
+   and its events. Errors: INVALID_ARG for out-of-range constants, DEVICE if
+   a HIP call fails. (Sec. 1: one tracker instance per GPU processing whole
+   time frames.) */
 tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out);
 
 /* Release the context (not the arena or the stream, which the caller owns). */
@@ -144,13 +154,21 @@ const char *tpcca_last_error(const tpcca_ctx *ctx);
 /* Use `stream` (a hipStream_t; NULL = null stream) for all device work. */
 tpcca_status tpcca_set_stream(tpcca_ctx *ctx, void *stream);
 
-/* Open a new, empty time frame; *frame_id receives its index (0, 1, ...). */
+/* Open a new, empty time frame; *frame_id receives its index (0, 1, ...).
+   The unit of work is a whole continuous-readout time frame of ~10 ms whose
+   collisions are not separated before tracking (Sec. 1); several frames
+   loaded together are tracked in one batched run. */
 tpcca_status tpcca_add_frame(tpcca_ctx *ctx, int32_t *frame_id);
 
 /* Drop all frames and their results. */
 tpcca_status tpcca_clear_frames(tpcca_ctx *ctx);
 
-/* Give the clusters of one sector of one frame: n entries of pad row
+/* Clusters are given in native TPC coordinates, pad row, pad direction and
+   drift time, because without a collision assignment they cannot be turned
+   into spatial coordinates before tracking (Sec. 1). Device pointers let
+   clusters already on the GPU stay there (Sec. 3: data remain on the GPU
+   between steps).
+   Give the clusters of one sector of one frame: n entries of pad row
    (uint8, < n_rows), local y (cm) and drift time (cm). Arrays are SoA.
    is_device_ptr = 0: host arrays, copied before return (the caller may free
    them); they are staged into the arena by the next run. is_device_ptr = 1:
@@ -163,10 +181,17 @@ tpcca_status tpcca_clear_frames(tpcca_ctx *ctx);
 tpcca_status tpcca_load_sector(tpcca_ctx *ctx, int32_t frame, int32_t sector, int64_t n,
                                const uint8_t *row, const float *y, const float *t, int32_t is_device_ptr);
 
-/* Arena bytes a run over the currently loaded frames needs. */
+/* Arena bytes a run over the currently loaded frames needs (the whole
+   frame must fit in GPU memory, Sec. 1). Grows the context's table block if
+   the loaded frames need more (the only call besides tpcca_create that
+   allocates). INVALID_ARG if a run over these frames would exceed the
+   32-bit positions of the device buffers (about 1.2e9 clusters). */
 tpcca_status tpcca_required_arena(tpcca_ctx *ctx, size_t *bytes);
 
-/* Use [device_ptr, device_ptr + bytes) as the arena (caller-owned device
+/* The arena holds every working buffer of a run; buffers that are dead
+   after a step are reused by later steps (Sec. 1: memory reuse for the
+   sequential steps of the tracking).
+   Use [device_ptr, device_ptr + bytes) as the arena (caller-owned device
    memory, e.g. a torch uint8 tensor; 256-byte aligned). Results of earlier
    runs live in the arena and stay valid until the next run or attach. One
    arena may serve several contexts whose runs are serialised on one stream
@@ -177,25 +202,37 @@ tpcca_status tpcca_required_arena(tpcca_ctx *ctx, size_t *bytes);
 tpcca_status tpcca_attach_arena(tpcca_ctx *ctx, void *device_ptr, size_t bytes);
 
 /* Enqueue the whole hot path over every loaded frame on the stream and
-   return without waiting. NOMEM if the arena is smaller than
-   tpcca_required_arena; STATE if no frame is loaded. */
+   return without waiting: full TPC track finding of the frames (Sec. 1,
+   the most compute-intensive synchronous step), seeded with drift time in
+   place of z (Sec. 1), derived from the HLT cellular-automaton tracker
+   (Sec. 1). NOMEM if the arena is smaller than tpcca_required_arena; STATE
+   if no frame is loaded or the frames changed since tpcca_required_arena in
+   a way that needs a larger table block. Allocates nothing. */
 tpcca_status tpcca_run(tpcca_ctx *ctx);
 
-/* Wait for the last run; DEVICE on a HIP error, ABORTED if it was aborted. */
+/* Wait for the last run; DEVICE on a HIP error, ABORTED if it was aborted,
+   CAPACITY if a pruned run overflowed its triplet pool. */
 tpcca_status tpcca_synchronize(tpcca_ctx *ctx);
 
 /* Ask a run in flight to stop early (checked between work items). The run's
-   results are then undefined and tpcca_synchronize returns ABORTED. */
+   results are then undefined and tpcca_synchronize returns ABORTED.
+   (Operational control of the online farm's processing, Sec. 2; not part
+   of the method.) */
 tpcca_status tpcca_request_abort(tpcca_ctx *ctx);
 
-/* Replay runs from a captured HIP graph (1) or launch kernel by kernel (0,
+/* Batched, graph-replayed runs over many uneven frames are this library's
+   extension of the whole-frame processing of Sec. 1 (the frames the farm
+   replays from memory in a loop, Sec. 2).
+   Replay runs from a captured HIP graph (1) or launch kernel by kernel (0,
    the default). With graphs on, the first run after a change of frames,
    arena, configuration or launch settings captures the whole kernel sequence
    on the stream; later runs launch that graph with one call. Per-stage
    timing is not recorded in graph mode. */
 tpcca_status tpcca_set_graph(tpcca_ctx *ctx, int32_t on);
 
-/* Launch shape of one stage (the tpcca_stats.stage_name order: 1 hist,
+/* Set by the autotuner (this library's extension; the paper only asks for
+   efficient use of the GPU, Sec. 1).
+   Launch shape of one stage (the tpcca_stats.stage_name order: 1 hist,
    3 scatter, 4 rowsort, 5 links, 6 seeds, 7 chainlen, 8 slots, 10 emit,
    11 fit): blocks_per_cu persistent workgroups per compute unit (0: keep).
    For stage 5, param sets how many clusters a neighbour-finding tile may
@@ -210,7 +247,8 @@ tpcca_status tpcca_set_launch(tpcca_ctx *ctx, int32_t stage, int32_t blocks_per_
 tpcca_status tpcca_copy(tpcca_ctx *ctx, const void *src, void *dst, size_t bytes);
 
 /* Enable (1) or disable (0) per-stage device timing with HIP events; either
-   call also resets the accumulated stage times. */
+   call also resets the accumulated stage times. (Measurement of the
+   tracking throughput that sizes the farm, Sec. 2.) */
 tpcca_status tpcca_set_timing(tpcca_ctx *ctx, int32_t on);
 
 /* Figures of the last run (synchronises first). */
@@ -218,27 +256,35 @@ tpcca_status tpcca_get_stats(tpcca_ctx *ctx, tpcca_stats *out);
 
 /* Results of the last run for one (frame, sector), copied to host memory
    (each call synchronises first). CAPACITY if cap is too small; *n_out
-   always receives the number of entries available. */
+   always receives the number of entries available. The tracks feed the
+   calibration and the compression of the synchronous phase (Sec. 1). */
 tpcca_status tpcca_get_tracks(tpcca_ctx *ctx, int32_t frame, int32_t sector, tpcca_track *out, int64_t cap,
                               int64_t *n_out);
 
 /* Input indices of the clusters of every track of the sector, track after
-   track, innermost cluster first (rows ascending). */
+   track, innermost cluster first (rows ascending). (The hits attached to
+   tracks, Sec. 2.) */
 tpcca_status tpcca_get_track_clusters(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *out, int64_t cap,
                                       int64_t *n_out);
 
 /* Track number of every input cluster of the sector (-1: none); out[n]
-   with n equal to the sector's cluster count. */
+   with n equal to the sector's cluster count. The compression removes hits
+   of tracks not used for physics by this assignment (Sec. 1). */
 tpcca_status tpcca_get_assignment(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *out, int64_t n);
 
-/* Neighbour links of every input cluster of the sector, in input indices
+/* The pad-row neighbour links of the cellular-automaton seeding (Sec. 1:
+   HLT-derived tracker, seeding with time as a coordinate).
+   Neighbour links of every input cluster of the sector, in input indices
    (-1: none): cleaned = 0 gives the best pair of step 2, cleaned = 1 keeps
    only mutual links. For checking and debugging. */
 tpcca_status tpcca_get_links(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t cleaned, int32_t *up,
                              int32_t *dn, int64_t n);
 
 /* ---------------------------------------------------------------------
- * Learned triplet pruning. A small network (12 features -> 64 -> 64 -> 1,
+ * Learned triplet pruning: an extension of this library, not in the paper
+ * (the paper names no network; the benchmark configuration that defines it
+ * is learned pruning of the neighbour triplets with a 12-64-64-1 MLP). A
+ * small network (12 features -> 64 -> 64 -> 1,
  * ReLU, BF16 weights and activations, FP32 biases and accumulation) scores
  * every accepted candidate triplet (down, cluster, up) of the neighbour
  * finder; with use_mlp = 1 triplets whose logit is below

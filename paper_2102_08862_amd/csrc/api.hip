@@ -63,6 +63,7 @@ struct Bump {
 const char *kStageNames[] = {"reset",   "hist",  "setup",   "scatter", "rowsort", "links", "seeds",
                              "chainlen", "slots", "clscan",  "emit",    "fit"};
 constexpr int kNumStages = 12;
+constexpr size_t kTabBlockDefault = 1 << 20;
 constexpr int kEvRing = 64;
 
 }  // namespace
@@ -212,6 +213,15 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
     }
     if (e != hipSuccess) {
         if (c->abort_host) (void)hipHostFree(c->abort_host);
+        delete c;
+        return TPCCA_ERR_DEVICE;
+    }
+    // the per-run tables (sector descriptors, chunk list, row tables) live in
+    // a small device block of the context; 1 MiB holds those of about 1e9
+    // clusters in ~100 frames, and only tpcca_required_arena grows it
+    c->tab_cap = kTabBlockDefault;
+    if (hipMalloc((void **)&c->tab_dev, c->tab_cap) != hipSuccess) {
+        (void)hipHostFree(c->abort_host);
         delete c;
         return TPCCA_ERR_DEVICE;
     }
@@ -413,8 +423,10 @@ tpcca_status tpcca_load_sector(tpcca_ctx *c, int32_t frame, int32_t sector, int6
 
 }  // extern "C"
 
-// Compute the arena layout and the host tables of the current frames.
-static tpcca_status plan(tpcca_ctx *c) {
+// Compute the arena layout and the host tables of the current frames. The
+// per-context table block is (re)allocated only when may_alloc is set (the
+// sizing call); a run whose tables no longer fit fails instead.
+static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     const int R = c->cfg.n_rows;
     const int NS = c->cfg.n_sectors;
     const int S = (int)c->frames.size() * NS;
@@ -458,6 +470,13 @@ static tpcca_status plan(tpcca_ctx *c) {
     const int64_t seed_cap = N / 2 + 64;
     const int64_t tseed_cap = N / std::max(2, c->cfg.min_track_hits) + 64;
     const int64_t trk_cap = tseed_cap;
+    // every device buffer is indexed with 32-bit positions: the chain copies
+    // (one 8-entry-aligned run per track, off8 is an int32 scan) hold up to
+    // N + 7 * trk_cap entries and the assignment buckets N rounded up to a
+    // bucket plus one bucket; both must stay below 2^31
+    if (N + 7 * trk_cap + 8 > (int64_t)INT32_MAX || (N / 16384 + 2) * (int64_t)16384 > (int64_t)INT32_MAX)
+        return fail(c, TPCCA_ERR_INVALID_ARG,
+                    "too many clusters in one run for 32-bit positions (" + std::to_string(N) + ")");
     const int64_t SR = (int64_t)S * R;
     {
         Bump t;
@@ -468,6 +487,9 @@ static tpcca_status plan(tpcca_ctx *c) {
         L.ycell = t.take(sizeof(YCell) * R);
         L.tab_bytes = t.off;
         if (L.tab_bytes > c->tab_cap) {
+            if (!may_alloc)
+                return fail(c, TPCCA_ERR_STATE,
+                            "the loaded frames need a larger table block: call tpcca_required_arena before tpcca_run");
             (void)hipStreamSynchronize(c->stream);
             if (c->tab_dev) (void)hipFree(c->tab_dev);
             c->tab_dev = nullptr;
@@ -741,8 +763,8 @@ extern "C" {
 
 tpcca_status tpcca_required_arena(tpcca_ctx *c, size_t *bytes) {
     if (!c || !bytes) return TPCCA_ERR_INVALID_ARG;
-    if (c->plan_dirty) {
-        tpcca_status s = plan(c);
+    if (c->plan_dirty || c->lay.tab_bytes > c->tab_cap) {
+        tpcca_status s = plan(c, true);
         if (s != TPCCA_OK) return s;
     }
     *bytes = c->lay.total;
@@ -771,7 +793,7 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
     if (!c) return TPCCA_ERR_INVALID_ARG;
     if (c->frames.empty()) return fail(c, TPCCA_ERR_STATE, "no frame loaded");
     if (c->plan_dirty) {
-        tpcca_status s = plan(c);
+        tpcca_status s = plan(c, false);
         if (s != TPCCA_OK) return s;
     }
     if (!c->arena || c->arena_bytes < c->lay.total)
@@ -1167,13 +1189,12 @@ tpcca_status tpcca_triplet_samples(tpcca_ctx *c, float keep, uint64_t seed, uint
     if (((uintptr_t)feat_dev & 15)) return fail(c, TPCCA_ERR_INVALID_ARG, "feature buffer must be 16-byte aligned");
     if (!c->have_results || !c->args.keep_pool || !c->arena)
         return fail(c, TPCCA_ERR_STATE, "no pruned run that kept its triplet pool");
-    unsigned long long *cnt_dev = nullptr;
-    HIPCHK(c, hipMallocAsync((void **)&cnt_dev, sizeof(unsigned long long), c->stream));
-    HIPCHK(c, hipMemsetAsync(cnt_dev, 0, sizeof(unsigned long long), c->stream));
+    // the counter lives in the run's counters (in the arena): no allocation
+    unsigned long long *cnt_dev = (unsigned long long *)(c->arena + c->lay.cnt + offsetof(Counters, n_samples));
+    launch_fill_i32((int32_t *)cnt_dev, 2, 0, c->stream);
     launch_samples(c->args, keep, seed, feat_dev, label_dev, cap, cnt_dev, std::max(1, c->n_cu) * 8, c->stream);
     unsigned long long h = 0;
     HIPCHK(c, hipMemcpyAsync(&h, cnt_dev, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipFreeAsync(cnt_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     *n_out = (int64_t)h;
     return (int64_t)h > cap ? fail(c, TPCCA_ERR_CAPACITY, "sample buffer too small") : TPCCA_OK;

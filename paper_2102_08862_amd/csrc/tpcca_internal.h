@@ -96,6 +96,7 @@ struct SiState {
 
 // Device counters of one run (zeroed at the start of the run).
 struct Counters {
+    unsigned long long n_samples;   // training examples written by the sampler (after a run)
     int32_t n_valid_total;
     int32_t n_tiles;
     int32_t tile_next;       // work queue of the neighbour-finding tiles
@@ -113,8 +114,9 @@ struct Counters {
     int32_t pool_used;       // triplet pool: slots holding triplets
     int32_t pool_overflow;   // triplets that did not fit the pool
     int32_t n_pruned;        // triplets below the logit threshold
-    int32_t pad[1];
+    int32_t pad[3];
 };
+static_assert(sizeof(Counters) % 8 == 0 && offsetof(Counters, n_samples) == 0, "64-bit counter first");
 
 // y cells of one pad row: cell = clamp(floor((y - ylo) * inv), 0, ny - 1).
 // Within each fine time bin a row is ordered by (cell, t, id), so a box

@@ -71,6 +71,15 @@ def save_weights(params, meta, path=WEIGHTS):
         json.dump({"meta": meta, "params": [float(v) for v in np.asarray(params, np.float32)]}, f)
 
 
+REPORT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "prune_gain_report.json")
+
+
+def load_report(path=REPORT):
+    """The training and gain-test report written next to the weights."""
+    with open(path) as f:
+        return json.load(f)
+
+
 def load_weights(path=WEIGHTS):
     """(params float32[5313], meta dict) or (None, None) if absent or invalid."""
     try:

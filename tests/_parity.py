@@ -4,10 +4,20 @@ import numpy as np
 
 import oracle
 
-# parameter tolerance: |gpu - oracle| <= REL * max(|oracle|, floor)
+# parameter tolerance: |gpu - oracle| <= REL * max(|oracle|, floor). The
+# floors are set at a small fraction of each parameter's natural scale:
+#   y, dt: 1 cm. dt = t - t_base is a residual-sized number (~0.1 cm) while
+#     the fit carries time over a track's drift span of up to ~10^2 cm in
+#     FP32 (resolution ~1e-5 cm), and y is mostly 10-40 cm;
+#   sin phi, tau: 1e-2 (both are O(1) slopes; below 1e-2 the check is
+#     absolute at 1e-6);
+#   q/pT: 0.1 1/GeV (pT = 10 GeV; |q/pT| of the generated tracks lies in
+#     (0, 10] 1/GeV).
+# The pure relative error (no floor) is reported beside it.
 REL = 1e-4
-FLOORS = {"y": 1.0, "dt": 1.0, "sinphi": 1.0, "tau": 1.0, "qpt": 1.0}
+FLOORS = {"y": 1.0, "dt": 1.0, "sinphi": 1e-2, "tau": 1e-2, "qpt": 0.1}
 CHI2_REL = 1e-3
+S_NEAR = 0.99      # |sin phi| beyond which one side's transport may fail and the other's not
 
 
 def oracle_cfg(x, **kw):
@@ -49,8 +59,29 @@ def compare_params(tracks, ref, row, y, t, ocfg):
     assert np.array_equal(tracks["t_base"], t[last])
     ok = (tracks["status"] == 0) & (fit["status"] == 0)
     excluded = int((~ok).sum())
-    # a status disagreement is only allowed at the |sin phi| limit
+    # an exclusion must be explained: both sides failed alike, one side did
+    # not converge, or the helix reaches |sin phi| >= S_NEAR on the chain
+    # (sin phi is linear in x, so its extremes are at the chain's ends)
+    x1 = x[row[ref["clusters"][ref["first"]]]].astype(np.float64)
+    why = {"both_failed": 0, "not_converged": 0, "sinphi_limit": 0}
+    for k in np.nonzero(~ok)[0]:
+        gs, fs = int(tracks["status"][k]), int(fit["status"][k])
+        if gs == fs == 2:
+            why["both_failed"] += 1
+            continue
+        if gs == 4 or fs == 4:
+            why["not_converged"] += 1
+            continue
+        near = False
+        for sl, q in ((float(fit["sinphi"][k]), float(fit["qpt"][k])), (float(tracks["sinphi"][k]), float(tracks["qpt"][k]))):
+            s1 = sl + 2.99792458e-3 * ocfg.bz * q * (float(tracks["x_ref"][k]) - x1[k])
+            near = near or max(abs(sl), abs(s1)) >= S_NEAR
+        init_s = abs(float(fit["init"][k][2]))
+        assert near or init_s >= S_NEAR, "track %d excluded (gpu status %d, oracle %d) far from the sin phi limit" % (
+            k, gs, fs)
+        why["sinphi_limit"] += 1
     worst = 0.0
+    pure = {}
     if ok.any():
         g = tracks[ok]
         f = fit[ok]
@@ -59,13 +90,16 @@ def compare_params(tracks, ref, row, y, t, ocfg):
                 "tau": (g["tau"], f["tau"]), "qpt": (g["qpt"], f["qpt"])}
         for k, (a, b) in cols.items():
             a = a.astype(np.float64)
-            rel = np.abs(a - b) / np.maximum(np.abs(b), FLOORS[k])
+            d = np.abs(a - b)
+            rel = d / np.maximum(np.abs(b), FLOORS[k])
             i = int(np.argmax(rel))
             assert rel[i] <= REL, "param %s: gpu %r oracle %r (rel %.3g, track %d)" % (k, a[i], b[i], rel[i], i)
             worst = max(worst, float(rel.max()))
+            nz = np.abs(b) > 0
+            pure[k] = float(np.percentile(d[nz] / np.abs(b[nz]), 99.9)) if nz.any() else 0.0
         c = g["chi2"].astype(np.float64)
         relc = np.abs(c - f["chi2"]) / np.maximum(f["chi2"], 1.0)
         assert relc.max() <= CHI2_REL, "chi2 rel %.3g" % relc.max()
         assert np.array_equal(g["ndf"], f["ndf"])
     assert excluded <= max(2, len(tracks) // 100), "%d tracks with a failed fit on one side" % excluded
-    return dict(worst=worst, excluded=excluded)
+    return dict(worst=worst, excluded=excluded, excluded_why=why, pure_rel_p999=pure)
