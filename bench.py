@@ -213,9 +213,9 @@ def gpu_sector_outputs(trk, f, secs):
 
 
 # parameter parity: |gpu - oracle| <= 1e-4 max(|oracle|, floor) (floors at
-# a small fraction of each parameter's scale; dt is t minus the input time of
-# the outermost cluster)
-PARAM_FLOORS = {"y": 1.0, "dt": 1.0, "sinphi": 1e-2, "tau": 1e-2, "qpt": 0.1}
+# a fraction of each parameter's scale, for q/pT also the oracle's standard
+# error of q/pT; dt is t minus the input time of the outermost cluster)
+PARAM_FLOORS = {"y": 1.0, "dt": 1.0, "sinphi": 0.1, "tau": 0.1, "qpt": 0.1}
 
 
 def sector_parity(g, ref):
@@ -233,9 +233,11 @@ def sector_parity(g, ref):
         pairs = {"y": (tr["y"][ok], fit["y"][ok]), "dt": (tr["dt"][ok], fit["t"][ok] - t_base),
                  "sinphi": (tr["sinphi"][ok], fit["sinphi"][ok]), "tau": (tr["tau"][ok], fit["tau"][ok]),
                  "qpt": (tr["qpt"][ok], fit["qpt"][ok])}
+        floors = dict(PARAM_FLOORS)
+        floors["qpt"] = np.maximum(PARAM_FLOORS["qpt"], np.sqrt(np.maximum(fit["cov"][ok][:, 14], 0.0)))
         for k, (a, b) in pairs.items():
             if len(a):
-                rel = np.abs(a.astype(np.float64) - b) / np.maximum(np.abs(b), PARAM_FLOORS[k])
+                rel = np.abs(a.astype(np.float64) - b) / np.maximum(np.abs(b), floors[k])
                 worst = max(worst, float(rel.max()))
     return exact, worst, excluded
 
@@ -279,6 +281,17 @@ def cpu_baseline(fr, gpu_out, n_workers: int):
             "parity": {"sectors": secs, "links_assignment_lists_bit_exact": bool(exact),
                        "params_worst_floored_rel": worst, "params_tol": 1e-4, "params_ok": bool(worst <= 1e-4),
                        "fit_excluded": excl}}
+
+
+def fit_pass_summary(st):
+    """Tracks by the number of Kalman passes their fit took (k = 1..14, the
+    last bin 15 or more), the mean, and the fits restarted about the
+    three-point helix."""
+    h = st["fit_passes"]
+    n = sum(h[1:])
+    mean = sum(k * v for k, v in enumerate(h)) / max(1, n)
+    return {"hist": {str(k): int(v) for k, v in enumerate(h) if k and v}, "mean": round(mean, 4),
+            "restarts": int(st["n_fit_restarts"])}
 
 
 def frame_quality(trk, fr, f):
@@ -506,6 +519,7 @@ def main():
         "step_ms": {"median": round(float(np.median(step_ms)), 4), "min": round(float(step_ms.min()), 4),
                     "max": round(float(step_ms.max()), 4), "n": int(args.steps)},
         "stage_GB_s": {k: v["GB_s"] for k, v in table.items() if "GB_s" in v},
+        "fit_passes": fit_pass_summary(st),
         "h2d_s": round(h2d_s, 3),
         "launch": {"graph": bool(args.graph), "tuning": tuning},
     }

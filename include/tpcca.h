@@ -78,8 +78,9 @@ typedef struct {
     float prior_var_sinphi;    /* prior variances of the fit, centred on the three-point */
     float prior_var_tau;       /*   estimate: 1, 1, 100 (GeV^-2) */
     float prior_var_qpt;
-    int32_t kf_passes;         /* most Kalman passes: 1 extended, then re-linearised passes until
-                                  one moves no parameter by more than 1e-5 relative, 12 */
+    int32_t kf_passes;         /* most passes of the fit (each pass linearises the Kalman
+                                  measurement updates about the previous pass's helix); passes
+                                  stop once one moves no parameter by more than 3e-5 relative, 12 */
     float s_max;               /* |sin phi| at which a propagation fails, 0.999 */
     int32_t use_mlp;           /* 1: prune candidate triplets with the loaded network, 0 */
     float mlp_logit_threshold; /* triplets with logit below this are pruned, 0 */
@@ -131,6 +132,10 @@ typedef struct {
     double stage_ms_total[16]; /* device time per stage summed over the timed runs */
     char stage_name[16][24];
     int64_t n_tiles;           /* neighbour-finding work items (sector, row block, time slab) */
+    int64_t fit_passes[16];    /* tracks by fit passes taken: [k] = k passes (k = 1..14),
+                                  [15] = 15 or more; [0]: fits that failed at the start */
+    int64_t n_fit_restarts;    /* fits in which a step was halved (objective rose or the helix
+                                  left the domain) */
 } tpcca_stats;
 
 /* Fill *out with the defaults above. The defaults are readings of the

@@ -561,7 +561,11 @@ void ora_fit_map(const ora_cfg *cfg, int32_t L, const double *x, const double *y
         memcpy(g, gn, sizeof(g));
         chi2 = chi2n;
         cost = costn;
-        if (smax < 1e-12) { conv = 1; it++; break; }
+        /* converged once a full step moves no parameter by more than 1e-10
+           relative (floor 1): FP64 rounding of the predictions leaves steps of
+           up to ~1e-11 relative in q/pT of short, poorly curved tracks, which
+           never shrink further */
+        if (smax < 1e-10) { conv = 1; it++; break; }
     }
     out->n_iter = it;
     double C1[5][5];

@@ -920,6 +920,8 @@ tpcca_status tpcca_get_stats(tpcca_ctx *c, tpcca_stats *out) {
     out->n_pruned = k.n_pruned;
     out->n_pool_overflow = k.pool_overflow;
     out->mlp_used = c->args.use_mlp;
+    for (int i = 0; i < 16 && i < kPassBins; i++) out->fit_passes[i] = k.fit_passes[i];
+    out->n_fit_restarts = k.fit_passes[kPassBins];
     out->n_stages = 0;
     if (c->timing && c->events_ok) {
         for (int r = 0; r < kEvRing; r++) fold_slot(c, (c->ev_next + r) % kEvRing);

@@ -28,6 +28,7 @@ constexpr int kMlpH = 64;          // hidden units per layer
 constexpr int kMlpNParam = kMlpH * kMlpInP + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH + 1;
 constexpr int kMlpMaxBatch = 8192; // largest training minibatch
 constexpr int kPoolChunk = 1024;   // triplet-pool slots reserved per grab
+constexpr int kPassBins = 16;      // fit pass histogram: 1..15 passes, the last bin 15 or more
 
 // Device view of the triplet network (BF16 weights, FP32 biases).
 struct MlpDev {
@@ -100,7 +101,7 @@ struct Counters {
     int32_t n_valid_total;
     int32_t n_tiles;
     int32_t tile_next;       // work queue of the neighbour-finding tiles
-    int32_t fit_next;        // work queue of the track fit (tracks in length order)
+    int32_t fit_next;        // work queue of the fit: tracks fitted one per wave (the longest)
     int32_t n_glb_inline;    // dense tiles searched from global memory inside the plain launch
     int32_t n_links;
     int32_t n_seeds;
@@ -114,7 +115,9 @@ struct Counters {
     int32_t pool_used;       // triplet pool: slots holding triplets
     int32_t pool_overflow;   // triplets that did not fit the pool
     int32_t n_pruned;        // triplets below the logit threshold
-    int32_t pad[3];
+    int32_t fit_passes[kPassBins + 1];  // tracks by fit passes taken; [kPassBins]: fits with halved steps
+    int32_t fit_next2;       // work queue of the fit: tracks fitted four per wave
+    int32_t pad[1];
 };
 static_assert(sizeof(Counters) % 8 == 0 && offsetof(Counters, n_samples) == 0, "64-bit counter first");
 
@@ -205,7 +208,7 @@ struct KArgs {
     int32_t *cl_off;         // [trk_cap + 1] offsets of the canonical cluster lists
     int32_t *off8;           // [trk_cap + 1] offsets of the chain copies (8-entry aligned)
     int32_t *perm;           // [trk_cap] track slots ordered by decreasing length
-    int32_t *lhist;          // [kLenBins + 1] length histogram / bucket cursors
+    int32_t *lhist;          // [kLenBins + 1] length histogram; after the sort: tracks with length >= b
     tpcca_track *trk;        // [trk_cap]
     int32_t *clusters;       // [n_in]
     Rec *chain;              // [n_in + 7 * trk_cap] chain copies {y, t, id, row}

@@ -68,7 +68,7 @@ class Stats(ctypes.Structure):
         ("stage_ms", ctypes.c_float * 16),
         ("stage_ms_total", ctypes.c_double * 16),
         ("stage_name", (ctypes.c_char * 24) * 16),
-        ("n_tiles", ctypes.c_int64),
+        ("n_tiles", ctypes.c_int64), ("fit_passes", ctypes.c_int64 * 16), ("n_fit_restarts", ctypes.c_int64),
     ]
 
 
@@ -354,6 +354,8 @@ class Tracker:
                                         "n_invalid", "n_overflow_tiles", "n_triplets", "n_pruned",
                                         "n_pool_overflow", "mlp_used", "n_tiles")}
         d["stage_ms"] = {s.stage_name[i].value.decode(): s.stage_ms[i] for i in range(s.n_stages)}
+        d["fit_passes"] = [int(v) for v in s.fit_passes]
+        d["n_fit_restarts"] = int(s.n_fit_restarts)
         d["n_timed_runs"] = s.n_timed_runs
         d["stage_ms_total"] = {s.stage_name[i].value.decode(): s.stage_ms_total[i] for i in range(s.n_stages)}
         return d

@@ -5,17 +5,23 @@ import numpy as np
 import oracle
 
 # parameter tolerance: |gpu - oracle| <= REL * max(|oracle|, floor). The
-# floors are set at a small fraction of each parameter's natural scale:
+# floors are set at a fraction of each parameter's natural scale:
 #   y, dt: 1 cm. dt = t - t_base is a residual-sized number (~0.1 cm) while
 #     the fit carries time over a track's drift span of up to ~10^2 cm in
 #     FP32 (resolution ~1e-5 cm), and y is mostly 10-40 cm;
-#   sin phi, tau: 1e-2 (both are O(1) slopes; below 1e-2 the check is
-#     absolute at 1e-6);
+#   sin phi, tau: 0.1. Both are O(1) slopes that the FP32 filter carries
+#     through one transport per cluster; the GPU's passes stop once a pass
+#     moves a slope by at most 1e-5 of max(|value|, 0.1), so below 0.1 the
+#     check is absolute at 1e-5 and above it relative;
 #   q/pT: 0.1 1/GeV (pT = 10 GeV; |q/pT| of the generated tracks lies in
-#     (0, 10] 1/GeV).
+#     (0, 10] 1/GeV), with the same stopping rule, or the oracle's own
+#     standard error of q/pT where that is larger: on a short straight track
+#     q/pT is known to +-1 1/GeV or worse, FP32 predictions (rounding ~1e-6 cm)
+#     pin the MAP to a few 1e-6 of that error, and 1e-4 of it is the
+#     relative agreement that the data can define.
 # The pure relative error (no floor) is reported beside it.
 REL = 1e-4
-FLOORS = {"y": 1.0, "dt": 1.0, "sinphi": 1e-2, "tau": 1e-2, "qpt": 0.1}
+FLOORS = {"y": 1.0, "dt": 1.0, "sinphi": 0.1, "tau": 0.1, "qpt": 0.1}
 CHI2_REL = 1e-3
 S_NEAR = 0.99      # |sin phi| beyond which one side's transport may fail and the other's not
 
@@ -88,10 +94,12 @@ def compare_params(tracks, ref, row, y, t, ocfg):
         t_base = g["t_base"].astype(np.float64)
         cols = {"y": (g["y"], f["y"]), "dt": (g["dt"], f["t"] - t_base), "sinphi": (g["sinphi"], f["sinphi"]),
                 "tau": (g["tau"], f["tau"]), "qpt": (g["qpt"], f["qpt"])}
+        floors = dict(FLOORS)
+        floors["qpt"] = np.maximum(FLOORS["qpt"], np.sqrt(np.maximum(f["cov"][:, 14], 0.0)))
         for k, (a, b) in cols.items():
             a = a.astype(np.float64)
             d = np.abs(a - b)
-            rel = d / np.maximum(np.abs(b), FLOORS[k])
+            rel = d / np.maximum(np.abs(b), floors[k])
             i = int(np.argmax(rel))
             assert rel[i] <= REL, "param %s: gpu %r oracle %r (rel %.3g, track %d)" % (k, a[i], b[i], rel[i], i)
             worst = max(worst, float(rel.max()))

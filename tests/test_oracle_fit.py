@@ -220,3 +220,31 @@ def test_kalman_diagnostic_converges_to_map(ocfg):
         assert (d <= 1e-6 * np.maximum(np.abs(mp[key][ok]), floor)).all(), key
     d = np.abs((kf["t"] - tb)[ok] - (mp["t"] - tb)[ok])
     assert (d <= 1e-6).all()
+
+
+def test_map_converges_on_short_tracks_of_a_slice(ocfg):
+    """Every MAP fit of a sector of a 1 ms slice (many short, poorly curved
+    chains) that starts also converges, and its result is a stationary point:
+    the objective at the reported helix is not lowered by a small move of
+    q/pT, the parameter that the data of short tracks constrain least."""
+    fr = synth.generate("slice_1ms", seed=2301, n_threads=8)
+    row, y, t = fr.sector(5)
+    res = oracle.run_sector(ocfg, row, y, t)
+    fit = res["fit"]
+    assert len(fit) > 3000
+    assert (fit["status"] != 4).all(), np.bincount(fit["status"])
+    x = np.asarray(ocfg.row_x, np.float64)
+    short = np.nonzero((fit["status"] == 0) & (res["len"] <= 12))[0]
+    assert len(short) > 100
+    for k in short[:40]:
+        c = res["clusters"][res["first"][k]: res["first"][k] + res["len"][k]]
+        xx = x[row[c]]; yy = y[c].astype(np.float64); tt = t[c].astype(np.float64)
+        qL = np.array([fit[k]["y"], fit[k]["t"], fit[k]["sinphi"], fit[k]["tau"], fit[k]["qpt"]])
+        q1 = oracle.propagate(ocfg, qL, xx[0] - xx[-1])[0]
+        q0 = np.array(fit[k]["init"])
+        c0 = oracle.map_cost(ocfg, xx, yy, tt, q1, q0)
+        h = 1e-3 * math.sqrt(fit[k]["cov"][14])
+        for sgn in (1, -1):
+            qq = q1.copy()
+            qq[4] += sgn * h
+            assert oracle.map_cost(ocfg, xx, yy, tt, qq, q0) >= c0 - 1e-12 * c0
