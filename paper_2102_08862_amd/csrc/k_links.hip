@@ -508,6 +508,199 @@ __device__ void tile_links(const KArgs &a, TileShared &T, const TileGeo &G, int 
     if ((tid & 63) == 0 && nl) atomicAdd(&T.links, nl);
 }
 
+// LDS written by lanes of one wave and read by others of the same wave:
+// the wave's LDS operations complete in order; this keeps the compiler from
+// moving them across.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------- plain search in LDS
+// The plain search of a staged tile, 64 own clusters per wave and round, with
+// loops whose trip counts are uniform over the wave (the maximum over its
+// lanes; lanes past their own count are masked), so that control flow
+// stays on the scalar unit once per step instead of once per lane branch:
+//  1. each lane takes the staged positions of the fine bins its box overlaps
+//     on the down and the up row (rows are staged in fine-bin order);
+//  2. box tests over those ranges, 32 positions per step, give a bit mask of
+//     the candidates on each row;
+//  3. every (down, up) pair of set bits is scored, and the lexicographic
+//     minimum of (c, up input index, down input index) kept.
+// Clusters without a gap-1 pair wait in their wave's queue and are searched
+// at gap 2, 64 at a time.
+constexpr int kPlainWq = kQueueCap / (kLinkBlock / 64);    // gap-2 queue of a wave
+
+__device__ inline int wave_max_u(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Staged fine-bin range of row j overlapped by [tlo, thi] (absolute LDS
+// positions; lo == hi: empty).
+__device__ inline void bin_range(const TileShared &T, const TileGeo &G, int j, int f0, int f1, int &lo, int &hi) {
+    const int b = T.base[j];
+    if (f1 < 0 || f0 >= G.nfb) {
+        lo = hi = b;
+        return;
+    }
+    lo = b + T.fs[j][max(f0, 0)];
+    hi = b + T.fs[j][min(f1, G.nfb - 1) + 1];
+}
+
+// Bit mask of the positions lo + k0 + [0, 32) in [lo, hi) whose cluster lies
+// in the box around (yi, ti) (down row: |yi - y| and |ti - t|; up row:
+// |y - yi| and |t - ti|). nk: the wave-uniform number of positions to test.
+template <bool Down>
+__device__ inline uint32_t box_mask(const TileShared &T, int lo, int hi, int k0, int nk, float yi, float ti, float wy,
+                                    float wt) {
+    uint32_t m = 0u;
+    for (int k = 0; k < nk; k++) {
+        const int p = lo + k0 + k;
+        const bool v = p < hi;
+        const float2 e = T.yt[v ? p : 0];
+        const float dy = Down ? __fsub_rn(yi, e.x) : __fsub_rn(e.x, yi);
+        const float dt = Down ? __fsub_rn(ti, e.y) : __fsub_rn(e.y, ti);
+        const bool in = v && fabsf(dy) <= wy && fabsf(dt) <= wt;
+        m |= (in ? 1u : 0u) << k;
+    }
+    return m;
+}
+
+// Best pair of the lane's own cluster (yi, ti) on staged rows jd / ju at gap
+// g (act: the lane has a cluster to search). bu/bd: sorted positions or -1.
+__device__ void flat_pair(const KArgs &a, const TileShared &T, const TileGeo &G, bool act, int jd, int ju, float yi,
+                          float ti, float w, float wy, float wt, int &bu, int &bd) {
+    const float st = slack(ti, wt);
+    int dlo = 0, dhi = 0, ulo = 0, uhi = 0;
+    if (act) {
+        const int f0 = fine_bin(__fsub_rn(__fsub_rn(ti, wt), st), G.t0, G.inv_cbw, G.nf) - G.fb0;
+        const int f1 = fine_bin(__fadd_rn(__fadd_rn(ti, wt), st), G.t0, G.inv_cbw, G.nf) - G.fb0;
+        bin_range(T, G, jd, f0, f1, dlo, dhi);
+        bin_range(T, G, ju, f0, f1, ulo, uhi);
+    }
+    const int maxd = wave_max_u(dhi - dlo), maxu = wave_max_u(uhi - ulo);
+    const float c2 = a.pair_c2;
+    bool found = false;
+    float bc = 0.f;
+    int bpu = 0, bpd = 0;
+    for (int d0 = 0; d0 < maxd; d0 += 32) {
+        const uint32_t dm = box_mask<true>(T, dlo, dhi, d0, min(32, maxd - d0), yi, ti, wy, wt);
+        if (!__any(dm != 0u)) continue;
+        for (int u0 = 0; u0 < maxu; u0 += 32) {
+            const uint32_t um = dm ? box_mask<false>(T, ulo, uhi, u0, min(32, maxu - u0), yi, ti, wy, wt) : 0u;
+            const int md = wave_max_u(um ? __popc(dm) : 0), mu = wave_max_u(__popc(um));
+            uint32_t dd = um ? dm : 0u;
+            for (int x = 0; x < md; x++) {
+                const bool vd = dd != 0u;
+                const int pd = dlo + d0 + (vd ? __builtin_ctz(dd) : 0);
+                dd &= dd - 1u;
+                const float2 ed = T.yt[vd ? pd : 0];
+                uint32_t uu = vd ? um : 0u;
+                for (int z = 0; z < mu; z++) {
+                    const bool v = uu != 0u;
+                    const int pu = ulo + u0 + (v ? __builtin_ctz(uu) : 0);
+                    uu &= uu - 1u;
+                    const float2 eu = T.yt[v ? pu : 0];
+                    const float c = pair_score(yi, ti, ed.x, ed.y, eu.x, eu.y, w);
+                    const bool acc = v && c <= c2;
+                    bool better = acc && (!found || c < bc);
+                    const bool tie = acc && found && c == bc;
+                    if (__any(tie)) {
+                        if (tie) {
+                            // exact tie of the score: compare input indices
+                            const int idu = a.rec[T.plo[ju] + (pu - T.base[ju])].id;
+                            const int idd = a.rec[T.plo[jd] + (pd - T.base[jd])].id;
+                            const int biu = a.rec[T.plo[ju] + (bpu - T.base[ju])].id;
+                            const int bid = a.rec[T.plo[jd] + (bpd - T.base[jd])].id;
+                            better = idu < biu || (idu == biu && idd < bid);
+                        }
+                    }
+                    found = found || acc;
+                    bc = better ? c : bc;
+                    bpu = better ? pu : bpu;
+                    bpd = better ? pd : bpd;
+                }
+            }
+        }
+    }
+    if (found) {
+        bu = T.plo[ju] + (bpu - T.base[ju]);
+        bd = T.plo[jd] + (bpd - T.base[jd]);
+    }
+}
+
+__device__ void tile_links_flat(const KArgs &a, TileShared &T, const TileGeo &G, int r0, int s0, int nown,
+                                int own_total) {
+    const int R = a.n_rows;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int jr0 = r0 - s0;
+    const int G2 = a.max_gap;
+    int16_t *WQ = T.queue + wv * kPlainWq;
+    int nq = 0, nl = 0;   // nq: wave-uniform
+    int base = wv * 64;
+    for (;;) {
+        const bool drain = nq >= 64 || (base >= own_total && nq > 0);
+        if (!drain && base >= own_total) break;
+        int o;
+        bool act;
+        int g;
+        if (drain) {
+            const int take = min(nq, 64);
+            act = lane < take;
+            o = act ? (int)WQ[nq - take + lane] : -1;
+            nq -= take;
+            g = 2;
+        } else {
+            o = base + lane;
+            act = o < own_total;
+            if (!act) o = -1;
+            base += kLinkBlock;
+            g = 1;
+        }
+        int j = 0, q = 0, r = 0;
+        float yi = 0.f, ti = 0.f, w = 0.f;
+        if (act) {
+            own_locate(T, jr0, nown, o, j, q);
+            r = s0 + j;
+            const float2 e = T.yt[T.base[j] + q];
+            yi = e.x;
+            ti = e.y;
+            act = r - g >= 0 && r + g <= R - 1;
+            if (act) w = a.w_tab[r * kMaxGap + g - 1];
+        }
+        int bu = -1, bd = -1;
+        flat_pair(a, T, G, act, j - g, j + g, yi, ti, w, a.win_y[g - 1], a.win_t[g - 1], bu, bd);
+        // gap 2 for the clusters without a gap-1 pair
+        const bool g2 = o >= 0 && g == 1 && bu < 0 && G2 >= 2 && r >= 2 && r + 2 <= R - 1;
+        const uint64_t m = __ballot(g2);
+        const int ng2 = __popcll(m);
+        if (ng2 && nq + ng2 > kPlainWq) {
+            // the queue is full: search them now (rare)
+            const bool act2 = g2;
+            int bu2 = -1, bd2 = -1;
+            float w2 = act2 ? a.w_tab[r * kMaxGap + 1] : 0.f;
+            flat_pair(a, T, G, act2, j - 2, j + 2, yi, ti, w2, a.win_y[1], a.win_t[1], bu2, bd2);
+            if (g2) {
+                bu = bu2;
+                bd = bd2;
+            }
+        } else if (g2) {
+            WQ[nq + __popcll(m & ((1ull << lane) - 1ull))] = (int16_t)o;
+        }
+        const bool queued = g2 && !(ng2 && nq + ng2 > kPlainWq);
+        if (ng2 && nq + ng2 <= kPlainWq) nq += ng2;
+        if (o >= 0 && !queued) {
+            a.link[T.plo[j] + q] = make_int2(bu, bd);
+            nl += (bu >= 0);
+        }
+        wave_lds_sync();
+    }
+    for (int off = 32; off > 0; off >>= 1) nl += __shfl_xor(nl, off);
+    if (lane == 0 && nl) atomicAdd(&T.links, nl);
+}
+
 // ---------------------------------------------------------------- pruned search
 // The network scores the candidate triplets inside the search, one wave at
 // a time (no workgroup barrier between the searches of a tile): per round,
@@ -540,13 +733,6 @@ struct alignas(16) PruneSharedT {
 static_assert(kTileCap <= (1 << 12) && kPrCap <= kTileCap, "16-bit LDS indices");
 using TilePr = TileSharedT<kPrCap, kWaves * kWq>;
 
-// LDS written by lanes of one wave and read by others of the same wave:
-// the wave's LDS operations complete in order; this keeps the compiler from
-// moving them across.
-__device__ inline void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
 
 __device__ inline int wave_excl_scan(int v, int &total) {
     const int lane = threadIdx.x & 63;
@@ -868,6 +1054,8 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
             //     order): a count over the bin, one lane per cluster;
             //  C: the row-local index of each rank (oq);
             //  D: (y, t) and y cell in rank order, read again from the row.
+            // The plain search stages each row in its fine-bin order (step A
+            // writes (y, t) directly; no ranking).
             {
                 const int wv = tid >> 6, lane = tid & 63;
                 int2 *yti = reinterpret_cast<int2 *>(T.yt);
@@ -885,9 +1073,13 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
                         int f = 0x7fffffff;
                         if (q < n) {
                             const float2 e = *reinterpret_cast<const float2 *>(a.rec + plo + q);
-                            T.cell[bj + q] = (uint8_t)ycell_of(yc, e.x);
                             f = fine_bin(e.y, G.t0, G.inv_cbw, G.nf) - G.fb0;
-                            yti[bj + q].x = f;
+                            if constexpr (Mode == kPlain) {
+                                T.yt[bj + q] = e;
+                            } else {
+                                T.cell[bj + q] = (uint8_t)ycell_of(yc, e.x);
+                                yti[bj + q].x = f;
+                            }
                         }
                         int fp = __shfl_up(f, 1);
                         if (lane == 0) fp = carry;
@@ -895,6 +1087,7 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
                             for (int b = max(fp + 1, 0); b <= min(f, G.nfb); b++) T.fs[j][b] = (int16_t)q;
                         carry = __shfl(f, 63);
                     }
+                    if constexpr (Mode == kPlain) continue;   // the plain search takes rows in fine-bin order
                     wave_lds_sync();
                     for (int q = lane; q < n; q += 64) {
                         const int f = yti[bj + q].x;
@@ -920,6 +1113,7 @@ __global__ __launch_bounds__(kLinkBlock, Mode == kPlain ? 4 : 3) void k_links(KA
             }
             __syncthreads();
             if constexpr (Mode == kPrune) tile_prune<InLds>(a, T, X.P, G, si, r0, s0, nsr, nown, own_total);
+            else if constexpr (Mode == kPlain) tile_links_flat(a, T, G, r0, s0, nown, own_total);
             else tile_links<Mode, true>(a, T, G, si, r0, s0, nown, own_total);
         } else {
             if constexpr (Mode == kPrune) tile_prune<InLds>(a, T, X.P, G, si, r0, s0, nsr, nown, own_total);
