@@ -34,7 +34,7 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector
 #            written (8)                                            16 B/cluster
 #   seeds:   links read (8), partner links gathered (8), cleaned up link
 #            written (4) (cleaning fused with the seed test)        20 B/cluster
-#   emit + fit: (y, t, link) per track cluster read (12), assignment
+#   walk + fit: (y, t, link) per track cluster read (12), assignment
 #            written (4), 128-byte track record per track           16 B/track cluster + 128 B/track
 # The per-kernel figures below split the same totals over the kernels that
 # move them (the grid's kernels each read or write an intermediate record).
@@ -44,8 +44,8 @@ STAGE_BYTES = {
     "rowsort": lambda s: 32 * s["n_clusters"],
     "links": lambda s: 16 * s["n_clusters"],
     "seeds": lambda s: 20 * s["n_clusters"],
-    # chain copy: records gathered, copies written
-    "emit": lambda s: 32 * s["n_track_clusters"],
+    # chain walk and copy: records gathered, copies written
+    "walk": lambda s: 32 * s["n_track_clusters"],
     # the fit (the cluster lists and the assignment run beside it)
     "fit": lambda s: 16 * s["n_track_clusters"] + 128 * s["n_tracks"],
 }
@@ -58,7 +58,7 @@ GRID_STAGES = ("hist", "setup", "scatter", "rowsort")
 
 # the kernel that dominates each stage (the stage's other launches are small)
 STAGE_KERNEL = {"hist": "k_hist", "scatter": "k_scatter", "rowsort": "k_rowsort", "links": "k_links",
-                "seeds": "k_seeds", "chainlen": "k_chainlen", "emit": "k_emit", "fit": "k_fit"}
+                "seeds": "k_seeds", "walk": "k_walk", "fit": "k_fit"}
 
 WORKLOADS = {
     "frame_10ms": "whole 10 ms TPC time frame: 36 sectors x 152 rows, 500 Pb-Pb collisions at 50 kHz "

@@ -237,9 +237,10 @@ tpcca_status tpcca_set_graph(tpcca_ctx *ctx, int32_t on);
 
 /* Set by the autotuner (this library's extension; the paper only asks for
    efficient use of the GPU, Sec. 1).
-   Launch shape of one stage (the tpcca_stats.stage_name order: 1 hist,
-   3 scatter, 4 rowsort, 5 links, 6 seeds, 7 chainlen, 8 slots, 10 emit,
-   11 fit): blocks_per_cu persistent workgroups per compute unit (0: keep).
+   Launch shape of one kernel group (1 histogram, 3 row scatter, 4 row sort,
+   5 neighbour links, 6 seeds, 7 chain walk and copy, 8 track slots,
+   10 cluster lists and assignment, 11 fit): blocks_per_cu persistent
+   workgroups per compute unit (0: keep).
    For stage 5, param sets how many clusters a neighbour-finding tile may
    stage in LDS (256..3072, 0: keep; smaller tiles give more work items).
    Results do not depend on these settings. */

@@ -15,14 +15,14 @@ import os
 
 import numpy as np
 
-STAGES = {            # stage index -> (name, blocks-per-CU candidates, tile-budget candidates)
+STAGES = {            # launch index -> (timed stage, blocks-per-CU candidates, tile-budget candidates)
     1: ("hist", (2, 4, 8, 16), (0,)),
     3: ("scatter", (1, 2, 4), (0,)),
     4: ("rowsort", (1, 2, 3, 4), (0,)),
     5: ("links", (2, 3, 4), (768, 1536, 2304, 3072)),
     6: ("seeds", (2, 4, 8, 16), (0,)),
-    7: ("chainlen", (2, 4, 8, 16), (0,)),
-    10: ("emit", (2, 4, 8, 16), (0,)),
+    7: ("walk", (2, 4, 8, 16), (0,)),
+    10: ("fit", (2, 4, 8, 16), (0,)),     # cluster lists, on the side stream beside the fit
     11: ("fit", (2, 4, 8, 16), (0,)),
 }
 

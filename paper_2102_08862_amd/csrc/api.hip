@@ -39,11 +39,11 @@ struct Layout {
     size_t tstart, ntile, tile_base, tiles, glb_tiles;
     int64_t tile_cap = 0;
     size_t tmp, rec, link, upc;
-    size_t seeds, tseed, tlen, tslot, tprov, prov;
+    size_t seeds, tseed, tlen, tslot, tchoff, choff;
     size_t bits, wpre;
     size_t trk_len, trk_seed, cl_off, trk;
     size_t clusters, assign, scan_tmp, asg_cnt;
-    size_t off8, perm, lhist, chain;
+    size_t perm, lhist, chain, chain_bytes, xslot;
     size_t pfeat, pd, pu, pc, pz, hoff, hn1, hn2;
     int64_t pool_cap = 0;
 };
@@ -60,9 +60,9 @@ struct Bump {
     }
 };
 
-const char *kStageNames[] = {"reset",   "hist",  "setup",   "scatter", "rowsort", "links", "seeds",
-                             "chainlen", "slots", "clscan",  "emit",    "fit"};
-constexpr int kNumStages = 12;
+const char *kStageNames[] = {"reset", "hist",  "setup",  "scatter", "rowsort", "links",
+                             "seeds", "walk",  "slots",  "clscan",  "fit"};
+constexpr int kNumStages = 11;
 constexpr size_t kTabBlockDefault = 1 << 20;
 constexpr int kEvRing = 64;
 
@@ -77,7 +77,7 @@ struct tpcca_ctx {
     // the cluster lists and the assignment run on a side stream beside the
     // fit (they share no buffer with it); forked and joined with events
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork0 = nullptr, ev_fork = nullptr, ev_sorted = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<std::vector<SectorIn>> frames;
     char *arena = nullptr;
     size_t arena_bytes = 0;
@@ -108,7 +108,7 @@ struct tpcca_ctx {
     size_t tab_cap = 0;
     int64_t n_in = 0;
     int32_t n_words = 0;
-    Launch lc[kNumStages];
+    Launch lc[kMaxStages];   // launch shapes by stage index (1 hist .. 11 fit; see tpcca_set_launch)
     bool use_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -230,15 +230,13 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
         for (int i = 0; i <= kNumStages; i++)
             if (hipEventCreate(&c->ev[r][i]) != hipSuccess) c->events_ok = false;
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork0, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_sorted, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         tpcca_destroy(c);
         return TPCCA_ERR_DEVICE;
     }
     const int cu = std::max(1, c->n_cu);
-    for (int i = 0; i < kNumStages; i++) c->lc[i] = Launch{cu * 8, 256};
+    for (int i = 0; i < kMaxStages; i++) c->lc[i] = Launch{cu * 8, 256};
     c->lc[3] = Launch{cu, 1024};      // scatter: 134 KB LDS, 1024 threads
     c->lc[4] = Launch{cu * 4, 1024};  // rowsort: 36 KB LDS, 1024 threads
     c->lc[5] = Launch{cu * 4, 256};  // links: 34 KB LDS -> 4 resident blocks per CU
@@ -281,7 +279,7 @@ void tpcca_destroy(tpcca_ctx *c) {
         (void)hipStreamSynchronize(c->side);
         (void)hipStreamDestroy(c->side);
     }
-    for (hipEvent_t e : {c->ev_fork0, c->ev_fork, c->ev_sorted, c->ev_join})
+    for (hipEvent_t e : {c->ev_fork, c->ev_join})
         if (e) (void)hipEventDestroy(e);
     if (c->abort_host) (void)hipHostFree(c->abort_host);
     if (c->tab_dev) (void)hipFree(c->tab_dev);
@@ -470,11 +468,12 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     const int64_t seed_cap = N / 2 + 64;
     const int64_t tseed_cap = N / std::max(2, c->cfg.min_track_hits) + 64;
     const int64_t trk_cap = tseed_cap;
+    // the chain copies: one run of a multiple of 4 entries per track
+    const int64_t chain_cap = N + 3 * trk_cap;
     // every device buffer is indexed with 32-bit positions: the chain copies
-    // (one 8-entry-aligned run per track, off8 is an int32 scan) hold up to
-    // N + 7 * trk_cap entries and the assignment buckets N rounded up to a
-    // bucket plus one bucket; both must stay below 2^31
-    if (N + 7 * trk_cap + 8 > (int64_t)INT32_MAX || (N / 16384 + 2) * (int64_t)16384 > (int64_t)INT32_MAX)
+    // hold up to N + 3 * trk_cap entries and the assignment buckets N rounded
+    // up to a bucket plus one bucket; both must stay below 2^31
+    if (chain_cap + 8 > (int64_t)INT32_MAX || (N / 16384 + 2) * (int64_t)16384 > (int64_t)INT32_MAX)
         return fail(c, TPCCA_ERR_INVALID_ARG,
                     "too many clusters in one run for 32-bit positions (" + std::to_string(N) + ")");
     const int64_t SR = (int64_t)S * R;
@@ -515,34 +514,37 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     if (L.tile_cap > (int64_t)0x7fff0000) return fail(c, TPCCA_ERR_INVALID_ARG, "too many sectors in one run");
     L.tiles = b.take(sizeof(int2) * L.tile_cap);
     L.glb_tiles = b.take(sizeof(int32_t) * L.tile_cap);
-    // the row-grouped staging buffer is dead after the row sort: the chain
-    // copies for the fit reuse it
-    // also holds the assignment's bucketed pairs after the row sort
-    L.tmp = b.take(std::max(sizeof(Rec) * N, sizeof(int2) * (size_t)(N + 16384)));
+    // Scratch region reused across the sequential steps:
+    //   scatter -> row sort:        tmp, the row-grouped records (16 B/cluster)
+    //   seeds -> walk:              cleaned up links and the seed list (slot)
+    //   walk -> fit:                the chain copies
+    //   lists -> assignment (side): the (input, track) pairs per bucket (slot)
+    // tmp and the chain copies share the region's start (tmp is dead after
+    // the row sort, before the walk writes the copies); the slot after the
+    // chain copies holds the cleaned links and seeds, then the pairs.
+    L.chain_bytes = sizeof(Rec) * (size_t)chain_cap;
+    const size_t slot_bytes = std::max(align_up(sizeof(int32_t) * (size_t)N, 256) + sizeof(int32_t) * (size_t)seed_cap,
+                                       sizeof(int2) * (size_t)(N + 2 * 16384));
+    L.chain = b.take(L.chain_bytes + 256 + slot_bytes);
+    L.tmp = L.chain;
+    L.xslot = L.chain + align_up(L.chain_bytes, 256);
+    L.upc = L.xslot;
+    L.seeds = L.xslot + align_up(sizeof(int32_t) * (size_t)N, 256);
     L.rec = b.take(sizeof(Rec) * N);
     L.link = b.take(sizeof(int2) * N);
-    L.upc = b.take(sizeof(int32_t) * N);
-    L.seeds = b.take(sizeof(int32_t) * seed_cap);
     L.tseed = b.take(sizeof(int32_t) * tseed_cap);
     L.tlen = b.take(sizeof(int32_t) * tseed_cap);
     L.tslot = b.take(sizeof(int32_t) * tseed_cap);
-    L.tprov = b.take(sizeof(int32_t) * tseed_cap);
-    // the chain walk records the positions it visits for the first
-    // prov_seeds seeds (chains are a few percent of the clusters); the output
-    // stage then gathers them instead of walking again
-    const int64_t prov_seeds = N / 32 + 64;
-    L.prov = b.take(sizeof(int32_t) * prov_seeds * R);
+    L.tchoff = b.take(sizeof(int32_t) * tseed_cap);
     L.bits = b.take(sizeof(uint32_t) * (W + 1));
     L.wpre = b.take(sizeof(int32_t) * (W + 1));
     L.trk_len = b.take(sizeof(int32_t) * (trk_cap + 1));
     L.trk_seed = b.take(sizeof(int32_t) * trk_cap);
     L.cl_off = b.take(sizeof(int32_t) * (trk_cap + 1));
     L.trk = b.take(sizeof(tpcca_track) * trk_cap);
-    L.off8 = b.take(sizeof(int32_t) * (trk_cap + 1));
+    L.choff = b.take(sizeof(int32_t) * trk_cap);
     L.perm = b.take(sizeof(int32_t) * trk_cap);
     L.lhist = b.take(sizeof(int32_t) * (kLenBins + 1));
-    // chain copies for the fit: every track's chain padded to 8 entries
-    L.chain = b.take(sizeof(Rec) * (N + 7 * trk_cap));
     L.clusters = b.take(sizeof(int32_t) * N);
     L.assign = b.take(sizeof(int32_t) * N);
     L.asg_cnt = b.take(sizeof(int32_t) * (N / 16384 + 2));
@@ -574,7 +576,7 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     a.n_words = (int32_t)W;
     a.seed_cap = (int32_t)seed_cap;
     a.tseed_cap = (int32_t)tseed_cap;
-    a.prov_seeds = (int32_t)prov_seeds;
+    a.chain_cap = chain_cap;
     a.trk_cap = (int32_t)trk_cap;
     a.max_gap = c->cfg.max_gap;
     a.n_rb = nrb;
@@ -642,8 +644,7 @@ static void bind_pointers(tpcca_ctx *c) {
     a.tseed = (int32_t *)(A + L.tseed);
     a.tlen = (int32_t *)(A + L.tlen);
     a.tslot = (int32_t *)(A + L.tslot);
-    a.tprov = (int32_t *)(A + L.tprov);
-    a.prov = (int32_t *)(A + L.prov);
+    a.tchoff = (int32_t *)(A + L.tchoff);
     a.bits = (uint32_t *)(A + L.bits);
     a.wpre = (int32_t *)(A + L.wpre);
     a.trk_len = (int32_t *)(A + L.trk_len);
@@ -651,12 +652,12 @@ static void bind_pointers(tpcca_ctx *c) {
     a.cl_off = (int32_t *)(A + L.cl_off);
     a.trk = (tpcca_track *)(A + L.trk);
     a.clusters = (int32_t *)(A + L.clusters);
-    a.off8 = (int32_t *)(A + L.off8);
+    a.choff = (int32_t *)(A + L.choff);
     a.perm = (int32_t *)(A + L.perm);
     a.lhist = (int32_t *)(A + L.lhist);
     a.chain = (Rec *)(A + L.chain);
     a.assign = (int32_t *)(A + L.assign);
-    a.asg_pairs = (int2 *)(A + L.tmp);
+    a.asg_pairs = (int2 *)(A + L.xslot);
     a.asg_cnt = (int32_t *)(A + L.asg_cnt);
     a.scan_tmp = (int32_t *)(A + L.scan_tmp);
     a.abort_flag = c->abort_dev;
@@ -717,29 +718,22 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     mark(st++);
     launch_seeds(a, c->lc[6], s);
     mark(st++);
-    launch_chainlen(a, c->lc[7], s);
+    launch_walk(a, c->lc[7], s);
     mark(st++);
     launch_scan_popc(a.bits, a.n_words, a.wpre, &cnt->n_tracks, a.scan_tmp, s);
     launch_track_slots(a, c->lc[8], s);
     launch_si_tracks(a, s);
     mark(st++);
     launch_scan_i32_dev(a.trk_len, &cnt->n_tracks, a.trk_cap, a.cl_off, &cnt->n_cl, a.scan_tmp, s);
-    launch_scan_round8_dev(a.trk_len, &cnt->n_tracks, a.trk_cap, a.off8, a.scan_tmp, s);
     launch_si_clusters(a, s);
     mark(st++);
-    // side stream: the length order of the fit beside the chain copy, then
-    // the cluster lists and the assignment beside the fit
-    (void)hipEventRecord(c->ev_fork0, s);
-    (void)hipStreamWaitEvent(c->side, c->ev_fork0, 0);
-    launch_len_sort(a, c->lc[11], c->side);
-    (void)hipEventRecord(c->ev_sorted, c->side);
-    launch_emit(a, c->lc[10], s);
+    // side stream: the cluster lists and the assignment, beside the length
+    // order and the fit on the main stream (they share no buffer)
     (void)hipEventRecord(c->ev_fork, s);
     (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
     launch_lists(a, c->lc[10], c->side);
     (void)hipEventRecord(c->ev_join, c->side);
-    mark(st++);
-    (void)hipStreamWaitEvent(s, c->ev_sorted, 0);
+    launch_len_sort(a, c->lc[11], s);
     launch_fit(a, c->lc[11], s);
     (void)hipStreamWaitEvent(s, c->ev_join, 0);   // join
     mark(st++);

@@ -4,16 +4,15 @@
 //                links (cleaning), kept up links written out (one 4-byte
 //                gather per chain step afterwards); seed = mutual up link
 //                and no mutual down link; seeds compacted with wave ballots
-//   k_chainlen   one lane per seed: walk the chain of mutual links to its
-//                end; chains with >= min_track_hits clusters are tracks; set
-//                the seed's bit in the sector's input-index bitmap
+//   k_walk       one lane per seed: walk the chain of mutual links to its
+//                end; chains with >= min_track_hits clusters are tracks: set
+//                the seed's bit in the sector's input-index bitmap and copy
+//                the chain's clusters {y, t, id, sector/row} to a reserved
+//                run of the chain copies (walked again, links in cache)
 //   (scan)       prefix popcounts of the bitmap give every track its number:
 //                tracks are numbered in ascending seed input index
 //   k_track_slot track slot, length and seed of every track
 //   (scan)       prefix of lengths -> offsets of the cluster lists
-//   k_emit       one lane per track: gather the chain's clusters (positions
-//                recorded by the walk, or a second walk) and write the
-//                track's chain copy {y, t, id, row} contiguously
 //   k_lists      cluster lists (input indices, rows ascending) and the
 //                assignment, through per-bucket runs
 //   k_asg_fill   the assignment, one bucket of input indices at a time
@@ -85,65 +84,98 @@ void launch_seeds(const KArgs &a, Launch l, hipStream_t s) {
     hipLaunchKernelGGL(k_seeds, dim3(max(1, min(l.grid, nch))), dim3(256), 0, s, a);
 }
 
-__global__ __launch_bounds__(256) void k_chainlen(KArgs a) {
+// One lane per seed: walk the chain of mutual links to its end (one 4-byte
+// cleaned-link gather per step); a chain of >= min_track_hits clusters is a
+// track: its seed bit is set in the sector's input-index bitmap, and a second
+// walk of the same chain (its links now in cache) copies its clusters
+// {y, t, input index, (sector instance << 8) | row} to a run of the chain
+// copies that the wave reserves with one atomic (runs of a multiple of 4
+// entries, so the fit's loads of 4 consecutive records are 64-byte aligned).
+constexpr int kWalkBatch = 4;
+
+__device__ inline int wave_excl_sum(int v, int &total) {
+    const int lane = threadIdx.x & 63;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    total = __shfl(x, 63);
+    return x - v;
+}
+
+__global__ __launch_bounds__(256) void k_walk(KArgs a) {
     TPCCA_ABORT_GUARD(a);
-    __shared__ int s_scan[256];
-    __shared__ int s_base;
     const int ns = min(a.cnt->n_seeds, a.seed_cap);
     const int R = a.n_rows;
+    const int lane = threadIdx.x & 63;
     const int stride = gridDim.x * blockDim.x;
-    for (int base = blockIdx.x * blockDim.x; base < ns; base += stride) {
-        const int k = base + threadIdx.x;
+    // uniform per wave: every lane of a wave runs the same iterations
+    for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < ns; base += stride) {
+        const int k = base + lane;
         int p = 0, L = 0;
         if (k < ns) {
             p = a.seeds[k];
-            // positions are kept 8 at a time in registers and stored as
-            // two 16-byte vectors (rows of prov are 16-byte aligned)
-            int32_t *pv = (k < a.prov_seeds && (R & 3) == 0) ? a.prov + (int64_t)k * R : nullptr;
             int q = p;
             L = 1;
-            int qb[8];
-            qb[0] = q;
             for (int step = 0; step < R; step++) {
                 const int u = a.upc[q];   // mutual up link (cleaned)
                 if (u < 0) break;
                 q = u;
-                if ((L & 7) == 0 && pv && L <= R - 8) {
-                    reinterpret_cast<int4 *>(pv + L - 8)[0] = make_int4(qb[0], qb[1], qb[2], qb[3]);
-                    reinterpret_cast<int4 *>(pv + L - 8)[1] = make_int4(qb[4], qb[5], qb[6], qb[7]);
-                }
-#pragma unroll
-                for (int b = 0; b < 8; b++)
-                    if (b == (L & 7)) qb[b] = q;
                 L++;
-            }
-            if (pv) {
-                const int j0 = (L - 1) & ~7;
-#pragma unroll
-                for (int b = 0; b < 8; b++)
-                    if (j0 + b < L && j0 + b < R) pv[j0 + b] = qb[b];
             }
         }
         const bool trk = (k < ns) && L >= a.min_track_hits;
-        int tot;
-        const int excl = block_excl_scan(trk ? 1 : 0, s_scan, tot);
-        if (threadIdx.x == 0) s_base = tot ? atomicAdd(&a.cnt->n_tseeds, tot) : 0;
-        __syncthreads();
-        const int slot = s_base + excl;
-        if (trk && slot < a.tseed_cap) {
+        const int len4 = trk ? (L + kWalkBatch - 1) & ~(kWalkBatch - 1) : 0;
+        int n_trk, n_ent;
+        const int r_trk = wave_excl_sum(trk ? 1 : 0, n_trk);
+        const int r_ent = wave_excl_sum(len4, n_ent);
+        int s0 = 0, c0 = 0;
+        if (lane == 0 && n_trk) {
+            s0 = atomicAdd(&a.cnt->n_tseeds, n_trk);
+            c0 = atomicAdd(&a.cnt->chain_next, n_ent);
+        }
+        s0 = __shfl(s0, 0);
+        c0 = __shfl(c0, 0);
+        const int slot = s0 + r_trk;
+        const int64_t off = (int64_t)c0 + r_ent;
+        if (trk && slot < a.tseed_cap && off + len4 <= (int64_t)a.chain_cap) {
             a.tseed[slot] = p;
             a.tlen[slot] = L;
-            a.tprov[slot] = (k < a.prov_seeds && L <= R && (R & 3) == 0) ? k : -1;
-            const Rec e = a.rec[p];
+            a.tchoff[slot] = (int32_t)off;
+            Rec e = a.rec[p];
             const int si = e.sr >> 8;
             atomicOr(&a.bits[a.si[si].word_base + (e.id >> 5)], 1u << (e.id & 31));
+            Rec *dst = a.chain + off;
+            int q = p;
+            for (int j0 = 0; j0 < L; j0 += kWalkBatch) {
+                Rec buf[kWalkBatch];
+#pragma unroll
+                for (int b = 0; b < kWalkBatch; b++) {
+                    const int j = j0 + b;
+                    if (j < L) {
+                        buf[b] = e;
+                        if (j + 1 < L) {
+                            q = a.upc[q];
+                            e = a.rec[q];
+                        }
+                    } else {
+                        buf[b] = Rec{0.f, 0.f, -1, e.sr};
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < kWalkBatch; b++)
+                    reinterpret_cast<int4 *>(dst + j0)[b] = *reinterpret_cast<const int4 *>(&buf[b]);
+            }
+        } else if (trk) {
+            atomicAdd(&a.cnt->overflow, 1);
         }
-        __syncthreads();
     }
 }
 
-void launch_chainlen(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL(k_chainlen, dim3(l.grid), dim3(256), 0, s, a);
+void launch_walk(const KArgs &a, Launch l, hipStream_t s) {
+    hipLaunchKernelGGL(k_walk, dim3(l.grid), dim3(256), 0, s, a);
 }
 
 __global__ __launch_bounds__(256) void k_track_slot(KArgs a) {
@@ -160,6 +192,7 @@ __global__ __launch_bounds__(256) void k_track_slot(KArgs a) {
         if (g < a.trk_cap) {
             a.trk_len[g] = a.tlen[k];
             a.trk_seed[g] = p;
+            a.choff[g] = a.tchoff[k];
         }
     }
 }
@@ -194,77 +227,6 @@ void launch_si_clusters(const KArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_si_clusters, dim3((a.n_si + 255) / 256), dim3(256), 0, s, a);
 }
 
-// One lane per track, in seed order (neighbouring seeds walk neighbouring
-// rows, so the gathers share cache lines). Each lane buffers 8 chain entries
-// in registers and writes them as one 128-byte line of its track's chain
-// copy, so the scattered per-lane output never leaves partial lines.
-constexpr int kEmitBatch = 8;
-
-__global__ __launch_bounds__(256) void k_emit(KArgs a) {
-    TPCCA_ABORT_GUARD(a);
-    const int nt = min(a.cnt->n_tseeds, a.tseed_cap);
-    const int R = a.n_rows;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nt; k += gridDim.x * blockDim.x) {
-        const int g = a.tslot[k];
-        if (g >= a.trk_cap) continue;
-        int q = a.tseed[k];
-        const int L = min(a.trk_len[g], R);
-        Rec *dst = a.chain + a.off8[g];
-        Rec e = a.rec[q];
-        const int pk = a.tprov[k];
-        if (pk >= 0) {
-            // positions recorded by the chain walk: independent gathers
-            const int32_t *pv = a.prov + (int64_t)pk * R;
-            for (int j0 = 0; j0 < L; j0 += kEmitBatch) {
-                int qs[kEmitBatch];
-#pragma unroll
-                for (int b = 0; b < kEmitBatch; b++) qs[b] = (j0 + b < L) ? pv[j0 + b] : -1;
-                Rec buf[kEmitBatch];
-#pragma unroll
-                for (int b = 0; b < kEmitBatch; b++) {
-                    if (qs[b] >= 0) {
-                        const Rec f = a.rec[qs[b]];
-                        buf[b].y = f.y;
-                        buf[b].t = f.t;
-                        buf[b].id = f.id;
-                        buf[b].sr = f.sr & 255;
-                    } else {
-                        buf[b] = Rec{0.f, 0.f, -1, 0};
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < kEmitBatch; b++) dst[j0 + b] = buf[b];
-            }
-            continue;
-        }
-        for (int j0 = 0; j0 < L; j0 += kEmitBatch) {
-            Rec buf[kEmitBatch];
-#pragma unroll
-            for (int b = 0; b < kEmitBatch; b++) {
-                const int j = j0 + b;
-                if (j < L) {
-                    buf[b].y = e.y;
-                    buf[b].t = e.t;
-                    buf[b].id = e.id;
-                    buf[b].sr = e.sr & 255;
-                    if (j + 1 < L) {
-                        q = a.upc[q];
-                        e = a.rec[q];
-                    }
-                } else {
-                    buf[b] = Rec{0.f, 0.f, -1, 0};
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < kEmitBatch; b++) dst[j0 + b] = buf[b];
-        }
-    }
-}
-
-void launch_emit(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL(k_emit, dim3(l.grid), dim3(256), 0, s, a);
-}
-
 // Canonical cluster lists and the assignment. The lists: the input indices
 // of the chain copies, written in list order (the lists of a range of tracks
 // are contiguous). The assignment is a permutation from track order to input
@@ -296,18 +258,18 @@ __global__ __launch_bounds__(256) void k_lists(KArgs a) {
     __shared__ int32_t h[kAsgHist];
     // per-track values of the range, loaded in parallel once (a track's
     // sector and offsets are a chain of dependent loads)
-    __shared__ int32_t m_len[kAsgTracks], m_cl[kAsgTracks], m_off8[kAsgTracks], m_ib[kAsgTracks],
+    __shared__ int32_t m_len[kAsgTracks], m_cl[kAsgTracks], m_choff[kAsgTracks], m_ib[kAsgTracks],
         m_tn[kAsgTracks];
     __shared__ int32_t s_lo, s_span;
     const int nt = min(a.cnt->n_tracks, a.trk_cap);
     for (int g0 = blockIdx.x * kAsgTracks; g0 < nt; g0 += gridDim.x * kAsgTracks) {
         const int g1 = min(g0 + kAsgTracks, nt);
         for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-            const int si = a.rec[a.trk_seed[g]].sr >> 8;
+            const int si = a.chain[a.choff[g]].sr >> 8;
             const int k = g - g0;
             m_len[k] = a.trk_len[g];
             m_cl[k] = a.cl_off[g];
-            m_off8[k] = a.off8[g];
+            m_choff[k] = a.choff[g];
             m_ib[k] = a.si[si].in_base;
             m_tn[k] = g - a.st[si].trk_base;
             if (g == g0) s_lo = a.si[si].in_base / kAsgBucket;
@@ -335,7 +297,7 @@ __global__ __launch_bounds__(256) void k_lists(KArgs a) {
                 if (p < P1) {
                     const int k = range_track(m_cl, nk, p);
                     tk[u] = k;
-                    id[u] = a.chain[m_off8[k] + (p - m_cl[k])].id;
+                    id[u] = a.chain[m_choff[k] + (p - m_cl[k])].id;
                 }
             }
 #pragma unroll
@@ -500,10 +462,6 @@ struct I32In {
     const int32_t *p;
     __device__ int operator()(int i) const { return p[i]; }
 };
-struct Round8In {
-    const int32_t *p;
-    __device__ int operator()(int i) const { return (p[i] + 7) & ~7; }
-};
 
 template <class F>
 __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(F f, const int32_t *n_dev, int32_t n_host, int32_t n_cap,
@@ -597,11 +555,4 @@ void launch_scan_i32_dev(const int32_t *in, const int32_t *n_dev, int32_t n_cap,
     scan_impl(I32In{in}, n_dev, 0, n_cap, out, total_dst, tmp, s);
 }
 
-}  // namespace tpcca
-
-namespace tpcca {
-void launch_scan_round8_dev(const int32_t *in, const int32_t *n_dev, int32_t n_cap, int32_t *out, int32_t *tmp,
-                            hipStream_t s) {
-    scan_impl(Round8In{in}, n_dev, 0, n_cap, out, nullptr, tmp, s);
-}
 }  // namespace tpcca

@@ -260,11 +260,10 @@ struct FitDone {
 // track computes it, lane 0 writes): the state at x_c carried to x_L, the
 // covariance from the Cholesky factor Hf of the information matrix at x_c
 // (null: zero), C' = F H^-1 F^T.
-__device__ inline void fit_emit(const KArgs &a, const float *sx, int g, int L, const Rec &cm, const Rec &cL,
+__device__ inline void fit_emit(const KArgs &a, const float *sx, int g, int L, const Rec &e0, const Rec &cm, const Rec &cL,
                                 float xc, const float q[5], float chi2, int status, const float (*Hf)[5],
                                 bool writer) {
     const float kB = a.bz_kb, smax = a.s_max;
-    const Rec e0 = a.rec[a.trk_seed[g]];
     const int si = e0.sr >> 8;
     tpcca_track o;
     o.frame = a.si[si].frame;
@@ -330,7 +329,7 @@ __device__ void fit_wave(const KArgs &a, const float *sx, int32_t *hist, FitDone
     const bool have = qi < nt;
     const int g = have ? a.perm[qi] : 0;
     const int L = have ? a.trk_len[g] : 0;
-    const Rec *ch = a.chain + (have ? a.off8[g] : 0);
+    const Rec *ch = a.chain + (have ? a.choff[g] : 0);
     // reference cluster (middle) and the clusters of this lane, relative
     const int mi = (L + 1) / 2 - 1;
     Rec cm = {}, c1 = {}, cL = {};
@@ -531,7 +530,7 @@ __device__ void fit_wave(const KArgs &a, const float *sx, int32_t *hist, FitDone
         float qf[5];
 #pragma unroll
         for (int i = 0; i < 5; i++) qf[i] = D.q[i];
-        fit_emit(a, sx, g, L, cm, cL, xc, qf, D.chi2, D.status, D.has_cov ? D.Hf : nullptr, gl == 0);
+        fit_emit(a, sx, g, L, c1, cm, cL, xc, qf, D.chi2, D.status, D.has_cov ? D.Hf : nullptr, gl == 0);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -101,7 +101,7 @@ struct Counters {
     int32_t n_valid_total;
     int32_t n_tiles;
     int32_t tile_next;       // work queue of the neighbour-finding tiles
-    int32_t fit_next;        // work queue of the fit: tracks fitted one per wave (the longest)
+    int32_t fit_next;        // work queue of the fit (tracks in length order)
     int32_t n_glb_inline;    // dense tiles searched from global memory inside the plain launch
     int32_t n_links;
     int32_t n_seeds;
@@ -116,7 +116,7 @@ struct Counters {
     int32_t pool_overflow;   // triplets that did not fit the pool
     int32_t n_pruned;        // triplets below the logit threshold
     int32_t fit_passes[kPassBins + 1];  // tracks by fit passes taken; [kPassBins]: fits with halved steps
-    int32_t fit_next2;       // work queue of the fit: tracks fitted four per wave
+    int32_t chain_next;      // chain copy entries handed out by the walk
     int32_t pad[1];
 };
 static_assert(sizeof(Counters) % 8 == 0 && offsetof(Counters, n_samples) == 0, "64-bit counter first");
@@ -198,20 +198,20 @@ struct KArgs {
     int32_t *tseed;          // [tseed_cap]
     int32_t *tlen;           // [tseed_cap]
     int32_t *tslot;          // [tseed_cap]
-    int32_t *tprov;          // [tseed_cap] row of the track's walk in prov, or -1
-    int32_t *prov;           // [prov_seeds * n_rows] positions visited by each seed's walk
-    int32_t prov_seeds;
+    int32_t *tchoff;         // [tseed_cap] offset of the track's chain copy (per track seed)
     uint32_t *bits;          // [n_words]
     int32_t *wpre;           // [n_words + 1]
     int32_t *trk_len;        // [trk_cap + 1]
     int32_t *trk_seed;       // [trk_cap]
     int32_t *cl_off;         // [trk_cap + 1] offsets of the canonical cluster lists
-    int32_t *off8;           // [trk_cap + 1] offsets of the chain copies (8-entry aligned)
+    int32_t *choff;          // [trk_cap] offset of each track's chain copy (4-entry aligned)
     int32_t *perm;           // [trk_cap] track slots ordered by decreasing length
     int32_t *lhist;          // [kLenBins + 1] length histogram; after the sort: tracks with length >= b
     tpcca_track *trk;        // [trk_cap]
     int32_t *clusters;       // [n_in]
-    Rec *chain;              // [n_in + 7 * trk_cap] chain copies {y, t, id, row}
+    Rec *chain;              // [chain_cap] chain copies {y, t, id, (si << 8) | row}, a run of a multiple
+                             // of 4 entries per track
+    int64_t chain_cap;       // n_in + 3 * trk_cap
     int32_t *assign;         // [n_in]
     int2 *asg_pairs;         // [buckets * 16384] (input index, track number), in the dead staging buffer
     int32_t *asg_cnt;        // [buckets] pairs per bucket of 16384 input indices
@@ -285,13 +285,10 @@ void launch_mlp_infer(const MlpDev &W, const uint16_t *X, const int32_t *n_dev, 
                       hipStream_t s);
 void launch_mlp_train(const MlpTrainArgs &t, hipStream_t s);
 void launch_seeds(const KArgs &a, Launch l, hipStream_t s);
-void launch_chainlen(const KArgs &a, Launch l, hipStream_t s);
+void launch_walk(const KArgs &a, Launch l, hipStream_t s);
 void launch_track_slots(const KArgs &a, Launch l, hipStream_t s);
-void launch_emit(const KArgs &a, Launch l, hipStream_t s);
 void launch_lists(const KArgs &a, Launch l, hipStream_t s);
 void launch_len_sort(const KArgs &a, Launch l, hipStream_t s);
-void launch_scan_round8_dev(const int32_t *in, const int32_t *n_dev, int32_t n_cap, int32_t *out, int32_t *tmp,
-                            hipStream_t s);
 void launch_fit(const KArgs &a, Launch l, hipStream_t s);
 // exclusive scans: out[i] = sum_{j<i} f(in[j]), out[n] = total, *total_dst = total
 void launch_scan_popc(const uint32_t *in, int32_t n, int32_t *out, int32_t *total_dst, int32_t *tmp,

@@ -9,7 +9,7 @@ is only valid for the kernels it was taken on.
 
   W="python -m paper_2102_08862_amd.traffic run"
   rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \\
-      'k_links|k_rowsort|k_scatter|k_hist|k_emit|k_lists|k_asg_fill|k_fit|k_seeds|k_chainlen|k_copy' \\
+      'k_links|k_rowsort|k_scatter|k_hist|k_lists|k_asg_fill|k_fit|k_seeds|k_walk|k_copy' \\
       -d OUT/fetch -o f --output-format csv -- $W
   rocprofv3 --pmc WRITE_SIZE (same options) -d OUT/write -o w --output-format csv -- $W
   python -m paper_2102_08862_amd.traffic summarize OUT/fetch OUT/write --out profiles/traffic_frame_10ms.txt
@@ -32,7 +32,7 @@ COPY_BYTES = 1 << 30
 SOURCES = {
     "k_hist": "k_grid.hip", "k_scatter": "k_grid.hip", "k_rowsort": "k_grid.hip", "k_copy": "k_grid.hip",
     "k_tiles": "k_links.hip", "k_links": "k_links.hip", "k_select": "k_links.hip",
-    "k_seeds": "k_chain.hip", "k_chainlen": "k_chain.hip", "k_emit": "k_chain.hip", "k_lists": "k_chain.hip",
+    "k_seeds": "k_chain.hip", "k_walk": "k_chain.hip", "k_lists": "k_chain.hip",
     "k_asg_fill": "k_chain.hip", "k_tile_list": "k_links.hip",
     "k_fit": "k_fit.hip", "k_mlp_infer": "k_mlp.hip",
 }
