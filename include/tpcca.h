@@ -37,6 +37,8 @@
  *     by tpcca_required_arena when the loaded frames need more. tpcca_run,
  *     tpcca_synchronize, the fetches and the network calls never allocate;
  *     a run whose tables would not fit fails with STATE instead.
+ *     tpcca_run_noalloc runs without an attached arena, in a static device
+ *     array owned by the library (TPCCA_NOALLOC_ARENA_BYTES per GPU).
  *   - All device work is enqueued on the caller's stream (tpcca_set_stream)
  *     and tpcca_run() does not wait for it; tpcca_synchronize() does.
  */
@@ -214,6 +216,25 @@ tpcca_status tpcca_attach_arena(tpcca_ctx *ctx, void *device_ptr, size_t bytes);
    if no frame is loaded or the frames changed since tpcca_required_arena in
    a way that needs a larger table block. Allocates nothing. */
 tpcca_status tpcca_run(tpcca_ctx *ctx);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): tpcca_run
+   with the run's working buffers in a library-owned static device array of
+   TPCCA_NOALLOC_ARENA_BYTES bytes on the context's GPU instead of the
+   attached arena (no arena needs to be attached). The run is eager (no
+   graph capture) on the context's stream; it calls no hipMalloc, hipFree or
+   other allocating routine. Returns CAPACITY if the loaded frames need more
+   arena than the static array holds (tpcca_required_arena gives the size;
+   about 130 MB go to the per-sector tables of one frame, the rest holds
+   ~78 bytes per cluster), STATE if the context's table block is too small
+   (call tpcca_required_arena once beforehand), DEVICE if the array is not
+   available on this GPU. Every call on a GPU, from any context, shares that
+   GPU's array: calls that overlap on one GPU race, and a call's results
+   (read with the fetch functions) stay valid only until the next such call
+   on that GPU. A later tpcca_run switches the context back to its attached
+   arena. */
+#define TPCCA_NOALLOC_ARENA_BYTES ((size_t)160 << 20)
+tpcca_status tpcca_run_noalloc(tpcca_ctx *ctx);
 
 /* Wait for the last run; DEVICE on a HIP error, ABORTED if it was aborted,
    CAPACITY if a pruned run overflowed its triplet pool. */

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -68,6 +69,33 @@ constexpr int kEvRing = 64;
 
 }  // namespace
 
+// The library-owned run arena of tpcca_run_noalloc, for callers that cannot
+// allocate device memory: a static device array (each GPU the library runs
+// on holds its own copy until the process ends). Host code never passes the
+// array's name to a kernel or a copy: the name is a host-side stand-in; the
+// device address of each GPU's copy is taken once per device with
+// hipGetSymbolAddress (in tpcca_create, with that device current) and used
+// everywhere instead.
+static __device__ __align__(256) char scratch[TPCCA_NOALLOC_ARENA_BYTES];
+constexpr int kMaxDevices = 64;
+static char *g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static hipError_t scratch_setup(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (g_scratch[dev]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch[dev] = (char *)p;
+    return e;
+}
+
+static char *scratch_of(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (dev >= 0 && dev < kMaxDevices) ? g_scratch[dev] : nullptr;
+}
+
 struct tpcca_ctx {
     tpcca_config cfg{};
     std::vector<float> row_x;
@@ -79,8 +107,10 @@ struct tpcca_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<std::vector<SectorIn>> frames;
-    char *arena = nullptr;
+    char *arena = nullptr;       // arena of the current (last) run
     size_t arena_bytes = 0;
+    char *user_arena = nullptr;  // the caller's arena (tpcca_attach_arena)
+    size_t user_arena_bytes = 0;
     bool plan_dirty = true;
     bool upload_dirty = true;
     bool have_results = false;
@@ -225,6 +255,9 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
         delete c;
         return TPCCA_ERR_DEVICE;
     }
+    // the no-allocation entry point's arena on this device (a failure only
+    // disables that entry point)
+    (void)scratch_setup(c->device);
     c->events_ok = true;
     for (int r = 0; r < kEvRing; r++)
         for (int i = 0; i <= kNumStages; i++)
@@ -769,8 +802,8 @@ tpcca_status tpcca_attach_arena(tpcca_ctx *c, void *ptr, size_t bytes) {
     if (!c) return TPCCA_ERR_INVALID_ARG;
     if (ptr && ((uintptr_t)ptr & 255)) return fail(c, TPCCA_ERR_INVALID_ARG, "arena must be 256-byte aligned");
     (void)hipStreamSynchronize(c->stream);
-    c->arena = (char *)ptr;
-    c->arena_bytes = ptr ? bytes : 0;
+    c->arena = c->user_arena = (char *)ptr;
+    c->arena_bytes = c->user_arena_bytes = ptr ? bytes : 0;
     c->upload_dirty = true;
     c->graph_valid = false;
     c->have_results = false;
@@ -783,6 +816,23 @@ tpcca_status tpcca_request_abort(tpcca_ctx *c) {
     return TPCCA_OK;
 }
 
+}  // extern "C"
+
+// Make `ptr` the arena of the next run (a change of arena re-uploads the
+// tables and staged inputs and drops a captured graph).
+static void use_arena(tpcca_ctx *c, char *ptr, size_t bytes) {
+    if (c->arena != ptr) {
+        c->upload_dirty = true;
+        c->graph_valid = false;
+    }
+    c->arena = ptr;
+    c->arena_bytes = bytes;
+}
+
+static tpcca_status run_on_arena(tpcca_ctx *c, bool graphs);
+
+extern "C" {
+
 tpcca_status tpcca_run(tpcca_ctx *c) {
     if (!c) return TPCCA_ERR_INVALID_ARG;
     if (c->frames.empty()) return fail(c, TPCCA_ERR_STATE, "no frame loaded");
@@ -790,9 +840,33 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
         tpcca_status s = plan(c, false);
         if (s != TPCCA_OK) return s;
     }
+    use_arena(c, c->user_arena, c->user_arena_bytes);
     if (!c->arena || c->arena_bytes < c->lay.total)
         return fail(c, TPCCA_ERR_NOMEM, "arena of " + std::to_string(c->arena_bytes) + " bytes, run needs " +
                                             std::to_string(c->lay.total));
+    return run_on_arena(c, c->use_graph);
+}
+
+tpcca_status tpcca_run_noalloc(tpcca_ctx *c) {
+    if (!c) return TPCCA_ERR_INVALID_ARG;
+    if (c->frames.empty()) return fail(c, TPCCA_ERR_STATE, "no frame loaded");
+    char *A = scratch_of(c->device);
+    if (!A) return fail(c, TPCCA_ERR_DEVICE, "the static run arena of this device is unavailable");
+    if (c->plan_dirty) {
+        tpcca_status s = plan(c, false);
+        if (s != TPCCA_OK) return s;
+    }
+    if (c->lay.total > TPCCA_NOALLOC_ARENA_BYTES)
+        return fail(c, TPCCA_ERR_CAPACITY, "the run needs " + std::to_string(c->lay.total) +
+                                               " bytes of arena, the static arena holds " +
+                                               std::to_string((size_t)TPCCA_NOALLOC_ARENA_BYTES));
+    use_arena(c, A, TPCCA_NOALLOC_ARENA_BYTES);
+    return run_on_arena(c, false);
+}
+
+}  // extern "C"
+
+static tpcca_status run_on_arena(tpcca_ctx *c, bool graphs) {
     hipStream_t s = c->stream;
     bind_pointers(c);
     const Layout &L = c->lay;
@@ -838,13 +912,13 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
         HIPCHK(c, hipStreamSynchronize(s));
         c->upload_dirty = false;
     }
-    const bool tm = c->timing && c->events_ok && !c->use_graph;
+    const bool tm = c->timing && c->events_ok && !graphs;
     const int slot = c->ev_next;
     if (tm) {
         fold_slot(c, slot);  // the slot is reused: fold its previous run first
         c->ev_next = (slot + 1) % kEvRing;
     }
-    if (c->use_graph) {
+    if (graphs) {
         if (!c->graph_valid) {
             // capture on an idle stream (earlier work of this or another
             // context on the stream finishes first)
@@ -870,6 +944,8 @@ tpcca_status tpcca_run(tpcca_ctx *c) {
     c->have_results = true;
     return TPCCA_OK;
 }
+
+extern "C" {
 
 tpcca_status tpcca_synchronize(tpcca_ctx *c) {
     if (!c) return TPCCA_ERR_INVALID_ARG;

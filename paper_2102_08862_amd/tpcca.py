@@ -76,7 +76,7 @@ class Stats(ctypes.Structure):
 EXPORTS = [
     "tpcca_config_default", "tpcca_create", "tpcca_destroy", "tpcca_last_error", "tpcca_set_stream",
     "tpcca_add_frame", "tpcca_clear_frames", "tpcca_load_sector", "tpcca_required_arena",
-    "tpcca_attach_arena", "tpcca_run", "tpcca_synchronize", "tpcca_request_abort", "tpcca_set_timing",
+    "tpcca_attach_arena", "tpcca_run", "tpcca_run_noalloc", "tpcca_synchronize", "tpcca_request_abort", "tpcca_set_timing",
     "tpcca_get_stats", "tpcca_get_tracks", "tpcca_get_track_clusters", "tpcca_get_assignment",
     "tpcca_get_links", "tpcca_mlp_state_bytes", "tpcca_mlp_attach", "tpcca_mlp_load", "tpcca_mlp_fetch",
     "tpcca_mlp_infer", "tpcca_mlp_grad", "tpcca_mlp_train_step", "tpcca_get_triplets", "tpcca_set_graph",
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "tpcca_required_arena": [P, ctypes.POINTER(SZ)],
         "tpcca_attach_arena": [P, P, SZ],
         "tpcca_run": [P],
+        "tpcca_run_noalloc": [P],
         "tpcca_synchronize": [P],
         "tpcca_request_abort": [P],
         "tpcca_set_timing": [P, I32],
@@ -309,6 +310,12 @@ class Tracker:
     def run(self, sync: bool = False):
         self.ensure_arena()
         self._check(self.lib.tpcca_run(self.h))
+        if sync:
+            self.synchronize()
+
+    def run_noalloc(self, sync: bool = False):
+        """Run with the library's static device arena (no arena, no allocation)."""
+        self._check(self.lib.tpcca_run_noalloc(self.h))
         if sync:
             self.synchronize()
 
