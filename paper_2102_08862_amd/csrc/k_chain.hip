@@ -39,40 +39,68 @@ __device__ inline int block_excl_scan(int v, int *sh, int &total) {
 
 
 // Compaction of a block's flags: one global atomic per chunk of kCompactChunk
-// positions, so that the single output counter is not contended.
+// positions, so that the single output counter is not contended. Inside a
+// chunk the seeds are listed in position order (sub-chunk k of 256
+// positions, then wave, then lane), so that neighbouring lanes of the chain
+// walk start from neighbouring clusters of one pad row and their walks
+// gather from the same cache lines.
 constexpr int kCompactPer = 32;
 constexpr int kCompactChunk = 256 * kCompactPer;
 
 __global__ __launch_bounds__(256) void k_seeds(KArgs a) {
     TPCCA_ABORT_GUARD(a);
-    __shared__ int s_scan[256];
+    __shared__ int s_cnt[kCompactPer * 4 + 1];
     __shared__ int s_base;
     const int n = min(a.cnt->n_valid_total, a.n_in);
     const int nch = (n + kCompactChunk - 1) / kCompactChunk;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const int base = c * kCompactChunk;
         uint32_t mask = 0;
 #pragma unroll 4
         for (int k = 0; k < kCompactPer; k++) {
             const int p = base + k * 256 + tid;
+            bool seed = false;
             if (p < n) {
                 const int2 l = a.link[p];
                 const bool mu = l.x >= 0 && l.x < n && a.link[l.x].y == p;
                 const bool md = l.y >= 0 && l.y < n && a.link[l.y].x == p;
                 a.upc[p] = mu ? l.x : -1;
-                if (mu && !md) mask |= 1u << k;
+                seed = mu && !md;
+                if (seed) mask |= 1u << k;
+            }
+            const uint64_t b = __ballot(seed);
+            if (lane == 0) s_cnt[k * 4 + wv] = __popcll(b);
+        }
+        __syncthreads();
+        // exclusive prefix over the (sub-chunk, wave) counts in position order
+        if (tid < 64) {
+            int carry = 0;
+            for (int i0 = 0; i0 < kCompactPer * 4; i0 += 64) {
+                const int v = s_cnt[i0 + tid];
+                int x = v;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(x, o);
+                    if (tid >= o) x += y;
+                }
+                s_cnt[i0 + tid] = carry + x - v;
+                carry += __shfl(x, 63);
+            }
+            if (tid == 0) {
+                s_base = carry ? atomicAdd(&a.cnt->n_seeds, carry) : 0;
+                s_cnt[kCompactPer * 4] = carry;
             }
         }
-        int tot;
-        const int excl = block_excl_scan(__popc(mask), s_scan, tot);
-        if (tid == 0) s_base = tot ? atomicAdd(&a.cnt->n_seeds, tot) : 0;
         __syncthreads();
-        int o = s_base + excl;
+        const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll 4
         for (int k = 0; k < kCompactPer; k++) {
-            if ((mask >> k) & 1u) {
+            const bool seed = (mask >> k) & 1u;
+            const uint64_t b = __ballot(seed);
+            if (seed) {
+                const int o = s_base + s_cnt[k * 4 + wv] + __popcll(b & below);
                 if (o < a.seed_cap) a.seeds[o] = base + k * 256 + tid;
-                o++;
             }
         }
         __syncthreads();
