@@ -112,6 +112,10 @@ def _load():
         lib.ora_sizeof_cfg.restype = ctypes.c_int32
         lib.ora_links_pruned.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_double,
                                          P, P, P, P]
+        lib.ora_follow.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P, P, P, P, P, P, P, P, P]
+        lib.ora_follow.restype = ctypes.c_int64
+        lib.ora_kf1_run.argtypes = [ctypes.c_int32, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]
+        lib.ora_kf1_run.restype = None
         lib.ora_triplets.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P]
         lib.ora_triplets.restype = ctypes.c_int64
         lib.ora_bf16.argtypes = [ctypes.c_float]
@@ -278,12 +282,74 @@ def fit_tracks(cfg: Config, first, ln, clusters, row, y, t, kf_passes: int = 0):
     return out
 
 
-def run_sector(cfg: Config, row, y, t, fit: bool = True):
+class _FollowCfg(ctypes.Structure):
+    _fields_ = [("win_y", ctypes.c_float), ("win_t", ctypes.c_float), ("chi2_max", ctypes.c_float),
+                ("q_slope", ctypes.c_float), ("var_y", ctypes.c_float), ("var_t", ctypes.c_float),
+                ("var_slope0", ctypes.c_float), ("max_miss", ctypes.c_int32)]
+
+
+@dataclass
+class FollowConfig:
+    """Constants of the track following (the readings adopted for this build)."""
+    win_y: float = 1.5          # search box half widths around the prediction (cm)
+    win_t: float = 1.5
+    chi2_max: float = 16.0      # gate on dy^2/Vy + dt^2/Vt
+    q_slope: float = 1e-4       # slope variance added per cm of |dx|
+    var_y: float = 0.01         # measurement variances (cm^2)
+    var_t: float = 0.01
+    var_slope0: float = 1.0     # initial slope variance
+    max_miss: int = 3           # consecutive rows without a cluster that end an extension
+
+    def _c(self):
+        c = _FollowCfg()
+        for k in ("win_y", "win_t", "chi2_max", "q_slope", "var_y", "var_t", "var_slope0", "max_miss"):
+            setattr(c, k, getattr(self, k))
+        return c
+
+
+def follow(cfg: Config, fcfg: FollowConfig, row, y, t, first, ln, clusters):
+    """Track following and selection of one sector's tracks: the kept tracks
+    (first, len, clusters), the assignment, and per input track the inward
+    and outward extension counts and the kept cluster count (-1: dropped)."""
+    lib = _load()
+    row, y, t = _in(row, y, t)
+    first = np.ascontiguousarray(first, np.int64); ln = np.ascontiguousarray(ln, np.int32)
+    clusters = np.ascontiguousarray(clusters, np.int32)
+    n, nt = len(row), len(first)
+    of = np.empty(max(nt, 1), np.int64); ol = np.empty(max(nt, 1), np.int32)
+    oc = np.empty(max(n, 1), np.int32); assign = np.empty(n, np.int32)
+    ei = np.zeros(max(nt, 1), np.int32); eo = np.zeros(max(nt, 1), np.int32); kept = np.zeros(max(nt, 1), np.int32)
+    c = cfg._c()
+    fc = fcfg._c()
+    k = lib.ora_follow(ctypes.byref(c), ctypes.byref(fc), n, _p(row), _p(y), _p(t), nt, _p(first), _p(ln),
+                       _p(clusters), _p(of), _p(ol), _p(oc), _p(assign), _p(ei), _p(eo), _p(kept))
+    nc = int(ol[:k].sum()) if k else 0
+    return dict(first=of[:k].copy(), len=ol[:k].copy(), clusters=oc[:nc].copy(), assign=assign,
+                ext_in=ei[:nt].copy(), ext_out=eo[:nt].copy(), kept=kept[:nt].copy())
+
+
+def kf1_run(x, m, var, var_slope0, q):
+    """The following's 1-D filter over the points (x, m) in order, started at
+    the first: (value, slope, p00, p01, p11) at the last point."""
+    lib = _load()
+    x = np.ascontiguousarray(x, np.float32); m = np.ascontiguousarray(m, np.float32)
+    out = np.zeros(5, np.float32)
+    lib.ora_kf1_run(len(x), _p(x), _p(m), var, var_slope0, q, _p(out))
+    return out
+
+
+def run_sector(cfg: Config, row, y, t, fit: bool = True, follow_cfg: FollowConfig | None = None):
     """The whole path on one sector: links, cleaning, chains, assignment, fit."""
     up, dn, gap = links(cfg, row, y, t)
     upc, dnc = clean(up, dn)
     first, ln, cl, assign = tracks(cfg, upc, dnc)
     res = dict(up=up, dn=dn, gap=gap, upc=upc, dnc=dnc, first=first, len=ln, clusters=cl, assign=assign)
+    if follow_cfg is not None:
+        fo = follow(cfg, follow_cfg, row, y, t, first, ln, cl)
+        res["chains"] = dict(first=first, len=ln, clusters=cl, assign=assign)
+        res.update(first=fo["first"], len=fo["len"], clusters=fo["clusters"], assign=fo["assign"],
+                   ext_in=fo["ext_in"], ext_out=fo["ext_out"], kept=fo["kept"])
+        first, ln, cl = fo["first"], fo["len"], fo["clusters"]
     if fit:
         res["fit"] = fit_tracks(cfg, first, ln, cl, row, y, t)
     return res

@@ -728,3 +728,232 @@ void ora_fit_tracks(const ora_cfg *cfg, int64_t n_tracks, const int64_t *first, 
 
 int32_t ora_sizeof_fit(void) { return (int32_t)sizeof(ora_fit); }
 int32_t ora_sizeof_cfg(void) { return (int32_t)sizeof(ora_cfg); }
+
+/* ------------------------------------------------------------ following */
+/* Track following and selection (the rest of an HLT-style tracklet
+   constructor: the paper, Sec. 1, derives the tracker from the Run 2 HLT
+   tracker and asks for more attached hits, Sec. 2; it prints no method, so
+   this is the reading adopted for this build, with FP32 decisions):
+
+   1. For every track of step 3, two linear Kalman filters in FP32, one for
+      y(x) and one for t(x), each with state (value, slope) and covariance
+      (p00, p01, p11), start at the innermost cluster with (value, 0) and
+      diag(var, var_slope0), and take the chain's clusters in row order. A
+      prediction by dx adds q_slope * |dx| to the slope variance:
+        a = a + b*dx;  u = p01 + dx*p11;  p00 = (p00 + dx*p01) + dx*u;
+        p01 = u;  p11 = p11 + q_slope*|dx|
+      an update with measurement m of variance s2:
+        S = p00 + s2;  k0 = p00/S;  k1 = p01/S;  r = m - a;
+        a = a + k0*r;  b = b + k1*r;
+        p00 = p00 - k0*p00;  p01 = p01 - k0*p01;  p11 = p11 - k1*p01(old)
+      (every operation one FP32 rounding, in this order).
+   2. Outward extension: row by row beyond the last cluster, predict both
+      filters to the row; among the row's clusters with |y - y_p| <= win_y
+      and |t - t_p| <= win_t take the one with the smallest
+      chi2 = (dy*dy)/(p00y + var_y) + (dt*dt)/(p00t + var_t), ties to the
+      smaller input index; accept it if chi2 <= chi2_max and update both
+      filters. max_miss consecutive rows without an accepted cluster, or the
+      last row, end the extension. Inward extension: the same from the
+      outermost cluster down (the filters restart there and take the chain
+      in descending rows).
+   3. Selection: a track's length is its chain plus both extensions; each
+      cluster goes to the longest track containing it (ties: smaller seed
+      input index); a track keeping fewer than min_track_hits clusters is
+      dropped and its clusters are left unassigned. The kept tracks, in
+      ascending seed input index, list their kept clusters in ascending
+      rows. */
+
+typedef struct {
+    float win_y, win_t;  /* search box half widths around the prediction (cm) */
+    float chi2_max;      /* gate */
+    float q_slope;       /* slope variance added per cm of |dx| */
+    float var_y, var_t;  /* measurement variances (cm^2) */
+    float var_slope0;    /* initial slope variance */
+    int32_t max_miss;    /* consecutive rows without a cluster that end an extension */
+} ora_follow_cfg;
+
+typedef struct { float a, b, p00, p01, p11; } ora_kf1;
+
+static void ora_kf1_init(ora_kf1 *f, float m, float var, float var_slope0) {
+    f->a = m; f->b = 0.0f; f->p00 = var; f->p01 = 0.0f; f->p11 = var_slope0;
+}
+
+static void ora_kf1_predict(ora_kf1 *f, float dx, float q) {
+    float bdx = f->b * dx;
+    f->a = f->a + bdx;
+    float dp11 = dx * f->p11;
+    float u = f->p01 + dp11;
+    float dp01 = dx * f->p01;
+    float s = f->p00 + dp01;
+    float du = dx * u;
+    f->p00 = s + du;
+    f->p01 = u;
+    float qa = q * fabsf(dx);
+    f->p11 = f->p11 + qa;
+}
+
+static void ora_kf1_update(ora_kf1 *f, float m, float s2) {
+    float S = f->p00 + s2;
+    float k0 = f->p00 / S;
+    float k1 = f->p01 / S;
+    float r = m - f->a;
+    float k0r = k0 * r, k1r = k1 * r;
+    f->a = f->a + k0r;
+    f->b = f->b + k1r;
+    float k0p00 = k0 * f->p00, k0p01 = k0 * f->p01, k1p01 = k1 * f->p01;
+    float n00 = f->p00 - k0p00;
+    float n01 = f->p01 - k0p01;
+    float n11 = f->p11 - k1p01;
+    f->p00 = n00; f->p01 = n01; f->p11 = n11;
+}
+
+/* The filter of step 1 over n points (x[i], m[i]) taken in the given
+   order, started at the first point; writes (a, b, p00, p01, p11). Exposed
+   so that the filter can be checked on its own. */
+void ora_kf1_run(int32_t n, const float *x, const float *m, float var, float var_slope0, float q,
+                 float *out5) {
+    ora_kf1 f;
+    ora_kf1_init(&f, m[0], var, var_slope0);
+    for (int32_t i = 1; i < n; i++) {
+        ora_kf1_predict(&f, x[i] - x[i - 1], q);
+        ora_kf1_update(&f, m[i], var);
+    }
+    out5[0] = f.a; out5[1] = f.b; out5[2] = f.p00; out5[3] = f.p01; out5[4] = f.p11;
+}
+
+/* One extension (dir = +1 outward, -1 inward) from row r_end, the filters
+   already at x[r_end]; appends accepted clusters to ext (rows in the order
+   visited), returns their count. */
+static int32_t ora_extend(const ora_cfg *cfg, const ora_follow_cfg *fc, const ora_rows *R, const float *y,
+                          const float *t, int r_end, int dir, ora_kf1 *fy, ora_kf1 *ft, int32_t *ext,
+                          int32_t **list, int32_t *cap) {
+    int32_t n = 0, miss = 0;
+    float xp = cfg->row_x[r_end];
+    for (int r = r_end + dir; r >= 0 && r < cfg->n_rows; r += dir) {
+        float xr = cfg->row_x[r];
+        float dx = xr - xp;
+        ora_kf1_predict(fy, dx, fc->q_slope);
+        ora_kf1_predict(ft, dx, fc->q_slope);
+        xp = xr;
+        float vy = fy->p00 + fc->var_y, vt = ft->p00 + fc->var_t;
+        int32_t nb = ora_box(R, y, t, r, fy->a, ft->a, fc->win_y, fc->win_t, 0, list, cap);
+        int32_t best = -1;
+        float bchi = 0.0f;
+        for (int32_t k = 0; k < nb; k++) {
+            int32_t c = (*list)[k];
+            float dy = y[c] - fy->a, dt = t[c] - ft->a;
+            float ey = dy * dy, et = dt * dt;
+            float chi = ey / vy + et / vt;
+            if (best < 0 || chi < bchi || (chi == bchi && c < best)) { best = c; bchi = chi; }
+        }
+        if (best >= 0 && bchi <= fc->chi2_max) {
+            ora_kf1_update(fy, y[best], fc->var_y);
+            ora_kf1_update(ft, t[best], fc->var_t);
+            ext[n++] = best;
+            miss = 0;
+        } else if (++miss >= fc->max_miss) {
+            break;
+        }
+    }
+    return n;
+}
+
+/* Following and selection of the tracks (first, len, clusters) of one
+   sector. Writes the kept tracks (out_first, out_len, out_clusters; same
+   capacities as the inputs: at most n_tracks tracks and n clusters) and the
+   assignment, and per input track the extension counts (ext_in, ext_out)
+   and whether it was kept (kept: kept clusters, or -1 when dropped).
+   Returns the number of kept tracks. */
+int64_t ora_follow(const ora_cfg *cfg, const ora_follow_cfg *fc, int64_t n, const uint8_t *row, const float *y,
+                   const float *t, int64_t n_tracks, const int64_t *first, const int32_t *len,
+                   const int32_t *clusters, int64_t *out_first, int32_t *out_len, int32_t *out_clusters,
+                   int32_t *assign, int32_t *ext_in, int32_t *ext_out, int32_t *kept) {
+    ora_rows R;
+    ora_rows_build(cfg, n, row, t, &R);
+    int32_t *list = NULL, cap = 0;
+    int32_t nr = cfg->n_rows;
+    /* per track: inward extension (rows descending) and outward (ascending) */
+    int64_t *eoff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_tracks + 1));
+    int32_t *ebuf = NULL;
+    int64_t ecap = 0, etot = 0;
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nr > 0 ? nr : 1));
+    for (int64_t k = 0; k < n_tracks; k++) {
+        const int32_t *c = clusters + first[k];
+        int32_t L = len[k];
+        eoff[k] = etot;
+        if (etot + 2 * nr > ecap) {
+            ecap = ecap ? 2 * ecap + 2 * nr : 4 * nr + 1024;
+            ebuf = (int32_t *)realloc(ebuf, sizeof(int32_t) * (size_t)ecap);
+        }
+        ora_kf1 fy, ft;
+        /* inward: start at the outermost cluster, chain in descending rows */
+        ora_kf1_init(&fy, y[c[L - 1]], fc->var_y, fc->var_slope0);
+        ora_kf1_init(&ft, t[c[L - 1]], fc->var_t, fc->var_slope0);
+        for (int32_t j = L - 2; j >= 0; j--) {
+            float dx = cfg->row_x[row[c[j]]] - cfg->row_x[row[c[j + 1]]];
+            ora_kf1_predict(&fy, dx, fc->q_slope);
+            ora_kf1_predict(&ft, dx, fc->q_slope);
+            ora_kf1_update(&fy, y[c[j]], fc->var_y);
+            ora_kf1_update(&ft, t[c[j]], fc->var_t);
+        }
+        ext_in[k] = ora_extend(cfg, fc, &R, y, t, row[c[0]], -1, &fy, &ft, ebuf + etot, &list, &cap);
+        etot += ext_in[k];
+        /* outward: start at the innermost cluster, chain in ascending rows */
+        ora_kf1_init(&fy, y[c[0]], fc->var_y, fc->var_slope0);
+        ora_kf1_init(&ft, t[c[0]], fc->var_t, fc->var_slope0);
+        for (int32_t j = 1; j < L; j++) {
+            float dx = cfg->row_x[row[c[j]]] - cfg->row_x[row[c[j - 1]]];
+            ora_kf1_predict(&fy, dx, fc->q_slope);
+            ora_kf1_predict(&ft, dx, fc->q_slope);
+            ora_kf1_update(&fy, y[c[j]], fc->var_y);
+            ora_kf1_update(&ft, t[c[j]], fc->var_t);
+        }
+        ext_out[k] = ora_extend(cfg, fc, &R, y, t, row[c[L - 1]], 1, &fy, &ft, ebuf + etot, &list, &cap);
+        etot += ext_out[k];
+    }
+    eoff[n_tracks] = etot;
+    /* claims: (length desc, seed input index asc) */
+    int32_t *bT = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int32_t *bS = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    for (int64_t i = 0; i < n; i++) { bT[i] = -1; bS[i] = INT32_MAX; }
+#define ORA_CLAIM(cl, T_, S_)                                                   \
+    do {                                                                       \
+        int32_t cc_ = (cl);                                                    \
+        if ((T_) > bT[cc_] || ((T_) == bT[cc_] && (S_) < bS[cc_])) {           \
+            bT[cc_] = (T_); bS[cc_] = (S_);                                    \
+        }                                                                      \
+    } while (0)
+    for (int64_t k = 0; k < n_tracks; k++) {
+        const int32_t *c = clusters + first[k];
+        int32_t T = len[k] + ext_in[k] + ext_out[k], S = c[0];
+        for (int32_t j = 0; j < len[k]; j++) ORA_CLAIM(c[j], T, S);
+        for (int64_t e = eoff[k]; e < eoff[k + 1]; e++) ORA_CLAIM(ebuf[e], T, S);
+    }
+#undef ORA_CLAIM
+    for (int64_t i = 0; i < n; i++) assign[i] = -1;
+    int64_t nt = 0, nc = 0;
+    for (int64_t k = 0; k < n_tracks; k++) {
+        const int32_t *c = clusters + first[k];
+        int32_t T = len[k] + ext_in[k] + ext_out[k], S = c[0];
+        /* the extended track in ascending rows: inward reversed, chain, outward */
+        int32_t m = 0;
+        for (int32_t e = ext_in[k] - 1; e >= 0; e--) tmp[m++] = ebuf[eoff[k] + e];
+        for (int32_t j = 0; j < len[k]; j++) tmp[m++] = c[j];
+        for (int32_t e = 0; e < ext_out[k]; e++) tmp[m++] = ebuf[eoff[k] + ext_in[k] + e];
+        int32_t keep = 0;
+        for (int32_t j = 0; j < m; j++) keep += (bT[tmp[j]] == T && bS[tmp[j]] == S);
+        if (keep < cfg->min_track_hits) { kept[k] = -1; continue; }
+        kept[k] = keep;
+        out_first[nt] = nc;
+        out_len[nt] = keep;
+        for (int32_t j = 0; j < m; j++)
+            if (bT[tmp[j]] == T && bS[tmp[j]] == S) {
+                out_clusters[nc++] = tmp[j];
+                assign[tmp[j]] = (int32_t)nt;
+            }
+        nt++;
+    }
+    free(bT); free(bS); free(tmp); free(eoff); free(ebuf); free(list);
+    ora_rows_free(&R);
+    return nt;
+}
