@@ -87,6 +87,32 @@ typedef struct {
     int32_t use_mlp;           /* 1: prune candidate triplets with the loaded network, 0 */
     float mlp_logit_threshold; /* triplets with logit below this are pruned, 0 */
     int32_t pool_per_cluster;  /* triplet-pool slots per input cluster (runs that keep the pool), 8 */
+    /* Track following (Sec. 1: the tracker derives from one that extends its
+       seeds with a Kalman filter; Sec. 2: more attached hits). With follow = 1
+       every chain is extended row by row beyond both ends by two linear 1-D
+       filters, y(x) and t(x) with state (value, slope), started at one chain
+       end with variances (follow_var_y or _t, follow_var_slope0); a prediction
+       by dx adds follow_q * |dx| to the slope variance. In each row the
+       cluster inside the box |y - y_pred| <= follow_win_y,
+       |t - t_pred| <= follow_win_t of least
+       chi2 = dy^2 / (P_yy + follow_var_y) + dt^2 / (P_tt + follow_var_t)
+       (ties: smaller input index) is taken if chi2 <= follow_chi2;
+       follow_max_miss consecutive rows without one end the extension. Each
+       cluster then goes to the longest extended track containing it (ties:
+       smaller input index of the chain's innermost cluster, the seed); tracks
+       keeping fewer than min_track_hits clusters are dropped. Kept tracks are
+       numbered in ascending seed input index, list their clusters in
+       ascending rows and are fitted; tpcca_track.seed is then the input
+       index of the chain's seed. Needs sectors of fewer than 2^24 clusters. */
+    int32_t follow;            /* 0 */
+    float follow_win_y;        /* 1.5 (cm) */
+    float follow_win_t;        /* 1.5 (cm) */
+    float follow_chi2;         /* 16 */
+    float follow_q;            /* 1e-4 (per cm) */
+    float follow_var_y;        /* 0.01 (cm^2) */
+    float follow_var_t;        /* 0.01 (cm^2) */
+    float follow_var_slope0;   /* 1 */
+    int32_t follow_max_miss;   /* 3 */
 } tpcca_config;
 
 /* One fitted track. Tracks of a sector are numbered 0..T-1 in ascending
@@ -97,7 +123,8 @@ typedef struct {
     int32_t status;            /* 0 ok; 2: propagation or initialisation failed;
                                   4: not converged within kf_passes passes */
     int64_t first;             /* offset of its clusters in the sector's cluster list */
-    int32_t seed;              /* input index of its innermost cluster */
+    int32_t seed;              /* input index of its innermost cluster (with following: of the
+                                  innermost cluster of the chain it grew from) */
     int32_t ndf;               /* 2*n_clusters - 5 */
     float x_ref;               /* x of the outermost cluster: parameters are given there */
     float y;                   /* local y (cm) */
@@ -138,6 +165,9 @@ typedef struct {
                                   [15] = 15 or more; [0]: fits that failed at the start */
     int64_t n_fit_restarts;    /* fits in which a step was halved (objective rose or the helix
                                   left the domain) */
+    int64_t n_chains;          /* runs with following: chains before the selection (n_tracks: kept) */
+    int64_t n_follow_added;    /* runs with following: clusters the extensions added, over all chains */
+    int64_t n_follow_dropped;  /* runs with following: chains dropped by the selection */
 } tpcca_stats;
 
 /* Fill *out with the defaults above. The defaults are readings of the
@@ -260,7 +290,8 @@ tpcca_status tpcca_set_graph(tpcca_ctx *ctx, int32_t on);
    efficient use of the GPU, Sec. 1).
    Launch shape of one kernel group (1 histogram, 3 row scatter, 4 row sort,
    5 neighbour links, 6 seeds, 7 chain walk and copy, 8 track slots,
-   10 cluster lists and assignment, 11 fit): blocks_per_cu persistent
+   9 selection after the track following, 10 cluster lists and assignment,
+   11 fit): blocks_per_cu persistent
    workgroups per compute unit (0: keep).
    For stage 5, param sets how many clusters a neighbour-finding tile may
    stage in LDS (256..3072, 0: keep; smaller tiles give more work items).

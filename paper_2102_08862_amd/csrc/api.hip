@@ -47,6 +47,8 @@ struct Layout {
     size_t perm, lhist, chain, chain_bytes, xslot;
     size_t pfeat, pd, pu, pc, pz, hoff, hn1, hn2;
     int64_t pool_cap = 0;
+    size_t fstage, xoff, xlen, xseed, xsi, klen;
+    int64_t ext_cap = 0;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -62,8 +64,11 @@ struct Bump {
 };
 
 const char *kStageNames[] = {"reset", "hist",  "setup",  "scatter", "rowsort", "links",
-                             "seeds", "walk",  "slots",  "clscan",  "fit"};
-constexpr int kNumStages = 11;
+                             "seeds", "walk",  "slots",  "follow",  "clscan", "fit"};
+constexpr int kNumStages = 12;
+// threads of the following kernel's grid: each owns a staging column of
+// n_rows entries
+constexpr int kFollowThreads = 1024 * 256;
 constexpr size_t kTabBlockDefault = 1 << 20;
 constexpr int kEvRing = 64;
 
@@ -207,6 +212,15 @@ tpcca_status tpcca_config_default(tpcca_config *out) {
     c.use_mlp = 0;
     c.mlp_logit_threshold = 0.0f;
     c.pool_per_cluster = 8;
+    c.follow = 0;
+    c.follow_win_y = 1.5f;
+    c.follow_win_t = 1.5f;
+    c.follow_chi2 = 16.0f;
+    c.follow_q = 1.0e-4f;
+    c.follow_var_y = 0.01f;
+    c.follow_var_t = 0.01f;
+    c.follow_var_slope0 = 1.0f;
+    c.follow_max_miss = 3;
     *out = c;
     return TPCCA_OK;
 }
@@ -225,6 +239,13 @@ tpcca_status tpcca_create(const tpcca_config *cfg, tpcca_ctx **out) {
     if (!(cfg->win_y > 0) || !(cfg->win_t > 0) || !(cfg->pair_c2 >= 0) || !(cfg->sigma_y > 0) ||
         !(cfg->sigma_t > 0) || !(cfg->prior_var_sinphi > 0) || !(cfg->prior_var_tau > 0) ||
         !(cfg->prior_var_qpt > 0) || !(cfg->s_max > 0 && cfg->s_max < 1) || !std::isfinite(cfg->bz_tesla))
+        return TPCCA_ERR_INVALID_ARG;
+    if (cfg->follow < 0 || cfg->follow > 1 || !(cfg->follow_win_y > 0) || !(cfg->follow_win_t > 0) ||
+        !(cfg->follow_chi2 >= 0) || !(cfg->follow_q >= 0) || !(cfg->follow_var_y > 0) ||
+        !(cfg->follow_var_t > 0) || !(cfg->follow_var_slope0 > 0) || !std::isfinite(cfg->follow_win_y) ||
+        !std::isfinite(cfg->follow_win_t) || !std::isfinite(cfg->follow_chi2) || !std::isfinite(cfg->follow_q) ||
+        !std::isfinite(cfg->follow_var_y) || !std::isfinite(cfg->follow_var_t) ||
+        !std::isfinite(cfg->follow_var_slope0) || cfg->follow_max_miss < 1 || cfg->follow_max_miss > 255)
         return TPCCA_ERR_INVALID_ARG;
     for (int r = 0; r < cfg->n_rows; r++) {
         if (!std::isfinite(cfg->row_x[r])) return TPCCA_ERR_INVALID_ARG;
@@ -354,7 +375,7 @@ tpcca_status tpcca_set_graph(tpcca_ctx *c, int32_t on) {
 
 tpcca_status tpcca_set_launch(tpcca_ctx *c, int32_t stage, int32_t blocks_per_cu, int32_t param) {
     if (!c) return TPCCA_ERR_INVALID_ARG;
-    static const int tunable[] = {1, 3, 4, 5, 6, 7, 8, 10, 11};
+    static const int tunable[] = {1, 3, 4, 5, 6, 7, 8, 9, 10, 11};
     bool ok = false;
     for (int v : tunable) ok = ok || v == stage;
     if (!ok || blocks_per_cu < 0 || blocks_per_cu > 64) return fail(c, TPCCA_ERR_INVALID_ARG, "bad stage or blocks");
@@ -594,6 +615,22 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     L.hoff = b.take(c->pool_run ? sizeof(int32_t) * N : 0);
     L.hn1 = b.take(c->pool_run ? sizeof(int32_t) * N : 0);
     L.hn2 = b.take(c->pool_run ? sizeof(int32_t) * N : 0);
+    // track following: the staging columns and the per-chain figures; the
+    // extended tracks take the slot after the chain copies (dead between the
+    // walk and the lists) and the claims the assignment (written afterwards)
+    const bool fol = c->cfg.follow != 0;
+    if (fol) {
+        for (int si = 0; si < S; si++)
+            if (c->si_host[si].n >= (1 << 24))
+                return fail(c, TPCCA_ERR_INVALID_ARG, "track following needs sectors of fewer than 2^24 clusters");
+    }
+    L.fstage = b.take(fol ? sizeof(int32_t) * (size_t)R * kFollowThreads : 0);
+    L.xoff = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
+    L.xlen = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
+    L.xseed = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
+    L.xsi = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
+    L.klen = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
+    L.ext_cap = fol ? std::min<int64_t>((int64_t)(slot_bytes / sizeof(int32_t)), INT32_MAX - 1024) : 0;
     const int64_t nblk = (std::max<int64_t>(std::max<int64_t>(W, trk_cap), NW) + kScanItems - 1) / kScanItems + 2;
     L.scan_tmp = b.take(sizeof(int32_t) * nblk);
     L.total = align_up(b.off, 256);
@@ -636,6 +673,17 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     a.var_tau = c->cfg.prior_var_tau;
     a.var_k = c->cfg.prior_var_qpt;
     a.s_max = c->cfg.s_max;
+    a.follow = fol ? 1 : 0;
+    a.f_win_y = c->cfg.follow_win_y;
+    a.f_win_t = c->cfg.follow_win_t;
+    a.f_chi2 = c->cfg.follow_chi2;
+    a.f_q = c->cfg.follow_q;
+    a.f_var_y = c->cfg.follow_var_y;
+    a.f_var_t = c->cfg.follow_var_t;
+    a.f_var_s0 = c->cfg.follow_var_slope0;
+    a.f_max_miss = c->cfg.follow_max_miss;
+    a.f_threads = kFollowThreads;
+    a.ext_cap = L.ext_cap;
     a.theta = c->cfg.mlp_logit_threshold;
     {
         volatile float c2 = c->cfg.pair_c2;
@@ -702,6 +750,13 @@ static void bind_pointers(tpcca_ctx *c) {
     a.hoff = (int32_t *)(A + L.hoff);
     a.hn1 = (int32_t *)(A + L.hn1);
     a.hn2 = (int32_t *)(A + L.hn2);
+    a.fstage = (int32_t *)(A + L.fstage);
+    a.ext = (int32_t *)(A + L.xslot);
+    a.xoff = (int32_t *)(A + L.xoff);
+    a.xlen = (int32_t *)(A + L.xlen);
+    a.xseed = (int32_t *)(A + L.xseed);
+    a.xsi = (int32_t *)(A + L.xsi);
+    a.klen = (int32_t *)(A + L.klen);
     a.use_mlp = (c->cfg.use_mlp && c->mlp_loaded) ? 1 : 0;
     a.keep_pool = (a.use_mlp && c->pool_run) ? 1 : 0;
     if (c->mlp) {
@@ -756,6 +811,16 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     launch_scan_popc(a.bits, a.n_words, a.wpre, &cnt->n_tracks, a.scan_tmp, s);
     launch_track_slots(a, c->lc[8], s);
     launch_si_tracks(a, s);
+    mark(st++);
+    if (a.follow) {
+        // claims go into the assignment (rebuilt whole by the lists)
+        launch_fill_i32(a.assign, a.n_in, 0, s);
+        launch_follow(a, c->lc[9], s);
+        // keep flags (in trk_len by chain track number) -> new track numbers
+        launch_scan_i32_dev(a.trk_len, &cnt->n_chains, a.trk_cap, a.cl_off, &cnt->n_tracks, a.scan_tmp, s);
+        launch_follow_slots(a, s);
+        launch_follow_copy(a, c->lc[9], s);
+    }
     mark(st++);
     launch_scan_i32_dev(a.trk_len, &cnt->n_tracks, a.trk_cap, a.cl_off, &cnt->n_cl, a.scan_tmp, s);
     launch_si_clusters(a, s);
@@ -950,6 +1015,15 @@ extern "C" {
 tpcca_status tpcca_synchronize(tpcca_ctx *c) {
     if (!c) return TPCCA_ERR_INVALID_ARG;
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->have_results && c->arena) {
+        int32_t ovf = 0;
+        HIPCHK(c, hipMemcpy(&ovf, c->arena + c->lay.cnt + offsetof(Counters, overflow), sizeof(ovf),
+                            hipMemcpyDeviceToHost));
+        if (ovf > 0) {
+            c->have_results = false;
+            return fail(c, TPCCA_ERR_CAPACITY, "track buffers overflowed (extended tracks of the following)");
+        }
+    }
     if (c->have_results && c->args.use_mlp && c->arena) {
         int32_t ovf = 0;
         HIPCHK(c, hipMemcpy(&ovf, c->arena + c->lay.cnt + offsetof(Counters, pool_overflow), sizeof(ovf),
@@ -992,6 +1066,11 @@ tpcca_status tpcca_get_stats(tpcca_ctx *c, tpcca_stats *out) {
     out->mlp_used = c->args.use_mlp;
     for (int i = 0; i < 16 && i < kPassBins; i++) out->fit_passes[i] = k.fit_passes[i];
     out->n_fit_restarts = k.fit_passes[kPassBins];
+    if (c->args.follow) {
+        out->n_chains = k.n_chains;
+        out->n_follow_added = k.f_added;
+        out->n_follow_dropped = k.f_dropped;
+    }
     out->n_stages = 0;
     if (c->timing && c->events_ok) {
         for (int r = 0; r < kEvRing; r++) fold_slot(c, (c->ev_next + r) % kEvRing);

@@ -270,7 +270,7 @@ __device__ inline void fit_emit(const KArgs &a, const float *sx, int g, int L, c
     o.sector = a.si[si].sector;
     o.n_clusters = L;
     o.first = (int64_t)(a.cl_off[g] - a.st[si].cl_base);
-    o.seed = e0.id;
+    o.seed = a.follow ? a.trk_seed[g] : e0.id;   // with following: the chain's seed
     o.ndf = 2 * L - 5;
     const float XL = sx[cL.sr & 255] - xc;
     o.x_ref = sx[cL.sr & 255];

@@ -117,7 +117,12 @@ struct Counters {
     int32_t n_pruned;        // triplets below the logit threshold
     int32_t fit_passes[kPassBins + 1];  // tracks by fit passes taken; [kPassBins]: fits with halved steps
     int32_t chain_next;      // chain copy entries handed out by the walk
-    int32_t pad[1];
+    // track following (runs with following only)
+    int32_t n_chains;        // chain tracks before the selection
+    int32_t ext_next;        // extended-track entries handed out
+    int32_t f_added;         // clusters added by the extensions (all chains)
+    int32_t f_dropped;       // chain tracks dropped by the selection
+    int32_t f_chain_next;    // chain copy entries of the kept tracks handed out
 };
 static_assert(sizeof(Counters) % 8 == 0 && offsetof(Counters, n_samples) == 0, "64-bit counter first");
 
@@ -171,6 +176,15 @@ struct KArgs {
     float sigma_y2, sigma_t2;
     float var_s, var_tau, var_k;
     float s_max;
+    // track following
+    int32_t follow;          // 1: extend the chains and resolve shared clusters before the fit
+    float f_win_y, f_win_t;  // search box half widths around the prediction
+    float f_chi2;            // gate
+    float f_q;               // slope variance added per cm of |dx|
+    float f_var_y, f_var_t;  // measurement variances
+    float f_var_s0;          // initial slope variance
+    int32_t f_max_miss;      // consecutive rows without a cluster that end an extension
+    int32_t f_threads;       // threads of the k_follow grid (staging columns)
     // tables
     const float *row_x;      // [n_rows]
     const float *w_tab;      // [n_rows * kMaxGap], (x_r - x_{r-g}) / (x_{r+g} - x_{r-g})
@@ -216,6 +230,13 @@ struct KArgs {
     int2 *asg_pairs;         // [buckets * 16384] (input index, track number), in the dead staging buffer
     int32_t *asg_cnt;        // [buckets] pairs per bucket of 16384 input indices
     int32_t *scan_tmp;       // block sums of the scans
+    // track following (per track seed k of the walk)
+    int32_t *fstage;         // [n_rows * f_threads] staging columns of the extensions
+    int32_t *ext;            // [ext_cap] extended tracks: job input indices in ascending rows
+    int64_t ext_cap;
+    int32_t *xoff, *xlen;    // [tseed_cap] offset and length of the extended track
+    int32_t *xseed, *xsi;    // [tseed_cap] seed input index (sector-local) and sector instance
+    int32_t *klen;           // [tseed_cap] clusters kept (0: dropped)
     const volatile int32_t *abort_flag;  // host-mapped
     // learned pruning (pruned runs only)
     int32_t use_mlp;
@@ -289,6 +310,9 @@ void launch_walk(const KArgs &a, Launch l, hipStream_t s);
 void launch_track_slots(const KArgs &a, Launch l, hipStream_t s);
 void launch_lists(const KArgs &a, Launch l, hipStream_t s);
 void launch_len_sort(const KArgs &a, Launch l, hipStream_t s);
+void launch_follow(const KArgs &a, Launch l, hipStream_t s);
+void launch_follow_slots(const KArgs &a, hipStream_t s);
+void launch_follow_copy(const KArgs &a, Launch l, hipStream_t s);
 void launch_fit(const KArgs &a, Launch l, hipStream_t s);
 // exclusive scans: out[i] = sum_{j<i} f(in[j]), out[n] = total, *total_dst = total
 void launch_scan_popc(const uint32_t *in, int32_t n, int32_t *out, int32_t *total_dst, int32_t *tmp,

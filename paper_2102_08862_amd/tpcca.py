@@ -45,6 +45,12 @@ class Config(ctypes.Structure):
         ("use_mlp", ctypes.c_int32),
         ("mlp_logit_threshold", ctypes.c_float),
         ("pool_per_cluster", ctypes.c_int32),
+        ("follow", ctypes.c_int32),
+        ("follow_win_y", ctypes.c_float), ("follow_win_t", ctypes.c_float),
+        ("follow_chi2", ctypes.c_float), ("follow_q", ctypes.c_float),
+        ("follow_var_y", ctypes.c_float), ("follow_var_t", ctypes.c_float),
+        ("follow_var_slope0", ctypes.c_float),
+        ("follow_max_miss", ctypes.c_int32),
     ]
 
 
@@ -69,6 +75,7 @@ class Stats(ctypes.Structure):
         ("stage_ms_total", ctypes.c_double * 16),
         ("stage_name", (ctypes.c_char * 24) * 16),
         ("n_tiles", ctypes.c_int64), ("fit_passes", ctypes.c_int64 * 16), ("n_fit_restarts", ctypes.c_int64),
+        ("n_chains", ctypes.c_int64), ("n_follow_added", ctypes.c_int64), ("n_follow_dropped", ctypes.c_int64),
     ]
 
 
@@ -359,7 +366,8 @@ class Tracker:
         self._check(self.lib.tpcca_get_stats(self.h, ctypes.byref(s)))
         d = {k: getattr(s, k) for k in ("n_clusters", "n_links", "n_seeds", "n_tracks", "n_track_clusters",
                                         "n_invalid", "n_overflow_tiles", "n_triplets", "n_pruned",
-                                        "n_pool_overflow", "mlp_used", "n_tiles")}
+                                        "n_pool_overflow", "mlp_used", "n_tiles", "n_chains", "n_follow_added",
+                                        "n_follow_dropped")}
         d["stage_ms"] = {s.stage_name[i].value.decode(): s.stage_ms[i] for i in range(s.n_stages)}
         d["fit_passes"] = [int(v) for v in s.fit_passes]
         d["n_fit_restarts"] = int(s.n_fit_restarts)
