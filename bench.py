@@ -242,10 +242,13 @@ def sector_parity(g, ref):
     return exact, worst, excluded
 
 
-def cpu_baseline(fr, gpu_out, n_workers: int):
+def cpu_baseline(fr, gpu_out, n_workers: int, follow_gpu=None):
     """The CPU oracle (whole path: links, cleaning, chains, MAP fit), timed on
     one sector with one thread and on n_workers sectors with one thread per
-    sector; every sector it computes is compared with the GPU's outputs."""
+    sector; every sector it computes is compared with the GPU's outputs. With
+    follow_gpu (the following tracker's outputs of the first sampled sector),
+    the oracle's path with following is timed on that sector (one thread) and
+    compared with them."""
     import oracle
     from paper_2102_08862_amd import synth
     x, _ = synth.geometry()
@@ -273,7 +276,20 @@ def cpu_baseline(fr, gpu_out, n_workers: int):
         if s in gpu_out:
             e, w, x_ = sector_parity(gpu_out[s], refs[s])
             exact, worst, excl = exact and e, max(worst, w), excl + x_
-    return {"value": nn / dtn, "unit": "clusters/s", "cores": len(secs), "kind": "oracle",
+    fol = None
+    if follow_gpu is not None:
+        row, y, t = fr.sector(s0)
+        t0 = time.perf_counter()
+        ref = oracle.run_sector(cfg, row, y, t, follow_cfg=oracle.FollowConfig())
+        dtf = time.perf_counter() - t0
+        g = follow_gpu
+        ex = (np.array_equal(g["assign"], ref["assign"]) and np.array_equal(g["clusters"], ref["clusters"])
+              and len(g["tracks"]) == len(ref["first"]) and np.array_equal(g["tracks"]["first"], ref["first"]))
+        fol = {"value_1thread": n1 / dtf, "unit": "clusters/s",
+               "sample": "sector %d (%d clusters), links + cleaning + chains + following + MAP fit, one thread, %.1f s"
+                         % (s0, n1, dtf),
+               "parity": {"assignment_lists_bit_exact": bool(ex)}}
+    return {"value": nn / dtn, "unit": "clusters/s", "cores": len(secs), "kind": "oracle", "follow": fol,
             "value_1thread": n1 / dt1, "host_cores": host_cores(), "cpu_model": cpu_model(),
             "sample": "sectors %s of the same frame (%d clusters), links + cleaning + chains + MAP fit, one thread "
                       "per sector, %.1f s; 1-thread figure: sector %d (%d clusters, %.1f s)"
@@ -299,7 +315,7 @@ def frame_quality(trk, fr, f):
     return metrics.frame_quality(fr, lambda s: trk.track_clusters(f, s), lambda s: trk.tracks(f, s)["n_clusters"])
 
 
-def pruned_leg(trk, fr, f, args, log):
+def pruned_leg(trk, fr, f, args, log, q_plain):
     """The MLP-pruned tracker on the same frame, at the trained network's
     threshold, timed like the plain one; with the efficiency of both against
     the generator's truth."""
@@ -309,7 +325,6 @@ def pruned_leg(trk, fr, f, args, log):
     if params is None or "theta" not in meta:
         log("pruned leg skipped: no trained weights")
         return {"skipped": "no trained weights"}
-    q_plain = None if args.no_quality else frame_quality(trk, fr, f)
     theta = float(meta["theta"])
     trk.set_graph(False)
     trk.mlp_load(params)
@@ -350,6 +365,55 @@ def pruned_leg(trk, fr, f, args, log):
     return out
 
 
+def follow_leg(fr, args, log, q_plain, tuning_on, sector):
+    """The tracker with track following (chain extension and shared-cluster
+    selection before the fit) on the same frame, timed like the plain one;
+    with its quality against the generator's truth beside the plain
+    tracker's, and one sector's outputs for the oracle comparison."""
+    import torch
+    from paper_2102_08862_amd import autotune, tpcca
+    trk = tpcca.Tracker(follow=1)
+    f = trk.load_frame_packed(fr)
+    need = trk.ensure_arena()
+    if tuning_on:
+        autotune.apply(trk, fr.n_clusters)
+        need = trk.ensure_arena()
+    for _ in range(max(1, args.warmup)):
+        trk.run()
+    trk.synchronize()
+    trk.set_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(trk.stream)
+    for _ in range(args.steps):
+        trk.run()
+    e1.record(trk.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = trk.stats()
+    runs = max(1, st["n_timed_runs"])
+    out = {"value": round(fr.n_clusters / (ms / 1e3), 1), "unit": "clusters/s", "ms_per_step": round(ms, 4),
+           "chains": int(st["n_chains"]), "tracks": int(st["n_tracks"]),
+           "track_clusters": int(st["n_track_clusters"]), "clusters_added": int(st["n_follow_added"]),
+           "chains_dropped": int(st["n_follow_dropped"]), "arena_GB": round(need / 1e9, 3),
+           "stage_ms": {k: round(v / runs, 4) for k, v in st["stage_ms_total"].items()}}
+    log("follow: %.3f ms/step (follow stage %.3f ms), %d chains -> %d tracks, %d clusters added"
+        % (ms, out["stage_ms"].get("follow", 0.0), out["chains"], out["tracks"], out["clusters_added"]))
+    if q_plain is not None:
+        q = frame_quality(trk, fr, f)
+        out["quality"] = {k: {"plain": round(q_plain[k], 6), "follow": round(q[k], 6)}
+                          for k in ("efficiency", "fake_rate", "clone_rate", "hit_efficiency")}
+        log("quality plain -> follow: %s" % out["quality"])
+    g = None
+    if sector is not None:
+        g = dict(assign=trk.assignment(f, sector), clusters=trk.track_clusters(f, sector),
+                 tracks=trk.tracks(f, sector))
+    del trk
+    torch.cuda.empty_cache()
+    return out, g
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,6 +429,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay each step from a captured HIP graph")
     ap.add_argument("--no-pruned", action="store_true", help="skip the MLP-pruned tracker leg")
     ap.add_argument("--no-quality", action="store_true", help="skip the truth-based efficiency of both trackers")
+    ap.add_argument("--no-follow", action="store_true", help="skip the track-following tracker leg")
     # the full 64-frame batch stalled in its second sub-batch on the GPU (cause
     # not found; see the design notes): the default runs the first 16 frames
     ap.add_argument("--batch-frames", type=int, default=16, help="batch64: use only the first N frames")
@@ -483,14 +548,19 @@ def main():
     ncpu = min(host_cores(), CPU_SHARE) if args.cpu_sectors < 0 else min(args.cpu_sectors, 36)
     gpu_out = gpu_sector_outputs(trk, f, sample_sectors(len(fr.rows), max(1, ncpu))) if ncpu > 0 else {}
 
+    q_plain = None if args.no_quality else frame_quality(trk, fr, f)
     pruned = None
     if not args.no_pruned:
-        pruned = pruned_leg(trk, fr, f, args, log)
+        pruned = pruned_leg(trk, fr, f, args, log, q_plain)
+    follow, follow_gpu = None, None
+    if not args.no_follow:
+        follow, follow_gpu = follow_leg(fr, args, log, q_plain, not args.no_tuning,
+                                        sample_sectors(len(fr.rows), 1)[0] if ncpu > 0 else None)
 
     cpu = None
     if ncpu > 0:
         log("cpu baseline: oracle on 1 sector (1 thread), then %d sectors (%d threads) ..." % (ncpu, ncpu))
-        cpu = cpu_baseline(fr, gpu_out, ncpu)
+        cpu = cpu_baseline(fr, gpu_out, ncpu, follow_gpu)
         log("cpu baseline: %.3g clusters/s (%d threads), %.3g clusters/s (1 thread); parity %s"
             % (cpu["value"], cpu["cores"], cpu["value_1thread"], cpu["parity"]))
 
@@ -512,6 +582,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roof,
         "pruned": pruned,
+        "follow": follow,
         "cpu_baseline": cpu,
         "counts": {k: int(st[k]) for k in ("n_links", "n_seeds", "n_tracks", "n_track_clusters", "n_invalid",
                                             "n_overflow_tiles", "n_tiles")},

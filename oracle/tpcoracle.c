@@ -743,14 +743,14 @@ int32_t ora_sizeof_cfg(void) { return (int32_t)sizeof(ora_cfg); }
         a = a + b*dx;  u = p01 + dx*p11;  p00 = (p00 + dx*p01) + dx*u;
         p01 = u;  p11 = p11 + q_slope*|dx|
       an update with measurement m of variance s2:
-        S = p00 + s2;  k0 = p00/S;  k1 = p01/S;  r = m - a;
+        S = p00 + s2;  iS = 1/S;  k0 = p00*iS;  k1 = p01*iS;  r = m - a;
         a = a + k0*r;  b = b + k1*r;
         p00 = p00 - k0*p00;  p01 = p01 - k0*p01;  p11 = p11 - k1*p01(old)
       (every operation one FP32 rounding, in this order).
    2. Outward extension: row by row beyond the last cluster, predict both
       filters to the row; among the row's clusters with |y - y_p| <= win_y
       and |t - t_p| <= win_t take the one with the smallest
-      chi2 = (dy*dy)/(p00y + var_y) + (dt*dt)/(p00t + var_t), ties to the
+      chi2 = (dy*dy)*(1/(p00y + var_y)) + (dt*dt)*(1/(p00t + var_t)), ties to the
       smaller input index; accept it if chi2 <= chi2_max and update both
       filters. max_miss consecutive rows without an accepted cluster, or the
       last row, end the extension. Inward extension: the same from the
@@ -794,8 +794,9 @@ static void ora_kf1_predict(ora_kf1 *f, float dx, float q) {
 
 static void ora_kf1_update(ora_kf1 *f, float m, float s2) {
     float S = f->p00 + s2;
-    float k0 = f->p00 / S;
-    float k1 = f->p01 / S;
+    float iS = 1.0f / S;
+    float k0 = f->p00 * iS;
+    float k1 = f->p01 * iS;
     float r = m - f->a;
     float k0r = k0 * r, k1r = k1 * r;
     f->a = f->a + k0r;
@@ -836,6 +837,7 @@ static int32_t ora_extend(const ora_cfg *cfg, const ora_follow_cfg *fc, const or
         ora_kf1_predict(ft, dx, fc->q_slope);
         xp = xr;
         float vy = fy->p00 + fc->var_y, vt = ft->p00 + fc->var_t;
+        float ivy = 1.0f / vy, ivt = 1.0f / vt;
         int32_t nb = ora_box(R, y, t, r, fy->a, ft->a, fc->win_y, fc->win_t, 0, list, cap);
         int32_t best = -1;
         float bchi = 0.0f;
@@ -843,7 +845,7 @@ static int32_t ora_extend(const ora_cfg *cfg, const ora_follow_cfg *fc, const or
             int32_t c = (*list)[k];
             float dy = y[c] - fy->a, dt = t[c] - ft->a;
             float ey = dy * dy, et = dt * dt;
-            float chi = ey / vy + et / vt;
+            float chi = ey * ivy + et * ivt;
             if (best < 0 || chi < bchi || (chi == bchi && c < best)) { best = c; bchi = chi; }
         }
         if (best >= 0 && bchi <= fc->chi2_max) {

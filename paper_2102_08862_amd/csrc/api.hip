@@ -47,7 +47,8 @@ struct Layout {
     size_t perm, lhist, chain, chain_bytes, xslot;
     size_t pfeat, pd, pu, pc, pz, hoff, hn1, hn2;
     int64_t pool_cap = 0;
-    size_t fstage, xoff, xlen, xseed, xsi, klen;
+    size_t xoff, xlen, xseed, xsi, klen, kchoff, ford, fhist;
+    int64_t n_fbins = 0;
     int64_t ext_cap = 0;
 };
 
@@ -66,9 +67,6 @@ struct Bump {
 const char *kStageNames[] = {"reset", "hist",  "setup",  "scatter", "rowsort", "links",
                              "seeds", "walk",  "slots",  "follow",  "clscan", "fit"};
 constexpr int kNumStages = 12;
-// threads of the following kernel's grid: each owns a staging column of
-// n_rows entries
-constexpr int kFollowThreads = 1024 * 256;
 constexpr size_t kTabBlockDefault = 1 << 20;
 constexpr int kEvRing = 64;
 
@@ -615,23 +613,29 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     L.hoff = b.take(c->pool_run ? sizeof(int32_t) * N : 0);
     L.hn1 = b.take(c->pool_run ? sizeof(int32_t) * N : 0);
     L.hn2 = b.take(c->pool_run ? sizeof(int32_t) * N : 0);
-    // track following: the staging columns and the per-chain figures; the
-    // extended tracks take the slot after the chain copies (dead between the
-    // walk and the lists) and the claims the assignment (written afterwards)
+    // track following: the per-chain figures; the extended tracks take the
+    // slot after the chain copies (dead between the walk and the lists) and
+    // the claims the assignment (written afterwards)
     const bool fol = c->cfg.follow != 0;
     if (fol) {
         for (int si = 0; si < S; si++)
             if (c->si_host[si].n >= (1 << 24))
                 return fail(c, TPCCA_ERR_INVALID_ARG, "track following needs sectors of fewer than 2^24 clusters");
     }
-    L.fstage = b.take(fol ? sizeof(int32_t) * (size_t)R * kFollowThreads : 0);
-    L.xoff = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
-    L.xlen = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
+    L.xoff = b.take(fol ? sizeof(int32_t) * 2 * tseed_cap : 0);
+    L.xlen = b.take(fol ? sizeof(int32_t) * 2 * tseed_cap : 0);
     L.xseed = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
     L.xsi = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
     L.klen = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
+    L.kchoff = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
+    L.ford = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
+    L.n_fbins = fol ? (int64_t)S * (kNcbMax / 8) : 0;
+    L.fhist = b.take(fol ? sizeof(int32_t) * 2 * (L.n_fbins + 1) : 0);
     L.ext_cap = fol ? std::min<int64_t>((int64_t)(slot_bytes / sizeof(int32_t)), INT32_MAX - 1024) : 0;
-    const int64_t nblk = (std::max<int64_t>(std::max<int64_t>(W, trk_cap), NW) + kScanItems - 1) / kScanItems + 2;
+    const int64_t nblk =
+        (std::max<int64_t>(std::max<int64_t>(std::max<int64_t>(W, trk_cap), NW), L.n_fbins) + kScanItems - 1) /
+            kScanItems +
+        2;
     L.scan_tmp = b.take(sizeof(int32_t) * nblk);
     L.total = align_up(b.off, 256);
     c->n_in = N;
@@ -682,8 +686,8 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     a.f_var_t = c->cfg.follow_var_t;
     a.f_var_s0 = c->cfg.follow_var_slope0;
     a.f_max_miss = c->cfg.follow_max_miss;
-    a.f_threads = kFollowThreads;
     a.ext_cap = L.ext_cap;
+    a.n_fbins = (int32_t)L.n_fbins;
     a.theta = c->cfg.mlp_logit_threshold;
     {
         volatile float c2 = c->cfg.pair_c2;
@@ -750,13 +754,15 @@ static void bind_pointers(tpcca_ctx *c) {
     a.hoff = (int32_t *)(A + L.hoff);
     a.hn1 = (int32_t *)(A + L.hn1);
     a.hn2 = (int32_t *)(A + L.hn2);
-    a.fstage = (int32_t *)(A + L.fstage);
     a.ext = (int32_t *)(A + L.xslot);
     a.xoff = (int32_t *)(A + L.xoff);
     a.xlen = (int32_t *)(A + L.xlen);
     a.xseed = (int32_t *)(A + L.xseed);
     a.xsi = (int32_t *)(A + L.xsi);
     a.klen = (int32_t *)(A + L.klen);
+    a.kchoff = (int32_t *)(A + L.kchoff);
+    a.ford = (int32_t *)(A + L.ford);
+    a.fhist = (int32_t *)(A + L.fhist);
     a.use_mlp = (c->cfg.use_mlp && c->mlp_loaded) ? 1 : 0;
     a.keep_pool = (a.use_mlp && c->pool_run) ? 1 : 0;
     if (c->mlp) {
@@ -815,11 +821,11 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     if (a.follow) {
         // claims go into the assignment (rebuilt whole by the lists)
         launch_fill_i32(a.assign, a.n_in, 0, s);
+        launch_fill_i32(a.fhist, a.n_fbins + 1, 0, s);
         launch_follow(a, c->lc[9], s);
         // keep flags (in trk_len by chain track number) -> new track numbers
         launch_scan_i32_dev(a.trk_len, &cnt->n_chains, a.trk_cap, a.cl_off, &cnt->n_tracks, a.scan_tmp, s);
-        launch_follow_slots(a, s);
-        launch_follow_copy(a, c->lc[9], s);
+        launch_follow_slots(a, c->lc[9], s);
     }
     mark(st++);
     launch_scan_i32_dev(a.trk_len, &cnt->n_tracks, a.trk_cap, a.cl_off, &cnt->n_cl, a.scan_tmp, s);

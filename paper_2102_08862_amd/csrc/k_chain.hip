@@ -184,6 +184,7 @@ __global__ __launch_bounds__(256) void k_walk(KArgs a) {
                     const int j = j0 + b;
                     if (j < L) {
                         buf[b] = e;
+                        if (a.follow) buf[b].id = q;   // the following reads sorted positions
                         if (j + 1 < L) {
                             q = a.upc[q];
                             e = a.rec[q];

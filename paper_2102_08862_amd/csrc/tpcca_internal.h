@@ -123,6 +123,8 @@ struct Counters {
     int32_t f_added;         // clusters added by the extensions (all chains)
     int32_t f_dropped;       // chain tracks dropped by the selection
     int32_t f_chain_next;    // chain copy entries of the kept tracks handed out
+    int32_t fq[8];           // following: per-XCD heads of the ordered chain shares
+    int32_t fkq[8];          // the same for the selection
 };
 static_assert(sizeof(Counters) % 8 == 0 && offsetof(Counters, n_samples) == 0, "64-bit counter first");
 
@@ -184,7 +186,6 @@ struct KArgs {
     float f_var_y, f_var_t;  // measurement variances
     float f_var_s0;          // initial slope variance
     int32_t f_max_miss;      // consecutive rows without a cluster that end an extension
-    int32_t f_threads;       // threads of the k_follow grid (staging columns)
     // tables
     const float *row_x;      // [n_rows]
     const float *w_tab;      // [n_rows * kMaxGap], (x_r - x_{r-g}) / (x_{r+g} - x_{r-g})
@@ -224,19 +225,24 @@ struct KArgs {
     tpcca_track *trk;        // [trk_cap]
     int32_t *clusters;       // [n_in]
     Rec *chain;              // [chain_cap] chain copies {y, t, id, (si << 8) | row}, a run of a multiple
-                             // of 4 entries per track
+                             // of 4 entries per track (the walk's copies, with following on, hold the
+                             // sorted position in place of id)
     int64_t chain_cap;       // n_in + 3 * trk_cap
     int32_t *assign;         // [n_in]
     int2 *asg_pairs;         // [buckets * 16384] (input index, track number), in the dead staging buffer
     int32_t *asg_cnt;        // [buckets] pairs per bucket of 16384 input indices
     int32_t *scan_tmp;       // block sums of the scans
     // track following (per track seed k of the walk)
-    int32_t *fstage;         // [n_rows * f_threads] staging columns of the extensions
-    int32_t *ext;            // [ext_cap] extended tracks: job input indices in ascending rows
+    int32_t *ext;            // [ext_cap] extended tracks: sorted positions in ascending rows
     int64_t ext_cap;
-    int32_t *xoff, *xlen;    // [tseed_cap] offset and length of the extended track
+    int32_t *xoff, *xlen;    // [2 * tseed_cap] per extension task (2k inward + chain, 2k + 1
+                             // outward): offset and count of its entries (-1: overflow)
     int32_t *xseed, *xsi;    // [tseed_cap] seed input index (sector-local) and sector instance
     int32_t *klen;           // [tseed_cap] clusters kept (0: dropped)
+    int32_t *kchoff;         // [tseed_cap] the kept track's chain copy
+    int32_t *ford;           // [tseed_cap] chain tracks in (sector instance, seed time) order
+    int32_t *fhist;          // [2 * (n_fbins + 1)] slab counts, then their exclusive prefix
+    int32_t n_fbins;         // n_si * (kNcbMax / 8) time slabs
     const volatile int32_t *abort_flag;  // host-mapped
     // learned pruning (pruned runs only)
     int32_t use_mlp;
@@ -311,8 +317,7 @@ void launch_track_slots(const KArgs &a, Launch l, hipStream_t s);
 void launch_lists(const KArgs &a, Launch l, hipStream_t s);
 void launch_len_sort(const KArgs &a, Launch l, hipStream_t s);
 void launch_follow(const KArgs &a, Launch l, hipStream_t s);
-void launch_follow_slots(const KArgs &a, hipStream_t s);
-void launch_follow_copy(const KArgs &a, Launch l, hipStream_t s);
+void launch_follow_slots(const KArgs &a, Launch l, hipStream_t s);
 void launch_fit(const KArgs &a, Launch l, hipStream_t s);
 // exclusive scans: out[i] = sum_{j<i} f(in[j]), out[n] = total, *total_dst = total
 void launch_scan_popc(const uint32_t *in, int32_t n, int32_t *out, int32_t *total_dst, int32_t *tmp,
