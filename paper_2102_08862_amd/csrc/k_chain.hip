@@ -268,20 +268,6 @@ constexpr int kAsgBucket = 16384;          // input indices per bucket (64 KB of
 constexpr int kAsgTracks = 512;            // tracks per workgroup range
 constexpr int kAsgHist = 4096;             // buckets a range may span (else direct stores)
 
-constexpr int kListUnroll = 4;
-
-// Track of list position p within a range: the last k with m_cl[k] <= p
-// (m_cl ascending; every track has at least one cluster).
-__device__ inline int range_track(const int32_t *m_cl, int nk, int p) {
-    int lo = 0, hi = nk - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (m_cl[mid] <= p) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 __global__ __launch_bounds__(256) void k_lists(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ int32_t h[kAsgHist];
@@ -311,35 +297,22 @@ __global__ __launch_bounds__(256) void k_lists(KArgs a) {
             for (int b = threadIdx.x; b < span; b += blockDim.x) h[b] = 0;
             __syncthreads();
         }
-        // lists, and the bucket counts: one flat loop over the range's
-        // contiguous list positions, kListUnroll loads in flight per lane
+        // lists, and the bucket counts: each wave takes whole tracks of the
+        // range, its lanes the track's clusters (coalesced record loads and
+        // list stores, no search for a position's track)
         const int nk = g1 - g0;
-        const int P0 = m_cl[0], P1 = m_cl[nk - 1] + m_len[nk - 1];
-        const int bd = blockDim.x;
-        for (int p0 = P0 + threadIdx.x; p0 < P1; p0 += kListUnroll * bd) {
-            int id[kListUnroll], tk[kListUnroll];
-#pragma unroll
-            for (int u = 0; u < kListUnroll; u++) {
-                const int p = p0 + u * bd;
-                tk[u] = -1;
-                id[u] = 0;
-                if (p < P1) {
-                    const int k = range_track(m_cl, nk, p);
-                    tk[u] = k;
-                    id[u] = a.chain[m_choff[k] + (p - m_cl[k])].id;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kListUnroll; u++) {
-                const int k = tk[u];
-                if (k < 0) continue;
-                a.clusters[p0 + u * bd] = id[u];
-                const int gi = m_ib[k] + id[u];
+        const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+        for (int k = threadIdx.x >> 6; k < nk; k += nw) {
+            const int L = m_len[k], cl = m_cl[k], co = m_choff[k], ib = m_ib[k], tn = m_tn[k];
+            for (int j = lane; j < L; j += 64) {
+                const int id = a.chain[co + j].id;
+                a.clusters[cl + j] = id;
+                const int gi = ib + id;
                 if (bucketed) {
                     atomicAdd(&h[gi / kAsgBucket - blo], 1);
                 } else {
                     const int bk = gi / kAsgBucket;   // a range spanning many sectors: one grab per pair
-                    a.asg_pairs[(int64_t)bk * kAsgBucket + atomicAdd(&a.asg_cnt[bk], 1)] = make_int2(gi, m_tn[k]);
+                    a.asg_pairs[(int64_t)bk * kAsgBucket + atomicAdd(&a.asg_cnt[bk], 1)] = make_int2(gi, tn);
                 }
             }
         }
@@ -352,24 +325,11 @@ __global__ __launch_bounds__(256) void k_lists(KArgs a) {
                 h[b] = v ? (blo + b) * kAsgBucket + atomicAdd(&a.asg_cnt[blo + b], v) : 0;   // < n_in + kAsgBucket
             }
             __syncthreads();
-            for (int p0 = P0 + threadIdx.x; p0 < P1; p0 += kListUnroll * bd) {
-                int id[kListUnroll], tk[kListUnroll];
-#pragma unroll
-                for (int u = 0; u < kListUnroll; u++) {
-                    const int p = p0 + u * bd;
-                    tk[u] = -1;
-                    id[u] = 0;
-                    if (p < P1) {
-                        tk[u] = range_track(m_cl, nk, p);
-                        id[u] = a.clusters[p];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kListUnroll; u++) {
-                    const int k = tk[u];
-                    if (k < 0) continue;
-                    const int gi = m_ib[k] + id[u];
-                    a.asg_pairs[(int64_t)atomicAdd(&h[gi / kAsgBucket - blo], 1)] = make_int2(gi, m_tn[k]);
+            for (int k = threadIdx.x >> 6; k < nk; k += nw) {
+                const int L = m_len[k], cl = m_cl[k], ib = m_ib[k], tn = m_tn[k];
+                for (int j = lane; j < L; j += 64) {
+                    const int gi = ib + a.clusters[cl + j];
+                    a.asg_pairs[(int64_t)atomicAdd(&h[gi / kAsgBucket - blo], 1)] = make_int2(gi, tn);
                 }
             }
         }

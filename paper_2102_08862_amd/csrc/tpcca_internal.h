@@ -12,11 +12,11 @@ namespace tpcca {
 constexpr int kMaxRows = 255;      // rows are uint8
 constexpr int kMaxGap = 2;         // symmetric row gaps handled by the link kernel
 constexpr int kNcbMax = 4096;      // coarse time bins per sector row (upper bound)
-constexpr int kFinePerCb = 2;      // fine bins per coarse bin (row sort)
+constexpr int kFinePerCb = 4;      // fine bins per coarse bin (row sort)
 constexpr int kTileRows = 8;       // own pad rows of a neighbour-finding tile
 constexpr int kMaxTileCb = 32;     // most own coarse bins of a tile
 constexpr int kTileCap = 3072;     // clusters a tile stages in LDS (own rows, +-kMaxGap rows, time halo)
-constexpr int kPrCap = 3072;       // the same for the pruned search (its LDS also holds the pair lists)
+constexpr int kPrCap = 2944;       // the same for the pruned search (its LDS also holds the pair lists)
 constexpr int kMaxYCells = 32;     // y cells per pad row in the row order
 constexpr int kChunk = 8192;       // clusters per histogram / scatter work item
 constexpr int kScanItems = 2048;   // elements per block of the device-wide scans
