@@ -7,9 +7,9 @@ reads for that copy (bytes copied / counter value), so the figures are in
 HBM bytes. The summary records a fingerprint of the kernel sources: a figure
 is only valid for the kernels it was taken on.
 
-  W="python -m paper_2102_08862_amd.traffic run"
+  W="python -m paper_2102_08862_amd.traffic run"   (add --follow for the follower's kernels)
   rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \\
-      'k_links|k_rowsort|k_scatter|k_hist|k_lists|k_asg_fill|k_fit|k_seeds|k_walk|k_copy' \\
+      'k_links|k_rowsort|k_scatter|k_hist|k_lists|k_asg_fill|k_fit|k_seeds|k_walk|k_follow|k_ford|k_copy' \\
       -d OUT/fetch -o f --output-format csv -- $W
   rocprofv3 --pmc WRITE_SIZE (same options) -d OUT/write -o w --output-format csv -- $W
   python -m paper_2102_08862_amd.traffic summarize OUT/fetch OUT/write --out profiles/traffic_frame_10ms.txt
@@ -35,6 +35,8 @@ SOURCES = {
     "k_seeds": "k_chain.hip", "k_walk": "k_chain.hip", "k_lists": "k_chain.hip",
     "k_asg_fill": "k_chain.hip", "k_tile_list": "k_links.hip",
     "k_fit": "k_fit.hip", "k_mlp_infer": "k_mlp.hip",
+    "k_follow": "k_follow.hip", "k_follow_keep": "k_follow.hip", "k_ford_hist": "k_follow.hip",
+    "k_ford_scatter": "k_follow.hip", "k_follow_slots": "k_follow.hip",
 }
 
 
@@ -62,11 +64,12 @@ def run(argv):
     ap.add_argument("--workload", default="frame_10ms")
     ap.add_argument("--seed", type=int, default=3000)
     ap.add_argument("--runs", type=int, default=2)
+    ap.add_argument("--follow", action="store_true", help="the tracker with track following")
     a = ap.parse_args(argv)
     import torch
     from . import synth, tpcca
     fr = synth.generate(a.workload, seed=a.seed, n_threads=min(16, os.cpu_count() or 1))
-    trk = tpcca.Tracker()
+    trk = tpcca.Tracker(follow=1) if a.follow else tpcca.Tracker()
     trk.load_frame_packed(fr)
     trk.ensure_arena()
     trk.run(sync=True)                       # warm-up
@@ -79,8 +82,8 @@ def run(argv):
     torch.cuda.synchronize()
     trk.copy(src, dst)
     torch.cuda.synchronize()
-    print("traffic workload: %s seed %d, %d clusters, %d timed runs, copy %d bytes"
-          % (a.workload, a.seed, fr.n_clusters, a.runs, COPY_BYTES), flush=True)
+    print("traffic workload: %s seed %d%s, %d clusters, %d timed runs, copy %d bytes"
+          % (a.workload, a.seed, " (following)" if a.follow else "", fr.n_clusters, a.runs, COPY_BYTES), flush=True)
 
 
 def _read(d):
