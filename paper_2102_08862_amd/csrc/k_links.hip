@@ -552,18 +552,27 @@ __device__ inline void bin_range(const TileShared &T, const TileGeo &G, int j, i
 // Bit mask of the positions lo + k0 + [0, 32) in [lo, hi) whose cluster lies
 // in the box around (yi, ti) (down row: |yi - y| and |ti - t|; up row:
 // |y - yi| and |t - ti|). nk: the wave-uniform number of positions to test.
+// Branch-free: four staged (y, t) pairs are read before any is tested.
 template <bool Down>
 __device__ inline uint32_t box_mask(const TileShared &T, int lo, int hi, int k0, int nk, float yi, float ti, float wy,
                                     float wt) {
     uint32_t m = 0u;
-    for (int k = 0; k < nk; k++) {
-        const int p = lo + k0 + k;
-        const bool v = p < hi;
-        const float2 e = T.yt[v ? p : 0];
-        const float dy = Down ? __fsub_rn(yi, e.x) : __fsub_rn(e.x, yi);
-        const float dt = Down ? __fsub_rn(ti, e.y) : __fsub_rn(e.y, ti);
-        const bool in = v && fabsf(dy) <= wy && fabsf(dt) <= wt;
-        m |= (in ? 1u : 0u) << k;
+    for (int k = 0; k < nk; k += 4) {
+        float2 e[4];
+        int p[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            p[u] = lo + k0 + k + u;
+            e[u] = T.yt[p[u] < hi ? p[u] : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const float dy = Down ? __fsub_rn(yi, e[u].x) : __fsub_rn(e[u].x, yi);
+            const float dt = Down ? __fsub_rn(ti, e[u].y) : __fsub_rn(e[u].y, ti);
+            const uint32_t in = (uint32_t)(p[u] < hi) & (uint32_t)(k + u < nk) & (uint32_t)(fabsf(dy) <= wy) &
+                                (uint32_t)(fabsf(dt) <= wt);
+            m |= in << (k + u);
+        }
     }
     return m;
 }
@@ -671,7 +680,9 @@ __device__ void tile_links_flat(const KArgs &a, TileShared &T, const TileGeo &G,
             if (act) w = a.w_tab[r * kMaxGap + g - 1];
         }
         int bu = -1, bd = -1;
-        flat_pair(a, T, G, act, j - g, j + g, yi, ti, w, a.win_y[g - 1], a.win_t[g - 1], bu, bd);
+        // g is the same for the whole wave (a fresh round or a gap-2 drain)
+        const int gu = __builtin_amdgcn_readfirstlane(g);
+        flat_pair(a, T, G, act, j - g, j + g, yi, ti, w, a.win_y[gu - 1], a.win_t[gu - 1], bu, bd);
         // gap 2 for the clusters without a gap-1 pair
         const bool g2 = o >= 0 && g == 1 && bu < 0 && G2 >= 2 && r >= 2 && r + 2 <= R - 1;
         const uint64_t m = __ballot(g2);
