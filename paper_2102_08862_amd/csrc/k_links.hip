@@ -599,38 +599,41 @@ __device__ void flat_pair(const KArgs &a, const TileShared &T, const TileGeo &G,
         if (!__any(dm != 0u)) continue;
         for (int u0 = 0; u0 < maxu; u0 += 32) {
             const uint32_t um = dm ? box_mask<false>(T, ulo, uhi, u0, min(32, maxu - u0), yi, ti, wy, wt) : 0u;
-            const int md = wave_max_u(um ? __popc(dm) : 0), mu = wave_max_u(__popc(um));
-            uint32_t dd = um ? dm : 0u;
-            for (int x = 0; x < md; x++) {
-                const bool vd = dd != 0u;
-                const int pd = dlo + d0 + (vd ? __builtin_ctz(dd) : 0);
-                dd &= dd - 1u;
-                const float2 ed = T.yt[vd ? pd : 0];
-                uint32_t uu = vd ? um : 0u;
-                for (int z = 0; z < mu; z++) {
-                    const bool v = uu != 0u;
-                    const int pu = ulo + u0 + (v ? __builtin_ctz(uu) : 0);
-                    uu &= uu - 1u;
-                    const float2 eu = T.yt[v ? pu : 0];
-                    const float c = pair_score(yi, ti, ed.x, ed.y, eu.x, eu.y, w);
-                    const bool acc = v && c <= c2;
-                    bool better = acc && (!found || c < bc);
-                    const bool tie = acc && found && c == bc;
-                    if (__any(tie)) {
-                        if (tie) {
-                            // exact tie of the score: compare input indices
-                            const int idu = a.rec[T.plo[ju] + (pu - T.base[ju])].id;
-                            const int idd = a.rec[T.plo[jd] + (pd - T.base[jd])].id;
-                            const int biu = a.rec[T.plo[ju] + (bpu - T.base[ju])].id;
-                            const int bid = a.rec[T.plo[jd] + (bpd - T.base[jd])].id;
-                            better = idu < biu || (idu == biu && idd < bid);
-                        }
+            // every (down, up) pair of set bits, one pair per step: the wave
+            // runs the largest pair count of its lanes
+            const int nd = um ? __popc(dm) : 0, nu = __popc(um);
+            const int tot = nd * nu;
+            const int mt = wave_max_u(tot);
+            uint32_t dd = um ? dm : 0u, uu = um;
+            for (int k = 0; k < mt; k++) {
+                const bool v = k < tot;
+                const int pd = dlo + d0 + (v ? __builtin_ctz(dd) : 0);
+                const int pu = ulo + u0 + (v ? __builtin_ctz(uu) : 0);
+                const float2 ed = T.yt[v ? pd : 0];
+                const float2 eu = T.yt[v ? pu : 0];
+                const float c = pair_score(yi, ti, ed.x, ed.y, eu.x, eu.y, w);
+                const bool acc = v && c <= c2;
+                bool better = acc && (!found || c < bc);
+                const bool tie = acc && found && c == bc;
+                if (__any(tie)) {
+                    if (tie) {
+                        // exact tie of the score: compare input indices
+                        const int idu = a.rec[T.plo[ju] + (pu - T.base[ju])].id;
+                        const int idd = a.rec[T.plo[jd] + (pd - T.base[jd])].id;
+                        const int biu = a.rec[T.plo[ju] + (bpu - T.base[ju])].id;
+                        const int bid = a.rec[T.plo[jd] + (bpd - T.base[jd])].id;
+                        better = idu < biu || (idu == biu && idd < bid);
                     }
-                    found = found || acc;
-                    bc = better ? c : bc;
-                    bpu = better ? pu : bpu;
-                    bpd = better ? pd : bpd;
                 }
+                found = found || acc;
+                bc = better ? c : bc;
+                bpu = better ? pu : bpu;
+                bpd = better ? pd : bpd;
+                // next pair: the next up bit, or the first up bit of the next down bit
+                const uint32_t un = uu & (uu - 1u);
+                const bool wrap = un == 0u;
+                uu = wrap ? um : un;
+                dd = wrap ? (dd & (dd - 1u)) : dd;
             }
         }
     }
