@@ -531,10 +531,16 @@ __device__ inline void wave_lds_sync() {
 // at gap 2, 64 at a time.
 constexpr int kPlainWq = kQueueCap / (kLinkBlock / 64);    // gap-2 queue of a wave
 
+// Maximum over the wave (every lane active): within each row of 16 lanes by
+// cross-lane moves (swap neighbours, pairs, half-row mirror, row mirror),
+// then over the four rows by lane reads.
 __device__ inline int wave_max_u(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return __builtin_amdgcn_readfirstlane(v);
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false));
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // Staged fine-bin range of row j overlapped by [tlo, thi] (absolute LDS
