@@ -86,7 +86,7 @@ typedef struct {
     float s_max;               /* |sin phi| at which a propagation fails, 0.999 */
     int32_t use_mlp;           /* 1: prune candidate triplets with the loaded network, 0 */
     float mlp_logit_threshold; /* triplets with logit below this are pruned, 0 */
-    int32_t pool_per_cluster;  /* triplet-pool slots per input cluster (runs that keep the pool), 8 */
+    int32_t pool_per_cluster;  /* triplet-pool slots per input cluster (runs that keep the pool), 4 */
     /* Track following (Sec. 1: the tracker derives from one that extends its
        seeds with a Kalman filter; Sec. 2: more attached hits). With follow = 1
        every chain is extended row by row beyond both ends by two linear 1-D

@@ -209,7 +209,7 @@ tpcca_status tpcca_config_default(tpcca_config *out) {
     c.s_max = 0.999f;
     c.use_mlp = 0;
     c.mlp_logit_threshold = 0.0f;
-    c.pool_per_cluster = 8;
+    c.pool_per_cluster = 4;
     c.follow = 0;
     c.follow_win_y = 1.5f;
     c.follow_win_t = 1.5f;

@@ -141,10 +141,12 @@ __device__ inline void filter_chain(const KArgs &a, const Rec *ch, int L, int di
 
 // One extension from row r_end in direction dir (+1 outward, -1 inward), the
 // filters already at x[r_end]. The sorted positions of the accepted clusters
-// go to stg[n0], stg[n0 + 1], ... (LDS, written by the group's first lane);
-// returns their count.
+// go to the chain's LDS staging row (written by the group's first lane): the
+// outward ones to stg[0], stg[1], ..., the inward ones to stg[R - 1],
+// stg[R - 2], ... (together at most R - L entries: the chain's own rows are
+// never visited); returns their count.
 __device__ int extend(const KArgs &a, int si, const SiState &S, int r_end, int dir, Kf1 &fy, Kf1 &ft, int gl,
-                      int32_t *stg, int n0) {
+                      int32_t *stg) {
     const int R = a.n_rows;
     const int nf = S.ncb * kFinePerCb;
     const float wy = a.f_win_y, wt = a.f_win_t;
@@ -206,7 +208,7 @@ __device__ int extend(const KArgs &a, int si, const SiState &S, int r_end, int d
         if (bid >= 0 && bchi <= a.f_chi2) {
             kf1_update(fy, by, a.f_var_y);
             kf1_update(ft, bt, a.f_var_t);
-            if (gl == 0) stg[n0 + n] = bp;
+            if (gl == 0) stg[dir > 0 ? n : a.n_rows - 1 - n] = bp;
             n++;
             miss = 0;
         } else if (++miss >= a.f_max_miss) {
@@ -288,7 +290,7 @@ __device__ inline bool next_chains(int32_t *heads, int nt, int xcd, int count, i
 // writes its clusters in ascending rows followed by the chain's, the outward
 // group its clusters in ascending rows: together the extended track. Both
 // then claim their clusters with the key of the whole track.
-// Dynamic LDS: n_rows staging entries per group of the block.
+// Dynamic LDS: n_rows staging entries per chain of the block.
 __global__ __launch_bounds__(kFolBlock) void k_follow(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     extern __shared__ int32_t fol_stage[];
@@ -297,7 +299,8 @@ __global__ __launch_bounds__(kFolBlock) void k_follow(KArgs a) {
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kFolG - 1), gbase = lane & ~(kFolG - 1), grp = lane / kFolG;
     const bool inward = (grp & 1) == 0;
-    int32_t *stg = fol_stage + ((threadIdx.x >> 6) * kFolPerWave + grp) * R;
+    // one staging row per chain, shared by its inward and outward group
+    int32_t *stg = fol_stage + ((threadIdx.x >> 6) * (kFolPerWave / 2) + (grp >> 1)) * R;
     uint32_t *claim = reinterpret_cast<uint32_t *>(a.assign);
     const int xcd = blockIdx.x % kXcd;
     int q = 0, c = 0, hi = 0;
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(kFolBlock) void k_follow(KArgs a) {
             const int dir = inward ? -1 : 1;
             Kf1 fy, ft;
             filter_chain(a, ch, L, dir, gl, gbase, fy, ft);
-            n = extend(a, si, S, (inward ? c0.sr : cL.sr) & 255, dir, fy, ft, gl, stg, 0);
+            n = extend(a, si, S, (inward ? c0.sr : cL.sr) & 255, dir, fy, ft, gl, stg);
             seed_id = a.rec[c0.id].id;
             if (inward && gl == 0) {
                 a.xseed[k] = seed_id;
@@ -339,8 +342,9 @@ __global__ __launch_bounds__(kFolBlock) void k_follow(KArgs a) {
                 int32_t *dst = a.ext + off;
                 const uint32_t key = claim_key(T, seed_id);
                 for (int i = gl; i < m; i += kFolG) {
-                    // inward: staged in descending rows, then the chain
-                    const int p = !inward ? stg[i] : i < n ? stg[n - 1 - i] : ch[i - n].id;
+                    // inward: staged downwards from the top of the row (so in
+                    // ascending rows from R - n), then the chain
+                    const int p = !inward ? stg[i] : i < n ? stg[R - n + i] : ch[i - n].id;
                     dst[i] = p;
                     atomicMax(&claim[p], key);
                 }
@@ -465,7 +469,7 @@ __global__ __launch_bounds__(256) void k_follow_slots(KArgs a) {
 }
 
 void launch_follow(const KArgs &a, Launch l, hipStream_t s) {
-    const size_t lds = sizeof(int32_t) * (kFolBlock / 64) * kFolPerWave * a.n_rows;
+    const size_t lds = sizeof(int32_t) * (kFolBlock / 64) * (kFolPerWave / 2) * a.n_rows;
     const int nfb = a.n_fbins;
     hipLaunchKernelGGL(k_ford_hist, dim3(l.grid), dim3(256), 0, s, a);
     launch_scan_i32(a.fhist, nfb, a.fhist + nfb + 1, nullptr, a.scan_tmp, s);
