@@ -291,7 +291,7 @@ __device__ inline bool next_chains(int32_t *heads, int nt, int xcd, int count, i
 // group its clusters in ascending rows: together the extended track. Both
 // then claim their clusters with the key of the whole track.
 // Dynamic LDS: n_rows staging entries per chain of the block.
-__global__ __launch_bounds__(kFolBlock) void k_follow(KArgs a) {
+__global__ __launch_bounds__(kFolBlock, 8) void k_follow(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     extern __shared__ int32_t fol_stage[];
     const int nt = min(a.cnt->n_tseeds, a.tseed_cap);
