@@ -47,7 +47,7 @@ struct Layout {
     size_t perm, lhist, chain, chain_bytes, xslot;
     size_t pfeat, pd, pu, pc, pz, hoff, hn1, hn2;
     int64_t pool_cap = 0;
-    size_t xoff, xlen, xseed, xsi, klen, kchoff, ford, fhist;
+    size_t xoff, xlen, xseed, xsi, klen, kchoff, ford, fhist, foff;
     int64_t n_fbins = 0;
     int64_t ext_cap = 0;
 };
@@ -629,6 +629,7 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     L.klen = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
     L.kchoff = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
     L.ford = b.take(fol ? sizeof(int32_t) * tseed_cap : 0);
+    L.foff = b.take(fol ? sizeof(uint32_t) * SR * kNcbMax : 0);
     L.n_fbins = fol ? (int64_t)S * (kNcbMax / 8) : 0;
     L.fhist = b.take(fol ? sizeof(int32_t) * 2 * (L.n_fbins + 1) : 0);
     L.ext_cap = fol ? std::min<int64_t>((int64_t)(slot_bytes / sizeof(int32_t)), INT32_MAX - 1024) : 0;
@@ -762,6 +763,7 @@ static void bind_pointers(tpcca_ctx *c) {
     a.klen = (int32_t *)(A + L.klen);
     a.kchoff = (int32_t *)(A + L.kchoff);
     a.ford = (int32_t *)(A + L.ford);
+    a.foff = c->cfg.follow ? (uint32_t *)(A + L.foff) : nullptr;
     a.fhist = (int32_t *)(A + L.fhist);
     a.use_mlp = (c->cfg.use_mlp && c->mlp_loaded) ? 1 : 0;
     a.keep_pool = (a.use_mlp && c->pool_run) ? 1 : 0;

@@ -151,6 +151,7 @@ __device__ int extend(const KArgs &a, int si, const SiState &S, int r_end, int d
     const int nf = S.ncb * kFinePerCb;
     const float wy = a.f_win_y, wt = a.f_win_t;
     const int32_t *co_si = a.coff + (int64_t)si * R * (kNcbMax + 1);
+    const uint32_t *fo_si = a.foff + (int64_t)si * R * kNcbMax;
     int n = 0, miss = 0;
     float xp = a.row_x[r_end];
     for (int r = r_end + dir; r >= 0 && r < R; r += dir) {
@@ -165,8 +166,18 @@ __device__ int extend(const KArgs &a, int si, const SiState &S, int r_end, int d
         const float st = fslack(tp, wt);
         const int f0 = fine_bin(__fsub_rn(__fsub_rn(tp, wt), st), S.t0, S.inv_cbw, nf);
         const int f1 = fine_bin(__fadd_rn(__fadd_rn(tp, wt), st), S.t0, S.inv_cbw, nf);
+        // candidates: the fine bins f0..f1 (a fine-bin start that does not
+        // fit its byte falls back to the coarse bin's bound: a superset)
         const int32_t *co = co_si + (int64_t)r * (kNcbMax + 1);
-        const int lo = co[f0 / kFinePerCb], hi = co[f1 / kFinePerCb + 1];
+        const uint32_t *fo = fo_si + (int64_t)r * kNcbMax;
+        const int cb0 = f0 / kFinePerCb, k0 = f0 % kFinePerCb;
+        const int cb1 = (f1 + 1) / kFinePerCb, k1 = (f1 + 1) % kFinePerCb;
+        const int c0s = co[cb0], c1s = co[cb1];
+        const uint32_t w0 = fo[cb0], w1 = k1 ? fo[cb1] : 0u;
+        const uint32_t b0 = k0 ? (w0 >> (8 * (k0 - 1))) & 255u : 0u;
+        const uint32_t b1 = k1 ? (w1 >> (8 * (k1 - 1))) & 255u : 0u;
+        const int lo = b0 == 255u ? c0s : c0s + (int)b0;
+        const int hi = !k1 ? c1s : b1 == 255u ? co[cb1 + 1] : c1s + (int)b1;
         // each lane: the best of its candidates lo + gl, lo + gl + G, ...
         // (two loads in flight per lane)
         int bid = -1, bp = -1;

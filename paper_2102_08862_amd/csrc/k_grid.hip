@@ -320,8 +320,11 @@ __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
         const int ncb = s.ncb, nf = ncb * kFinePerCb;
         const float t0 = s.t0, inv = s.inv_cbw;
         int32_t *co = a.coff + (int64_t)seg * (kNcbMax + 1);
+        uint32_t *fo = a.foff ? a.foff + (int64_t)seg * kNcbMax : nullptr;
         if (n == 0) {
             for (int cb = tid; cb <= ncb; cb += bd) co[cb] = start;
+            if (fo)
+                for (int cb = tid; cb < ncb; cb += bd) fo[cb] = 0u;
             continue;
         }
         for (int b = tid; b < nf; b += bd) fh[b] = 0;
@@ -349,6 +352,18 @@ __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
         }
         __syncthreads();
         for (int cb = tid; cb <= ncb; cb += bd) co[cb] = start + (cb < ncb ? fh[cb * kFinePerCb] : n);
+        if (fo) {
+            // the fine-bin starts of each coarse bin (for searches that read
+            // the sorted space directly)
+            for (int cb = tid; cb < ncb; cb += bd) {
+                const int b0 = fh[cb * kFinePerCb];
+                uint32_t packed = 0u;
+#pragma unroll
+                for (int k = 1; k < kFinePerCb; k++)
+                    packed |= (uint32_t)min(fh[cb * kFinePerCb + k] - b0, 255) << (8 * (k - 1));
+                fo[cb] = packed;
+            }
+        }
         __syncthreads();
         // counting-sort scatter by fine bin (order inside a bin is arbitrary:
         // the neighbour tiles order each bin by y cell in LDS)

@@ -12,7 +12,8 @@ namespace tpcca {
 constexpr int kMaxRows = 255;      // rows are uint8
 constexpr int kMaxGap = 2;         // symmetric row gaps handled by the link kernel
 constexpr int kNcbMax = 4096;      // coarse time bins per sector row (upper bound)
-constexpr int kFinePerCb = 4;      // fine bins per coarse bin (row sort)
+constexpr int kFinePerCb = 4;      // fine bins per coarse bin (row sort; at most 4: their
+                                   // starts inside a coarse bin are packed in one word)
 constexpr int kTileRows = 8;       // own pad rows of a neighbour-finding tile
 constexpr int kMaxTileCb = 32;     // most own coarse bins of a tile
 constexpr int kTileCap = 3072;     // clusters a tile stages in LDS (own rows, +-kMaxGap rows, time halo)
@@ -127,6 +128,7 @@ struct Counters {
     int32_t fkq[8];          // the same for the selection
 };
 static_assert(sizeof(Counters) % 8 == 0 && offsetof(Counters, n_samples) == 0, "64-bit counter first");
+static_assert(kFinePerCb >= 1 && kFinePerCb <= 4, "fine-bin starts packed in bytes 0..2 of a word");
 
 // y cells of one pad row: cell = clamp(floor((y - ylo) * inv), 0, ny - 1).
 // Within each fine time bin a row is ordered by (cell, t, id), so a box
@@ -240,6 +242,8 @@ struct KArgs {
     int32_t *xseed, *xsi;    // [tseed_cap] seed input index (sector-local) and sector instance
     int32_t *klen;           // [tseed_cap] clusters kept (0: dropped)
     int32_t *kchoff;         // [tseed_cap] the kept track's chain copy
+    uint32_t *foff;          // [n_si * n_rows * kNcbMax] per coarse bin: starts of its fine bins 1..3
+                             // relative to the bin's start, one byte each (255: not known)
     int32_t *ford;           // [tseed_cap] chain tracks in (sector instance, seed time) order
     int32_t *fhist;          // [2 * (n_fbins + 1)] slab counts, then their exclusive prefix
     int32_t n_fbins;         // n_si * (kNcbMax / 8) time slabs
