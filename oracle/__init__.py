@@ -355,6 +355,46 @@ def run_sector(cfg: Config, row, y, t, fit: bool = True, follow_cfg: FollowConfi
     return res
 
 
+# ------------------------------------------------------ collision time
+DRIFT_LENGTH = 250.0   # cm: t = v_d t_coll + (drift length - |z|) (R2)
+
+
+def track_t0(cfg: Config, x_ref, y, t, sinphi, tau, qpt):
+    """Collision time of a track in drift cm (R28): the drift time of its
+    helix at the point of closest approach to the beam line in the
+    transverse plane, minus the drift length. From the state at x_ref
+    (position (x_ref, y), direction (cos phi, sin phi), curvature
+    kappa = -kB q/pT) the signed arc length s to that point solves
+    r(s) . r'(s) = 0 on the circle, tan(kappa s) = -a kappa / (1 + b kappa)
+    with a = r . direction and b = r . left normal (the root nearest to the
+    state: s = -a for a straight track); the time there is t + tau s. For a
+    track of one side (z of one sign) this is v_d t_coll - z_vertex on the A
+    side and v_d t_coll + z_vertex on the C side. FP64."""
+    x = np.asarray(x_ref, np.float64); yy = np.asarray(y, np.float64)
+    s = np.asarray(sinphi, np.float64); k = -2.99792458e-3 * cfg.bz * np.asarray(qpt, np.float64)
+    c = np.sqrt(1.0 - s * s)
+    a = x * c + yy * s
+    b = -x * s + yy * c
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sd = np.where(k != 0.0, np.arctan2(-a * k, 1.0 + b * k) / np.where(k != 0.0, k, 1.0), -a)
+    return np.asarray(t, np.float64) + np.asarray(tau, np.float64) * sd - DRIFT_LENGTH
+
+
+def collision_groups(t0, gap: float):
+    """Collision candidates of one side of a frame (R29): the tracks in
+    ascending t0, a new group wherever the next t0 exceeds the previous by
+    more than gap. Group numbers in ascending t0; returns int32 per track."""
+    t0 = np.asarray(t0, np.float64)
+    out = np.zeros(len(t0), np.int32)
+    if len(t0) == 0:
+        return out
+    order = np.argsort(t0, kind="stable")
+    v = t0[order]
+    new = np.concatenate([[False], (v[1:] - v[:-1]) > gap])
+    out[order] = np.cumsum(new).astype(np.int32)
+    return out
+
+
 # ----------------------------------------------------------------- MLP
 MLP_IN, MLP_INP, MLP_H = 12, 16, 64
 MLP_NPARAM = MLP_H * MLP_INP + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1

@@ -1,0 +1,119 @@
+"""Pins of the oracle's collision time per track and collision grouping.
+
+The time is pinned by the generator's own helix code (an independent
+implementation of the particle trajectory): the truth helix of a generated
+particle, read at a pad row, gives back v_d t_coll - z_vertex (A side) or
+v_d t_coll + z_vertex (C side) to rounding; by a brute-force search of the
+closest approach on the circle; by the straight-line limit; and by the fits
+of a noise-free slice. The grouping is pinned by constructed time lists."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_08862_amd import synth
+
+V_D = 2.58   # cm/us (the generator's drift velocity)
+
+
+def test_truth_helix_gives_the_collision_time(geom, ocfg):
+    x = geom[0]
+    fr = synth.generate("slice_1ms", seed=2400, n_threads=8)
+    rng = np.random.default_rng(0)
+    picks = rng.choice(len(fr.tracks), 300, replace=False)
+    got, want, n = [], [], 0
+    for pid in picks:
+        tr = fr.tracks[pid]
+        q, pt, zv, tc = tr[0], tr[1], tr[4], tr[5]
+        for sector in range(36):
+            for r in (0, 60, 151):
+                h = synth.helix_at(tr, sector, float(x[r]), False)
+                if h is None:
+                    continue
+                Y, z, sphi, arc, t, dtdl = h
+                side = 1.0 if sector < 18 else -1.0
+                if z * side <= 0:
+                    continue
+                got.append(oracle.track_t0(ocfg, x[r], Y, t, sphi, dtdl, q / pt))
+                want.append(V_D * tc - side * zv)
+                n += 1
+                break
+    got, want = np.array(got), np.array(want)
+    assert n > 200
+    assert np.abs(got - want).max() < 1e-6
+
+
+def test_closest_approach_by_brute_force(ocfg):
+    # states of outgoing tracks: a circle through a point near the beam line,
+    # followed forward by less than a radian; the closest approach to the
+    # beam line is then found by a dense search around it
+    rng = np.random.default_rng(1)
+    kB = 2.99792458e-3 * ocfg.bz
+    for _ in range(200):
+        qpt = rng.uniform(-8, 8)
+        k = -kB * qpt
+        p0 = rng.uniform(-2, 2, 2)
+        ph = rng.uniform(-0.7, 0.7)
+        S = rng.uniform(60, min(200, 0.9 / abs(k)) if k else 200)
+        d0 = np.array([np.cos(ph), np.sin(ph)]); n0 = np.array([-np.sin(ph), np.cos(ph)])
+
+        def at(s):
+            s = np.asarray(s, np.float64)
+            if k == 0:
+                return p0[None] + d0[None] * s[..., None]
+            return p0[None] + d0[None] * (np.sin(k * s) / k)[..., None] + n0[None] * ((1 - np.cos(k * s)) / k)[..., None]
+        r = at(np.array([S]))[0]
+        phr = ph + k * S
+        tau, t = rng.uniform(-1.5, 1.5), rng.uniform(500, 2000)
+        ss = np.linspace(-S - 40, min(-S + 40, 0.0), 800001)
+        i = int(np.argmin(np.hypot(*at(ss + S).T)))
+        assert 0 < i < len(ss) - 1
+        t0 = oracle.track_t0(ocfg, r[0], r[1], t, np.sin(phr), tau, qpt)
+        s_formula = (t0 + oracle.DRIFT_LENGTH - t) / tau
+        assert abs(s_formula - ss[i]) < 2e-3
+
+
+def test_straight_track_limit(ocfg):
+    x, y, s, tau, t = 120.0, 7.5, 0.3, 0.8, 900.0
+    c = np.sqrt(1 - s * s)
+    a = x * c + y * s
+    assert oracle.track_t0(ocfg, x, y, t, s, tau, 0.0) == pytest.approx(t - tau * a - oracle.DRIFT_LENGTH, abs=1e-12)
+    assert oracle.track_t0(ocfg, x, y, t, s, tau, 1e-9) == pytest.approx(t - tau * a - oracle.DRIFT_LENGTH, abs=1e-6)
+
+
+def test_noise_free_fits_recover_the_collision_time(geom, ocfg):
+    fr = synth.generate("slice_1ms", seed=2401, n_threads=8, sigma_y=0.0, sigma_t=0.0, noise_frac=0.0)
+    for sector in (3, 21):
+        row, y, t = fr.sector(sector)
+        lab = fr.labels[sector]
+        res = oracle.run_sector(ocfg, row, y, t)
+        f = res["fit"]
+        ok = f["status"] == 0
+        t0 = oracle.track_t0(ocfg, f["x_ref"], f["y"], f["t"], f["sinphi"], f["tau"], f["qpt"])
+        side = 1.0 if sector < 18 else -1.0
+        good = 0
+        for k in np.nonzero(ok)[0]:
+            cl = res["clusters"][res["first"][k]:res["first"][k] + res["len"][k]]
+            pid, cnt = np.unique(lab[cl], return_counts=True)
+            p = pid[np.argmax(cnt)]
+            if p < 0:
+                continue
+            want = V_D * fr.tracks[p][5] - side * fr.tracks[p][4]
+            good += abs(t0[k] - want) < 0.05
+        assert good >= 0.97 * ok.sum() and ok.sum() > 1000
+
+
+def test_grouping_of_constructed_times():
+    rng = np.random.default_rng(3)
+    centers = np.cumsum(rng.uniform(5, 60, 40))
+    t0, truth = [], []
+    for g, c in enumerate(centers):
+        m = rng.integers(1, 30)
+        t0.extend(c + rng.uniform(-0.4, 0.4, m)); truth.extend([g] * m)
+    t0 = np.array(t0); truth = np.array(truth)
+    perm = rng.permutation(len(t0))
+    got = oracle.collision_groups(t0[perm], 2.0)
+    assert np.array_equal(got, truth[perm])
+    # a gap of exactly the threshold does not split; just above it does
+    assert oracle.collision_groups([0.0, 2.0, 4.0], 2.0).tolist() == [0, 0, 0]
+    assert oracle.collision_groups([0.0, 2.0 + 1e-9], 2.0).tolist() == [0, 1]
+    assert len(oracle.collision_groups([], 2.0)) == 0
