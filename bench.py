@@ -365,6 +365,38 @@ def pruned_leg(trk, fr, f, args, log, q_plain):
     return out
 
 
+def collisions_leg(trk, fr, f, log, quality=True):
+    """Collision candidates after the plain run: the time of
+    find_collisions (wall clock; it synchronises, with two host round trips)
+    and, against the generator's truth, the candidates' quality per side."""
+    from paper_2102_08862_amd import metrics
+    gap, min_len, window = 0.5, 60, 5.0
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        n_groups = trk.find_collisions(gap, min_len, window)
+        ts.append(time.perf_counter() - t0)
+    out = {"gap_cm": gap, "min_clusters": min_len, "window_cm": window, "groups": int(n_groups),
+           "ms": round(1e3 * float(np.median(ts)), 4)}
+    if quality:
+        half = len(fr.rows) // 2
+        tc = fr.tracks[:, 5]
+        for side, name in ((0, "A"), (1, "C")):
+            cols = [[], [], [], []]
+            for s in (range(half) if side == 0 else range(half, len(fr.rows))):
+                t0, g = trk.track_times(f, s)
+                tr = trk.tracks(f, s)
+                pm = metrics.track_majority(fr.labels[s], trk.track_clusters(f, s), tr["n_clusters"])
+                for c, v in zip(cols, (np.where(pm >= 0, tc[np.maximum(pm, 0)], -1.0), g, tr["n_clusters"],
+                                       np.isfinite(t0))):
+                    c.append(v)
+            q = metrics.collision_quality(*(np.concatenate(c) for c in cols), min_len)
+            out[name] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in q.items()}
+    log("collisions: %d groups in %.3f ms; %s" % (out["groups"], out["ms"],
+                                                 {k: out[k] for k in ("A", "C") if k in out}))
+    return out
+
+
 def follow_leg(fr, args, log, q_plain, tuning_on, sector):
     """The tracker with track following (chain extension and shared-cluster
     selection before the fit) on the same frame, timed like the plain one;
@@ -549,6 +581,7 @@ def main():
     gpu_out = gpu_sector_outputs(trk, f, sample_sectors(len(fr.rows), max(1, ncpu))) if ncpu > 0 else {}
 
     q_plain = None if args.no_quality else frame_quality(trk, fr, f)
+    collisions = collisions_leg(trk, fr, f, log, quality=not args.no_quality)
     pruned = None
     if not args.no_pruned:
         pruned = pruned_leg(trk, fr, f, args, log, q_plain)
@@ -583,6 +616,7 @@ def main():
         "roofline": roof,
         "pruned": pruned,
         "follow": follow,
+        "collisions": collisions,
         "cpu_baseline": cpu,
         "counts": {k: int(st[k]) for k in ("n_links", "n_seeds", "n_tracks", "n_track_clusters", "n_invalid",
                                             "n_overflow_tiles", "n_tiles")},

@@ -330,6 +330,44 @@ tpcca_status tpcca_get_track_clusters(tpcca_ctx *ctx, int32_t frame, int32_t sec
    of tracks not used for physics by this assignment (Sec. 1). */
 tpcca_status tpcca_get_assignment(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *out, int64_t n);
 
+/* Collision candidates (Sec. 1: with time as the seeding coordinate,
+   collisions are separated only after tracking). Every fitted track carries
+   its collision time t0 in drift cm: the drift time of its helix at the
+   closest approach to the beam line in the transverse plane, minus the
+   250 cm drift length (for a track of one side, v_d t_coll - z_vertex on the
+   A side, + z_vertex on the C side). tpcca_find_collisions works per frame
+   side (A: sectors 0 .. n_sectors/2 - 1, C: the rest) of every loaded frame:
+     - anchors are the tracks of at least min_clusters (>= 0) clusters with a
+       finite t0 (a short track extrapolates far to the beam line, so its t0
+       is coarse);
+     - the anchors in ascending t0 form a new group wherever t0 jumps by more
+       than gap_cm (> 0); a group's time is the mean t0 of its anchors;
+     - every other track with a finite t0 joins the group of nearest time (the
+       earlier on a tie) if it lies within window_cm (>= 0) of it.
+   Suggested values for 50 kHz Pb-Pb frames: gap 0.5, min_clusters 60,
+   window 5. Call after a run (it synchronises; its working arrays take the
+   arena's slot after the chain copies, so the result holds until the next
+   run, and CAPACITY if a side's anchor t0 range needs more bins (of half the
+   gap) than that slot holds: raise the gap); *n_groups_out = groups over all
+   frames and sides. INVALID_ARG for a bad argument, STATE before a run.
+   Tracks whose fit failed have t0 = NaN and no group. */
+tpcca_status tpcca_find_collisions(tpcca_ctx *ctx, float gap_cm, int32_t min_clusters, float window_cm,
+                                   int64_t *n_groups_out);
+
+/* t0 (drift cm) and group of every track of the sector, in track order
+   (group: within the frame side, in ascending t0; -1 if none or before
+   tpcca_find_collisions); either pointer may be null. CAPACITY if cap is
+   below the track count (*n_out holds it). */
+tpcca_status tpcca_get_track_times(tpcca_ctx *ctx, int32_t frame, int32_t sector, float *t0, int32_t *group,
+                                   int64_t cap, int64_t *n_out);
+
+/* The groups of one frame side (0: A, 1: C) in ascending t0: time (mean t0
+   of the anchors, rounded to FP32), tracks (anchors and attached) and
+   anchors; any pointer may be null. STATE before tpcca_find_collisions,
+   CAPACITY if cap is below the group count (*n_out holds it). */
+tpcca_status tpcca_get_collisions(tpcca_ctx *ctx, int32_t frame, int32_t side, float *t0, int32_t *n_tracks,
+                                  int32_t *n_anchors, int64_t cap, int64_t *n_out);
+
 /* The pad-row neighbour links of the cellular-automaton seeding (Sec. 1:
    HLT-derived tracker, seeding with time as a coordinate).
    Neighbour links of every input cluster of the sector, in input indices

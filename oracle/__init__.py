@@ -395,6 +395,43 @@ def collision_groups(t0, gap: float):
     return out
 
 
+def collision_assign(t0, n_clusters, gap: float, min_clusters: int, window: float):
+    """Collision candidates of one side of a frame with the tracks attached
+    to them (R29). Anchors are the tracks of at least min_clusters clusters
+    with a finite t0; they alone form the groups (collision_groups over the
+    anchors), and a group's time is the mean t0 of its anchors. Every other
+    track with a finite t0 joins the group whose time is nearest (the earlier
+    one on a tie) if that distance is at most window.
+
+    Returns (group per track, -1 for none; group times; anchors per group;
+    tracks per group)."""
+    t0 = np.asarray(t0, np.float64)
+    n_clusters = np.asarray(n_clusters)
+    group = np.full(len(t0), -1, np.int32)
+    fin = np.isfinite(t0)
+    anchor = fin & (n_clusters >= min_clusters)
+    ia = np.nonzero(anchor)[0]
+    if len(ia) == 0:
+        return group, np.zeros(0), np.zeros(0, np.int64), np.zeros(0, np.int64)
+    ga = collision_groups(t0[ia], gap)
+    group[ia] = ga
+    ng = int(ga.max()) + 1
+    n_anchor = np.bincount(ga, minlength=ng).astype(np.int64)
+    mean = np.bincount(ga, t0[ia], ng) / n_anchor
+    io = np.nonzero(fin & ~anchor)[0]
+    if len(io):
+        v = t0[io]
+        j = np.searchsorted(mean, v)
+        lo = np.clip(j - 1, 0, ng - 1)
+        hi = np.clip(j, 0, ng - 1)
+        d_lo, d_hi = np.abs(v - mean[lo]), np.abs(v - mean[hi])
+        near = np.where(d_lo <= d_hi, lo, hi)
+        dist = np.minimum(d_lo, d_hi)
+        group[io] = np.where(dist <= window, near, -1)
+    n_all = np.bincount(group[group >= 0], minlength=ng).astype(np.int64)
+    return group, mean, n_anchor, n_all
+
+
 # ----------------------------------------------------------------- MLP
 MLP_IN, MLP_INP, MLP_H = 12, 16, 64
 MLP_NPARAM = MLP_H * MLP_INP + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1

@@ -23,7 +23,7 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-fno-fast-mat
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]
 # sources whose FP32 arithmetic decides links, bins and chains
-EXACT = {"k_grid.hip", "k_links.hip", "k_chain.hip", "k_follow.hip"}
+EXACT = {"k_grid.hip", "k_links.hip", "k_chain.hip", "k_follow.hip", "k_t0.hip"}
 
 
 def sources():

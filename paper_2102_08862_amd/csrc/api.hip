@@ -42,7 +42,7 @@ struct Layout {
     size_t tmp, rec, link, upc;
     size_t seeds, tseed, tlen, tslot, tchoff, choff;
     size_t bits, wpre;
-    size_t trk_len, trk_seed, cl_off, trk;
+    size_t trk_len, trk_seed, cl_off, trk, trk_t0, trk_group, slot_bytes;
     size_t clusters, assign, scan_tmp, asg_cnt;
     size_t perm, lhist, chain, chain_bytes, xslot;
     size_t pfeat, pd, pu, pc, pz, hoff, hn1, hn2;
@@ -118,6 +118,10 @@ struct tpcca_ctx {
     bool upload_dirty = true;
     bool have_results = false;
     bool ran = false;
+    // collision candidates of the last tpcca_find_collisions (reset by a run)
+    bool coll_valid = false;
+    std::vector<int32_t> coll_n, coll_base;   // per side: groups, first group
+    size_t coll_sum_off = 0, coll_cnt_off = 0, coll_att_off = 0;   // arena offsets: sums, anchors, attached
     Layout lay;
     KArgs args{};
     std::string err;
@@ -594,6 +598,9 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     L.trk_seed = b.take(sizeof(int32_t) * trk_cap);
     L.cl_off = b.take(sizeof(int32_t) * (trk_cap + 1));
     L.trk = b.take(sizeof(tpcca_track) * trk_cap);
+    L.trk_t0 = b.take(sizeof(float) * trk_cap);
+    L.trk_group = b.take(sizeof(int32_t) * trk_cap);
+    L.slot_bytes = slot_bytes;
     L.choff = b.take(sizeof(int32_t) * trk_cap);
     L.perm = b.take(sizeof(int32_t) * trk_cap);
     L.lhist = b.take(sizeof(int32_t) * (kLenBins + 1));
@@ -737,6 +744,7 @@ static void bind_pointers(tpcca_ctx *c) {
     a.trk_seed = (int32_t *)(A + L.trk_seed);
     a.cl_off = (int32_t *)(A + L.cl_off);
     a.trk = (tpcca_track *)(A + L.trk);
+    a.trk_t0 = (float *)(A + L.trk_t0);
     a.clusters = (int32_t *)(A + L.clusters);
     a.choff = (int32_t *)(A + L.choff);
     a.perm = (int32_t *)(A + L.perm);
@@ -1015,6 +1023,7 @@ static tpcca_status run_on_arena(tpcca_ctx *c, bool graphs) {
     if (tm) c->ev_pending[slot] = true;
     c->ran = true;
     c->have_results = true;
+    c->coll_valid = false;
     return TPCCA_OK;
 }
 
@@ -1138,6 +1147,164 @@ tpcca_status tpcca_get_track_clusters(tpcca_ctx *c, int32_t frame, int32_t secto
         if (!out) return TPCCA_ERR_INVALID_ARG;
         HIPCHK(c, hipMemcpy(out, c->arena + c->lay.clusters + sizeof(int32_t) * (size_t)st.cl_base,
                             sizeof(int32_t) * (size_t)st.n_cl, hipMemcpyDeviceToHost));
+    }
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_find_collisions(tpcca_ctx *c, float gap_cm, int32_t min_clusters, float window_cm,
+                                   int64_t *n_groups_out) {
+    if (!c || !n_groups_out || !(gap_cm > 0.f) || !std::isfinite(gap_cm) || min_clusters < 0 ||
+        !(window_cm >= 0.f) || !std::isfinite(window_cm))
+        return TPCCA_ERR_INVALID_ARG;
+    *n_groups_out = 0;
+    if (!c->have_results) return fail(c, TPCCA_ERR_STATE, "no results (run first)");
+    tpcca_status ss = tpcca_synchronize(c);
+    if (ss != TPCCA_OK) return ss;
+    const int sides = 2 * (int)c->frames.size();
+    char *A = c->arena;
+    const Layout &L = c->lay;
+    // working arrays in the slot after the chain copies (dead after a run)
+    Bump b;
+    const size_t o_range = b.take(sizeof(uint32_t) * 2 * sides), o_nb = b.take(sizeof(int32_t) * sides),
+                 o_bb = b.take(sizeof(int32_t) * sides), o_ng = b.take(sizeof(int32_t) * sides),
+                 o_gb = b.take(sizeof(int32_t) * sides);
+    CollArgs ca{};
+    ca.n_sectors = c->cfg.n_sectors;
+    ca.gap = gap_cm;
+    ca.min_len = min_clusters;
+    ca.window = window_cm;
+    {
+        volatile float w = 0.5f * gap_cm;
+        ca.inv_w = 1.0f / w;
+    }
+    char *X = A + L.xslot;
+    ca.range = (uint32_t *)(X + o_range);
+    ca.nbins = (int32_t *)(X + o_nb);
+    ca.bin_base = (int32_t *)(X + o_bb);
+    ca.n_groups = (int32_t *)(X + o_ng);
+    ca.grp_base = (int32_t *)(X + o_gb);
+    ca.trk_group = (int32_t *)(A + L.trk_group);
+    std::vector<uint32_t> rng(2 * (size_t)sides);
+    for (int h = 0; h < sides; h++) {
+        rng[2 * h] = 0xffffffffu;
+        rng[2 * h + 1] = 0u;
+    }
+    HIPCHK(c, hipMemcpyAsync(ca.range, rng.data(), sizeof(uint32_t) * rng.size(), hipMemcpyHostToDevice, c->stream));
+    launch_t0_range(c->args, ca, c->stream);
+    HIPCHK(c, hipMemcpyAsync(rng.data(), ca.range, sizeof(uint32_t) * rng.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // bins of half the gap per side, over its t0 range (the same FP32
+    // arithmetic as the kernels' bin index)
+    std::vector<int32_t> nb(sides, 0), bb(sides, 0);
+    int64_t total = 0;
+    for (int h = 0; h < sides; h++) {
+        if (rng[2 * h] > rng[2 * h + 1]) continue;
+        const float lo = fkey_inv(rng[2 * h]), hi = fkey_inv(rng[2 * h + 1]);
+        volatile float d = hi - lo;
+        volatile float v = d * ca.inv_w;
+        const double bmax = std::floor((double)v);
+        if (!(bmax >= 0.0) || bmax > 1e9) return fail(c, TPCCA_ERR_CAPACITY, "collision-time range too wide");
+        nb[h] = (int32_t)bmax + 1;
+        bb[h] = (int32_t)total;
+        total += nb[h];
+    }
+    const size_t o_cnt = b.take(sizeof(uint32_t) * total), o_min = b.take(sizeof(uint32_t) * total),
+                 o_max = b.take(sizeof(uint32_t) * total), o_grp = b.take(sizeof(int32_t) * total);
+    if (b.off > L.slot_bytes || total > (int64_t)0x7fff0000)
+        return fail(c, TPCCA_ERR_CAPACITY, "collision-time bins exceed the scratch slot (raise the gap)");
+    ca.bin_cnt = (uint32_t *)(X + o_cnt);
+    ca.bin_min = (uint32_t *)(X + o_min);
+    ca.bin_max = (uint32_t *)(X + o_max);
+    ca.bin_grp = (int32_t *)(X + o_grp);
+    HIPCHK(c, hipMemcpyAsync(ca.nbins, nb.data(), sizeof(int32_t) * sides, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ca.bin_base, bb.data(), sizeof(int32_t) * sides, hipMemcpyHostToDevice, c->stream));
+    launch_fill_i32((int32_t *)ca.bin_cnt, total, 0, c->stream);
+    launch_fill_i32((int32_t *)ca.bin_min, total, -1, c->stream);
+    launch_fill_i32((int32_t *)ca.bin_max, total, 0, c->stream);
+    launch_t0_bins(c->args, ca, sides, c->stream);
+    std::vector<int32_t> ng(sides, 0), gb(sides, 0);
+    HIPCHK(c, hipMemcpyAsync(ng.data(), ca.n_groups, sizeof(int32_t) * sides, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int64_t groups = 0;
+    for (int h = 0; h < sides; h++) {
+        if (!nb[h]) ng[h] = 0;
+        gb[h] = (int32_t)groups;
+        groups += ng[h];
+    }
+    // group sums and counts after the bins
+    const size_t o_sum = b.take(sizeof(double) * groups), o_gc = b.take(sizeof(int32_t) * groups),
+                 o_ga = b.take(sizeof(int32_t) * groups);
+    if (b.off > L.slot_bytes) return fail(c, TPCCA_ERR_CAPACITY, "collision groups exceed the scratch slot");
+    ca.grp_sum = (double *)(X + o_sum);
+    ca.grp_cnt = (int32_t *)(X + o_gc);
+    ca.grp_att = (int32_t *)(X + o_ga);
+    HIPCHK(c, hipMemcpyAsync(ca.grp_base, gb.data(), sizeof(int32_t) * sides, hipMemcpyHostToDevice, c->stream));
+    launch_fill_i32((int32_t *)ca.grp_sum, 2 * groups, 0, c->stream);
+    launch_fill_i32(ca.grp_cnt, groups, 0, c->stream);
+    launch_fill_i32(ca.grp_att, groups, 0, c->stream);
+    launch_t0_group(c->args, ca, c->stream);
+    launch_t0_attach(c->args, ca, c->stream);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "collision kernels");
+    c->coll_n = ng;
+    c->coll_base = gb;
+    c->coll_sum_off = L.xslot + o_sum;
+    c->coll_cnt_off = L.xslot + o_gc;
+    c->coll_att_off = L.xslot + o_ga;
+    c->coll_valid = true;
+    *n_groups_out = groups;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_track_times(tpcca_ctx *c, int32_t frame, int32_t sector, float *t0, int32_t *group, int64_t cap,
+                                   int64_t *n_out) {
+    if (!c || !n_out) return TPCCA_ERR_INVALID_ARG;
+    int si;
+    SiState st;
+    tpcca_status s = locate(c, frame, sector, si, st);
+    if (s != TPCCA_OK) return s;
+    *n_out = st.n_tracks;
+    if (cap < st.n_tracks) return fail(c, TPCCA_ERR_CAPACITY, "buffer too small");
+    if (st.n_tracks > 0) {
+        if (t0)
+            HIPCHK(c, hipMemcpy(t0, c->arena + c->lay.trk_t0 + sizeof(float) * (size_t)st.trk_base,
+                                sizeof(float) * (size_t)st.n_tracks, hipMemcpyDeviceToHost));
+        if (group) {
+            if (c->coll_valid)
+                HIPCHK(c, hipMemcpy(group, c->arena + c->lay.trk_group + sizeof(int32_t) * (size_t)st.trk_base,
+                                    sizeof(int32_t) * (size_t)st.n_tracks, hipMemcpyDeviceToHost));
+            else
+                for (int64_t k = 0; k < st.n_tracks; k++) group[k] = -1;
+        }
+    }
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_collisions(tpcca_ctx *c, int32_t frame, int32_t side, float *t0, int32_t *n_tracks,
+                                  int32_t *n_anchors, int64_t cap, int64_t *n_out) {
+    if (!c || !n_out) return TPCCA_ERR_INVALID_ARG;
+    if (frame < 0 || frame >= (int32_t)c->frames.size() || side < 0 || side > 1)
+        return fail(c, TPCCA_ERR_INVALID_ARG, "frame or side out of range");
+    if (!c->coll_valid) return fail(c, TPCCA_ERR_STATE, "no collision candidates (call tpcca_find_collisions)");
+    const int h = 2 * frame + side;
+    const int n = c->coll_n[h];
+    *n_out = n;
+    if (cap < n) return fail(c, TPCCA_ERR_CAPACITY, "buffer too small");
+    if (n > 0) {
+        std::vector<double> sum(n);
+        std::vector<int32_t> cnt(n), att(n);
+        HIPCHK(c, hipMemcpy(sum.data(), c->arena + c->coll_sum_off + sizeof(double) * (size_t)c->coll_base[h],
+                            sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(cnt.data(), c->arena + c->coll_cnt_off + sizeof(int32_t) * (size_t)c->coll_base[h],
+                            sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(att.data(), c->arena + c->coll_att_off + sizeof(int32_t) * (size_t)c->coll_base[h],
+                            sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost));
+        for (int k = 0; k < n; k++) {
+            if (t0) t0[k] = cnt[k] ? (float)(sum[k] / cnt[k]) : 0.f;
+            if (n_tracks) n_tracks[k] = cnt[k] + att[k];
+            if (n_anchors) n_anchors[k] = cnt[k];
+        }
     }
     return TPCCA_OK;
 }

@@ -44,6 +44,7 @@ constexpr int kFitPerWave = 64 / kFitG;               // tracks per wave
 constexpr float kStepTol = 3e-5f;
 constexpr float kCostTol = 1e-4f;
 constexpr int kMaxHalvings = 8;
+constexpr float kDriftLength = 250.f;   // cm: t = v_d t_coll + (drift length - |z|)
 
 // Hardware reciprocal and reciprocal square root (about 1 ulp). In the
 // Jacobian and the solve of the normal equations their errors change the
@@ -313,7 +314,22 @@ __device__ inline void fit_emit(const KArgs &a, const float *sx, int g, int L, c
     } else {
         o.y = o.dt = o.sinphi = o.tau = o.qpt = o.chi2 = 0.f;
     }
-    if (writer) a.trk[g] = o;
+    // collision time: the drift time at the helix's closest approach to the
+    // beam line in the transverse plane, minus the drift length; the arc s
+    // back to it solves tan(kappa s) = -a kappa / (1 + b kappa) with a, b the
+    // position along and across the direction at x_ref
+    float t0 = __builtin_nanf("");
+    if (fin) {
+        const float kap = -kB * o.qpt;
+        const float cph = sqrtf(1.f - o.sinphi * o.sinphi);
+        const float pa = o.x_ref * cph + o.y * o.sinphi, pb = o.y * cph - o.x_ref * o.sinphi;
+        const float sd = kap != 0.f ? atan2f(-pa * kap, 1.f + pb * kap) / kap : -pa;
+        t0 = (o.t_base + o.dt) + o.tau * sd - kDriftLength;
+    }
+    if (writer) {
+        a.trk[g] = o;
+        a.trk_t0[g] = t0;
+    }
 }
 
 // Fit of the tracks at queue positions [base, base + 64 / G), G lanes each.

@@ -225,6 +225,7 @@ struct KArgs {
     int32_t *perm;           // [trk_cap] track slots ordered by decreasing length
     int32_t *lhist;          // [kLenBins + 1] length histogram; after the sort: tracks with length >= b
     tpcca_track *trk;        // [trk_cap]
+    float *trk_t0;           // [trk_cap] collision time of each track (drift cm; NaN if the fit failed)
     int32_t *clusters;       // [n_in]
     Rec *chain;              // [chain_cap] chain copies {y, t, id, (si << 8) | row}, a run of a multiple
                              // of 4 entries per track (the walk's copies, with following on, hold the
@@ -261,6 +262,27 @@ struct KArgs {
     int32_t *hoff;           // [n_in] first pool slot of each cluster
     int32_t *hn1, *hn2;      // [n_in] triplets of gap 1 / gap 2
     MlpDev mlp;
+};
+
+// Arguments of the collision grouping (after a run; all but trk_group in the
+// dead slot of the scratch region). A side is (frame, A or C): 2 per frame.
+struct CollArgs {
+    int32_t n_sectors;
+    float gap;               // a group ends where t0 jumps by more than this (cm)
+    float inv_w;             // 1 / bin width (bins of half the gap)
+    int32_t min_len;         // anchors: tracks of at least this many clusters
+    float window;            // other tracks join the nearest group within this (cm)
+    uint32_t *range;         // [2 * sides] smallest, largest t0 (order-preserving keys)
+    int32_t *nbins;          // [sides]
+    int32_t *bin_base;       // [sides]
+    uint32_t *bin_cnt, *bin_min, *bin_max;   // [bins]
+    int32_t *bin_grp;        // [bins] group of a non-empty bin, -1 if empty
+    int32_t *n_groups;       // [sides]
+    int32_t *grp_base;       // [sides]
+    double *grp_sum;         // [groups] sum of the t0 of its anchors (null: first pass)
+    int32_t *grp_cnt;        // [groups] anchors
+    int32_t *grp_att;        // [groups] other tracks attached
+    int32_t *trk_group;      // [trk_cap] group within its side, -1: none
 };
 
 // Order-preserving map of a float to an unsigned key.
@@ -331,5 +353,9 @@ void launch_scan_i32_dev(const int32_t *in, const int32_t *n_dev, int32_t n_cap,
                          int32_t *total_dst, int32_t *tmp, hipStream_t s);
 void launch_si_tracks(const KArgs &a, hipStream_t s);
 void launch_si_clusters(const KArgs &a, hipStream_t s);
+void launch_t0_range(const KArgs &a, const CollArgs &c, hipStream_t s);
+void launch_t0_bins(const KArgs &a, const CollArgs &c, int n_sides, hipStream_t s);
+void launch_t0_group(const KArgs &a, const CollArgs &c, hipStream_t s);
+void launch_t0_attach(const KArgs &a, const CollArgs &c, hipStream_t s);
 
 }  // namespace tpcca

@@ -12,6 +12,15 @@ used to judge the tracker and the learned pruning):
   - fake rate = fake tracks / all tracks;
   - hit efficiency = signal clusters of findable pairs that sit on a track
     matched to their own particle / signal clusters of findable pairs.
+
+Collision candidates (collision_quality) are judged by each track's
+majority collision (the collision of its majority particle):
+  - purity = anchors in groups of >= 10 anchors whose collision is their
+    group's majority collision / those anchors;
+  - a collision with >= 5 anchors is found if the group holding most of its
+    anchors holds at least half of them and has it as majority collision;
+  - attached = other tracks with a time that joined a group / those tracks;
+    correct = attached tracks whose collision is their group's majority.
 """
 from __future__ import annotations
 
@@ -84,3 +93,62 @@ def frame_quality(frame, get_clusters, get_lengths, sectors=None):
     tracker's outputs for sector s."""
     ss = range(len(frame.labels)) if sectors is None else sectors
     return summarize([sector_counts(frame.labels[s], get_clusters(s), get_lengths(s)) for s in ss])
+
+
+def track_majority(labels, clusters, lengths):
+    """Majority label of each track (ties: the smaller label; -1 if noise
+    wins); labels int32[n], clusters = concatenated cluster lists."""
+    lengths = np.asarray(lengths, np.int64)
+    T = len(lengths)
+    if T == 0:
+        return np.zeros(0, np.int64)
+    tid = np.repeat(np.arange(T), lengths)
+    lab = np.asarray(labels)[np.asarray(clusters)].astype(np.int64)
+    key = tid * (1 << 32) + (lab + 1)
+    uk, uc = np.unique(key, return_counts=True)
+    ut = uk >> 32
+    ul = (uk & 0xffffffff) - 1
+    order = np.lexsort((-uc, ut))
+    first = np.ones(len(order), bool)
+    first[1:] = ut[order][1:] != ut[order][:-1]
+    out = np.full(T, -1, np.int64)
+    out[ut[order][first]] = ul[order][first]
+    return out
+
+
+def collision_quality(coll, group, lengths, has_time, min_len):
+    """Collision-candidate quality of one frame side: coll = collision id of
+    each track's majority particle (negative for fakes), group = the track's
+    group (-1 none), lengths = clusters per track, has_time = finite t0."""
+    coll, group = np.asarray(coll, np.float64), np.asarray(group)
+    lengths, has_time = np.asarray(lengths), np.asarray(has_time, bool)
+    anc = has_time & (lengths >= min_len)
+    ng = int(group.max()) + 1 if len(group) else 0
+    ga, ca = group[anc], coll[anc]
+    size = np.bincount(ga, minlength=ng)
+    maj = np.full(ng + 1, -2.0)
+    if len(ga):
+        o = np.lexsort((ca, ga))
+        g_s, c_s = ga[o], ca[o]
+        start = np.r_[True, (g_s[1:] != g_s[:-1]) | (c_s[1:] != c_s[:-1])]
+        idx = np.nonzero(start)[0]
+        run = np.diff(np.r_[idx, len(g_s)])
+        o2 = np.lexsort((-run, g_s[idx]))
+        first = np.r_[True, g_s[idx][o2][1:] != g_s[idx][o2][:-1]]
+        maj[g_s[idx][o2][first]] = c_s[idx][o2][first]
+    big = size[ga] >= 10 if len(ga) else np.zeros(0, bool)
+    ok_a = (ca == maj[ga]) & (ca >= 0)
+    purity = float(ok_a[big].mean()) if big.any() else 1.0
+    found = considered = 0
+    v, c = np.unique(ca[ca >= 0], return_counts=True)
+    for vv, cc in zip(v[c >= 5], c[c >= 5]):
+        considered += 1
+        ug, uc = np.unique(ga[ca == vv], return_counts=True)
+        k = int(np.argmax(uc))
+        found += bool(uc[k] >= 0.5 * cc and maj[ug[k]] == vv)
+    short = has_time & ~anc
+    att = short & (group >= 0)
+    correct = (coll == maj[np.where(group >= 0, group, ng)]) & (coll >= 0)
+    return dict(groups=ng, anchors=int(anc.sum()), purity=purity, collisions=considered, found=found,
+                short=int(short.sum()), attached=float(att.sum() / max(short.sum(), 1)),
+                correct=float(correct[att].mean()) if att.any() else 1.0)

@@ -88,6 +88,7 @@ EXPORTS = [
     "tpcca_get_links", "tpcca_mlp_state_bytes", "tpcca_mlp_attach", "tpcca_mlp_load", "tpcca_mlp_fetch",
     "tpcca_mlp_infer", "tpcca_mlp_grad", "tpcca_mlp_train_step", "tpcca_get_triplets", "tpcca_set_graph",
     "tpcca_set_launch", "tpcca_set_pruning", "tpcca_set_triplet_pool", "tpcca_copy", "tpcca_triplet_samples",
+    "tpcca_find_collisions", "tpcca_get_track_times", "tpcca_get_collisions",
 ]
 
 MLP_NPARAM = 5313
@@ -128,6 +129,9 @@ def load_library(path: str = LIB_PATH):
         "tpcca_get_tracks": [P, I32, I32, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_track_clusters": [P, I32, I32, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_assignment": [P, I32, I32, P, I64],
+        "tpcca_find_collisions": [P, ctypes.c_float, I32, ctypes.c_float, ctypes.POINTER(I64)],
+        "tpcca_get_track_times": [P, I32, I32, P, P, I64, ctypes.POINTER(I64)],
+        "tpcca_get_collisions": [P, I32, I32, P, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_links": [P, I32, I32, I32, P, P, I64],
         "tpcca_mlp_state_bytes": [ctypes.POINTER(SZ)],
         "tpcca_mlp_attach": [P, P, SZ],
@@ -198,6 +202,11 @@ class Tracker:
             hh = self.h if h == -1 else h
             msg = self.lib.tpcca_last_error(hh).decode() if hh else ""
             raise TpccaError(st, msg)
+
+    def _check_cap(self, st):
+        """A size query: CAPACITY (the buffer of 0 entries is too small) is expected."""
+        if st != OK and st != ERR_CAPACITY:
+            self._check(st)
 
     def close(self):
         if getattr(self, "h", None):
@@ -402,6 +411,41 @@ class Tracker:
         out = np.zeros(n, np.int32)
         self._check(self.lib.tpcca_get_assignment(self.h, frame, sector, out.ctypes.data if n else None, n))
         return out
+
+    def find_collisions(self, gap_cm: float = 0.5, min_clusters: int = 60, window_cm: float = 5.0) -> int:
+        """Group the tracks of every loaded frame side into collision
+        candidates by their collision times: tracks of at least min_clusters
+        clusters form the groups (a new one where t0 jumps by more than
+        gap_cm), the others join the nearest group time within window_cm.
+        Returns the number of groups."""
+        n = ctypes.c_int64()
+        self._check(self.lib.tpcca_find_collisions(self.h, float(gap_cm), int(min_clusters), float(window_cm),
+                                                   ctypes.byref(n)))
+        return n.value
+
+    def track_times(self, frame, sector):
+        """(t0 float32, group int32) of every track of the sector."""
+        n = ctypes.c_int64()
+        self._check_cap(self.lib.tpcca_get_track_times(self.h, frame, sector, None, None, 0, ctypes.byref(n)))
+        t0 = np.zeros(n.value, np.float32)
+        g = np.zeros(n.value, np.int32)
+        if n.value:
+            self._check(self.lib.tpcca_get_track_times(self.h, frame, sector, t0.ctypes.data, g.ctypes.data, n.value,
+                                                       ctypes.byref(n)))
+        return t0, g
+
+    def collisions(self, frame, side):
+        """(time float32, tracks int32, anchors int32) of every group of a
+        frame side (0: A, 1: C), in ascending time."""
+        n = ctypes.c_int64()
+        self._check_cap(self.lib.tpcca_get_collisions(self.h, frame, side, None, None, None, 0, ctypes.byref(n)))
+        t0 = np.zeros(n.value, np.float32)
+        cnt = np.zeros(n.value, np.int32)
+        anc = np.zeros(n.value, np.int32)
+        if n.value:
+            self._check(self.lib.tpcca_get_collisions(self.h, frame, side, t0.ctypes.data, cnt.ctypes.data,
+                                                      anc.ctypes.data, n.value, ctypes.byref(n)))
+        return t0, cnt, anc
 
     def links(self, frame, sector, cleaned: bool = False):
         n = self.sector_n.get((frame, sector), 0)

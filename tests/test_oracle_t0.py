@@ -117,3 +117,61 @@ def test_grouping_of_constructed_times():
     assert oracle.collision_groups([0.0, 2.0, 4.0], 2.0).tolist() == [0, 0, 0]
     assert oracle.collision_groups([0.0, 2.0 + 1e-9], 2.0).tolist() == [0, 1]
     assert len(oracle.collision_groups([], 2.0)) == 0
+
+
+def _assign_brute(t0, n, gap, min_n, window):
+    """Pure-Python restatement: anchors sorted and cut at gaps, means by
+    summation, each other finite track to the first group of least distance."""
+    anchors = sorted((t, i) for i, t in enumerate(t0) if np.isfinite(t) and n[i] >= min_n)
+    groups = []
+    for t, i in anchors:
+        if groups and t - groups[-1][-1][0] <= gap:
+            groups[-1].append((t, i))
+        else:
+            groups.append([(t, i)])
+    out = [-1] * len(t0)
+    means = []
+    for g, members in enumerate(groups):
+        for _, i in members:
+            out[i] = g
+        means.append(sum(t for t, _ in members) / len(members))
+    for i, t in enumerate(t0):
+        if not np.isfinite(t) or n[i] >= min_n or not means:
+            continue
+        best, bd = -1, None
+        for g, m in enumerate(means):
+            if bd is None or abs(t - m) < bd:
+                best, bd = g, abs(t - m)
+        out[i] = best if bd <= window else -1
+    return out, means
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_attachment_by_brute_force(seed):
+    rng = np.random.default_rng(50 + seed)
+    m = int(rng.integers(0, 60))
+    t0 = np.round(rng.uniform(0, 40, m), 1)   # ties and exact threshold gaps occur
+    t0[rng.random(m) < 0.1] = np.nan
+    n = rng.integers(5, 100, m)
+    gap, min_n, window = 0.5 + 0.5 * (seed % 3), 40, [1.0, 3.0, 100.0][seed % 3]
+    want, means = _assign_brute(list(t0), list(n), gap, min_n, window)
+    got, mean, n_anchor, n_all = oracle.collision_assign(t0, n, gap, min_n, window)
+    assert got.tolist() == want
+    assert np.allclose(mean, means, rtol=0, atol=1e-12)
+    assert n_anchor.tolist() == [sum(1 for i in range(m) if want[i] == g and n[i] >= min_n) for g in range(len(means))]
+    assert n_all.tolist() == [want.count(g) for g in range(len(means))]
+
+
+def test_attachment_of_a_constructed_case():
+    # anchors (>= 10 clusters) at 0 and 0.3 (one group, mean 0.15) and at 10;
+    # short tracks at 5.075 (4.925 from both means, exactly in FP64: the tie
+    # goes to the earlier group), 9 (nearer the second) and 30 (beyond any
+    # window); a long track without a time belongs to no group
+    t0 = np.array([0.0, 0.3, 10.0, 5.075, 9.0, 30.0, np.nan])
+    n = np.array([10, 12, 50, 3, 3, 3, 80])
+    got, mean, na, nall = oracle.collision_assign(t0, n, 1.0, 10, 6.0)
+    assert got.tolist() == [0, 0, 1, 0, 1, -1, -1]
+    assert np.allclose(mean, [0.15, 10.0]) and na.tolist() == [2, 1] and nall.tolist() == [3, 2]
+    got, *_ = oracle.collision_assign(t0, n, 1.0, 10, 4.0)
+    assert got.tolist() == [0, 0, 1, -1, 1, -1, -1]
+    assert oracle.collision_assign(t0[:0], n[:0], 1.0, 10, 4.0)[0].size == 0
