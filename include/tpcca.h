@@ -295,6 +295,9 @@ tpcca_status tpcca_set_graph(tpcca_ctx *ctx, int32_t on);
    workgroups per compute unit (0: keep).
    For stage 5, param sets how many clusters a neighbour-finding tile may
    stage in LDS (256..3072, 0: keep; smaller tiles give more work items).
+   For stage 4, param sets how many clusters a (row, time slab) bucket of the
+   row sort may hold to be sorted in registers (1..8192, 0: keep; larger
+   buckets take a two-pass path through global memory).
    Results do not depend on these settings. */
 tpcca_status tpcca_set_launch(tpcca_ctx *ctx, int32_t stage, int32_t blocks_per_cu, int32_t param);
 

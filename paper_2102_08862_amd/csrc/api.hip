@@ -36,7 +36,7 @@ struct Layout {
     size_t inputs, st, cnt;
     // tables in the context's own device block (not in the arena)
     size_t si, chunk, row_x, w_tab, ycell, tab_bytes;
-    size_t rcnt, rstart, rcur, coff;
+    size_t rcnt, bcnt, bstart, bcur, coff;
     size_t tstart, ntile, tile_base, tiles, glb_tiles;
     int64_t tile_cap = 0;
     size_t tmp, rec, link, upc;
@@ -151,6 +151,7 @@ struct tpcca_ctx {
     hipGraphExec_t graph_exec = nullptr;
     bool graph_valid = false;
     int32_t tile_budget = kTileCap;  // clusters a neighbour tile may stage
+    int32_t sort_cap = kSortCap;     // clusters a row-sort bucket may hold to be sorted in registers
     char *mlp = nullptr;       // caller-owned network state buffer
     bool mlp_loaded = false;
     bool keep_pool = false;    // pruned runs list every triplet in the pool
@@ -381,15 +382,16 @@ tpcca_status tpcca_set_launch(tpcca_ctx *c, int32_t stage, int32_t blocks_per_cu
     bool ok = false;
     for (int v : tunable) ok = ok || v == stage;
     if (!ok || blocks_per_cu < 0 || blocks_per_cu > 64) return fail(c, TPCCA_ERR_INVALID_ARG, "bad stage or blocks");
-    if (param != 0 && (stage != 5 || param < 256 || param > kTileCap))
+    if (param != 0 && !((stage == 5 && param >= 256 && param <= kTileCap) || (stage == 4 && param >= 1 && param <= kSortCap)))
         return fail(c, TPCCA_ERR_INVALID_ARG, "bad param");
     if (stage == 4 && blocks_per_cu > 4) return fail(c, TPCCA_ERR_INVALID_ARG, "rowsort: at most 4 blocks per CU");
     if (stage == 3 && blocks_per_cu > 4) return fail(c, TPCCA_ERR_INVALID_ARG, "scatter: at most 4 blocks per CU");
     if (stage == 5 && blocks_per_cu > 4) return fail(c, TPCCA_ERR_INVALID_ARG, "links: at most 4 blocks per CU");
     (void)hipStreamSynchronize(c->stream);
     if (blocks_per_cu) c->lc[stage].grid = std::max(1, c->n_cu) * blocks_per_cu;
-    if (param) c->tile_budget = param;
-    c->plan_dirty = true;  // the tile budget is a kernel argument
+    if (param && stage == 5) c->tile_budget = param;
+    if (param && stage == 4) c->sort_cap = param;
+    c->plan_dirty = true;  // the tile budget and the sort capacity are kernel arguments
     c->graph_valid = false;
     return TPCCA_OK;
 }
@@ -557,8 +559,9 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     L.st = b.take(sizeof(SiState) * S);
     L.cnt = b.take(sizeof(Counters));
     L.rcnt = b.take(sizeof(int32_t) * SR);
-    L.rstart = b.take(sizeof(int32_t) * SR);
-    L.rcur = b.take(sizeof(int32_t) * SR);
+    L.bcnt = b.take(sizeof(int32_t) * SR * kNSlabMax);
+    L.bstart = b.take(sizeof(int32_t) * SR * kNSlabMax);
+    L.bcur = b.take(sizeof(int32_t) * SR * kNSlabMax);
     L.coff = b.take(sizeof(int32_t) * SR * (kNcbMax + 1));
     const int nrb = (R + kTileRows - 1) / kTileRows;
     const int64_t NW = (int64_t)S * nrb;
@@ -664,6 +667,7 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     a.n_rb = nrb;
     // the pruned search without the pool stages smaller tiles
     a.tile_budget = std::min(c->tile_budget, (c->cfg.use_mlp && !c->keep_pool) ? kPrCap : kTileCap);
+    a.sort_cap = c->sort_cap;
     a.tile_cap = (int32_t)L.tile_cap;
     a.min_track_hits = c->cfg.min_track_hits;
     a.kf_passes = c->cfg.kf_passes;
@@ -726,8 +730,9 @@ static void bind_pointers(tpcca_ctx *c) {
     a.cnt = (Counters *)(A + L.cnt);
     a.chunk = (const int32_t *)(D + L.chunk);
     a.rcnt = (int32_t *)(A + L.rcnt);
-    a.rstart = (int32_t *)(A + L.rstart);
-    a.rcur = (int32_t *)(A + L.rcur);
+    a.bcnt = (int32_t *)(A + L.bcnt);
+    a.bstart = (int32_t *)(A + L.bstart);
+    a.bcur = (int32_t *)(A + L.bcur);
     a.coff = (int32_t *)(A + L.coff);
     a.tmp = (Rec *)(A + L.tmp);
     a.rec = (Rec *)(A + L.rec);
@@ -798,12 +803,13 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     mark(st++);
     // reset: row counts, bitmap, assignment (fill kernels: graph-safe)
     launch_fill_i32(a.rcnt, (int64_t)a.n_si * a.n_rows, 0, s);
+    launch_fill_i32(a.bcnt, (int64_t)a.n_si * a.n_rows * kNSlabMax, 0, s);
     launch_fill_i32((int32_t *)a.bits, (int64_t)a.n_words + 1, 0, s);
     launch_fill_i32(a.asg_cnt, (int64_t)a.n_in / 16384 + 2, 0, s);
     mark(st++);
     launch_grid_hist(a, c->lc[1], s);  // also resets per-sector state and counters
     mark(st++);
-    launch_grid_setup(a, s);
+    launch_grid_setup(a, c->lc[1], s);
     mark(st++);
     launch_grid_scatter(a, c->lc[3], s);
     mark(st++);

@@ -1,18 +1,26 @@
 // Search-grid construction: per sector, clusters are grouped by pad row and
-// each row is ordered by fine drift-time bin (2 per coarse bin), with coarse
-// time bins giving O(1) range lookups. The grid is an acceleration structure
-// only: neighbour candidate sets are decided by exact predicates later, so
-// the layout cannot change any result.
+// each row is ordered by fine drift-time bin (kFinePerCb per coarse bin), with
+// coarse time bins giving O(1) range lookups. The grid is an acceleration
+// structure only: neighbour candidate sets are decided by exact predicates
+// later, so the layout cannot change any result.
+//
+// A row of a 10 ms frame holds tens of thousands of clusters, more than LDS
+// holds, so the scatter already splits every row into buckets of whole
+// coarse bins (time slabs of cps coarse bins, cps chosen per sector so that a
+// bucket holds about kSlabTarget clusters); the row sort then orders one
+// bucket at a time, its records in registers and its writes confined to the
+// bucket's range.
 //
 // Kernels (persistent, grid-stride over device-side work counts):
-//   k_si_init   reset per-sector state
-//   k_hist      per-chunk LDS row histogram + time range, validation
-//   k_si_rows   per sector: row prefix, bin geometry
-//   k_si_prefix sorted-space base of every sector
-//   k_scatter   scatter of clusters into row segments (staged by row in LDS)
-//   k_rowsort   per (sector,row): counting sort by fine time bin (LDS
-//               histogram, scatter); writes the coarse bin offsets used by
-//               the neighbour tiles
+//   k_si_init    reset per-sector state
+//   k_hist       per-chunk LDS row histogram + time range, validation
+//   k_si_rows    per sector: bin geometry and slab width
+//   k_si_prefix  sorted-space base of every sector
+//   k_bhist      per-chunk LDS histogram of the (row, slab) buckets
+//   k_si_buckets per sector: bucket starts (row-major, slab-minor)
+//   k_scatter    scatter of clusters into their buckets (staged in LDS)
+//   k_rowsort    per bucket: counting sort by fine time bin; writes the
+//                coarse-bin offsets (and fine-bin starts) of its bins
 #include "tpcca_internal.h"
 
 namespace tpcca {
@@ -121,6 +129,7 @@ __global__ __launch_bounds__(256) void k_hist(KArgs a) {
 
 __global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
     __shared__ int32_t sc[256];
+    __shared__ int32_t smax;
     const int R = a.n_rows;
     const int r = threadIdx.x;
     for (int si = blockIdx.x; si < a.n_si; si += gridDim.x) {
@@ -133,10 +142,10 @@ __global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
             sc[r] += x;
             __syncthreads();
         }
-        if (r < R) {
-            a.rstart[si * R + r] = sc[r] - v;
-            a.rcur[si * R + r] = sc[r] - v;
-        }
+        if (r == 0) smax = 0;
+        __syncthreads();
+        if (v) atomicMax(&smax, v);
+        __syncthreads();
         if (r == 0) {
             SiState s = a.st[si];
             const int nv = sc[255];
@@ -161,6 +170,9 @@ __global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
             s.inv_cbw = inv;
             s.ncb = ncb;
             s.n_valid = nv;
+            // slabs of the fullest row hold about kSlabTarget clusters
+            const int ns = min(max((smax + kSlabTarget - 1) / kSlabTarget, 1), kNSlabMax);
+            s.cps = (ncb + ns - 1) / ns;
             a.st[si] = s;
         }
         __syncthreads();
@@ -210,67 +222,151 @@ void launch_grid_hist(const KArgs &a, Launch l, hipStream_t s) {
         hipLaunchKernelGGL(k_hist, dim3(min(l.grid, a.n_chunks)), dim3(256), 0, s, a);
 }
 
-void launch_grid_setup(const KArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_si_rows, dim3(min(a.n_si, 4096)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_si_prefix, dim3(1), dim3(1024), 0, s, a);
+// Slab of a fine bin: whole coarse bins, cps of them per slab.
+__device__ inline int slab_of(int fine, int cps) { return fine / (cps * kFinePerCb); }
+
+// Clusters per (row, slab) bucket, one chunk of inputs at a time (the same
+// validation and fine bin as the scatter).
+__global__ __launch_bounds__(256) void k_bhist(KArgs a) {
+    TPCCA_ABORT_GUARD(a);
+    __shared__ int32_t h[kMaxRows * kNSlabMax];
+    const int R = a.n_rows, nb = R * kNSlabMax;
+    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
+        const int si = a.chunk[2 * c], start = a.chunk[2 * c + 1];
+        const SiDesc d = a.si[si];
+        const SiState S = a.st[si];
+        const int nf = S.ncb * kFinePerCb;
+        const int end = min(start + kChunk, d.n);
+        for (int k = threadIdx.x; k < nb; k += blockDim.x) h[k] = 0;
+        __syncthreads();
+        for (int i = start + threadIdx.x; i < end; i += blockDim.x) {
+            const int r = d.row[i];
+            const float y = d.y[i], t = d.t[i];
+            if (valid_cluster(r, y, t, R))
+                atomicAdd(&h[r * kNSlabMax + slab_of(fine_bin(t, S.t0, S.inv_cbw, nf), S.cps)], 1);
+        }
+        __syncthreads();
+        int32_t *g = a.bcnt + (int64_t)si * nb;
+        for (int k = threadIdx.x; k < nb; k += blockDim.x)
+            if (h[k]) atomicAdd(&g[k], h[k]);
+        __syncthreads();
+    }
 }
 
-// Scatter into row segments, one chunk of kChunk clusters at a time: the
-// chunk's clusters are ranked per row in LDS, the workgroup takes one range
-// of every row's segment cursor, stages the records grouped by row in LDS and
-// writes them out in that order, so consecutive lanes write consecutive
-// addresses of one row's range. Each input is read once.
+// Bucket starts of every sector: exclusive prefix over (row, slab) in row
+// order, slab order within a row (so a row's buckets are contiguous and in
+// time order). 1024 threads, two buckets each.
+__global__ __launch_bounds__(1024) void k_si_buckets(KArgs a) {
+    __shared__ int32_t wsum[16];
+    const int nb = a.n_rows * kNSlabMax;   // <= 2040
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int si = blockIdx.x; si < a.n_si; si += gridDim.x) {
+        const int32_t *cnt = a.bcnt + (int64_t)si * nb;
+        const int k0 = 2 * tid;
+        const int v0 = k0 < nb ? cnt[k0] : 0, v1 = k0 + 1 < nb ? cnt[k0 + 1] : 0;
+        const int v = v0 + v1;
+        int x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        if (tid < 64) {
+            const int u = tid < 16 ? wsum[tid] : 0;
+            int z = u;
+            for (int off = 1; off < 16; off <<= 1) {
+                const int y = __shfl_up(z, off);
+                if (tid >= off) z += y;
+            }
+            if (tid < 16) wsum[tid] = z - u;
+        }
+        __syncthreads();
+        const int e = wsum[w] + x - v;
+        int32_t *bs = a.bstart + (int64_t)si * nb, *bc = a.bcur + (int64_t)si * nb;
+        if (k0 < nb) {
+            bs[k0] = e;
+            bc[k0] = e;
+        }
+        if (k0 + 1 < nb) {
+            bs[k0 + 1] = e + v0;
+            bc[k0 + 1] = e + v0;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_grid_setup(const KArgs &a, Launch l, hipStream_t s) {
+    hipLaunchKernelGGL(k_si_rows, dim3(min(a.n_si, 4096)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_si_prefix, dim3(1), dim3(1024), 0, s, a);
+    if (a.n_chunks > 0) hipLaunchKernelGGL(k_bhist, dim3(min(l.grid, a.n_chunks)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_si_buckets, dim3(min(a.n_si, 4096)), dim3(1024), 0, s, a);
+}
+
+// Scatter into the (row, slab) buckets, one chunk of kChunk clusters at a
+// time: the chunk's clusters are ranked per bucket in LDS, the workgroup
+// takes one range of every bucket's cursor, stages the records grouped by
+// bucket in LDS and writes them out in that order, so consecutive lanes write
+// consecutive addresses of one bucket's range. Each input is read once.
 constexpr int kScatterBlock = 1024;
 constexpr int kScatterPer = kChunk / kScatterBlock;
+constexpr int kScatterBk = kMaxRows * kNSlabMax;
 static_assert(kScatterPer * kScatterBlock == kChunk, "a chunk must split evenly over the workgroup");
 
 __global__ __launch_bounds__(kScatterBlock) void k_scatter(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ Rec stage[kChunk];
-    __shared__ int32_t h[kMaxRows + 1], ls[kMaxRows + 1], gb[kMaxRows + 1];
+    __shared__ int32_t h[kScatterBk + 1], ls[kScatterBk + 1], gb[kScatterBk + 1];
     __shared__ int32_t s_nv;
     const int R = a.n_rows, tid = threadIdx.x;
+    const int nbk = R * kNSlabMax;
     for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
         const int si = a.chunk[2 * c], i0 = a.chunk[2 * c + 1];
         const SiDesc d = a.si[si];
-        const int sbase = a.st[si].sbase;
+        const SiState S = a.st[si];
+        const int nf = S.ncb * kFinePerCb;
         const int i1 = min(i0 + kChunk, d.n);
-        for (int r = tid; r < R; r += kScatterBlock) h[r] = 0;
+        for (int k = tid; k < nbk; k += kScatterBlock) h[k] = 0;
         __syncthreads();
-        int rr[kScatterPer], rk[kScatterPer];
+        int bk[kScatterPer], rk[kScatterPer];
         float yy[kScatterPer], tt[kScatterPer];
 #pragma unroll
         for (int k = 0; k < kScatterPer; k++) {
             const int i = i0 + k * kScatterBlock + tid;
-            rr[k] = -1;
+            bk[k] = -1;
             yy[k] = 0.f;
             tt[k] = 0.f;
             if (i < i1) {
                 const int r = d.row[i];
                 yy[k] = d.y[i];
                 tt[k] = d.t[i];
-                if (valid_cluster(r, yy[k], tt[k], R)) rr[k] = r;
+                if (valid_cluster(r, yy[k], tt[k], R))
+                    bk[k] = r * kNSlabMax + slab_of(fine_bin(tt[k], S.t0, S.inv_cbw, nf), S.cps);
             }
         }
 #pragma unroll
-        for (int k = 0; k < kScatterPer; k++) rk[k] = rr[k] >= 0 ? atomicAdd(&h[rr[k]], 1) : 0;
+        for (int k = 0; k < kScatterPer; k++) rk[k] = bk[k] >= 0 ? atomicAdd(&h[bk[k]], 1) : 0;
         __syncthreads();
-        // row starts inside the stage (one wave scans the rows) and one
-        // global range of every row's segment
+        // one global range of every bucket (all reservations in flight at
+        // once) and the bucket starts inside the stage (one wave scans)
+        {
+            int32_t *cur = a.bcur + (int64_t)si * nbk;
+            for (int k = tid; k < nbk; k += kScatterBlock) {
+                const int v = h[k];
+                gb[k] = v ? S.sbase + atomicAdd(&cur[k], v) : 0;
+            }
+        }
         if (tid < 64) {
             int carry = 0;
-            for (int r0 = 0; r0 < R; r0 += 64) {
-                const int r = r0 + tid;
-                const int v = r < R ? h[r] : 0;
+            for (int k0 = 0; k0 < nbk; k0 += 64) {
+                const int k = k0 + tid;
+                const int v = k < nbk ? h[k] : 0;
                 int x = v;
                 for (int off = 1; off < 64; off <<= 1) {
                     const int u = __shfl_up(x, off);
                     if (tid >= off) x += u;
                 }
-                if (r < R) {
-                    ls[r] = carry + x - v;
-                    gb[r] = v ? sbase + atomicAdd(&a.rcur[si * R + r], v) : 0;
-                }
+                if (k < nbk) ls[k] = carry + x - v;
                 carry += __shfl(x, 63);
             }
             if (tid == 0) s_nv = carry;
@@ -278,21 +374,21 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(KArgs a) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kScatterPer; k++) {
-            if (rr[k] >= 0) {
+            if (bk[k] >= 0) {
                 Rec e;
                 e.y = yy[k];
                 e.t = tt[k];
                 e.id = i0 + k * kScatterBlock + tid;
-                e.sr = (si << 8) | rr[k];
-                stage[ls[rr[k]] + rk[k]] = e;
+                e.sr = (si << 8) | (bk[k] / kNSlabMax);
+                stage[ls[bk[k]] + rk[k]] = e;
             }
         }
         __syncthreads();
         const int nv = s_nv;
         for (int j = tid; j < nv; j += kScatterBlock) {
             const Rec e = stage[j];
-            const int r = e.sr & 255;
-            a.tmp[gb[r] + (j - ls[r])] = e;
+            const int b = (e.sr & 255) * kNSlabMax + slab_of(fine_bin(e.t, S.t0, S.inv_cbw, nf), S.cps);
+            a.tmp[gb[b] + (j - ls[b])] = e;
         }
         __syncthreads();
     }
@@ -304,81 +400,139 @@ void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s) {
 
 constexpr int kFineMax = kNcbMax * kFinePerCb;
 constexpr int kSortBlock = 1024;
+constexpr int kSortPer = kSortCap / kSortBlock;
+static_assert(kSortPer * kSortBlock == kSortCap, "the register sort holds kSortPer records per thread");
+static_assert(kSortCap <= 8192 && kNcbMax * kFinePerCb <= (1 << 18), "bin and rank share one int (18 + 13 bits)");
 
+// Exclusive scan of fh[0, nb) in place: each thread sums a contiguous run of
+// bins, then wave and workgroup prefixes of the runs.
+__device__ inline void lds_scan_excl(int32_t *fh, int nb, int32_t *wsum) {
+    const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63, w = tid >> 6, nw = bd >> 6;
+    const int per = (nb + bd - 1) / bd;
+    const int lo = min(tid * per, nb), hi = min(lo + per, nb);
+    int sum = 0;
+    for (int b = lo; b < hi; b++) sum += fh[b];
+    int x = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    if (tid < 64) {
+        const int u = tid < nw ? wsum[tid] : 0;
+        int z = u;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(z, off);
+            if (tid >= off) z += y;
+        }
+        if (tid < nw) wsum[tid] = z - u;
+    }
+    __syncthreads();
+    int run = wsum[w] + x - sum;
+    for (int b = lo; b < hi; b++) {
+        const int v = fh[b];
+        fh[b] = run;
+        run += v;
+    }
+    __syncthreads();
+}
+
+// One (row, slab) bucket at a time. A bucket of at most sort_cap clusters
+// is read once into registers; one LDS atomic per cluster gives both the
+// fine-bin histogram and the cluster's rank inside its bin, and after the
+// scan every record is written straight to its place (the writes stay in the
+// bucket's range, so partial lines merge in the cache). A larger bucket
+// takes two passes over global memory. Order inside a fine bin is arbitrary:
+// the neighbour tiles order each bin by y cell in LDS. The coarse bins of the
+// bucket get their offsets (and, when asked, the starts of their fine bins
+// 1..kFinePerCb-1, one byte each, 255: beyond a byte); the row's last bucket
+// also writes the row's end.
 __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ int32_t fh[kFineMax];
-    __shared__ int32_t part[kSortBlock];
+    __shared__ int32_t wsum[kSortBlock / 64];
     const int R = a.n_rows;
-    const int nseg = a.n_si * R;
+    const int nbk = a.n_si * R * kNSlabMax;
     const int tid = threadIdx.x, bd = blockDim.x;
-    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+    for (int bk = blockIdx.x; bk < nbk; bk += gridDim.x) {
+        const int seg = bk / kNSlabMax, slab = bk - seg * kNSlabMax;
         const int si = seg / R;
-        const SiState s = a.st[si];
-        const int n = a.rcnt[seg];
-        const int start = s.sbase + a.rstart[seg];
-        const int ncb = s.ncb, nf = ncb * kFinePerCb;
-        const float t0 = s.t0, inv = s.inv_cbw;
+        const SiState S = a.st[si];
+        const int ncb = S.ncb, cps = S.cps;
+        const int ns = (ncb + cps - 1) / cps;
+        if (slab >= ns) continue;
+        const int cb0 = slab * cps, cb1 = min(cb0 + cps, ncb);
+        const int f0 = cb0 * kFinePerCb, nb = (cb1 - cb0) * kFinePerCb, nf = ncb * kFinePerCb;
+        const int n = a.bcnt[bk];
+        const int start = S.sbase + a.bstart[bk];
         int32_t *co = a.coff + (int64_t)seg * (kNcbMax + 1);
         uint32_t *fo = a.foff ? a.foff + (int64_t)seg * kNcbMax : nullptr;
         if (n == 0) {
-            for (int cb = tid; cb <= ncb; cb += bd) co[cb] = start;
-            if (fo)
-                for (int cb = tid; cb < ncb; cb += bd) fo[cb] = 0u;
+            for (int cb = cb0 + tid; cb < cb1; cb += bd) {
+                co[cb] = start;
+                if (fo) fo[cb] = 0u;
+            }
+            if (slab == ns - 1 && tid == 0) co[ncb] = start;
             continue;
         }
-        for (int b = tid; b < nf; b += bd) fh[b] = 0;
+        for (int b = tid; b < nb; b += bd) fh[b] = 0;
         __syncthreads();
-        for (int k = tid; k < n; k += bd) atomicAdd(&fh[fine_bin(a.tmp[start + k].t, t0, inv, nf)], 1);
-        __syncthreads();
-        // exclusive scan of fh[0, nf)
-        const int per = (nf + bd - 1) / bd;
-        const int lo = min(tid * per, nf), hi = min(lo + per, nf);
-        int sum = 0;
-        for (int b = lo; b < hi; b++) sum += fh[b];
-        part[tid] = sum;
-        __syncthreads();
-        for (int off = 1; off < bd; off <<= 1) {
-            const int x = (tid >= off) ? part[tid - off] : 0;
-            __syncthreads();
-            part[tid] += x;
-            __syncthreads();
+        const bool fast = n <= a.sort_cap;   // uniform
+        Rec e[kSortPer];
+        int lr[kSortPer];   // local fine bin << 13 | rank inside the bin (-1: none)
+        if (fast) {
+#pragma unroll
+            for (int j = 0; j < kSortPer; j++) {
+                const int k = tid + j * bd;
+                if (k < n) e[j] = a.tmp[start + k];
+            }
+#pragma unroll
+            for (int j = 0; j < kSortPer; j++) {
+                lr[j] = -1;
+                if (tid + j * bd < n) {
+                    const int l = min(max(fine_bin(e[j].t, S.t0, S.inv_cbw, nf) - f0, 0), nb - 1);
+                    lr[j] = (l << 13) | atomicAdd(&fh[l], 1);
+                }
+            }
+        } else {
+            for (int k = tid; k < n; k += bd)
+                atomicAdd(&fh[min(max(fine_bin(a.tmp[start + k].t, S.t0, S.inv_cbw, nf) - f0, 0), nb - 1)], 1);
         }
-        int run = part[tid] - sum;
-        for (int b = lo; b < hi; b++) {
-            const int v = fh[b];
-            fh[b] = run;
-            run += v;
-        }
         __syncthreads();
-        for (int cb = tid; cb <= ncb; cb += bd) co[cb] = start + (cb < ncb ? fh[cb * kFinePerCb] : n);
-        if (fo) {
-            // the fine-bin starts of each coarse bin (for searches that read
-            // the sorted space directly)
-            for (int cb = tid; cb < ncb; cb += bd) {
-                const int b0 = fh[cb * kFinePerCb];
+        lds_scan_excl(fh, nb, wsum);
+        for (int cb = cb0 + tid; cb < cb1; cb += bd) {
+            const int b0 = fh[(cb - cb0) * kFinePerCb];
+            co[cb] = start + b0;
+            if (fo) {
                 uint32_t packed = 0u;
 #pragma unroll
                 for (int k = 1; k < kFinePerCb; k++)
-                    packed |= (uint32_t)min(fh[cb * kFinePerCb + k] - b0, 255) << (8 * (k - 1));
+                    packed |= (uint32_t)min(fh[(cb - cb0) * kFinePerCb + k] - b0, 255) << (8 * (k - 1));
                 fo[cb] = packed;
             }
         }
-        __syncthreads();
-        // counting-sort scatter by fine bin (order inside a bin is arbitrary:
-        // the neighbour tiles order each bin by y cell in LDS)
-        for (int k = tid; k < n; k += bd) {
-            const Rec e = a.tmp[start + k];
-            a.rec[start + atomicAdd(&fh[fine_bin(e.t, t0, inv, nf)], 1)] = e;
+        if (slab == ns - 1 && tid == 0) co[ncb] = start + n;
+        if (fast) {
+#pragma unroll
+            for (int j = 0; j < kSortPer; j++)
+                if (lr[j] >= 0) a.rec[start + fh[lr[j] >> 13] + (lr[j] & 8191)] = e[j];
+        } else {
+            __syncthreads();   // the offsets above have read fh; it now becomes the cursors
+            for (int k = tid; k < n; k += bd) {
+                const Rec r = a.tmp[start + k];
+                const int l = min(max(fine_bin(r.t, S.t0, S.inv_cbw, nf) - f0, 0), nb - 1);
+                a.rec[start + atomicAdd(&fh[l], 1)] = r;
+            }
         }
         __syncthreads();
     }
 }
 
 void launch_grid_rowsort(const KArgs &a, Launch l, hipStream_t s) {
-    const int nseg = a.n_si * a.n_rows;
-    if (nseg > 0)
-        hipLaunchKernelGGL(k_rowsort, dim3(min(l.grid, nseg)), dim3(kSortBlock), 0, s, a);
+    const int nbk = a.n_si * a.n_rows * kNSlabMax;
+    if (nbk > 0)
+        hipLaunchKernelGGL(k_rowsort, dim3(min(l.grid, nbk)), dim3(kSortBlock), 0, s, a);
 }
 
 }  // namespace tpcca

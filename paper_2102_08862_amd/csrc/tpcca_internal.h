@@ -20,6 +20,9 @@ constexpr int kTileCap = 3072;     // clusters a tile stages in LDS (own rows, +
 constexpr int kPrCap = 2944;       // the same for the pruned search (its LDS also holds the pair lists)
 constexpr int kMaxYCells = 32;     // y cells per pad row in the row order
 constexpr int kChunk = 8192;       // clusters per histogram / scatter work item
+constexpr int kNSlabMax = 8;       // time slabs per pad row in the row sort's buckets
+constexpr int kSlabTarget = 4096;  // clusters a (row, slab) bucket should hold
+constexpr int kSortCap = 8192;     // most clusters a bucket sorts in registers (1024 threads x 8)
 constexpr int kScanItems = 2048;   // elements per block of the device-wide scans
 constexpr int kMaxStages = 16;
 constexpr int kLenBins = 256;      // chain lengths are < 256 (rows are uint8)
@@ -93,7 +96,7 @@ struct SiState {
     int32_t sbase;                 // first position of the sector in the sorted space
     int32_t trk_base, n_tracks;    // first global track slot, number of tracks
     int32_t cl_base, n_cl;         // first entry in the cluster lists, entries
-    int32_t pad[1];
+    int32_t cps;                   // coarse bins per time slab of the row sort's buckets
 };
 
 // Device counters of one run (zeroed at the start of the run).
@@ -197,9 +200,11 @@ struct KArgs {
     SiState *st;
     Counters *cnt;
     const int32_t *chunk;    // [2 * n_chunks] (si, start)
-    int32_t *rcnt;           // [n_si * n_rows]
-    int32_t *rstart;         // [n_si * n_rows] local exclusive prefix
-    int32_t *rcur;           // [n_si * n_rows]
+    int32_t *rcnt;           // [n_si * n_rows] clusters per row
+    int32_t *bcnt;           // [n_si * n_rows * kNSlabMax] clusters per (row, time slab) bucket
+    int32_t *bstart;         // [same] first position of the bucket within its sector
+    int32_t *bcur;           // [same] scatter cursor
+    int32_t sort_cap;        // buckets of at most this many clusters are sorted in registers
     int32_t *coff;           // [n_si * n_rows * (kNcbMax + 1)] global sorted positions
     int16_t *tstart;         // [n_si * n_rb * kNcbMax] first coarse bin of each tile
     int32_t *ntile;          // [n_si * n_rb + 1] tiles per (sector instance, row block)
@@ -324,7 +329,7 @@ struct Launch {
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 void launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStream_t s);
 void launch_grid_hist(const KArgs &a, Launch l, hipStream_t s);
-void launch_grid_setup(const KArgs &a, hipStream_t s);
+void launch_grid_setup(const KArgs &a, Launch l, hipStream_t s);
 void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s);
 void launch_grid_rowsort(const KArgs &a, Launch l, hipStream_t s);
 void launch_tiles(const KArgs &a, hipStream_t s);

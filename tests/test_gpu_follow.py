@@ -83,6 +83,21 @@ def test_single_sector(tp, x, seed):
     assert res["tracks"] > 50 and res["added"] > 0
 
 
+def test_row_sort_two_pass_path(tp, x):
+    """Every row-sort bucket sorted by the two-pass path (the fine-bin
+    starts the following reads come from it too): the oracle's results."""
+    fr = synth.generate("sector_300", seed=3)
+    row, y, t = fr.sector(0)
+    print("case follow sector_300 seed 3, two-pass row sort", flush=True)
+    trk = _tracker(tp)
+    trk.set_launch(4, 0, 1)
+    f = trk.add_frame()
+    trk.load_sector(f, 0, row, y, t, device=True)
+    trk.run(sync=True)
+    res = compare_follow(trk, f, 0, row, y, t, oracle_cfg(x))
+    assert res["tracks"] > 50 and res["added"] > 0
+
+
 def test_slice_1ms_sampled_sectors(tp, x):
     fr = synth.generate("slice_1ms", seed=2300)
     print("case follow slice_1ms seed 2300: %d clusters" % fr.n_clusters, flush=True)

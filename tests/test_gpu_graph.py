@@ -63,8 +63,9 @@ def test_launch_shapes_do_not_change_results(tp):
     f = base.load_frame_packed(fr)
     base.run(sync=True)
     ref = _outputs(base, f, sectors)
-    for stage, bpc, param in ((5, 1, 256), (5, 2, 1024), (5, 4, 3072), (4, 1, 0), (1, 2, 0), (6, 1, 0), (7, 2, 0), (10, 1, 0),
-                              (11, 4, 0), (3, 1, 0), (8, 1, 0)):
+    # (4, 1, 1) and (4, 2, 500): row-sort buckets take the two-pass path
+    for stage, bpc, param in ((5, 1, 256), (5, 2, 1024), (5, 4, 3072), (4, 1, 0), (4, 1, 1), (4, 2, 500), (1, 2, 0),
+                              (6, 1, 0), (7, 2, 0), (10, 1, 0), (11, 4, 0), (3, 1, 0), (8, 1, 0)):
         t = tp.Tracker()
         t.set_launch(stage, bpc, param)
         g = t.load_frame_packed(fr)
