@@ -585,7 +585,8 @@ __device__ inline uint32_t box_mask(const TileShared &T, int lo, int hi, int k0,
 
 // Best pair of the lane's own cluster (yi, ti) on staged rows jd / ju at gap
 // g (act: the lane has a cluster to search). bu/bd: sorted positions or -1.
-__device__ void flat_pair(const KArgs &a, const TileShared &T, const TileGeo &G, bool act, int jd, int ju, float yi,
+// Exact ties of the score are resolved on the input indices as they occur.
+__device__ void flat_pair_exact(const KArgs &a, const TileShared &T, const TileGeo &G, bool act, int jd, int ju, float yi,
                           float ti, float w, float wy, float wt, int &bu, int &bd) {
     const float st = slack(ti, wt);
     int dlo = 0, dhi = 0, ulo = 0, uhi = 0;
@@ -646,6 +647,77 @@ __device__ void flat_pair(const KArgs &a, const TileShared &T, const TileGeo &G,
     if (found) {
         bu = T.plo[ju] + (bpu - T.base[ju]);
         bd = T.plo[jd] + (bpd - T.base[jd]);
+    }
+}
+
+// The same search without the tie resolution in the loop: a lane only notes
+// (tied) that an accepted pair scored exactly its best so far. A lane that
+// never notes one has a unique minimum (of two pairs with the final minimal
+// score, the later visited finds the earlier as its best), so its result is
+// the exact one; the others search again with flat_pair_exact.
+__device__ void flat_pair_fast(const KArgs &a, const TileShared &T, const TileGeo &G, bool act, int jd, int ju,
+                               float yi, float ti, float w, float wy, float wt, int &bu, int &bd, bool &tied) {
+    const float st = slack(ti, wt);
+    int dlo = 0, dhi = 0, ulo = 0, uhi = 0;
+    if (act) {
+        const int f0 = fine_bin(__fsub_rn(__fsub_rn(ti, wt), st), G.t0, G.inv_cbw, G.nf) - G.fb0;
+        const int f1 = fine_bin(__fadd_rn(__fadd_rn(ti, wt), st), G.t0, G.inv_cbw, G.nf) - G.fb0;
+        bin_range(T, G, jd, f0, f1, dlo, dhi);
+        bin_range(T, G, ju, f0, f1, ulo, uhi);
+    }
+    const int maxd = wave_max_u(dhi - dlo), maxu = wave_max_u(uhi - ulo);
+    const float c2 = a.pair_c2;
+    bool found = false, tie = false;
+    float bc = 0.f;
+    int bpu = 0, bpd = 0;
+    for (int d0 = 0; d0 < maxd; d0 += 32) {
+        const uint32_t dm = box_mask<true>(T, dlo, dhi, d0, min(32, maxd - d0), yi, ti, wy, wt);
+        if (!__any(dm != 0u)) continue;
+        for (int u0 = 0; u0 < maxu; u0 += 32) {
+            const uint32_t um = dm ? box_mask<false>(T, ulo, uhi, u0, min(32, maxu - u0), yi, ti, wy, wt) : 0u;
+            const int nd = um ? __popc(dm) : 0, nu = __popc(um);
+            const int tot = nd * nu;
+            const int mt = wave_max_u(tot);
+            uint32_t dd = um ? dm : 0u, uu = um;
+            for (int k = 0; k < mt; k++) {
+                const bool v = k < tot;
+                const int pd = dlo + d0 + (v ? __builtin_ctz(dd) : 0);
+                const int pu = ulo + u0 + (v ? __builtin_ctz(uu) : 0);
+                const float2 ed = T.yt[v ? pd : 0];
+                const float2 eu = T.yt[v ? pu : 0];
+                const float c = pair_score(yi, ti, ed.x, ed.y, eu.x, eu.y, w);
+                const bool acc = v && c <= c2;
+                const bool better = acc && (!found || c < bc);
+                tie = tie || (acc && found && c == bc);
+                found = found || acc;
+                bc = better ? c : bc;
+                bpu = better ? pu : bpu;
+                bpd = better ? pd : bpd;
+                const uint32_t un = uu & (uu - 1u);
+                const bool wrap = un == 0u;
+                uu = wrap ? um : un;
+                dd = wrap ? (dd & (dd - 1u)) : dd;
+            }
+        }
+    }
+    tied = tie;
+    if (found) {
+        bu = T.plo[ju] + (bpu - T.base[ju]);
+        bd = T.plo[jd] + (bpd - T.base[jd]);
+    }
+}
+
+__device__ void flat_pair(const KArgs &a, const TileShared &T, const TileGeo &G, bool act, int jd, int ju, float yi,
+                          float ti, float w, float wy, float wt, int &bu, int &bd) {
+    bool tied = false;
+    flat_pair_fast(a, T, G, act, jd, ju, yi, ti, w, wy, wt, bu, bd, tied);
+    if (__any(tied)) {
+        int bu2 = -1, bd2 = -1;
+        flat_pair_exact(a, T, G, tied, jd, ju, yi, ti, w, wy, wt, bu2, bd2);
+        if (tied) {
+            bu = bu2;
+            bd = bd2;
+        }
     }
 }
 
