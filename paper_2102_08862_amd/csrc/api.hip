@@ -36,7 +36,7 @@ struct Layout {
     size_t inputs, st, cnt;
     // tables in the context's own device block (not in the arena)
     size_t si, chunk, row_x, w_tab, ycell, tab_bytes;
-    size_t rcnt, bcnt, bstart, bcur, coff;
+    size_t bcnt, bstart, bcur, coff;
     size_t tstart, ntile, tile_base, tiles, glb_tiles;
     int64_t tile_cap = 0;
     size_t tmp, rec, link, upc;
@@ -558,7 +558,6 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     }
     L.st = b.take(sizeof(SiState) * S);
     L.cnt = b.take(sizeof(Counters));
-    L.rcnt = b.take(sizeof(int32_t) * SR);
     L.bcnt = b.take(sizeof(int32_t) * SR * kNSlabMax);
     L.bstart = b.take(sizeof(int32_t) * SR * kNSlabMax);
     L.bcur = b.take(sizeof(int32_t) * SR * kNSlabMax);
@@ -729,7 +728,6 @@ static void bind_pointers(tpcca_ctx *c) {
     a.st = (SiState *)(A + L.st);
     a.cnt = (Counters *)(A + L.cnt);
     a.chunk = (const int32_t *)(D + L.chunk);
-    a.rcnt = (int32_t *)(A + L.rcnt);
     a.bcnt = (int32_t *)(A + L.bcnt);
     a.bstart = (int32_t *)(A + L.bstart);
     a.bcur = (int32_t *)(A + L.bcur);
@@ -802,14 +800,13 @@ static void enqueue_run(tpcca_ctx *c, hipStream_t s, bool tm, int slot) {
     };
     mark(st++);
     // reset: row counts, bitmap, assignment (fill kernels: graph-safe)
-    launch_fill_i32(a.rcnt, (int64_t)a.n_si * a.n_rows, 0, s);
     launch_fill_i32(a.bcnt, (int64_t)a.n_si * a.n_rows * kNSlabMax, 0, s);
     launch_fill_i32((int32_t *)a.bits, (int64_t)a.n_words + 1, 0, s);
     launch_fill_i32(a.asg_cnt, (int64_t)a.n_in / 16384 + 2, 0, s);
     mark(st++);
     launch_grid_hist(a, c->lc[1], s);  // also resets per-sector state and counters
     mark(st++);
-    launch_grid_setup(a, c->lc[1], s);
+    launch_grid_setup(a, s);
     mark(st++);
     launch_grid_scatter(a, c->lc[3], s);
     mark(st++);

@@ -5,18 +5,20 @@
 // later, so the layout cannot change any result.
 //
 // A row of a 10 ms frame holds tens of thousands of clusters, more than LDS
-// holds, so the scatter already splits every row into buckets of whole
-// coarse bins (time slabs of cps coarse bins, cps chosen per sector so that a
-// bucket holds about kSlabTarget clusters); the row sort then orders one
-// bucket at a time, its records in registers and its writes confined to the
-// bucket's range.
+// holds, so the histogram and the scatter already split every row into
+// buckets by time slab (floor(t / kSlabW), clamped; 4096 cm, a few thousand
+// clusters of a 10 ms frame row); the row sort then orders one bucket at a
+// time, its records in registers and its writes confined to the bucket's
+// range. The coarse bins are aligned so that each lies in one slab: their
+// width is a power of two (at most the slab width) and their origin a
+// multiple of it, which also makes every bin and slab index exact.
 //
 // Kernels (persistent, grid-stride over device-side work counts):
 //   k_si_init    reset per-sector state
-//   k_hist       per-chunk LDS row histogram + time range, validation
-//   k_si_rows    per sector: bin geometry and slab width
+//   k_hist       per-chunk LDS histogram of the (row, slab) buckets + time
+//                range, validation
+//   k_si_rows    per sector: bin geometry
 //   k_si_prefix  sorted-space base of every sector
-//   k_bhist      per-chunk LDS histogram of the (row, slab) buckets
 //   k_si_buckets per sector: bucket starts (row-major, slab-minor)
 //   k_scatter    scatter of clusters into their buckets (staged in LDS)
 //   k_rowsort    per bucket: counting sort by fine time bin; writes the
@@ -73,7 +75,7 @@ __global__ void k_si_init(KArgs a) {
 
 __global__ __launch_bounds__(256) void k_hist(KArgs a) {
     TPCCA_ABORT_GUARD(a);
-    __shared__ int32_t h[kMaxRows];
+    __shared__ int32_t h[kMaxRows * kNSlabMax];
     __shared__ uint32_t smin, smax;
     __shared__ int32_t sinv;
     const int R = a.n_rows;
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(256) void k_hist(KArgs a) {
         const int si = a.chunk[2 * c], start = a.chunk[2 * c + 1];
         const SiDesc d = a.si[si];
         const int end = min(start + kChunk, d.n);
-        for (int r = threadIdx.x; r < R; r += blockDim.x) h[r] = 0;
+        for (int k = threadIdx.x; k < R * kNSlabMax; k += blockDim.x) h[k] = 0;
         if (threadIdx.x == 0) {
             smin = 0xffffffffu;
             smax = 0u;
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(256) void k_hist(KArgs a) {
             const int r = d.row[i];
             const float y = d.y[i], t = d.t[i];
             if (valid_cluster(r, y, t, R)) {
-                atomicAdd(&h[r], 1);
+                atomicAdd(&h[r * kNSlabMax + slab_of_t(t)], 1);
                 const uint32_t k = fkey(t);
                 lmin = min(lmin, k);
                 lmax = max(lmax, k);
@@ -114,8 +116,9 @@ __global__ __launch_bounds__(256) void k_hist(KArgs a) {
             if (linv) atomicAdd(&sinv, linv);
         }
         __syncthreads();
-        for (int r = threadIdx.x; r < R; r += blockDim.x)
-            if (h[r]) atomicAdd(&a.rcnt[si * R + r], h[r]);
+        int32_t *g = a.bcnt + (int64_t)si * R * kNSlabMax;
+        for (int k = threadIdx.x; k < R * kNSlabMax; k += blockDim.x)
+            if (h[k]) atomicAdd(&g[k], h[k]);
         if (threadIdx.x == 0) {
             if (smax >= smin) {
                 atomicMin(&a.st[si].tmin_key, smin);
@@ -129,11 +132,15 @@ __global__ __launch_bounds__(256) void k_hist(KArgs a) {
 
 __global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
     __shared__ int32_t sc[256];
-    __shared__ int32_t smax;
     const int R = a.n_rows;
     const int r = threadIdx.x;
     for (int si = blockIdx.x; si < a.n_si; si += gridDim.x) {
-        const int v = (r < R) ? a.rcnt[si * R + r] : 0;
+        int v = 0;
+        if (r < R) {
+            const int32_t *c = a.bcnt + ((int64_t)si * R + r) * kNSlabMax;
+#pragma unroll
+            for (int k = 0; k < kNSlabMax; k++) v += c[k];
+        }
         sc[r] = v;
         __syncthreads();
         for (int off = 1; off < 256; off <<= 1) {
@@ -142,10 +149,6 @@ __global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
             sc[r] += x;
             __syncthreads();
         }
-        if (r == 0) smax = 0;
-        __syncthreads();
-        if (v) atomicMax(&smax, v);
-        __syncthreads();
         if (r == 0) {
             SiState s = a.st[si];
             const int nv = sc[255];
@@ -154,25 +157,27 @@ __global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
                 tmin = fkey_inv(s.tmin_key);
                 tmax = fkey_inv(s.tmax_key);
             }
+            // coarse bins: a power-of-two width, at least cbw_min and wide
+            // enough for kNcbMax - 4 bins to cover the range, from an origin
+            // that is a multiple of the width (exact bin indices, each bin
+            // inside one time slab)
             const float range = __fsub_rn(tmax, tmin);
-            float inv;
-            int ncb;
+            float cbw = 0.f, t0 = tmin;
+            int ncb = 1;
             if (__builtin_isfinite(range)) {
-                const float cbw = fmaxf(a.cbw_min, range / (float)(kNcbMax - 4));
-                inv = 1.0f / cbw;
-                ncb = (int)__fmul_rn(range, inv) + 1;
+                const float raw = fmaxf(a.cbw_min, range / (float)(kNcbMax - 4));
+                int e;
+                const float m = frexpf(raw, &e);   // raw = m * 2^e, m in [0.5, 1)
+                cbw = m == 0.5f ? raw : ldexpf(1.0f, e);
+                t0 = __fmul_rn(floorf(tmin / cbw), cbw);
+                ncb = (int)floorf((tmax - t0) / cbw) + 1;
                 ncb = min(max(ncb, 1), kNcbMax);
-            } else {
-                inv = 0.f;
-                ncb = 1;
             }
-            s.t0 = tmin;
-            s.inv_cbw = inv;
+            s.t0 = t0;
+            s.inv_cbw = cbw > 0.f ? 1.0f / cbw : 0.f;
             s.ncb = ncb;
             s.n_valid = nv;
-            // slabs of the fullest row hold about kSlabTarget clusters
-            const int ns = min(max((smax + kSlabTarget - 1) / kSlabTarget, 1), kNSlabMax);
-            s.cps = (ncb + ns - 1) / ns;
+            s.cps = (cbw > 0.f && cbw <= kSlabW) ? (int)(kSlabW / cbw) : 0;
             a.st[si] = s;
         }
         __syncthreads();
@@ -222,37 +227,6 @@ void launch_grid_hist(const KArgs &a, Launch l, hipStream_t s) {
         hipLaunchKernelGGL(k_hist, dim3(min(l.grid, a.n_chunks)), dim3(256), 0, s, a);
 }
 
-// Slab of a fine bin: whole coarse bins, cps of them per slab.
-__device__ inline int slab_of(int fine, int cps) { return fine / (cps * kFinePerCb); }
-
-// Clusters per (row, slab) bucket, one chunk of inputs at a time (the same
-// validation and fine bin as the scatter).
-__global__ __launch_bounds__(256) void k_bhist(KArgs a) {
-    TPCCA_ABORT_GUARD(a);
-    __shared__ int32_t h[kMaxRows * kNSlabMax];
-    const int R = a.n_rows, nb = R * kNSlabMax;
-    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
-        const int si = a.chunk[2 * c], start = a.chunk[2 * c + 1];
-        const SiDesc d = a.si[si];
-        const SiState S = a.st[si];
-        const int nf = S.ncb * kFinePerCb;
-        const int end = min(start + kChunk, d.n);
-        for (int k = threadIdx.x; k < nb; k += blockDim.x) h[k] = 0;
-        __syncthreads();
-        for (int i = start + threadIdx.x; i < end; i += blockDim.x) {
-            const int r = d.row[i];
-            const float y = d.y[i], t = d.t[i];
-            if (valid_cluster(r, y, t, R))
-                atomicAdd(&h[r * kNSlabMax + slab_of(fine_bin(t, S.t0, S.inv_cbw, nf), S.cps)], 1);
-        }
-        __syncthreads();
-        int32_t *g = a.bcnt + (int64_t)si * nb;
-        for (int k = threadIdx.x; k < nb; k += blockDim.x)
-            if (h[k]) atomicAdd(&g[k], h[k]);
-        __syncthreads();
-    }
-}
-
 // Bucket starts of every sector: exclusive prefix over (row, slab) in row
 // order, slab order within a row (so a row's buckets are contiguous and in
 // time order). 1024 threads, two buckets each.
@@ -296,10 +270,9 @@ __global__ __launch_bounds__(1024) void k_si_buckets(KArgs a) {
     }
 }
 
-void launch_grid_setup(const KArgs &a, Launch l, hipStream_t s) {
+void launch_grid_setup(const KArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_si_rows, dim3(min(a.n_si, 4096)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_si_prefix, dim3(1), dim3(1024), 0, s, a);
-    if (a.n_chunks > 0) hipLaunchKernelGGL(k_bhist, dim3(min(l.grid, a.n_chunks)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_si_buckets, dim3(min(a.n_si, 4096)), dim3(1024), 0, s, a);
 }
 
@@ -324,7 +297,6 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(KArgs a) {
         const int si = a.chunk[2 * c], i0 = a.chunk[2 * c + 1];
         const SiDesc d = a.si[si];
         const SiState S = a.st[si];
-        const int nf = S.ncb * kFinePerCb;
         const int i1 = min(i0 + kChunk, d.n);
         for (int k = tid; k < nbk; k += kScatterBlock) h[k] = 0;
         __syncthreads();
@@ -340,8 +312,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(KArgs a) {
                 const int r = d.row[i];
                 yy[k] = d.y[i];
                 tt[k] = d.t[i];
-                if (valid_cluster(r, yy[k], tt[k], R))
-                    bk[k] = r * kNSlabMax + slab_of(fine_bin(tt[k], S.t0, S.inv_cbw, nf), S.cps);
+                if (valid_cluster(r, yy[k], tt[k], R)) bk[k] = r * kNSlabMax + slab_of_t(tt[k]);
             }
         }
 #pragma unroll
@@ -387,7 +358,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(KArgs a) {
         const int nv = s_nv;
         for (int j = tid; j < nv; j += kScatterBlock) {
             const Rec e = stage[j];
-            const int b = (e.sr & 255) * kNSlabMax + slab_of(fine_bin(e.t, S.t0, S.inv_cbw, nf), S.cps);
+            const int b = (e.sr & 255) * kNSlabMax + slab_of_t(e.t);
             a.tmp[gb[b] + (j - ls[b])] = e;
         }
         __syncthreads();
@@ -460,11 +431,22 @@ __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
         const int si = seg / R;
         const SiState S = a.st[si];
         const int ncb = S.ncb, cps = S.cps;
-        const int ns = (ncb + cps - 1) / cps;
-        if (slab >= ns) continue;
-        const int cb0 = slab * cps, cb1 = min(cb0 + cps, ncb);
+        int cb0 = 0, cb1 = ncb, n = 0;
+        if (cps > 0) {
+            // slab s holds the coarse bins of [s, s + 1) * kSlabW (the first
+            // and the last slab also what the clamp puts there)
+            const int k0 = (int)__fmul_rn(S.t0, S.inv_cbw);   // the origin in bins (exact)
+            if (slab > 0) cb0 = min(max(slab * cps - k0, 0), ncb);
+            if (slab < kNSlabMax - 1) cb1 = min(max((slab + 1) * cps - k0, 0), ncb);
+            n = a.bcnt[bk];
+        } else {
+            // coarse bins wider than a slab: slab 0 sorts the whole row (its
+            // buckets are contiguous)
+            if (slab != 0) continue;
+            for (int k = 0; k < kNSlabMax; k++) n += a.bcnt[bk + k];
+        }
+        const bool last = cps == 0 || slab == kNSlabMax - 1;   // writes the row's end
         const int f0 = cb0 * kFinePerCb, nb = (cb1 - cb0) * kFinePerCb, nf = ncb * kFinePerCb;
-        const int n = a.bcnt[bk];
         const int start = S.sbase + a.bstart[bk];
         int32_t *co = a.coff + (int64_t)seg * (kNcbMax + 1);
         uint32_t *fo = a.foff ? a.foff + (int64_t)seg * kNcbMax : nullptr;
@@ -473,7 +455,7 @@ __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
                 co[cb] = start;
                 if (fo) fo[cb] = 0u;
             }
-            if (slab == ns - 1 && tid == 0) co[ncb] = start;
+            if (last && tid == 0) co[ncb] = start;
             continue;
         }
         for (int b = tid; b < nb; b += bd) fh[b] = 0;
@@ -512,7 +494,7 @@ __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
                 fo[cb] = packed;
             }
         }
-        if (slab == ns - 1 && tid == 0) co[ncb] = start + n;
+        if (last && tid == 0) co[ncb] = start + n;
         if (fast) {
 #pragma unroll
             for (int j = 0; j < kSortPer; j++)

@@ -21,7 +21,7 @@ constexpr int kPrCap = 2944;       // the same for the pruned search (its LDS al
 constexpr int kMaxYCells = 32;     // y cells per pad row in the row order
 constexpr int kChunk = 8192;       // clusters per histogram / scatter work item
 constexpr int kNSlabMax = 8;       // time slabs per pad row in the row sort's buckets
-constexpr int kSlabTarget = 4096;  // clusters a (row, slab) bucket should hold
+constexpr float kSlabW = 4096.0f;  // slab width in drift time (cm): slab = floor(t / kSlabW), clamped
 constexpr int kSortCap = 8192;     // most clusters a bucket sorts in registers (1024 threads x 8)
 constexpr int kScanItems = 2048;   // elements per block of the device-wide scans
 constexpr int kMaxStages = 16;
@@ -96,7 +96,8 @@ struct SiState {
     int32_t sbase;                 // first position of the sector in the sorted space
     int32_t trk_base, n_tracks;    // first global track slot, number of tracks
     int32_t cl_base, n_cl;         // first entry in the cluster lists, entries
-    int32_t cps;                   // coarse bins per time slab of the row sort's buckets
+    int32_t cps;                   // coarse bins per time slab (0: a coarse bin is wider than a slab,
+                                   // every row is sorted as one bucket)
 };
 
 // Device counters of one run (zeroed at the start of the run).
@@ -156,6 +157,13 @@ __device__ inline int fine_bin(float t, float t0, float inv_cbw, int nf) {
     return min(max((int)c, 0), nf - 1);
 }
 
+// Time slab of a cluster: floor(t / kSlabW) (exact: the width is a power of
+// two) clamped to [0, kNSlabMax).
+__device__ inline int slab_of_t(float t) {
+    const float v = fminf(fmaxf(__fmul_rn(t, 1.0f / kSlabW), 0.0f), (float)(kNSlabMax - 1));
+    return (int)v;
+}
+
 // A cluster in the sorted space: 16 bytes, one load per chain step.
 struct Rec {
     float y, t;
@@ -200,7 +208,6 @@ struct KArgs {
     SiState *st;
     Counters *cnt;
     const int32_t *chunk;    // [2 * n_chunks] (si, start)
-    int32_t *rcnt;           // [n_si * n_rows] clusters per row
     int32_t *bcnt;           // [n_si * n_rows * kNSlabMax] clusters per (row, time slab) bucket
     int32_t *bstart;         // [same] first position of the bucket within its sector
     int32_t *bcur;           // [same] scatter cursor
@@ -329,7 +336,7 @@ struct Launch {
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 void launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStream_t s);
 void launch_grid_hist(const KArgs &a, Launch l, hipStream_t s);
-void launch_grid_setup(const KArgs &a, Launch l, hipStream_t s);
+void launch_grid_setup(const KArgs &a, hipStream_t s);
 void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s);
 void launch_grid_rowsort(const KArgs &a, Launch l, hipStream_t s);
 void launch_tiles(const KArgs &a, hipStream_t s);
