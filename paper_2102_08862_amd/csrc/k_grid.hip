@@ -73,38 +73,64 @@ __global__ void k_si_init(KArgs a) {
     }
 }
 
+// Every workgroup takes a contiguous range of chunks (consecutive chunks
+// mostly belong to one sector) and keeps its LDS counts and time range until
+// the sector changes, so the flush to global memory happens about once per
+// (workgroup, sector); each thread loads kHistPer inputs before it counts
+// them.
+constexpr int kHistPer = 4;
+
 __global__ __launch_bounds__(256) void k_hist(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ int32_t h[kMaxRows * kNSlabMax];
     __shared__ uint32_t smin, smax;
     __shared__ int32_t sinv;
-    const int R = a.n_rows;
-    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
+    const int R = a.n_rows, nbk = R * kNSlabMax, bd = blockDim.x;
+    const int per = (a.n_chunks + gridDim.x - 1) / gridDim.x;
+    const int c0 = blockIdx.x * per, c1 = min(c0 + per, a.n_chunks);
+    for (int k = threadIdx.x; k < nbk; k += bd) h[k] = 0;
+    if (threadIdx.x == 0) {
+        smin = 0xffffffffu;
+        smax = 0u;
+        sinv = 0;
+    }
+    __syncthreads();
+    uint32_t lmin = 0xffffffffu, lmax = 0u;
+    int linv = 0;
+    for (int c = c0; c < c1; c++) {
         const int si = a.chunk[2 * c], start = a.chunk[2 * c + 1];
         const SiDesc d = a.si[si];
         const int end = min(start + kChunk, d.n);
-        for (int k = threadIdx.x; k < R * kNSlabMax; k += blockDim.x) h[k] = 0;
-        if (threadIdx.x == 0) {
-            smin = 0xffffffffu;
-            smax = 0u;
-            sinv = 0;
-        }
-        __syncthreads();
-        uint32_t lmin = 0xffffffffu, lmax = 0u;
-        int linv = 0;
-        for (int i = start + threadIdx.x; i < end; i += blockDim.x) {
-            const int r = d.row[i];
-            const float y = d.y[i], t = d.t[i];
-            if (valid_cluster(r, y, t, R)) {
-                atomicAdd(&h[r * kNSlabMax + slab_of_t(t)], 1);
-                const uint32_t k = fkey(t);
-                lmin = min(lmin, k);
-                lmax = max(lmax, k);
-            } else {
-                linv++;
+        for (int i0 = start + threadIdx.x; i0 < end; i0 += bd * kHistPer) {
+            int rr[kHistPer];
+            float yy[kHistPer], tt[kHistPer];
+#pragma unroll
+            for (int u = 0; u < kHistPer; u++) {
+                const int i = i0 + u * bd;
+                rr[u] = -1;
+                yy[u] = tt[u] = 0.f;
+                if (i < end) {
+                    rr[u] = d.row[i];
+                    yy[u] = d.y[i];
+                    tt[u] = d.t[i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kHistPer; u++) {
+                if (rr[u] < 0) continue;
+                if (valid_cluster(rr[u], yy[u], tt[u], R)) {
+                    atomicAdd(&h[rr[u] * kNSlabMax + slab_of_t(tt[u])], 1);
+                    const uint32_t k = fkey(tt[u]);
+                    lmin = min(lmin, k);
+                    lmax = max(lmax, k);
+                } else {
+                    linv++;
+                }
             }
         }
-        // wave reductions, then one LDS atomic per wave
+        // flush when the next chunk of this workgroup is another sector's
+        const bool flush = c + 1 == c1 || a.chunk[2 * (c + 1)] != si;   // uniform
+        if (!flush) continue;
         for (int off = 32; off > 0; off >>= 1) {
             lmin = min(lmin, (uint32_t)__shfl_xor((int)lmin, off));
             lmax = max(lmax, (uint32_t)__shfl_xor((int)lmax, off));
@@ -115,16 +141,24 @@ __global__ __launch_bounds__(256) void k_hist(KArgs a) {
             atomicMax(&smax, lmax);
             if (linv) atomicAdd(&sinv, linv);
         }
+        lmin = 0xffffffffu;
+        lmax = 0u;
+        linv = 0;
         __syncthreads();
-        int32_t *g = a.bcnt + (int64_t)si * R * kNSlabMax;
-        for (int k = threadIdx.x; k < R * kNSlabMax; k += blockDim.x)
+        int32_t *g = a.bcnt + (int64_t)si * nbk;
+        for (int k = threadIdx.x; k < nbk; k += bd) {
             if (h[k]) atomicAdd(&g[k], h[k]);
+            h[k] = 0;
+        }
         if (threadIdx.x == 0) {
             if (smax >= smin) {
                 atomicMin(&a.st[si].tmin_key, smin);
                 atomicMax(&a.st[si].tmax_key, smax);
             }
             if (sinv) atomicAdd(&a.cnt->n_invalid, sinv);
+            smin = 0xffffffffu;
+            smax = 0u;
+            sinv = 0;
         }
         __syncthreads();
     }
