@@ -319,62 +319,82 @@ constexpr int kScatterBlock = 1024;
 constexpr int kScatterPer = kChunk / kScatterBlock;
 constexpr int kScatterBk = kMaxRows * kNSlabMax;
 static_assert(kScatterPer * kScatterBlock == kChunk, "a chunk must split evenly over the workgroup");
+static_assert(kScatterBk <= 2 * kScatterBlock, "the bucket scan takes two buckets per thread");
 
 __global__ __launch_bounds__(kScatterBlock) void k_scatter(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ Rec stage[kChunk];
     __shared__ int32_t h[kScatterBk + 1], ls[kScatterBk + 1], gb[kScatterBk + 1];
+    __shared__ int32_t wsum[kScatterBlock / 64];
     __shared__ int32_t s_nv;
-    const int R = a.n_rows, tid = threadIdx.x;
-    const int nbk = R * kNSlabMax;
-    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
+    const int R = a.n_rows, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nbk = R * kNSlabMax;   // <= 2 * kScatterBlock
+    // the inputs of the workgroup's next chunk are loaded while the current
+    // one is written out
+    int rr[kScatterPer];
+    float yy[kScatterPer], tt[kScatterPer];
+    auto fetch = [&](int c) {
         const int si = a.chunk[2 * c], i0 = a.chunk[2 * c + 1];
         const SiDesc d = a.si[si];
-        const SiState S = a.st[si];
         const int i1 = min(i0 + kChunk, d.n);
-        for (int k = tid; k < nbk; k += kScatterBlock) h[k] = 0;
-        __syncthreads();
-        int bk[kScatterPer], rk[kScatterPer];
-        float yy[kScatterPer], tt[kScatterPer];
 #pragma unroll
         for (int k = 0; k < kScatterPer; k++) {
             const int i = i0 + k * kScatterBlock + tid;
-            bk[k] = -1;
-            yy[k] = 0.f;
-            tt[k] = 0.f;
+            rr[k] = -1;
+            yy[k] = tt[k] = 0.f;
             if (i < i1) {
-                const int r = d.row[i];
+                rr[k] = d.row[i];
                 yy[k] = d.y[i];
                 tt[k] = d.t[i];
-                if (valid_cluster(r, yy[k], tt[k], R)) bk[k] = r * kNSlabMax + slab_of_t(tt[k]);
             }
         }
+    };
+    if (blockIdx.x < a.n_chunks) fetch(blockIdx.x);
+    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
+        const int si = a.chunk[2 * c], i0 = a.chunk[2 * c + 1];
+        const SiState S = a.st[si];
+        for (int k = tid; k < nbk; k += kScatterBlock) h[k] = 0;
+        __syncthreads();
+        int bk[kScatterPer], rk[kScatterPer];
 #pragma unroll
-        for (int k = 0; k < kScatterPer; k++) rk[k] = bk[k] >= 0 ? atomicAdd(&h[bk[k]], 1) : 0;
+        for (int k = 0; k < kScatterPer; k++) {
+            bk[k] = rr[k] >= 0 && valid_cluster(rr[k], yy[k], tt[k], R) ? rr[k] * kNSlabMax + slab_of_t(tt[k]) : -1;
+            rk[k] = bk[k] >= 0 ? atomicAdd(&h[bk[k]], 1) : 0;
+        }
         __syncthreads();
         // one global range of every bucket (all reservations in flight at
-        // once) and the bucket starts inside the stage (one wave scans)
+        // once) and the bucket starts inside the stage (workgroup scan, two
+        // buckets per thread)
         {
             int32_t *cur = a.bcur + (int64_t)si * nbk;
             for (int k = tid; k < nbk; k += kScatterBlock) {
                 const int v = h[k];
                 gb[k] = v ? S.sbase + atomicAdd(&cur[k], v) : 0;
             }
-        }
-        if (tid < 64) {
-            int carry = 0;
-            for (int k0 = 0; k0 < nbk; k0 += 64) {
-                const int k = k0 + tid;
-                const int v = k < nbk ? h[k] : 0;
-                int x = v;
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int u = __shfl_up(x, off);
-                    if (tid >= off) x += u;
-                }
-                if (k < nbk) ls[k] = carry + x - v;
-                carry += __shfl(x, 63);
+            const int k0 = 2 * tid;
+            const int v0 = k0 < nbk ? h[k0] : 0, v1 = k0 + 1 < nbk ? h[k0 + 1] : 0;
+            const int v = v0 + v1;
+            int x = v;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int u = __shfl_up(x, off);
+                if (lane >= off) x += u;
             }
-            if (tid == 0) s_nv = carry;
+            if (lane == 63) wsum[w] = x;
+            __syncthreads();
+            if (tid < 64) {
+                const int u = tid < kScatterBlock / 64 ? wsum[tid] : 0;
+                int z = u;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int q = __shfl_up(z, off);
+                    if (tid >= off) z += q;
+                }
+                if (tid < kScatterBlock / 64) wsum[tid] = z - u;
+                if (tid == kScatterBlock / 64 - 1) s_nv = z;
+            }
+            __syncthreads();
+            const int e = wsum[w] + x - v;
+            if (k0 < nbk) ls[k0] = e;
+            if (k0 + 1 < nbk) ls[k0 + 1] = e + v0;
         }
         __syncthreads();
 #pragma unroll
@@ -389,6 +409,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(KArgs a) {
             }
         }
         __syncthreads();
+        if (c + gridDim.x < a.n_chunks) fetch(c + gridDim.x);
         const int nv = s_nv;
         for (int j = tid; j < nv; j += kScatterBlock) {
             const Rec e = stage[j];
