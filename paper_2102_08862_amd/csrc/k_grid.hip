@@ -199,7 +199,10 @@ __global__ __launch_bounds__(256) void k_si_rows(KArgs a) {
             float cbw = 0.f, t0 = tmin;
             int ncb = 1;
             if (__builtin_isfinite(range)) {
-                const float raw = fmaxf(a.cbw_min, range / (float)(kNcbMax - 4));
+                float raw = fmaxf(a.cbw_min, range / (float)(kNcbMax - 4));
+                // bins wider than a slab: every row is one bucket, so a row
+                // may have no more bins than a bucket's histogram holds
+                if (raw > kSlabW) raw = fmaxf(raw, range / (float)(kSortBins / kFinePerCb - 4));
                 int e;
                 const float m = frexpf(raw, &e);   // raw = m * 2^e, m in [0.5, 1)
                 cbw = m == 0.5f ? raw : ldexpf(1.0f, e);
@@ -424,7 +427,6 @@ void launch_grid_scatter(const KArgs &a, Launch l, hipStream_t s) {
     if (a.n_chunks > 0) hipLaunchKernelGGL(k_scatter, dim3(min(l.grid, a.n_chunks)), dim3(kScatterBlock), 0, s, a);
 }
 
-constexpr int kFineMax = kNcbMax * kFinePerCb;
 constexpr int kSortBlock = 1024;
 constexpr int kSortPer = kSortCap / kSortBlock;
 static_assert(kSortPer * kSortBlock == kSortCap, "the register sort holds kSortPer records per thread");
@@ -476,7 +478,7 @@ __device__ inline void lds_scan_excl(int32_t *fh, int nb, int32_t *wsum) {
 // also writes the row's end.
 __global__ __launch_bounds__(kSortBlock) void k_rowsort(KArgs a) {
     TPCCA_ABORT_GUARD(a);
-    __shared__ int32_t fh[kFineMax];
+    __shared__ int32_t fh[kSortBins];
     __shared__ int32_t wsum[kSortBlock / 64];
     const int R = a.n_rows;
     const int nbk = a.n_si * R * kNSlabMax;

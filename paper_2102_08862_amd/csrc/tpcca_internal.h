@@ -22,6 +22,9 @@ constexpr int kMaxYCells = 32;     // y cells per pad row in the row order
 constexpr int kChunk = 8192;       // clusters per histogram / scatter work item
 constexpr int kNSlabMax = 8;       // time slabs per pad row in the row sort's buckets
 constexpr float kSlabW = 4096.0f;  // slab width in drift time (cm): slab = floor(t / kSlabW), clamped
+constexpr int kSortBins = 2048;    // fine bins of one row-sort bucket: a slab holds kSlabW / cbw coarse
+                                   // bins of width cbw >= 8; a row sorted as one bucket, at most this many
+static_assert(kSortBins >= (int)kSlabW / 8 * kFinePerCb, "a slab's fine bins must fit the bucket histogram");
 constexpr int kSortCap = 8192;     // most clusters a bucket sorts in registers (1024 threads x 8)
 constexpr int kScanItems = 2048;   // elements per block of the device-wide scans
 constexpr int kMaxStages = 16;

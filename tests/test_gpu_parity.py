@@ -101,6 +101,32 @@ def test_degenerate_sectors(tp, x):
         compare_sector(trk, f, 0, row, y, t, oc)
 
 
+def test_wide_time_range(tp, x):
+    """Tracks near t = 0, a line at t = 1e6 and noise from t = -500 to
+    3e7: coarse bins wider than a row-sort time slab, so every row is sorted
+    as one bucket; and a range with negative times and the clamped slabs."""
+    fr = synth.generate("sector_300", seed=4)
+    r0, y0, t0 = fr.sector(0)
+    rng = np.random.default_rng(13)
+    rl = np.arange(10, 40, dtype=np.uint8)
+    yl = (0.25 * (x[rl] - x[10])).astype(np.float32)
+    tl = (1.0e6 + 0.5 * (x[rl] - x[10])).astype(np.float32)
+    n = 600
+    rn = rng.integers(0, 152, n).astype(np.uint8)
+    yn = rng.uniform(-30, 30, n).astype(np.float32)
+    tn = rng.uniform(-500, 3.0e7, n).astype(np.float32)
+    oc = oracle_cfg(x)
+    for name, parts in (("wide", ((r0, y0, t0), (rl, yl, tl), (rn, yn, tn))),
+                        ("negative", ((r0, y0, (t0 - 3000.0).astype(np.float32)), (rn[:50], yn[:50], tn[:50] * 0 - 400.0)))):
+        row = np.concatenate([p[0] for p in parts]).astype(np.uint8)
+        y = np.concatenate([p[1] for p in parts]).astype(np.float32)
+        t = np.concatenate([p[2] for p in parts]).astype(np.float32)
+        print("case", name, len(row), flush=True)
+        trk, f = _one_sector(tp, row, y, t)
+        res = compare_sector(trk, f, 0, row, y, t, oc)
+        print(res, flush=True)
+
+
 def test_dense_rows_overflow_lds(tp, x):
     """A hot spot with far more clusters per coarse bin than a neighbour tile
     can stage in LDS: those tiles are searched in global memory with the
