@@ -1236,17 +1236,18 @@ tpcca_status tpcca_find_collisions(tpcca_ctx *c, float gap_cm, int32_t min_clust
     }
     // group sums and counts after the bins
     const size_t o_sum = b.take(sizeof(double) * groups), o_gc = b.take(sizeof(int32_t) * groups),
-                 o_ga = b.take(sizeof(int32_t) * groups);
+                 o_ga = b.take(sizeof(int32_t) * groups), o_gm = b.take(sizeof(double) * groups);
     if (b.off > L.slot_bytes) return fail(c, TPCCA_ERR_CAPACITY, "collision groups exceed the scratch slot");
     ca.grp_sum = (double *)(X + o_sum);
     ca.grp_cnt = (int32_t *)(X + o_gc);
     ca.grp_att = (int32_t *)(X + o_ga);
+    ca.grp_mean = (double *)(X + o_gm);
     HIPCHK(c, hipMemcpyAsync(ca.grp_base, gb.data(), sizeof(int32_t) * sides, hipMemcpyHostToDevice, c->stream));
     launch_fill_i32((int32_t *)ca.grp_sum, 2 * groups, 0, c->stream);
     launch_fill_i32(ca.grp_cnt, groups, 0, c->stream);
     launch_fill_i32(ca.grp_att, groups, 0, c->stream);
     launch_t0_group(c->args, ca, c->stream);
-    launch_t0_attach(c->args, ca, c->stream);
+    launch_t0_attach(c->args, ca, (int)groups, c->stream);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "collision kernels");

@@ -15,8 +15,9 @@
 //
 //   k_t0_range   per (frame, side): smallest and largest anchor t0
 //   k_t0_bins    per anchor: count, smallest and largest t0 of its bin
-//   k_t0_scan    one wave per (frame, side): group number of every bin
+//   k_t0_scan    one workgroup per (frame, side): group number of every bin
 //   k_t0_group   per anchor: group number; per group: sum of t0 and count
+//   k_t0_mean    per group: mean t0 of its anchors
 //   k_t0_attach  per other track: nearest group time by binary search
 #include "tpcca_internal.h"
 
@@ -39,17 +40,39 @@ __device__ inline int bin_of(float t0, float lo, float inv_w) {
 
 }  // namespace
 
-// One block per sector instance.
+// One block per sector instance: the block's smallest and largest anchor
+// t0, then one atomic each.
 __global__ __launch_bounds__(256) void k_t0_range(KArgs a, CollArgs c) {
+    __shared__ uint32_t smin, smax;
     for (int si = blockIdx.x; si < a.n_si; si += gridDim.x) {
         const SiState S = a.st[si];
         const int h = side_of(a, si, c.n_sectors);
+        if (threadIdx.x == 0) {
+            smin = 0xffffffffu;
+            smax = 0u;
+        }
+        __syncthreads();
+        uint32_t lmin = 0xffffffffu, lmax = 0u;
         for (int k = threadIdx.x; k < S.n_tracks; k += blockDim.x) {
             const float t0 = a.trk_t0[S.trk_base + k];
             if (!anchor(a, c, S.trk_base + k, t0)) continue;
-            atomicMin(&c.range[2 * h], fkey(t0));
-            atomicMax(&c.range[2 * h + 1], fkey(t0));
+            lmin = min(lmin, fkey(t0));
+            lmax = max(lmax, fkey(t0));
         }
+        for (int off = 32; off > 0; off >>= 1) {
+            lmin = min(lmin, (uint32_t)__shfl_xor((int)lmin, off));
+            lmax = max(lmax, (uint32_t)__shfl_xor((int)lmax, off));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(&smin, lmin);
+            atomicMax(&smax, lmax);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && smin <= smax) {
+            atomicMin(&c.range[2 * h], smin);
+            atomicMax(&c.range[2 * h + 1], smax);
+        }
+        __syncthreads();
     }
 }
 
@@ -74,44 +97,97 @@ __global__ __launch_bounds__(256) void k_t0_bins(KArgs a, CollArgs c) {
     }
 }
 
-// One wave per (frame, side), 64 bins at a time: a non-empty bin opens a
-// group if the largest t0 of the previous non-empty bin lies more than the
-// gap below its smallest t0. bin_grp[b] = group number (-1: empty bin).
-__global__ __launch_bounds__(64) void k_t0_scan(CollArgs c) {
+// One workgroup of kScanWaves waves per (frame, side), each wave a
+// contiguous share of the bins, 64 at a time: a non-empty bin opens a group
+// if the largest t0 of the previous non-empty bin lies more than the gap
+// below its smallest t0. Three passes over a share: its last non-empty
+// bin's largest t0; the opens, given the carry from the shares before; the
+// group numbers, offset by the opens of the shares before.
+// bin_grp[b] = group number (-1: empty bin).
+constexpr int kScanWaves = 16;
+
+__global__ __launch_bounds__(64 * kScanWaves) void k_t0_scan(CollArgs c) {
+    __shared__ float s_last[kScanWaves];
+    __shared__ int s_any[kScanWaves], s_opens[kScanWaves];
     const int h = blockIdx.x;
     const int nb = c.nbins[h];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t *cnt = c.bin_cnt + c.bin_base[h];
     const uint32_t *bmin = c.bin_min + c.bin_base[h];
     const uint32_t *bmax = c.bin_max + c.bin_base[h];
     int32_t *grp = c.bin_grp + c.bin_base[h];
-    float prev_max = 0.f;   // largest t0 of the last non-empty bin so far (wave-uniform)
-    bool any = false;       // a non-empty bin has been seen
-    int groups = 0;         // groups opened so far
-    for (int b0 = 0; b0 < nb; b0 += 64) {
-        const int b = b0 + lane;
-        const bool ne = b < nb && cnt[b] > 0u;
-        const float mn = ne ? fkey_inv(bmin[b]) : 0.f, mx = ne ? fkey_inv(bmax[b]) : 0.f;
+    const int share = ((nb + kScanWaves - 1) / kScanWaves + 63) & ~63;
+    const int b0 = min(w * share, nb), b1 = min(b0 + share, nb);
+    // pass 1: the share's last non-empty bin
+    float last = 0.f;
+    bool any = false;
+    for (int k0 = b0; k0 < b1; k0 += 64) {
+        const int b = k0 + lane;
+        const bool ne = b < b1 && cnt[b] > 0u;
         const uint64_t m = __ballot(ne);
-        // the previous non-empty bin of this lane: the highest set lane below,
-        // else the carry from earlier chunks
-        const uint64_t below = m & ((1ull << lane) - 1ull);
-        const int src = below ? 63 - __builtin_clzll(below) : 0;
-        const float pm_lane = __shfl(mx, src);
-        const bool has_prev = below != 0ull || any;
-        const float pm = below ? pm_lane : prev_max;
-        const bool opens = ne && (!has_prev || __fsub_rn(mn, pm) > c.gap);
-        const uint64_t om = __ballot(opens);
-        const int g = groups + __popcll(om & ((2ull << lane) - 1ull)) - 1;
-        if (b < nb) grp[b] = ne ? g : -1;
         if (m) {
-            const int last = 63 - __builtin_clzll(m);
-            prev_max = __shfl(mx, last);
+            const float mx = ne ? fkey_inv(bmax[b]) : 0.f;
+            last = __shfl(mx, 63 - __builtin_clzll(m));
             any = true;
         }
-        groups += __popcll(om);
     }
-    if (lane == 0) c.n_groups[h] = groups;
+    if (lane == 0) {
+        s_last[w] = last;
+        s_any[w] = any;
+    }
+    __syncthreads();
+    // carry: the last non-empty bin of the shares before
+    bool have = false;
+    float carry = 0.f;
+    for (int v = w - 1; v >= 0; v--)
+        if (s_any[v]) {
+            have = true;
+            carry = s_last[v];
+            break;
+        }
+    // pass 2 counts the opens, pass 3 numbers the groups
+    int opens = 0;
+    for (int pass = 0; pass < 2; pass++) {
+        int base = 0;
+        if (pass == 1) {
+            for (int v = 0; v < w; v++) base += s_opens[v];
+        }
+        bool hv = have;
+        float pm_carry = carry;
+        int groups = base;
+        for (int k0 = b0; k0 < b1; k0 += 64) {
+            const int b = k0 + lane;
+            const bool ne = b < b1 && cnt[b] > 0u;
+            const float mn = ne ? fkey_inv(bmin[b]) : 0.f, mx = ne ? fkey_inv(bmax[b]) : 0.f;
+            const uint64_t m = __ballot(ne);
+            const uint64_t below = m & ((1ull << lane) - 1ull);
+            const int src = below ? 63 - __builtin_clzll(below) : 0;
+            const float pm_lane = __shfl(mx, src);
+            const bool has_prev = below != 0ull || hv;
+            const float pm = below ? pm_lane : pm_carry;
+            const bool op = ne && (!has_prev || __fsub_rn(mn, pm) > c.gap);
+            const uint64_t om = __ballot(op);
+            if (pass == 1 && b < b1) grp[b] = ne ? groups + __popcll(om & ((2ull << lane) - 1ull)) - 1 : -1;
+            if (m) {
+                pm_carry = __shfl(mx, 63 - __builtin_clzll(m));
+                hv = true;
+            }
+            groups += __popcll(om);
+        }
+        if (pass == 0) {
+            opens = groups;
+            if (lane == 0) s_opens[w] = opens;
+            __syncthreads();
+        } else if (w == kScanWaves - 1 && lane == 0) {
+            c.n_groups[h] = groups;
+        }
+    }
+}
+
+// Mean t0 of every group (after the group sums).
+__global__ __launch_bounds__(256) void k_t0_mean(CollArgs c, int n_groups_total) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_groups_total; g += gridDim.x * blockDim.x)
+        c.grp_mean[g] = c.grp_cnt[g] > 0 ? c.grp_sum[g] / (double)c.grp_cnt[g] : 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_t0_group(KArgs a, CollArgs c) {
@@ -146,8 +222,7 @@ __global__ __launch_bounds__(256) void k_t0_attach(KArgs a, CollArgs c) {
         const int h = side_of(a, si, c.n_sectors);
         const int ng = c.n_groups[h];
         if (ng <= 0) continue;
-        const double *sum = c.grp_sum + c.grp_base[h];
-        const int32_t *cnt = c.grp_cnt + c.grp_base[h];
+        const double *mean = c.grp_mean + c.grp_base[h];
         for (int k = threadIdx.x; k < S.n_tracks; k += blockDim.x) {
             const int g = S.trk_base + k;
             const float t0f = a.trk_t0[g];
@@ -156,11 +231,11 @@ __global__ __launch_bounds__(256) void k_t0_attach(KArgs a, CollArgs c) {
             int lo = 0, hi = ng;   // first group of mean >= v in [lo, hi]
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
-                if (sum[mid] / (double)cnt[mid] < v) lo = mid + 1;
+                if (mean[mid] < v) lo = mid + 1;
                 else hi = mid;
             }
             const int j0 = max(lo - 1, 0), j1 = min(lo, ng - 1);
-            const double d0 = fabs(v - sum[j0] / (double)cnt[j0]), d1 = fabs(v - sum[j1] / (double)cnt[j1]);
+            const double d0 = fabs(v - mean[j0]), d1 = fabs(v - mean[j1]);
             const int near = d0 <= d1 ? j0 : j1;
             const double d = d0 <= d1 ? d0 : d1;
             if (d <= (double)c.window) {
@@ -177,14 +252,16 @@ void launch_t0_range(const KArgs &a, const CollArgs &c, hipStream_t s) {
 
 void launch_t0_bins(const KArgs &a, const CollArgs &c, int n_sides, hipStream_t s) {
     if (a.n_si > 0) hipLaunchKernelGGL(k_t0_bins, dim3(min(a.n_si, 4096)), dim3(256), 0, s, a, c);
-    if (n_sides > 0) hipLaunchKernelGGL(k_t0_scan, dim3(n_sides), dim3(64), 0, s, c);
+    if (n_sides > 0) hipLaunchKernelGGL(k_t0_scan, dim3(n_sides), dim3(64 * kScanWaves), 0, s, c);
 }
 
 void launch_t0_group(const KArgs &a, const CollArgs &c, hipStream_t s) {
     if (a.n_si > 0) hipLaunchKernelGGL(k_t0_group, dim3(min(a.n_si, 4096)), dim3(256), 0, s, a, c);
 }
 
-void launch_t0_attach(const KArgs &a, const CollArgs &c, hipStream_t s) {
+void launch_t0_attach(const KArgs &a, const CollArgs &c, int n_groups_total, hipStream_t s) {
+    if (n_groups_total > 0)
+        hipLaunchKernelGGL(k_t0_mean, dim3(min((n_groups_total + 255) / 256, 4096)), dim3(256), 0, s, c, n_groups_total);
     if (a.n_si > 0) hipLaunchKernelGGL(k_t0_attach, dim3(min(a.n_si, 4096)), dim3(256), 0, s, a, c);
 }
 

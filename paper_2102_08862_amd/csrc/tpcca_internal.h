@@ -297,6 +297,7 @@ struct CollArgs {
     double *grp_sum;         // [groups] sum of the t0 of its anchors (null: first pass)
     int32_t *grp_cnt;        // [groups] anchors
     int32_t *grp_att;        // [groups] other tracks attached
+    double *grp_mean;        // [groups] mean t0 of the anchors
     int32_t *trk_group;      // [trk_cap] group within its side, -1: none
 };
 
@@ -371,6 +372,6 @@ void launch_si_clusters(const KArgs &a, hipStream_t s);
 void launch_t0_range(const KArgs &a, const CollArgs &c, hipStream_t s);
 void launch_t0_bins(const KArgs &a, const CollArgs &c, int n_sides, hipStream_t s);
 void launch_t0_group(const KArgs &a, const CollArgs &c, hipStream_t s);
-void launch_t0_attach(const KArgs &a, const CollArgs &c, hipStream_t s);
+void launch_t0_attach(const KArgs &a, const CollArgs &c, int n_groups_total, hipStream_t s);
 
 }  // namespace tpcca
