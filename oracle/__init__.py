@@ -432,6 +432,101 @@ def collision_assign(t0, n_clusters, gap: float, min_clusters: int, window: floa
     return group, mean, n_anchor, n_all
 
 
+# ---------------------------------------------------- sector merging
+MERGE_SIGMA = (0.5, 0.02, 0.5, 0.01)   # transverse miss (cm), direction (rad), time (cm), tau
+
+
+def sector_alpha(sector: int) -> float:
+    """Azimuth of a sector's centre (the local x axis): sectors k and k + 18
+    (A and C side) at ((k mod 18) + 1/2) 20 degrees."""
+    return ((sector % 18) + 0.5) * np.deg2rad(20.0)
+
+
+def merge_residuals(cfg: Config, A, B, dalpha: float):
+    """Residuals (R30) of track state B seen from the helix of track A, for
+    all pairs (rows A, columns B): B's reference point and direction are
+    rotated into A's frame (B's sector lies dalpha further in azimuth); on
+    A's circle (direction phi_A, curvature kappa = -kB q/pT) the point
+    nearest to B's lies at the turning angle theta = atan2(kappa a,
+    1 - kappa b), where (a, b) is B's point relative to A's along and across
+    A's direction, i.e. at transverse arc theta / kappa (a for a straight
+    track). Returned: the signed transverse miss (2 b - kappa (a^2 + b^2)) /
+    (1 + sqrt((kappa a)^2 + (1 - kappa b)^2)) (b for a straight track), B's
+    direction minus A's there (wrapped to (-pi, pi]), A's time there minus
+    B's, and tau_A - tau_B. A and B: dicts of x, y, t, sinphi, tau, qpt. FP64."""
+    ax, ay, at = (np.asarray(A[k], np.float64) for k in ("x", "y", "t"))
+    asp, atau, aq = (np.asarray(A[k], np.float64) for k in ("sinphi", "tau", "qpt"))
+    bx, by, bt = (np.asarray(B[k], np.float64) for k in ("x", "y", "t"))
+    bsp, btau = (np.asarray(B[k], np.float64) for k in ("sinphi", "tau"))
+    ca = np.sqrt(1.0 - asp * asp)
+    xb = bx * np.cos(dalpha) - by * np.sin(dalpha)
+    yb = bx * np.sin(dalpha) + by * np.cos(dalpha)
+    vx = xb[None, :] - ax[:, None]
+    vy = yb[None, :] - ay[:, None]
+    a = vx * ca[:, None] + vy * asp[:, None]
+    b = -vx * asp[:, None] + vy * ca[:, None]
+    k = (-2.99792458e-3 * cfg.bz * aq)[:, None]
+    th = np.arctan2(k * a, 1.0 - k * b)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        arc = np.where(k != 0.0, th / np.where(k != 0.0, k, 1.0), a)
+    h = np.sqrt((k * a) ** 2 + (1.0 - k * b) ** 2)
+    dr = (2.0 * b - k * (a * a + b * b)) / (1.0 + h)
+    dphi = np.arcsin(bsp)[None, :] + dalpha - (np.arcsin(asp)[:, None] + th)
+    dphi = np.arctan2(np.sin(dphi), np.cos(dphi))
+    dt = at[:, None] + atau[:, None] * arc - bt[None, :]
+    dtau = atau[:, None] - btau[None, :]
+    return dr, dphi, dt, dtau
+
+
+def merge_sectors(cfg: Config, tracks, min_clusters: int = 30, window: float = 8.0, d2_cut: float = 25.0,
+                  sectors=None):
+    """Sector merging of one frame (R30). tracks[s] for s = 0..35: dict of
+    the fitted parameters (x, y, t = fitted time at x, sinphi, tau, qpt),
+    status, n (clusters) and t0 of the sector's tracks. Eligible: status 0,
+    at least min_clusters clusters, finite t0. Sector k + 18 side has the
+    next sector (k + 1) mod 18 + 18 side, 20 degrees further. A pair
+    (A in s, B in next(s)) with |t0_A - t0_B| <= window is scored with
+    D2 = sum (residual / MERGE_SIGMA)^2 of merge_residuals(A, B) and is a
+    candidate if D2 <= d2_cut; it is merged if B is A's best candidate and A
+    is B's (least D2, then least index). Returns, per sector, int32 arrays
+    (next partner index in next(s), previous partner index in prev(s), -1
+    for none) and the D2 of each merged pair. sectors: only the pairs (s, next(s)) for s in it
+    (default: all)."""
+    sig = np.asarray(MERGE_SIGMA, np.float64)
+    nxt = [np.full(len(tracks[s]["status"]), -1, np.int32) for s in range(36)]
+    prv = [np.full(len(tracks[s]["status"]), -1, np.int32) for s in range(36)]
+    d2_pairs = []
+    for s in (range(36) if sectors is None else sectors):
+        side, kk = divmod(s, 18)
+        n = 18 * side + (kk + 1) % 18
+        A, B = tracks[s], tracks[n]
+        ea = np.nonzero((np.asarray(A["status"]) == 0) & (np.asarray(A["n"]) >= min_clusters)
+                        & np.isfinite(np.asarray(A["t0"], np.float64)))[0]
+        eb = np.nonzero((np.asarray(B["status"]) == 0) & (np.asarray(B["n"]) >= min_clusters)
+                        & np.isfinite(np.asarray(B["t0"], np.float64)))[0]
+        if len(ea) == 0 or len(eb) == 0:
+            continue
+        sub = lambda T, e: {k: np.asarray(T[k], np.float64)[e] for k in ("x", "y", "t", "sinphi", "tau", "qpt", "t0")}
+        a, b = sub(A, ea), sub(B, eb)
+        d2 = np.full((len(ea), len(eb)), np.inf)
+        for i0 in range(0, len(ea), 512):   # bounded memory
+            i1 = min(i0 + 512, len(ea))
+            r = merge_residuals(cfg, {k: v[i0:i1] for k, v in a.items()}, b, np.deg2rad(20.0))
+            v = sum((ri / si) ** 2 for ri, si in zip(r, sig))
+            near = np.abs(a["t0"][i0:i1, None] - b["t0"][None, :]) <= window
+            d2[i0:i1] = np.where(near & (v <= d2_cut), v, np.inf)
+        # best per row and per column: least D2, then least index (argmin takes the first)
+        best_b = np.argmin(d2, axis=1)
+        best_a = np.argmin(d2, axis=0)
+        for i in range(len(ea)):
+            j = best_b[i]
+            if np.isfinite(d2[i, j]) and best_a[j] == i:
+                nxt[s][ea[i]] = eb[j]
+                prv[n][eb[j]] = ea[i]
+                d2_pairs.append(d2[i, j])
+    return nxt, prv, np.asarray(d2_pairs)
+
+
 # ----------------------------------------------------------------- MLP
 MLP_IN, MLP_INP, MLP_H = 12, 16, 64
 MLP_NPARAM = MLP_H * MLP_INP + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1

@@ -1,0 +1,144 @@
+"""Pins of the oracle's sector merging (R30).
+
+The residuals are pinned by the generator's own helix code (an independent
+implementation of the trajectory): a particle's truth states in two
+adjacent sectors give zero residuals; by the straight-track limit; and by a
+scalar implementation that works from the circle's centre instead of the
+closed form. The selection (mutual best under the cut, least index on ties)
+is pinned by a pure-Python brute force."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_08862_amd import synth
+
+
+def _state(tr, sector, x):
+    """Truth state at row line x of a sector, if the particle crosses it on
+    the sector's own side of the membrane (z > 0 for sectors 0-17)."""
+    h = synth.helix_at(tr, sector, float(x), False)
+    if h is None:
+        return None
+    Y, z, sphi, arc, t, dtdl = h
+    if z * (1.0 if sector < 18 else -1.0) <= 0:
+        return None
+    return dict(x=float(x), y=Y, t=t, sinphi=sphi, tau=dtdl, qpt=tr[0] / tr[1])
+
+
+def test_truth_states_in_adjacent_sectors_match(geom, ocfg):
+    x = geom[0]
+    fr = synth.generate("slice_1ms", seed=2400, n_threads=8)
+    rng = np.random.default_rng(1)
+    done = 0
+    # pT >= 0.5 GeV: radius above 3 m, so two states of one sector pair lie
+    # within half a turn (the nearest point on the circle is defined modulo
+    # a turn, and a looper's states can be a turn apart)
+    for pid in rng.permutation(len(fr.tracks))[:8000]:
+        tr = fr.tracks[pid]
+        if tr[1] < 0.5:
+            continue
+        for s in range(36):
+            side, k = divmod(s, 18)
+            n = 18 * side + (k + 1) % 18
+            a = b = None
+            for r in range(151, -1, -10):
+                a = a or _state(tr, s, x[r])
+            for r in range(0, 152, 10):
+                b = b or _state(tr, n, x[r])
+            if a is None or b is None:
+                continue
+            A = {k_: np.array([v]) for k_, v in a.items()}
+            B = {k_: np.array([v]) for k_, v in b.items()}
+            dr, dphi, dt, dtau = (v[0, 0] for v in oracle.merge_residuals(ocfg, A, B, np.deg2rad(20.0)))
+            assert abs(dr) < 1e-6 and abs(dphi) < 1e-9 and abs(dt) < 1e-6 and dtau == 0.0, (pid, s, dr, dphi, dt)
+            done += 1
+            break
+        if done >= 200:
+            break
+    assert done >= 100
+
+
+def test_straight_track_limit(ocfg):
+    A = dict(x=np.array([100.0]), y=np.array([3.0]), t=np.array([50.0]), sinphi=np.array([0.3]),
+             tau=np.array([0.4]), qpt=np.array([0.0]))
+    B = dict(x=np.array([140.0]), y=np.array([-20.0]), t=np.array([61.0]), sinphi=np.array([0.1]),
+             tau=np.array([0.45]), qpt=np.array([1.0]))
+    dal = np.deg2rad(20.0)
+    dr, dphi, dt, dtau = (v[0, 0] for v in oracle.merge_residuals(ocfg, A, B, dal))
+    bx = 140.0 * np.cos(dal) + 20.0 * np.sin(dal)
+    by = 140.0 * np.sin(dal) - 20.0 * np.cos(dal)
+    c, s_ = np.sqrt(1 - 0.09), 0.3
+    along = (bx - 100.0) * c + (by - 3.0) * s_
+    across = -(bx - 100.0) * s_ + (by - 3.0) * c
+    assert abs(dr - across) < 1e-9
+    assert abs(dt - (50.0 + 0.4 * along - 61.0)) < 1e-9
+    assert abs(dphi - (np.arcsin(0.1) + dal - np.arcsin(0.3))) < 1e-12
+    assert abs(dtau - (-0.05)) < 1e-12
+
+
+def _residual_scalar(cfg, a, b, dal):
+    """From the circle's centre: the centre lies 1/kappa along A's left
+    normal; B's point, seen from the centre, sits at an angle from A's; the
+    arc is that angle over kappa, the miss the radius minus the distance."""
+    k = -2.99792458e-3 * cfg.bz * a["qpt"]
+    phi = np.arcsin(a["sinphi"])
+    bx = b["x"] * np.cos(dal) - b["y"] * np.sin(dal)
+    by = b["x"] * np.sin(dal) + b["y"] * np.cos(dal)
+    if k == 0.0:
+        along = (bx - a["x"]) * np.cos(phi) + (by - a["y"]) * np.sin(phi)
+        across = -(bx - a["x"]) * np.sin(phi) + (by - a["y"]) * np.cos(phi)
+        th, arc, miss = 0.0, along, across
+    else:
+        cx, cy = a["x"] - np.sin(phi) / k, a["y"] + np.cos(phi) / k
+        ang0 = np.arctan2(a["y"] - cy, a["x"] - cx)
+        ang1 = np.arctan2(by - cy, bx - cx)
+        th = np.arctan2(np.sin(ang1 - ang0), np.cos(ang1 - ang0))
+        arc = th / k
+        miss = np.sign(k) * (1.0 / abs(k) - np.hypot(bx - cx, by - cy))
+    dphi = np.arcsin(b["sinphi"]) + dal - (phi + th)
+    return (miss, np.arctan2(np.sin(dphi), np.cos(dphi)), a["t"] + a["tau"] * arc - b["t"], a["tau"] - b["tau"])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_merging_by_brute_force(ocfg, seed):
+    rng = np.random.default_rng(70 + seed)
+    tracks = []
+    for s in range(36):
+        m = int(rng.integers(0, 7))
+        tracks.append(dict(x=rng.uniform(90, 240, m), y=rng.uniform(-30, 30, m), t=rng.uniform(0, 60, m),
+                           sinphi=rng.uniform(-0.5, 0.5, m), tau=rng.uniform(-0.5, 0.5, m),
+                           qpt=rng.choice([0.0, 0.4, -0.7, 2.0], m), status=rng.choice([0, 0, 0, 2], m),
+                           n=rng.integers(20, 80, m), t0=np.round(rng.uniform(0, 30, m))))
+    cut = 1e9   # every pair in the window is a candidate: the selection decides
+    nxt, prv, _ = oracle.merge_sectors(ocfg, tracks, min_clusters=30, window=8.0, d2_cut=cut)
+    sig = oracle.MERGE_SIGMA
+    dal = np.deg2rad(20.0)
+    for s in range(36):
+        side, k = divmod(s, 18)
+        n = 18 * side + (k + 1) % 18
+        A, B = tracks[s], tracks[n]
+        el = lambda T, i: T["status"][i] == 0 and T["n"][i] >= 30
+        d2 = {}
+        for i in range(len(A["x"])):
+            for j in range(len(B["x"])):
+                if el(A, i) and el(B, j) and abs(A["t0"][i] - B["t0"][j]) <= 8.0:
+                    r = _residual_scalar(ocfg, {k_: A[k_][i] for k_ in A}, {k_: B[k_][j] for k_ in B}, dal)
+                    d2[(i, j)] = sum((ri / si) ** 2 for ri, si in zip(r, sig))
+        want = [-1] * len(A["x"])
+        for (i, j), v in d2.items():
+            bi = min((vv, jj) for (ii, jj), vv in d2.items() if ii == i)
+            bj = min((vv, ii) for (ii, jj), vv in d2.items() if jj == j)
+            if bi[1] == j and bj[1] == i:
+                want[i] = j
+        assert nxt[s].tolist() == want, (s, nxt[s], want)
+        for i, j in enumerate(want):
+            if j >= 0:
+                assert prv[n][j] == i
+    # the residuals themselves against the scalar form
+    a = {k_: tracks[0][k_][:3] for k_ in ("x", "y", "t", "sinphi", "tau", "qpt")}
+    b = {k_: tracks[1][k_][:3] for k_ in ("x", "y", "t", "sinphi", "tau", "qpt")}
+    R = oracle.merge_residuals(ocfg, a, b, dal)
+    for i in range(len(a["x"])):
+        for j in range(len(b["x"])):
+            r = _residual_scalar(ocfg, {k_: a[k_][i] for k_ in a}, {k_: b[k_][j] for k_ in b}, dal)
+            assert np.allclose([R[q][i, j] for q in range(4)], r, rtol=0, atol=1e-9)
