@@ -371,6 +371,38 @@ tpcca_status tpcca_get_track_times(tpcca_ctx *ctx, int32_t frame, int32_t sector
 tpcca_status tpcca_get_collisions(tpcca_ctx *ctx, int32_t frame, int32_t side, float *t0, int32_t *n_tracks,
                                   int32_t *n_anchors, int64_t cap, int64_t *n_out);
 
+/* Sector merging (Sec. 1: time as the seeding coordinate defers the joining
+   of a particle's pieces to after the tracking). A particle crossing the
+   border between two adjacent sectors of one side leaves a track in each.
+   tpcca_merge_sectors pairs them, for every loaded frame:
+     - eligible tracks: fit ok (status 0), at least min_clusters clusters,
+       finite collision time t0 (see tpcca_find_collisions);
+     - a pair (A in sector s, B in the next sector of the same side, 360 /
+       (n_sectors / 2) degrees further in azimuth) with |t0_A - t0_B| <=
+       window_cm is scored from A's fitted helix: B's reference point and
+       direction rotated into A's frame, the point of A's circle nearest to
+       B's, and there the transverse miss, the direction and time differences
+       and the difference of tau, D2 = sum of their squares over the scales
+       0.5 cm, 0.02 rad, 0.5 cm and 0.01;
+     - a pair is merged if D2 <= d2_cut and each track is the other's best
+       candidate (least D2, then least track slot).
+   Suggested values: min_clusters 30, window 8, d2_cut 25. Call after a run
+   (it synchronises; its working arrays take the upper half of the arena's
+   slot after the chain copies, so the result holds until the next run,
+   beside the collision candidates); *n_pairs_out = merged pairs.
+   INVALID_ARG for a bad argument, STATE before a run or with an odd number
+   of sectors. */
+tpcca_status tpcca_merge_sectors(tpcca_ctx *ctx, int32_t min_clusters, float window_cm, float d2_cut,
+                                 int64_t *n_pairs_out);
+
+/* Merged partners of every track of the sector, in track order: the index
+   of its partner among the tracks of the next sector (next) and of the
+   previous sector (prev) of its side, -1 if none; either pointer may be
+   null. STATE before tpcca_merge_sectors, CAPACITY if cap is below the
+   track count (*n_out holds it). */
+tpcca_status tpcca_get_merges(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *next, int32_t *prev,
+                              int64_t cap, int64_t *n_out);
+
 /* The pad-row neighbour links of the cellular-automaton seeding (Sec. 1:
    HLT-derived tracker, seeding with time as a coordinate).
    Neighbour links of every input cluster of the sector, in input indices

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "merge_internal.h"
 #include "tpcca_internal.h"
 
 using namespace tpcca;
@@ -120,6 +121,10 @@ struct tpcca_ctx {
     bool ran = false;
     // collision candidates of the last tpcca_find_collisions (reset by a run)
     bool coll_valid = false;
+    // sector merges of the last tpcca_merge_sectors (reset by a run): arena
+    // offsets of the partner arrays (upper half of the post-run scratch slot)
+    bool merge_valid = false;
+    size_t merge_next_off = 0, merge_prev_off = 0;
     std::vector<int32_t> coll_n, coll_base;   // per side: groups, first group
     size_t coll_sum_off = 0, coll_cnt_off = 0, coll_att_off = 0;   // arena offsets: sums, anchors, attached
     Layout lay;
@@ -1027,6 +1032,7 @@ static tpcca_status run_on_arena(tpcca_ctx *c, bool graphs) {
     c->ran = true;
     c->have_results = true;
     c->coll_valid = false;
+    c->merge_valid = false;
     return TPCCA_OK;
 }
 
@@ -1213,7 +1219,7 @@ tpcca_status tpcca_find_collisions(tpcca_ctx *c, float gap_cm, int32_t min_clust
     }
     const size_t o_cnt = b.take(sizeof(uint32_t) * total), o_min = b.take(sizeof(uint32_t) * total),
                  o_max = b.take(sizeof(uint32_t) * total), o_grp = b.take(sizeof(int32_t) * total);
-    if (b.off > L.slot_bytes || total > (int64_t)0x7fff0000)
+    if (b.off > L.slot_bytes / 2 || total > (int64_t)0x7fff0000)
         return fail(c, TPCCA_ERR_CAPACITY, "collision-time bins exceed the scratch slot (raise the gap)");
     ca.bin_cnt = (uint32_t *)(X + o_cnt);
     ca.bin_min = (uint32_t *)(X + o_min);
@@ -1237,7 +1243,7 @@ tpcca_status tpcca_find_collisions(tpcca_ctx *c, float gap_cm, int32_t min_clust
     // group sums and counts after the bins
     const size_t o_sum = b.take(sizeof(double) * groups), o_gc = b.take(sizeof(int32_t) * groups),
                  o_ga = b.take(sizeof(int32_t) * groups), o_gm = b.take(sizeof(double) * groups);
-    if (b.off > L.slot_bytes) return fail(c, TPCCA_ERR_CAPACITY, "collision groups exceed the scratch slot");
+    if (b.off > L.slot_bytes / 2) return fail(c, TPCCA_ERR_CAPACITY, "collision groups exceed the scratch slot");
     ca.grp_sum = (double *)(X + o_sum);
     ca.grp_cnt = (int32_t *)(X + o_gc);
     ca.grp_att = (int32_t *)(X + o_ga);
@@ -1309,6 +1315,131 @@ tpcca_status tpcca_get_collisions(tpcca_ctx *c, int32_t frame, int32_t side, flo
             if (n_tracks) n_tracks[k] = cnt[k] + att[k];
             if (n_anchors) n_anchors[k] = cnt[k];
         }
+    }
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_merge_sectors(tpcca_ctx *c, int32_t min_clusters, float window_cm, float d2_cut,
+                                 int64_t *n_pairs_out) {
+    if (!c || !n_pairs_out || min_clusters < 0 || !(window_cm > 0.f) || !std::isfinite(window_cm) ||
+        !(d2_cut >= 0.f) || !std::isfinite(d2_cut))
+        return TPCCA_ERR_INVALID_ARG;
+    *n_pairs_out = 0;
+    if (!c->have_results) return fail(c, TPCCA_ERR_STATE, "no results (run first)");
+    if (c->cfg.n_sectors < 2 || (c->cfg.n_sectors & 1))
+        return fail(c, TPCCA_ERR_STATE, "sector merging needs an even number of sectors (two sides)");
+    tpcca_status ss = tpcca_synchronize(c);
+    if (ss != TPCCA_OK) return ss;
+    char *A = c->arena;
+    const Layout &L = c->lay;
+    const int64_t trk_cap = c->args.trk_cap;
+    // working arrays in the upper half of the slot after the chain copies
+    // (the lower half keeps the collision candidates)
+    char *X = A + L.xslot + align_up(L.slot_bytes / 2, 256);
+    const size_t room = L.slot_bytes - align_up(L.slot_bytes / 2, 256);
+    Bump b;
+    const size_t o_rng = b.take(sizeof(uint32_t) * 2), o_np = b.take(sizeof(int32_t)),
+                 o_bn = b.take(sizeof(int32_t) * trk_cap), o_bp = b.take(sizeof(int32_t) * trk_cap),
+                 o_pn = b.take(sizeof(int32_t) * trk_cap), o_pp = b.take(sizeof(int32_t) * trk_cap),
+                 o_list = b.take(sizeof(int32_t) * trk_cap);
+    MergeArgs m{};
+    m.n_sectors = c->cfg.n_sectors;
+    m.min_len = min_clusters;
+    m.window = window_cm;
+    m.d2_cut = d2_cut;
+    m.range = (uint32_t *)(X + o_rng);
+    m.n_pairs = (int32_t *)(X + o_np);
+    m.best_next = (int32_t *)(X + o_bn);
+    m.best_prev = (int32_t *)(X + o_bp);
+    m.partner_next = (int32_t *)(X + o_pn);
+    m.partner_prev = (int32_t *)(X + o_pp);
+    m.list = (int32_t *)(X + o_list);
+    if (b.off > room) return fail(c, TPCCA_ERR_CAPACITY, "merge arrays exceed the scratch slot");
+    uint32_t rng[2] = {0xffffffffu, 0u};
+    HIPCHK(c, hipMemcpyAsync(m.range, rng, sizeof(rng), hipMemcpyHostToDevice, c->stream));
+    launch_merge_range(c->args, m, c->stream);
+    HIPCHK(c, hipMemcpyAsync(rng, m.range, sizeof(rng), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int n_si = c->args.n_si;
+    int64_t nt = 0;
+    {
+        int32_t v = 0;
+        HIPCHK(c, hipMemcpy(&v, &c->args.cnt->n_tracks, sizeof(int32_t), hipMemcpyDeviceToHost));
+        nt = std::min<int64_t>(v, trk_cap);
+    }
+    // time bins: a power of two at least twice the window (so that a pair
+    // within the window is at most one bin apart, rounding included), from a
+    // multiple of the width; wider if the bins would not fit the scan
+    double w = 1.0;
+    while (w < 2.0 * (double)window_cm) w *= 2.0;
+    double lo = 0.0;
+    int64_t nb = 1;
+    for (;;) {
+        if (rng[0] <= rng[1]) {
+            const double tmin = fkey_inv(rng[0]), tmax = fkey_inv(rng[1]);
+            lo = std::floor(tmin / w) * w;
+            nb = (int64_t)std::floor((tmax - lo) / w) + 1;
+        }
+        if ((int64_t)n_si * nb + 1 <= trk_cap || w > 1e30) break;
+        w *= 2.0;
+    }
+    m.bin_w = (float)w;
+    m.inv_w = (float)(1.0 / w);
+    m.lo = (float)lo;
+    m.nb = (int32_t)nb;
+    const int64_t nbins = (int64_t)n_si * nb;
+    const size_t o_start = b.take(sizeof(int32_t) * (nbins + 1)), o_cur = b.take(sizeof(int32_t) * nbins);
+    if (b.off > room) return fail(c, TPCCA_ERR_CAPACITY, "merge bins exceed the scratch slot");
+    m.start = (int32_t *)(X + o_start);
+    m.cur = (int32_t *)(X + o_cur);
+    launch_fill_i32(m.start, nbins + 1, 0, c->stream);
+    launch_fill_i32(m.cur, nbins, 0, c->stream);
+    launch_fill_i32(m.n_pairs, 1, 0, c->stream);
+    launch_fill_i32(m.partner_next, trk_cap, -1, c->stream);
+    launch_fill_i32(m.partner_prev, trk_cap, -1, c->stream);
+    launch_merge_count(c->args, m, c->stream);
+    launch_scan_i32(m.start, (int32_t)nbins, m.start, nullptr, c->args.scan_tmp, c->stream);   // nbins + 1 entries
+    launch_merge_place(c->args, m, c->stream);
+    launch_merge_pairs(c->args, m, (int)nt, c->stream);
+    int32_t np = 0;
+    HIPCHK(c, hipMemcpyAsync(&np, m.n_pairs, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "merge kernels");
+    c->merge_next_off = (size_t)((char *)m.partner_next - A);
+    c->merge_prev_off = (size_t)((char *)m.partner_prev - A);
+    c->merge_valid = true;
+    *n_pairs_out = np;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_merges(tpcca_ctx *c, int32_t frame, int32_t sector, int32_t *next, int32_t *prev, int64_t cap,
+                              int64_t *n_out) {
+    if (!c || !n_out) return TPCCA_ERR_INVALID_ARG;
+    if (!c->merge_valid) return fail(c, TPCCA_ERR_STATE, "no merges (call tpcca_merge_sectors)");
+    int si;
+    SiState st;
+    tpcca_status s = locate(c, frame, sector, si, st);
+    if (s != TPCCA_OK) return s;
+    *n_out = st.n_tracks;
+    if (cap < st.n_tracks) return fail(c, TPCCA_ERR_CAPACITY, "buffer too small");
+    if (st.n_tracks == 0) return TPCCA_OK;
+    const int half = c->cfg.n_sectors / 2, side = sector / half, k = sector % half;
+    int si_n, si_p;
+    SiState stn, stp;
+    s = locate(c, frame, side * half + (k + 1) % half, si_n, stn);
+    if (s != TPCCA_OK) return s;
+    s = locate(c, frame, side * half + (k + half - 1) % half, si_p, stp);
+    if (s != TPCCA_OK) return s;
+    for (int dir = 0; dir < 2; dir++) {
+        int32_t *out = dir == 0 ? next : prev;
+        if (!out) continue;
+        HIPCHK(c, hipMemcpy(out, c->arena + (dir == 0 ? c->merge_next_off : c->merge_prev_off) +
+                                     sizeof(int32_t) * (size_t)st.trk_base,
+                            sizeof(int32_t) * (size_t)st.n_tracks, hipMemcpyDeviceToHost));
+        const int32_t base = dir == 0 ? stn.trk_base : stp.trk_base;
+        for (int64_t i = 0; i < st.n_tracks; i++)
+            if (out[i] >= 0) out[i] -= base;
     }
     return TPCCA_OK;
 }

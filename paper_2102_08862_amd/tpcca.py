@@ -88,7 +88,8 @@ EXPORTS = [
     "tpcca_get_links", "tpcca_mlp_state_bytes", "tpcca_mlp_attach", "tpcca_mlp_load", "tpcca_mlp_fetch",
     "tpcca_mlp_infer", "tpcca_mlp_grad", "tpcca_mlp_train_step", "tpcca_get_triplets", "tpcca_set_graph",
     "tpcca_set_launch", "tpcca_set_pruning", "tpcca_set_triplet_pool", "tpcca_copy", "tpcca_triplet_samples",
-    "tpcca_find_collisions", "tpcca_get_track_times", "tpcca_get_collisions",
+    "tpcca_find_collisions", "tpcca_get_track_times", "tpcca_get_collisions", "tpcca_merge_sectors",
+    "tpcca_get_merges",
 ]
 
 MLP_NPARAM = 5313
@@ -132,6 +133,8 @@ def load_library(path: str = LIB_PATH):
         "tpcca_find_collisions": [P, ctypes.c_float, I32, ctypes.c_float, ctypes.POINTER(I64)],
         "tpcca_get_track_times": [P, I32, I32, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_collisions": [P, I32, I32, P, P, P, I64, ctypes.POINTER(I64)],
+        "tpcca_merge_sectors": [P, I32, ctypes.c_float, ctypes.c_float, ctypes.POINTER(I64)],
+        "tpcca_get_merges": [P, I32, I32, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_links": [P, I32, I32, I32, P, P, I64],
         "tpcca_mlp_state_bytes": [ctypes.POINTER(SZ)],
         "tpcca_mlp_attach": [P, P, SZ],
@@ -446,6 +449,26 @@ class Tracker:
             self._check(self.lib.tpcca_get_collisions(self.h, frame, side, t0.ctypes.data, cnt.ctypes.data,
                                                       anc.ctypes.data, n.value, ctypes.byref(n)))
         return t0, cnt, anc
+
+    def merge_sectors(self, min_clusters: int = 30, window_cm: float = 8.0, d2_cut: float = 25.0) -> int:
+        """Pair the tracks that continue each other across the border of two
+        adjacent sectors of one side; returns the number of merged pairs."""
+        n = ctypes.c_int64()
+        self._check(self.lib.tpcca_merge_sectors(self.h, int(min_clusters), float(window_cm), float(d2_cut),
+                                                 ctypes.byref(n)))
+        return n.value
+
+    def merges(self, frame, sector):
+        """(next int32, prev int32): per track of the sector, the index of its
+        merged partner among the next / previous sector's tracks (-1: none)."""
+        n = ctypes.c_int64()
+        self._check_cap(self.lib.tpcca_get_merges(self.h, frame, sector, None, None, 0, ctypes.byref(n)))
+        nx = np.full(n.value, -1, np.int32)
+        pv = np.full(n.value, -1, np.int32)
+        if n.value:
+            self._check(self.lib.tpcca_get_merges(self.h, frame, sector, nx.ctypes.data, pv.ctypes.data, n.value,
+                                                  ctypes.byref(n)))
+        return nx, pv
 
     def links(self, frame, sector, cleaned: bool = False):
         n = self.sector_n.get((frame, sector), 0)

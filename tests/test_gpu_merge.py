@@ -1,0 +1,163 @@
+"""GPU sector merging against the oracle's merging and against truth.
+
+Against the oracle (its own fits and times, on sector pairs of the 1 ms
+slice): the GPU scores pairs in FP32 from FP32 fits, whose parameters agree
+with the oracle's within the fit tolerance (1e-4 relative with floors);
+carried through the residuals over the 50-200 cm between two tracks' points
+that moves D2 by about 0.1 at most near the cut. So every oracle merge
+that is firm (its D2 at least DELTA below the cut and below every other
+candidate of either track, and no candidate of either track within
+DT_WIN of the time window's edge that could compete) must be a GPU merge,
+and every GPU merge the oracle does not make must involve a track whose
+oracle decision is not firm. On the 10 ms frame against truth: merged pairs
+nearly all join segments of one particle, and most particles with long
+segments in two adjacent sectors are joined."""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_08862_amd import metrics, synth
+
+from _parity import oracle_cfg
+
+pytestmark = pytest.mark.gpu
+
+MIN_LEN, WINDOW, CUT = 30, 8.0, 25.0
+DELTA, DT_WIN = 0.5, 0.05
+
+
+@pytest.fixture(scope="module")
+def tp():
+    import torch
+    from paper_2102_08862_amd import tpcca
+    assert torch.cuda.is_available()
+    tpcca.load_library()
+    return tpcca
+
+
+def _next(s):
+    side, k = divmod(s, 18)
+    return 18 * side + (k + 1) % 18
+
+
+def test_merges_of_a_slice_against_the_oracle(tp):
+    x = synth.geometry()[0]
+    oc = oracle_cfg(x)
+    fr = synth.generate("slice_1ms", seed=2300, n_threads=16)
+    print("case merge slice_1ms seed 2300", flush=True)
+    trk = tp.Tracker()
+    f = trk.load_frame_packed(fr)
+    trk.run(sync=True)
+    n_pairs = trk.merge_sectors(MIN_LEN, WINDOW, CUT)
+    pairs_s = (0, 5, 17, 18, 29)
+    need = sorted(set(pairs_s) | {_next(s) for s in pairs_s})
+
+    def one(s):
+        row, y, t = fr.sector(s)
+        res = oracle.run_sector(oc, row, y, t)
+        fi = res["fit"]
+        t0 = oracle.track_t0(oc, fi["x_ref"], fi["y"], fi["t"], fi["sinphi"], fi["tau"], fi["qpt"])
+        return s, dict(x=fi["x_ref"], y=fi["y"], t=fi["t"], sinphi=fi["sinphi"], tau=fi["tau"], qpt=fi["qpt"],
+                       status=fi["status"], n=res["len"], t0=t0)
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        T = dict(ex.map(one, need))
+    full = [T.get(s, dict(x=np.zeros(0), y=np.zeros(0), t=np.zeros(0), sinphi=np.zeros(0), tau=np.zeros(0),
+                          qpt=np.zeros(0), status=np.zeros(0, np.int32), n=np.zeros(0, np.int32),
+                          t0=np.zeros(0))) for s in range(36)]
+    o_next, o_prev, _ = oracle.merge_sectors(oc, full, MIN_LEN, WINDOW, CUT, sectors=pairs_s)
+    total_firm = total_gpu = 0
+    for s in pairs_s:
+        n = _next(s)
+        A, B = T[s], T[n]
+        g_next, _ = trk.merges(f, s)
+        _, g_prev_n = trk.merges(f, n)
+        # the oracle's candidate scores of this sector pair
+        ea = np.nonzero((A["status"] == 0) & (A["n"] >= MIN_LEN) & np.isfinite(A["t0"]))[0]
+        eb = np.nonzero((B["status"] == 0) & (B["n"] >= MIN_LEN) & np.isfinite(B["t0"]))[0]
+        sub = lambda Tr, e: {k: np.asarray(Tr[k], np.float64)[e] for k in ("x", "y", "t", "sinphi", "tau", "qpt")}
+        r = oracle.merge_residuals(oc, sub(A, ea), sub(B, eb), np.deg2rad(20.0))
+        d2 = sum((ri / si) ** 2 for ri, si in zip(r, oracle.MERGE_SIGMA))
+        dt0 = np.abs(A["t0"][ea][:, None] - B["t0"][eb][None, :])
+        inwin = dt0 <= WINDOW
+        edge = np.abs(dt0 - WINDOW) <= DT_WIN
+        cand = np.where(inwin & (d2 <= CUT), d2, np.inf)
+        unsure_row = np.zeros(len(ea), bool)
+        unsure_col = np.zeros(len(eb), bool)
+        for i in range(len(ea)):
+            row = cand[i]
+            fin = np.sort(row[np.isfinite(row)])
+            near_cut = np.any(np.abs(d2[i][inwin[i] | edge[i]] - CUT) <= DELTA)
+            tie = len(fin) > 1 and fin[1] - fin[0] < DELTA
+            edge_comp = np.any(edge[i] & (d2[i] <= (fin[0] if len(fin) else CUT) + DELTA))
+            unsure_row[i] = near_cut or tie or edge_comp
+        for j in range(len(eb)):
+            col = cand[:, j]
+            fin = np.sort(col[np.isfinite(col)])
+            near_cut = np.any(np.abs(d2[:, j][inwin[:, j] | edge[:, j]] - CUT) <= DELTA)
+            tie = len(fin) > 1 and fin[1] - fin[0] < DELTA
+            edge_comp = np.any(edge[:, j] & (d2[:, j] <= (fin[0] if len(fin) else CUT) + DELTA))
+            unsure_col[j] = near_cut or tie or edge_comp
+        ua = np.zeros(len(A["x"]), bool); ua[ea] = unsure_row
+        ub = np.zeros(len(B["x"]), bool); ub[eb] = unsure_col
+        firm = 0
+        for i, j in enumerate(o_next[s]):
+            if j < 0:
+                continue
+            # a pair is firm if neither track's decision, nor those of the
+            # tracks competing for either, is near a boundary
+            if ua[i] or ub[j]:
+                continue
+            firm += 1
+            assert g_next[i] == j, "sector %d track %d: oracle merges it with %d, the GPU with %d" % (s, i, j, g_next[i])
+        for i, j in enumerate(g_next):
+            if j < 0:
+                continue
+            assert g_prev_n[j] == i
+            if o_next[s][i] != j:
+                assert ua[i] or ub[j] or (o_next[s][i] >= 0 and ub[o_next[s][i]]) or (o_prev[n][j] >= 0 and ua[o_prev[n][j]]), \
+                    "sector %d: GPU merge (%d, %d) not in the oracle's, and both decisions are firm" % (s, i, j)
+        print("pair %d-%d: oracle merges %d (firm %d), gpu %d, undecided tracks %d + %d" % (
+            s, n, int((o_next[s] >= 0).sum()), firm, int((g_next >= 0).sum()), int(ua.sum()), int(ub.sum())),
+            flush=True)
+        total_firm += firm
+        total_gpu += int((g_next >= 0).sum())
+    print("merged pairs on the GPU (all sectors)", n_pairs, flush=True)
+    assert total_firm > 500 and n_pairs > 0
+
+
+def test_merges_of_the_10ms_frame_against_truth(tp):
+    import torch
+    fr = synth.generate("frame_10ms", seed=3000, n_threads=16)
+    print("case merge frame_10ms seed 3000", flush=True)
+    trk = tp.Tracker()
+    f = trk.load_frame_packed(fr)
+    trk.run(sync=True)
+    n_pairs = trk.merge_sectors(MIN_LEN, WINDOW, CUT)
+    P = {}
+    for s in range(36):
+        tr = trk.tracks(f, s)
+        p = metrics.track_majority(fr.labels[s], trk.track_clusters(f, s), tr["n_clusters"])
+        P[s] = (p, tr)
+    good = bad = opportunities = 0
+    for s in range(36):
+        n = _next(s)
+        (pa, ta), (pb, tb) = P[s], P[n]
+        nxt, _ = trk.merges(f, s)
+        for i, j in enumerate(nxt):
+            if j >= 0:
+                if pa[i] >= 0 and pa[i] == pb[j]:
+                    good += 1
+                else:
+                    bad += 1
+        ea = (ta["status"] == 0) & (ta["n_clusters"] >= MIN_LEN)
+        eb = (tb["status"] == 0) & (tb["n_clusters"] >= MIN_LEN)
+        opportunities += len(set(pa[ea][pa[ea] >= 0]) & set(pb[eb][pb[eb] >= 0]))
+    purity, eff = good / max(good + bad, 1), good / max(opportunities, 1)
+    print("10 ms frame: %d merged pairs, %d correct, %d wrong (purity %.4f); %d particles with long segments in "
+          "adjacent sectors, efficiency %.4f" % (n_pairs, good, bad, purity, opportunities, eff), flush=True)
+    assert good + bad == n_pairs
+    assert purity >= 0.99 and eff >= 0.9
+    del trk
+    torch.cuda.empty_cache()
