@@ -397,6 +397,48 @@ def collisions_leg(trk, fr, f, log, quality=True):
     return out
 
 
+def merge_leg(trk, fr, f, log, quality=True):
+    """Sector merging after the plain run: the time of merge_sectors (wall
+    clock; it synchronises) and, against the generator's truth, the share of
+    merged pairs that join one particle's segments (purity) and of the
+    particles with long segments in two adjacent sectors that are joined
+    (efficiency)."""
+    from paper_2102_08862_amd import metrics
+    min_len, window, cut = 30, 8.0, 25.0
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        n_pairs = trk.merge_sectors(min_len, window, cut)
+        ts.append(time.perf_counter() - t0)
+    out = {"min_clusters": min_len, "window_cm": window, "d2_cut": cut, "pairs": int(n_pairs),
+           "ms": round(1e3 * float(np.median(ts)), 4)}
+    if quality:
+        ns = len(fr.rows)
+        half = ns // 2
+        P = {}
+        for s in range(ns):
+            tr = trk.tracks(f, s)
+            P[s] = (metrics.track_majority(fr.labels[s], trk.track_clusters(f, s), tr["n_clusters"]), tr)
+        good = bad = opp = 0
+        for s in range(ns):
+            side, k = divmod(s, half)
+            n = side * half + (k + 1) % half
+            (pa, ta), (pb, tb) = P[s], P[n]
+            nxt, _ = trk.merges(f, s)
+            for i, j in enumerate(nxt):
+                if j >= 0:
+                    good += int(pa[i] >= 0 and pa[i] == pb[j])
+                    bad += int(not (pa[i] >= 0 and pa[i] == pb[j]))
+            ea = (ta["status"] == 0) & (ta["n_clusters"] >= min_len)
+            eb = (tb["status"] == 0) & (tb["n_clusters"] >= min_len)
+            opp += len(set(pa[ea][pa[ea] >= 0]) & set(pb[eb][pb[eb] >= 0]))
+        out["purity"] = round(good / max(good + bad, 1), 5)
+        out["efficiency"] = round(good / max(opp, 1), 5)
+    log("merge: %d pairs in %.3f ms; %s" % (out["pairs"], out["ms"],
+                                            {k: out[k] for k in ("purity", "efficiency") if k in out}))
+    return out
+
+
 def follow_leg(fr, args, log, q_plain, tuning_on, sector):
     """The tracker with track following (chain extension and shared-cluster
     selection before the fit) on the same frame, timed like the plain one;
@@ -582,6 +624,7 @@ def main():
 
     q_plain = None if args.no_quality else frame_quality(trk, fr, f)
     collisions = collisions_leg(trk, fr, f, log, quality=not args.no_quality)
+    merge = merge_leg(trk, fr, f, log, quality=not args.no_quality)
     pruned = None
     if not args.no_pruned:
         pruned = pruned_leg(trk, fr, f, args, log, q_plain)
@@ -617,6 +660,7 @@ def main():
         "pruned": pruned,
         "follow": follow,
         "collisions": collisions,
+        "merge": merge,
         "cpu_baseline": cpu,
         "counts": {k: int(st[k]) for k in ("n_links", "n_seeds", "n_tracks", "n_track_clusters", "n_invalid",
                                             "n_overflow_tiles", "n_tiles")},

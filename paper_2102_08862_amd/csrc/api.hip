@@ -1338,10 +1338,7 @@ tpcca_status tpcca_merge_sectors(tpcca_ctx *c, int32_t min_clusters, float windo
     char *X = A + L.xslot + align_up(L.slot_bytes / 2, 256);
     const size_t room = L.slot_bytes - align_up(L.slot_bytes / 2, 256);
     Bump b;
-    const size_t o_rng = b.take(sizeof(uint32_t) * 2), o_np = b.take(sizeof(int32_t)),
-                 o_bn = b.take(sizeof(int32_t) * trk_cap), o_bp = b.take(sizeof(int32_t) * trk_cap),
-                 o_pn = b.take(sizeof(int32_t) * trk_cap), o_pp = b.take(sizeof(int32_t) * trk_cap),
-                 o_list = b.take(sizeof(int32_t) * trk_cap);
+    const size_t o_rng = b.take(sizeof(uint32_t) * 2), o_np = b.take(sizeof(int32_t));
     MergeArgs m{};
     m.n_sectors = c->cfg.n_sectors;
     m.min_len = min_clusters;
@@ -1349,12 +1346,6 @@ tpcca_status tpcca_merge_sectors(tpcca_ctx *c, int32_t min_clusters, float windo
     m.d2_cut = d2_cut;
     m.range = (uint32_t *)(X + o_rng);
     m.n_pairs = (int32_t *)(X + o_np);
-    m.best_next = (int32_t *)(X + o_bn);
-    m.best_prev = (int32_t *)(X + o_bp);
-    m.partner_next = (int32_t *)(X + o_pn);
-    m.partner_prev = (int32_t *)(X + o_pp);
-    m.list = (int32_t *)(X + o_list);
-    if (b.off > room) return fail(c, TPCCA_ERR_CAPACITY, "merge arrays exceed the scratch slot");
     uint32_t rng[2] = {0xffffffffu, 0u};
     HIPCHK(c, hipMemcpyAsync(m.range, rng, sizeof(rng), hipMemcpyHostToDevice, c->stream));
     launch_merge_range(c->args, m, c->stream);
@@ -1367,11 +1358,11 @@ tpcca_status tpcca_merge_sectors(tpcca_ctx *c, int32_t min_clusters, float windo
         HIPCHK(c, hipMemcpy(&v, &c->args.cnt->n_tracks, sizeof(int32_t), hipMemcpyDeviceToHost));
         nt = std::min<int64_t>(v, trk_cap);
     }
-    // time bins: a power of two at least twice the window (so that a pair
-    // within the window is at most one bin apart, rounding included), from a
-    // multiple of the width; wider if the bins would not fit the scan
+    // time bins: the smallest power of two >= the window, from a multiple
+    // of the width (exact bin indices); wider if the bins would not fit the
+    // scan
     double w = 1.0;
-    while (w < 2.0 * (double)window_cm) w *= 2.0;
+    while (w < (double)window_cm) w *= 2.0;
     double lo = 0.0;
     int64_t nb = 1;
     for (;;) {
@@ -1388,19 +1379,32 @@ tpcca_status tpcca_merge_sectors(tpcca_ctx *c, int32_t min_clusters, float windo
     m.lo = (float)lo;
     m.nb = (int32_t)nb;
     const int64_t nbins = (int64_t)n_si * nb;
-    const size_t o_start = b.take(sizeof(int32_t) * (nbins + 1)), o_cur = b.take(sizeof(int32_t) * nbins);
-    if (b.off > room) return fail(c, TPCCA_ERR_CAPACITY, "merge bins exceed the scratch slot");
+    const int64_t ntr = std::max<int64_t>(nt, 1);
+    const size_t o_bn = b.take(sizeof(int32_t) * ntr), o_bp = b.take(sizeof(int32_t) * ntr),
+                 o_pn = b.take(sizeof(int32_t) * ntr), o_pp = b.take(sizeof(int32_t) * ntr),
+                 o_list = b.take(sizeof(int32_t) * ntr), o_mst = b.take(2 * sizeof(float4) * ntr),
+                 o_start = b.take(sizeof(int32_t) * (nbins + 1)), o_cur = b.take(sizeof(int32_t) * nbins);
+    if (b.off > room) return fail(c, TPCCA_ERR_CAPACITY, "merge arrays exceed the scratch slot");
+    m.best_next = (int32_t *)(X + o_bn);
+    m.best_prev = (int32_t *)(X + o_bp);
+    m.partner_next = (int32_t *)(X + o_pn);
+    m.partner_prev = (int32_t *)(X + o_pp);
+    m.list = (int32_t *)(X + o_list);
+    m.mst = (float4 *)(X + o_mst);
     m.start = (int32_t *)(X + o_start);
     m.cur = (int32_t *)(X + o_cur);
+    m.n_elig = m.start + nbins;   // the scan's total
     launch_fill_i32(m.start, nbins + 1, 0, c->stream);
     launch_fill_i32(m.cur, nbins, 0, c->stream);
     launch_fill_i32(m.n_pairs, 1, 0, c->stream);
-    launch_fill_i32(m.partner_next, trk_cap, -1, c->stream);
-    launch_fill_i32(m.partner_prev, trk_cap, -1, c->stream);
+    launch_fill_i32(m.best_next, ntr, -1, c->stream);
+    launch_fill_i32(m.best_prev, ntr, -1, c->stream);
+    launch_fill_i32(m.partner_next, ntr, -1, c->stream);
+    launch_fill_i32(m.partner_prev, ntr, -1, c->stream);
     launch_merge_count(c->args, m, c->stream);
     launch_scan_i32(m.start, (int32_t)nbins, m.start, nullptr, c->args.scan_tmp, c->stream);   // nbins + 1 entries
     launch_merge_place(c->args, m, c->stream);
-    launch_merge_pairs(c->args, m, (int)nt, c->stream);
+    launch_merge_pairs(c->args, m, (int)nt, (int)nt, c->stream);
     int32_t np = 0;
     HIPCHK(c, hipMemcpyAsync(&np, m.n_pairs, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

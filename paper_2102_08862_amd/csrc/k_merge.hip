@@ -19,12 +19,13 @@
 //   k_mg_range   smallest and largest eligible t0 (block-reduced)
 //   k_mg_count   eligible tracks per (sector instance, time bin)
 //   (scan)       bin starts
-//   k_mg_place   tracks grouped by bin
-//   k_mg_best    per eligible track: best candidate in the next and in the
-//                previous sector (bins within one of its own: the bin width
-//                is a power of two >= window from a multiple of it, so bin
-//                indices are exact and a pair within the window is at most
-//                one bin apart)
+//   k_mg_place   tracks grouped by bin, with a compact copy of their states
+//   k_mg_best    per eligible track, in bin order (neighbouring threads read
+//                overlapping candidate ranges): best candidate in the next
+//                and in the previous sector, over the bins of
+//                [t0 - 1.001 window, t0 + 1.001 window] (the bin index is
+//                monotone in t0, so no candidate within the window is
+//                missed)
 //   k_mg_mutual  mutual bests -> partners
 #include "merge_internal.h"
 
@@ -33,10 +34,6 @@ namespace tpcca {
 namespace {
 
 constexpr float kSigR = 0.5f, kSigPhi = 0.02f, kSigT = 0.5f, kSigTau = 0.01f;
-
-struct TrkState {
-    float x, y, t, s, tau, q, t0;
-};
 
 __device__ inline int si_of(const KArgs &a, const MergeArgs &m, int g) {
     const tpcca_track &T = a.trk[g];
@@ -48,9 +45,13 @@ __device__ inline bool eligible(const KArgs &a, const MergeArgs &m, int g) {
     return a.trk[g].status == 0 && a.trk_len[g] >= m.min_len && __builtin_isfinite(t0);
 }
 
-__device__ inline TrkState state_of(const KArgs &a, int g) {
-    const tpcca_track &T = a.trk[g];
-    return TrkState{T.x_ref, T.y, T.t_base + T.dt, T.sinphi, T.tau, T.qpt, a.trk_t0[g]};
+struct MState {
+    float x, y, t, s, tau, q, t0, phi;
+};
+
+__device__ inline MState mstate(const MergeArgs &m, int p) {
+    const float4 u = m.mst[2 * p], v = m.mst[2 * p + 1];
+    return MState{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
 }
 
 __device__ inline int bin_of(const MergeArgs &m, float t0) {
@@ -59,7 +60,7 @@ __device__ inline int bin_of(const MergeArgs &m, float t0) {
 }
 
 // D2 of the pair (A, B) with B's sector dal further in azimuth.
-__device__ inline float pair_d2(const TrkState &A, const TrkState &B, float kB, float cdal, float sdal, float dal) {
+__device__ inline float pair_d2(const MState &A, const MState &B, float kB, float cdal, float sdal, float dal) {
     const float ca = sqrtf(fmaxf(1.f - A.s * A.s, 0.f));
     const float xb = B.x * cdal - B.y * sdal, yb = B.x * sdal + B.y * cdal;
     const float vx = xb - A.x, vy = yb - A.y;
@@ -69,8 +70,11 @@ __device__ inline float pair_d2(const TrkState &A, const TrkState &B, float kB, 
     const float arc = k != 0.f ? th / k : a;
     const float h = sqrtf((k * a) * (k * a) + (1.f - k * b) * (1.f - k * b));
     const float dr = (2.f * b - k * (a * a + b * b)) / (1.f + h);
-    float dphi = asinf(B.s) + dal - (asinf(A.s) + th);
-    dphi = atan2f(sinf(dphi), cosf(dphi));
+    // direction difference wrapped to (-pi, pi]
+    float dphi = B.phi + dal - (A.phi + th);
+    const float pi = 3.14159265358979f;
+    while (dphi > pi) dphi -= 2.f * pi;
+    while (dphi <= -pi) dphi += 2.f * pi;
     const float dt = A.t + A.tau * arc - B.t;
     const float dtau = A.tau - B.tau;
     const float r0 = dr / kSigR, r1 = dphi / kSigPhi, r2 = dt / kSigT, r3 = dtau / kSigTau;
@@ -129,50 +133,53 @@ __global__ __launch_bounds__(256) void k_mg_place(KArgs a, MergeArgs m) {
             const int g = S.trk_base + k;
             if (!eligible(a, m, g)) continue;
             const int64_t c = (int64_t)si * m.nb + bin_of(m, a.trk_t0[g]);
-            m.list[m.start[c] + atomicAdd(&m.cur[c], 1)] = g;
+            const int p = m.start[c] + atomicAdd(&m.cur[c], 1);
+            const tpcca_track &T = a.trk[g];
+            m.list[p] = g;
+            m.mst[2 * p] = make_float4(T.x_ref, T.y, T.t_base + T.dt, T.sinphi);
+            m.mst[2 * p + 1] = make_float4(T.tau, T.qpt, a.trk_t0[g], asinf(T.sinphi));
         }
     }
 }
 
-// One thread per eligible track (grid-stride over the track slots): its
-// best candidate in the next sector (it is A) and in the previous sector
+// One thread per eligible track, in list order (grid-stride over the list):
+// its best candidate in the next sector (it is A) and in the previous sector
 // (it is B).
 __global__ __launch_bounds__(256) void k_mg_best(KArgs a, MergeArgs m) {
     const int half = m.n_sectors / 2;
     const float dal = 6.283185307179586f / (float)half;
     const float cdal = cosf(dal), sdal = sinf(dal);
     const float kB = a.bz_kb;
-    const int nt = min(a.cnt->n_tracks, a.trk_cap);
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nt; g += gridDim.x * blockDim.x) {
+    const int ne = *m.n_elig;
+    const float wide = m.window * 1.001f;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < ne; p += gridDim.x * blockDim.x) {
+        const int g = m.list[p];
+        const MState X = mstate(m, p);
+        const int si = si_of(a, m, g);
+        const int fr = si / m.n_sectors, sec = si - fr * m.n_sectors;
+        const int side = sec / half, k = sec - side * half;
+        const int si_next = fr * m.n_sectors + side * half + (k + 1) % half;
+        const int si_prev = fr * m.n_sectors + side * half + (k + half - 1) % half;
+        const int b0 = bin_of(m, X.t0 - wide), b1 = bin_of(m, X.t0 + wide);
         int bn = -1, bp = -1;
-        if (eligible(a, m, g)) {
-            const int si = si_of(a, m, g);
-            const int fr = si / m.n_sectors, sec = si - fr * m.n_sectors;
-            const int side = sec / half, k = sec - side * half;
-            const int si_next = fr * m.n_sectors + side * half + (k + 1) % half;
-            const int si_prev = fr * m.n_sectors + side * half + (k + half - 1) % half;
-            const TrkState X = state_of(a, g);
-            const int b = bin_of(m, X.t0);
-            const int b0 = max(b - 1, 0), b1 = min(b + 1, m.nb - 1);
-            float dn = 0.f, dp = 0.f;
-            for (int dir = 0; dir < 2; dir++) {
-                const int64_t base = (int64_t)(dir == 0 ? si_next : si_prev) * m.nb;
-                const int j0 = m.start[base + b0], j1 = m.start[base + b1 + 1];
-                for (int j = j0; j < j1; j++) {
-                    const int h = m.list[j];
-                    const TrkState Y = state_of(a, h);
-                    if (!(fabsf(X.t0 - Y.t0) <= m.window)) continue;
-                    const float d2 = dir == 0 ? pair_d2(X, Y, kB, cdal, sdal, dal) : pair_d2(Y, X, kB, cdal, sdal, dal);
-                    if (!(d2 <= m.d2_cut)) continue;
-                    if (dir == 0) {
-                        if (bn < 0 || d2 < dn || (d2 == dn && h < bn)) {
-                            bn = h;
-                            dn = d2;
-                        }
-                    } else if (bp < 0 || d2 < dp || (d2 == dp && h < bp)) {
-                        bp = h;
-                        dp = d2;
+        float dn = 0.f, dp = 0.f;
+        for (int dir = 0; dir < 2; dir++) {
+            const int64_t base = (int64_t)(dir == 0 ? si_next : si_prev) * m.nb;
+            const int j0 = m.start[base + b0], j1 = m.start[base + b1 + 1];
+            for (int j = j0; j < j1; j++) {
+                const MState Y = mstate(m, j);
+                if (!(fabsf(X.t0 - Y.t0) <= m.window)) continue;
+                const float d2 = dir == 0 ? pair_d2(X, Y, kB, cdal, sdal, dal) : pair_d2(Y, X, kB, cdal, sdal, dal);
+                if (!(d2 <= m.d2_cut)) continue;
+                const int h = m.list[j];
+                if (dir == 0) {
+                    if (bn < 0 || d2 < dn || (d2 == dn && h < bn)) {
+                        bn = h;
+                        dn = d2;
                     }
+                } else if (bp < 0 || d2 < dp || (d2 == dp && h < bp)) {
+                    bp = h;
+                    dp = d2;
                 }
             }
         }
@@ -205,11 +212,9 @@ void launch_merge_place(const KArgs &a, const MergeArgs &m, hipStream_t s) {
     if (a.n_si > 0) hipLaunchKernelGGL(k_mg_place, dim3(min(a.n_si, 4096)), dim3(256), 0, s, a, m);
 }
 
-void launch_merge_pairs(const KArgs &a, const MergeArgs &m, int n_tracks, hipStream_t s) {
-    if (n_tracks <= 0) return;
-    const int blocks = min((n_tracks + 255) / 256, 65535);
-    hipLaunchKernelGGL(k_mg_best, dim3(blocks), dim3(256), 0, s, a, m);
-    hipLaunchKernelGGL(k_mg_mutual, dim3(blocks), dim3(256), 0, s, a, m);
+void launch_merge_pairs(const KArgs &a, const MergeArgs &m, int n_tracks, int n_elig, hipStream_t s) {
+    if (n_elig > 0) hipLaunchKernelGGL(k_mg_best, dim3(min((n_elig + 255) / 256, 65535)), dim3(256), 0, s, a, m);
+    if (n_tracks > 0) hipLaunchKernelGGL(k_mg_mutual, dim3(min((n_tracks + 255) / 256, 65535)), dim3(256), 0, s, a, m);
 }
 
 }  // namespace tpcca

@@ -11,24 +11,26 @@ struct MergeArgs {
     int32_t min_len;         // eligible: at least this many clusters
     float window;            // collision-time window of a candidate pair (cm)
     float d2_cut;            // a pair is a candidate if D2 <= d2_cut
-    float bin_w;             // time bin width: a power of two >= window
+    float bin_w;             // time bin width: the smallest power of two >= window
     float inv_w;             // 1 / bin_w (exact)
     float lo;                // time of bin 0 (a multiple of bin_w)
     int32_t nb;              // bins per sector instance
     uint32_t *range;         // [2] smallest and largest eligible t0 (order-preserving keys)
     int32_t *start;          // [n_si * nb + 1] counts, then their exclusive prefix
     int32_t *cur;            // [n_si * nb] placement cursors
-    int32_t *list;           // [trk_cap] eligible tracks grouped by (sector instance, bin)
-    int32_t *best_next;      // [trk_cap] best candidate in the next sector (global slot, -1)
-    int32_t *best_prev;      // [trk_cap] best candidate in the previous sector
-    int32_t *partner_next;   // [trk_cap] merged partner in the next sector (global slot, -1)
-    int32_t *partner_prev;   // [trk_cap] merged partner in the previous sector
+    int32_t *list;           // [tracks] eligible tracks grouped by (sector instance, bin)
+    float4 *mst;             // [2 * tracks] their states in list order: (x, y, t, sin phi), (tau, q/pT, t0, phi)
+    int32_t *best_next;      // [tracks] best candidate in the next sector (global slot, -1)
+    int32_t *best_prev;      // [tracks] best candidate in the previous sector
+    int32_t *partner_next;   // [tracks] merged partner in the next sector (global slot, -1)
+    int32_t *partner_prev;   // [tracks] merged partner in the previous sector
+    int32_t *n_elig;         // [1] eligible tracks (the list's length)
     int32_t *n_pairs;        // [1]
 };
 
 void launch_merge_range(const KArgs &a, const MergeArgs &m, hipStream_t s);
 void launch_merge_count(const KArgs &a, const MergeArgs &m, hipStream_t s);
 void launch_merge_place(const KArgs &a, const MergeArgs &m, hipStream_t s);
-void launch_merge_pairs(const KArgs &a, const MergeArgs &m, int n_tracks, hipStream_t s);
+void launch_merge_pairs(const KArgs &a, const MergeArgs &m, int n_tracks, int n_elig, hipStream_t s);
 
 }  // namespace tpcca
