@@ -161,3 +161,34 @@ def test_merges_of_the_10ms_frame_against_truth(tp):
     assert purity >= 0.99 and eff >= 0.9
     del trk
     torch.cuda.empty_cache()
+
+
+def test_merges_of_a_batch_equal_single_frames(tp):
+    """Two frames in one run: each frame's merges (partner indices within
+    its own sectors) equal those of a run of that frame alone, and the
+    collision candidates of the batch leave them unchanged."""
+    frames = [synth.generate("frame_10ms", seed=4300 + i, n_threads=16, frame_us=1000.0 * L,
+                             n_collisions=int(round(50 * L))) for i, L in enumerate((0.4, 0.7))]
+    print("case merge batch of 2 frames", flush=True)
+    single = []
+    for fr in frames:
+        t = tp.Tracker()
+        f = t.load_frame_packed(fr)
+        t.run(sync=True)
+        t.merge_sectors(MIN_LEN, WINDOW, CUT)
+        single.append([t.merges(f, s) for s in range(36)])
+        del t
+    t = tp.Tracker()
+    ids = [t.load_frame_packed(fr) for fr in frames]
+    t.run(sync=True)
+    t.find_collisions()
+    n = t.merge_sectors(MIN_LEN, WINDOW, CUT)
+    t.find_collisions()   # the collision candidates use the other half of the scratch
+    total = 0
+    for k, f in enumerate(ids):
+        for s in range(36):
+            nx, pv = t.merges(f, s)
+            assert np.array_equal(nx, single[k][s][0]) and np.array_equal(pv, single[k][s][1]), (k, s)
+            total += int((nx >= 0).sum())
+    assert total == n and n > 1000
+    print("batch merges", n, flush=True)
