@@ -527,6 +527,20 @@ def merge_sectors(cfg: Config, tracks, min_clusters: int = 30, window: float = 8
     return nxt, prv, np.asarray(d2_pairs)
 
 
+
+def refit_merged(cfg: Config, xa, ya, ta, xb, yb, tb, dalpha: float):
+    """Global refit of a merged pair (R31): the clusters of the second track
+    (in the sector dalpha further in azimuth) rotated into the first track's
+    frame, appended to the first track's, ordered by local x (a stable sort:
+    ties keep that order), and fitted by fit_map as one track. FP64."""
+    xa, ya, ta, xb, yb, tb = (np.asarray(v, np.float64) for v in (xa, ya, ta, xb, yb, tb))
+    c, s = np.cos(dalpha), np.sin(dalpha)
+    x = np.concatenate([xa, xb * c - yb * s])
+    y = np.concatenate([ya, xb * s + yb * c])
+    t = np.concatenate([ta, tb])
+    o = np.argsort(x, kind="stable")
+    return fit_map(cfg, x[o], y[o], t[o])
+
 # ----------------------------------------------------------------- MLP
 MLP_IN, MLP_INP, MLP_H = 12, 16, 64
 MLP_NPARAM = MLP_H * MLP_INP + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1

@@ -142,3 +142,48 @@ def test_merging_by_brute_force(ocfg, seed):
         for j in range(len(b["x"])):
             r = _residual_scalar(ocfg, {k_: a[k_][i] for k_ in a}, {k_: b[k_][j] for k_ in b}, dal)
             assert np.allclose([R[q][i, j] for q in range(4)], r, rtol=0, atol=1e-9)
+
+
+def test_refit_of_noise_free_pieces_is_truth(geom, ocfg):
+    """Exact helix points of one particle in two adjacent sectors: the refit
+    of the merged pair, in the first sector's frame, is the truth state at
+    its outermost point (the same argument as for one sector's track: the
+    three-point estimate is exact, so is the MAP)."""
+    x = geom[0]
+    fr = synth.generate("slice_1ms", seed=2402, n_threads=8)
+    rng = np.random.default_rng(3)
+    dal = np.deg2rad(20.0)
+    done = 0
+    for pid in rng.permutation(len(fr.tracks))[:20000]:
+        tr = fr.tracks[pid]
+        if tr[1] < 0.5:
+            continue
+        for s in range(36):
+            side, k = divmod(s, 18)
+            n = 18 * side + (k + 1) % 18
+            pa = [(float(x[r]), _state(tr, s, x[r])) for r in range(152)]
+            pb = [(float(x[r]), _state(tr, n, x[r])) for r in range(152)]
+            # the crossings inside each sector's azimuthal acceptance (20 degrees)
+            pa = [(xx, h) for xx, h in pa if h is not None and abs(h["y"]) <= xx * np.tan(dal / 2)]
+            pb = [(xx, h) for xx, h in pb if h is not None and abs(h["y"]) <= xx * np.tan(dal / 2)]
+            if len(pa) < 8 or len(pb) < 8:
+                continue
+            xa = np.array([v[0] for v in pa]); ya = np.array([v[1]["y"] for v in pa])
+            ta = np.array([v[1]["t"] for v in pa])
+            xb = np.array([v[0] for v in pb]); yb = np.array([v[1]["y"] for v in pb])
+            tb = np.array([v[1]["t"] for v in pb])
+            f = oracle.refit_merged(ocfg, xa, ya, ta, xb, yb, tb, dal)
+            xr = max(xa.max(), (xb * np.cos(dal) - yb * np.sin(dal)).max())
+            assert f["status"] == 0 and abs(f["x_ref"] - xr) < 1e-12
+            tru = _state(tr, s, xr)
+            if tru is None or abs(tru["sinphi"]) > 0.95:
+                continue
+            got = np.array([f["y"], f["t"], f["sinphi"], f["tau"], f["qpt"]])
+            want = np.array([tru["y"], tru["t"], tru["sinphi"], tru["tau"], tru["qpt"]])
+            assert np.allclose(got, want, rtol=1e-8, atol=1e-8), (pid, s, got, want)
+            assert f["chi2"] < 1e-10
+            done += 1
+            break
+        if done >= 40:
+            break
+    assert done >= 20
