@@ -403,6 +403,30 @@ tpcca_status tpcca_merge_sectors(tpcca_ctx *ctx, int32_t min_clusters, float win
 tpcca_status tpcca_get_merges(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *next, int32_t *prev,
                               int64_t cap, int64_t *n_out);
 
+/* Global refit of the merged pairs (Sec. 1: the pieces of a particle found
+   in two sectors joined after the tracking; the fit is the helix fit of
+   tpcca_run, Sec. 3): every pair of tpcca_merge_sectors becomes one track
+   whose clusters are those of the first track (sector s) and of its partner
+   (next sector), the partner's rotated by the sector angle into sector s's
+   frame, ordered by increasing local x (ties: the first track's before the
+   partner's, each in its own order), and fitted like a track of sector s
+   with the x each cluster carries. Call after tpcca_merge_sectors (it
+   synchronises); the virtual tracks take the free part of the chain-copy
+   region and the arena's slot after the merge arrays, so the result holds
+   until the next run or merge. *n_out = pairs refitted. STATE before
+   tpcca_merge_sectors, CAPACITY if the virtual tracks do not fit. */
+tpcca_status tpcca_refit_merged(tpcca_ctx *ctx, int64_t *n_out);
+
+/* Refits whose first track lies in the sector, in the order of that track:
+   the fitted track (frame and sector of the first track, n_clusters of
+   both, x_ref the outermost cluster's x in that sector's frame, seed the
+   first track's, first not meaningful), the first track's index among the
+   sector's tracks (first_track) and its partner's among the next sector's
+   (partner); any pointer may be null. STATE before tpcca_refit_merged,
+   CAPACITY if cap is below the count (*n_out holds it). */
+tpcca_status tpcca_get_refits(tpcca_ctx *ctx, int32_t frame, int32_t sector, tpcca_track *tracks,
+                              int32_t *first_track, int32_t *partner, int64_t cap, int64_t *n_out);
+
 /* The pad-row neighbour links of the cellular-automaton seeding (Sec. 1:
    HLT-derived tracker, seeding with time as a coordinate).
    Neighbour links of every input cluster of the sector, in input indices

@@ -125,6 +125,11 @@ struct tpcca_ctx {
     // offsets of the partner arrays (upper half of the post-run scratch slot)
     bool merge_valid = false;
     size_t merge_next_off = 0, merge_prev_off = 0;
+    size_t merge_end = 0;   // first free byte after the merge arrays (offset in the arena)
+    // refits of the merged pairs (reset by a run or a new merge)
+    bool refit_valid = false;
+    size_t refit_pidx_off = 0, refit_pa_off = 0, refit_pb_off = 0, refit_trk_off = 0;
+    int64_t refit_n = 0;
     std::vector<int32_t> coll_n, coll_base;   // per side: groups, first group
     size_t coll_sum_off = 0, coll_cnt_off = 0, coll_att_off = 0;   // arena offsets: sums, anchors, attached
     Layout lay;
@@ -1033,6 +1038,7 @@ static tpcca_status run_on_arena(tpcca_ctx *c, bool graphs) {
     c->have_results = true;
     c->coll_valid = false;
     c->merge_valid = false;
+    c->refit_valid = false;
     return TPCCA_OK;
 }
 
@@ -1412,8 +1418,128 @@ tpcca_status tpcca_merge_sectors(tpcca_ctx *c, int32_t min_clusters, float windo
     if (e != hipSuccess) return hip_fail(c, e, "merge kernels");
     c->merge_next_off = (size_t)((char *)m.partner_next - A);
     c->merge_prev_off = (size_t)((char *)m.partner_prev - A);
+    c->merge_end = (size_t)(X - A) + align_up(b.off, 256);
     c->merge_valid = true;
+    c->refit_valid = false;
     *n_pairs_out = np;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_refit_merged(tpcca_ctx *c, int64_t *n_out) {
+    if (!c || !n_out) return TPCCA_ERR_INVALID_ARG;
+    *n_out = 0;
+    if (!c->merge_valid) return fail(c, TPCCA_ERR_STATE, "no merges (call tpcca_merge_sectors)");
+    tpcca_status ss = tpcca_synchronize(c);
+    if (ss != TPCCA_OK) return ss;
+    char *A = c->arena;
+    const Layout &L = c->lay;
+    const KArgs &a = c->args;
+    Counters k{};
+    HIPCHK(c, hipMemcpy(&k, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost));
+    const int64_t nt = std::min<int64_t>(k.n_tracks, a.trk_cap);
+    // the pair arrays after the merge arrays (upper half of the slot)
+    const size_t end = L.xslot + L.slot_bytes;
+    Bump b;
+    b.off = c->merge_end;
+    const size_t o_flags = b.take(sizeof(int32_t) * (nt + 1)), o_pidx = b.take(sizeof(int32_t) * (nt + 1));
+    if (b.off > end) return fail(c, TPCCA_ERR_CAPACITY, "refit arrays exceed the scratch slot");
+    RefitArgs r{};
+    r.n_sectors = c->cfg.n_sectors;
+    r.flags = (int32_t *)(A + o_flags);
+    r.pidx = (int32_t *)(A + o_pidx);
+    MergeArgs m{};
+    m.partner_next = (int32_t *)(A + c->merge_next_off);
+    launch_refit_flags(a, m, r, (int)nt, c->stream);
+    launch_scan_i32(r.flags, (int32_t)nt, r.pidx, nullptr, a.scan_tmp, c->stream);
+    int32_t np = 0;
+    HIPCHK(c, hipMemcpyAsync(&np, r.pidx + nt, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int64_t npr = std::max<int64_t>(np, 1);
+    const size_t o_pa = b.take(sizeof(int32_t) * npr), o_pb = b.take(sizeof(int32_t) * npr),
+                 o_vlen = b.take(sizeof(int32_t) * (npr + 1)), o_voff = b.take(sizeof(int32_t) * (npr + 1)),
+                 o_vseed = b.take(sizeof(int32_t) * npr), o_vperm = b.take(sizeof(int32_t) * npr),
+                 o_vt0 = b.take(sizeof(float) * npr), o_vtrk = b.take(sizeof(tpcca_track) * npr),
+                 o_vcnt = b.take(sizeof(Counters));
+    if (b.off > end) return fail(c, TPCCA_ERR_CAPACITY, "refit arrays exceed the scratch slot");
+    r.pa = (int32_t *)(A + o_pa);
+    r.pb = (int32_t *)(A + o_pb);
+    r.vlen = (int32_t *)(A + o_vlen);
+    r.voff = (int32_t *)(A + o_voff);
+    r.vseed = (int32_t *)(A + o_vseed);
+    r.vperm = (int32_t *)(A + o_vperm);
+    launch_refit_pairs(a, m, r, (int)nt, c->stream);
+    launch_scan_i32(r.vlen, np, r.voff, nullptr, a.scan_tmp, c->stream);
+    int32_t n_ent = 0;
+    HIPCHK(c, hipMemcpyAsync(&n_ent, r.voff + np, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // the virtual chains take the chain-copy region after the copies in use
+    const int64_t used = std::max<int64_t>(k.chain_next, k.f_chain_next);
+    r.vchain = a.chain + used;
+    r.vcap = std::max<int64_t>(a.chain_cap - used, 0);
+    if (n_ent > r.vcap) return fail(c, TPCCA_ERR_CAPACITY, "merged tracks exceed the free chain-copy space");
+    launch_refit_build(a, r, np, c->stream);
+    // the fit over the virtual tracks: its own track arrays and counters
+    KArgs va = a;
+    va.chain = r.vchain;
+    va.choff = r.voff;
+    va.trk_len = r.vlen;
+    va.perm = r.vperm;
+    va.trk_seed = r.vseed;
+    va.cl_off = r.voff;   // no cluster lists for refits: 'first' is not meaningful
+    va.trk = (tpcca_track *)(A + o_vtrk);
+    va.trk_t0 = (float *)(A + o_vt0);
+    va.cnt = (Counters *)(A + o_vcnt);
+    va.trk_cap = (int32_t)npr;
+    Counters z{};
+    z.n_tracks = np;
+    HIPCHK(c, hipMemcpyAsync(va.cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, c->stream));
+    // vlen was scanned into voff; the lengths themselves are still in vlen
+    if (np > 0) launch_fit_x(va, c->lc[11], c->stream);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "refit kernels");
+    c->refit_pidx_off = o_pidx;
+    c->refit_pa_off = o_pa;
+    c->refit_pb_off = o_pb;
+    c->refit_trk_off = o_vtrk;
+    c->refit_n = np;
+    c->refit_valid = true;
+    *n_out = np;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_refits(tpcca_ctx *c, int32_t frame, int32_t sector, tpcca_track *tracks, int32_t *first_track,
+                              int32_t *partner, int64_t cap, int64_t *n_out) {
+    if (!c || !n_out) return TPCCA_ERR_INVALID_ARG;
+    if (!c->refit_valid) return fail(c, TPCCA_ERR_STATE, "no refits (call tpcca_refit_merged)");
+    int si;
+    SiState st;
+    tpcca_status s = locate(c, frame, sector, si, st);
+    if (s != TPCCA_OK) return s;
+    const int half = c->cfg.n_sectors / 2, side = sector / half, k = sector % half;
+    int si_n;
+    SiState stn;
+    s = locate(c, frame, side * half + (k + 1) % half, si_n, stn);
+    if (s != TPCCA_OK) return s;
+    int32_t r0 = 0, r1 = 0;
+    const int32_t *pidx = (const int32_t *)(c->arena + c->refit_pidx_off);
+    HIPCHK(c, hipMemcpy(&r0, pidx + st.trk_base, sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&r1, pidx + st.trk_base + st.n_tracks, sizeof(int32_t), hipMemcpyDeviceToHost));
+    const int64_t n = r1 - r0;
+    *n_out = n;
+    if (cap < n) return fail(c, TPCCA_ERR_CAPACITY, "buffer too small");
+    if (n == 0) return TPCCA_OK;
+    if (tracks)
+        HIPCHK(c, hipMemcpy(tracks, c->arena + c->refit_trk_off + sizeof(tpcca_track) * (size_t)r0,
+                            sizeof(tpcca_track) * (size_t)n, hipMemcpyDeviceToHost));
+    for (int dir = 0; dir < 2; dir++) {
+        int32_t *out = dir == 0 ? first_track : partner;
+        if (!out) continue;
+        HIPCHK(c, hipMemcpy(out, c->arena + (dir == 0 ? c->refit_pa_off : c->refit_pb_off) + sizeof(int32_t) * (size_t)r0,
+                            sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost));
+        const int32_t base = dir == 0 ? st.trk_base : stn.trk_base;
+        for (int64_t i = 0; i < n; i++) out[i] -= base;
+    }
     return TPCCA_OK;
 }
 

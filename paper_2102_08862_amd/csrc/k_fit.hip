@@ -261,6 +261,14 @@ struct FitDone {
 // track computes it, lane 0 writes): the state at x_c carried to x_L, the
 // covariance from the Cholesky factor Hf of the information matrix at x_c
 // (null: zero), C' = F H^-1 F^T.
+// x of a cluster: the pad row's x, or (for refits of merged tracks, whose
+// clusters come from two sectors) the x the record carries in its id field.
+template <bool kX>
+__device__ inline float xof(const float *sx, const Rec &e) {
+    return kX ? __int_as_float(e.id) : sx[e.sr & 255];
+}
+
+template <bool kX>
 __device__ inline void fit_emit(const KArgs &a, const float *sx, int g, int L, const Rec &e0, const Rec &cm, const Rec &cL,
                                 float xc, const float q[5], float chi2, int status, const float (*Hf)[5],
                                 bool writer) {
@@ -271,10 +279,10 @@ __device__ inline void fit_emit(const KArgs &a, const float *sx, int g, int L, c
     o.sector = a.si[si].sector;
     o.n_clusters = L;
     o.first = (int64_t)(a.cl_off[g] - a.st[si].cl_base);
-    o.seed = a.follow ? a.trk_seed[g] : e0.id;   // with following: the chain's seed
+    o.seed = (kX || a.follow) ? a.trk_seed[g] : e0.id;   // with following (or a refit): the chain's seed
     o.ndf = 2 * L - 5;
-    const float XL = sx[cL.sr & 255] - xc;
-    o.x_ref = sx[cL.sr & 255];
+    const float XL = xof<kX>(sx, cL) - xc;
+    o.x_ref = xof<kX>(sx, cL);
     o.t_base = cL.t;
     float yo = 0.f, to = 0.f, so = 0.f;
     Jac J{};
@@ -333,7 +341,7 @@ __device__ inline void fit_emit(const KArgs &a, const float *sx, int g, int L, c
 }
 
 // Fit of the tracks at queue positions [base, base + 64 / G), G lanes each.
-template <int G>
+template <int G, bool kX>
 __device__ void fit_wave(const KArgs &a, const float *sx, int32_t *hist, FitDone *done, int base, int nt) {
     const int lane = threadIdx.x & 63;
     const int gl = lane & (G - 1);        // lane within the track's group
@@ -354,16 +362,16 @@ __device__ void fit_wave(const KArgs &a, const float *sx, int32_t *hist, FitDone
         c1 = ch[0];
         cL = ch[L - 1];
     }
-    const float xc = sx[cm.sr & 255];
+    const float xc = xof<kX>(sx, cm);
     // three-point estimate at the innermost cluster (positions relative to it)
-    const float X1 = sx[c1.sr & 255] - xc;
+    const float X1 = xof<kX>(sx, c1) - xc;
     bool ok = have;
     float q0s = 0.f, q0tau = 0.f, q0k = 0.f;
     float q[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     if (ok) {
-        const float x1 = sx[c1.sr & 255];
+        const float x1 = xof<kX>(sx, c1);
         const float Xm = xc - x1, Ym = cm.y - c1.y;
-        const float XL = sx[cL.sr & 255] - x1, YL = cL.y - c1.y, TL = cL.t - c1.t;
+        const float XL = xof<kX>(sx, cL) - x1, YL = cL.y - c1.y, TL = cL.t - c1.t;
         const float bcx = XL - Xm, bcy = YL - Ym;
         const float cr = Xm * YL - Ym * XL;
         const float dab = sqrtf(Xm * Xm + Ym * Ym), dac = sqrtf(XL * XL + YL * YL),
@@ -429,7 +437,7 @@ __device__ void fit_wave(const KArgs &a, const float *sx, int32_t *hist, FitDone
                 const Rec e = ch[j];
                 float yo, to;
                 Jac J;
-                transport_pass(kB, smax, q, c0, ic0, sx[e.sr & 255] - xc, yo, to, J, dom);
+                transport_pass(kB, smax, q, c0, ic0, xof<kX>(sx, e) - xc, yo, to, J, dom);
                 const float ry = (e.y - cm.y) - yo, rt = (e.t - cm.t) - to;
                 sm[kSys] += J.ys;
                 sm[kSyk] += J.yk;
@@ -546,7 +554,7 @@ __device__ void fit_wave(const KArgs &a, const float *sx, int32_t *hist, FitDone
         float qf[5];
 #pragma unroll
         for (int i = 0; i < 5; i++) qf[i] = D.q[i];
-        fit_emit(a, sx, g, L, c1, cm, cL, xc, qf, D.chi2, D.status, D.has_cov ? D.Hf : nullptr, gl == 0);
+        fit_emit<kX>(a, sx, g, L, c1, cm, cL, xc, qf, D.chi2, D.status, D.has_cov ? D.Hf : nullptr, gl == 0);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -555,6 +563,7 @@ __device__ void fit_wave(const KArgs &a, const float *sx, int32_t *hist, FitDone
 // Every wave takes kFitPerWave tracks at a time from the queue (track slots
 // in order of decreasing length, so the tracks of a wave have about the same
 // length).
+template <bool kX>
 __global__ __launch_bounds__(256) void k_fit(KArgs a) {
     TPCCA_ABORT_GUARD(a);
     __shared__ float sx[kMaxRows];
@@ -571,7 +580,7 @@ __global__ __launch_bounds__(256) void k_fit(KArgs a) {
         if (lane == 0) base = atomicAdd(&a.cnt->fit_next, kFitPerWave);
         base = __shfl(base, 0);
         if (base >= nt) break;
-        fit_wave<kFitG>(a, sx, hist, wd, base, nt);
+        fit_wave<kFitG, kX>(a, sx, hist, wd, base, nt);
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= kPassBins; i += blockDim.x)
@@ -579,7 +588,11 @@ __global__ __launch_bounds__(256) void k_fit(KArgs a) {
 }
 
 void launch_fit(const KArgs &a, Launch l, hipStream_t s) {
-    hipLaunchKernelGGL(k_fit, dim3(l.grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_fit<false>, dim3(l.grid), dim3(256), 0, s, a);
+}
+
+void launch_fit_x(const KArgs &a, Launch l, hipStream_t s) {
+    hipLaunchKernelGGL(k_fit<true>, dim3(l.grid), dim3(256), 0, s, a);
 }
 
 }  // namespace tpcca

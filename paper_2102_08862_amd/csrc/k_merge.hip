@@ -27,6 +27,10 @@
 //                monotone in t0, so no candidate within the window is
 //                missed)
 //   k_mg_mutual  mutual bests -> partners
+//   k_rf_*       refit of the merged pairs: pair list in the order of the
+//                first track's slot, virtual tracks (clusters of both in the
+//                first track's frame, ordered by x), then the fit kernel
+//                with the x each record carries
 #include "merge_internal.h"
 
 namespace tpcca {
@@ -198,6 +202,95 @@ __global__ __launch_bounds__(256) void k_mg_mutual(KArgs a, MergeArgs m) {
             atomicAdd(m.n_pairs, 1);
         }
     }
+}
+
+// ------------------------------------------------------------ refit
+constexpr int kRfMax = 2 * kMaxRows + 2;   // clusters of a virtual track
+
+__global__ __launch_bounds__(256) void k_rf_flags(KArgs a, MergeArgs m, RefitArgs r, int nt) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nt; g += gridDim.x * blockDim.x)
+        r.flags[g] = m.partner_next[g] >= 0 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_rf_pairs(KArgs a, MergeArgs m, RefitArgs r, int nt) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nt; g += gridDim.x * blockDim.x) {
+        const int h = m.partner_next[g];
+        if (h < 0) continue;
+        const int i = r.pidx[g];
+        r.pa[i] = g;
+        r.pb[i] = h;
+        r.vlen[i] = min(a.trk_len[g] + a.trk_len[h], kRfMax);
+        r.vseed[i] = (int32_t)a.trk[g].seed;   // the first track's seed as reported
+        r.vperm[i] = i;
+    }
+}
+
+// One wave per pair: the clusters of both tracks in the first track's frame
+// (the partner's rotated by the sector angle), each placed at its rank by x
+// (ties in the order first track, then partner, each in its own order).
+
+__global__ __launch_bounds__(256) void k_rf_build(KArgs a, RefitArgs r, int np) {
+    __shared__ float xs_all[4][kRfMax];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    float *xs = xs_all[w];
+    const int half = r.n_sectors / 2;
+    const float dal = 6.283185307179586f / (float)half;
+    const float cd = cosf(dal), sd = sinf(dal);
+    const int nw = gridDim.x * (blockDim.x >> 6);
+    for (int i = blockIdx.x * (blockDim.x >> 6) + w; i < np; i += nw) {
+        const int g = r.pa[i], h = r.pb[i];
+        const int LA = a.trk_len[g], LB = a.trk_len[h], L = min(LA + LB, kRfMax);
+        const Rec *ca = a.chain + a.choff[g], *cb = a.chain + a.choff[h];
+        const int si = ca[0].sr >> 8;
+        constexpr int kPer = (kRfMax + 63) / 64;
+        float xx[kPer], yy[kPer], tt[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const int j = lane + 64 * u;
+            xx[u] = yy[u] = tt[u] = 0.f;
+            if (j < L) {
+                const Rec e = j < LA ? ca[j] : cb[j - LA];
+                const float x = a.row_x[e.sr & 255];
+                if (j < LA) {
+                    xx[u] = x;
+                    yy[u] = e.y;
+                } else {
+                    xx[u] = x * cd - e.y * sd;
+                    yy[u] = x * sd + e.y * cd;
+                }
+                tt[u] = e.t;
+                xs[j] = xx[u];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        Rec *dst = r.vchain + r.voff[i];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const int j = lane + 64 * u;
+            if (j < L) {
+                int rank = 0;
+                for (int k = 0; k < L; k++) rank += (xs[k] < xx[u] || (xs[k] == xx[u] && k < j)) ? 1 : 0;
+                dst[rank] = Rec{yy[u], tt[u], __float_as_int(xx[u]), si << 8};
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+void launch_refit_flags(const KArgs &a, const MergeArgs &m, const RefitArgs &r, int n_tracks, hipStream_t s) {
+    if (n_tracks > 0)
+        hipLaunchKernelGGL(k_rf_flags, dim3(min((n_tracks + 255) / 256, 65535)), dim3(256), 0, s, a, m, r, n_tracks);
+}
+
+void launch_refit_pairs(const KArgs &a, const MergeArgs &m, const RefitArgs &r, int n_tracks, hipStream_t s) {
+    if (n_tracks > 0)
+        hipLaunchKernelGGL(k_rf_pairs, dim3(min((n_tracks + 255) / 256, 65535)), dim3(256), 0, s, a, m, r, n_tracks);
+}
+
+void launch_refit_build(const KArgs &a, const RefitArgs &r, int n_pairs, hipStream_t s) {
+    if (n_pairs > 0) hipLaunchKernelGGL(k_rf_build, dim3(min((n_pairs + 3) / 4, 65535)), dim3(256), 0, s, a, r, n_pairs);
 }
 
 void launch_merge_range(const KArgs &a, const MergeArgs &m, hipStream_t s) {

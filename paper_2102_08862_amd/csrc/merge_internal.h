@@ -28,6 +28,27 @@ struct MergeArgs {
     int32_t *n_pairs;        // [1]
 };
 
+// Refit of the merged pairs: each pair becomes one virtual track (the first
+// track's clusters and its partner's rotated into the first track's frame,
+// ordered by x), fitted by the fit kernel with the x carried by each record.
+struct RefitArgs {
+    int32_t n_sectors;
+    int32_t *flags;          // [tracks + 1] 1 where the track has a partner in the next sector
+    int32_t *pidx;           // [tracks + 1] exclusive prefix of flags: the pair index of a track
+    int32_t *pa, *pb;        // [pairs] the pair's tracks (global slots), A in the lower sector
+    int32_t *vlen;           // [pairs + 1] clusters of the virtual track, then (scan) their offsets
+    int32_t *voff;           // [pairs + 1]
+    int32_t *vseed;          // [pairs] seed of the first track (its tpcca_track.seed)
+    int32_t *vperm;          // [pairs] fit order (identity)
+    Rec *vchain;             // [entries] virtual chains {y, t, bits of x, (si << 8)}
+    int64_t vcap;            // entries available
+};
+
+void launch_refit_flags(const KArgs &a, const MergeArgs &m, const RefitArgs &r, int n_tracks, hipStream_t s);
+void launch_refit_pairs(const KArgs &a, const MergeArgs &m, const RefitArgs &r, int n_tracks, hipStream_t s);
+void launch_refit_build(const KArgs &a, const RefitArgs &r, int n_pairs, hipStream_t s);
+void launch_fit_x(const KArgs &a, Launch l, hipStream_t s);
+
 void launch_merge_range(const KArgs &a, const MergeArgs &m, hipStream_t s);
 void launch_merge_count(const KArgs &a, const MergeArgs &m, hipStream_t s);
 void launch_merge_place(const KArgs &a, const MergeArgs &m, hipStream_t s);

@@ -89,7 +89,7 @@ EXPORTS = [
     "tpcca_mlp_infer", "tpcca_mlp_grad", "tpcca_mlp_train_step", "tpcca_get_triplets", "tpcca_set_graph",
     "tpcca_set_launch", "tpcca_set_pruning", "tpcca_set_triplet_pool", "tpcca_copy", "tpcca_triplet_samples",
     "tpcca_find_collisions", "tpcca_get_track_times", "tpcca_get_collisions", "tpcca_merge_sectors",
-    "tpcca_get_merges",
+    "tpcca_get_merges", "tpcca_refit_merged", "tpcca_get_refits",
 ]
 
 MLP_NPARAM = 5313
@@ -135,6 +135,8 @@ def load_library(path: str = LIB_PATH):
         "tpcca_get_collisions": [P, I32, I32, P, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_merge_sectors": [P, I32, ctypes.c_float, ctypes.c_float, ctypes.POINTER(I64)],
         "tpcca_get_merges": [P, I32, I32, P, P, I64, ctypes.POINTER(I64)],
+        "tpcca_refit_merged": [P, ctypes.POINTER(I64)],
+        "tpcca_get_refits": [P, I32, I32, P, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_links": [P, I32, I32, I32, P, P, I64],
         "tpcca_mlp_state_bytes": [ctypes.POINTER(SZ)],
         "tpcca_mlp_attach": [P, P, SZ],
@@ -469,6 +471,27 @@ class Tracker:
             self._check(self.lib.tpcca_get_merges(self.h, frame, sector, nx.ctypes.data, pv.ctypes.data, n.value,
                                                   ctypes.byref(n)))
         return nx, pv
+
+    def refit_merged(self) -> int:
+        """Fit every merged pair as one track (clusters of both in the first
+        track's sector frame); returns the number of pairs refitted."""
+        n = ctypes.c_int64()
+        self._check(self.lib.tpcca_refit_merged(self.h, ctypes.byref(n)))
+        return n.value
+
+    def refits(self, frame, sector):
+        """(tracks TRACK_DTYPE, first int32, partner int32): the refits whose
+        first track lies in the sector, that track's index among the
+        sector's tracks and its partner's among the next sector's."""
+        n = ctypes.c_int64()
+        self._check_cap(self.lib.tpcca_get_refits(self.h, frame, sector, None, None, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, TRACK_DTYPE)
+        fi = np.full(n.value, -1, np.int32)
+        pa = np.full(n.value, -1, np.int32)
+        if n.value:
+            self._check(self.lib.tpcca_get_refits(self.h, frame, sector, out.ctypes.data, fi.ctypes.data,
+                                                  pa.ctypes.data, n.value, ctypes.byref(n)))
+        return out, fi, pa
 
     def links(self, frame, sector, cleaned: bool = False):
         n = self.sector_n.get((frame, sector), 0)
