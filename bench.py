@@ -398,11 +398,12 @@ def collisions_leg(trk, fr, f, log, quality=True):
 
 
 def merge_leg(trk, fr, f, log, quality=True):
-    """Sector merging after the plain run: the time of merge_sectors (wall
-    clock; it synchronises) and, against the generator's truth, the share of
-    merged pairs that join one particle's segments (purity) and of the
-    particles with long segments in two adjacent sectors that are joined
-    (efficiency)."""
+    """Sector merging after the plain run: the time of merge_sectors and of
+    the global refit of the merged pairs (wall clock; both synchronise) and,
+    against the generator's truth, the share of merged pairs that join one
+    particle's segments (purity), of the particles with long segments in two
+    adjacent sectors that are joined (efficiency), and the median q/pT error
+    of the first piece alone and of the refit."""
     from paper_2102_08862_amd import metrics
     min_len, window, cut = 30, 8.0, 25.0
     ts = []
@@ -412,6 +413,14 @@ def merge_leg(trk, fr, f, log, quality=True):
         ts.append(time.perf_counter() - t0)
     out = {"min_clusters": min_len, "window_cm": window, "d2_cut": cut, "pairs": int(n_pairs),
            "ms": round(1e3 * float(np.median(ts)), 4)}
+    # the global refit of the merged pairs (wall clock; it synchronises)
+    tr_ = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        n_ref = trk.refit_merged()
+        tr_.append(time.perf_counter() - t0)
+    out["refit_ms"] = round(1e3 * float(np.median(tr_)), 4)
+    out["refits"] = int(n_ref)
     if quality:
         ns = len(fr.rows)
         half = ns // 2
@@ -420,11 +429,18 @@ def merge_leg(trk, fr, f, log, quality=True):
             tr = trk.tracks(f, s)
             P[s] = (metrics.track_majority(fr.labels[s], trk.track_clusters(f, s), tr["n_clusters"]), tr)
         good = bad = opp = 0
+        dq_piece, dq_refit = [], []
         for s in range(ns):
             side, k = divmod(s, half)
             n = side * half + (k + 1) % half
             (pa, ta), (pb, tb) = P[s], P[n]
             nxt, _ = trk.merges(f, s)
+            rf, rfi, _ = trk.refits(f, s)
+            for k_, i in enumerate(rfi):
+                if pa[i] >= 0 and ta["status"][i] == 0 and rf["status"][k_] == 0:
+                    q = fr.tracks[pa[i]][0] / fr.tracks[pa[i]][1]
+                    dq_piece.append(abs(float(ta["qpt"][i]) - q))
+                    dq_refit.append(abs(float(rf["qpt"][k_]) - q))
             for i, j in enumerate(nxt):
                 if j >= 0:
                     good += int(pa[i] >= 0 and pa[i] == pb[j])
@@ -434,8 +450,13 @@ def merge_leg(trk, fr, f, log, quality=True):
             opp += len(set(pa[ea][pa[ea] >= 0]) & set(pb[eb][pb[eb] >= 0]))
         out["purity"] = round(good / max(good + bad, 1), 5)
         out["efficiency"] = round(good / max(opp, 1), 5)
-    log("merge: %d pairs in %.3f ms; %s" % (out["pairs"], out["ms"],
-                                            {k: out[k] for k in ("purity", "efficiency") if k in out}))
+        # q/pT resolution against truth: first piece alone vs the refit
+        if dq_refit:
+            out["median_dqpt_piece"] = round(float(np.median(dq_piece)), 5)
+            out["median_dqpt_refit"] = round(float(np.median(dq_refit)), 5)
+    log("merge: %d pairs in %.3f ms, refit %.3f ms; %s" % (
+        out["pairs"], out["ms"], out["refit_ms"],
+        {k: out[k] for k in ("purity", "efficiency", "median_dqpt_piece", "median_dqpt_refit") if k in out}))
     return out
 
 
