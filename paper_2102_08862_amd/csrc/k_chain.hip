@@ -120,6 +120,9 @@ void launch_seeds(const KArgs &a, Launch l, hipStream_t s) {
 // copies that the wave reserves with one atomic (runs of a multiple of 4
 // entries, so the fit's loads of 4 consecutive records are 64-byte aligned).
 constexpr int kWalkBatch = 4;
+// positions of a chain's first clusters kept in registers by the first walk,
+// so that the second walk gathers their records without chasing the links
+constexpr int kWalkKeep = 32;
 
 __device__ inline int wave_excl_sum(int v, int &total) {
     const int lane = threadIdx.x & 63;
@@ -143,15 +146,31 @@ __global__ __launch_bounds__(256) void k_walk(KArgs a) {
     for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < ns; base += stride) {
         const int k = base + lane;
         int p = 0, L = 0;
+        int pos[kWalkKeep];
         if (k < ns) {
             p = a.seeds[k];
             int q = p;
             L = 1;
-            for (int step = 0; step < R; step++) {
-                const int u = a.upc[q];   // mutual up link (cleaned)
-                if (u < 0) break;
-                q = u;
-                L++;
+            pos[0] = p;
+            // L - 1 steps taken so far, at most R in all
+#pragma unroll
+            for (int j = 1; j < kWalkKeep; j++) {
+                if (L == j && j <= R) {
+                    const int u = a.upc[q];   // mutual up link (cleaned)
+                    if (u >= 0) {
+                        q = u;
+                        L++;
+                    }
+                }
+                pos[j] = q;
+            }
+            if (L == kWalkKeep) {
+                for (int step = kWalkKeep - 1; step < R; step++) {
+                    const int u = a.upc[q];
+                    if (u < 0) break;
+                    q = u;
+                    L++;
+                }
             }
         }
         const bool trk = (k < ns) && L >= a.min_track_hits;
@@ -172,25 +191,43 @@ __global__ __launch_bounds__(256) void k_walk(KArgs a) {
             a.tseed[slot] = p;
             a.tlen[slot] = L;
             a.tchoff[slot] = (int32_t)off;
-            Rec e = a.rec[p];
-            const int si = e.sr >> 8;
-            atomicOr(&a.bits[a.si[si].word_base + (e.id >> 5)], 1u << (e.id & 31));
+            const Rec e0 = a.rec[p];
+            const int si = e0.sr >> 8;
+            atomicOr(&a.bits[a.si[si].word_base + (e0.id >> 5)], 1u << (e0.id & 31));
             Rec *dst = a.chain + off;
-            int q = p;
-            for (int j0 = 0; j0 < L; j0 += kWalkBatch) {
+            // the first kWalkKeep clusters: independent gathers
+#pragma unroll
+            for (int j0 = 0; j0 < kWalkKeep; j0 += kWalkBatch) {
+                if (j0 < L) {
+                    Rec buf[kWalkBatch];
+#pragma unroll
+                    for (int b = 0; b < kWalkBatch; b++) {
+                        const int j = j0 + b;
+                        if (j < L) {
+                            buf[b] = a.rec[pos[j]];
+                            if (a.follow) buf[b].id = pos[j];   // the following reads sorted positions
+                        } else {
+                            buf[b] = Rec{0.f, 0.f, -1, e0.sr};
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < kWalkBatch; b++)
+                        reinterpret_cast<int4 *>(dst + j0)[b] = *reinterpret_cast<const int4 *>(&buf[b]);
+                }
+            }
+            // the rest: follow the links on from the last kept position
+            int q = pos[kWalkKeep - 1];
+            for (int j0 = kWalkKeep; j0 < L; j0 += kWalkBatch) {
                 Rec buf[kWalkBatch];
 #pragma unroll
                 for (int b = 0; b < kWalkBatch; b++) {
                     const int j = j0 + b;
                     if (j < L) {
-                        buf[b] = e;
-                        if (a.follow) buf[b].id = q;   // the following reads sorted positions
-                        if (j + 1 < L) {
-                            q = a.upc[q];
-                            e = a.rec[q];
-                        }
+                        q = a.upc[q];
+                        buf[b] = a.rec[q];
+                        if (a.follow) buf[b].id = q;
                     } else {
-                        buf[b] = Rec{0.f, 0.f, -1, e.sr};
+                        buf[b] = Rec{0.f, 0.f, -1, e0.sr};
                     }
                 }
 #pragma unroll
