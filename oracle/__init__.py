@@ -528,6 +528,73 @@ def merge_sectors(cfg: Config, tracks, min_clusters: int = 30, window: float = 8
 
 
 
+MEMBRANE_S_MAX = 300.0   # largest transverse arc (cm) at which two pieces' time lines may meet
+MEMBRANE_S_TOL = 1.0     # time tolerance (cm) of that test
+
+
+def membrane_residuals(cfg: Config, A, B):
+    """Residuals (R32) of track state B (sector k + 18, C side) seen from
+    the helix of track A (sector k, A side, the same azimuth): the transverse
+    miss and direction difference at the point of A's circle nearest to B's
+    (merge_residuals with no rotation), and tau_A + tau_B (the drift time
+    runs against z on the A side and with it on the C side, so one
+    particle's two pieces have opposite tau). Also returns whether the two
+    pieces' time lines, t0 + tau s against the transverse arc s from the
+    beam line, meet at an arc in [0, MEMBRANE_S_MAX] (within
+    MEMBRANE_S_TOL cm of time): that is where the particle crosses z = 0.
+    All pairs (rows A, columns B). FP64."""
+    dr, dphi, _, _ = merge_residuals(cfg, A, B, 0.0)
+    atau = np.asarray(A["tau"], np.float64)[:, None]
+    btau = np.asarray(B["tau"], np.float64)[None, :]
+    dtau = atau + btau
+    dT = np.asarray(B["t0"], np.float64)[None, :] - np.asarray(A["t0"], np.float64)[:, None]
+    span = MEMBRANE_S_MAX * (atau - btau)
+    meet = (dT >= np.minimum(0.0, span) - MEMBRANE_S_TOL) & (dT <= np.maximum(0.0, span) + MEMBRANE_S_TOL)
+    return dr, dphi, dtau, meet
+
+
+def merge_membrane(cfg: Config, tracks, min_clusters: int = 30, window: float = 30.0, d2_cut: float = 25.0,
+                   sectors=None):
+    """Membrane merging of one frame (R32): a pair (A in sector k of the A
+    side, B in sector k + 18) with both eligible as in merge_sectors,
+    |t0_A - t0_B| <= window (the two pieces' collision times differ by twice
+    the vertex z) and time lines that meet in front of the readout is scored
+    with D2 = (dr / 0.5)^2 + (dphi / 0.02)^2 + (dtau / 0.01)^2 of
+    membrane_residuals; candidates have D2 <= d2_cut; a pair is merged if
+    each is the other's best (least D2, then least index). Returns, per
+    sector, int32 arrays of the partner's index in the other side's sector
+    (-1: none), and the D2 of each merged pair. sectors: only the pairs
+    (k, k + 18) for k in it (default: 0..17)."""
+    sig = np.asarray(MERGE_SIGMA, np.float64)
+    part = [np.full(len(tracks[s]["status"]), -1, np.int32) for s in range(36)]
+    d2_pairs = []
+    el = lambda T: np.nonzero((np.asarray(T["status"]) == 0) & (np.asarray(T["n"]) >= min_clusters)
+                              & np.isfinite(np.asarray(T["t0"], np.float64)))[0]
+    for s in (range(18) if sectors is None else sectors):
+        A, B = tracks[s], tracks[s + 18]
+        ea, eb = el(A), el(B)
+        if len(ea) == 0 or len(eb) == 0:
+            continue
+        sub = lambda T, e: {k: np.asarray(T[k], np.float64)[e] for k in ("x", "y", "t", "sinphi", "tau", "qpt", "t0")}
+        a, b = sub(A, ea), sub(B, eb)
+        d2 = np.full((len(ea), len(eb)), np.inf)
+        for i0 in range(0, len(ea), 512):
+            i1 = min(i0 + 512, len(ea))
+            dr, dphi, dtau, meet = membrane_residuals(cfg, {k: v[i0:i1] for k, v in a.items()}, b)
+            v = (dr / sig[0]) ** 2 + (dphi / sig[1]) ** 2 + (dtau / sig[3]) ** 2
+            near = np.abs(a["t0"][i0:i1, None] - b["t0"][None, :]) <= window
+            d2[i0:i1] = np.where(near & meet & (v <= d2_cut), v, np.inf)
+        best_b = np.argmin(d2, axis=1)
+        best_a = np.argmin(d2, axis=0)
+        for i in range(len(ea)):
+            j = best_b[i]
+            if np.isfinite(d2[i, j]) and best_a[j] == i:
+                part[s][ea[i]] = eb[j]
+                part[s + 18][eb[j]] = ea[i]
+                d2_pairs.append(d2[i, j])
+    return part, np.asarray(d2_pairs)
+
+
 def refit_merged(cfg: Config, xa, ya, ta, xb, yb, tb, dalpha: float):
     """Global refit of a merged pair (R31): the clusters of the second track
     (in the sector dalpha further in azimuth) rotated into the first track's

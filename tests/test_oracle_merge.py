@@ -187,3 +187,98 @@ def test_refit_of_noise_free_pieces_is_truth(geom, ocfg):
         if done >= 40:
             break
     assert done >= 20
+
+
+def _side_state(tr, sector, x):
+    """Truth state (with the collision time of its own side's track) at row
+    line x of a sector, inside the sector's azimuthal acceptance, on the
+    sector's own side of the membrane."""
+    h = _state(tr, sector, x)
+    if h is None or abs(h["y"]) > x * np.tan(np.deg2rad(10.0)):
+        return None
+    return h
+
+
+def test_truth_pieces_across_the_membrane_match(geom, ocfg):
+    """A particle that crosses z = 0 inside the drift volume: its truth
+    states on the two sides give zero transverse residuals, opposite tau,
+    collision times (track_t0 of each state) that differ by twice the vertex
+    z, and time lines that meet at the arc where z = 0."""
+    x = geom[0]
+    fr = synth.generate("frame_10ms", seed=2403, n_threads=8, frame_us=400.0, n_collisions=20)
+    done = 0
+    for pid in range(len(fr.tracks)):
+        tr = fr.tracks[pid]
+        q, pt, phi0, tgl, zv = tr[:5]
+        if pt < 0.5 or tgl == 0.0:
+            continue
+        s_cross = -zv / tgl
+        if not (x[10] < s_cross < x[140]):
+            continue
+        for k in range(18):
+            a = b = None
+            for r in range(152):
+                a = a or _side_state(tr, k, x[r])
+                b = b or _side_state(tr, k + 18, x[151 - r])
+            if a is None or b is None:
+                continue
+            A = {k_: np.array([v]) for k_, v in a.items()}
+            B = {k_: np.array([v]) for k_, v in b.items()}
+            for T in (A, B):
+                T["t0"] = oracle.track_t0(ocfg, T["x"], T["y"], T["t"], T["sinphi"], T["tau"], T["qpt"])
+            dr, dphi, dtau, meet = (v[0, 0] for v in oracle.membrane_residuals(ocfg, A, B))
+            assert abs(dr) < 1e-6 and abs(dphi) < 1e-9 and dtau == 0.0 and meet, (pid, k, dr, dphi, dtau)
+            assert abs((B["t0"][0] - A["t0"][0]) - 2.0 * zv) < 1e-6
+            s_meet = (B["t0"][0] - A["t0"][0]) / (A["tau"][0] - B["tau"][0])
+            assert abs(s_meet - s_cross) < 1e-6 * max(1.0, s_cross), (s_meet, s_cross)
+            done += 1
+            break
+        if done >= 30:
+            break
+    assert done >= 10
+
+
+def _meet_scalar(t0a, taua, t0b, taub):
+    """Is there an arc s in [0, 300] where the time lines t0 + tau s of the
+    two pieces (A: tau_A, B: tau_B) agree within 1 cm?"""
+    D = taua - taub
+    dT = t0b - t0a
+    s = min(max(dT / D, 0.0), 300.0) if D != 0.0 else 0.0
+    return abs(dT - D * s) <= 1.0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_membrane_merging_by_brute_force(ocfg, seed):
+    rng = np.random.default_rng(90 + seed)
+    tracks = []
+    for s in range(36):
+        m = int(rng.integers(0, 7))
+        tracks.append(dict(x=rng.uniform(90, 240, m), y=rng.uniform(-30, 30, m), t=rng.uniform(0, 60, m),
+                           sinphi=rng.uniform(-0.5, 0.5, m), tau=rng.choice([-0.1, -0.02, 0.0, 0.03, 0.1], m),
+                           qpt=rng.choice([0.0, 0.4, -0.7, 2.0], m), status=rng.choice([0, 0, 0, 2], m),
+                           n=rng.integers(20, 80, m), t0=np.round(rng.uniform(0, 40, m))))
+    cut = 1e9   # every pair in the window whose time lines meet is a candidate
+    part, _ = oracle.merge_membrane(ocfg, tracks, min_clusters=30, window=30.0, d2_cut=cut)
+    sig = oracle.MERGE_SIGMA
+    for k in range(18):
+        A, B = tracks[k], tracks[k + 18]
+        el = lambda T, i: T["status"][i] == 0 and T["n"][i] >= 30
+        d2 = {}
+        for i in range(len(A["x"])):
+            for j in range(len(B["x"])):
+                if not (el(A, i) and el(B, j) and abs(A["t0"][i] - B["t0"][j]) <= 30.0):
+                    continue
+                if not _meet_scalar(A["t0"][i], A["tau"][i], B["t0"][j], B["tau"][j]):
+                    continue
+                r = _residual_scalar(ocfg, {k_: A[k_][i] for k_ in A}, {k_: B[k_][j] for k_ in B}, 0.0)
+                d2[(i, j)] = (r[0] / sig[0]) ** 2 + (r[1] / sig[1]) ** 2 + ((A["tau"][i] + B["tau"][j]) / sig[3]) ** 2
+        want_a = [-1] * len(A["x"])
+        want_b = [-1] * len(B["x"])
+        for (i, j), v in d2.items():
+            bi = min((vv, jj) for (ii, jj), vv in d2.items() if ii == i)
+            bj = min((vv, ii) for (ii, jj), vv in d2.items() if jj == j)
+            if bi[1] == j and bj[1] == i:
+                want_a[i] = j
+                want_b[j] = i
+        assert list(part[k]) == want_a, (k, list(part[k]), want_a)
+        assert list(part[k + 18]) == want_b
