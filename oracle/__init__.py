@@ -528,8 +528,21 @@ def merge_sectors(cfg: Config, tracks, min_clusters: int = 30, window: float = 8
 
 
 
-MEMBRANE_S_MAX = 300.0   # largest transverse arc (cm) at which two pieces' time lines may meet
+MEMBRANE_S_MARGIN = 5.0  # arc margin (cm) of the crossing test
 MEMBRANE_S_TOL = 1.0     # time tolerance (cm) of that test
+
+
+def ref_arc(cfg: Config, x_ref, y, sinphi, qpt):
+    """Transverse arc from the point of closest approach to the beam line to
+    the state at (x_ref, y) (minus the arc of track_t0). FP64."""
+    x = np.asarray(x_ref, np.float64); yy = np.asarray(y, np.float64)
+    s = np.asarray(sinphi, np.float64); k = -2.99792458e-3 * cfg.bz * np.asarray(qpt, np.float64)
+    c = np.sqrt(1.0 - s * s)
+    a = x * c + yy * s
+    b = -x * s + yy * c
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sd = np.where(k != 0.0, np.arctan2(-a * k, 1.0 + b * k) / np.where(k != 0.0, k, 1.0), -a)
+    return -sd
 
 
 def membrane_residuals(cfg: Config, A, B):
@@ -538,18 +551,23 @@ def membrane_residuals(cfg: Config, A, B):
     miss and direction difference at the point of A's circle nearest to B's
     (merge_residuals with no rotation), and tau_A + tau_B (the drift time
     runs against z on the A side and with it on the C side, so one
-    particle's two pieces have opposite tau). Also returns whether the two
-    pieces' time lines, t0 + tau s against the transverse arc s from the
-    beam line, meet at an arc in [0, MEMBRANE_S_MAX] (within
-    MEMBRANE_S_TOL cm of time): that is where the particle crosses z = 0.
-    All pairs (rows A, columns B). FP64."""
+    particle's two pieces have opposite tau). Also returns whether the
+    particle's crossing of z = 0 lies between the pieces: the two time lines
+    t0 + tau s (s the transverse arc from the beam line) agree within
+    MEMBRANE_S_TOL cm at some s from the inner piece's reference arc (the
+    smaller of the two, ref_arc) to the outer piece's, widened by
+    MEMBRANE_S_MARGIN cm at both ends. All pairs (rows A, columns B). FP64."""
     dr, dphi, _, _ = merge_residuals(cfg, A, B, 0.0)
     atau = np.asarray(A["tau"], np.float64)[:, None]
     btau = np.asarray(B["tau"], np.float64)[None, :]
     dtau = atau + btau
     dT = np.asarray(B["t0"], np.float64)[None, :] - np.asarray(A["t0"], np.float64)[:, None]
-    span = MEMBRANE_S_MAX * (atau - btau)
-    meet = (dT >= np.minimum(0.0, span) - MEMBRANE_S_TOL) & (dT <= np.maximum(0.0, span) + MEMBRANE_S_TOL)
+    sa = ref_arc(cfg, A["x"], A["y"], A["sinphi"], A["qpt"])[:, None]
+    sb = ref_arc(cfg, B["x"], B["y"], B["sinphi"], B["qpt"])[None, :]
+    s_lo = np.minimum(sa, sb) - MEMBRANE_S_MARGIN
+    s_hi = np.maximum(sa, sb) + MEMBRANE_S_MARGIN
+    D = atau - btau
+    meet = (dT >= np.minimum(D * s_lo, D * s_hi) - MEMBRANE_S_TOL) & (dT <= np.maximum(D * s_lo, D * s_hi) + MEMBRANE_S_TOL)
     return dr, dphi, dtau, meet
 
 
@@ -558,7 +576,7 @@ def merge_membrane(cfg: Config, tracks, min_clusters: int = 30, window: float = 
     """Membrane merging of one frame (R32): a pair (A in sector k of the A
     side, B in sector k + 18) with both eligible as in merge_sectors,
     |t0_A - t0_B| <= window (the two pieces' collision times differ by twice
-    the vertex z) and time lines that meet in front of the readout is scored
+    the vertex z) and time lines that meet between the pieces is scored
     with D2 = (dr / 0.5)^2 + (dphi / 0.02)^2 + (dtau / 0.01)^2 of
     membrane_residuals; candidates have D2 <= d2_cut; a pair is merged if
     each is the other's best (least D2, then least index). Returns, per

@@ -22,7 +22,7 @@ def _state(tr, sector, x):
     Y, z, sphi, arc, t, dtdl = h
     if z * (1.0 if sector < 18 else -1.0) <= 0:
         return None
-    return dict(x=float(x), y=Y, t=t, sinphi=sphi, tau=dtdl, qpt=tr[0] / tr[1])
+    return dict(x=float(x), y=Y, t=t, sinphi=sphi, tau=dtdl, qpt=tr[0] / tr[1], arc=arc)
 
 
 def test_truth_states_in_adjacent_sectors_match(geom, ocfg):
@@ -201,9 +201,12 @@ def _side_state(tr, sector, x):
 
 def test_truth_pieces_across_the_membrane_match(geom, ocfg):
     """A particle that crosses z = 0 inside the drift volume: its truth
-    states on the two sides give zero transverse residuals, opposite tau,
+    states on the two sides (the A side's at its innermost row, the C
+    side's at its outermost, so that the crossing lies between them,
+    whichever side the particle starts on) give zero transverse residuals, opposite tau,
     collision times (track_t0 of each state) that differ by twice the vertex
-    z, and time lines that meet at the arc where z = 0."""
+    z, time lines that meet at the arc where z = 0, and that arc between the
+    states' reference arcs."""
     x = geom[0]
     fr = synth.generate("frame_10ms", seed=2403, n_threads=8, frame_us=400.0, n_collisions=20)
     done = 0
@@ -231,6 +234,11 @@ def test_truth_pieces_across_the_membrane_match(geom, ocfg):
             assert abs((B["t0"][0] - A["t0"][0]) - 2.0 * zv) < 1e-6
             s_meet = (B["t0"][0] - A["t0"][0]) / (A["tau"][0] - B["tau"][0])
             assert abs(s_meet - s_cross) < 1e-6 * max(1.0, s_cross), (s_meet, s_cross)
+            ra = oracle.ref_arc(ocfg, A["x"], A["y"], A["sinphi"], A["qpt"])[0]
+            rb = oracle.ref_arc(ocfg, B["x"], B["y"], B["sinphi"], B["qpt"])[0]
+            assert min(ra, rb) <= s_cross <= max(ra, rb), (ra, rb, s_cross)
+            # the arc of each state: that of the generator's own helix
+            assert abs(ra - a["arc"]) < 1e-6 and abs(rb - b["arc"]) < 1e-6, (ra, a["arc"], rb, b["arc"])
             done += 1
             break
         if done >= 30:
@@ -238,12 +246,27 @@ def test_truth_pieces_across_the_membrane_match(geom, ocfg):
     assert done >= 10
 
 
-def _meet_scalar(t0a, taua, t0b, taub):
-    """Is there an arc s in [0, 300] where the time lines t0 + tau s of the
-    two pieces (A: tau_A, B: tau_B) agree within 1 cm?"""
-    D = taua - taub
-    dT = t0b - t0a
-    s = min(max(dT / D, 0.0), 300.0) if D != 0.0 else 0.0
+def _ref_arc_scalar(cfg, T):
+    """Arc from the beam line's closest approach to the state, from the
+    circle's centre: the closest point of the circle to the origin lies on
+    the ray from the centre through the origin."""
+    k = -2.99792458e-3 * cfg.bz * T["qpt"]
+    phi = np.arcsin(T["sinphi"])
+    if k == 0.0:
+        return T["x"] * np.cos(phi) + T["y"] * np.sin(phi)
+    cx, cy = T["x"] - np.sin(phi) / k, T["y"] + np.cos(phi) / k
+    d = np.arctan2(T["y"] - cy, T["x"] - cx) - np.arctan2(-cy, -cx)
+    return np.arctan2(np.sin(d), np.cos(d)) / k
+
+
+def _meet_scalar(cfg, A, B):
+    """Is there an arc s between the pieces' reference arcs (widened by 5
+    cm) where the time lines t0 + tau s of A and B agree within 1 cm?"""
+    sa, sb = _ref_arc_scalar(cfg, A), _ref_arc_scalar(cfg, B)
+    lo, hi = min(sa, sb) - 5.0, max(sa, sb) + 5.0
+    D = A["tau"] - B["tau"]
+    dT = B["t0"] - A["t0"]
+    s = min(max(dT / D, lo), hi) if D != 0.0 else lo
     return abs(dT - D * s) <= 1.0
 
 
@@ -268,9 +291,10 @@ def test_membrane_merging_by_brute_force(ocfg, seed):
             for j in range(len(B["x"])):
                 if not (el(A, i) and el(B, j) and abs(A["t0"][i] - B["t0"][j]) <= 30.0):
                     continue
-                if not _meet_scalar(A["t0"][i], A["tau"][i], B["t0"][j], B["tau"][j]):
+                Ai, Bj = {k_: A[k_][i] for k_ in A}, {k_: B[k_][j] for k_ in B}
+                if not _meet_scalar(ocfg, Ai, Bj):
                     continue
-                r = _residual_scalar(ocfg, {k_: A[k_][i] for k_ in A}, {k_: B[k_][j] for k_ in B}, 0.0)
+                r = _residual_scalar(ocfg, Ai, Bj, 0.0)
                 d2[(i, j)] = (r[0] / sig[0]) ** 2 + (r[1] / sig[1]) ** 2 + ((A["tau"][i] + B["tau"][j]) / sig[3]) ** 2
         want_a = [-1] * len(A["x"])
         want_b = [-1] * len(B["x"])
@@ -282,3 +306,4 @@ def test_membrane_merging_by_brute_force(ocfg, seed):
                 want_b[j] = i
         assert list(part[k]) == want_a, (k, list(part[k]), want_a)
         assert list(part[k + 18]) == want_b
+    assert sum(int((p >= 0).sum()) for p in part[:18]) > 0
