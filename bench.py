@@ -403,7 +403,8 @@ def merge_leg(trk, fr, f, log, quality=True):
     against the generator's truth, the share of merged pairs that join one
     particle's segments (purity), of the particles with long segments in two
     adjacent sectors that are joined (efficiency), and the median q/pT error
-    of the first piece alone and of the refit."""
+    of the first piece alone and of the refit; then the membrane merging
+    (sector k with k + 18), timed and scored the same way."""
     from paper_2102_08862_amd import metrics
     min_len, window, cut = 30, 8.0, 25.0
     ts = []
@@ -421,6 +422,15 @@ def merge_leg(trk, fr, f, log, quality=True):
         tr_.append(time.perf_counter() - t0)
     out["refit_ms"] = round(1e3 * float(np.median(tr_)), 4)
     out["refits"] = int(n_ref)
+    # membrane merging (sector k with k + 18; wall clock, it synchronises)
+    tm_ = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        n_mem = trk.merge_membrane(min_len, 30.0, cut)
+        tm_.append(time.perf_counter() - t0)
+    out["membrane_ms"] = round(1e3 * float(np.median(tm_)), 4)
+    out["membrane_pairs"] = int(n_mem)
+    trk.refit_merged()   # the refit placed after the membrane merges, so both hold
     if quality:
         ns = len(fr.rows)
         half = ns // 2
@@ -450,13 +460,27 @@ def merge_leg(trk, fr, f, log, quality=True):
             opp += len(set(pa[ea][pa[ea] >= 0]) & set(pb[eb][pb[eb] >= 0]))
         out["purity"] = round(good / max(good + bad, 1), 5)
         out["efficiency"] = round(good / max(opp, 1), 5)
+        mg = mb = mo = 0
+        for k in range(half):
+            (pa, ta), (pb, tb) = P[k], P[k + half]
+            for i, j in enumerate(trk.membrane_merges(f, k)):
+                if j >= 0:
+                    ok = pa[i] >= 0 and pa[i] == pb[j]
+                    mg += int(ok)
+                    mb += int(not ok)
+            ea = (ta["status"] == 0) & (ta["n_clusters"] >= min_len)
+            eb = (tb["status"] == 0) & (tb["n_clusters"] >= min_len)
+            mo += len(set(pa[ea][pa[ea] >= 0]) & set(pb[eb][pb[eb] >= 0]))
+        out["membrane_purity"] = round(mg / max(mg + mb, 1), 5)
+        out["membrane_efficiency"] = round(mg / max(mo, 1), 5)
         # q/pT resolution against truth: first piece alone vs the refit
         if dq_refit:
             out["median_dqpt_piece"] = round(float(np.median(dq_piece)), 5)
             out["median_dqpt_refit"] = round(float(np.median(dq_refit)), 5)
-    log("merge: %d pairs in %.3f ms, refit %.3f ms; %s" % (
-        out["pairs"], out["ms"], out["refit_ms"],
-        {k: out[k] for k in ("purity", "efficiency", "median_dqpt_piece", "median_dqpt_refit") if k in out}))
+    log("merge: %d pairs in %.3f ms, refit %.3f ms, membrane %d pairs in %.3f ms; %s" % (
+        out["pairs"], out["ms"], out["refit_ms"], out["membrane_pairs"], out["membrane_ms"],
+        {k: out[k] for k in ("purity", "efficiency", "median_dqpt_piece", "median_dqpt_refit", "membrane_purity",
+                             "membrane_efficiency") if k in out}))
     return out
 
 

@@ -403,6 +403,43 @@ tpcca_status tpcca_merge_sectors(tpcca_ctx *ctx, int32_t min_clusters, float win
 tpcca_status tpcca_get_merges(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *next, int32_t *prev,
                               int64_t cap, int64_t *n_out);
 
+/* Membrane merging (Sec. 1, as for tpcca_merge_sectors: seeding in time
+   leaves z, and so the side a track crosses to, unknown until after the
+   tracking). A particle crossing z = 0 inside the drift volume leaves a
+   track in sector k of the A side and one in sector k + n_sectors / 2 of
+   the C side, at the same azimuth. tpcca_merge_membrane pairs them, for
+   every loaded frame:
+     - eligible tracks as for tpcca_merge_sectors;
+     - a pair (A in sector k < n_sectors / 2, B in sector k + n_sectors / 2)
+       with |t0_A - t0_B| <= window_cm (the two pieces' collision times
+       differ by twice the vertex z) whose time lines t0 + tau s, s the
+       transverse arc from the beam line, meet within 1 cm at an s between
+       the two tracks' reference arcs widened by 5 cm (the particle crosses
+       z = 0 where one piece ends and the other starts) is scored from A's
+       helix at
+       B's reference point: the transverse miss and the direction
+       difference, and tau_A + tau_B (drift time runs against z on the A
+       side and with it on the C side), D2 = sum of their squares over 0.5
+       cm, 0.02 rad and 0.01;
+     - a pair is merged if D2 <= d2_cut and each track is the other's best
+       candidate (least D2, then least track slot).
+   Suggested values: min_clusters 30, window 30, d2_cut 25. Call after a run
+   (it synchronises); its working arrays follow the sector merges' in the
+   arena's slot (a refit made before is dropped), so the result holds until
+   the next run or sector merge. *n_pairs_out = merged pairs. INVALID_ARG
+   for a bad argument, STATE before a run or with an odd number of sectors,
+   CAPACITY if the working arrays do not fit. */
+tpcca_status tpcca_merge_membrane(tpcca_ctx *ctx, int32_t min_clusters, float window_cm, float d2_cut,
+                                  int64_t *n_pairs_out);
+
+/* Membrane partners of every track of the sector, in track order: the index
+   of its partner among the tracks of the sector on the other side at the
+   same azimuth (sector +- n_sectors / 2), -1 if none; partner may be null.
+   STATE before tpcca_merge_membrane, CAPACITY if cap is below the track
+   count (*n_out holds it). */
+tpcca_status tpcca_get_membrane_merges(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *partner, int64_t cap,
+                                       int64_t *n_out);
+
 /* Global refit of the merged pairs (Sec. 1: the pieces of a particle found
    in two sectors joined after the tracking; the fit is the helix fit of
    tpcca_run, Sec. 3): every pair of tpcca_merge_sectors becomes one track
@@ -413,7 +450,7 @@ tpcca_status tpcca_get_merges(tpcca_ctx *ctx, int32_t frame, int32_t sector, int
    with the x each cluster carries. Call after tpcca_merge_sectors (it
    synchronises); the virtual tracks take the free part of the chain-copy
    region and the arena's slot after the merge arrays, so the result holds
-   until the next run or merge. *n_out = pairs refitted. STATE before
+   until the next run or merge (sector or membrane). *n_out = pairs refitted. STATE before
    tpcca_merge_sectors, CAPACITY if the virtual tracks do not fit. */
 tpcca_status tpcca_refit_merged(tpcca_ctx *ctx, int64_t *n_out);
 

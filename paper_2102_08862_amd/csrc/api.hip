@@ -126,6 +126,9 @@ struct tpcca_ctx {
     bool merge_valid = false;
     size_t merge_next_off = 0, merge_prev_off = 0;
     size_t merge_end = 0;   // first free byte after the merge arrays (offset in the arena)
+    // membrane merges (reset by a run or a new sector merge)
+    bool mem_valid = false;
+    size_t mem_a_off = 0, mem_c_off = 0, mem_end = 0;
     // refits of the merged pairs (reset by a run or a new merge)
     bool refit_valid = false;
     size_t refit_pidx_off = 0, refit_pa_off = 0, refit_pb_off = 0, refit_trk_off = 0;
@@ -1038,6 +1041,7 @@ static tpcca_status run_on_arena(tpcca_ctx *c, bool graphs) {
     c->have_results = true;
     c->coll_valid = false;
     c->merge_valid = false;
+    c->mem_valid = false;
     c->refit_valid = false;
     return TPCCA_OK;
 }
@@ -1325,28 +1329,19 @@ tpcca_status tpcca_get_collisions(tpcca_ctx *c, int32_t frame, int32_t side, flo
     return TPCCA_OK;
 }
 
-tpcca_status tpcca_merge_sectors(tpcca_ctx *c, int32_t min_clusters, float window_cm, float d2_cut,
-                                 int64_t *n_pairs_out) {
-    if (!c || !n_pairs_out || min_clusters < 0 || !(window_cm > 0.f) || !std::isfinite(window_cm) ||
-        !(d2_cut >= 0.f) || !std::isfinite(d2_cut))
-        return TPCCA_ERR_INVALID_ARG;
-    *n_pairs_out = 0;
-    if (!c->have_results) return fail(c, TPCCA_ERR_STATE, "no results (run first)");
-    if (c->cfg.n_sectors < 2 || (c->cfg.n_sectors & 1))
-        return fail(c, TPCCA_ERR_STATE, "sector merging needs an even number of sectors (two sides)");
-    tpcca_status ss = tpcca_synchronize(c);
-    if (ss != TPCCA_OK) return ss;
+// The merge pipeline (range, bins, placement, best candidates, mutual bests)
+// with its working arrays in [region, region + room) of the arena; used =
+// bytes taken.
+static tpcca_status run_merge(tpcca_ctx *c, int32_t membrane, int32_t min_clusters, float window_cm, float d2_cut,
+                              size_t region, size_t room, MergeArgs &m, size_t &used, int64_t *n_pairs_out) {
     char *A = c->arena;
-    const Layout &L = c->lay;
+    char *X = A + region;
     const int64_t trk_cap = c->args.trk_cap;
-    // working arrays in the upper half of the slot after the chain copies
-    // (the lower half keeps the collision candidates)
-    char *X = A + L.xslot + align_up(L.slot_bytes / 2, 256);
-    const size_t room = L.slot_bytes - align_up(L.slot_bytes / 2, 256);
     Bump b;
     const size_t o_rng = b.take(sizeof(uint32_t) * 2), o_np = b.take(sizeof(int32_t));
-    MergeArgs m{};
+    m = MergeArgs{};
     m.n_sectors = c->cfg.n_sectors;
+    m.membrane = membrane;
     m.min_len = min_clusters;
     m.window = window_cm;
     m.d2_cut = d2_cut;
@@ -1416,12 +1411,63 @@ tpcca_status tpcca_merge_sectors(tpcca_ctx *c, int32_t min_clusters, float windo
     HIPCHK(c, hipStreamSynchronize(c->stream));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "merge kernels");
-    c->merge_next_off = (size_t)((char *)m.partner_next - A);
-    c->merge_prev_off = (size_t)((char *)m.partner_prev - A);
-    c->merge_end = (size_t)(X - A) + align_up(b.off, 256);
-    c->merge_valid = true;
-    c->refit_valid = false;
+    used = align_up(b.off, 256);
     *n_pairs_out = np;
+    return TPCCA_OK;
+}
+
+static tpcca_status merge_check(tpcca_ctx *c, int32_t min_clusters, float window_cm, float d2_cut,
+                                int64_t *n_pairs_out) {
+    if (!c || !n_pairs_out || min_clusters < 0 || !(window_cm > 0.f) || !std::isfinite(window_cm) ||
+        !(d2_cut >= 0.f) || !std::isfinite(d2_cut))
+        return TPCCA_ERR_INVALID_ARG;
+    *n_pairs_out = 0;
+    if (!c->have_results) return fail(c, TPCCA_ERR_STATE, "no results (run first)");
+    if (c->cfg.n_sectors < 2 || (c->cfg.n_sectors & 1))
+        return fail(c, TPCCA_ERR_STATE, "merging needs an even number of sectors (two sides)");
+    return tpcca_synchronize(c);
+}
+
+tpcca_status tpcca_merge_sectors(tpcca_ctx *c, int32_t min_clusters, float window_cm, float d2_cut,
+                                 int64_t *n_pairs_out) {
+    tpcca_status ss = merge_check(c, min_clusters, window_cm, d2_cut, n_pairs_out);
+    if (ss != TPCCA_OK) return ss;
+    const Layout &L = c->lay;
+    // working arrays in the upper half of the slot after the chain copies
+    // (the lower half keeps the collision candidates); the membrane merges
+    // and the refits come after them
+    const size_t region = L.xslot + align_up(L.slot_bytes / 2, 256);
+    const size_t room = L.slot_bytes - align_up(L.slot_bytes / 2, 256);
+    c->merge_valid = c->mem_valid = c->refit_valid = false;
+    MergeArgs m;
+    size_t used = 0;
+    ss = run_merge(c, 0, min_clusters, window_cm, d2_cut, region, room, m, used, n_pairs_out);
+    if (ss != TPCCA_OK) return ss;
+    c->merge_next_off = (size_t)((char *)m.partner_next - c->arena);
+    c->merge_prev_off = (size_t)((char *)m.partner_prev - c->arena);
+    c->merge_end = region + used;
+    c->merge_valid = true;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_merge_membrane(tpcca_ctx *c, int32_t min_clusters, float window_cm, float d2_cut,
+                                  int64_t *n_pairs_out) {
+    tpcca_status ss = merge_check(c, min_clusters, window_cm, d2_cut, n_pairs_out);
+    if (ss != TPCCA_OK) return ss;
+    const Layout &L = c->lay;
+    // after the sector merges (if any) in the upper half of the slot; a
+    // refit placed there before is overwritten
+    const size_t region = c->merge_valid ? c->merge_end : L.xslot + align_up(L.slot_bytes / 2, 256);
+    const size_t room = L.xslot + L.slot_bytes - region;
+    c->mem_valid = c->refit_valid = false;
+    MergeArgs m;
+    size_t used = 0;
+    ss = run_merge(c, 1, min_clusters, window_cm, d2_cut, region, room, m, used, n_pairs_out);
+    if (ss != TPCCA_OK) return ss;
+    c->mem_a_off = (size_t)((char *)m.partner_next - c->arena);
+    c->mem_c_off = (size_t)((char *)m.partner_prev - c->arena);
+    c->mem_end = region + used;
+    c->mem_valid = true;
     return TPCCA_OK;
 }
 
@@ -1437,10 +1483,11 @@ tpcca_status tpcca_refit_merged(tpcca_ctx *c, int64_t *n_out) {
     Counters k{};
     HIPCHK(c, hipMemcpy(&k, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost));
     const int64_t nt = std::min<int64_t>(k.n_tracks, a.trk_cap);
-    // the pair arrays after the merge arrays (upper half of the slot)
+    // the pair arrays after the merge arrays and the membrane merges (upper
+    // half of the slot)
     const size_t end = L.xslot + L.slot_bytes;
     Bump b;
-    b.off = c->merge_end;
+    b.off = c->mem_valid ? std::max(c->merge_end, c->mem_end) : c->merge_end;
     const size_t o_flags = b.take(sizeof(int32_t) * (nt + 1)), o_pidx = b.take(sizeof(int32_t) * (nt + 1));
     if (b.off > end) return fail(c, TPCCA_ERR_CAPACITY, "refit arrays exceed the scratch slot");
     RefitArgs r{};
@@ -1571,6 +1618,30 @@ tpcca_status tpcca_get_merges(tpcca_ctx *c, int32_t frame, int32_t sector, int32
         for (int64_t i = 0; i < st.n_tracks; i++)
             if (out[i] >= 0) out[i] -= base;
     }
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_membrane_merges(tpcca_ctx *c, int32_t frame, int32_t sector, int32_t *partner, int64_t cap,
+                                       int64_t *n_out) {
+    if (!c || !n_out) return TPCCA_ERR_INVALID_ARG;
+    if (!c->mem_valid) return fail(c, TPCCA_ERR_STATE, "no membrane merges (call tpcca_merge_membrane)");
+    int si;
+    SiState st;
+    tpcca_status s = locate(c, frame, sector, si, st);
+    if (s != TPCCA_OK) return s;
+    *n_out = st.n_tracks;
+    if (cap < st.n_tracks) return fail(c, TPCCA_ERR_CAPACITY, "buffer too small");
+    if (st.n_tracks == 0 || !partner) return TPCCA_OK;
+    const int half = c->cfg.n_sectors / 2, side = sector / half;
+    int si_o;
+    SiState sto;
+    s = locate(c, frame, side == 0 ? sector + half : sector - half, si_o, sto);
+    if (s != TPCCA_OK) return s;
+    HIPCHK(c, hipMemcpy(partner, c->arena + (side == 0 ? c->mem_a_off : c->mem_c_off) +
+                                     sizeof(int32_t) * (size_t)st.trk_base,
+                        sizeof(int32_t) * (size_t)st.n_tracks, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < st.n_tracks; i++)
+        if (partner[i] >= 0) partner[i] -= sto.trk_base;
     return TPCCA_OK;
 }
 

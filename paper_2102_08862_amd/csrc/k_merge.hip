@@ -16,6 +16,13 @@
 // cm, 0.02, 0.5 cm, 0.01. A pair is a candidate if D2 <= d2_cut and merged
 // if each track is the other's best candidate (least D2, then least index).
 //
+// Membrane merging (a particle crossing z = 0 leaves a track in sector k of
+// the A side and one in sector k + n/2 of the C side, at the same azimuth)
+// runs the same kernels with pairs (k, k + n/2), no rotation, the time
+// residual replaced by a test that the two time lines t0 + tau s meet
+// between the pieces, and tau_A + tau_B in place of tau_A - tau_B (the
+// drift time runs against z on the A side and with it on the C side).
+//
 //   k_mg_range   smallest and largest eligible t0 (block-reduced)
 //   k_mg_count   eligible tracks per (sector instance, time bin)
 //   (scan)       bin starts
@@ -85,6 +92,43 @@ __device__ inline float pair_d2(const MState &A, const MState &B, float kB, floa
     return r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3;
 }
 
+// Membrane pairs: A in sector k (A side), B in sector k + n/2, the same
+// azimuth. D2 of the transverse miss, the direction difference and
+// tau_A + tau_B; infinite unless the time lines t0 + tau s of the two meet
+// (within kMemSTol of time) at an arc s between the two states' arcs from
+// the beam line, widened by kMemSMargin: a particle crossing z = 0 ends one
+// piece and starts the other there.
+constexpr float kMemSMargin = 5.f, kMemSTol = 1.f;
+
+// Transverse arc from the beam line's closest approach to the state.
+__device__ inline float ref_arc(const MState &X, float kB) {
+    const float c = sqrtf(fmaxf(1.f - X.s * X.s, 0.f));
+    const float a = X.x * c + X.y * X.s, b = -X.x * X.s + X.y * c;
+    const float k = -kB * X.q;
+    return k != 0.f ? -atan2f(-a * k, 1.f + b * k) / k : a;
+}
+
+__device__ inline float pair_d2_mem(const MState &A, const MState &B, float kB) {
+    const float D = A.tau - B.tau, dT = B.t0 - A.t0;
+    const float sa = ref_arc(A, kB), sb = ref_arc(B, kB);
+    const float e0 = D * (fminf(sa, sb) - kMemSMargin), e1 = D * (fmaxf(sa, sb) + kMemSMargin);
+    if (!(dT >= fminf(e0, e1) - kMemSTol && dT <= fmaxf(e0, e1) + kMemSTol)) return __builtin_inff();
+    const float ca = sqrtf(fmaxf(1.f - A.s * A.s, 0.f));
+    const float vx = B.x - A.x, vy = B.y - A.y;
+    const float a = vx * ca + vy * A.s, b = -vx * A.s + vy * ca;
+    const float k = -kB * A.q;
+    const float th = atan2f(k * a, 1.f - k * b);
+    const float h = sqrtf((k * a) * (k * a) + (1.f - k * b) * (1.f - k * b));
+    const float dr = (2.f * b - k * (a * a + b * b)) / (1.f + h);
+    float dphi = B.phi - (A.phi + th);
+    const float pi = 3.14159265358979f;
+    while (dphi > pi) dphi -= 2.f * pi;
+    while (dphi <= -pi) dphi += 2.f * pi;
+    const float dtau = A.tau + B.tau;
+    const float r0 = dr / kSigR, r1 = dphi / kSigPhi, r3 = dtau / kSigTau;
+    return r0 * r0 + r1 * r1 + r3 * r3;
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(256) void k_mg_range(KArgs a, MergeArgs m) {
@@ -148,7 +192,8 @@ __global__ __launch_bounds__(256) void k_mg_place(KArgs a, MergeArgs m) {
 
 // One thread per eligible track, in list order (grid-stride over the list):
 // its best candidate in the next sector (it is A) and in the previous sector
-// (it is B).
+// (it is B); across the membrane, an A-side track's best in the C-side
+// sector of its azimuth, a C-side track's best in the A-side one.
 __global__ __launch_bounds__(256) void k_mg_best(KArgs a, MergeArgs m) {
     const int half = m.n_sectors / 2;
     const float dal = 6.283185307179586f / (float)half;
@@ -162,18 +207,24 @@ __global__ __launch_bounds__(256) void k_mg_best(KArgs a, MergeArgs m) {
         const int si = si_of(a, m, g);
         const int fr = si / m.n_sectors, sec = si - fr * m.n_sectors;
         const int side = sec / half, k = sec - side * half;
-        const int si_next = fr * m.n_sectors + side * half + (k + 1) % half;
-        const int si_prev = fr * m.n_sectors + side * half + (k + half - 1) % half;
+        const int si_next = m.membrane ? (side == 0 ? fr * m.n_sectors + half + k : -1)
+                                       : fr * m.n_sectors + side * half + (k + 1) % half;
+        const int si_prev = m.membrane ? (side == 1 ? fr * m.n_sectors + k : -1)
+                                       : fr * m.n_sectors + side * half + (k + half - 1) % half;
         const int b0 = bin_of(m, X.t0 - wide), b1 = bin_of(m, X.t0 + wide);
         int bn = -1, bp = -1;
         float dn = 0.f, dp = 0.f;
         for (int dir = 0; dir < 2; dir++) {
-            const int64_t base = (int64_t)(dir == 0 ? si_next : si_prev) * m.nb;
+            const int sj = dir == 0 ? si_next : si_prev;
+            if (sj < 0) continue;
+            const int64_t base = (int64_t)sj * m.nb;
             const int j0 = m.start[base + b0], j1 = m.start[base + b1 + 1];
             for (int j = j0; j < j1; j++) {
                 const MState Y = mstate(m, j);
                 if (!(fabsf(X.t0 - Y.t0) <= m.window)) continue;
-                const float d2 = dir == 0 ? pair_d2(X, Y, kB, cdal, sdal, dal) : pair_d2(Y, X, kB, cdal, sdal, dal);
+                const float d2 = m.membrane ? (dir == 0 ? pair_d2_mem(X, Y, kB) : pair_d2_mem(Y, X, kB))
+                                            : (dir == 0 ? pair_d2(X, Y, kB, cdal, sdal, dal)
+                                                        : pair_d2(Y, X, kB, cdal, sdal, dal));
                 if (!(d2 <= m.d2_cut)) continue;
                 const int h = m.list[j];
                 if (dir == 0) {

@@ -8,6 +8,7 @@ namespace tpcca {
 
 struct MergeArgs {
     int32_t n_sectors;       // sectors per frame (both sides)
+    int32_t membrane;        // 0: adjacent sectors of one side; 1: sector k (A side) with k + n/2 (C side)
     int32_t min_len;         // eligible: at least this many clusters
     float window;            // collision-time window of a candidate pair (cm)
     float d2_cut;            // a pair is a candidate if D2 <= d2_cut
@@ -20,8 +21,10 @@ struct MergeArgs {
     int32_t *cur;            // [n_si * nb] placement cursors
     int32_t *list;           // [tracks] eligible tracks grouped by (sector instance, bin)
     float4 *mst;             // [2 * tracks] their states in list order: (x, y, t, sin phi), (tau, q/pT, t0, phi)
-    int32_t *best_next;      // [tracks] best candidate in the next sector (global slot, -1)
-    int32_t *best_prev;      // [tracks] best candidate in the previous sector
+    int32_t *best_next;      // [tracks] best candidate in the next sector (global slot, -1);
+                             //   across the membrane: in the C-side sector (A-side tracks)
+    int32_t *best_prev;      // [tracks] best candidate in the previous sector (across the
+                             //   membrane: in the A-side sector, C-side tracks)
     int32_t *partner_next;   // [tracks] merged partner in the next sector (global slot, -1)
     int32_t *partner_prev;   // [tracks] merged partner in the previous sector
     int32_t *n_elig;         // [1] eligible tracks (the list's length)

@@ -89,7 +89,8 @@ EXPORTS = [
     "tpcca_mlp_infer", "tpcca_mlp_grad", "tpcca_mlp_train_step", "tpcca_get_triplets", "tpcca_set_graph",
     "tpcca_set_launch", "tpcca_set_pruning", "tpcca_set_triplet_pool", "tpcca_copy", "tpcca_triplet_samples",
     "tpcca_find_collisions", "tpcca_get_track_times", "tpcca_get_collisions", "tpcca_merge_sectors",
-    "tpcca_get_merges", "tpcca_refit_merged", "tpcca_get_refits",
+    "tpcca_get_merges", "tpcca_refit_merged", "tpcca_get_refits", "tpcca_merge_membrane",
+    "tpcca_get_membrane_merges",
 ]
 
 MLP_NPARAM = 5313
@@ -136,6 +137,8 @@ def load_library(path: str = LIB_PATH):
         "tpcca_merge_sectors": [P, I32, ctypes.c_float, ctypes.c_float, ctypes.POINTER(I64)],
         "tpcca_get_merges": [P, I32, I32, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_refit_merged": [P, ctypes.POINTER(I64)],
+        "tpcca_merge_membrane": [P, I32, ctypes.c_float, ctypes.c_float, ctypes.POINTER(I64)],
+        "tpcca_get_membrane_merges": [P, I32, I32, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_refits": [P, I32, I32, P, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_links": [P, I32, I32, I32, P, P, I64],
         "tpcca_mlp_state_bytes": [ctypes.POINTER(SZ)],
@@ -471,6 +474,25 @@ class Tracker:
             self._check(self.lib.tpcca_get_merges(self.h, frame, sector, nx.ctypes.data, pv.ctypes.data, n.value,
                                                   ctypes.byref(n)))
         return nx, pv
+
+    def merge_membrane(self, min_clusters: int = 30, window_cm: float = 30.0, d2_cut: float = 25.0) -> int:
+        """Pair the tracks of one particle on the two sides of the central
+        membrane (sector k and k + 18); returns the number of merged pairs."""
+        n = ctypes.c_int64()
+        self._check(self.lib.tpcca_merge_membrane(self.h, int(min_clusters), float(window_cm), float(d2_cut),
+                                                  ctypes.byref(n)))
+        return n.value
+
+    def membrane_merges(self, frame, sector):
+        """int32 per track of the sector: its membrane partner's index among
+        the other side's sector's tracks (-1: none)."""
+        n = ctypes.c_int64()
+        self._check_cap(self.lib.tpcca_get_membrane_merges(self.h, frame, sector, None, 0, ctypes.byref(n)))
+        out = np.full(n.value, -1, np.int32)
+        if n.value:
+            self._check(self.lib.tpcca_get_membrane_merges(self.h, frame, sector, out.ctypes.data, n.value,
+                                                           ctypes.byref(n)))
+        return out
 
     def refit_merged(self) -> int:
         """Fit every merged pair as one track (clusters of both in the first
