@@ -626,6 +626,24 @@ def refit_merged(cfg: Config, xa, ya, ta, xb, yb, tb, dalpha: float):
     o = np.argsort(x, kind="stable")
     return fit_map(cfg, x[o], y[o], t[o])
 
+
+def remove_clusters(n_clusters: int, assign, status, qpt, pt_min: float):
+    """Removal of the clusters of tracks not used for physics (R33), one
+    sector: the input indices kept, ascending. A cluster is removed if its
+    track (assign: the sector's track number per input cluster, -1 for none)
+    has a successful fit (status 0) and a transverse momentum below pt_min
+    (|q/pT| > 1 / pt_min); clusters of no track, and of tracks whose fit
+    failed, are kept."""
+    assign = np.asarray(assign, np.int64)
+    status = np.asarray(status)
+    qpt = np.asarray(qpt, np.float64)
+    assert len(assign) == n_clusters
+    low = (status == 0) & (np.abs(qpt) > 1.0 / pt_min)
+    removed = np.zeros(n_clusters, bool)
+    on = assign >= 0
+    removed[on] = low[assign[on]]
+    return np.nonzero(~removed)[0].astype(np.int32)
+
 # ----------------------------------------------------------------- MLP
 MLP_IN, MLP_INP, MLP_H = 12, 16, 64
 MLP_NPARAM = MLP_H * MLP_INP + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
