@@ -365,6 +365,37 @@ def pruned_leg(trk, fr, f, args, log, q_plain):
     return out
 
 
+def remove_leg(trk, fr, f, log, quality=True, pt_min=0.15):
+    """Removal of the clusters of fitted tracks below pt_min after the plain
+    run: the time of remove_clusters (wall clock; it synchronises, two
+    passes over the assignment) and the share of the frame removed; against
+    the generator's truth, the share of the removed clusters that belong to
+    particles above pt_min."""
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        kept = trk.remove_clusters(pt_min)
+        ts.append(time.perf_counter() - t0)
+    n = fr.n_clusters
+    out = {"pt_min_gev": pt_min, "ms": round(1e3 * float(np.median(ts)), 4), "kept": int(kept.numel()),
+           "removed_share": round(1.0 - kept.numel() / max(n, 1), 5)}
+    if quality:
+        k = kept.cpu().numpy()
+        pt = fr.tracks[:, 1]
+        removed = high = 0
+        for s in range(len(fr.rows)):
+            b, c = trk.removal_range(f, s)
+            keep = np.zeros(len(fr.rows[s]), bool)
+            keep[k[b:b + c]] = True
+            lab = fr.labels[s]
+            removed += int((~keep).sum())
+            high += int((~keep & (lab >= 0) & (pt[np.maximum(lab, 0)] >= pt_min)).sum())
+        out["removed_above_pt_min"] = round(high / max(removed, 1), 5)
+    log("remove: %.2f%% of the clusters removed in %.3f ms; %s" % (
+        100.0 * out["removed_share"], out["ms"], {k_: out[k_] for k_ in ("removed_above_pt_min",) if k_ in out}))
+    return out
+
+
 def collisions_leg(trk, fr, f, log, quality=True):
     """Collision candidates after the plain run: the time of
     find_collisions (wall clock; it synchronises, with two host round trips)
@@ -670,6 +701,7 @@ def main():
     q_plain = None if args.no_quality else frame_quality(trk, fr, f)
     collisions = collisions_leg(trk, fr, f, log, quality=not args.no_quality)
     merge = merge_leg(trk, fr, f, log, quality=not args.no_quality)
+    remove = remove_leg(trk, fr, f, log, quality=not args.no_quality)
     pruned = None
     if not args.no_pruned:
         pruned = pruned_leg(trk, fr, f, args, log, q_plain)
@@ -706,6 +738,7 @@ def main():
         "follow": follow,
         "collisions": collisions,
         "merge": merge,
+        "remove": remove,
         "cpu_baseline": cpu,
         "counts": {k: int(st[k]) for k in ("n_links", "n_seeds", "n_tracks", "n_track_clusters", "n_invalid",
                                             "n_overflow_tiles", "n_tiles")},

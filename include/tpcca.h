@@ -440,6 +440,27 @@ tpcca_status tpcca_merge_membrane(tpcca_ctx *ctx, int32_t min_clusters, float wi
 tpcca_status tpcca_get_membrane_merges(tpcca_ctx *ctx, int32_t frame, int32_t sector, int32_t *partner, int64_t cap,
                                        int64_t *n_out);
 
+/* Removal of the clusters of tracks not used for physics (Sec. 1: the
+   compression of the synchronous phase drops the TPC hits of tracks not
+   used for physics, using the tracking's assignment). A cluster is removed
+   if its track has a successful fit (status 0) and pT below pt_min (GeV),
+   i.e. |q/pT| > 1 / pt_min; clusters of no track, and of tracks whose fit
+   failed, are kept. kept: device pointer (caller-owned) to cap int32
+   entries; receives the kept clusters' input indices (sector-local),
+   ascending, sector after sector in (frame, sector) order of the run
+   (tpcca_get_removal_range gives each sector's part). *n_kept = kept
+   clusters of the whole run, also when cap is too small (then nothing is
+   written and CAPACITY is returned: kept may be null with cap = 0 to
+   query). Synchronises. INVALID_ARG for pt_min <= 0 or a null kept with
+   cap > 0, STATE before a run. */
+tpcca_status tpcca_remove_clusters(tpcca_ctx *ctx, float pt_min, int32_t *kept, int64_t cap, int64_t *n_kept);
+
+/* The sector's part of the last tpcca_remove_clusters output: its first
+   entry and its count. STATE before tpcca_remove_clusters (the ranges hold
+   until the next run). */
+tpcca_status tpcca_get_removal_range(tpcca_ctx *ctx, int32_t frame, int32_t sector, int64_t *begin,
+                                     int64_t *count);
+
 /* Global refit of the merged pairs (Sec. 1: the pieces of a particle found
    in two sectors joined after the tracking; the fit is the helix fit of
    tpcca_run, Sec. 3): every pair of tpcca_merge_sectors becomes one track

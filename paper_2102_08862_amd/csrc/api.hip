@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "compress_internal.h"
 #include "merge_internal.h"
 #include "tpcca_internal.h"
 
@@ -41,6 +42,7 @@ struct Layout {
     size_t tstart, ntile, tile_base, tiles, glb_tiles;
     int64_t tile_cap = 0;
     size_t tmp, rec, link, upc;
+    size_t rm_tflag, rm_cnt;   // cluster removal: per-track flags, per-chunk counts
     size_t seeds, tseed, tlen, tslot, tchoff, choff;
     size_t bits, wpre;
     size_t trk_len, trk_seed, cl_off, trk, trk_t0, trk_group, slot_bytes;
@@ -126,6 +128,7 @@ struct tpcca_ctx {
     bool merge_valid = false;
     size_t merge_next_off = 0, merge_prev_off = 0;
     size_t merge_end = 0;   // first free byte after the merge arrays (offset in the arena)
+    bool rm_valid = false;   // cluster removal's chunk offsets (reset by a run)
     // membrane merges (reset by a run or a new sector merge)
     bool mem_valid = false;
     size_t mem_a_off = 0, mem_c_off = 0, mem_end = 0;
@@ -622,6 +625,8 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     L.clusters = b.take(sizeof(int32_t) * N);
     L.assign = b.take(sizeof(int32_t) * N);
     L.asg_cnt = b.take(sizeof(int32_t) * (N / 16384 + 2));
+    L.rm_tflag = b.take(trk_cap);
+    L.rm_cnt = b.take(sizeof(int32_t) * (c->chunks.size() / 2 + 1));
     c->pool_run = c->cfg.use_mlp != 0 && c->keep_pool;
     // every workgroup of the neighbour search may leave up to one partly used
     // chunk of the pool behind
@@ -1041,6 +1046,7 @@ static tpcca_status run_on_arena(tpcca_ctx *c, bool graphs) {
     c->have_results = true;
     c->coll_valid = false;
     c->merge_valid = false;
+    c->rm_valid = false;
     c->mem_valid = false;
     c->refit_valid = false;
     return TPCCA_OK;
@@ -1618,6 +1624,63 @@ tpcca_status tpcca_get_merges(tpcca_ctx *c, int32_t frame, int32_t sector, int32
         for (int64_t i = 0; i < st.n_tracks; i++)
             if (out[i] >= 0) out[i] -= base;
     }
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_remove_clusters(tpcca_ctx *c, float pt_min, int32_t *kept, int64_t cap, int64_t *n_kept) {
+    if (!c || !n_kept || !(pt_min > 0.f) || !std::isfinite(pt_min) || cap < 0 || (cap > 0 && !kept))
+        return TPCCA_ERR_INVALID_ARG;
+    *n_kept = 0;
+    if (!c->have_results) return fail(c, TPCCA_ERR_STATE, "no results (run first)");
+    tpcca_status ss = tpcca_synchronize(c);
+    if (ss != TPCCA_OK) return ss;
+    const KArgs &a = c->args;
+    const Layout &L = c->lay;
+    c->rm_valid = false;
+    RemoveArgs r{};
+    r.qpt_max = 1.f / pt_min;
+    r.tflag = (uint8_t *)(c->arena + L.rm_tflag);
+    r.ccnt = (int32_t *)(c->arena + L.rm_cnt);
+    r.out = kept;
+    r.cap = cap;
+    int32_t nt = 0;
+    HIPCHK(c, hipMemcpy(&nt, &a.cnt->n_tracks, sizeof(int32_t), hipMemcpyDeviceToHost));
+    nt = std::min(nt, a.trk_cap);
+    launch_remove_flags(a, r, nt, c->stream);
+    launch_remove_count(a, r, c->stream);
+    launch_scan_i32(r.ccnt, a.n_chunks, r.ccnt, nullptr, a.scan_tmp, c->stream);   // n_chunks + 1 entries
+    int32_t total = 0;
+    HIPCHK(c, hipMemcpyAsync(&total, r.ccnt + a.n_chunks, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *n_kept = total;
+    c->rm_valid = true;
+    if (cap < total) return fail(c, TPCCA_ERR_CAPACITY, "kept-cluster buffer too small");
+    launch_remove_write(a, r, c->stream);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "removal kernels");
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_removal_range(tpcca_ctx *c, int32_t frame, int32_t sector, int64_t *begin, int64_t *count) {
+    if (!c || !begin || !count) return TPCCA_ERR_INVALID_ARG;
+    if (!c->rm_valid) return fail(c, TPCCA_ERR_STATE, "no removal (call tpcca_remove_clusters)");
+    int si;
+    SiState st;
+    tpcca_status s = locate(c, frame, sector, si, st);
+    if (s != TPCCA_OK) return s;
+    // the sector's chunks are consecutive in the chunk table
+    const int nch = (int)(c->chunks.size() / 2);
+    int k0 = 0;
+    while (k0 < nch && c->chunks[2 * k0] < si) k0++;
+    int k1 = k0;
+    while (k1 < nch && c->chunks[2 * k1] == si) k1++;
+    int32_t v[2] = {0, 0};
+    const int32_t *cc = (const int32_t *)(c->arena + c->lay.rm_cnt);
+    HIPCHK(c, hipMemcpy(&v[0], cc + k0, sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&v[1], cc + k1, sizeof(int32_t), hipMemcpyDeviceToHost));
+    *begin = v[0];
+    *count = v[1] - v[0];
     return TPCCA_OK;
 }
 

@@ -1,0 +1,21 @@
+// Compression consumers of the assignment (after a run): device arguments
+// and launchers. Not part of the C ABI.
+#pragma once
+
+#include "tpcca_internal.h"
+
+namespace tpcca {
+
+struct RemoveArgs {
+    float qpt_max;           // a fitted track with |q/pT| above this is not used for physics (1 / pT_min)
+    uint8_t *tflag;          // [tracks] 1: the track's clusters are removed
+    int32_t *ccnt;           // [chunks + 1] kept clusters per input chunk, then (scan) their offsets
+    int32_t *out;            // [cap] kept input indices (sector-local), sector after sector, ascending
+    int64_t cap;
+};
+
+void launch_remove_flags(const KArgs &a, const RemoveArgs &r, int n_tracks, hipStream_t s);
+void launch_remove_count(const KArgs &a, const RemoveArgs &r, hipStream_t s);
+void launch_remove_write(const KArgs &a, const RemoveArgs &r, hipStream_t s);
+
+}  // namespace tpcca

@@ -1,0 +1,116 @@
+// Removal of the clusters of tracks not used for physics (Sec. 1: the
+// compression of the synchronous phase drops TPC hits of such tracks, using
+// the tracking's assignment). A cluster goes if its track has a successful
+// fit and a transverse momentum below the threshold; clusters of no track,
+// or of a track whose fit failed, stay. The kept clusters are listed by
+// input index, ascending, sector after sector (the run's input chunks in
+// order), so that the compressed sector is a plain subset of the input.
+//
+//   k_rm_flags   one byte per track: removed or not (a small table that the
+//                per-cluster gathers then find in cache)
+//   k_rm_count   kept clusters per input chunk (one workgroup per chunk)
+//   (scan)       chunk offsets in the output
+//   k_rm_write   order-preserving compaction of each chunk: 32 rounds of
+//                256 consecutive inputs; per round a ballot per wave, the
+//                (round, wave) counts scanned in LDS, each kept input
+//                written at its rank
+#include "compress_internal.h"
+
+namespace tpcca {
+
+namespace {
+
+constexpr int kRmRounds = kChunk / 256;   // 32 rounds of 256 inputs per chunk
+static_assert(kChunk % 256 == 0 && kRmRounds <= 32, "one mask bit per round");
+
+__device__ inline bool kept(const KArgs &a, const RemoveArgs &r, const SiDesc &d, int trk_base, int c) {
+    const int t = a.assign[d.in_base + c];   // the sector's track number, -1: none
+    return t < 0 || !r.tflag[trk_base + t];
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_rm_flags(KArgs a, RemoveArgs r, int nt) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nt; g += gridDim.x * blockDim.x) {
+        const tpcca_track &T = a.trk[g];
+        r.tflag[g] = (T.status == 0 && fabsf(T.qpt) > r.qpt_max) ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rm_count(KArgs a, RemoveArgs r) {
+    __shared__ int s_w[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+        const int si = a.chunk[2 * ch], st = a.chunk[2 * ch + 1];
+        const SiDesc d = a.si[si];
+        const int trk_base = a.st[si].trk_base;
+        const int end = min(st + kChunk, d.n);
+        int cnt = 0;
+        for (int c = st + threadIdx.x; c < end; c += blockDim.x) cnt += kept(a, r, d, trk_base, c) ? 1 : 0;
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        if (lane == 0) s_w[w] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) r.ccnt[ch] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rm_write(KArgs a, RemoveArgs r) {
+    __shared__ int s_cnt[kRmRounds * 4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+        const int si = a.chunk[2 * ch], st = a.chunk[2 * ch + 1];
+        const SiDesc d = a.si[si];
+        const int trk_base = a.st[si].trk_base;
+        const int end = min(st + kChunk, d.n);
+        uint32_t mask = 0;   // bit k: this thread's input of round k is kept
+        for (int k = 0; k < kRmRounds; k++) {
+            const int c = st + k * 256 + threadIdx.x;
+            const bool kp = c < end && kept(a, r, d, trk_base, c);
+            if (kp) mask |= 1u << k;
+            const uint64_t b = __ballot(kp);
+            if (lane == 0) s_cnt[k * 4 + w] = __popcll(b);
+        }
+        __syncthreads();
+        // exclusive prefix of the (round, wave) counts, in input order
+        if (threadIdx.x < 64) {
+            const int i0 = 2 * threadIdx.x;
+            const int v0 = s_cnt[i0], v1 = s_cnt[i0 + 1];
+            int x = v0 + v1;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o);
+                if (threadIdx.x >= o) x += y;
+            }
+            const int ex = x - v0 - v1;
+            s_cnt[i0] = ex;
+            s_cnt[i0 + 1] = ex + v0;
+        }
+        __syncthreads();
+        const int64_t base = r.ccnt[ch];
+        for (int k = 0; k < kRmRounds; k++) {
+            const bool kp = (mask >> k) & 1u;
+            const uint64_t b = __ballot(kp);
+            if (kp) {
+                const int64_t pos = base + s_cnt[k * 4 + w] + __popcll(b & below);
+                if (pos < r.cap) r.out[pos] = st + k * 256 + threadIdx.x;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+void launch_remove_flags(const KArgs &a, const RemoveArgs &r, int n_tracks, hipStream_t s) {
+    if (n_tracks > 0)
+        hipLaunchKernelGGL(k_rm_flags, dim3(min((n_tracks + 255) / 256, 65535)), dim3(256), 0, s, a, r, n_tracks);
+}
+
+void launch_remove_count(const KArgs &a, const RemoveArgs &r, hipStream_t s) {
+    if (a.n_chunks > 0) hipLaunchKernelGGL(k_rm_count, dim3(min(a.n_chunks, 65535)), dim3(256), 0, s, a, r);
+}
+
+void launch_remove_write(const KArgs &a, const RemoveArgs &r, hipStream_t s) {
+    if (a.n_chunks > 0) hipLaunchKernelGGL(k_rm_write, dim3(min(a.n_chunks, 65535)), dim3(256), 0, s, a, r);
+}
+
+}  // namespace tpcca

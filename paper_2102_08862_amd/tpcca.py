@@ -90,7 +90,7 @@ EXPORTS = [
     "tpcca_set_launch", "tpcca_set_pruning", "tpcca_set_triplet_pool", "tpcca_copy", "tpcca_triplet_samples",
     "tpcca_find_collisions", "tpcca_get_track_times", "tpcca_get_collisions", "tpcca_merge_sectors",
     "tpcca_get_merges", "tpcca_refit_merged", "tpcca_get_refits", "tpcca_merge_membrane",
-    "tpcca_get_membrane_merges",
+    "tpcca_get_membrane_merges", "tpcca_remove_clusters", "tpcca_get_removal_range",
 ]
 
 MLP_NPARAM = 5313
@@ -139,6 +139,8 @@ def load_library(path: str = LIB_PATH):
         "tpcca_refit_merged": [P, ctypes.POINTER(I64)],
         "tpcca_merge_membrane": [P, I32, ctypes.c_float, ctypes.c_float, ctypes.POINTER(I64)],
         "tpcca_get_membrane_merges": [P, I32, I32, P, I64, ctypes.POINTER(I64)],
+        "tpcca_remove_clusters": [P, ctypes.c_float, P, I64, ctypes.POINTER(I64)],
+        "tpcca_get_removal_range": [P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64)],
         "tpcca_get_refits": [P, I32, I32, P, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_links": [P, I32, I32, I32, P, P, I64],
         "tpcca_mlp_state_bytes": [ctypes.POINTER(SZ)],
@@ -493,6 +495,24 @@ class Tracker:
             self._check(self.lib.tpcca_get_membrane_merges(self.h, frame, sector, out.ctypes.data, n.value,
                                                            ctypes.byref(n)))
         return out
+
+    def remove_clusters(self, pt_min: float = 0.15):
+        """Drop the clusters of fitted tracks below pt_min (GeV): returns a
+        device int32 tensor of the kept clusters' input indices, sector
+        after sector (removal_range gives each sector's part)."""
+        import torch
+        n = ctypes.c_int64()
+        self._check_cap(self.lib.tpcca_remove_clusters(self.h, float(pt_min), None, 0, ctypes.byref(n)))
+        out = torch.empty(max(n.value, 1), dtype=torch.int32, device="cuda")
+        self._check(self.lib.tpcca_remove_clusters(self.h, float(pt_min), ctypes.c_void_p(out.data_ptr()), n.value,
+                                                   ctypes.byref(n)))
+        return out[:n.value]
+
+    def removal_range(self, frame, sector):
+        """(begin, count) of the sector's kept clusters in remove_clusters' output."""
+        b, c = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.tpcca_get_removal_range(self.h, frame, sector, ctypes.byref(b), ctypes.byref(c)))
+        return b.value, c.value
 
     def refit_merged(self) -> int:
         """Fit every merged pair as one track (clusters of both in the first
