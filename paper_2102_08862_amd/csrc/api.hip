@@ -42,7 +42,7 @@ struct Layout {
     size_t tstart, ntile, tile_base, tiles, glb_tiles;
     int64_t tile_cap = 0;
     size_t tmp, rec, link, upc;
-    size_t rm_tflag, rm_cnt;   // cluster removal: per-track flags, per-chunk counts
+    size_t rm_bits, rm_cnt;    // cluster removal: bitmap of removed inputs, per-chunk counts
     size_t seeds, tseed, tlen, tslot, tchoff, choff;
     size_t bits, wpre;
     size_t trk_len, trk_seed, cl_off, trk, trk_t0, trk_group, slot_bytes;
@@ -625,7 +625,7 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     L.clusters = b.take(sizeof(int32_t) * N);
     L.assign = b.take(sizeof(int32_t) * N);
     L.asg_cnt = b.take(sizeof(int32_t) * (N / 16384 + 2));
-    L.rm_tflag = b.take(trk_cap);
+    L.rm_bits = b.take(sizeof(uint32_t) * (size_t)(N / 32 + 2));
     L.rm_cnt = b.take(sizeof(int32_t) * (c->chunks.size() / 2 + 1));
     c->pool_run = c->cfg.use_mlp != 0 && c->keep_pool;
     // every workgroup of the neighbour search may leave up to one partly used
@@ -1638,14 +1638,16 @@ tpcca_status tpcca_remove_clusters(tpcca_ctx *c, float pt_min, int32_t *kept, in
     const Layout &L = c->lay;
     c->rm_valid = false;
     RemoveArgs r{};
+    r.n_sectors = c->cfg.n_sectors;
     r.qpt_max = 1.f / pt_min;
-    r.tflag = (uint8_t *)(c->arena + L.rm_tflag);
+    r.bits = (uint32_t *)(c->arena + L.rm_bits);
     r.ccnt = (int32_t *)(c->arena + L.rm_cnt);
     r.out = kept;
     r.cap = cap;
     int32_t nt = 0;
     HIPCHK(c, hipMemcpy(&nt, &a.cnt->n_tracks, sizeof(int32_t), hipMemcpyDeviceToHost));
     nt = std::min(nt, a.trk_cap);
+    launch_fill_i32((int32_t *)r.bits, (int64_t)(a.n_in / 32 + 2), 0, c->stream);
     launch_remove_flags(a, r, nt, c->stream);
     launch_remove_count(a, r, c->stream);
     launch_scan_i32(r.ccnt, a.n_chunks, r.ccnt, nullptr, a.scan_tmp, c->stream);   // n_chunks + 1 entries

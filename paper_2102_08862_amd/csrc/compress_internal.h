@@ -7,8 +7,9 @@
 namespace tpcca {
 
 struct RemoveArgs {
+    int32_t n_sectors;       // sectors per frame
     float qpt_max;           // a fitted track with |q/pT| above this is not used for physics (1 / pT_min)
-    uint8_t *tflag;          // [tracks] 1: the track's clusters are removed
+    uint32_t *bits;          // [n_in / 32 + 2] 1: the cluster (job input index) is removed
     int32_t *ccnt;           // [chunks + 1] kept clusters per input chunk, then (scan) their offsets
     int32_t *out;            // [cap] kept input indices (sector-local), sector after sector, ascending
     int64_t cap;

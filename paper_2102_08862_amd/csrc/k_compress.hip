@@ -6,14 +6,16 @@
 // input index, ascending, sector after sector (the run's input chunks in
 // order), so that the compressed sector is a plain subset of the input.
 //
-//   k_rm_flags   one byte per track: removed or not (a small table that the
-//                per-cluster gathers then find in cache)
+//   k_rm_flags   per removed track, its clusters' bits in a bitmap over the
+//                run's inputs (few tracks go, so the per-cluster passes read
+//                one bit per input instead of gathering track records)
 //   k_rm_count   kept clusters per input chunk (one workgroup per chunk)
 //   (scan)       chunk offsets in the output
 //   k_rm_write   order-preserving compaction of each chunk: 32 rounds of
 //                256 consecutive inputs; per round a ballot per wave, the
 //                (round, wave) counts scanned in LDS, each kept input
 //                written at its rank
+// Both passes issue a thread's 32 bitmap loads before using any.
 #include "compress_internal.h"
 
 namespace tpcca {
@@ -23,9 +25,23 @@ namespace {
 constexpr int kRmRounds = kChunk / 256;   // 32 rounds of 256 inputs per chunk
 static_assert(kChunk % 256 == 0 && kRmRounds <= 32, "one mask bit per round");
 
-__device__ inline bool kept(const KArgs &a, const RemoveArgs &r, const SiDesc &d, int trk_base, int c) {
-    const int t = a.assign[d.in_base + c];   // the sector's track number, -1: none
-    return t < 0 || !r.tflag[trk_base + t];
+// Bit k set: this thread's input of round k (st + 256 k + thread) is kept.
+// The bitmap loads of all rounds are issued before any is used.
+__device__ inline uint32_t chunk_mask(const RemoveArgs &r, const SiDesc &d, int st, int end) {
+    uint32_t wd[kRmRounds];
+#pragma unroll
+    for (int k = 0; k < kRmRounds; k++) {
+        const int c = st + k * 256 + (int)threadIdx.x;
+        wd[k] = c < end ? r.bits[(d.in_base + c) >> 5] : 0xffffffffu;
+    }
+    uint32_t mask = 0;
+#pragma unroll
+    for (int k = 0; k < kRmRounds; k++) {
+        const int c = st + k * 256 + (int)threadIdx.x;
+        const bool kp = c < end && !((wd[k] >> ((d.in_base + c) & 31)) & 1u);
+        mask |= (kp ? 1u : 0u) << k;
+    }
+    return mask;
 }
 
 }  // namespace
@@ -33,7 +49,14 @@ __device__ inline bool kept(const KArgs &a, const RemoveArgs &r, const SiDesc &d
 __global__ __launch_bounds__(256) void k_rm_flags(KArgs a, RemoveArgs r, int nt) {
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nt; g += gridDim.x * blockDim.x) {
         const tpcca_track &T = a.trk[g];
-        r.tflag[g] = (T.status == 0 && fabsf(T.qpt) > r.qpt_max) ? 1 : 0;
+        if (!(T.status == 0 && fabsf(T.qpt) > r.qpt_max)) continue;
+        // a removed track: mark its clusters (its list holds sector-local input indices)
+        const int in_base = a.si[T.frame * r.n_sectors + T.sector].in_base;
+        const int c0 = a.cl_off[g], L = a.trk_len[g];
+        for (int j = 0; j < L; j++) {
+            const int gi = in_base + a.clusters[c0 + j];
+            atomicOr(&r.bits[gi >> 5], 1u << (gi & 31));
+        }
     }
 }
 
@@ -43,10 +66,8 @@ __global__ __launch_bounds__(256) void k_rm_count(KArgs a, RemoveArgs r) {
     for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
         const int si = a.chunk[2 * ch], st = a.chunk[2 * ch + 1];
         const SiDesc d = a.si[si];
-        const int trk_base = a.st[si].trk_base;
         const int end = min(st + kChunk, d.n);
-        int cnt = 0;
-        for (int c = st + threadIdx.x; c < end; c += blockDim.x) cnt += kept(a, r, d, trk_base, c) ? 1 : 0;
+        int cnt = __popc(chunk_mask(r, d, st, end));
         for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
         if (lane == 0) s_w[w] = cnt;
         __syncthreads();
@@ -62,14 +83,10 @@ __global__ __launch_bounds__(256) void k_rm_write(KArgs a, RemoveArgs r) {
     for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
         const int si = a.chunk[2 * ch], st = a.chunk[2 * ch + 1];
         const SiDesc d = a.si[si];
-        const int trk_base = a.st[si].trk_base;
         const int end = min(st + kChunk, d.n);
-        uint32_t mask = 0;   // bit k: this thread's input of round k is kept
+        const uint32_t mask = chunk_mask(r, d, st, end);
         for (int k = 0; k < kRmRounds; k++) {
-            const int c = st + k * 256 + threadIdx.x;
-            const bool kp = c < end && kept(a, r, d, trk_base, c);
-            if (kp) mask |= 1u << k;
-            const uint64_t b = __ballot(kp);
+            const uint64_t b = __ballot((mask >> k) & 1u);
             if (lane == 0) s_cnt[k * 4 + w] = __popcll(b);
         }
         __syncthreads();
