@@ -644,6 +644,67 @@ def remove_clusters(n_clusters: int, assign, status, qpt, pt_min: float):
     removed[on] = low[assign[on]]
     return np.nonzero(~removed)[0].astype(np.int32)
 
+
+ENT_Q = 16.0        # quantisation: 1/16 cm
+ENT_H = 255         # symbols in [-ENT_H, ENT_H] have a bin; the rest share the escape bin
+ENT_BINS = 2 * ENT_H + 2
+ENT_STREAMS = 5     # row step; y, t first differences; y, t track-model residuals
+
+
+def entropy_symbols(row, y, t):
+    """Symbols of one track's clusters (rows ascending) for the entropy
+    reduction (R34). Coordinates are quantised to 1/16 cm (FP32 product,
+    rounded to nearest even). Every cluster after the first gives: the row
+    step dr_j; the first differences of y and t; and the track-model
+    residuals of y and t: the first difference for the second cluster, and
+    from the third on the exact integer q_j dr_{j-1} - q_{j-1} (dr_{j-1} +
+    dr_j) + q_{j-2} dr_j (dr_{j-1} times the miss of the straight-line
+    extrapolation in row number). Returns int64 [n - 1, 5]."""
+    r = np.asarray(row, np.int64)
+    qy = np.rint(np.asarray(y, np.float32) * np.float32(ENT_Q)).astype(np.int64)
+    qt = np.rint(np.asarray(t, np.float32) * np.float32(ENT_Q)).astype(np.int64)
+    n = len(r)
+    out = np.zeros((max(n - 1, 0), ENT_STREAMS), np.int64)
+    for j in range(1, n):
+        dr = r[j] - r[j - 1]
+        out[j - 1, 0] = dr
+        out[j - 1, 1] = qy[j] - qy[j - 1]
+        out[j - 1, 2] = qt[j] - qt[j - 1]
+        if j == 1:
+            out[j - 1, 3] = qy[j] - qy[j - 1]
+            out[j - 1, 4] = qt[j] - qt[j - 1]
+        else:
+            dp = r[j - 1] - r[j - 2]
+            out[j - 1, 3] = qy[j] * dp - qy[j - 1] * (dp + dr) + qy[j - 2] * dr
+            out[j - 1, 4] = qt[j] * dp - qt[j - 1] * (dp + dr) + qt[j - 2] * dr
+    return out
+
+
+def entropy_histograms(first, ln, clusters, row, y, t):
+    """Histograms [5, ENT_BINS] of the symbols of every track of a sector
+    (symbol s in bin s + ENT_H if |s| <= ENT_H, else the last bin)."""
+    h = np.zeros((ENT_STREAMS, ENT_BINS), np.int64)
+    row = np.asarray(row); y = np.asarray(y, np.float32); t = np.asarray(t, np.float32)
+    for f0, L in zip(first, ln):
+        c = clusters[f0:f0 + L]
+        sym = entropy_symbols(row[c], y[c], t[c])
+        b = np.where(np.abs(sym) <= ENT_H, sym + ENT_H, ENT_BINS - 1)
+        for k in range(ENT_STREAMS):
+            h[k] += np.bincount(b[:, k], minlength=ENT_BINS)
+    return h
+
+
+def entropy_bits(h, escape_bits: float = 32.0):
+    """Order-0 entropy in bits of each stream's symbols (an escape costs its
+    bin's code plus escape_bits)."""
+    h = np.asarray(h, np.float64)
+    out = []
+    for k in range(h.shape[0]):
+        n = h[k].sum()
+        p = h[k][h[k] > 0] / max(n, 1.0)
+        out.append(float(-(h[k][h[k] > 0] * np.log2(p)).sum() + escape_bits * h[k][-1]))
+    return np.asarray(out)
+
 # ----------------------------------------------------------------- MLP
 MLP_IN, MLP_INP, MLP_H = 12, 16, 64
 MLP_NPARAM = MLP_H * MLP_INP + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
