@@ -461,6 +461,22 @@ tpcca_status tpcca_remove_clusters(tpcca_ctx *ctx, float pt_min, int32_t *kept, 
 tpcca_status tpcca_get_removal_range(tpcca_ctx *ctx, int32_t frame, int32_t sector, int64_t *begin,
                                      int64_t *count);
 
+/* Entropy reduction of the cluster properties (Sec. 1: the compression
+   reduces the entropy of the hit properties before the ANS coding), as
+   symbol histograms of the track clusters. Per track (clusters in rows
+   ascending), coordinates quantised to 1/16 cm (y * 16 and t * 16 in FP32,
+   rounded to nearest even), every cluster after the first gives five
+   symbols: the row step dr_j; the first differences of y and of t; and the
+   track-model residuals of y and of t: the first difference for the second
+   cluster, then q_j dr_{j-1} - q_{j-1} (dr_{j-1} + dr_j) + q_{j-2} dr_j
+   (dr_{j-1} times the miss of the straight-line extrapolation in row
+   number). hist: host pointer to 5 x 512 int64 counts, stream after
+   stream; symbol s counts in bin s + 255 if |s| <= 255, else in bin 511.
+   frame = sector = -1: every track of the run; otherwise the tracks of
+   that sector. Synchronises. INVALID_ARG for a null hist or an unknown
+   sector, STATE before a run. */
+tpcca_status tpcca_entropy_histograms(tpcca_ctx *ctx, int32_t frame, int32_t sector, int64_t *hist);
+
 /* Global refit of the merged pairs (Sec. 1: the pieces of a particle found
    in two sectors joined after the tracking; the fit is the helix fit of
    tpcca_run, Sec. 3): every pair of tpcca_merge_sectors becomes one track

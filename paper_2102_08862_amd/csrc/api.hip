@@ -43,6 +43,7 @@ struct Layout {
     int64_t tile_cap = 0;
     size_t tmp, rec, link, upc;
     size_t rm_bits, rm_cnt;    // cluster removal: bitmap of removed inputs, per-chunk counts
+    size_t ent_hist;           // entropy reduction: symbol histograms
     size_t seeds, tseed, tlen, tslot, tchoff, choff;
     size_t bits, wpre;
     size_t trk_len, trk_seed, cl_off, trk, trk_t0, trk_group, slot_bytes;
@@ -627,6 +628,7 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     L.asg_cnt = b.take(sizeof(int32_t) * (N / 16384 + 2));
     L.rm_bits = b.take(sizeof(uint32_t) * (size_t)(N / 32 + 2));
     L.rm_cnt = b.take(sizeof(int32_t) * (c->chunks.size() / 2 + 1));
+    L.ent_hist = b.take(sizeof(int32_t) * kEntStreams * kEntBins);
     c->pool_run = c->cfg.use_mlp != 0 && c->keep_pool;
     // every workgroup of the neighbour search may leave up to one partly used
     // chunk of the pool behind
@@ -1661,6 +1663,36 @@ tpcca_status tpcca_remove_clusters(tpcca_ctx *c, float pt_min, int32_t *kept, in
     HIPCHK(c, hipStreamSynchronize(c->stream));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "removal kernels");
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_entropy_histograms(tpcca_ctx *c, int32_t frame, int32_t sector, int64_t *hist) {
+    if (!c || !hist) return TPCCA_ERR_INVALID_ARG;
+    if (!c->have_results) return fail(c, TPCCA_ERR_STATE, "no results (run first)");
+    tpcca_status ss = tpcca_synchronize(c);
+    if (ss != TPCCA_OK) return ss;
+    EntropyArgs e{};
+    e.only_si = -1;
+    if (frame >= 0 || sector >= 0) {
+        int si;
+        SiState st;
+        ss = locate(c, frame, sector, si, st);
+        if (ss != TPCCA_OK) return ss;
+        e.only_si = si;
+    }
+    e.hist = (int32_t *)(c->arena + c->lay.ent_hist);
+    const KArgs &a = c->args;
+    int32_t nt = 0;
+    HIPCHK(c, hipMemcpy(&nt, &a.cnt->n_tracks, sizeof(int32_t), hipMemcpyDeviceToHost));
+    nt = std::min(nt, a.trk_cap);
+    launch_fill_i32(e.hist, kEntStreams * kEntBins, 0, c->stream);
+    launch_entropy_hist(a, e, nt, c->stream);
+    int32_t h[kEntStreams * kEntBins];
+    HIPCHK(c, hipMemcpyAsync(h, e.hist, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return hip_fail(c, err, "entropy kernel");
+    for (int i = 0; i < kEntStreams * kEntBins; i++) hist[i] = h[i];
     return TPCCA_OK;
 }
 

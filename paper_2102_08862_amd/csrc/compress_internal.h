@@ -15,6 +15,18 @@ struct RemoveArgs {
     int64_t cap;
 };
 
+// Entropy reduction: symbol histograms of the track clusters.
+constexpr int kEntH = 255;                 // symbols in [-kEntH, kEntH] have a bin
+constexpr int kEntBins = 2 * kEntH + 2;    // ... and the last bin holds the rest
+constexpr int kEntStreams = 5;             // row step; y, t first differences; y, t track-model residuals
+
+struct EntropyArgs {
+    int32_t only_si;         // sector instance to take, -1: all
+    int32_t *hist;           // [kEntStreams * kEntBins] counts
+};
+
+void launch_entropy_hist(const KArgs &a, const EntropyArgs &e, int n_tracks, hipStream_t s);
+
 void launch_remove_flags(const KArgs &a, const RemoveArgs &r, int n_tracks, hipStream_t s);
 void launch_remove_count(const KArgs &a, const RemoveArgs &r, hipStream_t s);
 void launch_remove_write(const KArgs &a, const RemoveArgs &r, hipStream_t s);

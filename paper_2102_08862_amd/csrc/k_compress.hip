@@ -117,6 +117,56 @@ __global__ __launch_bounds__(256) void k_rm_write(KArgs a, RemoveArgs r) {
     }
 }
 
+// Entropy reduction of the cluster properties: one thread per track walks
+// its chain copy (16-byte records, rows ascending) and bins, per cluster
+// after the first, the row step, the first differences of the quantised
+// y and t (1/16 cm, FP32 product rounded to nearest even) and the
+// track-model residuals: the first difference for the second cluster, then
+// q_j dr_{j-1} - q_{j-1} (dr_{j-1} + dr_j) + q_{j-2} dr_j (exact in 64-bit
+// integers). Histograms in LDS per workgroup, added to the global ones.
+__device__ inline int ent_bin(long long v) { return (v >= -kEntH && v <= kEntH) ? (int)v + kEntH : kEntBins - 1; }
+
+__global__ __launch_bounds__(256) void k_ent_hist(KArgs a, EntropyArgs e, int nt) {
+    __shared__ int32_t h[kEntStreams * kEntBins];
+    for (int i = threadIdx.x; i < kEntStreams * kEntBins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nt; g += gridDim.x * blockDim.x) {
+        const int L = a.trk_len[g];
+        if (L < 2) continue;
+        const Rec *ch = a.chain + a.choff[g];
+        if (e.only_si >= 0 && (ch[0].sr >> 8) != e.only_si) continue;
+        int r1 = 0, y1 = 0, t1 = 0, r2 = 0, y2 = 0, t2 = 0;   // clusters j - 1 and j - 2
+        for (int j = 0; j < L; j++) {
+            const Rec c = ch[j];
+            const int r = c.sr & 255, qy = __float2int_rn(c.y * 16.f), qt = __float2int_rn(c.t * 16.f);
+            if (j >= 1) {
+                const int dr = r - r1;
+                atomicAdd(&h[0 * kEntBins + ent_bin(dr)], 1);
+                atomicAdd(&h[1 * kEntBins + ent_bin((long long)qy - y1)], 1);
+                atomicAdd(&h[2 * kEntBins + ent_bin((long long)qt - t1)], 1);
+                long long ry = (long long)qy - y1, rt = (long long)qt - t1;
+                if (j >= 2) {
+                    const long long dp = r1 - r2;
+                    ry = (long long)qy * dp - (long long)y1 * (dp + dr) + (long long)y2 * dr;
+                    rt = (long long)qt * dp - (long long)t1 * (dp + dr) + (long long)t2 * dr;
+                }
+                atomicAdd(&h[3 * kEntBins + ent_bin(ry)], 1);
+                atomicAdd(&h[4 * kEntBins + ent_bin(rt)], 1);
+            }
+            r2 = r1; y2 = y1; t2 = t1;
+            r1 = r; y1 = qy; t1 = qt;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kEntStreams * kEntBins; i += blockDim.x)
+        if (h[i]) atomicAdd(&e.hist[i], h[i]);
+}
+
+void launch_entropy_hist(const KArgs &a, const EntropyArgs &e, int n_tracks, hipStream_t s) {
+    if (n_tracks > 0)
+        hipLaunchKernelGGL(k_ent_hist, dim3(min((n_tracks + 255) / 256, 4096)), dim3(256), 0, s, a, e, n_tracks);
+}
+
 void launch_remove_flags(const KArgs &a, const RemoveArgs &r, int n_tracks, hipStream_t s) {
     if (n_tracks > 0)
         hipLaunchKernelGGL(k_rm_flags, dim3(min((n_tracks + 255) / 256, 65535)), dim3(256), 0, s, a, r, n_tracks);

@@ -90,7 +90,7 @@ EXPORTS = [
     "tpcca_set_launch", "tpcca_set_pruning", "tpcca_set_triplet_pool", "tpcca_copy", "tpcca_triplet_samples",
     "tpcca_find_collisions", "tpcca_get_track_times", "tpcca_get_collisions", "tpcca_merge_sectors",
     "tpcca_get_merges", "tpcca_refit_merged", "tpcca_get_refits", "tpcca_merge_membrane",
-    "tpcca_get_membrane_merges", "tpcca_remove_clusters", "tpcca_get_removal_range",
+    "tpcca_get_membrane_merges", "tpcca_remove_clusters", "tpcca_get_removal_range", "tpcca_entropy_histograms",
 ]
 
 MLP_NPARAM = 5313
@@ -141,6 +141,7 @@ def load_library(path: str = LIB_PATH):
         "tpcca_get_membrane_merges": [P, I32, I32, P, I64, ctypes.POINTER(I64)],
         "tpcca_remove_clusters": [P, ctypes.c_float, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_removal_range": [P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64)],
+        "tpcca_entropy_histograms": [P, I32, I32, P],
         "tpcca_get_refits": [P, I32, I32, P, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_links": [P, I32, I32, I32, P, P, I64],
         "tpcca_mlp_state_bytes": [ctypes.POINTER(SZ)],
@@ -513,6 +514,14 @@ class Tracker:
         b, c = ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.tpcca_get_removal_range(self.h, frame, sector, ctypes.byref(b), ctypes.byref(c)))
         return b.value, c.value
+
+    def entropy_histograms(self, frame: int = -1, sector: int = -1) -> np.ndarray:
+        """int64 [5, 512] symbol histograms of the track clusters (row step;
+        y, t first differences; y, t track-model residuals) of the run, or of
+        one sector."""
+        h = np.zeros((5, 512), np.int64)
+        self._check(self.lib.tpcca_entropy_histograms(self.h, int(frame), int(sector), h.ctypes.data))
+        return h
 
     def refit_merged(self) -> int:
         """Fit every merged pair as one track (clusters of both in the first
