@@ -546,7 +546,7 @@ def ref_arc(cfg: Config, x_ref, y, sinphi, qpt):
 
 
 def membrane_residuals(cfg: Config, A, B):
-    """Residuals (R32) of track state B (sector k + 18, C side) seen from
+    """Residuals (Sec. 1, reading R32) of track state B (sector k + 18, C side) seen from
     the helix of track A (sector k, A side, the same azimuth): the transverse
     miss and direction difference at the point of A's circle nearest to B's
     (merge_residuals with no rotation), and tau_A + tau_B (the drift time
@@ -573,7 +573,7 @@ def membrane_residuals(cfg: Config, A, B):
 
 def merge_membrane(cfg: Config, tracks, min_clusters: int = 30, window: float = 30.0, d2_cut: float = 25.0,
                    sectors=None):
-    """Membrane merging of one frame (R32): a pair (A in sector k of the A
+    """Membrane merging of one frame (Sec. 1, reading R32): a pair (A in sector k of the A
     side, B in sector k + 18) with both eligible as in merge_sectors,
     |t0_A - t0_B| <= window (the two pieces' collision times differ by twice
     the vertex z) and time lines that meet between the pieces is scored
@@ -614,7 +614,7 @@ def merge_membrane(cfg: Config, tracks, min_clusters: int = 30, window: float = 
 
 
 def refit_merged(cfg: Config, xa, ya, ta, xb, yb, tb, dalpha: float):
-    """Global refit of a merged pair (R31): the clusters of the second track
+    """Global refit of a merged pair (Sec. 1 and Sec. 3, reading R31): the clusters of the second track
     (in the sector dalpha further in azimuth) rotated into the first track's
     frame, appended to the first track's, ordered by local x (a stable sort:
     ties keep that order), and fitted by fit_map as one track. FP64."""
@@ -628,7 +628,7 @@ def refit_merged(cfg: Config, xa, ya, ta, xb, yb, tb, dalpha: float):
 
 
 def remove_clusters(n_clusters: int, assign, status, qpt, pt_min: float):
-    """Removal of the clusters of tracks not used for physics (R33), one
+    """Removal of the clusters of tracks not used for physics (Sec. 1, reading R33), one
     sector: the input indices kept, ascending. A cluster is removed if its
     track (assign: the sector's track number per input cluster, -1 for none)
     has a successful fit (status 0) and a transverse momentum below pt_min
@@ -653,7 +653,7 @@ ENT_STREAMS = 5     # row step; y, t first differences; y, t track-model residua
 
 def entropy_symbols(row, y, t):
     """Symbols of one track's clusters (rows ascending) for the entropy
-    reduction (R34). Coordinates are quantised to 1/16 cm (FP32 product,
+    reduction (Sec. 1, reading R34). Coordinates are quantised to 1/16 cm (FP32 product,
     rounded to nearest even). Every cluster after the first gives: the row
     step dr_j; the first differences of y and t; and the track-model
     residuals of y and t: the first difference for the second cluster, and
