@@ -70,8 +70,14 @@ __device__ inline int bin_of(const MergeArgs &m, float t0) {
     return min(max(b, 0), m.nb - 1);
 }
 
-// D2 of the pair (A, B) with B's sector dal further in azimuth.
-__device__ inline float pair_d2(const MState &A, const MState &B, float kB, float cdal, float sdal, float dal) {
+// D2 of the pair (A, B) with B's sector dal further in azimuth; infinite
+// once the tau term alone exceeds the cut (D2 is a sum of squares, and an
+// FP32 sum of non-negative terms is at least each of them, so no candidate
+// is lost).
+__device__ inline float pair_d2(const MState &A, const MState &B, float kB, float cdal, float sdal, float dal,
+                                float cut) {
+    const float r3 = (A.tau - B.tau) / kSigTau;
+    if (!(r3 * r3 <= cut)) return __builtin_inff();
     const float ca = sqrtf(fmaxf(1.f - A.s * A.s, 0.f));
     const float xb = B.x * cdal - B.y * sdal, yb = B.x * sdal + B.y * cdal;
     const float vx = xb - A.x, vy = yb - A.y;
@@ -87,8 +93,7 @@ __device__ inline float pair_d2(const MState &A, const MState &B, float kB, floa
     while (dphi > pi) dphi -= 2.f * pi;
     while (dphi <= -pi) dphi += 2.f * pi;
     const float dt = A.t + A.tau * arc - B.t;
-    const float dtau = A.tau - B.tau;
-    const float r0 = dr / kSigR, r1 = dphi / kSigPhi, r2 = dt / kSigT, r3 = dtau / kSigTau;
+    const float r0 = dr / kSigR, r1 = dphi / kSigPhi, r2 = dt / kSigT;
     return r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3;
 }
 
@@ -108,7 +113,9 @@ __device__ inline float ref_arc(const MState &X, float kB) {
     return k != 0.f ? -atan2f(-a * k, 1.f + b * k) / k : a;
 }
 
-__device__ inline float pair_d2_mem(const MState &A, const MState &B, float kB) {
+__device__ inline float pair_d2_mem(const MState &A, const MState &B, float kB, float cut) {
+    const float r3 = (A.tau + B.tau) / kSigTau;   // as in pair_d2: the cheap term first
+    if (!(r3 * r3 <= cut)) return __builtin_inff();
     const float D = A.tau - B.tau, dT = B.t0 - A.t0;
     const float sa = ref_arc(A, kB), sb = ref_arc(B, kB);
     const float e0 = D * (fminf(sa, sb) - kMemSMargin), e1 = D * (fmaxf(sa, sb) + kMemSMargin);
@@ -124,8 +131,7 @@ __device__ inline float pair_d2_mem(const MState &A, const MState &B, float kB) 
     const float pi = 3.14159265358979f;
     while (dphi > pi) dphi -= 2.f * pi;
     while (dphi <= -pi) dphi += 2.f * pi;
-    const float dtau = A.tau + B.tau;
-    const float r0 = dr / kSigR, r1 = dphi / kSigPhi, r3 = dtau / kSigTau;
+    const float r0 = dr / kSigR, r1 = dphi / kSigPhi;
     return r0 * r0 + r1 * r1 + r3 * r3;
 }
 
@@ -222,9 +228,9 @@ __global__ __launch_bounds__(256) void k_mg_best(KArgs a, MergeArgs m) {
             for (int j = j0; j < j1; j++) {
                 const MState Y = mstate(m, j);
                 if (!(fabsf(X.t0 - Y.t0) <= m.window)) continue;
-                const float d2 = m.membrane ? (dir == 0 ? pair_d2_mem(X, Y, kB) : pair_d2_mem(Y, X, kB))
-                                            : (dir == 0 ? pair_d2(X, Y, kB, cdal, sdal, dal)
-                                                        : pair_d2(Y, X, kB, cdal, sdal, dal));
+                const float d2 = m.membrane ? (dir == 0 ? pair_d2_mem(X, Y, kB, m.d2_cut) : pair_d2_mem(Y, X, kB, m.d2_cut))
+                                            : (dir == 0 ? pair_d2(X, Y, kB, cdal, sdal, dal, m.d2_cut)
+                                                        : pair_d2(Y, X, kB, cdal, sdal, dal, m.d2_cut));
                 if (!(d2 <= m.d2_cut)) continue;
                 const int h = m.list[j];
                 if (dir == 0) {
