@@ -21,6 +21,17 @@
  *   4. an FP32 Kalman helix fit of every track, iterated (re-linearised)
  *      so that it converges to the maximum-a-posteriori helix.
  *
+ * Optional inside a run: track following with shared-cluster selection
+ * (config.follow), and pruning of candidate triplets by a small network
+ * (config.use_mlp). After a run, on the resident results: collision times
+ * and candidates (tpcca_find_collisions), merging across adjacent sectors
+ * and across the central membrane (tpcca_merge_sectors,
+ * tpcca_merge_membrane), the global refit of sector-merged pairs
+ * (tpcca_refit_merged), and the compression consumers of the assignment:
+ * removal of the clusters of tracks not used for physics
+ * (tpcca_remove_clusters) and the symbol histograms of the entropy
+ * reduction (tpcca_entropy_histograms).
+ *
  * Conventions
  *   - Every function returns a tpcca_status; no exception crosses the ABI.
  *     tpcca_last_error() gives a message for the last failing call.
