@@ -705,6 +705,112 @@ def entropy_bits(h, escape_bits: float = 32.0):
         out.append(float(-(h[k][h[k] > 0] * np.log2(p)).sum() + escape_bits * h[k][-1]))
     return np.asarray(out)
 
+
+ANS_BITS = 16              # frequencies of a model sum to 2^16
+ANS_L = 1 << 23            # the coder's state stays in [2^23, 2^31)
+
+
+def ans_model(h):
+    """Frequencies (sum 2^16, every bin with a count >= 1) of one stream's
+    histogram for the rANS coder (R35): f = max(1, floor(count 2^16 /
+    total)) for counted bins; the shortfall is added to the bin of the
+    largest count (lowest index on ties), an excess taken one unit at a
+    time from the bin of the largest frequency (lowest index on ties).
+    Bins without a count get 0; the escape bin always gets at least 1.
+    Returns int64 frequencies and cumulative starts."""
+    h = np.asarray(h, np.int64).copy()
+    h[-1] = max(h[-1], 1)
+    tot = int(h.sum())
+    M = 1 << ANS_BITS
+    f = np.where(h > 0, np.maximum(1, (h * M) // tot), 0)
+    d = M - int(f.sum())
+    if d > 0:
+        f[int(np.argmax(h))] += d
+    while d < 0:
+        i = int(np.argmax(f))
+        f[i] -= 1
+        d += 1
+    c = np.concatenate([[0], np.cumsum(f)[:-1]])
+    return f, c
+
+
+def _ans_put(x, f, c, out):
+    xmax = ((ANS_L >> ANS_BITS) << 8) * f
+    while x >= xmax:
+        out.append(x & 255)
+        x >>= 8
+    return ((x // f) << ANS_BITS) + (x % f) + c
+
+
+def ans_encode_track(sym, models):
+    """rANS bytes of one track's symbols (rows of entropy_symbols): one
+    state, the clusters' symbols coded last to first so that a decoder reads
+    them first to last; each symbol through its stream's model, a symbol
+    beyond +-ENT_H as the escape bin followed by its value as two uniform
+    16-bit parts. Returns the bytes in decoding order (the final state, 4
+    bytes little end last, first)."""
+    x = ANS_L
+    out = []
+    for row in np.asarray(sym, np.int64)[::-1]:
+        for k in range(ENT_STREAMS - 1, -1, -1):
+            v = int(row[k])
+            f, c = models[k]
+            if abs(v) <= ENT_H:
+                x = _ans_put(x, int(f[v + ENT_H]), int(c[v + ENT_H]), out)
+            else:
+                u = v & 0xFFFFFFFF
+                x = _ans_put(x, 1, u & 0xFFFF, out)          # low half (decoded last)
+                x = _ans_put(x, 1, u >> 16, out)             # high half
+                x = _ans_put(x, int(f[-1]), int(c[-1]), out)
+    for _ in range(4):
+        out.append(x & 255)
+        x >>= 8
+    return bytes(reversed(out))
+
+
+def ans_decode_track(data, n, models):
+    """Inverse of ans_encode_track for n clusters' symbols."""
+    data = bytes(data)
+    x, p = 0, 0
+    for _ in range(4):
+        x = (x << 8) | data[p]
+        p += 1
+    M = (1 << ANS_BITS) - 1
+
+    def get(f, c):
+        nonlocal x, p
+        s = x & M
+        i = int(np.searchsorted(c, s, side="right") - 1)
+        x = int(f[i]) * (x >> ANS_BITS) + s - int(c[i])
+        while x < ANS_L:
+            x = (x << 8) | data[p]
+            p += 1
+        return i
+
+    def get_raw():
+        nonlocal x, p
+        s = x & M
+        x = (x >> ANS_BITS)
+        while x < ANS_L:
+            x = (x << 8) | data[p]
+            p += 1
+        return s
+
+    out = np.zeros((n, ENT_STREAMS), np.int64)
+    for j in range(n):
+        for k in range(ENT_STREAMS):
+            f, c = models[k]
+            i = get(f, c)
+            if i == ENT_BINS - 1:
+                hi = get_raw()
+                lo = get_raw()
+                u = (hi << 16) | lo
+                out[j, k] = u - (1 << 32) if u >= (1 << 31) else u
+            else:
+                out[j, k] = i - ENT_H
+    assert p == len(data)
+    return out
+
 # ----------------------------------------------------------------- MLP
 MLP_IN, MLP_INP, MLP_H = 12, 16, 64
 MLP_NPARAM = MLP_H * MLP_INP + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1

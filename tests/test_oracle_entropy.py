@@ -50,3 +50,45 @@ def test_entropy_of_known_histograms():
     assert abs(e[0] - 40.0) < 1e-9 and e[1] == 0.0
     h[1, -1] = 8                                      # half escapes: 1 bit each plus 32
     assert abs(oracle.entropy_bits(h)[1] - (16.0 + 8 * 32.0)) < 1e-9
+
+
+def _models(h):
+    return [oracle.ans_model(h[k]) for k in range(oracle.ENT_STREAMS)]
+
+
+def test_ans_model_sums_and_covers():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        h = np.zeros(oracle.ENT_BINS, np.int64)
+        nz = rng.choice(oracle.ENT_BINS, int(rng.integers(1, 400)), replace=False)
+        h[nz] = rng.integers(1, 10 ** int(rng.integers(1, 7)), len(nz))
+        f, c = oracle.ans_model(h)
+        assert f.sum() == 1 << oracle.ANS_BITS and (f[h > 0] >= 1).all() and f[-1] >= 1
+        assert (f[(h == 0) & (np.arange(len(h)) < len(h) - 1)] == 0).all()
+        assert c[0] == 0 and (np.diff(c) == f[:-1]).all()
+
+
+def test_ans_round_trip_and_size():
+    """Random tracks (escapes included) decode to their symbols, and the
+    bytes stay within a few percent of the order-0 entropy."""
+    rng = np.random.default_rng(4)
+    syms = []
+    for _ in range(60):
+        n = int(rng.integers(1, 60))
+        s = np.stack([rng.integers(1, 3, n), rng.normal(0, 6, n).round(), rng.normal(0, 3, n).round(),
+                      rng.normal(0, 20, n).round(), rng.integers(-400, 400, n)], axis=1).astype(np.int64)
+        s[rng.random(s.shape) < 0.01] = 70000
+        syms.append(s)
+    h = np.zeros((oracle.ENT_STREAMS, oracle.ENT_BINS), np.int64)
+    for s in syms:
+        b = np.where(np.abs(s) <= oracle.ENT_H, s + oracle.ENT_H, oracle.ENT_BINS - 1)
+        for k in range(oracle.ENT_STREAMS):
+            h[k] += np.bincount(b[:, k], minlength=oracle.ENT_BINS)
+    models = _models(h)
+    total = 0
+    for s in syms:
+        data = oracle.ans_encode_track(s, models)
+        assert np.array_equal(oracle.ans_decode_track(data, len(s), models), s)
+        total += len(data)
+    bound = oracle.entropy_bits(h).sum() / 8.0
+    assert bound <= total <= 1.05 * bound + 4 * len(syms)
