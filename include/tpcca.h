@@ -488,6 +488,28 @@ tpcca_status tpcca_get_removal_range(tpcca_ctx *ctx, int32_t frame, int32_t sect
    sector, STATE before a run. */
 tpcca_status tpcca_entropy_histograms(tpcca_ctx *ctx, int32_t frame, int32_t sector, int64_t *hist);
 
+/* ANS coding of one sector's track clusters (Sec. 1: entropy compression
+   with ANS after the entropy reduction): the symbols of
+   tpcca_entropy_histograms, coded per track by rANS with one 32-bit state
+   (kept in [2^23, 2^31), byte renormalisation) and, per stream, a 16-bit
+   frequency model from the sector's histogram: f = max(1, floor(count *
+   2^16 / total)) for counted bins (the escape bin counted at least once),
+   the shortfall to 2^16 added to the bin of the largest count, an excess
+   taken one unit at a time from the bin of the largest frequency (lowest
+   index on ties). Per track the clusters' symbols are coded last to first
+   and streams 4 to 0, so a decoder reads cluster 2 stream 0 first; an
+   escape is the escape bin followed by the value's 32 bits as two uniform
+   16-bit parts (high part first in decoding order). bytes: device pointer
+   (caller-owned) to cap bytes; each track's bytes are in decoding order,
+   the final state first (most significant byte first). offsets: host
+   pointer to n_offsets int64 (at least the sector's track count + 1), or
+   null: the start of every track's bytes, then the end. *n_bytes = the
+   sector's bytes, also when cap is too small (then nothing is written and
+   CAPACITY is returned; bytes may be null with cap = 0 to query).
+   Synchronises. INVALID_ARG for a bad pointer, STATE before a run. */
+tpcca_status tpcca_ans_encode(tpcca_ctx *ctx, int32_t frame, int32_t sector, uint8_t *bytes, int64_t cap,
+                              int64_t *offsets, int64_t n_offsets, int64_t *n_bytes);
+
 /* Global refit of the merged pairs (Sec. 1: the pieces of a particle found
    in two sectors joined after the tracking; the fit is the helix fit of
    tpcca_run, Sec. 3): every pair of tpcca_merge_sectors becomes one track

@@ -44,6 +44,7 @@ struct Layout {
     size_t tmp, rec, link, upc;
     size_t rm_bits, rm_cnt;    // cluster removal: bitmap of removed inputs, per-chunk counts
     size_t ent_hist;           // entropy reduction: symbol histograms
+    size_t ans_tab, ans_size;  // rANS: frequency tables, per-track byte counts
     size_t seeds, tseed, tlen, tslot, tchoff, choff;
     size_t bits, wpre;
     size_t trk_len, trk_seed, cl_off, trk, trk_t0, trk_group, slot_bytes;
@@ -629,6 +630,8 @@ static tpcca_status plan(tpcca_ctx *c, bool may_alloc) {
     L.rm_bits = b.take(sizeof(uint32_t) * (size_t)(N / 32 + 2));
     L.rm_cnt = b.take(sizeof(int32_t) * (c->chunks.size() / 2 + 1));
     L.ent_hist = b.take(sizeof(int32_t) * kEntStreams * kEntBins);
+    L.ans_tab = b.take(2 * sizeof(uint32_t) * kEntStreams * kEntBins);
+    L.ans_size = b.take(sizeof(int32_t) * (size_t)(trk_cap + 1));
     c->pool_run = c->cfg.use_mlp != 0 && c->keep_pool;
     // every workgroup of the neighbour search may leave up to one partly used
     // chunk of the pool behind
@@ -1693,6 +1696,99 @@ tpcca_status tpcca_entropy_histograms(tpcca_ctx *c, int32_t frame, int32_t secto
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return hip_fail(c, err, "entropy kernel");
     for (int i = 0; i < kEntStreams * kEntBins; i++) hist[i] = h[i];
+    return TPCCA_OK;
+}
+
+// rANS frequency model of one stream: f = max(1, floor(count 2^16 / total))
+// for counted bins (the escape bin counted at least once), the shortfall to
+// 2^16 added to the bin of the largest count, an excess taken one unit at a
+// time from the bin of the largest frequency (lowest index on ties).
+static void ans_model(const int64_t *hin, uint32_t *f, uint32_t *c) {
+    int64_t h[kEntBins];
+    int64_t tot = 0;
+    for (int i = 0; i < kEntBins; i++) h[i] = hin[i];
+    h[kEntBins - 1] = std::max<int64_t>(h[kEntBins - 1], 1);
+    for (int i = 0; i < kEntBins; i++) tot += h[i];
+    const int64_t M = 1 << 16;
+    int64_t sum = 0;
+    for (int i = 0; i < kEntBins; i++) {
+        f[i] = h[i] > 0 ? (uint32_t)std::max<int64_t>(1, h[i] * M / tot) : 0u;
+        sum += f[i];
+    }
+    int64_t d = M - sum;
+    if (d > 0) {
+        int im = 0;
+        for (int i = 1; i < kEntBins; i++)
+            if (h[i] > h[im]) im = i;
+        f[im] += (uint32_t)d;
+    }
+    while (d < 0) {
+        int im = 0;
+        for (int i = 1; i < kEntBins; i++)
+            if (f[i] > f[im]) im = i;
+        f[im]--;
+        d++;
+    }
+    c[0] = 0;
+    for (int i = 1; i < kEntBins; i++) c[i] = c[i - 1] + f[i - 1];
+}
+
+tpcca_status tpcca_ans_encode(tpcca_ctx *c, int32_t frame, int32_t sector, uint8_t *bytes, int64_t cap,
+                              int64_t *offsets, int64_t n_offsets, int64_t *n_bytes) {
+    if (!c || !n_bytes || cap < 0 || (cap > 0 && !bytes)) return TPCCA_ERR_INVALID_ARG;
+    *n_bytes = 0;
+    if (!c->have_results) return fail(c, TPCCA_ERR_STATE, "no results (run first)");
+    tpcca_status ss = tpcca_synchronize(c);
+    if (ss != TPCCA_OK) return ss;
+    int si;
+    SiState st;
+    ss = locate(c, frame, sector, si, st);
+    if (ss != TPCCA_OK) return ss;
+    const KArgs &a = c->args;
+    const Layout &L = c->lay;
+    // the sector's symbol histograms, then the models
+    EntropyArgs e{};
+    e.only_si = si;
+    e.hist = (int32_t *)(c->arena + L.ent_hist);
+    int32_t nt = 0;
+    HIPCHK(c, hipMemcpy(&nt, &a.cnt->n_tracks, sizeof(int32_t), hipMemcpyDeviceToHost));
+    nt = std::min(nt, a.trk_cap);
+    launch_fill_i32(e.hist, kEntStreams * kEntBins, 0, c->stream);
+    launch_entropy_hist(a, e, nt, c->stream);
+    int32_t h32[kEntStreams * kEntBins];
+    HIPCHK(c, hipMemcpyAsync(h32, e.hist, sizeof(h32), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    uint32_t tab[2 * kEntStreams * kEntBins];
+    for (int k = 0; k < kEntStreams; k++) {
+        int64_t h[kEntBins];
+        for (int i = 0; i < kEntBins; i++) h[i] = h32[k * kEntBins + i];
+        ans_model(h, tab + k * kEntBins, tab + kEntStreams * kEntBins + k * kEntBins);
+    }
+    AnsArgs n{};
+    n.trk_base = st.trk_base;
+    n.n_tracks = st.n_tracks;
+    n.freq = (const uint32_t *)(c->arena + L.ans_tab);
+    n.cum = n.freq + kEntStreams * kEntBins;
+    n.size = (int32_t *)(c->arena + L.ans_size);
+    n.out = bytes;
+    HIPCHK(c, hipMemcpyAsync(c->arena + L.ans_tab, tab, sizeof(tab), hipMemcpyHostToDevice, c->stream));
+    launch_ans_size(a, n, c->stream);
+    launch_scan_i32(n.size, st.n_tracks, n.size, nullptr, a.scan_tmp, c->stream);   // n_tracks + 1 entries
+    int32_t total = 0;
+    HIPCHK(c, hipMemcpyAsync(&total, n.size + st.n_tracks, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *n_bytes = total;
+    if (cap < total) return fail(c, TPCCA_ERR_CAPACITY, "byte buffer too small");
+    if (offsets && n_offsets < (int64_t)st.n_tracks + 1) return fail(c, TPCCA_ERR_CAPACITY, "offset array too small");
+    launch_ans_write(a, n, c->stream);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return hip_fail(c, err, "rANS kernels");
+    if (offsets) {
+        std::vector<int32_t> o((size_t)st.n_tracks + 1);
+        HIPCHK(c, hipMemcpy(o.data(), n.size, sizeof(int32_t) * o.size(), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < o.size(); i++) offsets[i] = o[i];
+    }
     return TPCCA_OK;
 }
 

@@ -27,6 +27,20 @@ struct EntropyArgs {
 
 void launch_entropy_hist(const KArgs &a, const EntropyArgs &e, int n_tracks, hipStream_t s);
 
+// rANS coding of one sector's tracks: one 32-bit state per track, 16-bit
+// frequency models per stream.
+constexpr uint32_t kAnsL = 1u << 23;
+struct AnsArgs {
+    int32_t trk_base, n_tracks;   // the sector's tracks: global slots [trk_base, trk_base + n_tracks)
+    const uint32_t *freq;         // [kEntStreams * kEntBins]
+    const uint32_t *cum;          // [kEntStreams * kEntBins]
+    int32_t *size;                // [n_tracks + 1] bytes per track, then (scan) their offsets
+    uint8_t *out;                 // caller's device buffer
+};
+
+void launch_ans_size(const KArgs &a, const AnsArgs &n, hipStream_t s);
+void launch_ans_write(const KArgs &a, const AnsArgs &n, hipStream_t s);
+
 void launch_remove_flags(const KArgs &a, const RemoveArgs &r, int n_tracks, hipStream_t s);
 void launch_remove_count(const KArgs &a, const RemoveArgs &r, hipStream_t s);
 void launch_remove_write(const KArgs &a, const RemoveArgs &r, hipStream_t s);

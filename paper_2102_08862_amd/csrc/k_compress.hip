@@ -167,6 +167,100 @@ void launch_entropy_hist(const KArgs &a, const EntropyArgs &e, int n_tracks, hip
         hipLaunchKernelGGL(k_ent_hist, dim3(min((n_tracks + 255) / 256, 4096)), dim3(256), 0, s, a, e, n_tracks);
 }
 
+// rANS coding of a sector's tracks (ANS coding after the entropy
+// reduction, Sec. 1): one thread per track encodes its symbols (those of
+// k_ent_hist) from the last cluster to the second and, within a cluster,
+// from the last stream to the first, so that a decoder reads them in
+// order; a symbol beyond +-kEntH goes as the escape bin followed by its 32
+// bits as two uniform 16-bit parts. A first pass counts each track's bytes
+// (final state included), a second writes them from the end of the track's
+// range backwards, so that they lie in decoding order.
+namespace {
+
+__device__ inline void ans_put(uint32_t &x, uint32_t f, uint32_t c, uint8_t *out, int64_t &pos, int &nb) {
+    // every coded symbol has f >= 1 (the model comes from the same symbols);
+    // the clamp keeps the loop below finite (at most 3 bytes) whatever the table
+    f = f ? f : 1u;
+    const uint32_t xmax = ((kAnsL >> 16) << 8) * f;
+    while (x >= xmax) {
+        if (out) out[--pos] = (uint8_t)(x & 255u);
+        nb++;
+        x >>= 8;
+    }
+    x = ((x / f) << 16) + (x % f) + c;
+}
+
+__device__ inline void ans_sym(uint32_t &x, const AnsArgs &n, int k, long long v, uint8_t *out, int64_t &pos,
+                               int &nb) {
+    if (v >= -kEntH && v <= kEntH) {
+        const int i = k * kEntBins + (int)v + kEntH;
+        ans_put(x, n.freq[i], n.cum[i], out, pos, nb);
+    } else {
+        const uint32_t u = (uint32_t)(v & 0xffffffffll);
+        ans_put(x, 1u, u & 0xffffu, out, pos, nb);
+        ans_put(x, 1u, u >> 16, out, pos, nb);
+        const int i = k * kEntBins + kEntBins - 1;
+        ans_put(x, n.freq[i], n.cum[i], out, pos, nb);
+    }
+}
+
+// Encodes track g; out == nullptr: count only. Returns the byte count.
+__device__ inline int ans_track(const KArgs &a, const AnsArgs &n, int g, uint8_t *out, int64_t end) {
+    const int L = a.trk_len[g];
+    const Rec *ch = a.chain + a.choff[g];
+    uint32_t x = kAnsL;
+    int nb = 0;
+    int64_t pos = end;
+    for (int j = L - 1; j >= 1; j--) {
+        const Rec c0 = ch[j], c1 = ch[j - 1];
+        const int r = c0.sr & 255, r1 = c1.sr & 255;
+        const int qy = __float2int_rn(c0.y * 16.f), qt = __float2int_rn(c0.t * 16.f);
+        const int y1 = __float2int_rn(c1.y * 16.f), t1 = __float2int_rn(c1.t * 16.f);
+        const int dr = r - r1;
+        long long ry = (long long)qy - y1, rt = (long long)qt - t1;
+        if (j >= 2) {
+            const Rec c2 = ch[j - 2];
+            const long long dp = r1 - (c2.sr & 255);
+            const int y2 = __float2int_rn(c2.y * 16.f), t2 = __float2int_rn(c2.t * 16.f);
+            ry = (long long)qy * dp - (long long)y1 * (dp + dr) + (long long)y2 * dr;
+            rt = (long long)qt * dp - (long long)t1 * (dp + dr) + (long long)t2 * dr;
+        }
+        ans_sym(x, n, 4, rt, out, pos, nb);
+        ans_sym(x, n, 3, ry, out, pos, nb);
+        ans_sym(x, n, 2, (long long)qt - t1, out, pos, nb);
+        ans_sym(x, n, 1, (long long)qy - y1, out, pos, nb);
+        ans_sym(x, n, 0, dr, out, pos, nb);
+    }
+    for (int b = 0; b < 4; b++) {
+        if (out) out[--pos] = (uint8_t)(x & 255u);
+        nb++;
+        x >>= 8;
+    }
+    return nb;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_ans_size(KArgs a, AnsArgs n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n.n_tracks; i += gridDim.x * blockDim.x)
+        n.size[i] = ans_track(a, n, n.trk_base + i, nullptr, 0);
+}
+
+__global__ __launch_bounds__(256) void k_ans_write(KArgs a, AnsArgs n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n.n_tracks; i += gridDim.x * blockDim.x)
+        ans_track(a, n, n.trk_base + i, n.out, n.size[i + 1]);
+}
+
+void launch_ans_size(const KArgs &a, const AnsArgs &n, hipStream_t s) {
+    if (n.n_tracks > 0)
+        hipLaunchKernelGGL(k_ans_size, dim3(min((n.n_tracks + 255) / 256, 4096)), dim3(256), 0, s, a, n);
+}
+
+void launch_ans_write(const KArgs &a, const AnsArgs &n, hipStream_t s) {
+    if (n.n_tracks > 0)
+        hipLaunchKernelGGL(k_ans_write, dim3(min((n.n_tracks + 255) / 256, 4096)), dim3(256), 0, s, a, n);
+}
+
 void launch_remove_flags(const KArgs &a, const RemoveArgs &r, int n_tracks, hipStream_t s) {
     if (n_tracks > 0)
         hipLaunchKernelGGL(k_rm_flags, dim3(min((n_tracks + 255) / 256, 65535)), dim3(256), 0, s, a, r, n_tracks);

@@ -91,6 +91,7 @@ EXPORTS = [
     "tpcca_find_collisions", "tpcca_get_track_times", "tpcca_get_collisions", "tpcca_merge_sectors",
     "tpcca_get_merges", "tpcca_refit_merged", "tpcca_get_refits", "tpcca_merge_membrane",
     "tpcca_get_membrane_merges", "tpcca_remove_clusters", "tpcca_get_removal_range", "tpcca_entropy_histograms",
+    "tpcca_ans_encode",
 ]
 
 MLP_NPARAM = 5313
@@ -142,6 +143,7 @@ def load_library(path: str = LIB_PATH):
         "tpcca_remove_clusters": [P, ctypes.c_float, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_removal_range": [P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64)],
         "tpcca_entropy_histograms": [P, I32, I32, P],
+        "tpcca_ans_encode": [P, I32, I32, P, I64, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_refits": [P, I32, I32, P, P, P, I64, ctypes.POINTER(I64)],
         "tpcca_get_links": [P, I32, I32, I32, P, P, I64],
         "tpcca_mlp_state_bytes": [ctypes.POINTER(SZ)],
@@ -522,6 +524,19 @@ class Tracker:
         h = np.zeros((5, 512), np.int64)
         self._check(self.lib.tpcca_entropy_histograms(self.h, int(frame), int(sector), h.ctypes.data))
         return h
+
+    def ans_encode(self, frame, sector):
+        """rANS bytes of the sector's track clusters: (device uint8 tensor,
+        int64 offsets of every track's bytes, then the end)."""
+        import torch
+        n = ctypes.c_int64()
+        self._check_cap(self.lib.tpcca_ans_encode(self.h, frame, sector, None, 0, None, 0, ctypes.byref(n)))
+        nt = len(self.tracks(frame, sector))
+        out = torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+        off = np.zeros(nt + 1, np.int64)
+        self._check(self.lib.tpcca_ans_encode(self.h, frame, sector, ctypes.c_void_p(out.data_ptr()), n.value,
+                                              off.ctypes.data, len(off), ctypes.byref(n)))
+        return out[:n.value], off
 
     def refit_merged(self) -> int:
         """Fit every merged pair as one track (clusters of both in the first
