@@ -29,8 +29,9 @@
  * tpcca_merge_membrane), the global refit of sector-merged pairs
  * (tpcca_refit_merged), and the compression consumers of the assignment:
  * removal of the clusters of tracks not used for physics
- * (tpcca_remove_clusters) and the symbol histograms of the entropy
- * reduction (tpcca_entropy_histograms).
+ * (tpcca_remove_clusters), the symbol histograms of the entropy reduction
+ * (tpcca_entropy_histograms) and the rANS coding of a sector's track
+ * clusters (tpcca_ans_encode).
  *
  * Conventions
  *   - Every function returns a tpcca_status; no exception crosses the ABI.
