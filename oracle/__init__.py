@@ -708,6 +708,7 @@ def entropy_bits(h, escape_bits: float = 32.0):
 
 ANS_BITS = 16              # frequencies of a model sum to 2^16
 ANS_L = 1 << 23            # the coder's state stays in [2^23, 2^31)
+ANS_STREAMS = (0, 3, 4)    # coded: the row step and the track-model residuals (the rest follows from them)
 
 
 def ans_model(h):
@@ -743,16 +744,17 @@ def _ans_put(x, f, c, out):
 
 
 def ans_encode_track(sym, models):
-    """rANS bytes of one track's symbols (rows of entropy_symbols): one
-    state, the clusters' symbols coded last to first so that a decoder reads
-    them first to last; each symbol through its stream's model, a symbol
+    """rANS bytes of one track's symbols (rows of entropy_symbols; the
+    streams ANS_STREAMS are coded, the first differences following from
+    them): one state, the clusters' symbols coded last to first so that a
+    decoder reads them first to last; each symbol through its stream's model, a symbol
     beyond +-ENT_H as the escape bin followed by its value as two uniform
     16-bit parts. Returns the bytes in decoding order (the final state, 4
     bytes little end last, first)."""
     x = ANS_L
     out = []
     for row in np.asarray(sym, np.int64)[::-1]:
-        for k in range(ENT_STREAMS - 1, -1, -1):
+        for k in ANS_STREAMS[::-1]:
             v = int(row[k])
             f, c = models[k]
             if abs(v) <= ENT_H:
@@ -769,7 +771,8 @@ def ans_encode_track(sym, models):
 
 
 def ans_decode_track(data, n, models):
-    """Inverse of ans_encode_track for n clusters' symbols."""
+    """Inverse of ans_encode_track for n clusters' symbols: int64 [n, 5]
+    with the coded streams filled (the others zero)."""
     data = bytes(data)
     x, p = 0, 0
     for _ in range(4):
@@ -798,7 +801,7 @@ def ans_decode_track(data, n, models):
 
     out = np.zeros((n, ENT_STREAMS), np.int64)
     for j in range(n):
-        for k in range(ENT_STREAMS):
+        for k in ANS_STREAMS:
             f, c = models[k]
             i = get(f, c)
             if i == ENT_BINS - 1:

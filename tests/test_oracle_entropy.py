@@ -88,7 +88,8 @@ def test_ans_round_trip_and_size():
     total = 0
     for s in syms:
         data = oracle.ans_encode_track(s, models)
-        assert np.array_equal(oracle.ans_decode_track(data, len(s), models), s)
+        coded = list(oracle.ANS_STREAMS)
+        assert np.array_equal(oracle.ans_decode_track(data, len(s), models)[:, coded], s[:, coded])
         total += len(data)
-    bound = oracle.entropy_bits(h).sum() / 8.0
+    bound = oracle.entropy_bits(h)[list(oracle.ANS_STREAMS)].sum() / 8.0
     assert bound <= total <= 1.05 * bound + 4 * len(syms)
