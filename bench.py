@@ -372,7 +372,9 @@ def remove_leg(trk, fr, f, log, quality=True, pt_min=0.15):
     the generator's truth, the share of the removed clusters that belong to
     particles above pt_min. Then the entropy reduction: the time of the
     symbol histograms and the order-0 bits per track cluster of (row, y, t)
-    coded as first differences and as track-model residuals."""
+    coded as first differences and as track-model residuals; and the rANS
+    bytes of every sector (wall clock of the 36 calls, host round trips
+    included)."""
     ts = []
     for _ in range(5):
         t0 = time.perf_counter()
@@ -408,10 +410,20 @@ def remove_leg(trk, fr, f, log, quality=True, pt_min=0.15):
     out["entropy_ms"] = round(1e3 * float(np.median(te)), 4)
     out["bits_per_cluster_first_diff"] = round(bits[0] + bits[1] + bits[2], 4)
     out["bits_per_cluster_track_model"] = round(bits[0] + bits[3] + bits[4], 4)
+    # rANS coding of every sector's track clusters (per-sector models)
+    t0 = time.perf_counter()
+    n_bytes = 0
+    for s in range(len(fr.rows)):
+        data, _ = trk.ans_encode(f, s)
+        n_bytes += int(data.numel())
+    out["ans_ms_all_sectors"] = round(1e3 * (time.perf_counter() - t0), 3)
+    out["ans_bits_per_track_cluster"] = round(8.0 * n_bytes / max(int(h[0].sum()) + len(fr.rows), 1), 4)
     log("remove: %.2f%% of the clusters removed in %.3f ms; %s" % (
         100.0 * out["removed_share"], out["ms"], {k_: out[k_] for k_ in ("removed_above_pt_min", "entropy_ms",
                                                                         "bits_per_cluster_first_diff",
-                                                                        "bits_per_cluster_track_model") if k_ in out}))
+                                                                        "bits_per_cluster_track_model",
+                                                                        "ans_ms_all_sectors",
+                                                                        "ans_bits_per_track_cluster") if k_ in out}))
     return out
 
 

@@ -490,15 +490,17 @@ tpcca_status tpcca_get_removal_range(tpcca_ctx *ctx, int32_t frame, int32_t sect
 tpcca_status tpcca_entropy_histograms(tpcca_ctx *ctx, int32_t frame, int32_t sector, int64_t *hist);
 
 /* ANS coding of one sector's track clusters (Sec. 1: entropy compression
-   with ANS after the entropy reduction): the symbols of
-   tpcca_entropy_histograms, coded per track by rANS with one 32-bit state
+   with ANS after the entropy reduction): of the symbols of
+   tpcca_entropy_histograms, the row step and the track-model residuals of
+   y and t (streams 0, 3, 4; the first differences follow from them), coded
+   per track by rANS with one 32-bit state
    (kept in [2^23, 2^31), byte renormalisation) and, per stream, a 16-bit
    frequency model from the sector's histogram: f = max(1, floor(count *
    2^16 / total)) for counted bins (the escape bin counted at least once),
    the shortfall to 2^16 added to the bin of the largest count, an excess
    taken one unit at a time from the bin of the largest frequency (lowest
    index on ties). Per track the clusters' symbols are coded last to first
-   and streams 4 to 0, so a decoder reads cluster 2 stream 0 first; an
+   and streams 4, 3, 0, so a decoder reads cluster 2 stream 0 first; an
    escape is the escape bin followed by the value's 32 bits as two uniform
    16-bit parts (high part first in decoding order). bytes: device pointer
    (caller-owned) to cap bytes; each track's bytes are in decoding order,

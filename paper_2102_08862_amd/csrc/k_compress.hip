@@ -168,10 +168,10 @@ void launch_entropy_hist(const KArgs &a, const EntropyArgs &e, int n_tracks, hip
 }
 
 // rANS coding of a sector's tracks (ANS coding after the entropy
-// reduction, Sec. 1): one thread per track encodes its symbols (those of
-// k_ent_hist) from the last cluster to the second and, within a cluster,
-// from the last stream to the first, so that a decoder reads them in
-// order; a symbol beyond +-kEntH goes as the escape bin followed by its 32
+// reduction, Sec. 1): one thread per track encodes its row steps and
+// track-model residuals (streams 0, 3 and 4 of k_ent_hist) from the last
+// cluster to the second and, within a cluster, from the last stream to the
+// first, so that a decoder reads them in order; a symbol beyond +-kEntH goes as the escape bin followed by its 32
 // bits as two uniform 16-bit parts. A first pass counts each track's bytes
 // (final state included), a second writes them from the end of the track's
 // range backwards, so that they lie in decoding order.
@@ -225,10 +225,10 @@ __device__ inline int ans_track(const KArgs &a, const AnsArgs &n, int g, uint8_t
             ry = (long long)qy * dp - (long long)y1 * (dp + dr) + (long long)y2 * dr;
             rt = (long long)qt * dp - (long long)t1 * (dp + dr) + (long long)t2 * dr;
         }
+        // coded: the row step and the track-model residuals (the first
+        // differences follow from them)
         ans_sym(x, n, 4, rt, out, pos, nb);
         ans_sym(x, n, 3, ry, out, pos, nb);
-        ans_sym(x, n, 2, (long long)qt - t1, out, pos, nb);
-        ans_sym(x, n, 1, (long long)qy - y1, out, pos, nb);
         ans_sym(x, n, 0, dr, out, pos, nb);
     }
     for (int b = 0; b < 4; b++) {

@@ -1,9 +1,10 @@
 """GPU rANS coding of a sector's track clusters against the oracle's coder.
 
 The oracle takes its own tracks (bit-exact with the GPU's), its own symbol
-histogram of the sector and its own model, and encodes each track; the
-GPU's bytes must equal them byte for byte, track for track, and decode
-(with the oracle's decoder) to the track's symbols."""
+histogram of the sector and its own model, and encodes each track (the row step and the track-model residuals; the
+first differences follow from them); the GPU's bytes must equal them byte
+for byte, track for track, and decode (with the oracle's decoder) to the
+track's symbols."""
 import numpy as np
 import pytest
 
@@ -49,8 +50,9 @@ def test_ans_bytes_of_sectors_against_the_oracle(tp):
             got = data[off[i]:off[i + 1]]
             assert got == want, (s, i, len(got), len(want))
             if i % 97 == 0:
-                assert np.array_equal(oracle.ans_decode_track(got, len(sym), models), sym)
+                coded = list(oracle.ANS_STREAMS)
+                assert np.array_equal(oracle.ans_decode_track(got, len(sym), models)[:, coded], sym[:, coded])
             total += len(want)
-        bits = oracle.entropy_bits(h).sum()
+        bits = oracle.entropy_bits(h)[list(oracle.ANS_STREAMS)].sum()
         print("sector %d: %d tracks, %d bytes, order-0 bound %.0f bytes" % (s, len(first), total, bits / 8), flush=True)
         assert total <= 1.02 * bits / 8 + 4 * len(first)
